@@ -1,0 +1,960 @@
+/*
+ * FP64 CPU oracle: full-path ultrasound Monte Carlo tracer, pulse shaping,
+ * plane-wave delay-and-sum and envelope (UltraRay, arXiv 2501.05828).
+ *
+ * TEST INFRASTRUCTURE ONLY -- loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no
+ * code, header, table or constant generator with the HIP library.
+ *
+ * Structure follows the paper's pipeline (Fig. 2): emission (Sec. 2.3 "Ray
+ * Emission", Eqs. 4 and 6), traversal with Snell/Fresnel interface events and
+ * the reflect-or-transmit choice (Sec. 2.3 "Ray Traversal", Eqs. 7-11), the
+ * transducer sampling of secondary rays with the receive directivity
+ * (Sec. 2.3 "Transducer Sampling", Eq. 13), recording into the time-pressure
+ * signal, the Gaussian-windowed sinusoidal pulse (Eq. 14) and classic
+ * plane-wave delay-and-sum with demodulation and log compression
+ * (Sec. 2.3 "Phase Calculation and Signal Processing").  Point scatterers and
+ * attenuation, which the paper lists as future work (Sec. 5), follow the
+ * readings documented with each function below.
+ *
+ * Intersections are brute force over all primitives.  Random numbers come
+ * from Philox4x32-10 (Salmon et al., SC'11) with the counter layout
+ *   (ray, element | tx << 16, segment | purpose << 16, k)
+ * and purposes 0 emission, 1 reflect/transmit choice, 2 receiving-element
+ * choice for scatterer k, 3 proposal cell.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+#define EPS_T 1e-9          /* self-intersection guard along a ray [m]      */
+#define NCELL 1024          /* 32 x 32 emission-direction cells             */
+
+/* ------------------------------------------------------------------ vectors */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static void sub3(const double *a, const double *b, double *c) { c[0] = a[0] - b[0]; c[1] = a[1] - b[1]; c[2] = a[2] - b[2]; }
+static void normalize3(double *a)
+{
+    double l = sqrt(dot3(a, a));
+    a[0] /= l; a[1] /= l; a[2] /= l;
+}
+
+/* ------------------------------------------------------------------- Philox */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* uniform in (0,1), exact in double: (x + 1/2) / 2^32 */
+static double unif(uint32_t x) { return ((double)x + 0.5) * (1.0 / 4294967296.0); }
+
+/* ------------------------------------------------------------------ context */
+typedef struct {
+    const or_acq *a;
+    const or_scene *s;
+    double *ka;      /* amplitude attenuation per material [Np/m] at f_c */
+    double *inv_c;   /* 1/c per material [s/m]                           */
+    double *xe;      /* element centres along x [m]                      */
+    double *tau;     /* [tx][e] transmit delays [s]                      */
+    double area_e, n_per_tx, t_max, half_ap;
+    int64_t id_sph0, id_pln0, id_box;
+} octx;
+
+typedef struct {
+    double *hist;      /* [tx][e][n] or NULL */
+    or_event *ev;
+    int64_t cap, n;
+    or_stats st;
+} sink;
+
+double or_delay(const or_acq *a, int64_t tx, int64_t e)
+{
+    /* Plane-wave steering (Sec. 2.3 "Ray Emission", Fig. 3): the element
+     * delay grows linearly along the array with the sine of the angle,
+     * referenced to the element that fires first so that all delays are
+     * non-negative. */
+    double xe = ((double)e - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
+    double x0 = (0.0 - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
+    double xl = ((double)(a->n_elements - 1) - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
+    double st = sin(a->angles[tx]);
+    double xref = st >= 0 ? x0 : xl;
+    return (xe - xref) * st / a->c0;
+}
+
+static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
+{
+    memset(C, 0, sizeof(*C));
+    C->a = a;
+    C->s = s;
+    C->ka = (double *)malloc(sizeof(double) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    C->inv_c = (double *)malloc(sizeof(double) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    C->xe = (double *)malloc(sizeof(double) * (size_t)a->n_elements);
+    C->tau = (double *)malloc(sizeof(double) * (size_t)(a->n_elements * a->n_tx));
+    if (!C->ka || !C->inv_c || !C->xe || !C->tau) return -1;
+    for (int64_t m = 0; m < s->n_mat; ++m) {
+        /* alpha [dB/(cm MHz)] * f [MHz] * 100 cm/m * ln(10)/20 Np/dB */
+        C->ka[m] = s->mat[3 * m + 1] * (a->f_c * 1e-6) * 100.0 * log(10.0) / 20.0;
+        C->inv_c[m] = 1.0 / s->mat[3 * m + 2];
+    }
+    for (int64_t e = 0; e < a->n_elements; ++e)
+        C->xe[e] = ((double)e - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
+    for (int64_t tx = 0; tx < a->n_tx; ++tx)
+        for (int64_t e = 0; e < a->n_elements; ++e)
+            C->tau[tx * a->n_elements + e] = or_delay(a, tx, e);
+    C->area_e = a->pitch * a->elevation;
+    C->n_per_tx = (double)a->n_elements * (double)a->rays_per_element;
+    C->t_max = (double)a->n_samples / a->f_s;
+    C->half_ap = 0.5 * (double)a->n_elements * a->pitch;
+    C->id_sph0 = s->n_tri;
+    C->id_pln0 = s->n_tri + s->n_sph;
+    C->id_box = s->n_tri + s->n_sph + s->n_pln;
+    return 0;
+}
+
+static void ctx_free(octx *C)
+{
+    free(C->ka); free(C->inv_c); free(C->xe); free(C->tau);
+}
+
+static void draw(const octx *C, uint32_t ray, int64_t e, int64_t tx, int64_t seg, uint32_t purpose,
+                 uint32_t k, uint32_t out[4])
+{
+    uint32_t ctr[4] = {ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k};
+    uint32_t key[2] = {(uint32_t)C->a->seed, (uint32_t)(C->a->seed >> 32)};
+    or_philox(ctr, key, out);
+}
+
+/* --------------------------------------------------------- emission (Eq. 4, 6) */
+/* Equal-area map of the unit square onto the +z hemisphere: Shirley-Chiu
+ * concentric square-to-disk map followed by the area-preserving lift
+ * z = 1 - r^2, (x, y) scaled by sqrt(2 - r^2).  Uniform (a, b) give uniform
+ * directions (pdf 1/(2 pi) per steradian); each of 32x32 square cells maps to
+ * 2 pi / 1024 sr. */
+void or_hemisphere(double a, double b, double d[3])
+{
+    double sa = 2.0 * a - 1.0, sb = 2.0 * b - 1.0, r, phi;
+    if (sa == 0.0 && sb == 0.0) {
+        d[0] = 0.0; d[1] = 0.0; d[2] = 1.0;
+        return;
+    }
+    if (fabs(sa) > fabs(sb)) {
+        r = sa;
+        phi = (PI / 4.0) * (sb / sa);
+    } else {
+        r = sb;
+        phi = PI / 2.0 - (PI / 4.0) * (sa / sb);
+    }
+    double r2 = r * r, sc = sqrt(2.0 - r2);
+    d[0] = r * cos(phi) * sc;
+    d[1] = r * sin(phi) * sc;
+    d[2] = 1.0 - r2;
+}
+
+/* Ray emission: origin uniform on the element face, direction from the
+ * proposal, Monte Carlo weight = emission directivity (cosine, Eq. 6) over
+ * (number of rays per transmit x direction pdf) as in Eq. 4. */
+static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3], double d[3], double *w)
+{
+    const or_acq *a = C->a;
+    uint32_t x[4];
+    draw(C, ray, e, tx, 0, 0, 0, x);
+    double u0 = unif(x[0]), u1 = unif(x[1]), u2 = unif(x[2]), u3 = unif(x[3]);
+    o[0] = C->xe[e] + (u0 - 0.5) * a->pitch;
+    o[1] = (u1 - 0.5) * a->elevation;
+    o[2] = 0.0;
+    double ca, cb, pdf;
+    if (a->cdf == NULL) {
+        ca = u2;
+        cb = u3;
+        pdf = 1.0 / (2.0 * PI);
+    } else {
+        uint32_t y[4];
+        draw(C, ray, e, tx, 0, 3, 0, y);
+        double uc = unif(y[0]);
+        const float *cdf = a->cdf + (tx * a->n_elements + e) * NCELL;
+        int cell = NCELL - 1;
+        for (int c = 0; c < NCELL; ++c) {
+            if (uc <= (double)cdf[c]) {
+                cell = c;
+                break;
+            }
+        }
+        ca = ((double)(cell % 32) + u2) / 32.0;
+        cb = ((double)(cell / 32) + u3) / 32.0;
+        pdf = (double)a->pdf[(tx * a->n_elements + e) * NCELL + cell] * (double)NCELL / (2.0 * PI);
+    }
+    or_hemisphere(ca, cb, d);
+    *w = d[2] / (C->n_per_tx * pdf);
+}
+
+/* ------------------------------------------------------ directivity (Eq. 13) */
+double or_directivity(double alpha, double alpha_m, double alpha_c)
+{
+    double al = fabs(alpha);
+    if (al > alpha_c) return 0.0;
+    if (al <= alpha_m) return 1.0;
+    return (alpha_c - al) / (alpha_c - alpha_m);
+}
+
+/* ------------------------------------------------ interface (Eqs. 7-11) */
+/* Reflect-or-transmit at an impedance boundary.  ng is the geometric normal
+ * (pointing to the front side); the side the ray comes from fixes which
+ * material is "before" (Z1) and "after" (Z2), eta = Z1/Z2.  Reflection iff
+ * y < A_r^2; a negative radicand in Eq. 8 (total internal reflection) gives
+ * A_r^2 = 1.  Returns 1 for reflection. */
+static int fresnel_step(const double d[3], const double ng[3], double z_front, double z_back, double y,
+                        double od[3], double *R_out, int *from_front)
+{
+    double n[3] = {ng[0], ng[1], ng[2]};
+    double z1, z2;
+    if (dot3(d, n) < 0.0) {
+        z1 = z_front; z2 = z_back; *from_front = 1;
+    } else {
+        z1 = z_back; z2 = z_front; *from_front = 0;
+        n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2];
+    }
+    double cos_r = -dot3(d, n);                       /* Eq. 7 */
+    double eta = z1 / z2;
+    double rad = 1.0 - eta * eta * (1.0 - cos_r * cos_r);
+    double R, cos_t = 0.0;
+    if (rad < 0.0) {
+        R = 1.0;
+    } else {
+        cos_t = sqrt(rad);                            /* Eq. 8 */
+        double den = z1 * cos_r + z2 * cos_t;
+        if (den == 0.0) {
+            R = 1.0;
+        } else {
+            double A = (z1 * cos_r - z2 * cos_t) / den;  /* Eq. 11 */
+            R = A * A;
+        }
+    }
+    *R_out = R;
+    if (y < R) {                                      /* Eq. 9 */
+        od[0] = d[0] + 2.0 * cos_r * n[0];
+        od[1] = d[1] + 2.0 * cos_r * n[1];
+        od[2] = d[2] + 2.0 * cos_r * n[2];
+        normalize3(od);
+        return 1;
+    }
+    double f = eta * cos_r - cos_t;                   /* Eq. 10 */
+    od[0] = eta * d[0] + f * n[0];
+    od[1] = eta * d[1] + f * n[1];
+    od[2] = eta * d[2] + f * n[2];
+    normalize3(od);
+    return 0;
+}
+
+int or_interface(const double d[3], const double n[3], double z_front, double z_back, double y,
+                 double out_d[3], double *R)
+{
+    int ff;
+    return fresnel_step(d, n, z_front, z_back, y, out_d, R, &ff);
+}
+
+/* Transmitted intensity fraction 1 - A_r^2 for a straight (unbent) crossing. */
+static double transmit_fraction(double z1, double z2, double cos_r)
+{
+    double eta = z1 / z2;
+    double rad = 1.0 - eta * eta * (1.0 - cos_r * cos_r);
+    if (rad < 0.0) return 0.0;
+    double cos_t = sqrt(rad);
+    double den = z1 * cos_r + z2 * cos_t;
+    if (den == 0.0) return 0.0;
+    double A = (z1 * cos_r - z2 * cos_t) / den;
+    return 1.0 - A * A;
+}
+
+/* ------------------------------------------------------------ intersections */
+/* Moller-Trumbore ray/triangle test; returns 1 and the ray parameter on a hit. */
+static int tri_isect(const double *v, const double o[3], const double d[3], double *t_out)
+{
+    double e1[3], e2[3], p[3], tv[3], q[3];
+    sub3(v + 3, v, e1);
+    sub3(v + 6, v, e2);
+    cross3(d, e2, p);
+    double det = dot3(e1, p);
+    if (det == 0.0) return 0;
+    double inv = 1.0 / det;
+    sub3(o, v, tv);
+    double u = dot3(tv, p) * inv;
+    if (u < 0.0 || u > 1.0) return 0;
+    cross3(tv, e1, q);
+    double vv = dot3(d, q) * inv;
+    if (vv < 0.0 || u + vv > 1.0) return 0;
+    *t_out = dot3(e2, q) * inv;
+    return 1;
+}
+
+static void tri_normal(const double *v, double n[3])
+{
+    double e1[3], e2[3];
+    sub3(v + 3, v, e1);
+    sub3(v + 6, v, e2);
+    cross3(e1, e2, n);
+    normalize3(n);
+}
+
+static int sph_roots(const double *s, const double o[3], const double d[3], double *t0, double *t1)
+{
+    double oc[3];
+    sub3(o, s, oc);
+    double b = dot3(oc, d);
+    double c = dot3(oc, oc) - s[3] * s[3];
+    double disc = b * b - c;
+    if (disc < 0.0) return 0;
+    double sq = sqrt(disc);
+    *t0 = -b - sq;
+    *t1 = -b + sq;
+    return 1;
+}
+
+static int pln_isect(const double *p, const double o[3], const double d[3], double *t)
+{
+    double den = dot3(p, d);
+    if (den == 0.0) return 0;
+    *t = (p[3] - dot3(p, o)) / den;
+    return 1;
+}
+
+/* Exit through the absorbing box; face 0..2 = min x,y,z, 3..5 = max x,y,z. */
+static double box_exit(const double *box, const double o[3], const double d[3], int *face)
+{
+    double best = INFINITY;
+    int f = -1;
+    for (int i = 0; i < 3; ++i) {
+        double t;
+        int fi;
+        if (d[i] > 0.0) {
+            t = (box[3 + i] - o[i]) / d[i];
+            fi = 3 + i;
+        } else if (d[i] < 0.0) {
+            t = (box[i] - o[i]) / d[i];
+            fi = i;
+        } else {
+            continue;
+        }
+        if (t < best) {
+            best = t;
+            f = fi;
+        }
+    }
+    *face = f;
+    return best;
+}
+
+typedef struct {
+    double t;
+    int64_t id;
+    int face;
+} hit;
+
+static void consider(hit *h, double t, int64_t id)
+{
+    if (t < h->t || (t == h->t && id < h->id)) {
+        h->t = t;
+        h->id = id;
+    }
+}
+
+/* Closest hit over every primitive with t > EPS_T.  The flat primitive the
+ * ray has just left (skip) is excluded; the box exit always exists and loses
+ * ties because its id is the largest. */
+static hit closest(const octx *C, const double o[3], const double d[3], int64_t skip)
+{
+    const or_scene *s = C->s;
+    hit h;
+    h.t = box_exit(s->box, o, d, &h.face);
+    h.id = C->id_box;
+    for (int64_t i = 0; i < s->n_tri; ++i) {
+        double t;
+        if (i == skip) continue;
+        if (tri_isect(s->tri + 9 * i, o, d, &t) && t > EPS_T) consider(&h, t, i);
+    }
+    for (int64_t j = 0; j < s->n_sph; ++j) {
+        double t0, t1;
+        if (!sph_roots(s->sph + 4 * j, o, d, &t0, &t1)) continue;
+        if (t0 > EPS_T) consider(&h, t0, C->id_sph0 + j);
+        else if (t1 > EPS_T) consider(&h, t1, C->id_sph0 + j);
+    }
+    for (int64_t p = 0; p < s->n_pln; ++p) {
+        double t;
+        if (C->id_pln0 + p == skip) continue;
+        if (pln_isect(s->pln + 4 * p, o, d, &t) && t > EPS_T) consider(&h, t, C->id_pln0 + p);
+    }
+    return h;
+}
+
+int64_t or_closest_hit(const or_scene *s, const double o[3], const double d[3], int64_t skip, double *t_hit)
+{
+    octx C;
+    memset(&C, 0, sizeof(C));
+    C.s = s;
+    C.id_sph0 = s->n_tri;
+    C.id_pln0 = s->n_tri + s->n_sph;
+    C.id_box = s->n_tri + s->n_sph + s->n_pln;
+    hit h = closest(&C, o, d, skip);
+    *t_hit = h.t;
+    return h.id;
+}
+
+/* Every crossing of the open segment (EPS_T, t_max - EPS_T); returns the
+ * count and, if ts != NULL, up to cap crossing distances (unsorted). */
+int64_t or_crossings(const or_scene *s, const double o[3], const double d[3], double t_max, double *ts,
+                     int64_t cap)
+{
+    int64_t n = 0;
+    double lo = EPS_T, hi = t_max - EPS_T;
+    for (int64_t i = 0; i < s->n_tri; ++i) {
+        double t;
+        if (tri_isect(s->tri + 9 * i, o, d, &t) && t > lo && t < hi) {
+            if (ts && n < cap) ts[n] = t;
+            ++n;
+        }
+    }
+    for (int64_t j = 0; j < s->n_sph; ++j) {
+        double t0, t1;
+        if (!sph_roots(s->sph + 4 * j, o, d, &t0, &t1)) continue;
+        if (t0 > lo && t0 < hi) { if (ts && n < cap) ts[n] = t0; ++n; }
+        if (t1 > lo && t1 < hi) { if (ts && n < cap) ts[n] = t1; ++n; }
+    }
+    for (int64_t p = 0; p < s->n_pln; ++p) {
+        double t;
+        if (pln_isect(s->pln + 4 * p, o, d, &t) && t > lo && t < hi) {
+            if (ts && n < cap) ts[n] = t;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------ records */
+static void log_event(sink *K, int64_t kind, int64_t tx, int64_t elem, int64_t seg, int64_t id, double t,
+                      double v, const double p[3])
+{
+    if (!K->ev) return;
+    if (K->n < K->cap) {
+        or_event *E = &K->ev[K->n];
+        E->kind = kind; E->tx = tx; E->elem = elem; E->seg = seg; E->id = id;
+        E->t = t; E->value = v;
+        E->x = p ? p[0] : 0.0; E->y = p ? p[1] : 0.0; E->z = p ? p[2] : 0.0;
+    }
+    K->n++;
+}
+
+/* Record an arriving contribution into the element's time-pressure signal
+ * (Sec. 2.3 "Phase Calculation").  Sample n holds arrivals in
+ * [n/fs, (n+1)/fs) (nearest / box filter); the linear (tent) filter splits a
+ * record between the two samples whose centres (n + 1/2)/fs bracket it.
+ * Arrivals at or after S/fs fall outside the record window. */
+static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, int64_t seg, int64_t id,
+                   double t, double v, const double p[3])
+{
+    const or_acq *a = C->a;
+    log_event(K, kind, tx, e, seg, id, t, v, p);
+    if (!(t < C->t_max) || t < 0.0) {
+        K->st.dropped++;
+        return;
+    }
+    K->st.records++;
+    double x = t * a->f_s;
+    double fr = x - floor(x);
+    if (fr < 1e-5 || fr > 1.0 - 1e-5) K->st.edge_band++;
+    if (!K->hist) return;
+    double *h = K->hist + (tx * a->n_elements + e) * a->n_samples;
+    if (a->binning == 0) {
+        int64_t n = (int64_t)floor(x);
+        if (n >= 0 && n < a->n_samples) h[n] += v;
+    } else {
+        double tau = x - 0.5;
+        double f0 = floor(tau);
+        int64_t n0 = (int64_t)f0;
+        double f = tau - f0;
+        if (n0 >= 0 && n0 < a->n_samples) h[n0] += (1.0 - f) * v;
+        if (n0 + 1 >= 0 && n0 + 1 < a->n_samples) h[n0 + 1] += f * v;
+    }
+}
+
+/* ------------------------------------------ transducer sampling at scatterers */
+/* A point scatterer k whose capture capsule (radius r_s) contains the primary
+ * segment re-radiates isotropically with signed albedo a_k.  A secondary ray
+ * is cast from the projection point q to the centre of a uniformly chosen
+ * element e' (Sec. 2.3 "Transducer Sampling").  It keeps its straight
+ * direction and is multiplied by the transmitted fraction 1 - A_r^2 at every
+ * boundary it crosses (zero on total internal reflection), and by the
+ * attenuation and delay of each medium along it.  The receive directivity
+ * (Eq. 13) uses the angle between the reversed arrival direction and the
+ * element normal.  The element subtends area*cos(alpha)/r^2 of the 4 pi
+ * re-radiation, divided by the 1/E choice probability. */
+static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg, int64_t k,
+                        const double o[3], const double d[3], double w, double t, int64_t med, double s)
+{
+    const or_acq *a = C->a;
+    const or_scene *sc = C->s;
+    double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+    double wq = w * exp(-C->ka[med] * s);
+    double tq = t + s * C->inv_c[med];
+    uint32_t x[4];
+    draw(C, ray, e, tx, seg, 2, (uint32_t)k, x);
+    int64_t er = (int64_t)(((uint64_t)x[0] * (uint64_t)a->n_elements) >> 32);
+    double v[3] = {C->xe[er] - q[0], 0.0 - q[1], 0.0 - q[2]};
+    double dist = sqrt(dot3(v, v));
+    double vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
+    double cos_a = -vh[2];
+    double ca = cos_a > 1.0 ? 1.0 : (cos_a < -1.0 ? -1.0 : cos_a);
+    double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
+    K->st.scatter_events++;
+    if (fdir <= 0.0) {
+        K->st.nee_zero++;
+        return;
+    }
+    K->st.nee_cast++;
+    /* every crossing of the secondary ray, in any order */
+    double T = 1.0, sum_a = 0.0, sum_c = 0.0;
+    double lo = EPS_T, hi = dist - EPS_T;
+    for (int64_t pid = 0; pid < sc->n_tri + sc->n_sph + sc->n_pln; ++pid) {
+        double ts[2];
+        int nt = 0;
+        double ng[2][3];
+        int64_t mf, mb;
+        if (pid < sc->n_tri) {
+            double tt;
+            if (tri_isect(sc->tri + 9 * pid, q, vh, &tt) && tt > lo && tt < hi) {
+                ts[nt] = tt;
+                tri_normal(sc->tri + 9 * pid, ng[nt]);
+                ++nt;
+            }
+            mf = sc->tri_mat[2 * pid];
+            mb = sc->tri_mat[2 * pid + 1];
+        } else if (pid < sc->n_tri + sc->n_sph) {
+            int64_t j = pid - sc->n_tri;
+            const double *sp = sc->sph + 4 * j;
+            double t0, t1;
+            if (sph_roots(sp, q, vh, &t0, &t1)) {
+                double tr[2] = {t0, t1};
+                for (int r = 0; r < 2; ++r) {
+                    if (tr[r] > lo && tr[r] < hi) {
+                        ts[nt] = tr[r];
+                        for (int i = 0; i < 3; ++i) ng[nt][i] = (q[i] + tr[r] * vh[i] - sp[i]) / sp[3];
+                        ++nt;
+                    }
+                }
+            }
+            mf = sc->sph_mat[2 * j];
+            mb = sc->sph_mat[2 * j + 1];
+        } else {
+            int64_t p = pid - sc->n_tri - sc->n_sph;
+            double tt;
+            if (pln_isect(sc->pln + 4 * p, q, vh, &tt) && tt > lo && tt < hi) {
+                ts[nt] = tt;
+                for (int i = 0; i < 3; ++i) ng[nt][i] = sc->pln[4 * p + i];
+                ++nt;
+            }
+            mf = sc->pln_mat[2 * p];
+            mb = sc->pln_mat[2 * p + 1];
+        }
+        for (int c = 0; c < nt; ++c) {
+            double dn = dot3(vh, ng[c]);
+            int64_t before = dn < 0.0 ? mf : mb, after = dn < 0.0 ? mb : mf;
+            T *= transmit_fraction(sc->mat[3 * before], sc->mat[3 * after], fabs(dn));
+            sum_a += (C->ka[after] - C->ka[before]) * (dist - ts[c]);
+            sum_c += (C->inv_c[after] - C->inv_c[before]) * (dist - ts[c]);
+        }
+    }
+    if (T == 0.0) {
+        K->st.nee_blocked++;
+        return;
+    }
+    double att = exp(-(C->ka[med] * dist + sum_a));
+    double tc = tq + dist * C->inv_c[med] + sum_c;
+    double amp = sc->scat[4 * k + 3];
+    double c = wq * amp * (double)a->n_elements * C->area_e * cos_a * fdir / (4.0 * PI * dist * dist) * T * att;
+    record(C, K, 1, tx, er, seg, k, tc, c, q);
+}
+
+/* All scatterers whose capture capsule the segment [0, t_seg) passes:
+ * projection s = (p_k - o).d in [0, t_seg) and perpendicular distance <= r_s. */
+static void scatter_events(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg,
+                           const double o[3], const double d[3], double w, double t, int64_t med, double t_seg)
+{
+    const or_scene *sc = C->s;
+    double r2 = C->a->r_s * C->a->r_s;
+    for (int64_t k = 0; k < sc->n_scat; ++k) {
+        double p[3];
+        sub3(sc->scat + 4 * k, o, p);
+        double s = dot3(p, d);
+        if (!(s >= 0.0 && s < t_seg)) continue;
+        double perp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
+        if (dot3(perp, perp) > r2) continue;
+        scatter_nee(C, K, tx, e, ray, seg, k, o, d, w, t, med, s);
+    }
+}
+
+/* ------------------------------------------------------------- path tracing */
+/* Follows one primary ray (Sec. 2.3 "Ray Traversal") for segments
+ * 0..max_bounces.  Each segment: closest hit; scatterer events on the
+ * segment; transport (attenuation exp(-alpha f d), delay d/c, path length);
+ * then the hit: the box exit through the transducer aperture records
+ * weight x directivity into the element it lands on, any other box exit
+ * absorbs, an impedance boundary draws reflect-or-transmit unless the
+ * interaction limit is reached.  The ray also ends when its path exceeds
+ * max_path (the segment is clipped there) or its time leaves the window. */
+static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, const double o_in[3],
+                       const double d_in[3], double w, double t, int64_t med)
+{
+    const or_acq *a = C->a;
+    const or_scene *sc = C->s;
+    double o[3] = {o_in[0], o_in[1], o_in[2]}, d[3] = {d_in[0], d_in[1], d_in[2]};
+    double len = 0.0;
+    int64_t last = -1;
+    K->st.rays++;
+    for (int64_t b = 0; b <= a->max_bounces; ++b) {
+        K->st.segments++;
+        hit h = closest(C, o, d, last);
+        double t_seg = h.t;
+        int clipped = 0;
+        if (len + t_seg > a->max_path) {
+            t_seg = a->max_path - len;
+            clipped = 1;
+        }
+        scatter_events(C, K, tx, e, ray, b, o, d, w, t, med, t_seg);
+        w *= exp(-C->ka[med] * t_seg);
+        t += t_seg * C->inv_c[med];
+        len += t_seg;
+        for (int i = 0; i < 3; ++i) o[i] += t_seg * d[i];
+        if (clipped) {
+            K->st.term_path++;
+            log_event(K, 4, tx, e, b, -3, t, w, o);
+            return;
+        }
+        if (t >= C->t_max) {
+            K->st.term_time++;
+            log_event(K, 4, tx, e, b, -2, t, w, o);
+            return;
+        }
+        if (h.id == C->id_box) {
+            if (h.face == 2 && fabs(o[0]) <= C->half_ap && fabs(o[1]) <= 0.5 * a->elevation) {
+                int64_t er = (int64_t)floor((o[0] + C->half_ap) / a->pitch);
+                if (er < 0) er = 0;
+                if (er > a->n_elements - 1) er = a->n_elements - 1;
+                double ca = -d[2];
+                ca = ca > 1.0 ? 1.0 : (ca < -1.0 ? -1.0 : ca);
+                double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
+                if (fdir > 0.0) {
+                    K->st.direct_hits++;
+                    record(C, K, 0, tx, er, b, -1, t, w * fdir, o);
+                }
+            }
+            K->st.term_box++;
+            log_event(K, 4, tx, e, b, -1, t, w, o);
+            return;
+        }
+        if (b == a->max_bounces) {
+            K->st.term_bounce++;
+            log_event(K, 4, tx, e, b, -4, t, w, o);
+            return;
+        }
+        /* impedance boundary */
+        double ng[3];
+        int64_t mf, mb;
+        if (h.id < C->id_sph0) {
+            tri_normal(sc->tri + 9 * h.id, ng);
+            mf = sc->tri_mat[2 * h.id];
+            mb = sc->tri_mat[2 * h.id + 1];
+        } else if (h.id < C->id_pln0) {
+            const double *sp = sc->sph + 4 * (h.id - C->id_sph0);
+            for (int i = 0; i < 3; ++i) ng[i] = (o[i] - sp[i]) / sp[3];
+            mf = sc->sph_mat[2 * (h.id - C->id_sph0)];
+            mb = sc->sph_mat[2 * (h.id - C->id_sph0) + 1];
+        } else {
+            const double *pp = sc->pln + 4 * (h.id - C->id_pln0);
+            for (int i = 0; i < 3; ++i) ng[i] = pp[i];
+            mf = sc->pln_mat[2 * (h.id - C->id_pln0)];
+            mb = sc->pln_mat[2 * (h.id - C->id_pln0) + 1];
+        }
+        uint32_t x[4];
+        draw(C, ray, e, tx, b, 1, 0, x);
+        double y = unif(x[0]), R, nd[3];
+        int from_front;
+        int refl = fresnel_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], y, nd, &R, &from_front);
+        int64_t before = from_front ? mf : mb, after = from_front ? mb : mf;
+        if (before != med) K->st.media_mismatch++;
+        if (refl) {
+            if (R >= 1.0) K->st.tir++;
+            else K->st.reflect++;
+            med = before;
+        } else {
+            K->st.transmit++;
+            med = after;
+        }
+        log_event(K, refl ? 2 : 3, tx, e, b, h.id, t, w, o);
+        d[0] = nd[0]; d[1] = nd[1]; d[2] = nd[2];
+        last = (h.id < C->id_sph0 || h.id >= C->id_pln0) ? h.id : -1;
+    }
+}
+
+static void stats_add(or_stats *a, const or_stats *b)
+{
+    const int64_t *pb = (const int64_t *)b;
+    int64_t *pa = (int64_t *)a;
+    for (size_t i = 0; i < sizeof(or_stats) / sizeof(int64_t); ++i) pa[i] += pb[i];
+}
+
+static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t stride, double *ch_raw,
+                      or_stats *st_out)
+{
+    if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
+        a->rays_per_element < 0 || a->max_bounces < 0 || a->max_bounces > 65535 || stride <= 0)
+        return -1;
+    octx C;
+    if (ctx_init(&C, a, s)) return -2;
+    int nt = n_threads;
+#ifdef _OPENMP
+    if (nt <= 0) nt = omp_get_max_threads();
+#else
+    nt = 1;
+#endif
+    if (nt < 1) nt = 1;
+    size_t nh = (size_t)(a->n_tx * a->n_elements * a->n_samples);
+    sink *sinks = (sink *)calloc((size_t)nt, sizeof(sink));
+    if (!sinks) return -2;
+    for (int i = 0; i < nt; ++i) {
+        sinks[i].hist = (double *)calloc(nh, sizeof(double));
+        if (!sinks[i].hist) return -2;
+    }
+    int64_t per_el = (a->rays_per_element + stride - 1) / stride;
+    int64_t n_work = a->n_tx * a->n_elements * per_el;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+    for (int64_t i = 0; i < n_work; ++i) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int64_t rr = (i % per_el) * stride;
+        int64_t e = (i / per_el) % a->n_elements;
+        int64_t tx = i / (per_el * a->n_elements);
+        double o[3], d[3], w;
+        emit(&C, tx, e, (uint32_t)rr, o, d, &w);
+        trace_path(&C, &sinks[tid], tx, e, (uint32_t)rr, o, d, w, C.tau[tx * a->n_elements + e],
+                   s->top_medium);
+    }
+    memset(ch_raw, 0, nh * sizeof(double));
+    or_stats st;
+    memset(&st, 0, sizeof(st));
+    for (int i = 0; i < nt; ++i) {
+        for (size_t j = 0; j < nh; ++j) ch_raw[j] += sinks[i].hist[j];
+        stats_add(&st, &sinks[i].st);
+        free(sinks[i].hist);
+    }
+    free(sinks);
+    if (st_out) *st_out = st;
+    ctx_free(&C);
+    return 0;
+}
+
+int or_trace(const or_acq *a, const or_scene *s, int n_threads, double *ch_raw, or_stats *st)
+{
+    return trace_impl(a, s, n_threads, 1, ch_raw, st);
+}
+
+int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, double *ch_raw,
+                    or_stats *st)
+{
+    return trace_impl(a, s, n_threads, ray_stride, ch_raw, st);
+}
+
+/* Explicit rays (origin, direction, weight, time, ids) traced one by one;
+ * logs every record and interface event. */
+int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n, or_event *ev, int64_t cap,
+                  int64_t *n_ev, double *ch_raw, or_stats *st_out)
+{
+    octx C;
+    if (ctx_init(&C, a, s)) return -2;
+    sink K;
+    memset(&K, 0, sizeof(K));
+    K.ev = ev;
+    K.cap = cap;
+    K.hist = ch_raw;
+    if (ch_raw) memset(ch_raw, 0, sizeof(double) * (size_t)(a->n_tx * a->n_elements * a->n_samples));
+    for (int64_t i = 0; i < n; ++i) {
+        const or_ray *r = &rays[i];
+        trace_path(&C, &K, r->tx, r->elem, (uint32_t)r->ray, r->o, r->d, r->w, r->t, r->medium);
+    }
+    if (n_ev) *n_ev = K.n;
+    if (st_out) *st_out = K.st;
+    ctx_free(&C);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- pulse Eq. 14 */
+/* Analytic pulse h[m] = g(m/fs) (sin(2 pi fc m/fs) - i cos(2 pi fc m/fs)),
+ * whose real part is Eq. 14 with the Gaussian written exp(-t^2/(2 sigma^2));
+ * sigma is set so the envelope's full width at half maximum equals n_cycles
+ * periods.  Taps |m| <= K = ceil(3 sigma fs). */
+int or_pulse_taps(const or_acq *a, double *taps, int64_t cap)
+{
+    double sig = a->n_cycles / (2.0 * sqrt(2.0 * log(2.0)) * a->f_c);
+    int K = (int)ceil(3.0 * sig * a->f_s);
+    if (taps == NULL) return K;
+    if (2 * K + 1 > cap) return -1;
+    for (int m = -K; m <= K; ++m) {
+        double tm = (double)m / a->f_s;
+        double g = exp(-tm * tm / (2.0 * sig * sig));
+        double ph = 2.0 * PI * a->f_c * tm;
+        taps[2 * (m + K)] = g * sin(ph);
+        taps[2 * (m + K) + 1] = -g * cos(ph);
+    }
+    return K;
+}
+
+/* ch_rf[n] = sum_m h[m] ch_raw[n - m], zero outside the record. */
+int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf)
+{
+    int K = or_pulse_taps(a, NULL, 0);
+    double *h = (double *)malloc(sizeof(double) * (size_t)(2 * (2 * K + 1)));
+    if (!h) return -2;
+    or_pulse_taps(a, h, 2 * K + 1);
+    int64_t S = a->n_samples, nch = n_channels;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        const double *x = ch_raw + ch * S;
+        double *y = ch_rf + 2 * ch * S;
+        for (int64_t n = 0; n < S; ++n) {
+            double re = 0.0, im = 0.0;
+            for (int m = -K; m <= K; ++m) {
+                int64_t j = n - m;
+                if (j < 0 || j >= S) continue;
+                re += h[2 * (m + K)] * x[j];
+                im += h[2 * (m + K) + 1] * x[j];
+            }
+            y[2 * n] = re;
+            y[2 * n + 1] = im;
+        }
+    }
+    free(h);
+    return 0;
+}
+
+/* ------------------------------------------------------------------- DAS */
+/* Plane-wave delay-and-sum with coherent compounding: the transmit delay is
+ * the steered plane wavefront's arrival at the pixel, referenced like the
+ * emission delays; the receive delay is the straight path back to each
+ * element; both use c0.  Sample n stands for time (n + 1/2)/fs; the analytic
+ * channel signal is linearly interpolated (zero outside [0, S-1)), weighted
+ * by a Hann window over the receive aperture and summed over elements and
+ * transmits. */
+static void das_point(const or_acq *a, const double *xe, const double *apod, double x, double z,
+                      const double *ch_rf, double out[2])
+{
+    int64_t E = a->n_elements, S = a->n_samples;
+    double re = 0.0, im = 0.0;
+    for (int64_t tx = 0; tx < a->n_tx; ++tx) {
+        double st = sin(a->angles[tx]), ct = cos(a->angles[tx]);
+        double xref = st >= 0 ? xe[0] : xe[E - 1];
+        double ttx = ((x - xref) * st + z * ct) / a->c0;
+        for (int64_t e = 0; e < E; ++e) {
+            double dx = x - xe[e];
+            double trx = sqrt(dx * dx + z * z) / a->c0;
+            double idx = (ttx + trx) * a->f_s - 0.5;
+            double f0 = floor(idx);
+            int64_t i0 = (int64_t)f0;
+            double fr = idx - f0;
+            if (i0 < 0 || i0 >= S - 1) continue;
+            const double *p = ch_rf + 2 * ((tx * E + e) * S + i0);
+            re += apod[e] * ((1.0 - fr) * p[0] + fr * p[2]);
+            im += apod[e] * ((1.0 - fr) * p[1] + fr * p[3]);
+        }
+    }
+    out[0] = re;
+    out[1] = im;
+}
+
+static int das_tables(const or_acq *a, double **xe, double **apod)
+{
+    int64_t E = a->n_elements;
+    *xe = (double *)malloc(sizeof(double) * (size_t)E);
+    *apod = (double *)malloc(sizeof(double) * (size_t)E);
+    if (!*xe || !*apod) return -2;
+    for (int64_t e = 0; e < E; ++e) {
+        (*xe)[e] = ((double)e - 0.5 * (double)(E - 1)) * a->pitch;
+        (*apod)[e] = 0.5 - 0.5 * cos(2.0 * PI * ((double)e + 0.5) / (double)E);
+    }
+    return 0;
+}
+
+int or_das(const or_acq *a, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
+           const double *ch_rf, int n_threads, double *iq)
+{
+    double *xe, *apod;
+    if (das_tables(a, &xe, &apod)) return -2;
+    double dx = nx > 1 ? (x1 - x0) / (double)(nx - 1) : 0.0;
+    double dz = nz > 1 ? (z1 - z0) / (double)(nz - 1) : 0.0;
+    int nt = n_threads;
+#ifdef _OPENMP
+    if (nt <= 0) nt = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+    for (int64_t ix = 0; ix < nx; ++ix) {
+        for (int64_t iz = 0; iz < nz; ++iz)
+            das_point(a, xe, apod, x0 + (double)ix * dx, z0 + (double)iz * dz, ch_rf, iq + 2 * (ix * nz + iz));
+    }
+    (void)nt;
+    free(xe);
+    free(apod);
+    return 0;
+}
+
+int or_das_points(const or_acq *a, const double *xz, int64_t n, const double *ch_rf, double *iq)
+{
+    double *xe, *apod;
+    if (das_tables(a, &xe, &apod)) return -2;
+    for (int64_t i = 0; i < n; ++i) das_point(a, xe, apod, xz[2 * i], xz[2 * i + 1], ch_rf, iq + 2 * i);
+    free(xe);
+    free(apod);
+    return 0;
+}
+
+/* Envelope |IQ| and log compression to a dynamic range of dr_db decibels. */
+int or_envelope(int64_t n, const double *iq, double dr_db, double *env, double *bmode)
+{
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        env[i] = sqrt(iq[2 * i] * iq[2 * i] + iq[2 * i + 1] * iq[2 * i + 1]);
+        if (env[i] > mx) mx = env[i];
+    }
+    if (!bmode) return 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double db = (mx > 0.0 && env[i] > 0.0) ? 20.0 * log10(env[i] / mx) : -dr_db;
+        bmode[i] = db < -dr_db ? -dr_db : db;
+    }
+    return 0;
+}

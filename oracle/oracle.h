@@ -1,0 +1,97 @@
+/*
+ * FP64 CPU oracle for the full-path ultrasound Monte Carlo tracer
+ * (UltraRay, arXiv 2501.05828) and its plane-wave beamformer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code
+ * with the HIP library: every formula here is written out independently from
+ * the paper (and from the readings listed where the paper is silent).
+ *
+ * All arithmetic is IEEE double precision.  Intersections are brute force
+ * over every primitive (no acceleration structure), so the result is the
+ * plain definition of "closest hit" / "every crossing".
+ *
+ * Units: metres, seconds, m/s; Z in MRayl; alpha in dB/(cm MHz).
+ * Frame: x lateral, y elevation, z depth; transducer face z = 0 facing +z.
+ */
+#ifndef UR_ORACLE_H
+#define UR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Every field is 8 bytes wide so the layout is identical for ctypes. */
+typedef struct {
+    int64_t n_elements, n_tx, n_samples, rays_per_element, max_bounces, binning;
+    double pitch, elevation, f_c, f_s, c0, n_cycles, r_s, max_path, alpha_m, alpha_c;
+    uint64_t seed;
+    const double *angles;      /* [n_tx] steering angles, rad                         */
+    const float *pdf;          /* [n_tx][n_elements][1024] mixed proposal q', or NULL */
+    const float *cdf;          /* [n_tx][n_elements][1024] inclusive CDF of q', or NULL */
+} or_acq;
+
+typedef struct {
+    int64_t n_mat, n_tri, n_sph, n_pln, n_scat, top_medium;
+    const double *mat;         /* [n_mat][3]: Z, alpha, c        */
+    const double *box;         /* [6]: min xyz, max xyz          */
+    const double *tri;         /* [n_tri][9]: v0 v1 v2           */
+    const int32_t *tri_mat;    /* [n_tri][2]: front, back        */
+    const double *sph;         /* [n_sph][4]: centre, radius     */
+    const int32_t *sph_mat;    /* [n_sph][2]: outside, inside    */
+    const double *pln;         /* [n_pln][4]: n, d with n.x = d  */
+    const int32_t *pln_mat;    /* [n_pln][2]: front, back        */
+    const double *scat;        /* [n_scat][4]: position, amplitude */
+} or_scene;
+
+typedef struct {
+    int64_t rays, segments, reflect, transmit, tir, scatter_events, nee_zero, nee_cast,
+            nee_blocked, direct_hits, records, dropped, edge_band, term_box, term_bounce,
+            term_time, term_path, media_mismatch;
+} or_stats;
+
+/* One entry of a path log (explicit-ray tracing). */
+typedef struct {
+    int64_t kind;   /* 0 direct-hit record, 1 scatter (NEE) record, 2 reflect, 3 transmit, 4 end */
+    int64_t tx, elem, seg, id;  /* elem: receiving element for records; id: scatterer or primitive */
+    double t, value, x, y, z;   /* t: arrival / event time; value: contribution or weight */
+} or_event;
+
+/* Explicit ray: origin, unit direction, weight, start time, ids for the RNG. */
+typedef struct {
+    double o[3], d[3], w, t;
+    int64_t tx, elem, ray, medium;
+} or_ray;
+
+/* Global primitive ids: triangles, then spheres, then planes, then the box. */
+
+int or_trace(const or_acq *a, const or_scene *s, int n_threads, double *ch_raw, or_stats *st);
+int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n,
+                  or_event *ev, int64_t cap, int64_t *n_ev, double *ch_raw, or_stats *st);
+int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride,
+                    double *ch_raw, or_stats *st);
+
+int or_pulse_taps(const or_acq *a, double *taps, int64_t cap);   /* returns K, taps [2K+1][2] */
+int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf);
+int or_das(const or_acq *a, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
+           const double *ch_rf, int n_threads, double *iq);
+int or_das_points(const or_acq *a, const double *xz, int64_t n, const double *ch_rf, double *iq);
+int or_envelope(int64_t n, const double *iq, double dr_db, double *env, double *bmode);
+
+/* Building blocks exposed for the pins. */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void or_hemisphere(double a, double b, double d[3]);
+double or_directivity(double alpha, double alpha_m, double alpha_c);
+int or_interface(const double d[3], const double n[3], double z_front, double z_back, double y,
+                 double out_d[3], double *R);
+double or_delay(const or_acq *a, int64_t tx, int64_t e);
+int64_t or_closest_hit(const or_scene *s, const double o[3], const double d[3], int64_t skip,
+                       double *t_hit);
+int64_t or_crossings(const or_scene *s, const double o[3], const double d[3], double t_max,
+                     double *ts, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,283 @@
+"""Seeded synthetic workloads (scenes, probe, acquisition, image grid).
+
+This module only *builds inputs*: geometry, material tables, scatterer
+clouds and parameter values.  It contains none of the simulation method's
+arithmetic (no delays, no physics, no sampling), so both the HIP library and
+the CPU oracle can be fed from it without sharing any method code.
+
+Units are SI (metres, seconds, m/s) except impedance Z in MRayl and
+attenuation alpha in dB/(cm MHz).  Frame: x lateral, y elevation, z depth;
+the transducer face is the plane z = 0 and faces +z.
+
+The phantoms stand in for the paper's CT-derived vertebra in water (Sec. 4):
+the real mesh and acquisitions are not available, so procedural tubes with
+seeded surface noise, layered soft tissue and point-scatterer clouds of the
+stated sizes are used instead.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MM = 1e-3
+
+NEAREST = 0
+LINEAR = 1
+
+
+@dataclass
+class Scene:
+    materials: np.ndarray        # (M,3) float64: Z [MRayl], alpha [dB/(cm MHz)], c [m/s]
+    box: np.ndarray              # (6,) float64: xmin, ymin, zmin, xmax, ymax, zmax [m]
+    top_medium: int              # material touching the transducer face
+    tri: np.ndarray              # (NT,9) float64: v0, v1, v2
+    tri_mat: np.ndarray          # (NT,2) int32: material on the front / back side
+    sph: np.ndarray              # (NS,4) float64: centre xyz, radius
+    sph_mat: np.ndarray          # (NS,2) int32: outside / inside material
+    pln: np.ndarray              # (NP,4) float64: unit normal n, offset d (n.x = d)
+    pln_mat: np.ndarray          # (NP,2) int32: front (n side) / back material
+    scat: np.ndarray             # (K,4) float64: position xyz, amplitude
+
+    def counts(self) -> dict:
+        return dict(materials=len(self.materials), triangles=len(self.tri),
+                    spheres=len(self.sph), planes=len(self.pln),
+                    scatterers=len(self.scat))
+
+
+@dataclass
+class Acquisition:
+    n_elements: int
+    pitch: float                 # m
+    elevation: float             # m (element height along y)
+    f_c: float                   # Hz
+    f_s: float                   # Hz
+    n_samples: int
+    angles: np.ndarray           # (T,) steering angles [rad]
+    rays_per_element: int        # rays per element per transmit
+    max_bounces: int
+    max_path: float              # m
+    alpha_m: float               # main-beam angle [rad]
+    alpha_c: float               # cutoff angle [rad]
+    c0: float                    # beamforming / delay speed of sound [m/s]
+    n_cycles: float              # pulse length in cycles
+    r_s: float                   # scatterer capture radius [m]
+    binning: int = NEAREST
+
+    @property
+    def n_tx(self) -> int:
+        return int(len(self.angles))
+
+    @property
+    def n_rays(self) -> int:
+        return self.n_tx * self.n_elements * self.rays_per_element
+
+
+@dataclass
+class Grid:
+    nx: int
+    nz: int
+    x0: float
+    x1: float
+    z0: float
+    z1: float
+
+
+@dataclass
+class Workload:
+    name: str
+    scene: Scene
+    acq: Acquisition
+    grid: Grid
+    seed: int = 0x5EED0001       # Philox key for the tracer
+    scene_seed: int = 1
+    apod: str = "hann"
+    extra: dict = field(default_factory=dict)
+
+    def with_rays(self, rays_per_element: int) -> "Workload":
+        acq = dataclasses.replace(self.acq, rays_per_element=int(rays_per_element))
+        return dataclasses.replace(self, acq=acq)
+
+
+def _empty_i2():
+    return np.zeros((0, 2), np.int32)
+
+
+def _f64(x, n):
+    a = np.asarray(x, np.float64).reshape(-1, n)
+    return np.ascontiguousarray(a)
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, np.int32).reshape(-1, 2))
+
+
+def tube_mesh(rng, axis_x, axis_z, n_phi, n_y, y_half, r_mean, r_amp):
+    """Open tube along y with radius r_mean + r_amp * n(phi, y).
+
+    n is a normalised sum of three seeded sinusoids in (phi, y), so it stays in
+    [-1, 1] and is periodic in phi.  Triangles are wound so that the geometric
+    normal (v1-v0)x(v2-v0) points out of the tube.
+    """
+    m = rng.integers(2, 7, size=3)
+    ky = rng.integers(1, 4, size=3) * (2 * np.pi / (2 * y_half))
+    amp = rng.uniform(0.5, 1.0, size=3)
+    ph = rng.uniform(0, 2 * np.pi, size=3)
+    phi = np.arange(n_phi) * (2 * np.pi / n_phi)
+    y = -y_half + np.arange(n_y + 1) * (2 * y_half / n_y)
+    P, Y = np.meshgrid(phi, y, indexing="ij")            # (n_phi, n_y+1)
+    noise = sum(amp[i] * np.sin(m[i] * P + ky[i] * Y + ph[i]) for i in range(3)) / amp.sum()
+    r = r_mean + r_amp * noise
+    V = np.stack([axis_x + r * np.cos(P), Y, axis_z + r * np.sin(P)], -1)
+    i = np.arange(n_phi)[:, None]
+    j = np.arange(n_y)[None, :]
+    ip = (i + 1) % n_phi
+    a = V[i, j]
+    b = V[i, j + 1]
+    c = V[ip, j]
+    d = V[ip, j + 1]
+    t1 = np.stack([a, b, c], -2)                           # (n_phi, n_y, 3, 3)
+    t2 = np.stack([c, b, d], -2)
+    tri = np.stack([t1, t2], 2).reshape(-1, 9)
+    return np.ascontiguousarray(tri, np.float64)
+
+
+def tiny(scene_seed: int = 1, rays_per_element: int = 1024, n_scatterers: int = 2000) -> Workload:
+    """Plain tracer, tiny: 64 elements, one 0-degree plane wave, 40 mm cube.
+
+    Planar reflector at 20 mm depth (Z 7.8), one 3 mm sphere (Z 3.0) whose
+    centre is uniform in the box and rejected if it would cut the reflector,
+    2000 uniform scatterers with N(0,1) amplitudes.
+    """
+    rng = np.random.default_rng(scene_seed)
+    box = np.array([-20 * MM, -20 * MM, 0.0, 20 * MM, 20 * MM, 40 * MM])
+    mats = np.array([[1.5, 0.5, 1540.0],     # 0: medium
+                     [7.8, 0.5, 1540.0],     # 1: reflector half-space z > 20 mm
+                     [3.0, 0.5, 1540.0]])    # 2: sphere
+    r = 3 * MM
+    while True:
+        cen = rng.uniform(box[:3] + r, box[3:] - r)
+        if abs(cen[2] - 20 * MM) >= r:
+            break
+    sph = np.array([[cen[0], cen[1], cen[2], r]])
+    sph_mat = np.array([[0 if cen[2] < 20 * MM else 1, 2]])
+    pln = np.array([[0.0, 0.0, 1.0, 20 * MM]])
+    pln_mat = np.array([[1, 0]])
+    pos = rng.uniform(box[:3], box[3:], size=(n_scatterers, 3))
+    amp = rng.normal(0.0, 1.0, size=(n_scatterers, 1))
+    scene = Scene(_f64(mats, 3), box, 0, np.zeros((0, 9)), _empty_i2(),
+                  _f64(sph, 4), _i32(sph_mat), _f64(pln, 4), _i32(pln_mat),
+                  _f64(np.hstack([pos, amp]), 4))
+    acq = Acquisition(64, 0.3 * MM, 4 * MM, 5e6, 40e6, 2048, np.deg2rad([0.0]),
+                      rays_per_element, 4, 0.2, np.deg2rad(2.0), np.deg2rad(2.0),
+                      1540.0, 5.0, 1540.0 / (2 * 5e6))
+    grid = Grid(128, 256, -9.6 * MM, 9.6 * MM, 1 * MM, 40 * MM)
+    return Workload("tiny", scene, acq, grid, scene_seed=scene_seed)
+
+
+def _layers(rng, box, z_first=(4, 10), z_gap=(4, 10)):
+    z1 = rng.uniform(*z_first) * MM
+    z2 = z1 + rng.uniform(*z_gap) * MM
+    Z = rng.uniform(1.4, 1.7, size=3)
+    c = rng.uniform(1450, 1600, size=3)
+    mats = [[Z[i], 0.5, c[i]] for i in range(3)]
+    pln = np.array([[0.0, 0.0, 1.0, z1], [0.0, 0.0, 1.0, z2]])
+    pln_mat = np.array([[1, 0], [2, 1]])
+    return mats, pln, pln_mat, (z1, z2)
+
+
+def bone(scene_seed: int = 1, rays_per_element: int = 78125, angles_deg=None,
+         n_phi: int = 300, n_y: int = 100, n_scatterers: int = 50_000,
+         grid_n=(512, 512)) -> Workload:
+    """Plain tracer, bone phantom: 128 elements, 11 plane waves -10..10 deg.
+
+    Three seeded soft-tissue slabs (Z in 1.4-1.7, c in 1450-1600), a 60k
+    triangle tube (radius 8 mm +- 2 mm of sinusoidal noise, Z 7.8, 10
+    dB/cm/MHz) and 50k scatterers with lognormal amplitudes (sigma 0.5).
+    """
+    rng = np.random.default_rng(scene_seed)
+    if angles_deg is None:
+        angles_deg = np.arange(-10, 11, 2)
+    box = np.array([-30 * MM, -20 * MM, 0.0, 30 * MM, 20 * MM, 80 * MM])
+    mats, pln, pln_mat, _ = _layers(rng, box)
+    mats.append([7.8, 10.0, 1540.0])        # 3: bone
+    ax = rng.uniform(-5, 5) * MM
+    az = rng.uniform(35, 45) * MM
+    tri = tube_mesh(rng, ax, az, n_phi, n_y, 25 * MM, 8 * MM, 2 * MM)
+    tri_mat = np.tile(np.array([[2, 3]], np.int32), (len(tri), 1))
+    pos = rng.uniform(box[:3], box[3:], size=(n_scatterers, 3))
+    amp = np.exp(0.5 * rng.normal(size=(n_scatterers, 1)))
+    scene = Scene(_f64(mats, 3), box, 0, tri, _i32(tri_mat), np.zeros((0, 4)), _empty_i2(),
+                  _f64(pln, 4), _i32(pln_mat), _f64(np.hstack([pos, amp]), 4))
+    acq = Acquisition(128, 0.3 * MM, 4 * MM, 5e6, 40e6, 4096, np.deg2rad(np.asarray(angles_deg, float)),
+                      rays_per_element, 8, 0.2, np.deg2rad(2.0), np.deg2rad(2.0),
+                      1540.0, 5.0, 1540.0 / (2 * 5e6))
+    grid = Grid(grid_n[0], grid_n[1], -19.2 * MM, 19.2 * MM, 1 * MM, 79 * MM)
+    w = Workload("bone", scene, acq, grid, scene_seed=scene_seed)
+    w.extra.update(tube_axis=(ax, az))
+    return w
+
+
+def batched(scene_seed: int = 1, rays_per_element: int = 156250) -> Workload:
+    """Bone phantom with 21 plane waves -20..20 deg, 2e7 rays per transmit,
+    beamformed to a 1024x1024 compounded image with Hann apodisation."""
+    w = bone(scene_seed, rays_per_element, angles_deg=np.arange(-20, 21, 2), grid_n=(1024, 1024))
+    w.name = "batched"
+    return w
+
+
+def learned(scene_seed: int = 1, rays_per_element: int = 78125) -> Workload:
+    """Bone phantom used to train and evaluate the learned emission proposal."""
+    w = bone(scene_seed, rays_per_element)
+    w.name = "learned"
+    return w
+
+
+def large(scene_seed: int = 1, rays_per_element: int = 124008, n_phi: int = 1000, n_y: int = 125,
+          n_scatterers: int = 1_000_000) -> Workload:
+    """Differentiable large scene: 192 elements, 21 angles, two 250k-triangle
+    tubes, 4 spheres, 1e6 scatterers, six (Z, alpha) materials, linear
+    (tent) binning so the channel data is continuous in arrival time."""
+    rng = np.random.default_rng(scene_seed)
+    box = np.array([-40 * MM, -20 * MM, 0.0, 40 * MM, 20 * MM, 80 * MM])
+    mats, pln, pln_mat, (z1, z2) = _layers(rng, box)
+    mats.append([7.8, 10.0, 1540.0])        # 3: bone
+    mats.append([2.0, 1.0, 1540.0])         # 4: sphere material A
+    mats.append([1.2, 0.3, 1540.0])         # 5: sphere material B
+    axes = [(rng.uniform(-22, -12) * MM, rng.uniform(35, 45) * MM),
+            (rng.uniform(12, 22) * MM, rng.uniform(45, 55) * MM)]
+    tris = [tube_mesh(rng, a[0], a[1], n_phi, n_y, 25 * MM, 8 * MM, 2 * MM) for a in axes]
+    tri = np.concatenate(tris, 0)
+    tri_mat = np.tile(np.array([[2, 3]], np.int32), (len(tri), 1))
+    sph = []
+    while len(sph) < 4:
+        r = rng.uniform(2, 4) * MM
+        c = rng.uniform(box[:3] + r + 1 * MM, box[3:] - r - 1 * MM)
+        if c[2] - r < z2 + 1 * MM:
+            continue
+        if any(np.hypot(c[0] - a[0], c[2] - a[1]) < 10 * MM + r + 1 * MM for a in axes):
+            continue
+        if any(np.linalg.norm(c - s[:3]) < r + s[3] + 1 * MM for s in sph):
+            continue
+        sph.append(np.array([c[0], c[1], c[2], r]))
+    sph = np.array(sph)
+    sph_mat = np.array([[2, 4], [2, 4], [2, 5], [2, 5]])
+    pos = rng.uniform(box[:3], box[3:], size=(n_scatterers, 3))
+    amp = np.exp(0.5 * rng.normal(size=(n_scatterers, 1)))
+    scene = Scene(_f64(mats, 3), box, 0, tri, _i32(tri_mat), _f64(sph, 4), _i32(sph_mat),
+                  _f64(pln, 4), _i32(pln_mat), _f64(np.hstack([pos, amp]), 4))
+    acq = Acquisition(192, 0.3 * MM, 4 * MM, 5e6, 40e6, 4096, np.deg2rad(np.arange(-20, 21, 2.0)),
+                      rays_per_element, 8, 0.2, np.deg2rad(2.0), np.deg2rad(2.0),
+                      1540.0, 5.0, 1540.0 / (2 * 5e6), binning=LINEAR)
+    grid = Grid(512, 512, -28.8 * MM, 28.8 * MM, 1 * MM, 79 * MM)
+    w = Workload("large", scene, acq, grid, scene_seed=scene_seed)
+    w.extra.update(tube_axes=axes)
+    return w
+
+
+CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "large": large}
+
+
+def make(name: str, **kw) -> Workload:
+    return CONFIGS[name](**kw)
