@@ -1,0 +1,217 @@
+/*
+ * ultraray.h -- C ABI of the MI355X (gfx950) full-path ultrasound ray tracer.
+ *
+ * The library computes the pressure signal P(e, t) received by every element
+ * e of a linear transducer over time t for a plane-wave acquisition pattern,
+ * and turns these per-element signals into a B-mode image (UltraRay, arXiv
+ * 2501.05828, Sec. 2.1 problem statement and Sec. 2.3 signal processing).
+ *
+ * Conventions shared by every entry point
+ *   Units     metres, seconds, m/s; impedance Z in MRayl; attenuation in
+ *             dB/(cm MHz); angles in radians.
+ *   Frame     x lateral, y elevation, z depth.  The transducer face is the
+ *             plane z = 0 of the scene box and faces +z.  Element e has its
+ *             centre at x_e = (e - (E-1)/2) * pitch, y = 0, z = 0.
+ *   Layouts   channel data [n_tx][n_elements][n_samples], samples
+ *             contiguous; complex data interleaved (re, im) float pairs;
+ *             images [nx][nz], depth contiguous.  Sample n of the channel
+ *             data stands for arrival times in [n/fs, (n+1)/fs).
+ *   Memory    "_dev" pointers are device (HIP) memory owned by the caller;
+ *             other pointers are host memory, read (or written) before the
+ *             call returns.  The library owns the uploaded scene, its
+ *             acceleration structures and all workspace.
+ *   Streams   "stream" is a hipStream_t (NULL = the default stream).  Device
+ *             outputs are valid once the stream has reached the end of the
+ *             call's work; entry points that fill host outputs synchronise
+ *             the stream before returning.
+ *   Errors    Every entry point returns a ur_status (0 = success).  On a
+ *             validation failure nothing is launched and no output is
+ *             written; ur_last_error() returns a message describing the last
+ *             failure on that context.  No C++ exception crosses the ABI.
+ *   Threads   A context is used by one host thread at a time.
+ */
+#ifndef ULTRARAY_H
+#define ULTRARAY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UR_API __attribute__((visibility("default")))
+
+typedef enum {
+    UR_OK = 0,
+    UR_ERR_INVALID_ARG = -1,   /* bad pointer, size, count or value            */
+    UR_ERR_CALL_ORDER = -2,    /* e.g. trace before scene upload / setup       */
+    UR_ERR_OOM = -3,           /* device or host allocation failed             */
+    UR_ERR_HIP = -4,           /* a HIP runtime call failed                    */
+    UR_ERR_SCENE = -5,         /* inconsistent scene (materials, geometry)     */
+    UR_ERR_CAPACITY = -6,      /* a fixed-capacity table or buffer is too small */
+    UR_ERR_UNSUPPORTED = -7    /* feature or size outside the supported range  */
+} ur_status;
+
+typedef struct ur_context ur_context;
+
+/* Scene (host arrays, copied by ur_scene_upload).  Every surface separates a
+ * "front" material (the side its geometric normal points to) from a "back"
+ * material; a sphere's front is its outside.  Triangles use the normal
+ * (v1 - v0) x (v2 - v0).  The axis-aligned box absorbs every ray that leaves
+ * it; its face z = box[2] must be the transducer plane z = 0.  Scatterers are
+ * points with a signed re-radiation amplitude. */
+typedef struct {
+    int64_t n_mat, n_tri, n_sph, n_pln, n_scat, top_medium;
+    const double *mat;        /* [n_mat][3] Z [MRayl], alpha [dB/(cm MHz)], c [m/s]; n_mat <= 16 */
+    const double *box;        /* [6] xmin, ymin, zmin(=0), xmax, ymax, zmax                  */
+    const double *tri;        /* [n_tri][9] v0, v1, v2                                         */
+    const int32_t *tri_mat;   /* [n_tri][2] front, back                                        */
+    const double *sph;        /* [n_sph][4] centre, radius; n_sph <= 64                        */
+    const int32_t *sph_mat;   /* [n_sph][2] outside, inside                                    */
+    const double *pln;        /* [n_pln][4] unit normal n and d, plane n.x = d; n_pln <= 64    */
+    const int32_t *pln_mat;   /* [n_pln][2] front (n side), back                               */
+    const double *scat;       /* [n_scat][4] position, amplitude                               */
+} ur_scene_desc;
+
+/* Linear array (Sec. 2.3 "Ray Emission": number of lateral elements and
+ * elevational extent; a linear array has infinite radius). */
+typedef struct {
+    int64_t n_elements;       /* 1 .. 65535                        */
+    double pitch;             /* element pitch [m]                 */
+    double elevation;         /* element height along y [m]        */
+    double f_c;               /* centre frequency [Hz]             */
+} ur_probe_desc;
+
+#define UR_BIN_NEAREST 0      /* a record adds to the sample whose interval holds its time   */
+#define UR_BIN_LINEAR 1       /* tent split between the two samples whose centres bracket it */
+
+/* Plane-wave acquisition and tracer limits. */
+typedef struct {
+    int64_t n_tx;             /* number of steered plane waves, 1 .. 65535              */
+    int64_t n_samples;        /* samples per channel                                     */
+    int64_t rays_per_element; /* rays emitted per element and transmit, < 2^32           */
+    int64_t max_bounces;      /* interface interactions before termination (Sec. 2.3)    */
+    int64_t binning;          /* UR_BIN_NEAREST or UR_BIN_LINEAR                          */
+    double f_s;               /* sampling frequency [Hz]                                  */
+    double c0;                /* speed of sound for steering delays and beamforming [m/s] */
+    double n_cycles;          /* pulse length in cycles (Eq. 14)                          */
+    double r_s;               /* scatterer capture radius [m]                             */
+    double max_path;          /* maximum path length [m]                                   */
+    double alpha_m, alpha_c;  /* receive main-beam and cut-off angles (Eq. 13) [rad]       */
+    const double *angles;     /* [n_tx] steering angles [rad] (host)                       */
+} ur_acq_desc;
+
+#define UR_APOD_NONE 0
+#define UR_APOD_HANN 1
+
+/* Image grid: pixel (i, j) sits at x = x0 + i (x1-x0)/(nx-1), z = z0 + j (z1-z0)/(nz-1). */
+typedef struct {
+    int64_t nx, nz, apod;
+    double x0, x1, z0, z1;
+    double dynamic_range_db;  /* log compression range for the B-mode output (90 dB in Sec. 4) */
+} ur_grid_desc;
+
+/* Counters of one trace call (filled only when requested). */
+typedef struct {
+    uint64_t rays, segments, reflect, transmit, tir, scatter_events, nee_zero, nee_cast, nee_blocked,
+             direct_hits, records, dropped, edge_band, term_box, term_bounce, term_time, term_path,
+             media_mismatch;
+    uint64_t tri_nodes, tri_tests, scat_nodes, scat_tests, shadow_nodes, shadow_tri_tests;
+    double kernel_ms;         /* trace-kernel time between HIP events on the call's stream */
+} ur_trace_stats;
+
+/* One entry of an explicit-ray path log (ur_trace_rays). */
+typedef struct {
+    int64_t kind;             /* 0 direct-hit record, 1 scatterer record, 2 reflect, 3 transmit, 4 end */
+    int64_t tx, elem, seg, id;
+    double t, value, x, y, z;
+} ur_event;
+
+/* Explicit ray for ur_trace_rays. */
+typedef struct {
+    double o[3], d[3], w, t;  /* origin, unit direction, weight, start time */
+    int64_t tx, elem, ray, medium;
+} ur_ray;
+
+/* Creates a context bound to HIP device `hip_device`.  *out receives the
+ * handle (NULL on failure). */
+UR_API ur_status ur_context_create(int hip_device, ur_context **out);
+
+/* Frees the context and everything the library allocated for it.  NULL is a no-op. */
+UR_API void ur_context_destroy(ur_context *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+UR_API const char *ur_last_error(const ur_context *ctx);
+
+/* Library version string. */
+UR_API const char *ur_version(void);
+
+/* Validates and uploads the scene (Sec. 4 scene: meshes with per-material
+ * impedance; scatterers and attenuation per the spec additions),
+ * builds the triangle and scatterer bounding-volume hierarchies on the host
+ * and copies them to the device.  Replaces any previous scene.  Synchronous. */
+UR_API ur_status ur_scene_upload(ur_context *ctx, const ur_scene_desc *scene);
+
+/* Transmit setup: element centres, plane-wave steering delays (Sec. 2.3 "Ray
+ * Emission", Fig. 3), pulse taps (Eq. 14) and tracer limits.  Requires a
+ * scene (material count is checked against it).  Synchronous. */
+UR_API ur_status ur_transmit_setup(ur_context *ctx, const ur_probe_desc *probe, const ur_acq_desc *acq);
+
+/* Sets the emission-direction proposal: pdf_dev and cdf_dev are device arrays
+ * [n_tx][n_elements][1024] over the 32x32 equal-area direction cells (pdf: the
+ * probability of each cell, summing to 1; cdf: its inclusive prefix sum).
+ * NULL, NULL restores uniform emission.  The arrays are read during later
+ * traces and must stay alive until the proposal is replaced.  (Eq. 4's p_t.) */
+UR_API ur_status ur_set_proposal(ur_context *ctx, const float *pdf_dev, const float *cdf_dev);
+
+/* Traces every ray of every transmit (Sec. 2.2 Eq. 4 estimator with the
+ * Sec. 2.3 emission, traversal and transducer sampling) and writes the
+ * channel data ch_raw_dev [n_tx][n_elements][n_samples] (zero-filled first).
+ * If ch_rf_dev is not NULL, also writes the pulse-shaped analytic channel
+ * data [n_tx][n_elements][n_samples][2] (as ur_pulse).  Only rays with
+ * index r = ray_offset + k * ray_stride are traced (stride 1, offset 0 traces
+ * all; the estimator's normalisation is unchanged).  If stats is not NULL the
+ * call synchronises the stream and fills it (the counting kernel variant is
+ * used, which also counts traversal work). */
+UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
+                          float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
+
+/* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
+ * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at
+ * half maximum n_cycles / f_c, taps |m| <= ceil(3 sigma f_s), zero outside the
+ * record.  Layouts as in ur_trace. */
+UR_API ur_status ur_pulse(ur_context *ctx, const float *ch_raw_dev, float *ch_rf_dev, void *stream);
+
+/* Plane-wave delay-and-sum with coherent compounding over transmits,
+ * followed by demodulation (envelope) and log compression (Sec. 2.3 "Phase
+ * Calculation and Signal Processing").  ch_rf_dev as written by ur_pulse.
+ * Outputs (any may be NULL, not all): iq_dev [nx][nz][2], env_dev [nx][nz],
+ * bmode_dev [nx][nz] in dB within [-dynamic_range_db, 0]. */
+UR_API ur_status ur_beamform(ur_context *ctx, const ur_grid_desc *grid, const float *ch_rf_dev, float *iq_dev,
+                             float *env_dev, float *bmode_dev, void *stream);
+
+/* Device time (milliseconds, between HIP events recorded on the call's
+ * stream immediately around the kernel) of the trace kernel of the last
+ * ur_trace call and of the delay-and-sum kernel of the last ur_beamform call;
+ * -1 where no such call was made.  Waits for those events. */
+UR_API ur_status ur_last_kernel_ms(ur_context *ctx, double *trace_ms, double *das_ms);
+
+/* Test and debugging aid: traces the given host rays one by one with the
+ * same device code path as ur_trace and returns their path logs (host
+ * events, at most cap; *n_events receives the total count).  If ch_raw_dev is
+ * not NULL the records are also binned into it (zero-filled first).
+ * Synchronous. */
+UR_API ur_status ur_trace_rays(ur_context *ctx, uint64_t seed, const ur_ray *rays, int64_t n_rays,
+                               ur_event *events, int64_t cap, int64_t *n_events, float *ch_raw_dev,
+                               void *stream);
+
+/* Philox4x32-10 evaluated on the device for n counters (host arrays
+ * ctr [n][4], out [n][4]) under key (key0, key1); for checking that the
+ * device stream equals the published generator.  Synchronous. */
+UR_API ur_status ur_philox(ur_context *ctx, const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1,
+                           uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

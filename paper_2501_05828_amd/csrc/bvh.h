@@ -1,0 +1,26 @@
+// Host-side bounding volume hierarchy builder (binned surface-area
+// heuristic), emitted as a threaded depth-first node array for stackless
+// traversal on the device.
+#pragma once
+#include <vector>
+
+#include "bvh_layout.h"
+
+namespace ur {
+
+struct PrimBounds {
+    double lo[3], hi[3];
+};
+
+struct BvhResult {
+    std::vector<BvhNode> nodes;   // depth-first preorder, skip indices set
+    std::vector<int> order;       // BVH slot -> original primitive index
+    int max_depth = 0;
+};
+
+// Builds over `prims`.  Leaves hold at most `leaf_max` (<= 15) primitives.
+// Node boxes are the FP64 union of their primitives' boxes grown by
+// `dilate` metres and rounded outward to FP32.
+BvhResult build_bvh(const std::vector<PrimBounds> &prims, int leaf_max, double dilate);
+
+}  // namespace ur

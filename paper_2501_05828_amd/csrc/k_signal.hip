@@ -1,0 +1,140 @@
+// Signal processing on gfx950: pulse shaping (Eq. 14), plane-wave
+// delay-and-sum with coherent compounding, envelope and log compression
+// (UltraRay, arXiv 2501.05828, Sec. 2.3 "Phase Calculation and Signal
+// Processing").
+#include <algorithm>
+
+#include "ur_internal.h"
+
+namespace {
+using namespace ur;
+
+constexpr int kFirTile = 256;
+constexpr int kMaxHalfTaps = 512;
+
+// ch_rf[ch][n] = sum_{|m|<=K} h[m] ch_raw[ch][n-m].  One block filters a
+// 256-sample tile of one channel; the tile plus its 2K halo is staged in LDS
+// with coalesced loads, taps sit in LDS, every lane produces one complex
+// output.
+__global__ __launch_bounds__(kFirTile) void k_pulse(const float *__restrict__ raw, float2 *__restrict__ rf,
+                                                     const float2 *__restrict__ taps, int K, int S) {
+    __shared__ float xs[kFirTile + 2 * kMaxHalfTaps];
+    __shared__ float2 hs[2 * kMaxHalfTaps + 1];
+    const int64_t ch = blockIdx.y;
+    const int n0 = blockIdx.x * kFirTile;
+    const float *x = raw + ch * S;
+    for (int i = threadIdx.x; i < kFirTile + 2 * K; i += kFirTile) {
+        const int n = n0 - K + i;
+        xs[i] = (n >= 0 && n < S) ? x[n] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < 2 * K + 1; i += kFirTile) hs[i] = taps[i];
+    __syncthreads();
+    const int n = n0 + threadIdx.x;
+    if (n >= S) return;
+    float re = 0.0f, im = 0.0f;
+    // output n reads input n - m = xs[threadIdx.x + K - m]
+    for (int m = -K; m <= K; ++m) {
+        const float v = xs[threadIdx.x + K - m];
+        const float2 h = hs[m + K];
+        re = fmaf(h.x, v, re);
+        im = fmaf(h.y, v, im);
+    }
+    rf[ch * S + n] = make_float2(re, im);
+}
+
+// Delay-and-sum: one lane per pixel, lanes of a wavefront run down one image
+// column (depth contiguous), so for a fixed (transmit, element) the 64 lanes
+// gather from a short, monotone stretch of that channel.  The receive delay
+// (one FP64 square root per pixel and element) is hoisted out of the
+// transmit loop; the fractional sample index is formed in FP64 so that the
+// interpolation weight and sample match the reference index exactly; the
+// interpolation and accumulation are FP32.
+__global__ __launch_bounds__(256) void k_das(DasParams p) {
+    const int iz = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ix = blockIdx.y;
+    if (iz >= p.nz) return;
+    const double x = p.x0 + (double)ix * p.dx;
+    const double z = p.z0 + (double)iz * p.dz;
+    const double zz = z * z;
+    float re = 0.0f, im = 0.0f;
+    for (int e = 0; e < p.E; ++e) {
+        const double dxe = x - p.xe[e];
+        const double trx = sqrt(dxe * dxe + zz) * p.fs_over_c0;
+        const float a = p.apod[e];
+        const float2 *ch = p.rf + (int64_t)e * p.S;
+        float er = 0.0f, ei = 0.0f;
+        for (int tx = 0; tx < p.T; ++tx) {
+            const double4 c = p.txc[tx];
+            const double idx = x * c.x + z * c.y + c.z + trx;
+            const double f0 = floor(idx);
+            const int i0 = (int)f0;
+            if (i0 < 0 || i0 >= p.S - 1) continue;
+            const float fr = (float)(idx - f0);
+            const float2 *s = ch + (int64_t)tx * p.E * p.S + i0;
+            const float2 v0 = s[0], v1 = s[1];
+            er += fmaf(fr, v1.x - v0.x, v0.x);
+            ei += fmaf(fr, v1.y - v0.y, v0.y);
+        }
+        re = fmaf(a, er, re);
+        im = fmaf(a, ei, im);
+    }
+    const int64_t o = (int64_t)ix * p.nz + iz;
+    if (p.iq) p.iq[o] = make_float2(re, im);
+    if (p.env) p.env[o] = sqrtf(re * re + im * im);
+}
+
+// Non-negative floats order like their bit patterns.
+__global__ void k_absmax(const float *env, int64_t n, unsigned int *max_bits) {
+    __shared__ unsigned int red[256];
+    unsigned int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(fmaxf(env[i], 0.0f)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(max_bits, red[0]);
+}
+
+__global__ void k_logcompress(const float *env, float *bmode, int64_t n, float dr, const unsigned int *max_bits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float mx = __uint_as_float(*max_bits);
+    const float v = env[i];
+    float db = (mx > 0.0f && v > 0.0f) ? 20.0f * log10f(v / mx) : -dr;
+    bmode[i] = db < -dr ? -dr : db;
+}
+
+__global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
+
+}  // namespace
+
+hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
+                           hipStream_t s) {
+    if (K > kMaxHalfTaps) return hipErrorInvalidValue;
+    if (n_ch <= 0 || S <= 0) return hipSuccess;
+    for (int64_t c0 = 0; c0 < n_ch; c0 += 65535) {   // grid.y is limited to 65535 channels per launch
+        const int64_t nc = std::min<int64_t>(65535, n_ch - c0);
+        dim3 grid((unsigned)((S + kFirTile - 1) / kFirTile), (unsigned)nc);
+        hipLaunchKernelGGL(k_pulse, grid, dim3(kFirTile), 0, s, raw + c0 * S, rf + c0 * S, taps, K, S);
+    }
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s) {
+    dim3 grid((unsigned)((p.nz + 255) / 256), (unsigned)p.nx);
+    hipLaunchKernelGGL(k_das, grid, dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_bmode(const float *env, float *bmode, int64_t n, float dr_db, unsigned int *max_bits,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, max_bits);
+    const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, env, n, max_bits);
+    hipLaunchKernelGGL(k_logcompress, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, env, bmode, n, dr_db,
+                       max_bits);
+    return hipGetLastError();
+}

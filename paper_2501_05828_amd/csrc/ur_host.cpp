@@ -1,0 +1,657 @@
+// Host runtime behind the C ABI (include/ultraray.h): context, validation,
+// scene upload with BVH construction, transmit setup, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ultraray.h"
+#include "bvh.h"
+#include "ur_internal.h"
+
+using namespace ur;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+}  // namespace
+
+struct ur_context {
+    int device = 0;
+    std::string err;
+    // scene (host copies of what later calls need)
+    bool has_scene = false;
+    std::vector<double> mat;               // [n_mat][3]
+    double box[6] = {0};
+    int top_medium = 0;
+    int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
+    int n_tnodes = 0, n_snodes = 0;
+    std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer BVH
+    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_scat, d_scat_id,
+        d_snodes;
+    // setup
+    bool has_setup = false;
+    ur_probe_desc probe{};
+    ur_acq_desc acq{};
+    std::vector<double> angles;
+    int K = 0;
+    DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr;
+    const float *pdf = nullptr, *cdf = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool trace_timed = false, das_timed = false;
+
+    ur_status fail(ur_status code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    ur_status hip_fail(hipError_t e, const char *what) {
+        return fail(UR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+namespace {
+
+#define HIP_TRY(ctx, call)                                 \
+    do {                                                   \
+        hipError_t _e = (call);                            \
+        if (_e != hipSuccess) return (ctx)->hip_fail(_e, #call); \
+    } while (0)
+
+ur_status alloc(ur_context *c, DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return UR_OK;
+    b.release();
+    if (bytes == 0) return UR_OK;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return c->fail(UR_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return UR_OK;
+}
+
+template <class T>
+ur_status upload(ur_context *c, DevBuf &b, const std::vector<T> &v) {
+    ur_status s = alloc(c, b, v.size() * sizeof(T));
+    if (s) return s;
+    if (!v.empty()) HIP_TRY(c, hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return UR_OK;
+}
+
+bool finite_all(const double *p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+ur_status set_device(ur_context *c) {
+    HIP_TRY(c, hipSetDevice(c->device));
+    return UR_OK;
+}
+
+// Material constants at the probe's centre frequency.
+ur_status upload_materials(ur_context *c) {
+    const int64_t nm = (int64_t)c->mat.size() / 3;
+    std::vector<Material> m(nm);
+    const double fmhz = c->has_setup ? c->probe.f_c * 1e-6 : 0.0;
+    for (int64_t i = 0; i < nm; ++i) {
+        m[i].Z = c->mat[3 * i];
+        m[i].ka = c->mat[3 * i + 1] * fmhz * 100.0 * std::log(10.0) / 20.0;   // dB/(cm MHz) -> Np/m
+        m[i].inv_c = 1.0 / c->mat[3 * i + 2];
+        m[i].pad = 0.0;
+    }
+    return upload(c, c->d_mat, m);
+}
+
+template <class F>
+ur_status guarded(ur_context *c, F &&f) {
+    if (!c) return UR_ERR_INVALID_ARG;
+    try {
+        ur_status s = set_device(c);
+        if (s) return s;
+        return f();
+    } catch (const std::bad_alloc &) {
+        return c->fail(UR_ERR_OOM, "host allocation failed");
+    } catch (...) {
+        return c->fail(UR_ERR_INVALID_ARG, "unexpected host exception");
+    }
+}
+
+ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
+    const ur_acq_desc &a = c->acq;
+    const ur_probe_desc &pr = c->probe;
+    std::memset(&P, 0, sizeof(P));
+    P.E = (int)pr.n_elements;
+    P.T = (int)a.n_tx;
+    P.S = (int)a.n_samples;
+    P.binning = (int)a.binning;
+    P.n_el = (uint32_t)a.rays_per_element;
+    P.B = (int)a.max_bounces;
+    P.proposal = c->cdf != nullptr;
+    P.key0 = (uint32_t)seed;
+    P.key1 = (uint32_t)(seed >> 32);
+    P.pitch = pr.pitch;
+    P.elev = pr.elevation;
+    P.fs = a.f_s;
+    P.t_max = (double)a.n_samples / a.f_s;
+    P.max_path = a.max_path;
+    P.alpha_m = a.alpha_m;
+    P.alpha_c = a.alpha_c;
+    P.r_s2 = a.r_s * a.r_s;
+    P.n_per_tx = (double)pr.n_elements * (double)a.rays_per_element;
+    P.half_ap = 0.5 * (double)pr.n_elements * pr.pitch;
+    P.area_e = pr.pitch * pr.elevation;
+    P.xe = (const double *)c->d_xe.p;
+    P.tau = (const double *)c->d_tau.p;
+    P.pdf = c->pdf;
+    P.cdf = c->cdf;
+    P.n_mat = (int)(c->mat.size() / 3);
+    P.n_sph = (int)c->n_sph;
+    P.n_pln = (int)c->n_pln;
+    P.top_medium = c->top_medium;
+    P.id_sph0 = c->n_tri;
+    P.id_pln0 = c->n_tri + c->n_sph;
+    P.id_box = c->n_tri + c->n_sph + c->n_pln;
+    for (int i = 0; i < 6; ++i) P.box[i] = c->box[i];
+    P.mat = (const Material *)c->d_mat.p;
+    P.sph = (const double *)c->d_sph.p;
+    P.sph_mat = (const int *)c->d_sph_mat.p;
+    P.pln = (const double *)c->d_pln.p;
+    P.pln_mat = (const int *)c->d_pln_mat.p;
+    P.tri = (const double *)c->d_tri.p;
+    P.tri_mat = (const int *)c->d_tri_mat.p;
+    P.tri_id = (const int *)c->d_tri_id.p;
+    P.tnodes = (const BvhNode *)c->d_tnodes.p;
+    P.n_tri = (int)c->n_tri;
+    P.n_tnodes = c->n_tnodes;
+    P.scat = (const double4 *)c->d_scat.p;
+    P.scat_id = (const int *)c->d_scat_id.p;
+    P.snodes = (const BvhNode *)c->d_snodes.p;
+    P.n_scat = (int)c->n_scat;
+    P.n_snodes = c->n_snodes;
+    return UR_OK;
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    const int i = threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t zero_f32(float *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+UR_API const char *ur_version(void) { return "ultraray-mi355x 0.1 (gfx950)"; }
+
+UR_API ur_status ur_context_create(int hip_device, ur_context **out) {
+    if (!out) return UR_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return UR_ERR_HIP;
+    if (hip_device < 0 || hip_device >= n) return UR_ERR_INVALID_ARG;
+    ur_context *c = new (std::nothrow) ur_context();
+    if (!c) return UR_ERR_OOM;
+    c->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete c;
+        return UR_ERR_HIP;
+    }
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return UR_ERR_HIP;
+        }
+    }
+    *out = c;
+    return UR_OK;
+}
+
+UR_API void ur_context_destroy(ur_context *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
+                      &c->d_tri_id, &c->d_tnodes, &c->d_scat, &c->d_scat_id, &c->d_snodes, &c->d_xe, &c->d_tau,
+                      &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_maxbits, &c->d_env, &c->d_rays,
+                      &c->d_events, &c->d_evcount, &c->d_ctr})
+        b->release();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+UR_API const char *ur_last_error(const ur_context *c) { return c ? c->err.c_str() : "null context"; }
+
+UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
+    return guarded(c, [&]() -> ur_status {
+        if (!s) return c->fail(UR_ERR_INVALID_ARG, "scene is NULL");
+        if (s->n_mat < 1 || s->n_mat > kMaxMat) return c->fail(UR_ERR_UNSUPPORTED, "n_mat must be in [1, %d]", kMaxMat);
+        if (s->n_tri < 0 || s->n_sph < 0 || s->n_pln < 0 || s->n_scat < 0)
+            return c->fail(UR_ERR_INVALID_ARG, "negative primitive count");
+        if (s->n_sph > kMaxSph || s->n_pln > kMaxPln)
+            return c->fail(UR_ERR_UNSUPPORTED, "at most %d spheres and %d planes", kMaxSph, kMaxPln);
+        if (s->n_tri >= (1 << 27) || s->n_scat >= (1 << 27))
+            return c->fail(UR_ERR_UNSUPPORTED, "at most 2^27 triangles / scatterers");
+        if (!s->mat || !s->box || (s->n_tri && (!s->tri || !s->tri_mat)) || (s->n_sph && (!s->sph || !s->sph_mat)) ||
+            (s->n_pln && (!s->pln || !s->pln_mat)) || (s->n_scat && !s->scat))
+            return c->fail(UR_ERR_INVALID_ARG, "NULL array for a non-empty primitive set");
+        if (!finite_all(s->mat, 3 * s->n_mat) || !finite_all(s->box, 6) || !finite_all(s->tri, 9 * s->n_tri) ||
+            !finite_all(s->sph, 4 * s->n_sph) || !finite_all(s->pln, 4 * s->n_pln) ||
+            !finite_all(s->scat, 4 * s->n_scat))
+            return c->fail(UR_ERR_INVALID_ARG, "non-finite scene value");
+        for (int64_t m = 0; m < s->n_mat; ++m)
+            if (!(s->mat[3 * m] > 0) || !(s->mat[3 * m + 1] >= 0) || !(s->mat[3 * m + 2] > 0))
+                return c->fail(UR_ERR_SCENE, "material %lld needs Z > 0, alpha >= 0, c > 0", (long long)m);
+        for (int i = 0; i < 3; ++i)
+            if (!(s->box[i] < s->box[3 + i])) return c->fail(UR_ERR_SCENE, "box min must be below max");
+        if (s->box[2] != 0.0) return c->fail(UR_ERR_SCENE, "the box face z = box[2] must be the transducer plane z = 0");
+        if (s->top_medium < 0 || s->top_medium >= s->n_mat) return c->fail(UR_ERR_SCENE, "top_medium out of range");
+        auto bad_mat = [&](const int32_t *m, int64_t n) {
+            for (int64_t i = 0; i < 2 * n; ++i)
+                if (m[i] < 0 || m[i] >= s->n_mat) return true;
+            return false;
+        };
+        if (bad_mat(s->tri_mat, s->n_tri) || bad_mat(s->sph_mat, s->n_sph) || bad_mat(s->pln_mat, s->n_pln))
+            return c->fail(UR_ERR_SCENE, "material index out of range");
+        for (int64_t j = 0; j < s->n_sph; ++j)
+            if (!(s->sph[4 * j + 3] > 0)) return c->fail(UR_ERR_SCENE, "sphere %lld radius must be > 0", (long long)j);
+        for (int64_t j = 0; j < s->n_pln; ++j) {
+            const double *p = s->pln + 4 * j;
+            if (std::fabs(std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) - 1.0) > 1e-9)
+                return c->fail(UR_ERR_SCENE, "plane %lld normal is not unit length", (long long)j);
+        }
+        c->has_scene = false;
+        c->mat.assign(s->mat, s->mat + 3 * s->n_mat);
+        std::memcpy(c->box, s->box, sizeof(c->box));
+        c->top_medium = (int)s->top_medium;
+        c->n_tri = s->n_tri;
+        c->n_sph = s->n_sph;
+        c->n_pln = s->n_pln;
+        c->n_scat = s->n_scat;
+        c->scat.assign(s->scat, s->scat + 4 * s->n_scat);
+        ur_status st;
+        if ((st = upload_materials(c))) return st;
+        if ((st = upload(c, c->d_sph, std::vector<double>(s->sph, s->sph + 4 * s->n_sph)))) return st;
+        if ((st = upload(c, c->d_sph_mat, std::vector<int32_t>(s->sph_mat, s->sph_mat + 2 * s->n_sph)))) return st;
+        if ((st = upload(c, c->d_pln, std::vector<double>(s->pln, s->pln + 4 * s->n_pln)))) return st;
+        if ((st = upload(c, c->d_pln_mat, std::vector<int32_t>(s->pln_mat, s->pln_mat + 2 * s->n_pln)))) return st;
+        // triangles: BVH with leaves of <= 4, 1 um dilation
+        {
+            std::vector<PrimBounds> pb(s->n_tri);
+            for (int64_t i = 0; i < s->n_tri; ++i) {
+                const double *v = s->tri + 9 * i;
+                for (int k = 0; k < 3; ++k) {
+                    pb[i].lo[k] = std::min(v[k], std::min(v[3 + k], v[6 + k]));
+                    pb[i].hi[k] = std::max(v[k], std::max(v[3 + k], v[6 + k]));
+                }
+            }
+            BvhResult r = build_bvh(pb, 4, 1e-6);
+            std::vector<double> tri(9 * s->n_tri);
+            std::vector<int32_t> tm(2 * s->n_tri), tid(s->n_tri);
+            for (int64_t k = 0; k < s->n_tri; ++k) {
+                const int o = r.order[k];
+                const double *v = s->tri + 9 * (int64_t)o;
+                for (int j = 0; j < 3; ++j) {
+                    tri[9 * k + j] = v[j];
+                    tri[9 * k + 3 + j] = v[3 + j] - v[j];
+                    tri[9 * k + 6 + j] = v[6 + j] - v[j];
+                }
+                tm[2 * k] = s->tri_mat[2 * o];
+                tm[2 * k + 1] = s->tri_mat[2 * o + 1];
+                tid[k] = o;
+            }
+            c->n_tnodes = (int)r.nodes.size();
+            if ((st = upload(c, c->d_tri, tri))) return st;
+            if ((st = upload(c, c->d_tri_mat, tm))) return st;
+            if ((st = upload(c, c->d_tri_id, tid))) return st;
+            if ((st = upload(c, c->d_tnodes, r.nodes))) return st;
+        }
+        c->has_scene = true;
+        c->n_snodes = 0;   // the scatterer BVH depends on r_s: built at transmit setup
+        if (c->has_setup) {
+            c->has_setup = false;
+            ur_acq_desc a = c->acq;
+            a.angles = c->angles.data();
+            ur_probe_desc p = c->probe;
+            return ur_transmit_setup(c, &p, &a);
+        }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const ur_acq_desc *a) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_scene) return c->fail(UR_ERR_CALL_ORDER, "upload a scene before transmit setup");
+        if (!p || !a || !a->angles) return c->fail(UR_ERR_INVALID_ARG, "probe, acquisition and angles are required");
+        if (p->n_elements < 1 || p->n_elements > 65535) return c->fail(UR_ERR_INVALID_ARG, "n_elements must be in [1, 65535]");
+        if (!(p->pitch > 0) || !(p->elevation > 0) || !(p->f_c > 0) || !std::isfinite(p->pitch) ||
+            !std::isfinite(p->elevation) || !std::isfinite(p->f_c))
+            return c->fail(UR_ERR_INVALID_ARG, "pitch, elevation and f_c must be positive");
+        if (a->n_tx < 1 || a->n_tx > 65535) return c->fail(UR_ERR_INVALID_ARG, "n_tx must be in [1, 65535]");
+        if (a->n_samples < 2 || a->n_samples > (1 << 24)) return c->fail(UR_ERR_INVALID_ARG, "n_samples must be in [2, 2^24]");
+        if (a->rays_per_element < 0 || a->rays_per_element > 0xFFFFFFFFll)
+            return c->fail(UR_ERR_INVALID_ARG, "rays_per_element must be in [0, 2^32)");
+        if (a->max_bounces < 0 || a->max_bounces > 65535) return c->fail(UR_ERR_INVALID_ARG, "max_bounces must be in [0, 65535]");
+        if (a->binning != UR_BIN_NEAREST && a->binning != UR_BIN_LINEAR) return c->fail(UR_ERR_INVALID_ARG, "unknown binning mode");
+        const double v[] = {a->f_s, a->c0, a->n_cycles, a->max_path};
+        for (double x : v)
+            if (!(x > 0) || !std::isfinite(x)) return c->fail(UR_ERR_INVALID_ARG, "f_s, c0, n_cycles and max_path must be positive");
+        if (!(a->r_s >= 0) || !std::isfinite(a->r_s)) return c->fail(UR_ERR_INVALID_ARG, "r_s must be >= 0");
+        if (!(a->alpha_m >= 0) || !(a->alpha_c >= a->alpha_m) || !(a->alpha_c <= M_PI))
+            return c->fail(UR_ERR_INVALID_ARG, "need 0 <= alpha_m <= alpha_c <= pi");
+        for (int64_t t = 0; t < a->n_tx; ++t)
+            if (!std::isfinite(a->angles[t]) || std::fabs(a->angles[t]) >= M_PI / 2)
+                return c->fail(UR_ERR_INVALID_ARG, "steering angle %lld must be finite and within (-pi/2, pi/2)", (long long)t);
+        const double sig = a->n_cycles / (2.0 * std::sqrt(2.0 * std::log(2.0)) * p->f_c);
+        const int K = (int)std::ceil(3.0 * sig * a->f_s);
+        if (K > 512) return c->fail(UR_ERR_UNSUPPORTED, "pulse needs %d half-taps, at most 512 are supported", K);
+        const double work = (double)a->n_tx * (double)p->n_elements * (double)a->rays_per_element;
+        if (work > 9.0e15) return c->fail(UR_ERR_UNSUPPORTED, "too many rays");
+
+        c->has_setup = false;
+        c->probe = *p;
+        c->acq = *a;
+        c->angles.assign(a->angles, a->angles + a->n_tx);
+        c->acq.angles = nullptr;
+        c->K = K;
+        const int64_t E = p->n_elements, T = a->n_tx;
+        // element centres and plane-wave delays referenced to the first-firing element
+        std::vector<double> xe(E), tau(T * E);
+        for (int64_t e = 0; e < E; ++e) xe[e] = ((double)e - 0.5 * (double)(E - 1)) * p->pitch;
+        for (int64_t t = 0; t < T; ++t) {
+            const double st = std::sin(c->angles[t]);
+            const double xref = st >= 0 ? xe[0] : xe[E - 1];
+            for (int64_t e = 0; e < E; ++e) tau[t * E + e] = (xe[e] - xref) * st / a->c0;
+        }
+        // analytic pulse taps (Eq. 14), Gaussian with FWHM of n_cycles periods
+        std::vector<float2> taps(2 * K + 1);
+        for (int m = -K; m <= K; ++m) {
+            const double tm = (double)m / a->f_s;
+            const double g = std::exp(-tm * tm / (2.0 * sig * sig));
+            const double ph = 2.0 * M_PI * p->f_c * tm;
+            taps[m + K] = make_float2((float)(g * std::sin(ph)), (float)(-g * std::cos(ph)));
+        }
+        // beamforming constants per transmit: idx = x*A + z*B + C + r*fs/c0
+        std::vector<double4> txc(T);
+        const double k = a->f_s / a->c0;
+        for (int64_t t = 0; t < T; ++t) {
+            const double st = std::sin(c->angles[t]), ct = std::cos(c->angles[t]);
+            const double xref = st >= 0 ? xe[0] : xe[E - 1];
+            txc[t] = make_double4(st * k, ct * k, -xref * st * k - 0.5, 0.0);
+        }
+        // receive apodisation tables: [0, E) uniform, [E, 2E) Hann over the full aperture
+        std::vector<float> apod(2 * E);
+        for (int64_t e = 0; e < E; ++e) {
+            apod[e] = 1.0f;
+            apod[E + e] = (float)(0.5 - 0.5 * std::cos(2.0 * M_PI * ((double)e + 0.5) / (double)E));
+        }
+        ur_status st;
+        if ((st = upload(c, c->d_apod, apod))) return st;
+        if ((st = upload(c, c->d_xe, xe))) return st;
+        if ((st = upload(c, c->d_tau, tau))) return st;
+        if ((st = upload(c, c->d_taps, taps))) return st;
+        if ((st = upload(c, c->d_txc, txc))) return st;
+        if ((st = alloc(c, c->d_stats, kNumStats * sizeof(unsigned long long)))) return st;
+        if ((st = alloc(c, c->d_maxbits, 256))) return st;
+        c->has_setup = true;
+        if ((st = upload_materials(c))) return st;
+        // scatterers: BVH over capture balls of radius r_s, leaves of <= 8
+        {
+            const double rs = a->r_s;
+            std::vector<PrimBounds> pb(c->n_scat);
+            for (int64_t i = 0; i < c->n_scat; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    pb[i].lo[k] = c->scat[4 * i + k] - rs;
+                    pb[i].hi[k] = c->scat[4 * i + k] + rs;
+                }
+            BvhResult r = build_bvh(pb, 8, rs * 1e-5 + 1e-6);
+            std::vector<double4> sc(c->n_scat);
+            std::vector<int32_t> sid(c->n_scat);
+            for (int64_t k = 0; k < c->n_scat; ++k) {
+                const double *q = c->scat.data() + 4 * (int64_t)r.order[k];
+                sc[k] = make_double4(q[0], q[1], q[2], q[3]);
+                sid[k] = r.order[k];
+            }
+            c->n_snodes = (int)r.nodes.size();
+            if ((st = upload(c, c->d_scat, sc))) return st;
+            if ((st = upload(c, c->d_scat_id, sid))) return st;
+            if ((st = upload(c, c->d_snodes, r.nodes))) return st;
+        }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_set_proposal(ur_context *c, const float *pdf_dev, const float *cdf_dev) {
+    return guarded(c, [&]() -> ur_status {
+        if ((pdf_dev == nullptr) != (cdf_dev == nullptr))
+            return c->fail(UR_ERR_INVALID_ARG, "pdf and cdf must both be set or both be NULL");
+        c->pdf = pdf_dev;
+        c->cdf = cdf_dev;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int64_t ray_offset, float *ch_raw_dev,
+                          float *ch_rf_dev, ur_trace_stats *stats, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
+        if (!ch_raw_dev) return c->fail(UR_ERR_INVALID_ARG, "ch_raw_dev is NULL");
+        if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
+            return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
+        hipStream_t s = (hipStream_t)stream;
+        TraceParams P;
+        fill_params(c, P, seed);
+        const int64_t nel = c->acq.rays_per_element;
+        P.stride = ray_stride;
+        P.offset = ray_offset;
+        P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
+        P.n_work = (int64_t)P.T * P.E * P.per_el;
+        P.ch_raw = ch_raw_dev;
+        const int64_t n_ch = (int64_t)P.T * P.E * P.S;
+        HIP_TRY(c, zero_f32(ch_raw_dev, n_ch, s));
+        if (stats) {
+            P.stats = (unsigned long long *)c->d_stats.p;
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P.stats, kNumStats);
+            HIP_TRY(c, hipGetLastError());
+        }
+        HIP_TRY(c, hipEventRecord(c->ev[0], s));
+        HIP_TRY(c, ur_launch_trace(P, stats != nullptr, s));
+        HIP_TRY(c, hipEventRecord(c->ev[1], s));
+        c->trace_timed = true;
+        if (ch_rf_dev) HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
+                                                  (int64_t)P.T * P.E, P.S, s));
+        if (stats) {
+            unsigned long long h[kNumStats];
+            HIP_TRY(c, hipMemcpyAsync(h, P.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            uint64_t *dst = &stats->rays;
+            for (int k = 0; k < kNumStats; ++k) dst[k] = h[k];
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+            stats->kernel_ms = ms;
+        }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_pulse(ur_context *c, const float *ch_raw_dev, float *ch_rf_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!ch_raw_dev || !ch_rf_dev) return c->fail(UR_ERR_INVALID_ARG, "NULL channel buffer");
+        HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
+                                   c->acq.n_tx * c->probe.n_elements, (int)c->acq.n_samples, (hipStream_t)stream));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, float *iq_dev, float *env_dev,
+                             float *bmode_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!g || !ch_rf_dev) return c->fail(UR_ERR_INVALID_ARG, "grid and ch_rf_dev are required");
+        if (!iq_dev && !env_dev && !bmode_dev) return c->fail(UR_ERR_INVALID_ARG, "no output requested");
+        if (g->nx < 1 || g->nz < 1 || g->nx > 65535 || g->nz > (1 << 24))
+            return c->fail(UR_ERR_INVALID_ARG, "grid size out of range");
+        const double gv[] = {g->x0, g->x1, g->z0, g->z1, g->dynamic_range_db};
+        if (!finite_all(gv, 5)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
+        if (bmode_dev && !(g->dynamic_range_db > 0)) return c->fail(UR_ERR_INVALID_ARG, "dynamic range must be > 0");
+        if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t E = c->probe.n_elements, npx = g->nx * g->nz;
+        ur_status st;
+        float *env = env_dev;
+        if (!env && bmode_dev) {
+            if ((st = alloc(c, c->d_env, npx * sizeof(float)))) return st;
+            env = (float *)c->d_env.p;
+        }
+        DasParams P;
+        P.E = (int)E;
+        P.T = (int)c->acq.n_tx;
+        P.S = (int)c->acq.n_samples;
+        P.nx = (int)g->nx;
+        P.nz = (int)g->nz;
+        P.x0 = g->x0;
+        P.dx = g->nx > 1 ? (g->x1 - g->x0) / (double)(g->nx - 1) : 0.0;
+        P.z0 = g->z0;
+        P.dz = g->nz > 1 ? (g->z1 - g->z0) / (double)(g->nz - 1) : 0.0;
+        P.fs_over_c0 = c->acq.f_s / c->acq.c0;
+        P.fs = c->acq.f_s;
+        P.xe = (const double *)c->d_xe.p;
+        P.apod = (const float *)c->d_apod.p + (g->apod == UR_APOD_HANN ? E : 0);
+        P.txc = (const double4 *)c->d_txc.p;
+        P.rf = (const float2 *)ch_rf_dev;
+        P.iq = (float2 *)iq_dev;
+        P.env = env;
+        HIP_TRY(c, hipEventRecord(c->ev[2], s));
+        HIP_TRY(c, ur_launch_das(P, s));
+        HIP_TRY(c, hipEventRecord(c->ev[3], s));
+        c->das_timed = true;
+        if (bmode_dev)
+            HIP_TRY(c, ur_launch_bmode(env, bmode_dev, npx, (float)g->dynamic_range_db, (unsigned int *)c->d_maxbits.p, s));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_last_kernel_ms(ur_context *c, double *trace_ms, double *das_ms) {
+    return guarded(c, [&]() -> ur_status {
+        float ms = 0.f;
+        if (trace_ms) {
+            *trace_ms = -1.0;
+            if (c->trace_timed) {
+                HIP_TRY(c, hipEventSynchronize(c->ev[1]));
+                HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+                *trace_ms = ms;
+            }
+        }
+        if (das_ms) {
+            *das_ms = -1.0;
+            if (c->das_timed) {
+                HIP_TRY(c, hipEventSynchronize(c->ev[3]));
+                HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+                *das_ms = ms;
+            }
+        }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_trace_rays(ur_context *c, uint64_t seed, const ur_ray *rays, int64_t n, ur_event *events, int64_t cap,
+                               int64_t *n_events, float *ch_raw_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (n < 0 || cap < 0 || (n > 0 && !rays) || (cap > 0 && !events))
+            return c->fail(UR_ERR_INVALID_ARG, "bad ray or event buffer");
+        const int64_t nm = (int64_t)c->mat.size() / 3;
+        for (int64_t i = 0; i < n; ++i) {
+            const ur_ray &r = rays[i];
+            if (r.tx < 0 || r.tx >= c->acq.n_tx || r.elem < 0 || r.elem >= c->probe.n_elements || r.medium < 0 ||
+                r.medium >= nm || r.ray < 0 || r.ray > 0xFFFFFFFFll || !finite_all(r.o, 3) || !finite_all(r.d, 3) ||
+                !std::isfinite(r.w) || !std::isfinite(r.t))
+                return c->fail(UR_ERR_INVALID_ARG, "ray %lld has an out-of-range field", (long long)i);
+            const double l = std::sqrt(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
+            if (std::fabs(l - 1.0) > 1e-9) return c->fail(UR_ERR_INVALID_ARG, "ray %lld direction is not unit", (long long)i);
+            for (int k = 0; k < 3; ++k)
+                if (r.o[k] < c->box[k] || r.o[k] > c->box[3 + k])
+                    return c->fail(UR_ERR_INVALID_ARG, "ray %lld starts outside the box", (long long)i);
+        }
+        hipStream_t s = (hipStream_t)stream;
+        ur_status st;
+        if ((st = alloc(c, c->d_rays, std::max<int64_t>(n, 1) * sizeof(ur_ray)))) return st;
+        if ((st = alloc(c, c->d_events, std::max<int64_t>(cap, 1) * sizeof(ur_event)))) return st;
+        if ((st = alloc(c, c->d_evcount, 64))) return st;
+        TraceParams P;
+        fill_params(c, P, seed);
+        const int64_t n_ch = (int64_t)P.T * P.E * P.S;
+        float *raw = ch_raw_dev;
+        DevBuf tmp;
+        if (!raw) {
+            if ((st = alloc(c, tmp, n_ch * sizeof(float)))) return st;
+            raw = (float *)tmp.p;
+        }
+        P.ch_raw = raw;
+        P.stats = (unsigned long long *)c->d_stats.p;
+        if (n) HIP_TRY(c, hipMemcpy(c->d_rays.p, rays, n * sizeof(ur_ray), hipMemcpyHostToDevice));
+        HIP_TRY(c, zero_f32(raw, n_ch, s));
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)c->d_evcount.p, 1);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P.stats, kNumStats);
+        EventLog L{c->d_events.p, (unsigned long long *)c->d_evcount.p, cap};
+        HIP_TRY(c, ur_launch_trace_rays(P, c->d_rays.p, n, L, s));
+        unsigned long long cnt = 0;
+        HIP_TRY(c, hipMemcpyAsync(&cnt, c->d_evcount.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        const int64_t keep = std::min<int64_t>((int64_t)cnt, cap);
+        if (keep) HIP_TRY(c, hipMemcpy(events, c->d_events.p, keep * sizeof(ur_event), hipMemcpyDeviceToHost));
+        if (n_events) *n_events = (int64_t)cnt;
+        tmp.release();
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_philox(ur_context *c, const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t *out) {
+    return guarded(c, [&]() -> ur_status {
+        if (n < 0 || (n > 0 && (!ctr || !out))) return c->fail(UR_ERR_INVALID_ARG, "bad counter buffer");
+        if (n == 0) return UR_OK;
+        ur_status st;
+        if ((st = alloc(c, c->d_ctr, 2 * n * 4 * sizeof(uint32_t)))) return st;
+        uint32_t *dc = (uint32_t *)c->d_ctr.p, *dout = dc + 4 * n;
+        HIP_TRY(c, hipMemcpy(dc, ctr, 4 * n * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(c, ur_launch_philox(dc, dout, n, key0, key1, nullptr));
+        HIP_TRY(c, hipDeviceSynchronize());
+        HIP_TRY(c, hipMemcpy(out, dout, 4 * n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        return UR_OK;
+    });
+}
+
+}  // extern "C"

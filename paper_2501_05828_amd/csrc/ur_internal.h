@@ -1,0 +1,91 @@
+// Internal data layouts shared by the host runtime (ur_host.cpp) and the
+// gfx950 kernels (*.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bvh_layout.h"
+
+namespace ur {
+
+constexpr int kMaxMat = 16;
+constexpr int kMaxSph = 64;
+constexpr int kMaxPln = 64;
+constexpr int kCells = 1024;          // 32 x 32 emission-direction cells
+constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
+constexpr int kNumStats = 24;
+
+// Per-material constants, FP64: impedance, amplitude attenuation [Np/m] at
+// the centre frequency, slowness [s/m].
+struct Material {
+    double Z, ka, inv_c, pad;
+};
+
+struct TraceParams {
+    // acquisition
+    int E, T, S, binning;
+    uint32_t n_el;                    // rays per element per transmit
+    int B;                            // max interface interactions
+    int proposal;                     // 0 uniform, 1 table
+    uint32_t key0, key1;
+    int64_t stride, offset, per_el, n_work;
+    double pitch, elev, fs, t_max, max_path, alpha_m, alpha_c, r_s2, n_per_tx, half_ap, area_e;
+    const double *xe;                 // [E]
+    const double *tau;                // [T][E]
+    const float *pdf, *cdf;           // [T][E][1024] or null
+    // scene
+    int n_mat, n_sph, n_pln, top_medium;
+    int64_t id_sph0, id_pln0, id_box;
+    double box[6];
+    const Material *mat;              // [n_mat]
+    const double *sph;                // [n_sph][4]
+    const int *sph_mat;               // [n_sph][2]
+    const double *pln;                // [n_pln][4]
+    const int *pln_mat;               // [n_pln][2]
+    // triangles in BVH leaf order: v0, e1 = v1 - v0, e2 = v2 - v0
+    const double *tri;                // [n_tri][9]
+    const int *tri_mat;               // [n_tri][2]
+    const int *tri_id;                // original index (tie-break, exclusion)
+    const BvhNode *tnodes;
+    int n_tri, n_tnodes;
+    // scatterers in BVH leaf order
+    const double4 *scat;              // position, amplitude
+    const int *scat_id;               // original index (RNG counter)
+    const BvhNode *snodes;
+    int n_scat, n_snodes;
+    // outputs
+    float *ch_raw;                    // [T][E][S]
+    unsigned long long *stats;        // [kNumStats] or null
+};
+
+// Explicit-ray logging (test path).
+struct EventLog {
+    void *events;                     // ur_event [cap]
+    unsigned long long *count;
+    int64_t cap;
+};
+
+struct DasParams {
+    int E, T, S, nx, nz;
+    double x0, dx, z0, dz, fs_over_c0, fs;
+    const double *xe;                 // [E]
+    const float *apod;                // [E]
+    const double4 *txc;               // [T]: (sin*fs/c0, cos*fs/c0, -xref*sin*fs/c0 - 1/2, 0)
+    const float2 *rf;                 // [T][E][S]
+    float2 *iq;                       // [nx][nz] or null
+    float *env;                       // [nx][nz]
+};
+
+}  // namespace ur
+
+// kernel launchers (defined in the .hip files)
+hipError_t ur_launch_trace(const ur::TraceParams &p, bool count, hipStream_t s);
+hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
+                                hipStream_t s);
+hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
+                           hipStream_t s);
+hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s);
+hipError_t ur_launch_bmode(const float *env, float *bmode, int64_t n, float dr_db, unsigned int *max_bits,
+                           hipStream_t s);
+hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
+                            hipStream_t s);
