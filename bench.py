@@ -1,0 +1,213 @@
+"""Benchmark of the full-path ultrasound simulation on one MI355X.
+
+A step is one pass of the hot path over one acquisition of the bone-phantom
+workload (128 elements, 11 plane waves -10..10 deg, 1e7 rays per transmit,
+8 bounces, 60k-triangle tube, 3 slabs, 50k scatterers, 4096 samples): trace
+and bin every ray, pulse-shape the channel data, delay-and-sum to a 512x512
+compounded image, envelope and log compression.  Inputs are resident on the
+GPU before timing starts; each step draws a fresh Philox key.
+
+Prints one JSON line.  The roofline entry is for the trace kernel (the
+dominant kernel): algorithmic FLOPs of one launch (per-unit costs below x
+unit counts from an instrumented pass over the same workload) divided by its
+average duration, measured with HIP events that the library records on the
+stream it launches on.  The CPU baseline is the FP64 oracle timed on a
+bounded, evenly strided sample of the same rays.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "traced rays/s + DAS frames/s; channel MSE at equal GPU time, learned vs uniform"
+PEAK_FP32 = 157.3e12      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk with packed FMA)
+PEAK_FP64 = 78.6e12       # MI355X vector FP64 (256 CU x 2.4 GHz x 128 FLOP/clk)
+PEAK_HBM = 8.0e12
+
+# Algorithmic FLOPs per counted unit of the trace kernel (add/sub/mul = 1,
+# fma = 2, div/sqrt/exp/acos = 1; compares, min/max and integer RNG work are
+# not counted).  Only the part of each test that always executes is counted.
+FP32_PER_NODE = 12          # slab test: 6 sub + 6 mul
+FP64_PER_CELL = 4           # DDA step: next crossing (fma) + advance
+FP64_PER_TRI_TEST = 24      # Moller-Trumbore up to the first barycentric test
+FP64_PER_SCAT_TEST = 8      # projection of the scatterer on the segment
+FP64_PER_SEGMENT = 16       # box exit (6) + transport (10)
+FP64_PER_PLANE = 12         # per plane per segment / secondary ray
+FP64_PER_SPHERE = 20        # per sphere per segment / secondary ray
+FP64_PER_INTERFACE = 60     # normal, Eqs. 7-11, new direction, renormalisation
+FP64_PER_EVENT = 25         # projection point, element choice geometry, directivity
+FP64_PER_NEE = 20           # contribution and record (plus planes/spheres)
+FP64_PER_RAY = 40           # emission: origin, hemisphere map, weight
+
+
+def trace_flops(st, n_pln, n_sph):
+    f32 = FP32_PER_NODE * (st["tri_nodes"] + st["shadow_nodes"])
+    f64 = (FP64_PER_TRI_TEST * (st["tri_tests"] + st["shadow_tri_tests"])
+           + FP64_PER_CELL * st["scat_cells"]
+           + FP64_PER_SCAT_TEST * st["scat_tests"]
+           + st["segments"] * (FP64_PER_SEGMENT + FP64_PER_PLANE * n_pln + FP64_PER_SPHERE * n_sph)
+           + FP64_PER_INTERFACE * (st["reflect"] + st["transmit"] + st["tir"])
+           + FP64_PER_EVENT * st["scatter_events"]
+           + st["nee_cast"] * (FP64_PER_NEE + FP64_PER_PLANE * n_pln + FP64_PER_SPHERE * n_sph)
+           + FP64_PER_RAY * st["rays"])
+    return float(f32), float(f64)
+
+
+def kernel_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload, n_launch_bytes_hint=None):
+    """HBM bytes per trace launch from committed rocprofv3 PMC summaries, or
+    None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc_trace_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, "paper_2501_05828_amd", "csrc", "k_trace.hip")
+    if d.get("kernel_hash") != kernel_hash(src):
+        return None
+    return d["fetch_bytes"] / d["copy_fetch_factor"] + d["write_bytes"] / d["copy_write_factor"]
+
+
+def cpu_threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(workload, target_rays):
+    from oracle import oracle as O
+    nel = workload.acq.rays_per_element
+    per_el = max(1, target_rays // (workload.acq.n_tx * workload.acq.n_elements))
+    stride = max(1, nel // per_el)
+    threads = cpu_threads()
+    t0 = time.perf_counter()
+    _, st = O.trace(workload, n_threads=threads, ray_stride=stride)
+    dt = time.perf_counter() - t0
+    return {"value": st["rays"] / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th ray of each (transmit, element): {st['rays']} rays of the same "
+                      f"workload traced in {dt:.1f} s (FP64, brute-force intersection)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=24000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (rays shard by transmit; "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 3}))
+        return
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.make(args.workload)
+    sim = Simulator(w)
+    acq, grid = w.acq, w.grid
+    n_rays = acq.n_rays
+    print(f"[bench] {w.name}: {n_rays:.3e} rays/frame, grid {grid.nx}x{grid.nz}", file=sys.stderr, flush=True)
+
+    # instrumented pass: unit counts for the algorithmic FLOPs of one launch
+    st = sim.trace(seed=w.seed, stats=True)
+    f32, f64 = trace_flops(st, len(w.scene.pln), len(w.scene.sph))
+    print(f"[bench] counting pass: {st['kernel_ms']:.1f} ms, records {st['records']}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        sim.step(seed=w.seed + 1000 + i)
+    torch.cuda.synchronize()
+    trace_ms, das_ms = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sim.step(seed=w.seed + i)
+        tm, dm = sim.kernel_ms()
+        trace_ms.append(tm)
+        das_ms.append(dm)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    t_trace = sum(trace_ms) / len(trace_ms) * 1e-3
+    t_das = sum(das_ms) / len(das_ms) * 1e-3
+    print(f"[bench] {ms_step:.1f} ms/step, trace kernel {1e3 * t_trace:.1f} ms, DAS {1e3 * t_das:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    achieved = (f32 + f64) / t_trace
+    peak = (f32 + f64) / (f32 / PEAK_FP32 + f64 / PEAK_FP64)
+    traffic = load_traffic(w.name)
+    out = {
+        "metric": METRIC,
+        "value": n_rays * args.steps / elapsed,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name} phantom: {acq.n_elements} elements, {acq.n_tx} plane waves "
+                        f"{round(float(acq.angles[0]) * 57.29578)}..{round(float(acq.angles[-1]) * 57.29578)} deg, "
+                        f"{acq.n_elements * acq.rays_per_element:.2e} rays/transmit, {acq.max_bounces} bounces, "
+                        f"{len(w.scene.tri)} triangles, {len(w.scene.pln)} planes, {len(w.scene.sph)} spheres, "
+                        f"{len(w.scene.scat)} scatterers, {acq.n_samples} samples at {acq.f_s / 1e6:.0f} MHz, "
+                        f"DAS {grid.nx}x{grid.nz}",
+            "rays_per_frame": n_rays,
+            "scene_seed": w.scene_seed,
+        },
+        "frames_per_s": args.steps / elapsed,
+        "das_frames_per_s": 1.0 / t_das,
+        "trace_kernel_ms": 1e3 * t_trace,
+        "das_kernel_ms": 1e3 * t_das,
+        "roofline": {
+            "kernel": "k_trace",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "flops_fp32": f32,
+            "flops_fp64": f64,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

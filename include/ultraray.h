@@ -116,7 +116,7 @@ typedef struct {
     uint64_t rays, segments, reflect, transmit, tir, scatter_events, nee_zero, nee_cast, nee_blocked,
              direct_hits, records, dropped, edge_band, term_box, term_bounce, term_time, term_path,
              media_mismatch;
-    uint64_t tri_nodes, tri_tests, scat_nodes, scat_tests, shadow_nodes, shadow_tri_tests;
+    uint64_t tri_nodes, tri_tests, scat_cells, scat_tests, shadow_nodes, shadow_tri_tests;
     double kernel_ms;         /* trace-kernel time between HIP events on the call's stream */
 } ur_trace_stats;
 
@@ -175,6 +175,15 @@ UR_API ur_status ur_set_proposal(ur_context *ctx, const float *pdf_dev, const fl
  * used, which also counts traversal work). */
 UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
+
+/* Work-size limits of later ur_trace calls: at most rays_per_launch rays are
+ * traced per kernel launch, and up to nee_queue_capacity transducer-sampling
+ * candidates (64 bytes each, library-owned device memory) are queued per
+ * launch before their secondary rays are cast.  If a launch produces more
+ * candidates than fit, that launch's range is traced again with the
+ * secondary rays cast inline, so results never depend on these limits.
+ * Defaults: 2^25 rays, 2^22 candidates. */
+UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
 /* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
  * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at

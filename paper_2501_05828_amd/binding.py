@@ -50,7 +50,7 @@ class GridDesc(C.Structure):
 
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
-               "term_time", "term_path", "media_mismatch", "tri_nodes", "tri_tests", "scat_nodes", "scat_tests",
+               "term_time", "term_path", "media_mismatch", "tri_nodes", "tri_tests", "scat_cells", "scat_tests",
                "shadow_nodes", "shadow_tri_tests"]
 
 
@@ -87,6 +87,7 @@ SIGNATURES = [
     ("ur_set_proposal", C.c_int, [_CTX, C.c_void_p, C.c_void_p]),
     ("ur_trace", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, P(TraceStats),
                            C.c_void_p]),
+    ("ur_set_limits", C.c_int, [_CTX, C.c_int64, C.c_int64]),
     ("ur_pulse", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_last_kernel_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double)]),
@@ -102,6 +103,9 @@ def load(path: str = LIB_PATH):
     """Loads libultraray.so and declares every entry point.  Raises if missing."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes this library bind to that runtime instead of a second copy
+        import torch  # noqa: F401
         if not os.path.exists(path):
             raise ImportError(f"{path} is not built: run __graft_entry__.build() (the HIP library is required; "
                               "there is no CPU fallback)")
@@ -207,6 +211,9 @@ class Context:
                                _stream_ptr(stream))
         self.check(rc, "ur_trace")
         return st.as_dict() if st is not None else None
+
+    def ur_set_limits(self, rays_per_launch, nee_queue_capacity):
+        self.check(self.lib.ur_set_limits(self.h, int(rays_per_launch), int(nee_queue_capacity)), "ur_set_limits")
 
     def ur_pulse(self, ch_raw, ch_rf, stream=None):
         self.check(self.lib.ur_pulse(self.h, _ptr(ch_raw), _ptr(ch_rf), _stream_ptr(stream)), "ur_pulse")

@@ -1,0 +1,49 @@
+// Host construction of the uniform scatterer grid (counting sort by cell).
+#include "scatter_grid.h"
+
+#include <algorithm>
+
+namespace ur {
+
+ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_scat, double r_s, double margin) {
+    ScatterGrid g;
+    double ext[3], vol = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        ext[k] = box[3 + k] - box[k];
+        vol *= ext[k];
+    }
+    const double rho = n_scat > 0 ? (double)n_scat / vol : 1.0 / vol;
+    double h = std::cbrt(0.5 / rho);
+    h = std::max(h, 4.0 * r_s);
+    h = std::max(h, std::cbrt(vol / (double)(1 << 24)) * 1.0001);
+    for (int k = 0; k < 3; ++k) {
+        g.info.lo[k] = box[k];
+        g.info.n[k] = std::max(1, (int)std::ceil(ext[k] / h));
+    }
+    g.info.h = h;
+    g.info.inv_h = 1.0 / h;
+    const long cells = (long)g.info.n[0] * g.info.n[1] * g.info.n[2];
+    g.cell_start.assign(cells + 1, 0);
+    const double r = r_s + margin;
+    auto range = [&](const double *p, int k, int &a, int &b) {
+        a = (int)std::floor((p[k] - r - g.info.lo[k]) * g.info.inv_h);
+        b = (int)std::floor((p[k] + r - g.info.lo[k]) * g.info.inv_h);
+        a = std::max(a, 0);
+        b = std::min(b, g.info.n[k] - 1);
+    };
+    auto for_cells = [&](const double *p, auto &&fn) {
+        int a[3], b[3];
+        for (int k = 0; k < 3; ++k) range(p, k, a[k], b[k]);
+        for (int z = a[2]; z <= b[2]; ++z)
+            for (int y = a[1]; y <= b[1]; ++y)
+                for (int x = a[0]; x <= b[0]; ++x) fn((long)(z * g.info.n[1] + y) * g.info.n[0] + x);
+    };
+    for (long i = 0; i < n_scat; ++i) for_cells(scat + 4 * i, [&](long c) { ++g.cell_start[c + 1]; });
+    for (long c = 0; c < cells; ++c) g.cell_start[c + 1] += g.cell_start[c];
+    g.items.resize(g.cell_start[cells]);
+    std::vector<int> fill(g.cell_start.begin(), g.cell_start.end() - 1);
+    for (long i = 0; i < n_scat; ++i) for_cells(scat + 4 * i, [&](long c) { g.items[fill[c]++] = (int)i; });
+    return g;
+}
+
+}  // namespace ur

@@ -11,8 +11,9 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ultraray.h"
+#include "ultraray.h"
 #include "bvh.h"
+#include "scatter_grid.h"
 #include "ur_internal.h"
 
 using namespace ur;
@@ -40,17 +41,21 @@ struct ur_context {
     double box[6] = {0};
     int top_medium = 0;
     int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
-    int n_tnodes = 0, n_snodes = 0;
-    std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer BVH
-    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_scat, d_scat_id,
-        d_snodes;
+    int n_tnodes = 0;
+    std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer grid
+    GridInfo grid{};
+    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_cell_start, d_items,
+        d_item_id, d_work;
     // setup
     bool has_setup = false;
     ur_probe_desc probe{};
     ur_acq_desc acq{};
     std::vector<double> angles;
     int K = 0;
-    DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr;
+    DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
+        d_nee, d_counters;
+    int64_t rays_per_launch = int64_t(1) << 25;
+    int64_t nee_cap = int64_t(1) << 22;
     const float *pdf = nullptr, *cdf = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool trace_timed = false, das_timed = false;
@@ -157,6 +162,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.max_path = a.max_path;
     P.alpha_m = a.alpha_m;
     P.alpha_c = a.alpha_c;
+    P.cos_alpha_c = std::cos(a.alpha_c);
     P.r_s2 = a.r_s * a.r_s;
     P.n_per_tx = (double)pr.n_elements * (double)a.rays_per_element;
     P.half_ap = 0.5 * (double)pr.n_elements * pr.pitch;
@@ -184,11 +190,12 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.tnodes = (const BvhNode *)c->d_tnodes.p;
     P.n_tri = (int)c->n_tri;
     P.n_tnodes = c->n_tnodes;
-    P.scat = (const double4 *)c->d_scat.p;
-    P.scat_id = (const int *)c->d_scat_id.p;
-    P.snodes = (const BvhNode *)c->d_snodes.p;
+    P.grid = c->grid;
+    P.cell_start = (const int *)c->d_cell_start.p;
+    P.items = (const double4 *)c->d_items.p;
+    P.item_id = (const int *)c->d_item_id.p;
     P.n_scat = (int)c->n_scat;
-    P.n_snodes = c->n_snodes;
+    P.work_next = (unsigned long long *)c->d_work.p;
     return UR_OK;
 }
 
@@ -243,9 +250,9 @@ UR_API void ur_context_destroy(ur_context *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
-                      &c->d_tri_id, &c->d_tnodes, &c->d_scat, &c->d_scat_id, &c->d_snodes, &c->d_xe, &c->d_tau,
-                      &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_maxbits, &c->d_env, &c->d_rays,
-                      &c->d_events, &c->d_evcount, &c->d_ctr})
+                      &c->d_tri_id, &c->d_tnodes, &c->d_cell_start, &c->d_items, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
+                      &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
+                      &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -338,8 +345,7 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
             if ((st = upload(c, c->d_tri_id, tid))) return st;
             if ((st = upload(c, c->d_tnodes, r.nodes))) return st;
         }
-        c->has_scene = true;
-        c->n_snodes = 0;   // the scatterer BVH depends on r_s: built at transmit setup
+        c->has_scene = true;   // the scatterer grid depends on r_s: built at transmit setup
         if (c->has_setup) {
             c->has_setup = false;
             ur_acq_desc a = c->acq;
@@ -424,30 +430,25 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         if ((st = upload(c, c->d_taps, taps))) return st;
         if ((st = upload(c, c->d_txc, txc))) return st;
         if ((st = alloc(c, c->d_stats, kNumStats * sizeof(unsigned long long)))) return st;
+        if ((st = alloc(c, c->d_stats2, kNumStats * sizeof(unsigned long long)))) return st;
+        if ((st = alloc(c, c->d_counters, 8 * sizeof(unsigned long long)))) return st;
         if ((st = alloc(c, c->d_maxbits, 256))) return st;
         c->has_setup = true;
         if ((st = upload_materials(c))) return st;
-        // scatterers: BVH over capture balls of radius r_s, leaves of <= 8
+        // scatterers: uniform grid; each registered in the cells its capture
+        // ball (radius r_s plus a 1 um margin) overlaps
         {
-            const double rs = a->r_s;
-            std::vector<PrimBounds> pb(c->n_scat);
-            for (int64_t i = 0; i < c->n_scat; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    pb[i].lo[k] = c->scat[4 * i + k] - rs;
-                    pb[i].hi[k] = c->scat[4 * i + k] + rs;
-                }
-            BvhResult r = build_bvh(pb, 8, rs * 1e-5 + 1e-6);
-            std::vector<double4> sc(c->n_scat);
-            std::vector<int32_t> sid(c->n_scat);
-            for (int64_t k = 0; k < c->n_scat; ++k) {
-                const double *q = c->scat.data() + 4 * (int64_t)r.order[k];
-                sc[k] = make_double4(q[0], q[1], q[2], q[3]);
-                sid[k] = r.order[k];
+            ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6);
+            std::vector<double4> items(g.items.size());
+            for (size_t k = 0; k < g.items.size(); ++k) {
+                const double *q = c->scat.data() + 4 * (int64_t)g.items[k];
+                items[k] = make_double4(q[0], q[1], q[2], q[3]);
             }
-            c->n_snodes = (int)r.nodes.size();
-            if ((st = upload(c, c->d_scat, sc))) return st;
-            if ((st = upload(c, c->d_scat_id, sid))) return st;
-            if ((st = upload(c, c->d_snodes, r.nodes))) return st;
+            c->grid = g.info;
+            if ((st = upload(c, c->d_cell_start, g.cell_start))) return st;
+            if ((st = upload(c, c->d_items, items))) return st;
+            if ((st = upload(c, c->d_item_id, g.items))) return st;
+            if ((st = alloc(c, c->d_work, 256))) return st;
         }
         return UR_OK;
     });
@@ -480,28 +481,72 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         P.n_work = (int64_t)P.T * P.E * P.per_el;
         P.ch_raw = ch_raw_dev;
         const int64_t n_ch = (int64_t)P.T * P.E * P.S;
+        ur_status st;
+        if ((st = alloc(c, c->d_nee, (size_t)c->nee_cap * sizeof(NeeEntry)))) return st;
         HIP_TRY(c, zero_f32(ch_raw_dev, n_ch, s));
+        unsigned long long *ctr = (unsigned long long *)c->d_counters.p;
+        P.nee = (NeeEntry *)c->d_nee.p;
+        P.nee_cap = c->nee_cap;
+        P.nee_count = ctr + 2;
+        unsigned long long *st1 = stats ? (unsigned long long *)c->d_stats.p : nullptr;
+        unsigned long long *st2 = stats ? (unsigned long long *)c->d_stats2.p : nullptr;
         if (stats) {
-            P.stats = (unsigned long long *)c->d_stats.p;
-            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P.stats, kNumStats);
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, st1, kNumStats);
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, st2, kNumStats);
             HIP_TRY(c, hipGetLastError());
         }
         HIP_TRY(c, hipEventRecord(c->ev[0], s));
-        HIP_TRY(c, ur_launch_trace(P, stats != nullptr, s));
+        // Work is launched in ranges: trace with queued transducer sampling,
+        // cast the queue, then (only if the queue overflowed) re-trace the
+        // range casting the sampling rays inline without direct hits.
+        for (int64_t begin = 0; begin < P.n_work; begin += c->rays_per_launch) {
+            P.work_begin = begin;
+            P.work_end = std::min(P.n_work, begin + c->rays_per_launch);
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 3);
+            HIP_TRY(c, hipGetLastError());
+            P.work_next = ctr;
+            P.stats = st1;
+            HIP_TRY(c, ur_launch_trace(P, stats != nullptr, kDeferNee, s));
+            HIP_TRY(c, ur_launch_nee(P, stats != nullptr, s));
+            TraceParams P2 = P;
+            P2.work_next = ctr + 1;
+            P2.stats = st2;
+            HIP_TRY(c, ur_launch_trace(P2, stats != nullptr, kInlineNeeOnly, s));
+        }
         HIP_TRY(c, hipEventRecord(c->ev[1], s));
         c->trace_timed = true;
         if (ch_rf_dev) HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
                                                   (int64_t)P.T * P.E, P.S, s));
         if (stats) {
-            unsigned long long h[kNumStats];
-            HIP_TRY(c, hipMemcpyAsync(h, P.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+            unsigned long long h[kNumStats], h2[kNumStats];
+            HIP_TRY(c, hipMemcpyAsync(h, st1, sizeof(h), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipMemcpyAsync(h2, st2, sizeof(h2), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipStreamSynchronize(s));
+            // the overflow re-trace contributes only its transducer-sampling work
             uint64_t *dst = &stats->rays;
             for (int k = 0; k < kNumStats; ++k) dst[k] = h[k];
+            stats->nee_cast += h2[7];
+            stats->nee_blocked += h2[8];
+            stats->records += h2[10];
+            stats->dropped += h2[11];
+            stats->edge_band += h2[12];
+            stats->shadow_nodes += h2[22];
+            stats->shadow_tri_tests += h2[23];
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
             stats->kernel_ms = ms;
         }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_set_limits(ur_context *c, int64_t rays_per_launch, int64_t nee_queue_capacity) {
+    return guarded(c, [&]() -> ur_status {
+        if (rays_per_launch < 1 || nee_queue_capacity < 1 || nee_queue_capacity > (int64_t(1) << 31))
+            return c->fail(UR_ERR_INVALID_ARG, "need rays_per_launch >= 1 and 1 <= nee_queue_capacity <= 2^31");
+        c->rays_per_launch = rays_per_launch;
+        c->nee_cap = nee_queue_capacity;
+        c->d_nee.release();
         return UR_OK;
     });
 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "bvh_layout.h"
+#include "scatter_grid.h"
 
 namespace ur {
 
@@ -21,6 +22,23 @@ struct Material {
     double Z, ka, inv_c, pad;
 };
 
+// Transducer-sampling candidate: a scatterer capture whose chosen element
+// passes the receive cut-off; the secondary ray is cast by a later kernel.
+struct NeeEntry {
+    double q[3];       // capture point on the primary segment
+    double wq;         // primary weight at q times the scatterer amplitude
+    double tq;         // arrival time at q
+    int tx, er, med, seg;
+    int k, e;          // scatterer (original index) and emitting element, for logs
+    uint32_t ray, pad;
+};
+
+// Trace-kernel modes.
+enum TraceMode {
+    kDeferNee = 0,     // direct hits recorded, transducer sampling queued
+    kInlineNeeOnly = 1 // transducer sampling cast inline, direct hits not recorded
+};
+
 struct TraceParams {
     // acquisition
     int E, T, S, binning;
@@ -30,6 +48,7 @@ struct TraceParams {
     uint32_t key0, key1;
     int64_t stride, offset, per_el, n_work;
     double pitch, elev, fs, t_max, max_path, alpha_m, alpha_c, r_s2, n_per_tx, half_ap, area_e;
+    double cos_alpha_c;               // cosine of the receive cut-off angle
     const double *xe;                 // [E]
     const double *tau;                // [T][E]
     const float *pdf, *cdf;           // [T][E][1024] or null
@@ -48,14 +67,21 @@ struct TraceParams {
     const int *tri_id;                // original index (tie-break, exclusion)
     const BvhNode *tnodes;
     int n_tri, n_tnodes;
-    // scatterers in BVH leaf order
-    const double4 *scat;              // position, amplitude
-    const int *scat_id;               // original index (RNG counter)
-    const BvhNode *snodes;
-    int n_scat, n_snodes;
-    // outputs
+    // scatterers: uniform grid, items grouped by cell (copies of position +
+    // amplitude, and the original index that keys the RNG counter)
+    GridInfo grid;
+    const int *cell_start;            // [cells + 1]
+    const double4 *items;             // [n_items]
+    const int *item_id;               // [n_items]
+    int n_scat;
+    // outputs and work distribution
     float *ch_raw;                    // [T][E][S]
     unsigned long long *stats;        // [kNumStats] or null
+    unsigned long long *work_next;    // persistent-kernel work counter (zeroed before launch)
+    int64_t work_begin, work_end;     // work items [begin, end) of this launch
+    NeeEntry *nee;                    // transducer-sampling queue
+    unsigned long long *nee_count;    // entries written (may exceed capacity)
+    int64_t nee_cap;
 };
 
 // Explicit-ray logging (test path).
@@ -79,7 +105,8 @@ struct DasParams {
 }  // namespace ur
 
 // kernel launchers (defined in the .hip files)
-hipError_t ur_launch_trace(const ur::TraceParams &p, bool count, hipStream_t s);
+hipError_t ur_launch_trace(const ur::TraceParams &p, bool count, int mode, hipStream_t s);
+hipError_t ur_launch_nee(const ur::TraceParams &p, bool count, hipStream_t s);
 hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
                                 hipStream_t s);
 hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,

@@ -1,0 +1,90 @@
+// Host self-check of the scatterer grid and the DDA walk used on the device
+// (same header): for random segments inside the box, the captures found by
+// the walk with interval ownership equal the brute-force set, each once.
+// usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed>
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+#include <random>
+#include <vector>
+
+#include "scatter_grid.h"
+
+using namespace ur;
+
+int main(int argc, char **argv) {
+    if (argc < 7) return 2;
+    long n = std::atol(argv[2]);
+    std::vector<double> S(4 * n), box(6);
+    FILE *f = std::fopen(argv[1], "rb");
+    if (!f || std::fread(S.data(), 8, S.size(), f) != S.size()) return 2;
+    std::fclose(f);
+    f = std::fopen(argv[3], "rb");
+    if (!f || std::fread(box.data(), 8, 6, f) != 6) return 2;
+    std::fclose(f);
+    double rs = std::atof(argv[4]);
+    long nseg = std::atol(argv[5]);
+    ScatterGrid g = build_scatter_grid(box.data(), S.data(), n, rs, rs * 1e-5 + 1e-6);
+    // structure: every scatterer registered in the cell that holds its centre
+    for (long i = 0; i < n; ++i) {
+        int c[3];
+        bool inside = true;
+        for (int k = 0; k < 3; ++k) {
+            c[k] = (int)std::floor((S[4 * i + k] - g.info.lo[k]) * g.info.inv_h);
+            if (c[k] < 0 || c[k] >= g.info.n[k]) inside = false;
+        }
+        if (!inside) continue;
+        long cell = ((long)c[2] * g.info.n[1] + c[1]) * g.info.n[0] + c[0];
+        bool found = false;
+        for (int j = g.cell_start[cell]; j < g.cell_start[cell + 1]; ++j) found |= g.items[j] == i;
+        if (!found) { std::printf("scatterer %ld missing from its cell\n", i); return 1; }
+    }
+    std::mt19937_64 rng(std::atol(argv[6]));
+    std::uniform_real_distribution<double> U(0, 1);
+    std::normal_distribution<double> N(0, 1);
+    long bad = 0, events = 0, cells = 0, tests = 0;
+    for (long q = 0; q < nseg; ++q) {
+        double o[3], d[3], l = 0;
+        for (int k = 0; k < 3; ++k) o[k] = box[k] + (box[3 + k] - box[k]) * U(rng);
+        if (q % 5 == 0) o[2] = box[2];
+        for (int k = 0; k < 3; ++k) { d[k] = N(rng); l += d[k] * d[k]; }
+        l = std::sqrt(l);
+        for (int k = 0; k < 3; ++k) d[k] /= l;
+        if (q % 11 == 0) { d[0] = 0; d[1] = 0; d[2] = 1; }
+        if (q % 13 == 0) { d[0] = 1; d[1] = 0; d[2] = 0; o[2] = box[2] + 7 * g.info.h; }
+        double tend = INFINITY;
+        for (int k = 0; k < 3; ++k) {
+            if (d[k] > 0) tend = std::fmin(tend, (box[3 + k] - o[k]) / d[k]);
+            if (d[k] < 0) tend = std::fmin(tend, (box[k] - o[k]) / d[k]);
+        }
+        tend *= U(rng) < 0.3 ? U(rng) : 1.0;
+        std::vector<int> want, got;
+        for (long i = 0; i < n; ++i) {
+            double p[3] = {S[4 * i] - o[0], S[4 * i + 1] - o[1], S[4 * i + 2] - o[2]};
+            double s = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
+            if (!(s >= 0 && s < tend)) continue;
+            double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
+            if (pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2] <= rs * rs) want.push_back((int)i);
+        }
+        cells += dda_walk(g.info, o, d, tend, [&](int cell, double ta, double tb) {
+            for (int j = g.cell_start[cell]; j < g.cell_start[cell + 1]; ++j) {
+                const int i = g.items[j];
+                ++tests;
+                double p[3] = {S[4 * i] - o[0], S[4 * i + 1] - o[1], S[4 * i + 2] - o[2]};
+                double s = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
+                if (!(s >= ta && s < tb)) continue;
+                double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
+                if (pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2] <= rs * rs) got.push_back(i);
+            }
+            return true;
+        });
+        std::sort(want.begin(), want.end());
+        std::sort(got.begin(), got.end());
+        if (want != got) ++bad;
+        events += (long)want.size();
+    }
+    std::printf("grid %dx%dx%d h=%.3g items=%zu segments=%ld events=%ld cells/seg=%.1f tests/seg=%.1f bad=%ld\n",
+                g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, g.items.size(), nseg, events,
+                (double)cells / nseg, (double)tests / nseg, bad);
+    return bad ? 1 : 0;
+}

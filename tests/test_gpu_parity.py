@@ -274,3 +274,18 @@ def test_abi_errors(torch_gpu):
         ctx.ur_trace(1, buf, ray_stride=0)
     with pytest.raises(binding.URError, match="INVALID_ARG"):
         ctx.ur_trace_rays(1, [dict(o=[0, 0, -1.0], d=[0, 0, 1.0])])
+
+
+def test_sampling_queue_overflow_retrace(torch_gpu, oracle):
+    """A transducer-sampling queue far too small for the launch: the range is
+    traced again with inline secondary rays and the result is unchanged."""
+    w = scenes.tiny(rays_per_element=512)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45)))
+    s = _sim(w)
+    s.ctx.ur_set_limits(4096, 7)
+    st = s.trace(stats=True, pulse=False)
+    g = s.ch_raw.cpu().numpy()
+    ref, ost = oracle.trace(w)
+    for k in EXACT_STATS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert rel_l2(g, ref) <= TOL_CH
