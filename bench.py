@@ -43,19 +43,19 @@ FP64_PER_PLANE = 12         # per plane per segment / secondary ray
 FP64_PER_SPHERE = 20        # per sphere per segment / secondary ray
 FP64_PER_INTERFACE = 60     # normal, Eqs. 7-11, new direction, renormalisation
 FP64_PER_EVENT = 25         # projection point, element choice geometry, directivity
-FP64_PER_NEE = 20           # contribution and record (plus planes/spheres)
 FP64_PER_RAY = 40           # emission: origin, hemisphere map, weight
 
 
 def trace_flops(st, n_pln, n_sph):
-    f32 = FP32_PER_NODE * (st["tri_nodes"] + st["shadow_nodes"])
-    f64 = (FP64_PER_TRI_TEST * (st["tri_tests"] + st["shadow_tri_tests"])
+    """FLOPs of the trace kernel proper (the secondary rays are cast by a
+    separate kernel and are excluded)."""
+    f32 = FP32_PER_NODE * st["tri_nodes"]
+    f64 = (FP64_PER_TRI_TEST * st["tri_tests"]
            + FP64_PER_CELL * st["scat_cells"]
            + FP64_PER_SCAT_TEST * st["scat_tests"]
            + st["segments"] * (FP64_PER_SEGMENT + FP64_PER_PLANE * n_pln + FP64_PER_SPHERE * n_sph)
            + FP64_PER_INTERFACE * (st["reflect"] + st["transmit"] + st["tir"])
            + FP64_PER_EVENT * st["scatter_events"]
-           + st["nee_cast"] * (FP64_PER_NEE + FP64_PER_PLANE * n_pln + FP64_PER_SPHERE * n_sph)
            + FP64_PER_RAY * st["rays"])
     return float(f32), float(f64)
 

@@ -117,7 +117,7 @@ typedef struct {
              direct_hits, records, dropped, edge_band, term_box, term_bounce, term_time, term_path,
              media_mismatch;
     uint64_t tri_nodes, tri_tests, scat_cells, scat_tests, shadow_nodes, shadow_tri_tests;
-    double kernel_ms;         /* trace-kernel time between HIP events on the call's stream */
+    double kernel_ms;         /* time of the whole trace stage between HIP events on the call's stream */
 } ur_trace_stats;
 
 /* One entry of an explicit-ray path log (ur_trace_rays). */
@@ -182,7 +182,7 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
  * launch before their secondary rays are cast.  If a launch produces more
  * candidates than fit, that launch's range is traced again with the
  * secondary rays cast inline, so results never depend on these limits.
- * Defaults: 2^25 rays, 2^22 candidates. */
+ * Defaults: 2^30 rays, 2^22 candidates. */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
 /* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
@@ -199,10 +199,11 @@ UR_API ur_status ur_pulse(ur_context *ctx, const float *ch_raw_dev, float *ch_rf
 UR_API ur_status ur_beamform(ur_context *ctx, const ur_grid_desc *grid, const float *ch_rf_dev, float *iq_dev,
                              float *env_dev, float *bmode_dev, void *stream);
 
-/* Device time (milliseconds, between HIP events recorded on the call's
- * stream immediately around the kernel) of the trace kernel of the last
- * ur_trace call and of the delay-and-sum kernel of the last ur_beamform call;
- * -1 where no such call was made.  Waits for those events. */
+/* Device time in milliseconds, between HIP events recorded on the call's
+ * stream immediately around each kernel launch: the trace-kernel launches of
+ * the last ur_trace call (summed; secondary-ray casting and pulse shaping
+ * excluded) and the delay-and-sum kernel of the last ur_beamform call; -1
+ * where no such call was made.  Waits for those events. */
 UR_API ur_status ur_last_kernel_ms(ur_context *ctx, double *trace_ms, double *das_ms);
 
 /* Test and debugging aid: traces the given host rays one by one with the

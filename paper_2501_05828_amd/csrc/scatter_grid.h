@@ -27,57 +27,76 @@ struct GridInfo {
     int n[3];           // cells per axis
 };
 
-// Visits the cells pierced by o + t d for t in [0, t_end) in order.  visit
-// returns false to stop early.  Returns the number of cells visited.  Axis
-// state is kept in scalars (no dynamically indexed arrays) so that device
-// code keeps it in registers.
-template <class F>
-UR_HD int dda_walk(const GridInfo &g, const double *o, const double *d, double t_end, F &&visit) {
-    const double h = g.h;
-    int cx = (int)floor((o[0] - g.lo[0]) * g.inv_h);
-    int cy = (int)floor((o[1] - g.lo[1]) * g.inv_h);
-    int cz = (int)floor((o[2] - g.lo[2]) * g.inv_h);
-    cx = cx < 0 ? 0 : (cx > g.n[0] - 1 ? g.n[0] - 1 : cx);
-    cy = cy < 0 ? 0 : (cy > g.n[1] - 1 ? g.n[1] - 1 : cy);
-    cz = cz < 0 ? 0 : (cz > g.n[2] - 1 ? g.n[2] - 1 : cz);
-    const int sx = d[0] > 0.0 ? 1 : (d[0] < 0.0 ? -1 : 0);
-    const int sy = d[1] > 0.0 ? 1 : (d[1] < 0.0 ? -1 : 0);
-    const int sz = d[2] > 0.0 ? 1 : (d[2] < 0.0 ? -1 : 0);
-    const double ix = sx ? 1.0 / d[0] : 0.0, iy = sy ? 1.0 / d[1] : 0.0, iz = sz ? 1.0 / d[2] : 0.0;
-    // parameter at which the ray crosses the next cell face on each axis
-    double tmx = sx ? (g.lo[0] + (double)(cx + (sx > 0)) * h - o[0]) * ix : INFINITY;
-    double tmy = sy ? (g.lo[1] + (double)(cy + (sy > 0)) * h - o[1]) * iy : INFINITY;
-    double tmz = sz ? (g.lo[2] + (double)(cz + (sz > 0)) * h - o[2]) * iz : INFINITY;
-    const int nx = g.n[0], nxy = g.n[0] * g.n[1];
-    int cell = cz * nxy + cy * nx + cx;
-    const int limit = g.n[0] + g.n[1] + g.n[2] + 3;
-    double ta = 0.0;
-    int visited = 0;
-    while (true) {
-        const bool ax = tmx <= tmy && tmx <= tmz;
-        const bool ay = !ax && tmy <= tmz;
-        const double tn = ax ? tmx : (ay ? tmy : tmz);
-        const double tb = tn < t_end ? tn : t_end;
-        ++visited;
-        if (tb > ta && !visit(cell, ta, tb)) break;
-        if (tb >= t_end || visited >= limit) break;
-        if (ax) {
+// Cell-by-cell walker.  After init(), the ray is in cell `cell` for the
+// parameter interval [ta, bound(t_end)); step() moves to the next pierced
+// cell (false once the ray leaves the grid).  Axis state is kept in scalars
+// (no dynamically indexed arrays) so device code keeps it in registers.
+struct DdaIter {
+    int cx, cy, cz, sx, sy, sz, cell;
+    double ix, iy, iz, tmx, tmy, tmz, ta;
+
+    UR_HD void init(const GridInfo &g, const double *o, const double *d) {
+        cx = (int)floor((o[0] - g.lo[0]) * g.inv_h);
+        cy = (int)floor((o[1] - g.lo[1]) * g.inv_h);
+        cz = (int)floor((o[2] - g.lo[2]) * g.inv_h);
+        cx = cx < 0 ? 0 : (cx > g.n[0] - 1 ? g.n[0] - 1 : cx);
+        cy = cy < 0 ? 0 : (cy > g.n[1] - 1 ? g.n[1] - 1 : cy);
+        cz = cz < 0 ? 0 : (cz > g.n[2] - 1 ? g.n[2] - 1 : cz);
+        sx = d[0] > 0.0 ? 1 : (d[0] < 0.0 ? -1 : 0);
+        sy = d[1] > 0.0 ? 1 : (d[1] < 0.0 ? -1 : 0);
+        sz = d[2] > 0.0 ? 1 : (d[2] < 0.0 ? -1 : 0);
+        ix = sx ? 1.0 / d[0] : 0.0;
+        iy = sy ? 1.0 / d[1] : 0.0;
+        iz = sz ? 1.0 / d[2] : 0.0;
+        // parameter at which the ray crosses the next cell face on each axis
+        tmx = sx ? (g.lo[0] + (double)(cx + (sx > 0)) * g.h - o[0]) * ix : INFINITY;
+        tmy = sy ? (g.lo[1] + (double)(cy + (sy > 0)) * g.h - o[1]) * iy : INFINITY;
+        tmz = sz ? (g.lo[2] + (double)(cz + (sz > 0)) * g.h - o[2]) * iz : INFINITY;
+        cell = (cz * g.n[1] + cy) * g.n[0] + cx;
+        ta = 0.0;
+    }
+    UR_HD double bound(double t_end) const {
+        const double tn = fmin(tmx, fmin(tmy, tmz));
+        return tn < t_end ? tn : t_end;
+    }
+    // Moves to the next cell; the interval start becomes the previous bound.
+    UR_HD bool step(const GridInfo &g, const double *o, double tb) {
+        if (tmx <= tmy && tmx <= tmz) {
             cx += sx;
-            if (cx < 0 || cx >= g.n[0]) break;
+            if (cx < 0 || cx >= g.n[0]) return false;
             cell += sx;
-            tmx = (g.lo[0] + (double)(cx + (sx > 0)) * h - o[0]) * ix;
-        } else if (ay) {
+            tmx = (g.lo[0] + (double)(cx + (sx > 0)) * g.h - o[0]) * ix;
+        } else if (tmy <= tmz) {
             cy += sy;
-            if (cy < 0 || cy >= g.n[1]) break;
-            cell += sy * nx;
-            tmy = (g.lo[1] + (double)(cy + (sy > 0)) * h - o[1]) * iy;
+            if (cy < 0 || cy >= g.n[1]) return false;
+            cell += sy * g.n[0];
+            tmy = (g.lo[1] + (double)(cy + (sy > 0)) * g.h - o[1]) * iy;
         } else {
             cz += sz;
-            if (cz < 0 || cz >= g.n[2]) break;
-            cell += sz * nxy;
-            tmz = (g.lo[2] + (double)(cz + (sz > 0)) * h - o[2]) * iz;
+            if (cz < 0 || cz >= g.n[2]) return false;
+            cell += sz * g.n[0] * g.n[1];
+            tmz = (g.lo[2] + (double)(cz + (sz > 0)) * g.h - o[2]) * iz;
         }
         if (tb > ta) ta = tb;
+        return true;
+    }
+};
+
+// Visits the cells pierced by o + t d for t in [0, t_end) in order, with
+// the interval [ta, tb) spent in each (empty intervals skipped).  visit
+// returns false to stop early.  Returns the number of cells stepped through.
+template <class F>
+UR_HD int dda_walk(const GridInfo &g, const double *o, const double *d, double t_end, F &&visit) {
+    DdaIter it;
+    it.init(g, o, d);
+    const int limit = g.n[0] + g.n[1] + g.n[2] + 3;
+    int visited = 0;
+    while (true) {
+        const double tb = it.bound(t_end);
+        ++visited;
+        if (tb > it.ta && !visit(it.cell, it.ta, tb)) break;
+        if (tb >= t_end || visited >= limit) break;
+        if (!it.step(g, o, tb)) break;
     }
     return visited;
 }

@@ -54,7 +54,9 @@ struct ur_context {
     int K = 0;
     DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
         d_nee, d_counters;
-    int64_t rays_per_launch = int64_t(1) << 25;
+    int64_t rays_per_launch = int64_t(1) << 30;
+    std::vector<hipEvent_t> tev;           // [2 * launches] around each trace-kernel launch
+    int n_tev = 0;
     int64_t nee_cap = int64_t(1) << 22;
     const float *pdf = nullptr, *cdf = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -255,6 +257,8 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters})
         b->release();
     for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->tev)
         if (e) (void)hipEventDestroy(e);
     delete c;
 }
@@ -495,6 +499,14 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, st2, kNumStats);
             HIP_TRY(c, hipGetLastError());
         }
+        const int64_t launches = (P.n_work + c->rays_per_launch - 1) / c->rays_per_launch;
+        while ((int64_t)c->tev.size() < 2 * launches) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            c->tev.push_back(e);
+        }
+        c->n_tev = 0;
+        c->trace_timed = false;
         HIP_TRY(c, hipEventRecord(c->ev[0], s));
         // Work is launched in ranges: trace with queued transducer sampling,
         // cast the queue, then (only if the queue overflowed) re-trace the
@@ -506,7 +518,10 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             HIP_TRY(c, hipGetLastError());
             P.work_next = ctr;
             P.stats = st1;
+            HIP_TRY(c, hipEventRecord(c->tev[2 * c->n_tev], s));
             HIP_TRY(c, ur_launch_trace(P, stats != nullptr, kDeferNee, s));
+            HIP_TRY(c, hipEventRecord(c->tev[2 * c->n_tev + 1], s));
+            ++c->n_tev;
             HIP_TRY(c, ur_launch_nee(P, stats != nullptr, s));
             TraceParams P2 = P;
             P2.work_next = ctr + 1;
@@ -514,7 +529,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             HIP_TRY(c, ur_launch_trace(P2, stats != nullptr, kInlineNeeOnly, s));
         }
         HIP_TRY(c, hipEventRecord(c->ev[1], s));
-        c->trace_timed = true;
+        c->trace_timed = c->n_tev > 0;
         if (ch_rf_dev) HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
                                                   (int64_t)P.T * P.E, P.S, s));
         if (stats) {
@@ -615,9 +630,13 @@ UR_API ur_status ur_last_kernel_ms(ur_context *c, double *trace_ms, double *das_
         if (trace_ms) {
             *trace_ms = -1.0;
             if (c->trace_timed) {
-                HIP_TRY(c, hipEventSynchronize(c->ev[1]));
-                HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-                *trace_ms = ms;
+                double sum = 0.0;
+                for (int i = 0; i < c->n_tev; ++i) {
+                    HIP_TRY(c, hipEventSynchronize(c->tev[2 * i + 1]));
+                    HIP_TRY(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
+                    sum += ms;
+                }
+                *trace_ms = sum;
             }
         }
         if (das_ms) {
