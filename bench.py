@@ -101,6 +101,96 @@ def cpu_baseline(workload, target_rays):
                       f"workload traced in {dt:.1f} s (FP64, brute-force intersection)"}
 
 
+def learned_experiment(args):
+    """Channel-data MSE against GPU time for uniform and learned emission on
+    the bone phantom: reference = mean of uniform traces totalling 1e9 rays per
+    transmit; MSE of Re(ch_rf); time = device time of trace (including the
+    secondary-ray kernel) and pulse shaping, proposal inference included."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.proposal import Proposal
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.learned()
+    acq0 = w.acq
+    E, T = acq0.n_elements, acq0.n_tx
+    sim = Simulator(w)
+
+    def set_rays(per_tx):
+        sim.set_acquisition(dataclasses.replace(acq0, rays_per_element=max(1, int(per_tx) // E)))
+
+    def timed_trace(seed):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sim.trace(seed=seed, pulse=True)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    t0 = time.perf_counter()
+    set_rays(args.ref_rays_per_tx / args.ref_parts)
+    ref = torch.zeros_like(sim.ch_rf[..., 0], dtype=torch.float64)
+    for k in range(args.ref_parts):
+        timed_trace(0xAB000000 + k)
+        ref += sim.ch_rf[..., 0].double()
+    ref /= args.ref_parts
+    t_ref = time.perf_counter() - t0
+    print(f"[learned] reference {args.ref_rays_per_tx:.1e} rays/tx in {t_ref:.1f} s", file=sys.stderr, flush=True)
+
+    prop = Proposal(sim)
+    set_rays(1e7)
+    t0 = time.perf_counter()
+    n_rec, offered = prop.record(args.record_traces)
+    losses = prop.train(steps=args.train_steps, batch=1 << 16, lr=1e-3, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"[learned] {n_rec} records, {args.train_steps} steps in {t_train:.1f} s, loss {losses}",
+          file=sys.stderr, flush=True)
+
+    budgets = [1e6, 3e6, 1e7, 3e7, 1e8]
+    curves = {"uniform": [], "learned": []}
+    for mode in ("uniform", "learned"):
+        for bi, per_tx in enumerate(budgets):
+            set_rays(per_tx)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            if mode == "learned":
+                prop.enable(0.1)
+            else:
+                prop.disable()
+            b.record()
+            b.synchronize()
+            t_inf = a.elapsed_time(b) * 1e-3 if mode == "learned" else 0.0
+            reps = 2 if per_tx < 3e7 else 1
+            mse, tg = 0.0, 0.0
+            for r in range(reps):
+                tg += timed_trace(0xCD000000 + 97 * bi + r + (0 if mode == "uniform" else 50000))
+                mse += float(((sim.ch_rf[..., 0].double() - ref) ** 2).mean())
+            curves[mode].append({"rays_per_tx": per_tx, "mse": mse / reps, "gpu_s": tg / reps + t_inf})
+            print(f"[learned] {mode} {per_tx:.0e}/tx: mse {mse / reps:.4e} time {tg / reps + t_inf:.4f} s",
+                  file=sys.stderr, flush=True)
+    # time uniform needs to reach each learned MSE (log-log interpolation)
+    lu = np.log([c["mse"] for c in curves["uniform"]])
+    tu = np.log([c["gpu_s"] for c in curves["uniform"]])
+    ratios = []
+    for c in curves["learned"]:
+        m = np.log(c["mse"])
+        if lu.min() <= m <= lu.max():
+            order = np.argsort(lu)
+            t_u = float(np.exp(np.interp(m, lu[order], tu[order])))
+            ratios.append({"rays_per_tx": c["rays_per_tx"], "learned_s": c["gpu_s"], "uniform_s_same_mse": t_u,
+                           "time_ratio": c["gpu_s"] / t_u})
+    out = {"metric": "channel MSE at equal GPU time, learned vs uniform", "workload": "bone phantom (learned)",
+           "reference_rays_per_tx": args.ref_rays_per_tx, "records": n_rec, "records_offered": offered,
+           "train_steps": args.train_steps, "train_s": t_train, "loss_log": losses, "curves": curves,
+           "learned_time_over_uniform_time_at_equal_mse": ratios}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +199,12 @@ def main():
     ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=24000)
+    ap.add_argument("--experiment", choices=["learned"], default=None,
+                    help="learned: channel MSE vs GPU time, learned vs uniform emission")
+    ap.add_argument("--ref-rays-per-tx", type=float, default=1e9)
+    ap.add_argument("--ref-parts", type=int, default=10)
+    ap.add_argument("--record-traces", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -121,6 +217,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.experiment == "learned":
+        learned_experiment(args)
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 28, device="cuda")
         b = torch.empty_like(a)

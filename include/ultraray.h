@@ -215,6 +215,55 @@ UR_API ur_status ur_trace_rays(ur_context *ctx, uint64_t seed, const ur_ray *ray
                                ur_event *events, int64_t cap, int64_t *n_events, float *ch_raw_dev,
                                void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned emission proposal (Eq. 4's direction pdf p_t, learned per
+ * (transmit, element) row).  The network maps the row's normalised element
+ * position and steering angle plus a 32-dimensional random Fourier encoding
+ * [sin(2 pi B v), cos(2 pi B v)], B given as 16x2 floats, through three ReLU
+ * layers of width 64 to a softmax over the 32x32 equal-area direction cells
+ * (77,120 FP32 parameters in the order W1[34][64], b1[64], W2[64][64], b2,
+ * W3[64][64], b3, W4[64][1024], b4[1024]).  Matrix products use BF16 operands
+ * with FP32 accumulation.  Rows are r = tx * n_elements + e for the current
+ * transmit setup; a new setup requires ur_mlp_init again.
+ * ------------------------------------------------------------------------- */
+
+/* Loads parameters (host, 77,120 floats) and the Fourier matrix (host,
+ * 16x2 floats) and resets the Adam state.  Synchronous. */
+UR_API ur_status ur_mlp_init(ur_context *ctx, const float *params, const float *rff);
+
+/* Copies the current parameters to host memory (77,120 floats).  Synchronous. */
+UR_API ur_status ur_mlp_get_params(ur_context *ctx, float *params);
+
+/* q_dev [rows][1024]: the network's direction distribution for every row. */
+UR_API ur_status ur_mlp_forward(ur_context *ctx, float *q_dev, void *stream);
+
+/* Weighted cross-entropy L = -sum H log q / sum H for the target histogram
+ * hist_dev [rows][1024] (summed contribution magnitudes per emission cell),
+ * its gradient grad_dev [77,120] and the loss loss_dev [1] (nullable). */
+UR_API ur_status ur_mlp_loss_grad(ur_context *ctx, const float *hist_dev, float *grad_dev, float *loss_dev,
+                                  void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the loss above. */
+UR_API ur_status ur_mlp_train_step(ur_context *ctx, const float *hist_dev, float lr, float *loss_dev, void *stream);
+
+/* Proposal tables for ur_set_proposal: pdf = (1 - eps) q + eps / 1024 (the
+ * uniform component keeps every direction reachable, so the 1/pdf-weighted
+ * estimator stays unbiased) and its inclusive prefix sum, [rows][1024]. */
+UR_API ur_status ur_mlp_proposal_tables(ur_context *ctx, float eps, float *pdf_dev, float *cdf_dev, void *stream);
+
+/* Recording of contributions during later ur_trace calls: every binned
+ * contribution c appends {bin = (tx * n_elements + emitting element) * 1024 +
+ * emission cell (uint32), |c| (float)} to rec_dev (8-byte entries, capacity
+ * cap) and increments *count_dev (device, unsigned 64-bit; counts also the
+ * records that did not fit).  rec_dev = NULL stops recording. */
+UR_API ur_status ur_set_record(ur_context *ctx, void *rec_dev, int64_t cap, unsigned long long *count_dev);
+
+/* Minibatch target: hist_dev [rows][1024] is zeroed, then `batch` records
+ * drawn uniformly with replacement from rec_dev[0, n_rec) (Philox with key
+ * `seed`, counter (draw, step)) add their |c| to their bins. */
+UR_API ur_status ur_record_histogram(ur_context *ctx, const void *rec_dev, int64_t n_rec, int64_t batch,
+                                     uint64_t seed, uint32_t step, float *hist_dev, void *stream);
+
 /* Philox4x32-10 evaluated on the device for n counters (host arrays
  * ctr [n][4], out [n][4]) under key (key0, key1); for checking that the
  * device stream equals the published generator.  Synchronous. */

@@ -87,6 +87,7 @@ typedef struct {
 
 typedef struct {
     double *hist;      /* [tx][e][n] or NULL */
+    double *rhist;     /* [tx][e_emit][cell]: summed |c| of binned contributions, or NULL */
     or_event *ev;
     int64_t cap, n;
     or_stats st;
@@ -178,7 +179,8 @@ void or_hemisphere(double a, double b, double d[3])
 /* Ray emission: origin uniform on the element face, direction from the
  * proposal, Monte Carlo weight = emission directivity (cosine, Eq. 6) over
  * (number of rays per transmit x direction pdf) as in Eq. 4. */
-static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3], double d[3], double *w)
+static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3], double d[3], double *w,
+                 int64_t *cell_out)
 {
     const or_acq *a = C->a;
     uint32_t x[4];
@@ -192,6 +194,7 @@ static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3]
         ca = u2;
         cb = u3;
         pdf = 1.0 / (2.0 * PI);
+        *cell_out = (int64_t)floor(32.0 * u3) * 32 + (int64_t)floor(32.0 * u2);
     } else {
         uint32_t y[4];
         draw(C, ray, e, tx, 0, 3, 0, y);
@@ -204,6 +207,7 @@ static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3]
                 break;
             }
         }
+        *cell_out = cell;
         ca = ((double)(cell % 32) + u2) / 32.0;
         cb = ((double)(cell / 32) + u3) / 32.0;
         pdf = (double)a->pdf[(tx * a->n_elements + e) * NCELL + cell] * (double)NCELL / (2.0 * PI);
@@ -473,7 +477,7 @@ static void log_event(sink *K, int64_t kind, int64_t tx, int64_t elem, int64_t s
  * record between the two samples whose centres (n + 1/2)/fs bracket it.
  * Arrivals at or after S/fs fall outside the record window. */
 static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, int64_t seg, int64_t id,
-                   double t, double v, const double p[3])
+                   double t, double v, const double p[3], int64_t e_emit, int64_t cell)
 {
     const or_acq *a = C->a;
     log_event(K, kind, tx, e, seg, id, t, v, p);
@@ -482,6 +486,7 @@ static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, 
         return;
     }
     K->st.records++;
+    if (K->rhist && cell >= 0) K->rhist[(tx * a->n_elements + e_emit) * NCELL + cell] += fabs(v);
     double x = t * a->f_s;
     double fr = x - floor(x);
     if (fr < 1e-5 || fr > 1.0 - 1e-5) K->st.edge_band++;
@@ -512,7 +517,7 @@ static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, 
  * element normal.  The element subtends area*cos(alpha)/r^2 of the 4 pi
  * re-radiation, divided by the 1/E choice probability. */
 static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg, int64_t k,
-                        const double o[3], const double d[3], double w, double t, int64_t med, double s)
+                        const double o[3], const double d[3], double w, double t, int64_t med, double s, int64_t cell)
 {
     const or_acq *a = C->a;
     const or_scene *sc = C->s;
@@ -594,13 +599,14 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     double tc = tq + dist * C->inv_c[med] + sum_c;
     double amp = sc->scat[4 * k + 3];
     double c = wq * amp * (double)a->n_elements * C->area_e * cos_a * fdir / (4.0 * PI * dist * dist) * T * att;
-    record(C, K, 1, tx, er, seg, k, tc, c, q);
+    record(C, K, 1, tx, er, seg, k, tc, c, q, e, cell);
 }
 
 /* All scatterers whose capture capsule the segment [0, t_seg) passes:
  * projection s = (p_k - o).d in [0, t_seg) and perpendicular distance <= r_s. */
 static void scatter_events(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg,
-                           const double o[3], const double d[3], double w, double t, int64_t med, double t_seg)
+                           const double o[3], const double d[3], double w, double t, int64_t med, double t_seg,
+                           int64_t cell)
 {
     const or_scene *sc = C->s;
     double r2 = C->a->r_s * C->a->r_s;
@@ -611,7 +617,7 @@ static void scatter_events(const octx *C, sink *K, int64_t tx, int64_t e, uint32
         if (!(s >= 0.0 && s < t_seg)) continue;
         double perp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
         if (dot3(perp, perp) > r2) continue;
-        scatter_nee(C, K, tx, e, ray, seg, k, o, d, w, t, med, s);
+        scatter_nee(C, K, tx, e, ray, seg, k, o, d, w, t, med, s, cell);
     }
 }
 
@@ -625,7 +631,7 @@ static void scatter_events(const octx *C, sink *K, int64_t tx, int64_t e, uint32
  * interaction limit is reached.  The ray also ends when its path exceeds
  * max_path (the segment is clipped there) or its time leaves the window. */
 static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, const double o_in[3],
-                       const double d_in[3], double w, double t, int64_t med)
+                       const double d_in[3], double w, double t, int64_t med, int64_t cell)
 {
     const or_acq *a = C->a;
     const or_scene *sc = C->s;
@@ -642,7 +648,7 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
             t_seg = a->max_path - len;
             clipped = 1;
         }
-        scatter_events(C, K, tx, e, ray, b, o, d, w, t, med, t_seg);
+        scatter_events(C, K, tx, e, ray, b, o, d, w, t, med, t_seg, cell);
         w *= exp(-C->ka[med] * t_seg);
         t += t_seg * C->inv_c[med];
         len += t_seg;
@@ -667,7 +673,7 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
                 double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
                 if (fdir > 0.0) {
                     K->st.direct_hits++;
-                    record(C, K, 0, tx, er, b, -1, t, w * fdir, o);
+                    record(C, K, 0, tx, er, b, -1, t, w * fdir, o, e, cell);
                 }
             }
             K->st.term_box++;
@@ -726,7 +732,7 @@ static void stats_add(or_stats *a, const or_stats *b)
 }
 
 static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t stride, double *ch_raw,
-                      or_stats *st_out)
+                      double *rec_hist, or_stats *st_out)
 {
     if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
         a->rays_per_element < 0 || a->max_bounces < 0 || a->max_bounces > 65535 || stride <= 0)
@@ -743,9 +749,14 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
     size_t nh = (size_t)(a->n_tx * a->n_elements * a->n_samples);
     sink *sinks = (sink *)calloc((size_t)nt, sizeof(sink));
     if (!sinks) return -2;
+    size_t nr = (size_t)(a->n_tx * a->n_elements * NCELL);
     for (int i = 0; i < nt; ++i) {
         sinks[i].hist = (double *)calloc(nh, sizeof(double));
         if (!sinks[i].hist) return -2;
+        if (rec_hist) {
+            sinks[i].rhist = (double *)calloc(nr, sizeof(double));
+            if (!sinks[i].rhist) return -2;
+        }
     }
     int64_t per_el = (a->rays_per_element + stride - 1) / stride;
     int64_t n_work = a->n_tx * a->n_elements * per_el;
@@ -761,17 +772,22 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
         int64_t e = (i / per_el) % a->n_elements;
         int64_t tx = i / (per_el * a->n_elements);
         double o[3], d[3], w;
-        emit(&C, tx, e, (uint32_t)rr, o, d, &w);
+        int64_t cell = -1;
+        emit(&C, tx, e, (uint32_t)rr, o, d, &w, &cell);
         trace_path(&C, &sinks[tid], tx, e, (uint32_t)rr, o, d, w, C.tau[tx * a->n_elements + e],
-                   s->top_medium);
+                   s->top_medium, cell);
     }
     memset(ch_raw, 0, nh * sizeof(double));
     or_stats st;
     memset(&st, 0, sizeof(st));
+    if (rec_hist) memset(rec_hist, 0, nr * sizeof(double));
     for (int i = 0; i < nt; ++i) {
         for (size_t j = 0; j < nh; ++j) ch_raw[j] += sinks[i].hist[j];
+        if (rec_hist)
+            for (size_t j = 0; j < nr; ++j) rec_hist[j] += sinks[i].rhist[j];
         stats_add(&st, &sinks[i].st);
         free(sinks[i].hist);
+        free(sinks[i].rhist);
     }
     free(sinks);
     if (st_out) *st_out = st;
@@ -781,13 +797,13 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
 
 int or_trace(const or_acq *a, const or_scene *s, int n_threads, double *ch_raw, or_stats *st)
 {
-    return trace_impl(a, s, n_threads, 1, ch_raw, st);
+    return trace_impl(a, s, n_threads, 1, ch_raw, NULL, st);
 }
 
 int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, double *ch_raw,
-                    or_stats *st)
+                    double *rec_hist, or_stats *st)
 {
-    return trace_impl(a, s, n_threads, ray_stride, ch_raw, st);
+    return trace_impl(a, s, n_threads, ray_stride, ch_raw, rec_hist, st);
 }
 
 /* Explicit rays (origin, direction, weight, time, ids) traced one by one;
@@ -805,7 +821,7 @@ int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_
     if (ch_raw) memset(ch_raw, 0, sizeof(double) * (size_t)(a->n_tx * a->n_elements * a->n_samples));
     for (int64_t i = 0; i < n; ++i) {
         const or_ray *r = &rays[i];
-        trace_path(&C, &K, r->tx, r->elem, (uint32_t)r->ray, r->o, r->d, r->w, r->t, r->medium);
+        trace_path(&C, &K, r->tx, r->elem, (uint32_t)r->ray, r->o, r->d, r->w, r->t, r->medium, -1);
     }
     if (n_ev) *n_ev = K.n;
     if (st_out) *st_out = K.st;

@@ -69,8 +69,10 @@ typedef struct {
 int or_trace(const or_acq *a, const or_scene *s, int n_threads, double *ch_raw, or_stats *st);
 int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n,
                   or_event *ev, int64_t cap, int64_t *n_ev, double *ch_raw, or_stats *st);
+/* rec_hist (nullable) [n_tx][n_elements][1024] receives the summed |c| of
+ * binned contributions by emitting element and emission direction cell. */
 int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride,
-                    double *ch_raw, or_stats *st);
+                    double *ch_raw, double *rec_hist, or_stats *st);
 
 int or_pulse_taps(const or_acq *a, double *taps, int64_t cap);   /* returns K, taps [2K+1][2] */
 int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf);

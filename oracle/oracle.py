@@ -84,7 +84,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         L.or_trace.argtypes = [P(Acq), P(SceneS), C.c_int, P(C.c_double), P(Stats)]
-        L.or_trace_subset.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64, P(C.c_double), P(Stats)]
+        L.or_trace_subset.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64, P(C.c_double), P(C.c_double),
+                                      P(Stats)]
         L.or_trace_rays.argtypes = [P(Acq), P(SceneS), P(Ray), C.c_int64, P(Event), C.c_int64,
                                     P(C.c_int64), P(C.c_double), P(Stats)]
         L.or_pulse_taps.argtypes = [P(Acq), P(C.c_double), C.c_int64]
@@ -172,17 +173,22 @@ def make_scene(sc, keep):
                   pln=_dp(pln), pln_mat=_ip(keep.i32(sc.pln_mat)), scat=_dp(scat))
 
 
-def trace(workload, n_threads: int = 0, ray_stride: int = 1, seed=None, pdf=None, cdf=None):
-    """Channel data ch_raw[tx][e][n] (float64) and trace statistics."""
+def trace(workload, n_threads: int = 0, ray_stride: int = 1, seed=None, pdf=None, cdf=None, rec_hist=False):
+    """Channel data ch_raw[tx][e][n] (float64) and trace statistics; with
+    rec_hist also the |c| histogram [tx][e_emit][1024] of the contributions."""
     keep = _Keep()
     acq = workload.acq
     a = make_acq(acq, workload.seed if seed is None else seed, keep, pdf, cdf)
     s = make_scene(workload.scene, keep)
     out = np.zeros((acq.n_tx, acq.n_elements, acq.n_samples), np.float64)
+    rh = np.zeros((acq.n_tx, acq.n_elements, 1024), np.float64) if rec_hist else None
     st = Stats()
-    rc = lib().or_trace_subset(C.byref(a), C.byref(s), int(n_threads), int(ray_stride), _dp(out), C.byref(st))
+    rc = lib().or_trace_subset(C.byref(a), C.byref(s), int(n_threads), int(ray_stride), _dp(out),
+                               _dp(rh) if rec_hist else None, C.byref(st))
     if rc != 0:
         raise RuntimeError(f"or_trace failed ({rc})")
+    if rec_hist:
+        return out, st.as_dict(), rh
     return out, st.as_dict()
 
 

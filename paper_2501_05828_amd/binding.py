@@ -94,6 +94,15 @@ SIGNATURES = [
     ("ur_trace_rays", C.c_int, [_CTX, C.c_uint64, P(Ray), C.c_int64, P(Event), C.c_int64, P(C.c_int64),
                                 C.c_void_p, C.c_void_p]),
     ("ur_philox", C.c_int, [_CTX, P(C.c_uint32), C.c_int64, C.c_uint32, C.c_uint32, P(C.c_uint32)]),
+    ("ur_mlp_init", C.c_int, [_CTX, P(C.c_float), P(C.c_float)]),
+    ("ur_mlp_get_params", C.c_int, [_CTX, P(C.c_float)]),
+    ("ur_mlp_forward", C.c_int, [_CTX, C.c_void_p, C.c_void_p]),
+    ("ur_mlp_loss_grad", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ur_mlp_train_step", C.c_int, [_CTX, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p]),
+    ("ur_mlp_proposal_tables", C.c_int, [_CTX, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ur_set_record", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_void_p]),
+    ("ur_record_histogram", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.c_uint32, C.c_void_p,
+                                      C.c_void_p]),
 ]
 
 _lib = None
@@ -258,3 +267,42 @@ class Context:
                                 int(key1) & 0xFFFFFFFF, out.ctypes.data_as(P(C.c_uint32)))
         self.check(rc, "ur_philox")
         return out
+
+    # ---------------------------------------------------------- proposal network
+    def ur_mlp_init(self, params, rff):
+        p = np.ascontiguousarray(np.asarray(params, np.float32).ravel())
+        b = np.ascontiguousarray(np.asarray(rff, np.float32).ravel())
+        if p.size != 77120 or b.size != 32:
+            raise ValueError("need 77120 parameters and a 16x2 Fourier matrix")
+        self.check(self.lib.ur_mlp_init(self.h, p.ctypes.data_as(P(C.c_float)), b.ctypes.data_as(P(C.c_float))),
+                   "ur_mlp_init")
+
+    def ur_mlp_get_params(self):
+        out = np.zeros(77120, np.float32)
+        self.check(self.lib.ur_mlp_get_params(self.h, out.ctypes.data_as(P(C.c_float))), "ur_mlp_get_params")
+        return out
+
+    def ur_mlp_forward(self, q, stream=None):
+        self.check(self.lib.ur_mlp_forward(self.h, _ptr(q), _stream_ptr(stream)), "ur_mlp_forward")
+
+    def ur_mlp_loss_grad(self, hist, grad, loss=None, stream=None):
+        self.check(self.lib.ur_mlp_loss_grad(self.h, _ptr(hist), _ptr(grad), _ptr(loss), _stream_ptr(stream)),
+                   "ur_mlp_loss_grad")
+
+    def ur_mlp_train_step(self, hist, lr, loss=None, stream=None):
+        self.check(self.lib.ur_mlp_train_step(self.h, _ptr(hist), float(lr), _ptr(loss), _stream_ptr(stream)),
+                   "ur_mlp_train_step")
+
+    def ur_mlp_proposal_tables(self, eps, pdf, cdf, stream=None):
+        self.check(self.lib.ur_mlp_proposal_tables(self.h, float(eps), _ptr(pdf), _ptr(cdf), _stream_ptr(stream)),
+                   "ur_mlp_proposal_tables")
+
+    def ur_set_record(self, rec=None, count=None):
+        cap = rec.numel() // 2 if rec is not None else 0
+        self.check(self.lib.ur_set_record(self.h, _ptr(rec), int(cap), _ptr(count)), "ur_set_record")
+
+    def ur_record_histogram(self, rec, n_rec, batch, seed, step, hist, stream=None):
+        self.check(self.lib.ur_record_histogram(self.h, _ptr(rec), int(n_rec), int(batch),
+                                                C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(step) & 0xFFFFFFFF,
+                                                _ptr(hist), _stream_ptr(stream)), "ur_record_histogram")
+

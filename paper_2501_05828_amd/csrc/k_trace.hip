@@ -19,6 +19,7 @@
 // loop iteration and, when the ray ends, fetches the next ray of the
 // acquisition from a global counter (one atomic per wavefront), so lanes do
 // not idle behind long paths (rays trapped by total internal reflection).
+#include "philox.h"
 #include "ur_internal.h"
 #include "ultraray.h"
 
@@ -40,33 +41,10 @@ enum {
             ++cnt.v[k];         \
     } while (0)
 
-// ------------------------------------------------------------------ Philox
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with the key bumped by the Weyl constants.
-__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
-                                       uint32_t out[4]) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
-}
-
 // counter = (ray, element | tx << 16, segment | purpose << 16, k)
 __device__ __forceinline__ void draw(const TraceParams &P, uint32_t ray, int e, int tx, int seg, uint32_t purpose,
                                      uint32_t k, uint32_t out[4]) {
-    philox(ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k, P.key0, P.key1, out);
+    philox4x32_10(ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k, P.key0, P.key1, out);
 }
 
 __device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
@@ -268,13 +246,19 @@ __device__ __forceinline__ void log_event(const EventLog &L, int kind, int tx, i
 // Bins one arriving contribution into ch_raw with device-scope float atomics.
 template <bool COUNT, bool LOG>
 __device__ __forceinline__ void record(const TraceParams &P, const EventLog &L, Counters &cnt, int kind, int tx,
-                                       int e, int seg, int64_t id, double t, double v, const double *p) {
+                                       int e, int seg, int64_t id, double t, double v, const double *p, int e_emit,
+                                       int cell) {
     log_event<LOG>(L, kind, tx, e, seg, id, t, v, p);
     if (!(t < P.t_max) || t < 0.0) {
         CNT(C_DROPPED);
         return;
     }
     CNT(C_RECORDS);
+    if (P.rec && cell >= 0) {
+        const unsigned long long slot = atomicAdd(P.rec_count, 1ull);
+        if ((int64_t)slot < P.rec_cap)
+            P.rec[slot] = RecordEntry{(uint32_t)(((int64_t)tx * P.E + e_emit) * kCells + cell), (float)fabs(v)};
+    }
     const double x = t * P.fs;
     if constexpr (COUNT) {
         const double fr = x - floor(x);
@@ -465,7 +449,7 @@ __device__ __forceinline__ bool shadow(const TraceParams &P, const double *q, co
 template <bool COUNT>
 __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cnt, int tx, int e, uint32_t ray,
                                               int seg, int k, double amp, const double *o, const double *d,
-                                              double w, double t, int med, double s, NeeEntry &c) {
+                                              double w, double t, int med, double s, int cell, NeeEntry &c) {
     const Material M = P.mat[med];
     c.q[0] = o[0] + s * d[0];
     c.q[1] = o[1] + s * d[1];
@@ -493,7 +477,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     c.k = k;
     c.e = e;
     c.ray = ray;
-    c.pad = 0;
+    c.cell = cell;
     return true;
 }
 
@@ -520,7 +504,7 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
     const double att = exp(-(M.ka * dist + sum_a));
     const double tc = c.tq + dist * M.inv_c + sum_c;
     const double val = c.wq * (double)P.E * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
-    record<COUNT, LOG>(P, L, cnt, 1, c.tx, c.er, c.seg, c.k, tc, val, c.q);
+    record<COUNT, LOG>(P, L, cnt, 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
 }
 
 // Captures on the segment [0, t_seg) from the scatterer grid.  Candidates are
@@ -529,12 +513,12 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
 template <bool COUNT, bool LOG, int MODE>
 __device__ __forceinline__ void scatter_events(const TraceParams &P, const EventLog &L, Counters &cnt, int tx, int e,
                                                uint32_t ray, int seg, const double *o, const double *d, double w,
-                                               double t, int med, double t_seg) {
+                                               double t, int med, double t_seg, int cell) {
     if (P.n_scat == 0) return;
-    dda_walk(P.grid, o, d, t_seg, [&](int cell, double ta, double tb) {
+    dda_walk(P.grid, o, d, t_seg, [&](int gcell, double ta, double tb) {
         CNT(C_SCAT_CELLS);
-        const int j1 = P.cell_start[cell + 1];
-        for (int j = P.cell_start[cell]; j < j1; ++j) {
+        const int j1 = P.cell_start[gcell + 1];
+        for (int j = P.cell_start[gcell]; j < j1; ++j) {
             CNT(C_SCAT_TESTS);
             const double4 sk = P.items[j];
             const double p[3] = {sk.x - o[0], sk.y - o[1], sk.z - o[2]};
@@ -543,7 +527,7 @@ __device__ __forceinline__ void scatter_events(const TraceParams &P, const Event
             const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
             if (dot3(pp, pp) > P.r_s2) continue;
             NeeEntry c;
-            if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, o, d, w, t, med, s, c)) continue;
+            if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, o, d, w, t, med, s, cell, c)) continue;
             if constexpr (LOG || MODE == kInlineNeeOnly) {
                 nee_cast<COUNT, LOG>(P, L, cnt, c);
             } else {
@@ -561,6 +545,7 @@ struct RayState {
     int64_t last;      // flat primitive just left (excluded from the next hit), -1 if none
     int med, seg, tx, e;
     uint32_t ray;
+    int cell;          // emission direction cell (32 x 32 grid), -1 for explicit rays
 };
 
 // Advances a primary ray by one segment (Sec. 2.3 "Ray Traversal"): closest
@@ -583,7 +568,7 @@ __device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, 
         t_seg = P.max_path - R.len;
         clipped = true;
     }
-    scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg);
+    scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg, R.cell);
     const Material M = P.mat[R.med];
     R.w *= exp(-M.ka * t_seg);
     R.t += t_seg * M.inv_c;
@@ -609,7 +594,7 @@ __device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, 
             const double fdir = directivity(acos(ca), P.alpha_m, P.alpha_c);
             if (MODE != kInlineNeeOnly && fdir > 0.0) {
                 CNT(C_DIRECT);
-                record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t, R.w * fdir, o);
+                record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t, R.w * fdir, o, R.e, R.cell);
             }
         }
         CNT(C_TERM_BOX);
@@ -701,7 +686,7 @@ __device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, 
 // the uniform or tabulated proposal on the equal-area map, weight
 // cos(theta) / (rays per transmit * pdf).
 __device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32_t ray, double *o, double *d,
-                                     double &w) {
+                                     double &w, int &cell_out) {
     uint32_t x[4];
     draw(P, ray, e, tx, 0, 0, 0, x);
     const double u0 = u01(x[0]), u1 = u01(x[1]), u2 = u01(x[2]), u3 = u01(x[3]);
@@ -713,6 +698,7 @@ __device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32
         ca = u2;
         cb = u3;
         pdf = 1.0 / (2.0 * M_PI);
+        cell_out = (int)((x[3] >> 27) * 32u + (x[2] >> 27));   // floor(32 u3) * 32 + floor(32 u2)
     } else {
         uint32_t y[4];
         draw(P, ray, e, tx, 0, 3, 0, y);
@@ -726,6 +712,7 @@ __device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32
             else lo = mid + 1;
         }
         const int cell = lo < kCells ? lo : kCells - 1;
+        cell_out = cell;
         ca = ((double)(cell % 32) + u2) / 32.0;
         cb = ((double)(cell / 32) + u3) / 32.0;
         pdf = (double)P.pdf[row + cell] * (double)kCells / (2.0 * M_PI);
@@ -788,7 +775,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
                         R.e = (int)(q % P.E);
                         R.tx = (int)(q / P.E);
-                        emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w);
+                        emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;
                         R.last = -1;
@@ -845,6 +832,7 @@ __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *
         R.tx = (int)r.tx;
         R.e = (int)r.elem;
         R.ray = (uint32_t)r.ray;
+        R.cell = -1;
         ++cnt.v[C_RAYS];
         while (advance<true, true, kDeferNee>(P, L, cnt, R)) {
         }
@@ -856,7 +844,7 @@ __global__ void k_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t r[4];
-    philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1, r);
+    philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1, r);
     for (int j = 0; j < 4; ++j) out[4 * i + j] = r[j];
 }
 

@@ -55,6 +55,14 @@ struct ur_context {
     DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
         d_nee, d_counters;
     int64_t rays_per_launch = int64_t(1) << 30;
+    // proposal network (rows = transmits x elements of the current setup)
+    bool mlp_ready = false;
+    int mlp_rows = 0, mlp_step = 0;
+    DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
+    // contribution recording
+    RecordEntry *rec = nullptr;
+    unsigned long long *rec_count = nullptr;
+    int64_t rec_cap = 0;
     std::vector<hipEvent_t> tev;           // [2 * launches] around each trace-kernel launch
     int n_tev = 0;
     int64_t nee_cap = int64_t(1) << 22;
@@ -254,7 +262,9 @@ UR_API void ur_context_destroy(ur_context *c) {
     for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
                       &c->d_tri_id, &c->d_tnodes, &c->d_cell_start, &c->d_items, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
                       &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
-                      &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters})
+                      &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
+                      &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
+                      &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -437,6 +447,11 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         if ((st = alloc(c, c->d_stats2, kNumStats * sizeof(unsigned long long)))) return st;
         if ((st = alloc(c, c->d_counters, 8 * sizeof(unsigned long long)))) return st;
         if ((st = alloc(c, c->d_maxbits, 256))) return st;
+        if ((st = upload(c, c->d_angles, c->angles))) return st;
+        if (c->mlp_ready && T * E != c->mlp_rows) {
+            c->mlp_ready = false;   // the network's rows follow the acquisition
+            c->pdf = c->cdf = nullptr;
+        }
         c->has_setup = true;
         if ((st = upload_materials(c))) return st;
         // scatterers: uniform grid; each registered in the cells its capture
@@ -492,6 +507,9 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         P.nee = (NeeEntry *)c->d_nee.p;
         P.nee_cap = c->nee_cap;
         P.nee_count = ctr + 2;
+        P.rec = c->rec;
+        P.rec_count = c->rec_count;
+        P.rec_cap = c->rec_cap;
         unsigned long long *st1 = stats ? (unsigned long long *)c->d_stats.p : nullptr;
         unsigned long long *st2 = stats ? (unsigned long long *)c->d_stats2.p : nullptr;
         if (stats) {
@@ -714,6 +732,181 @@ UR_API ur_status ur_philox(ur_context *c, const uint32_t *ctr, int64_t n, uint32
         HIP_TRY(c, ur_launch_philox(dc, dout, n, key0, key1, nullptr));
         HIP_TRY(c, hipDeviceSynchronize());
         HIP_TRY(c, hipMemcpy(out, dout, 4 * n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        return UR_OK;
+    });
+}
+
+
+// ------------------------------------------------------------ proposal network
+namespace {
+constexpr int kIn = 34, kHid = 64, kOut = 1024, kParams = 77120;
+constexpr int oW1 = 0, ob1 = oW1 + kIn * kHid, oW2 = ob1 + kHid, ob2 = oW2 + kHid * kHid, oW3 = ob2 + kHid,
+              ob3 = oW3 + kHid * kHid, oW4 = ob3 + kHid, ob4 = oW4 + kHid * kOut;
+static_assert(ob4 + kOut == kParams, "parameter layout");
+
+ur_status mlp_forward(ur_context *c, hipStream_t s) {
+    const int R = c->mlp_rows;
+    const float *th = (const float *)c->d_theta.p;
+    double amax = 0.0;
+    for (double a : c->angles) amax = std::max(amax, std::fabs(a));
+    if (amax == 0.0) amax = 1.0;
+    HIP_TRY(c, ur_mlp_features((const double *)c->d_xe.p, (const double *)c->d_angles.p, (int)c->probe.n_elements,
+                               (int)c->acq.n_tx, 0.5 * (double)c->probe.n_elements * c->probe.pitch, amax,
+                               (const float *)c->d_rff.p, (float *)c->d_X.p, s));
+    float *X = (float *)c->d_X.p, *H1 = (float *)c->d_H1.p, *H2 = (float *)c->d_H2.p, *H3 = (float *)c->d_H3.p;
+    HIP_TRY(c, ur_mlp_gemm(X, kIn, 1, th + oW1, kHid, 1, H1, R, kHid, kIn, th + ob1, nullptr, 1, s));
+    HIP_TRY(c, ur_mlp_gemm(H1, kHid, 1, th + oW2, kHid, 1, H2, R, kHid, kHid, th + ob2, nullptr, 1, s));
+    HIP_TRY(c, ur_mlp_gemm(H2, kHid, 1, th + oW3, kHid, 1, H3, R, kHid, kHid, th + ob3, nullptr, 1, s));
+    HIP_TRY(c, ur_mlp_gemm(H3, kHid, 1, th + oW4, kOut, 1, (float *)c->d_Z.p, R, kOut, kHid, th + ob4, nullptr, 0, s));
+    return UR_OK;
+}
+
+// Loss and gradient of the weighted cross-entropy into grad (device).
+ur_status mlp_backward(ur_context *c, const float *hist, float *grad, float *loss, hipStream_t s) {
+    const int R = c->mlp_rows;
+    const float *th = (const float *)c->d_theta.p;
+    float *X = (float *)c->d_X.p, *H1 = (float *)c->d_H1.p, *H2 = (float *)c->d_H2.p, *H3 = (float *)c->d_H3.p;
+    float *dZ = (float *)c->d_dZ.p, *d3 = (float *)c->d_dH3.p, *d2 = (float *)c->d_dH2.p, *d1 = (float *)c->d_dH1.p;
+    float *tot = (float *)c->d_scal.p;
+    ur_status st;
+    if ((st = mlp_forward(c, s))) return st;
+    HIP_TRY(c, ur_mlp_sum(hist, (int64_t)R * kOut, tot, s));
+    if (loss) HIP_TRY(c, ur_mlp_fill(loss, 1, 0.f, s));
+    HIP_TRY(c, ur_mlp_softmax_ce((const float *)c->d_Z.p, hist, tot, nullptr, dZ, loss, R, s));
+    HIP_TRY(c, ur_mlp_gemm(H3, 1, kHid, dZ, kOut, 1, grad + oW4, kHid, kOut, R, nullptr, nullptr, 0, s));
+    HIP_TRY(c, ur_mlp_colsum(dZ, R, kOut, grad + ob4, s));
+    HIP_TRY(c, ur_mlp_gemm(dZ, kOut, 1, th + oW4, 1, kOut, d3, R, kHid, kOut, nullptr, H3, 0, s));
+    HIP_TRY(c, ur_mlp_gemm(H2, 1, kHid, d3, kHid, 1, grad + oW3, kHid, kHid, R, nullptr, nullptr, 0, s));
+    HIP_TRY(c, ur_mlp_colsum(d3, R, kHid, grad + ob3, s));
+    HIP_TRY(c, ur_mlp_gemm(d3, kHid, 1, th + oW3, 1, kHid, d2, R, kHid, kHid, nullptr, H2, 0, s));
+    HIP_TRY(c, ur_mlp_gemm(H1, 1, kHid, d2, kHid, 1, grad + oW2, kHid, kHid, R, nullptr, nullptr, 0, s));
+    HIP_TRY(c, ur_mlp_colsum(d2, R, kHid, grad + ob2, s));
+    HIP_TRY(c, ur_mlp_gemm(d2, kHid, 1, th + oW2, 1, kHid, d1, R, kHid, kHid, nullptr, H1, 0, s));
+    HIP_TRY(c, ur_mlp_gemm(X, 1, kIn, d1, kHid, 1, grad + oW1, kIn, kHid, R, nullptr, nullptr, 0, s));
+    HIP_TRY(c, ur_mlp_colsum(d1, R, kHid, grad + ob1, s));
+    return UR_OK;
+}
+
+ur_status mlp_check(ur_context *c) {
+    if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+    if (!c->mlp_ready) return c->fail(UR_ERR_CALL_ORDER, "call ur_mlp_init after the transmit setup");
+    return UR_OK;
+}
+}  // namespace
+
+UR_API ur_status ur_mlp_init(ur_context *c, const float *params, const float *rff) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!params || !rff) return c->fail(UR_ERR_INVALID_ARG, "params and rff are required");
+        for (int i = 0; i < kParams; ++i)
+            if (!std::isfinite(params[i])) return c->fail(UR_ERR_INVALID_ARG, "non-finite parameter %d", i);
+        const int64_t R = c->acq.n_tx * c->probe.n_elements;
+        if (R > (1 << 20)) return c->fail(UR_ERR_UNSUPPORTED, "at most 2^20 (transmit, element) rows");
+        c->mlp_rows = (int)R;
+        ur_status st;
+        const size_t P = kParams * sizeof(float);
+        if ((st = alloc(c, c->d_theta, P)) || (st = alloc(c, c->d_m, P)) || (st = alloc(c, c->d_v, P)) ||
+            (st = alloc(c, c->d_grad, P)) || (st = alloc(c, c->d_rff, 32 * sizeof(float))) ||
+            (st = alloc(c, c->d_X, R * kIn * sizeof(float))) || (st = alloc(c, c->d_H1, R * kHid * sizeof(float))) ||
+            (st = alloc(c, c->d_H2, R * kHid * sizeof(float))) || (st = alloc(c, c->d_H3, R * kHid * sizeof(float))) ||
+            (st = alloc(c, c->d_Z, R * kOut * sizeof(float))) || (st = alloc(c, c->d_dZ, R * kOut * sizeof(float))) ||
+            (st = alloc(c, c->d_dH3, R * kHid * sizeof(float))) || (st = alloc(c, c->d_dH2, R * kHid * sizeof(float))) ||
+            (st = alloc(c, c->d_dH1, R * kHid * sizeof(float))) || (st = alloc(c, c->d_scal, 64)))
+            return st;
+        HIP_TRY(c, hipMemcpy(c->d_theta.p, params, P, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_rff.p, rff, 32 * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemset(c->d_m.p, 0, P));
+        HIP_TRY(c, hipMemset(c->d_v.p, 0, P));
+        HIP_TRY(c, hipDeviceSynchronize());
+        c->mlp_step = 0;
+        c->mlp_ready = true;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_mlp_get_params(ur_context *c, float *params) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!params) return c->fail(UR_ERR_INVALID_ARG, "params is NULL");
+        HIP_TRY(c, hipDeviceSynchronize());
+        HIP_TRY(c, hipMemcpy(params, c->d_theta.p, kParams * sizeof(float), hipMemcpyDeviceToHost));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_mlp_forward(ur_context *c, float *q_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!q_dev) return c->fail(UR_ERR_INVALID_ARG, "q_dev is NULL");
+        hipStream_t s = (hipStream_t)stream;
+        if ((st = mlp_forward(c, s))) return st;
+        HIP_TRY(c, ur_mlp_softmax_ce((const float *)c->d_Z.p, nullptr, nullptr, q_dev, nullptr, nullptr, c->mlp_rows, s));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_mlp_loss_grad(ur_context *c, const float *hist_dev, float *grad_dev, float *loss_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!hist_dev || !grad_dev) return c->fail(UR_ERR_INVALID_ARG, "hist_dev and grad_dev are required");
+        return mlp_backward(c, hist_dev, grad_dev, loss_dev, (hipStream_t)stream);
+    });
+}
+
+UR_API ur_status ur_mlp_train_step(ur_context *c, const float *hist_dev, float lr, float *loss_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!hist_dev) return c->fail(UR_ERR_INVALID_ARG, "hist_dev is NULL");
+        if (!(lr > 0.f) || !std::isfinite(lr)) return c->fail(UR_ERR_INVALID_ARG, "learning rate must be positive");
+        hipStream_t s = (hipStream_t)stream;
+        if ((st = mlp_backward(c, hist_dev, (float *)c->d_grad.p, loss_dev, s))) return st;
+        ++c->mlp_step;
+        const double b1 = 0.9, b2 = 0.999;
+        HIP_TRY(c, ur_mlp_adam((float *)c->d_theta.p, (float *)c->d_m.p, (float *)c->d_v.p, (const float *)c->d_grad.p,
+                               kParams, lr, (float)b1, (float)b2, 1e-8f, (float)(1.0 - std::pow(b1, c->mlp_step)),
+                               (float)(1.0 - std::pow(b2, c->mlp_step)), s));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_mlp_proposal_tables(ur_context *c, float eps, float *pdf_dev, float *cdf_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!pdf_dev || !cdf_dev) return c->fail(UR_ERR_INVALID_ARG, "pdf_dev and cdf_dev are required");
+        if (!(eps > 0.f && eps <= 1.f)) return c->fail(UR_ERR_INVALID_ARG, "uniform mixture weight must be in (0, 1]");
+        hipStream_t s = (hipStream_t)stream;
+        if ((st = mlp_forward(c, s))) return st;
+        HIP_TRY(c, ur_mlp_softmax_ce((const float *)c->d_Z.p, nullptr, nullptr, (float *)c->d_dZ.p, nullptr, nullptr,
+                                     c->mlp_rows, s));
+        HIP_TRY(c, ur_mlp_tables((const float *)c->d_dZ.p, c->mlp_rows, eps, pdf_dev, cdf_dev, s));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_set_record(ur_context *c, void *rec_dev, int64_t cap, unsigned long long *count_dev) {
+    return guarded(c, [&]() -> ur_status {
+        if (rec_dev && (cap < 1 || !count_dev)) return c->fail(UR_ERR_INVALID_ARG, "need cap >= 1 and a count pointer");
+        c->rec = (RecordEntry *)rec_dev;
+        c->rec_cap = rec_dev ? cap : 0;
+        c->rec_count = rec_dev ? count_dev : nullptr;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_record_histogram(ur_context *c, const void *rec_dev, int64_t n_rec, int64_t batch, uint64_t seed,
+                                     uint32_t step, float *hist_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!hist_dev || (n_rec > 0 && !rec_dev) || n_rec < 0 || batch < 0)
+            return c->fail(UR_ERR_INVALID_ARG, "bad record or histogram buffer");
+        const int64_t bins = c->acq.n_tx * c->probe.n_elements * kOut;
+        HIP_TRY(c, ur_mlp_record_hist((const RecordEntry *)rec_dev, n_rec, batch, seed, step, bins, hist_dev,
+                                      (hipStream_t)stream));
         return UR_OK;
     });
 }

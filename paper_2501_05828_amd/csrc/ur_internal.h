@@ -29,8 +29,16 @@ struct NeeEntry {
     double wq;         // primary weight at q times the scatterer amplitude
     double tq;         // arrival time at q
     int tx, er, med, seg;
-    int k, e;          // scatterer (original index) and emitting element, for logs
-    uint32_t ray, pad;
+    int k, e;          // scatterer (original index) and emitting element
+    uint32_t ray;
+    int cell;          // emission direction cell of the primary ray
+};
+
+// Recorded contribution for training the emission proposal:
+// bin = (tx * E + emitting element) * 1024 + emission cell, value = |c|.
+struct RecordEntry {
+    uint32_t bin;
+    float value;
 };
 
 // Trace-kernel modes.
@@ -82,6 +90,9 @@ struct TraceParams {
     NeeEntry *nee;                    // transducer-sampling queue
     unsigned long long *nee_count;    // entries written (may exceed capacity)
     int64_t nee_cap;
+    RecordEntry *rec;                 // contribution records, or null
+    unsigned long long *rec_count;    // records offered (may exceed capacity)
+    int64_t rec_cap;
 };
 
 // Explicit-ray logging (test path).
@@ -114,5 +125,19 @@ hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int
 hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s);
 hipError_t ur_launch_bmode(const float *env, float *bmode, int64_t n, float dr_db, unsigned int *max_bits,
                            hipStream_t s);
+hipError_t ur_mlp_gemm(const float *A, int64_t sar, int64_t sac, const float *B, int64_t sbr, int64_t sbc, float *C,
+                       int M, int N, int K, const float *bias, const float *mask, int relu, hipStream_t s);
+hipError_t ur_mlp_features(const double *xe, const double *angles, int E, int T, double half_ap, double amax,
+                           const float *rff, float *X, hipStream_t s);
+hipError_t ur_mlp_softmax_ce(const float *Z, const float *H, const float *tot, float *Q, float *dZ, float *loss,
+                             int R, hipStream_t s);
+hipError_t ur_mlp_colsum(const float *X, int R, int N, float *out, hipStream_t s);
+hipError_t ur_mlp_sum(const float *x, int64_t n, float *out, hipStream_t s);
+hipError_t ur_mlp_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t ur_mlp_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s);
+hipError_t ur_mlp_tables(const float *Q, int R, float eps, float *pdf, float *cdf, hipStream_t s);
+hipError_t ur_mlp_record_hist(const ur::RecordEntry *rec, int64_t n_rec, int64_t batch, uint64_t seed, uint32_t step,
+                              int64_t n_bins, float *hist, hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);

@@ -1,0 +1,66 @@
+"""Learned emission proposal driven through the C ABI.
+
+record(): trace with uniform emission while the library appends every binned
+contribution (row, emission cell, |c|).  train(): Adam steps on minibatch
+histograms drawn from those records.  enable(): the network's direction
+distribution, mixed with eps of uniform, becomes the emission pdf of later
+traces (weights 1/pdf keep the estimator unbiased).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import scenes
+
+
+class Proposal:
+    def __init__(self, sim, seed: int = 7):
+        self.sim = sim
+        self.ctx = sim.ctx
+        params, rff = scenes.proposal_init(seed)
+        self.ctx.ur_mlp_init(params, rff)
+        a = sim.w.acq
+        self.rows = a.n_tx * a.n_elements
+        dev = sim.dev
+        self.hist = torch.zeros((self.rows, 1024), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.pdf = torch.empty((self.rows, 1024), dtype=torch.float32, device=dev)
+        self.cdf = torch.empty((self.rows, 1024), dtype=torch.float32, device=dev)
+        self.rec = None
+        self.n_rec = 0
+
+    def record(self, n_traces: int, cap: int = 1 << 22, seed0: int = 0x1234_0000):
+        """Records contributions of n_traces uniform traces of the current
+        acquisition; returns (records kept, records offered)."""
+        dev = self.sim.dev
+        self.rec = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ctx.ur_set_proposal(None, None)
+        self.ctx.ur_set_record(self.rec, count)
+        try:
+            for i in range(n_traces):
+                self.sim.trace(seed=seed0 + i, pulse=False)
+        finally:
+            self.ctx.ur_set_record(None)
+        offered = int(count.item())
+        self.n_rec = min(offered, cap)
+        return self.n_rec, offered
+
+    def train(self, steps: int = 2000, batch: int = 1 << 16, lr: float = 1e-3, seed: int = 11,
+              log_every: int = 0):
+        if self.n_rec == 0:
+            raise RuntimeError("no recorded contributions to train on")
+        losses = []
+        for step in range(steps):
+            self.ctx.ur_record_histogram(self.rec, self.n_rec, batch, seed, step, self.hist)
+            self.ctx.ur_mlp_train_step(self.hist, lr, self.loss)
+            if log_every and (step % log_every == 0 or step == steps - 1):
+                losses.append((step, float(self.loss.item())))
+        return losses
+
+    def enable(self, eps: float = 0.1):
+        self.ctx.ur_mlp_proposal_tables(eps, self.pdf, self.cdf)
+        self.ctx.ur_set_proposal(self.pdf, self.cdf)
+
+    def disable(self):
+        self.ctx.ur_set_proposal(None, None)

@@ -276,6 +276,19 @@ def large(scene_seed: int = 1, rays_per_element: int = 124008, n_phi: int = 1000
     return w
 
 
+def proposal_init(seed: int = 7):
+    """Seeded initial parameters of the 34-64-64-64-1024 proposal network:
+    He-normal weights, zero biases, laid out W1, b1, W2, b2, W3, b3, W4, b4
+    with W stored (inputs, outputs).  Also the 16x2 random Fourier matrix
+    (standard normal).  Inputs shared by the library and the reference."""
+    rng = np.random.default_rng(seed)
+    shapes = [(34, 64), (64,), (64, 64), (64,), (64, 64), (64,), (64, 1024), (1024,)]
+    parts = [rng.normal(0.0, np.sqrt(2.0 / sh[0]), size=sh).ravel() if len(sh) == 2 else np.zeros(sh)
+             for sh in shapes]
+    rff = rng.normal(size=(16, 2))
+    return np.concatenate(parts).astype(np.float32), rff.astype(np.float32)
+
+
 CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "large": large}
 
 
