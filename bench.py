@@ -209,8 +209,8 @@ def main():
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (rays shard by transmit; "
-              "see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (rays would shard by transmit "
+              "and element rows, with one reduction of the channel data)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -147,10 +147,19 @@ UR_API const char *ur_last_error(const ur_context *ctx);
 UR_API const char *ur_version(void);
 
 /* Validates and uploads the scene (Sec. 4 scene: meshes with per-material
- * impedance; scatterers and attenuation per the spec additions),
+ * impedance; point scatterers and frequency-dependent attenuation extend the
+ * paper's surface-only model),
  * builds the triangle and scatterer bounding-volume hierarchies on the host
  * and copies them to the device.  Replaces any previous scene.  Synchronous. */
 UR_API ur_status ur_scene_upload(ur_context *ctx, const ur_scene_desc *scene);
+
+/* Replaces parameter values of the uploaded scene without rebuilding its
+ * acceleration structures (for optimisation loops): mat [n_mat][3] (Z,
+ * alpha, c as in ur_scene_desc), scat_amp [n_scat] (scatterer amplitudes),
+ * sph [n_sph][4] (centre, radius); each is a host array or NULL (kept).
+ * Scatterer positions, meshes, planes and material indices stay fixed.  On
+ * an invalid value nothing is changed.  Synchronous. */
+UR_API ur_status ur_scene_update(ur_context *ctx, const double *mat, const double *scat_amp, const double *sph);
 
 /* Transmit setup: element centres, plane-wave steering delays (Sec. 2.3 "Ray
  * Emission", Fig. 3), pulse taps (Eq. 14) and tracer limits.  Requires a
@@ -263,6 +272,66 @@ UR_API ur_status ur_set_record(ur_context *ctx, void *rec_dev, int64_t cap, unsi
  * `seed`, counter (draw, step)) add their |c| to their bins. */
 UR_API ur_status ur_record_histogram(ur_context *ctx, const void *rec_dev, int64_t n_rec, int64_t batch,
                                      uint64_t seed, uint32_t step, float *hist_dev, void *stream);
+
+/* ---------------------------------------------------------------- adjoint
+ * Gradients of a scalar loss L of the simulated data, for gradient-based
+ * inversion (the differentiability the method is built for, Sec. 1 and
+ * Sec. 3).  The signal chain is linear up to the envelope, and its adjoints
+ * are the transposed operators; the trace adjoint regenerates every path from
+ * its counters (path replay) and differentiates the contributions along it.
+ *
+ * Gradients are interior (frozen-decision) derivatives: the discontinuities
+ * of the estimator in geometry (a path starting or ceasing to capture a
+ * scatterer, to hit the aperture or a triangle) contribute no boundary term.
+ */
+
+/* Adjoint of ur_pulse: g_raw[k] = sum_m Re h[m] Re g_rf[k + m] + Im h[m] Im
+ * g_rf[k + m] for every channel (the transpose of the Eq. 14 convolution).
+ * g_rf_dev: complex float [n_tx][n_elements][n_samples] (interleaved re, im),
+ * g_raw_dev: float [n_tx][n_elements][n_samples], overwritten.  Async. */
+UR_API ur_status ur_pulse_adjoint(ur_context *ctx, const float *g_rf_dev, float *g_raw_dev, void *stream);
+
+/* Adjoint of ur_beamform (delay-and-sum and envelope).  Give exactly one of
+ * g_env_dev (float [nx][nz], dL/d envelope; needs iq_dev, the complex IQ
+ * image [nx][nz] of the forward call) and g_iq_dev (complex float [nx][nz],
+ * dL/d IQ).  g_rf_dev (complex float [n_tx][n_elements][n_samples]) is
+ * overwritten with dL/d ch_rf; the grid and apodisation must be those of the
+ * forward call.  Pixels with |IQ| = 0 pass no envelope gradient.  The
+ * transpose scatters with float atomics, so its summation order (and the
+ * last bits of g_rf) vary from call to call.  Async. */
+UR_API ur_status ur_beamform_adjoint(ur_context *ctx, const ur_grid_desc *grid, const float *iq_dev,
+                                     const float *g_env_dev, const float *g_iq_dev, float *g_rf_dev, void *stream);
+
+/* Gradient outputs of ur_trace_adjoint (device pointers; NULL = not wanted).
+ *   amp        float  [n_scat]      dL/d scatterer amplitude (scene order)
+ *   alpha      double [n_mat]       dL/d attenuation alpha [per dB/(cm MHz)]
+ *                                   (at most 8 materials)
+ *   Z          double [n_mat]       dL/d acoustic impedance [per MRayl]
+ *   sph_center double [n_sph][3]    dL/d sphere centre coordinates [per m]
+ * frozen_choice = 0: the reflect-or-transmit choice of Eqs. 7-11 keeps its
+ * probability attached to the weight (R / value(R), (1 - R) / value(1 - R)),
+ * which adds the derivative of the choice probability (the gradient of the
+ * expectation over the choice); 1: the choice counts as fixed, giving the
+ * derivative of the fixed-seed estimator between decision changes. */
+typedef struct ur_grad_desc {
+    float *amp;
+    double *alpha;
+    double *Z;
+    double *sph_center;
+    int32_t frozen_choice;
+} ur_grad_desc;
+
+/* Path-replay adjoint of ur_trace for the same (seed, ray_stride,
+ * ray_offset): with g_raw_dev = dL/d ch_raw (float [n_tx][n_elements]
+ * [n_samples]), accumulates into each requested output of `grads` (each is
+ * cleared first) the derivative of L through every binned contribution c at
+ * arrival time t: g(t) dc + c g'(t) dt, where g' (the slope of g between
+ * sample centres) is non-zero only with linear binning.  Amplitude and
+ * attenuation gradients come from one replay; every impedance and every
+ * sphere coordinate takes one forward-mode (dual number) replay.  The same
+ * proposal tables as the forward call must be set.  Async on `stream`. */
+UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
+                                  const float *g_raw_dev, const ur_grad_desc *grads, void *stream);
 
 /* Philox4x32-10 evaluated on the device for n counters (host arrays
  * ctr [n][4], out [n][4]) under key (key0, key1); for checking that the

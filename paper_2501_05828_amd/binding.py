@@ -73,6 +73,11 @@ class Ray(C.Structure):
                 ("tx", C.c_int64), ("elem", C.c_int64), ("ray", C.c_int64), ("medium", C.c_int64)]
 
 
+class GradDesc(C.Structure):
+    _fields_ = [("amp", C.c_void_p), ("alpha", C.c_void_p), ("Z", C.c_void_p), ("sph_center", C.c_void_p),
+                ("frozen_choice", C.c_int32)]
+
+
 EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end"}
 
 # (name, restype, argtypes) for every entry point declared in include/ultraray.h
@@ -103,6 +108,11 @@ SIGNATURES = [
     ("ur_set_record", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_void_p]),
     ("ur_record_histogram", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.c_uint32, C.c_void_p,
                                       C.c_void_p]),
+    ("ur_scene_update", C.c_int, [_CTX, P(C.c_double), P(C.c_double), P(C.c_double)]),
+    ("ur_pulse_adjoint", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ur_beamform_adjoint", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    ("ur_trace_adjoint", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, P(GradDesc), C.c_void_p]),
 ]
 
 _lib = None
@@ -197,6 +207,7 @@ class Context:
                       tri_mat=ip(i32(scene.tri_mat)), sph=dp(sph), sph_mat=ip(i32(scene.sph_mat)), pln=dp(pln),
                       pln_mat=ip(i32(scene.pln_mat)), scat=dp(scat))
         self.check(self.lib.ur_scene_upload(self.h, C.byref(d)), "ur_scene_upload")
+        self.scene_sizes = {"mat": 3 * len(mat), "scat_amp": len(scat), "sph": 4 * len(sph)}
 
     def ur_transmit_setup(self, acq):
         ang = np.ascontiguousarray(np.asarray(acq.angles, np.float64))
@@ -234,6 +245,41 @@ class Context:
         rc = self.lib.ur_beamform(self.h, C.byref(g), _ptr(ch_rf), _ptr(iq), _ptr(env), _ptr(bmode),
                                   _stream_ptr(stream))
         self.check(rc, "ur_beamform")
+
+    def ur_scene_update(self, mat=None, scat_amp=None, sph=None):
+        keep = []
+
+        sizes = getattr(self, "scene_sizes", None)
+        if sizes is None:
+            raise URError("ur_scene_update: upload a scene first")
+
+        def arr(a, name):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, np.float64).ravel()
+            if a.size != sizes[name]:
+                raise URError(f"ur_scene_update: {name} has {a.size} values, the scene needs {sizes[name]}")
+            keep.append(a)
+            return a.ctypes.data_as(P(C.c_double))
+        self.check(self.lib.ur_scene_update(self.h, arr(mat, "mat"), arr(scat_amp, "scat_amp"), arr(sph, "sph")), "ur_scene_update")
+
+    def ur_pulse_adjoint(self, g_rf, g_raw, stream=None):
+        self.check(self.lib.ur_pulse_adjoint(self.h, _ptr(g_rf), _ptr(g_raw), _stream_ptr(stream)), "ur_pulse_adjoint")
+
+    def ur_beamform_adjoint(self, grid, g_rf, iq=None, g_env=None, g_iq=None, apod=UR_APOD_HANN, stream=None):
+        g = GridDesc(nx=grid.nx, nz=grid.nz, apod=apod, x0=grid.x0, x1=grid.x1, z0=grid.z0, z1=grid.z1,
+                     dynamic_range_db=90.0)
+        rc = self.lib.ur_beamform_adjoint(self.h, C.byref(g), _ptr(iq), _ptr(g_env), _ptr(g_iq), _ptr(g_rf),
+                                          _stream_ptr(stream))
+        self.check(rc, "ur_beamform_adjoint")
+
+    def ur_trace_adjoint(self, seed, g_raw, amp=None, alpha=None, Z=None, sph_center=None, frozen_choice=False,
+                         ray_stride=1, ray_offset=0, stream=None):
+        d = GradDesc(amp=_ptr(amp), alpha=_ptr(alpha), Z=_ptr(Z), sph_center=_ptr(sph_center),
+                     frozen_choice=1 if frozen_choice else 0)
+        rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
+                                       int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
+        self.check(rc, "ur_trace_adjoint")
 
     def ur_last_kernel_ms(self):
         a, b = C.c_double(), C.c_double()

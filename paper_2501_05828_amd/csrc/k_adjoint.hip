@@ -1,0 +1,543 @@
+// Path-replay adjoint of the channel-data estimator on gfx950.
+//
+// Every path of a trace is regenerated from its Philox counters at the
+// current parameters theta0 and followed with the same decisions (closest
+// primitive, reflect-or-transmit, captures, receiving elements, crossings).
+// Along the path each quantity is carried as a dual number (value, tangent)
+// for one parameter direction; at every contribution c with arrival time t
+// the gradient of J = sum_records g(t) c receives g(t) dc + c g'(t) dt, where
+// g is the adjoint of the binned channel data (g' is non-zero only for the
+// linear binning filter).
+//
+// The reflect-or-transmit choice keeps its probability attached: the weight
+// is multiplied by R / value(R) after a reflection and (1 - R) / value(1 - R)
+// after a transmission, so that the tangent carries the derivative of the
+// choice probability and the gradient is that of the expectation for the
+// sampled decisions.  The value pass (no tangent) also accumulates the
+// gradients with respect to every scatterer amplitude (dc/da_k = c / a_k) and
+// every attenuation coefficient (d log c / d alpha_m = -kappa x path length in
+// material m).
+#include "trace_device.h"
+#include "ultraray.h"
+
+namespace {
+using namespace ur;
+using namespace ur::dev;
+
+constexpr int kAdjMat = kAdjMaxMat;
+
+struct D {
+    double v, t;
+};
+__device__ __forceinline__ D dd(double v) { return D{v, 0.0}; }
+__device__ __forceinline__ D operator+(D a, D b) { return D{a.v + b.v, a.t + b.t}; }
+__device__ __forceinline__ D operator-(D a, D b) { return D{a.v - b.v, a.t - b.t}; }
+__device__ __forceinline__ D operator-(D a) { return D{-a.v, -a.t}; }
+__device__ __forceinline__ D operator*(D a, D b) { return D{a.v * b.v, a.t * b.v + a.v * b.t}; }
+__device__ __forceinline__ D operator*(double s, D a) { return D{s * a.v, s * a.t}; }
+__device__ __forceinline__ D operator/(D a, D b) { return D{a.v / b.v, (a.t * b.v - a.v * b.t) / (b.v * b.v)}; }
+__device__ __forceinline__ D dsqrt(D a) {
+    const double r = sqrt(a.v);
+    return D{r, a.t / (2.0 * r)};
+}
+__device__ __forceinline__ D dexp(D a) {
+    const double e = exp(a.v);
+    return D{e, a.t * e};
+}
+__device__ __forceinline__ D dacos(D a) {
+    const double x = fmin(1.0, fmax(-1.0, a.v));
+    const double s = sqrt(fmax(1.0 - x * x, 1e-300));
+    return D{acos(x), -a.t / s};
+}
+__device__ __forceinline__ D ddot(const D *a, const D *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ __forceinline__ D ddot(const D *a, const double *b) {
+    return b[0] * a[0] + b[1] * a[1] + b[2] * a[2];
+}
+
+// Parameter direction of the tangent pass.
+struct Tangent {
+    int kind;     // 0 value pass, 1 impedance of material `index`, 2 coordinate `coord` of sphere `index`
+    int index, coord;
+};
+
+struct AdjParams {
+    TraceParams P;
+    Tangent tan;
+    const float *g;          // [T][E][S] adjoint of the binned channel data
+    float *grad_amp;         // [n_scat] or null (value pass)
+    double *grad_alpha;      // [n_mat] or null (value pass)
+    double *grad_out;        // [1] tangent-pass result
+    double kappa;            // d ka / d alpha [Np/m per dB/(cm MHz)]
+    int attach_choice;       // 1: keep R / value(R) on the path weight
+};
+
+__device__ __forceinline__ D mat_Z(const AdjParams &A, int m) {
+    return D{A.P.mat[m].Z, (A.tan.kind == 1 && A.tan.index == m) ? 1.0 : 0.0};
+}
+
+__device__ __forceinline__ void sph_center(const AdjParams &A, int j, D *c, double *r) {
+    const double *s = A.P.sph + 4 * j;
+    for (int k = 0; k < 3; ++k) c[k] = D{s[k], (A.tan.kind == 2 && A.tan.index == j && A.tan.coord == k) ? 1.0 : 0.0};
+    *r = s[3];
+}
+
+// Adjoint of the binned data at arrival time t and its slope in t.
+__device__ __forceinline__ bool adj_at(const AdjParams &A, int tx, int e, double t, double &g, double &gs) {
+    const TraceParams &P = A.P;
+    if (!(t < P.t_max) || t < 0.0) return false;
+    const float *ch = A.g + ((int64_t)tx * P.E + e) * P.S;
+    const double x = t * P.fs;
+    if (P.binning == UR_BIN_NEAREST) {
+        const int n = (int)floor(x);
+        g = (n >= 0 && n < P.S) ? (double)ch[n] : 0.0;
+        gs = 0.0;
+    } else {
+        const double tau = x - 0.5, f0 = floor(tau), f = tau - f0;
+        const int n0 = (int)f0;
+        const double g0 = (n0 >= 0 && n0 < P.S) ? (double)ch[n0] : 0.0;
+        const double g1 = (n0 + 1 >= 0 && n0 + 1 < P.S) ? (double)ch[n0 + 1] : 0.0;
+        g = (1.0 - f) * g0 + f * g1;
+        gs = (g1 - g0) * P.fs;
+    }
+    return true;
+}
+
+struct Acc {
+    double tan;               // tangent-pass accumulator
+    double alpha[kAdjMat];    // value pass: dJ/d alpha_m
+};
+
+// Dual-number transmitted fraction 1 - A_r^2 of a straight crossing.
+__device__ __forceinline__ D transmit_fraction_d(D z1, D z2, D cos_r) {
+    const D eta = z1 / z2;
+    const D rad = dd(1.0) - eta * eta * (dd(1.0) - cos_r * cos_r);
+    if (rad.v < 0.0) return dd(0.0);
+    const D cos_t = dsqrt(rad);
+    const D den = z1 * cos_r + z2 * cos_t;
+    if (den.v == 0.0) return dd(0.0);
+    const D Ar = (z1 * cos_r - z2 * cos_t) / den;
+    return dd(1.0) - Ar * Ar;
+}
+
+// Crossings of the secondary ray q + s vh, s in (eps, dist - eps): product of
+// transmitted fractions, order-free attenuation and slowness sums, and (value
+// pass) the length spent in each material.
+__device__ bool shadow_d(const AdjParams &A, const D *q, const D *vh, D dist, int med, D &T, D &sum_a, D &sum_c,
+                         double *len_m) {
+    const TraceParams &P = A.P;
+    T = dd(1.0);
+    sum_a = dd(0.0);
+    sum_c = dd(0.0);
+    const double lo = kEpsT, hi = dist.v - kEpsT;
+    if (len_m) {
+        for (int m = 0; m < kAdjMat; ++m) len_m[m] = 0.0;
+        for (int m = 0; m < kAdjMat; ++m)
+            if (m == med) len_m[m] = dist.v;
+    }
+    auto cross_at = [&](D t, const D *ng, int mf, int mb) {
+        const D dn = ddot(vh, ng);
+        const bool front = dn.v < 0.0;
+        const int before = front ? mf : mb, after = front ? mb : mf;
+        const D adn = front ? -dn : dn;
+        T = T * transmit_fraction_d(mat_Z(A, before), mat_Z(A, after), adn);
+        const D rem = dist - t;
+        sum_a = sum_a + (P.mat[after].ka - P.mat[before].ka) * rem;
+        sum_c = sum_c + (P.mat[after].inv_c - P.mat[before].inv_c) * rem;
+        if (len_m)
+            for (int m = 0; m < kAdjMat; ++m) len_m[m] += ((m == after) - (m == before)) * rem.v;
+    };
+    const double qv[3] = {q[0].v, q[1].v, q[2].v}, vv[3] = {vh[0].v, vh[1].v, vh[2].v};
+    if (P.n_tnodes > 0) {
+        const CullRay cr = make_cull(qv, vv);
+        const float tmf = cull_tmax(dist.v);
+        int ni = 0;
+        while (ni < P.n_tnodes) {
+            const Node n = load_node(P.tnodes, ni);
+            if (!slab(n, cr, tmf)) {
+                ni = node_skip(n);
+                continue;
+            }
+            const int leaf = node_leaf(n);
+            if (leaf < 0) {
+                ++ni;
+                continue;
+            }
+            for (int k = leaf >> 4; k < (leaf >> 4) + (leaf & 15); ++k) {
+                const double *tr = P.tri + 9 * (int64_t)k;
+                double tv;
+                if (!tri_isect(tr, qv, vv, tv) || !(tv > lo && tv < hi)) continue;
+                // t = e2.(tv x e1) / e1.(d x e2) with tv = q - v0
+                const double *v0 = tr, *e1 = tr + 3, *e2 = tr + 6;
+                const D tq[3] = {q[0] - dd(v0[0]), q[1] - dd(v0[1]), q[2] - dd(v0[2])};
+                const D pv[3] = {vh[1] * dd(e2[2]) - vh[2] * dd(e2[1]), vh[2] * dd(e2[0]) - vh[0] * dd(e2[2]),
+                                 vh[0] * dd(e2[1]) - vh[1] * dd(e2[0])};
+                const D det = ddot(pv, e1);
+                const D qq[3] = {tq[1] * dd(e1[2]) - tq[2] * dd(e1[1]), tq[2] * dd(e1[0]) - tq[0] * dd(e1[2]),
+                                 tq[0] * dd(e1[1]) - tq[1] * dd(e1[0])};
+                const D t = ddot(qq, e2) / det;
+                double nv[3];
+                tri_normal(tr, nv);
+                const D ng[3] = {dd(nv[0]), dd(nv[1]), dd(nv[2])};
+                cross_at(t, ng, P.tri_mat[2 * k], P.tri_mat[2 * k + 1]);
+                if (T.v == 0.0) return false;
+            }
+            ni = node_skip(n);
+        }
+    }
+    for (int j = 0; j < P.n_sph; ++j) {
+        D c[3];
+        double r;
+        sph_center(A, j, c, &r);
+        const D oc[3] = {q[0] - c[0], q[1] - c[1], q[2] - c[2]};
+        const D b = ddot(oc, vh);
+        const D cc = ddot(oc, oc) - dd(r * r);
+        const D disc = b * b - cc;
+        if (disc.v < 0.0) continue;
+        const D sq = dsqrt(disc);
+        const D roots[2] = {-b - sq, -b + sq};
+        for (int k = 0; k < 2; ++k) {
+            if (!(roots[k].v > lo && roots[k].v < hi)) continue;
+            const D ng[3] = {(q[0] + roots[k] * vh[0] - c[0]) / dd(r), (q[1] + roots[k] * vh[1] - c[1]) / dd(r),
+                             (q[2] + roots[k] * vh[2] - c[2]) / dd(r)};
+            cross_at(roots[k], ng, P.sph_mat[2 * j], P.sph_mat[2 * j + 1]);
+        }
+    }
+    for (int j = 0; j < P.n_pln; ++j) {
+        const double *pl = P.pln + 4 * j;
+        const D den = ddot(vh, pl);
+        if (den.v == 0.0) continue;
+        const D t = (dd(pl[3]) - ddot(q, pl)) / den;
+        if (!(t.v > lo && t.v < hi)) continue;
+        const D ng[3] = {dd(pl[0]), dd(pl[1]), dd(pl[2])};
+        cross_at(t, ng, P.pln_mat[2 * j], P.pln_mat[2 * j + 1]);
+    }
+    return T.v != 0.0;
+}
+
+// Accumulates the gradient of one contribution c arriving at time t.
+// c_unit is the contribution per unit amplitude of scatterer k (k < 0: none).
+__device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx, int er, D c, D t, int k,
+                                           double c_unit, const double *len_path, const double *len_sh) {
+    double g, gs;
+    if (!adj_at(A, tx, er, t.v, g, gs)) return;
+    if (A.tan.kind != 0) {
+        acc.tan += g * c.t + gs * c.v * t.t;
+        return;
+    }
+    if (A.grad_amp && k >= 0) atomicAdd(A.grad_amp + k, (float)(g * c_unit));
+    if (A.grad_alpha)
+        for (int m = 0; m < kAdjMat; ++m) {
+            const double L = len_path[m] + (len_sh ? len_sh[m] : 0.0);
+            // d/d alpha_m of g(t) c: the amplitude factor exp(-kappa alpha L)
+            acc.alpha[m] += g * c.v * (-A.kappa * L);
+        }
+}
+
+__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray) {
+    const TraceParams &P = A.P;
+    double o0[3], d0[3], w0;
+    int cell;
+    emit(P, tx, e, ray, o0, d0, w0, cell);
+    D o[3] = {dd(o0[0]), dd(o0[1]), dd(o0[2])}, d[3] = {dd(d0[0]), dd(d0[1]), dd(d0[2])};
+    D w = dd(w0), t = dd(P.tau[(int64_t)tx * P.E + e]), len = dd(0.0);
+    double len_m[kAdjMat];
+    for (int m = 0; m < kAdjMat; ++m) len_m[m] = 0.0;
+    int med = P.top_medium;
+    int64_t last = -1;
+    for (int b = 0; b <= P.B; ++b) {
+        // closest primitive by value
+        const double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
+        double tbest = INFINITY;
+        int face = -1;
+        for (int i = 0; i < 3; ++i) {
+            double tt;
+            int fi;
+            if (dv[i] > 0.0) {
+                tt = (P.box[3 + i] - ov[i]) / dv[i];
+                fi = 3 + i;
+            } else if (dv[i] < 0.0) {
+                tt = (P.box[i] - ov[i]) / dv[i];
+                fi = i;
+            } else {
+                continue;
+            }
+            if (tt < tbest) {
+                tbest = tt;
+                face = fi;
+            }
+        }
+        int64_t hid = P.id_box;
+        int hloc = -1;
+        if (P.n_tnodes > 0) {
+            const CullRay cr = make_cull(ov, dv);
+            float tmf = cull_tmax(tbest);
+            int ni = 0;
+            while (ni < P.n_tnodes) {
+                const Node n = load_node(P.tnodes, ni);
+                if (!slab(n, cr, tmf)) {
+                    ni = node_skip(n);
+                    continue;
+                }
+                const int leaf = node_leaf(n);
+                if (leaf < 0) {
+                    ++ni;
+                    continue;
+                }
+                for (int k = leaf >> 4; k < (leaf >> 4) + (leaf & 15); ++k) {
+                    const int id = P.tri_id[k];
+                    if (id == last) continue;
+                    double tt;
+                    if (tri_isect(P.tri + 9 * (int64_t)k, ov, dv, tt) && tt > kEpsT &&
+                        (tt < tbest || (tt == tbest && id < hid))) {
+                        tbest = tt;
+                        hid = id;
+                        hloc = k;
+                        tmf = cull_tmax(tt);
+                    }
+                }
+                ni = node_skip(n);
+            }
+        }
+        for (int j = 0; j < P.n_sph; ++j) {
+            double t0, t1;
+            if (!sph_roots(P.sph + 4 * j, ov, dv, t0, t1)) continue;
+            const double tt = t0 > kEpsT ? t0 : t1;
+            if (!(tt > kEpsT)) continue;
+            const int64_t id = P.id_sph0 + j;
+            if (tt < tbest || (tt == tbest && id < hid)) {
+                tbest = tt;
+                hid = id;
+                hloc = j;
+            }
+        }
+        for (int j = 0; j < P.n_pln; ++j) {
+            const int64_t id = P.id_pln0 + j;
+            double tt;
+            if (id == last || !pln_isect(P.pln + 4 * j, ov, dv, tt) || !(tt > kEpsT)) continue;
+            if (tt < tbest || (tt == tbest && id < hid)) {
+                tbest = tt;
+                hid = id;
+                hloc = j;
+            }
+        }
+        // dual distance to the chosen primitive
+        D th;
+        D sc[3];
+        double srad = 0.0;
+        if (hid == P.id_box) {
+            const int ax = face % 3;
+            th = (dd(P.box[face]) - o[ax]) / d[ax];
+        } else if (hid < P.id_sph0) {
+            const double *tr = P.tri + 9 * (int64_t)hloc, *v0 = tr, *e1 = tr + 3, *e2 = tr + 6;
+            const D tq[3] = {o[0] - dd(v0[0]), o[1] - dd(v0[1]), o[2] - dd(v0[2])};
+            const D pv[3] = {d[1] * dd(e2[2]) - d[2] * dd(e2[1]), d[2] * dd(e2[0]) - d[0] * dd(e2[2]),
+                             d[0] * dd(e2[1]) - d[1] * dd(e2[0])};
+            const D qq[3] = {tq[1] * dd(e1[2]) - tq[2] * dd(e1[1]), tq[2] * dd(e1[0]) - tq[0] * dd(e1[2]),
+                             tq[0] * dd(e1[1]) - tq[1] * dd(e1[0])};
+            th = ddot(qq, e2) / ddot(pv, e1);
+        } else if (hid < P.id_pln0) {
+            sph_center(A, hloc, sc, &srad);
+            const D oc[3] = {o[0] - sc[0], o[1] - sc[1], o[2] - sc[2]};
+            const D bb = ddot(oc, d), cc = ddot(oc, oc) - dd(srad * srad);
+            const D sq = dsqrt(bb * bb - cc);
+            const D r0 = -bb - sq;
+            th = r0.v > kEpsT ? r0 : -bb + sq;
+        } else {
+            const double *pl = P.pln + 4 * hloc;
+            th = (dd(pl[3]) - ddot(o, pl)) / ddot(d, pl);
+        }
+        th.v = tbest;   // the value follows the forward query exactly
+        D tseg = th;
+        bool clipped = false;
+        if (len.v + tseg.v > P.max_path) {
+            tseg = dd(P.max_path) - len;
+            clipped = true;
+        }
+        // captures on [0, tseg) and their secondary rays
+        if (P.n_scat > 0) {
+            const Material M = P.mat[med];
+            dda_walk(P.grid, ov, dv, tseg.v, [&](int gcell, double ta, double tb) {
+                const int j1 = P.cell_start[gcell + 1];
+                for (int j = P.cell_start[gcell]; j < j1; ++j) {
+                    const double4 sk = P.items[j];
+                    const double p[3] = {sk.x - ov[0], sk.y - ov[1], sk.z - ov[2]};
+                    const double s = dot3(p, dv);
+                    if (!(s >= ta && s < tb)) continue;
+                    const double pp[3] = {p[0] - s * dv[0], p[1] - s * dv[1], p[2] - s * dv[2]};
+                    if (dot3(pp, pp) > P.r_s2) continue;
+                    const int k = P.item_id[j];
+                    uint32_t x[4];
+                    draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
+                    const int er = (int)(((uint64_t)x[0] * (uint64_t)P.E) >> 32);
+                    const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
+                    const D sd = ddot(pd, d);
+                    const D q[3] = {o[0] + sd * d[0], o[1] + sd * d[1], o[2] + sd * d[2]};
+                    const D v[3] = {dd(P.xe[er]) - q[0], -q[1], -q[2]};
+                    const D dist = dsqrt(ddot(v, v));
+                    const D vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
+                    const D cos_a = -vh[2];
+                    const D al = dacos(cos_a);
+                    D f;
+                    if (al.v > P.alpha_c) continue;
+                    if (al.v <= P.alpha_m) f = dd(1.0);
+                    else f = (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
+                    D T, sa, sc2;
+                    double lsh[kAdjMat];
+                    if (!shadow_d(A, q, vh, dist, med, T, sa, sc2, A.tan.kind == 0 ? lsh : nullptr)) continue;
+                    const D wq = w * dexp(-(M.ka * sd));
+                    const D tq = t + M.inv_c * sd;
+                    const D att = dexp(-(M.ka * dist + sa));
+                    const D tc = tq + M.inv_c * dist + sc2;
+                    const D cu = wq * dd((double)P.E * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
+                    const D cval = sk.w * cu;
+                    if (A.tan.kind == 0) {
+                        double lp[kAdjMat];
+                        for (int m = 0; m < kAdjMat; ++m) lp[m] = len_m[m] + (m == med ? sd.v : 0.0);
+                        contribute(A, acc, tx, er, cval, tc, k, cu.v, lp, lsh);
+                    } else {
+                        contribute(A, acc, tx, er, cval, tc, k, cu.v, nullptr, nullptr);
+                    }
+                }
+                return true;
+            });
+        }
+        // transport
+        const Material M = P.mat[med];
+        w = w * dexp(-(M.ka * tseg));
+        t = t + M.inv_c * tseg;
+        len = len + tseg;
+        for (int m = 0; m < kAdjMat; ++m)
+            if (m == med) len_m[m] += tseg.v;
+        for (int i = 0; i < 3; ++i) o[i] = o[i] + tseg * d[i];
+        if (clipped || t.v >= P.t_max) return;
+        if (hid == P.id_box) {
+            if (face == 2 && fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev) {
+                int er = (int)floor((o[0].v + P.half_ap) / P.pitch);
+                er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+                const D al = dacos(-d[2]);
+                if (al.v <= P.alpha_c) {
+                    const D f = al.v <= P.alpha_m ? dd(1.0) : (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
+                    contribute(A, acc, tx, er, w * f, t, -1, 0.0, len_m, nullptr);
+                }
+            }
+            return;
+        }
+        if (b == P.B) return;
+        // interface: dual normal, Eqs. 7-11, attached choice probability
+        D ng[3];
+        int mf, mb;
+        if (hid < P.id_sph0) {
+            double nv[3];
+            tri_normal(P.tri + 9 * (int64_t)hloc, nv);
+            for (int i = 0; i < 3; ++i) ng[i] = dd(nv[i]);
+            mf = P.tri_mat[2 * hloc];
+            mb = P.tri_mat[2 * hloc + 1];
+        } else if (hid < P.id_pln0) {
+            for (int i = 0; i < 3; ++i) ng[i] = (o[i] - sc[i]) / dd(srad);
+            mf = P.sph_mat[2 * hloc];
+            mb = P.sph_mat[2 * hloc + 1];
+        } else {
+            const double *pl = P.pln + 4 * hloc;
+            for (int i = 0; i < 3; ++i) ng[i] = dd(pl[i]);
+            mf = P.pln_mat[2 * hloc];
+            mb = P.pln_mat[2 * hloc + 1];
+        }
+        int before, after;
+        if (ddot(d, ng).v < 0.0) {
+            before = mf;
+            after = mb;
+        } else {
+            before = mb;
+            after = mf;
+            for (int i = 0; i < 3; ++i) ng[i] = -ng[i];
+        }
+        const D z1 = mat_Z(A, before), z2 = mat_Z(A, after);
+        const D cos_r = -ddot(d, ng);
+        const D eta = z1 / z2;
+        const D rad = dd(1.0) - eta * eta * (dd(1.0) - cos_r * cos_r);
+        D R = dd(1.0), cos_t = dd(0.0);
+        if (rad.v >= 0.0) {
+            cos_t = dsqrt(rad);
+            const D den = z1 * cos_r + z2 * cos_t;
+            if (den.v != 0.0) {
+                const D Ar = (z1 * cos_r - z2 * cos_t) / den;
+                R = Ar * Ar;
+            }
+        }
+        uint32_t x[4];
+        draw(P, ray, e, tx, b, 1, 0, x);
+        const double y = u01(x[0]);
+        D nd[3];
+        if (y < R.v) {
+            for (int i = 0; i < 3; ++i) nd[i] = d[i] + dd(2.0) * cos_r * ng[i];
+            if (A.attach_choice) w = w * (R / dd(R.v));
+            med = before;
+        } else {
+            const D f = eta * cos_r - cos_t;
+            for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * ng[i];
+            const D Tr = dd(1.0) - R;
+            if (A.attach_choice) w = w * (Tr / dd(Tr.v));
+            med = after;
+        }
+        const D l = dsqrt(ddot(nd, nd));
+        for (int i = 0; i < 3; ++i) d[i] = nd[i] / l;
+        last = (hid < P.id_sph0 || hid >= P.id_pln0) ? hid : -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_replay(AdjParams A) {
+    Acc acc;
+    acc.tan = 0.0;
+    for (int m = 0; m < kAdjMat; ++m) acc.alpha[m] = 0.0;
+    const TraceParams &P = A.P;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n_work) {
+        const int64_t q = i / P.per_el;
+        const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
+        replay_path(A, acc, (int)(q / P.E), (int)(q % P.E), ray);
+    }
+    // wavefront sums, one atomic per wavefront and output
+    const int lane = threadIdx.x & 63;
+    if (A.tan.kind != 0) {
+        double v = acc.tan;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && v != 0.0) atomicAdd(A.grad_out, v);
+    } else if (A.grad_alpha) {
+        for (int m = 0; m < kAdjMat && m < P.n_mat; ++m) {
+            double v = acc.alpha[m];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && v != 0.0) atomicAdd(A.grad_alpha + m, v);
+        }
+    }
+}
+
+__global__ void k_zero_f64(double *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
+                            double *grad_alpha, double *grad_out, double kappa, int attach_choice, hipStream_t s) {
+    AdjParams A;
+    A.P = p;
+    A.tan = Tangent{kind, index, coord};
+    A.g = g;
+    A.grad_amp = grad_amp;
+    A.grad_alpha = grad_alpha;
+    A.grad_out = grad_out;
+    A.kappa = kappa;
+    A.attach_choice = attach_choice;
+    if (kind != 0) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, grad_out, 1);
+    if (p.n_work <= 0) return hipGetLastError();
+    const int64_t blocks = (p.n_work + 255) / 256;
+    hipLaunchKernelGGL(k_replay, dim3((unsigned)blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}

@@ -109,6 +109,76 @@ __global__ void k_logcompress(const float *env, float *bmode, int64_t n, float d
 
 __global__ void k_zero_u32(unsigned int *p) { *p = 0u; }
 
+// ------------------------------------------------------------- adjoints
+// Envelope |IQ|: dL/dIQ = dL/denv * IQ / |IQ| (zero where |IQ| = 0).
+__global__ void k_env_adj(const float2 *iq, const float *g_env, float2 *g_iq, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 z = iq[i];
+    const float a = sqrtf(z.x * z.x + z.y * z.y);
+    const float s = a > 0.f ? g_env[i] / a : 0.f;
+    g_iq[i] = make_float2(s * z.x, s * z.y);
+}
+
+// Transpose of the delay-and-sum: every (pixel, transmit, element) term
+// w_e ((1 - f) rf[i0] + f rf[i0 + 1]) scatters w_e (1 - f) g and w_e f g
+// into the channel-data adjoint (float atomics; same indices as k_das).
+__global__ __launch_bounds__(256) void k_das_adj(DasParams p, const float2 *g_iq, float *g_rf) {
+    const int iz = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ix = blockIdx.y;
+    if (iz >= p.nz) return;
+    const float2 g = g_iq[(int64_t)ix * p.nz + iz];
+    if (g.x == 0.f && g.y == 0.f) return;
+    const double x = p.x0 + (double)ix * p.dx;
+    const double z = p.z0 + (double)iz * p.dz;
+    const double zz = z * z;
+    for (int e = 0; e < p.E; ++e) {
+        const double dxe = x - p.xe[e];
+        const double trx = sqrt(dxe * dxe + zz) * p.fs_over_c0;
+        const float a = p.apod[e];
+        for (int tx = 0; tx < p.T; ++tx) {
+            const double4 c = p.txc[tx];
+            const double idx = x * c.x + z * c.y + c.z + trx;
+            const double f0 = floor(idx);
+            const int i0 = (int)f0;
+            if (i0 < 0 || i0 >= p.S - 1) continue;
+            const float fr = (float)(idx - f0);
+            float *s = g_rf + 2 * (((int64_t)tx * p.E + e) * p.S + i0);
+            const float w0 = a * (1.f - fr), w1 = a * fr;
+            unsafeAtomicAdd(s, w0 * g.x);
+            unsafeAtomicAdd(s + 1, w0 * g.y);
+            unsafeAtomicAdd(s + 2, w1 * g.x);
+            unsafeAtomicAdd(s + 3, w1 * g.y);
+        }
+    }
+}
+
+// Transpose of the pulse convolution: g_raw[k] = sum_m Re(h[m]) g_re[k + m]
+// + Im(h[m]) g_im[k + m] (a correlation), staged like k_pulse.
+__global__ __launch_bounds__(kFirTile) void k_pulse_adj(const float2 *__restrict__ g_rf, float *__restrict__ g_raw,
+                                                        const float2 *__restrict__ taps, int K, int S) {
+    __shared__ float2 gs[kFirTile + 2 * kMaxHalfTaps];
+    __shared__ float2 hs[2 * kMaxHalfTaps + 1];
+    const int64_t ch = blockIdx.y;
+    const int n0 = blockIdx.x * kFirTile;
+    const float2 *g = g_rf + ch * S;
+    for (int i = threadIdx.x; i < kFirTile + 2 * K; i += kFirTile) {
+        const int n = n0 - K + i;
+        gs[i] = (n >= 0 && n < S) ? g[n] : make_float2(0.f, 0.f);
+    }
+    for (int i = threadIdx.x; i < 2 * K + 1; i += kFirTile) hs[i] = taps[i];
+    __syncthreads();
+    const int k = n0 + threadIdx.x;
+    if (k >= S) return;
+    float acc = 0.f;
+    for (int m = -K; m <= K; ++m) {
+        const float2 v = gs[threadIdx.x + K + m];
+        const float2 h = hs[m + K];
+        acc = fmaf(h.x, v.x, fmaf(h.y, v.y, acc));
+    }
+    g_raw[ch * S + k] = acc;
+}
+
 }  // namespace
 
 hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
@@ -119,6 +189,30 @@ hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int
         const int64_t nc = std::min<int64_t>(65535, n_ch - c0);
         dim3 grid((unsigned)((S + kFirTile - 1) / kFirTile), (unsigned)nc);
         hipLaunchKernelGGL(k_pulse, grid, dim3(kFirTile), 0, s, raw + c0 * S, rf + c0 * S, taps, K, S);
+    }
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_env_adj(const float2 *iq, const float *g_env, float2 *g_iq, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_env_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, iq, g_env, g_iq, n);
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_das_adj(const ur::DasParams &p, const float2 *g_iq, float *g_rf, hipStream_t s) {
+    dim3 grid((unsigned)((p.nz + 255) / 256), (unsigned)p.nx);
+    hipLaunchKernelGGL(k_das_adj, grid, dim3(256), 0, s, p, g_iq, g_rf);
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_pulse_adj(const float2 *g_rf, float *g_raw, const float2 *taps, int K, int64_t n_ch, int S,
+                               hipStream_t s) {
+    if (K > kMaxHalfTaps) return hipErrorInvalidValue;
+    if (n_ch <= 0 || S <= 0) return hipSuccess;
+    for (int64_t c0 = 0; c0 < n_ch; c0 += 65535) {
+        const int64_t nc = std::min<int64_t>(65535, n_ch - c0);
+        dim3 grid((unsigned)((S + kFirTile - 1) / kFirTile), (unsigned)nc);
+        hipLaunchKernelGGL(k_pulse_adj, grid, dim3(kFirTile), 0, s, g_rf + c0 * S, g_raw + c0 * S, taps, K, S);
     }
     return hipGetLastError();
 }

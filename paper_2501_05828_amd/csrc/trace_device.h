@@ -1,0 +1,232 @@
+// Device-side geometry and sampling shared by the trace kernel and the
+// path-replay adjoint: RNG draws, FP32 conservative box culling, FP64
+// primitive tests, interface fractions, receive directivity, the emission
+// map and ray emission.
+#pragma once
+#include "philox.h"
+#include "ur_internal.h"
+
+namespace ur {
+namespace dev {
+
+// counter = (ray, element | tx << 16, segment | purpose << 16, k)
+__device__ __forceinline__ void draw(const TraceParams &P, uint32_t ray, int e, int tx, int seg, uint32_t purpose,
+                                     uint32_t k, uint32_t out[4]) {
+    philox4x32_10(ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k, P.key0, P.key1, out);
+}
+
+__device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+
+__device__ __forceinline__ double dot3(const double *a, const double *b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// ------------------------------------------------------------- FP32 culling
+struct CullRay {
+    float ox, oy, oz, ix, iy, iz;
+};
+
+__device__ __forceinline__ float safe_inv(double d) {
+    const double a = fabs(d) < 1e-20 ? copysign(1e-20, d) : d;
+    return (float)(1.0 / a);
+}
+
+__device__ __forceinline__ CullRay make_cull(const double *o, const double *d) {
+    CullRay c;
+    c.ox = (float)o[0];
+    c.oy = (float)o[1];
+    c.oz = (float)o[2];
+    c.ix = safe_inv(d[0]);
+    c.iy = safe_inv(d[1]);
+    c.iz = safe_inv(d[2]);
+    return c;
+}
+
+// conservative upper bound of an FP64 ray parameter for the FP32 box test
+__device__ __forceinline__ float cull_tmax(double t) { return (float)(t * (1.0 + 1e-6) + 1e-6); }
+
+struct Node {
+    float4 lo, hi;
+};
+
+__device__ __forceinline__ Node load_node(const BvhNode *nodes, int i) {
+    const float4 *p = reinterpret_cast<const float4 *>(nodes + i);
+    return Node{p[0], p[1]};
+}
+
+__device__ __forceinline__ bool slab(const Node &n, const CullRay &r, float tmax) {
+    const float tx0 = (n.lo.x - r.ox) * r.ix, tx1 = (n.hi.x - r.ox) * r.ix;
+    const float ty0 = (n.lo.y - r.oy) * r.iy, ty1 = (n.hi.y - r.oy) * r.iy;
+    const float tz0 = (n.lo.z - r.oz) * r.iz, tz1 = (n.hi.z - r.oz) * r.iz;
+    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+    return tn <= tf;
+}
+
+__device__ __forceinline__ int node_skip(const Node &n) { return __float_as_int(n.lo.w); }
+__device__ __forceinline__ int node_leaf(const Node &n) { return __float_as_int(n.hi.w); }
+
+// ---------------------------------------------------------- FP64 primitives
+// Moller-Trumbore with precomputed edges e1 = v1 - v0, e2 = v2 - v0.  The
+// barycentric tests compare the numerators against the determinant (sign
+// aware), so only accepted hits pay for the division.
+__device__ __forceinline__ bool tri_isect(const double *tr, const double *o, const double *d, double &t) {
+    const double *v0 = tr, *e1 = tr + 3, *e2 = tr + 6;
+    const double p0 = d[1] * e2[2] - d[2] * e2[1];
+    const double p1 = d[2] * e2[0] - d[0] * e2[2];
+    const double p2 = d[0] * e2[1] - d[1] * e2[0];
+    const double det = e1[0] * p0 + e1[1] * p1 + e1[2] * p2;
+    if (det == 0.0) return false;
+    const double t0 = o[0] - v0[0], t1 = o[1] - v0[1], t2 = o[2] - v0[2];
+    const double un = t0 * p0 + t1 * p1 + t2 * p2;
+    if (det > 0.0 ? (un < 0.0 || un > det) : (un > 0.0 || un < det)) return false;
+    const double q0 = t1 * e1[2] - t2 * e1[1];
+    const double q1 = t2 * e1[0] - t0 * e1[2];
+    const double q2 = t0 * e1[1] - t1 * e1[0];
+    const double vn = d[0] * q0 + d[1] * q1 + d[2] * q2;
+    if (det > 0.0 ? (vn < 0.0 || un + vn > det) : (vn > 0.0 || un + vn < det)) return false;
+    t = (e2[0] * q0 + e2[1] * q1 + e2[2] * q2) / det;
+    return true;
+}
+
+__device__ __forceinline__ void tri_normal(const double *tr, double *n) {
+    const double *e1 = tr + 3, *e2 = tr + 6;
+    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    n[0] /= l;
+    n[1] /= l;
+    n[2] /= l;
+}
+
+__device__ __forceinline__ bool sph_roots(const double *s, const double *o, const double *d, double &t0,
+                                          double &t1) {
+    const double oc[3] = {o[0] - s[0], o[1] - s[1], o[2] - s[2]};
+    const double b = dot3(oc, d);
+    const double c = dot3(oc, oc) - s[3] * s[3];
+    const double disc = b * b - c;
+    if (disc < 0.0) return false;
+    const double sq = sqrt(disc);
+    t0 = -b - sq;
+    t1 = -b + sq;
+    return true;
+}
+
+__device__ __forceinline__ bool pln_isect(const double *p, const double *o, const double *d, double &t) {
+    const double den = dot3(p, d);
+    if (den == 0.0) return false;
+    t = (p[3] - dot3(p, o)) / den;
+    return true;
+}
+
+// Transmitted intensity fraction 1 - A_r^2 (Eqs. 8, 11) of a straight crossing.
+__device__ __forceinline__ double transmit_fraction(double z1, double z2, double cos_r) {
+    const double eta = z1 / z2;
+    const double rad = 1.0 - eta * eta * (1.0 - cos_r * cos_r);
+    if (rad < 0.0) return 0.0;
+    const double cos_t = sqrt(rad);
+    const double den = z1 * cos_r + z2 * cos_t;
+    if (den == 0.0) return 0.0;
+    const double A = (z1 * cos_r - z2 * cos_t) / den;
+    return 1.0 - A * A;
+}
+
+// Receive directivity, Eq. 13.
+__device__ __forceinline__ double directivity(double al, double am, double ac) {
+    al = fabs(al);
+    if (al > ac) return 0.0;
+    if (al <= am) return 1.0;
+    return (ac - al) / (ac - am);
+}
+
+// sin and cos of |x| <= pi/4 by their Taylor series in x^2 through x^17 and
+// x^16 (truncation below 1e-17 relative on this range), Horner form.
+__device__ __forceinline__ void sincos_quarter(double x, double &sn, double &cs) {
+    const double y = x * x;
+    double ps = 1.0 / 355687428096000.0;               //  1/17!
+    ps = fma(ps, y, -1.0 / 1307674368000.0);           // -1/15!
+    ps = fma(ps, y, 1.0 / 6227020800.0);               //  1/13!
+    ps = fma(ps, y, -1.0 / 39916800.0);                // -1/11!
+    ps = fma(ps, y, 1.0 / 362880.0);                   //  1/9!
+    ps = fma(ps, y, -1.0 / 5040.0);                    // -1/7!
+    ps = fma(ps, y, 1.0 / 120.0);                      //  1/5!
+    ps = fma(ps, y, -1.0 / 6.0);                       // -1/3!
+    sn = fma(ps * y, x, x);
+    double pc = 1.0 / 20922789888000.0;                //  1/16!
+    pc = fma(pc, y, -1.0 / 87178291200.0);             // -1/14!
+    pc = fma(pc, y, 1.0 / 479001600.0);                //  1/12!
+    pc = fma(pc, y, -1.0 / 3628800.0);                 // -1/10!
+    pc = fma(pc, y, 1.0 / 40320.0);                    //  1/8!
+    pc = fma(pc, y, -1.0 / 720.0);                     // -1/6!
+    pc = fma(pc, y, 1.0 / 24.0);                       //  1/4!
+    pc = fma(pc, y, -0.5);                             // -1/2!
+    cs = fma(pc, y, 1.0);
+}
+
+// Equal-area square -> hemisphere map: Shirley-Chiu concentric disk, then
+// the area-preserving lift z = 1 - r^2, xy scaled by sqrt(2 - r^2).  The disk
+// angle is (pi/4) u or pi/2 - (pi/4) u with |u| <= 1.
+__device__ __forceinline__ void hemisphere(double a, double b, double *d) {
+    const double sa = 2.0 * a - 1.0, sb = 2.0 * b - 1.0;
+    if (sa == 0.0 && sb == 0.0) {
+        d[0] = 0.0;
+        d[1] = 0.0;
+        d[2] = 1.0;
+        return;
+    }
+    double r, sp, cp;
+    if (fabs(sa) > fabs(sb)) {
+        r = sa;
+        sincos_quarter((M_PI / 4.0) * (sb / sa), sp, cp);
+    } else {
+        r = sb;
+        sincos_quarter((M_PI / 4.0) * (sa / sb), cp, sp);   // cos(pi/2 - x) = sin x
+    }
+    const double r2 = r * r, sc = sqrt(2.0 - r2);
+    d[0] = r * cp * sc;
+    d[1] = r * sp * sc;
+    d[2] = 1.0 - r2;
+}
+
+// Emission (Eqs. 4 and 6): origin uniform on the element face, direction from
+// the uniform or tabulated proposal on the equal-area map, weight
+// cos(theta) / (rays per transmit * pdf).
+__device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32_t ray, double *o, double *d,
+                                     double &w, int &cell_out) {
+    uint32_t x[4];
+    draw(P, ray, e, tx, 0, 0, 0, x);
+    const double u0 = u01(x[0]), u1 = u01(x[1]), u2 = u01(x[2]), u3 = u01(x[3]);
+    o[0] = P.xe[e] + (u0 - 0.5) * P.pitch;
+    o[1] = (u1 - 0.5) * P.elev;
+    o[2] = 0.0;
+    double ca, cb, pdf;
+    if (!P.proposal) {
+        ca = u2;
+        cb = u3;
+        pdf = 1.0 / (2.0 * M_PI);
+        cell_out = (int)((x[3] >> 27) * 32u + (x[2] >> 27));   // floor(32 u3) * 32 + floor(32 u2)
+    } else {
+        uint32_t y[4];
+        draw(P, ray, e, tx, 0, 3, 0, y);
+        const double uc = u01(y[0]);
+        const int64_t row = ((int64_t)tx * P.E + e) * kCells;
+        const float *cdf = P.cdf + row;
+        int lo = 0, hi = kCells;                 // first cell with uc <= cdf[cell]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (uc <= (double)cdf[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        const int cell = lo < kCells ? lo : kCells - 1;
+        cell_out = cell;
+        ca = ((double)(cell % 32) + u2) / 32.0;
+        cb = ((double)(cell / 32) + u3) / 32.0;
+        pdf = (double)P.pdf[row + cell] * (double)kCells / (2.0 * M_PI);
+    }
+    hemisphere(ca, cb, d);
+    w = d[2] / (P.n_per_tx * pdf);
+}
+
+}  // namespace dev
+}  // namespace ur

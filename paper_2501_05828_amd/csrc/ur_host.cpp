@@ -43,6 +43,8 @@ struct ur_context {
     int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
     int n_tnodes = 0;
     std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer grid
+    std::vector<double> sph;               // [n_sph][4]
+    std::vector<int32_t> item_order;       // scatterer index of each grid item
     GridInfo grid{};
     DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_cell_start, d_items,
         d_item_id, d_work;
@@ -58,6 +60,7 @@ struct ur_context {
     // proposal network (rows = transmits x elements of the current setup)
     bool mlp_ready = false;
     int mlp_rows = 0, mlp_step = 0;
+    DevBuf d_giq;                          // adjoint of IQ inside ur_beamform_adjoint
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
     RecordEntry *rec = nullptr;
@@ -322,6 +325,7 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
         c->n_pln = s->n_pln;
         c->n_scat = s->n_scat;
         c->scat.assign(s->scat, s->scat + 4 * s->n_scat);
+        c->sph.assign(s->sph, s->sph + 4 * s->n_sph);
         ur_status st;
         if ((st = upload_materials(c))) return st;
         if ((st = upload(c, c->d_sph, std::vector<double>(s->sph, s->sph + 4 * s->n_sph)))) return st;
@@ -366,6 +370,46 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
             a.angles = c->angles.data();
             ur_probe_desc p = c->probe;
             return ur_transmit_setup(c, &p, &a);
+        }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_scene_update(ur_context *c, const double *mat, const double *scat_amp, const double *sph) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_scene) return c->fail(UR_ERR_CALL_ORDER, "upload a scene first");
+        const int64_t nm = (int64_t)c->mat.size() / 3;
+        if (mat) {
+            if (!finite_all(mat, 3 * nm)) return c->fail(UR_ERR_INVALID_ARG, "non-finite material value");
+            for (int64_t m = 0; m < nm; ++m)
+                if (!(mat[3 * m] > 0) || !(mat[3 * m + 1] >= 0) || !(mat[3 * m + 2] > 0))
+                    return c->fail(UR_ERR_SCENE, "material %lld needs Z > 0, alpha >= 0, c > 0", (long long)m);
+        }
+        if (scat_amp && !finite_all(scat_amp, c->n_scat)) return c->fail(UR_ERR_INVALID_ARG, "non-finite amplitude");
+        if (sph) {
+            if (!finite_all(sph, 4 * c->n_sph)) return c->fail(UR_ERR_INVALID_ARG, "non-finite sphere value");
+            for (int64_t j = 0; j < c->n_sph; ++j)
+                if (!(sph[4 * j + 3] > 0)) return c->fail(UR_ERR_SCENE, "sphere %lld radius must be > 0", (long long)j);
+        }
+        ur_status st;
+        if (mat) {
+            c->mat.assign(mat, mat + 3 * nm);
+            if ((st = upload_materials(c))) return st;
+        }
+        if (sph) {
+            c->sph.assign(sph, sph + 4 * c->n_sph);
+            if ((st = upload(c, c->d_sph, c->sph))) return st;
+        }
+        if (scat_amp) {
+            for (int64_t k = 0; k < c->n_scat; ++k) c->scat[4 * k + 3] = scat_amp[k];
+            if (c->has_setup) {
+                std::vector<double4> items(c->item_order.size());
+                for (size_t k = 0; k < items.size(); ++k) {
+                    const double *q = c->scat.data() + 4 * (int64_t)c->item_order[k];
+                    items[k] = make_double4(q[0], q[1], q[2], q[3]);
+                }
+                if ((st = upload(c, c->d_items, items))) return st;
+            }
         }
         return UR_OK;
     });
@@ -464,6 +508,7 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
                 items[k] = make_double4(q[0], q[1], q[2], q[3]);
             }
             c->grid = g.info;
+            c->item_order = g.items;
             if ((st = upload(c, c->d_cell_start, g.cell_start))) return st;
             if ((st = upload(c, c->d_items, items))) return st;
             if ((st = upload(c, c->d_item_id, g.items))) return st;
@@ -736,6 +781,101 @@ UR_API ur_status ur_philox(ur_context *c, const uint32_t *ctr, int64_t n, uint32
     });
 }
 
+
+// ------------------------------------------------------------ adjoint
+UR_API ur_status ur_pulse_adjoint(ur_context *c, const float *g_rf_dev, float *g_raw_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!g_rf_dev || !g_raw_dev) return c->fail(UR_ERR_INVALID_ARG, "NULL channel buffer");
+        HIP_TRY(c, ur_launch_pulse_adj((const float2 *)g_rf_dev, g_raw_dev, (const float2 *)c->d_taps.p, c->K,
+                                       c->acq.n_tx * c->probe.n_elements, (int)c->acq.n_samples, (hipStream_t)stream));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_beamform_adjoint(ur_context *c, const ur_grid_desc *g, const float *iq_dev, const float *g_env_dev,
+                                     const float *g_iq_dev, float *g_rf_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!g || !g_rf_dev) return c->fail(UR_ERR_INVALID_ARG, "grid and g_rf_dev are required");
+        if ((g_env_dev == nullptr) == (g_iq_dev == nullptr))
+            return c->fail(UR_ERR_INVALID_ARG, "give exactly one of g_env_dev and g_iq_dev");
+        if (g_env_dev && !iq_dev) return c->fail(UR_ERR_INVALID_ARG, "the envelope adjoint needs iq_dev");
+        if (g->nx < 1 || g->nz < 1 || g->nx > 65535 || g->nz > (1 << 24))
+            return c->fail(UR_ERR_INVALID_ARG, "grid size out of range");
+        const double gv[] = {g->x0, g->x1, g->z0, g->z1};
+        if (!finite_all(gv, 4)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
+        if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t E = c->probe.n_elements, npx = g->nx * g->nz;
+        const float2 *giq = (const float2 *)g_iq_dev;
+        if (g_env_dev) {
+            ur_status st;
+            if ((st = alloc(c, c->d_giq, npx * sizeof(float2)))) return st;
+            HIP_TRY(c, ur_launch_env_adj((const float2 *)iq_dev, g_env_dev, (float2 *)c->d_giq.p, npx, s));
+            giq = (const float2 *)c->d_giq.p;
+        }
+        DasParams P;
+        P.E = (int)E;
+        P.T = (int)c->acq.n_tx;
+        P.S = (int)c->acq.n_samples;
+        P.nx = (int)g->nx;
+        P.nz = (int)g->nz;
+        P.x0 = g->x0;
+        P.dx = g->nx > 1 ? (g->x1 - g->x0) / (double)(g->nx - 1) : 0.0;
+        P.z0 = g->z0;
+        P.dz = g->nz > 1 ? (g->z1 - g->z0) / (double)(g->nz - 1) : 0.0;
+        P.fs_over_c0 = c->acq.f_s / c->acq.c0;
+        P.fs = c->acq.f_s;
+        P.xe = (const double *)c->d_xe.p;
+        P.apod = (const float *)c->d_apod.p + (g->apod == UR_APOD_HANN ? E : 0);
+        P.txc = (const double4 *)c->d_txc.p;
+        P.rf = nullptr;
+        P.iq = nullptr;
+        P.env = nullptr;
+        HIP_TRY(c, zero_f32(g_rf_dev, 2 * (int64_t)P.T * E * P.S, s));
+        HIP_TRY(c, ur_launch_das_adj(P, giq, g_rf_dev, s));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
+                                  const float *g_raw_dev, const ur_grad_desc *grads, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
+        if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
+        if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center)
+            return c->fail(UR_ERR_INVALID_ARG, "no gradient requested");
+        if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
+            return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
+        const int n_mat = (int)(c->mat.size() / 3);
+        if (grads->alpha && n_mat > kAdjMaxMat)
+            return c->fail(UR_ERR_UNSUPPORTED, "attenuation gradients support at most %d materials", kAdjMaxMat);
+        hipStream_t s = (hipStream_t)stream;
+        TraceParams P;
+        fill_params(c, P, seed);
+        const int64_t nel = c->acq.rays_per_element;
+        P.stride = ray_stride;
+        P.offset = ray_offset;
+        P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
+        P.n_work = (int64_t)P.T * P.E * P.per_el;
+        const double kappa = c->probe.f_c * 1e-6 * 100.0 * std::log(10.0) / 20.0;
+        if (grads->amp) HIP_TRY(c, zero_f32(grads->amp, c->n_scat, s));
+        if (grads->alpha) HIP_TRY(c, ur_launch_zero_f64(grads->alpha, n_mat, s));
+        if (grads->amp || grads->alpha)
+            HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, kappa, 1, s));
+        if (grads->Z)
+            for (int m = 0; m < n_mat; ++m)
+                HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, kappa,
+                                            !grads->frozen_choice, s));
+        if (grads->sph_center)
+            for (int j = 0; j < (int)c->n_sph; ++j)
+                for (int k = 0; k < 3; ++k)
+                    HIP_TRY(c, ur_launch_replay(P, 2, j, k, g_raw_dev, nullptr, nullptr, grads->sph_center + 3 * j + k,
+                                                kappa, !grads->frozen_choice, s));
+        return UR_OK;
+    });
+}
 
 // ------------------------------------------------------------ proposal network
 namespace {

@@ -9,6 +9,7 @@
 
 namespace ur {
 
+constexpr int kAdjMaxMat = 8;   // materials with attenuation gradients
 constexpr int kMaxMat = 16;
 constexpr int kMaxSph = 64;
 constexpr int kMaxPln = 64;
@@ -139,5 +140,12 @@ hipError_t ur_mlp_adam(float *w, float *m, float *v, const float *g, int n, floa
 hipError_t ur_mlp_tables(const float *Q, int R, float eps, float *pdf, float *cdf, hipStream_t s);
 hipError_t ur_mlp_record_hist(const ur::RecordEntry *rec, int64_t n_rec, int64_t batch, uint64_t seed, uint32_t step,
                               int64_t n_bins, float *hist, hipStream_t s);
+hipError_t ur_launch_env_adj(const float2 *iq, const float *g_env, float2 *g_iq, int64_t n, hipStream_t s);
+hipError_t ur_launch_das_adj(const ur::DasParams &p, const float2 *g_iq, float *g_rf, hipStream_t s);
+hipError_t ur_launch_pulse_adj(const float2 *g_rf, float *g_raw, const float2 *taps, int K, int64_t n_ch, int S,
+                               hipStream_t s);
+hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s);
+hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
+                            double *grad_alpha, double *grad_out, double kappa, int attach_choice, hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);

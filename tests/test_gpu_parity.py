@@ -17,7 +17,7 @@ from paper_2501_05828_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-TOL_CH = 1e-4          # channel data, relative L2 (spec bound)
+TOL_CH = 1e-4          # channel data, relative L2
 TOL_SIG = 2e-5         # FP32 pulse / DAS on identical inputs: ~1e-6 expected from FP32 taps and sums
 EXACT_STATS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
