@@ -60,9 +60,17 @@ def trace_flops(st, n_pln, n_sph):
     return float(f32), float(f64)
 
 
-def kernel_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+TRACE_SOURCES = ["k_trace.hip", "trace_device.h", "scatter_grid.h", "bvh_layout.h", "philox.h", "ur_internal.h"]
+
+
+def kernel_hash():
+    """Hash of the trace kernel's source (the .hip file and the headers it
+    includes), to tell whether stored counter readings still apply."""
+    h = hashlib.sha256()
+    for name in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_05828_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload, n_launch_bytes_hint=None):
@@ -73,8 +81,7 @@ def load_traffic(workload, n_launch_bytes_hint=None):
         return None
     with open(path) as f:
         d = json.load(f)
-    src = os.path.join(ROOT, "paper_2501_05828_amd", "csrc", "k_trace.hip")
-    if d.get("kernel_hash") != kernel_hash(src):
+    if d.get("kernel_hash") != kernel_hash():
         return None
     return d["fetch_bytes"] / d["copy_fetch_factor"] + d["write_bytes"] / d["copy_write_factor"]
 
@@ -198,16 +205,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=24000)
+    ap.add_argument("--cpu-rays", type=int, default=150000)
     ap.add_argument("--experiment", choices=["learned"], default=None,
                     help="learned: channel MSE vs GPU time, learned vs uniform emission")
     ap.add_argument("--ref-rays-per-tx", type=float, default=1e9)
     ap.add_argument("--ref-parts", type=int, default=10)
     ap.add_argument("--record-traces", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (rays would shard by transmit "
               "and element rows, with one reduction of the channel data)", file=sys.stderr)
@@ -242,6 +253,7 @@ def main():
     st = sim.trace(seed=w.seed, stats=True)
     f32, f64 = trace_flops(st, len(w.scene.pln), len(w.scene.sph))
     print(f"[bench] counting pass: {st['kernel_ms']:.1f} ms, records {st['records']}", file=sys.stderr, flush=True)
+    print(f"[bench] counts {json.dumps(st)}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         sim.step(seed=w.seed + 1000 + i)
