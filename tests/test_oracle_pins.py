@@ -410,6 +410,37 @@ def test_emission_weights_mirror_statistics(oracle):
     assert first >= math.floor(2 * D / 1540 * w.acq.f_s)
 
 
+def test_learned_emission_mirror_statistics(oracle):
+    """The same mirror with a peaked emission-cell table (cell probability
+    q, p(omega) = q 1024 / (2 pi)): the 1/p weighting keeps the direct-hit
+    sum at pi sin^2(alpha_m) (Eq. 4 with a non-uniform p_t).  The recorded
+    |c| histogram sums to the channel data (every contribution is positive
+    here) and lies only in cells that contain directions inside the cone."""
+    D = 6 * MM
+    sc = homogeneous(alpha=0.0, planes=[[0, 0, 1, D]], pln_mat=[[1, 0]],
+                     mats=[[1.5, 0.0, 1540.0], [1.5e9, 0.0, 1540.0]], box=(-60, -60, 0, 60, 60, 40))
+    am = math.radians(10)
+    w = with_scene(sc, alpha_m=am, alpha_c=am, elevation=40 * MM, max_bounces=1).with_rays(512)
+    i, j = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    q = 1.0 + 9.0 * np.exp(-((i - 15.5) ** 2 + (j - 15.5) ** 2) / (2 * 4.0 ** 2))
+    q = (q / q.sum()).ravel()
+    E = w.acq.n_elements
+    pdf = np.tile(q.astype(np.float32), (1, E, 1))
+    cdf = np.cumsum(pdf.astype(np.float64), -1).astype(np.float32)
+    cdf[..., -1] = 1.0
+    ch, st, hist = oracle.trace(w, pdf=pdf, cdf=cdf, rec_hist=True)
+    n_hit = st["direct_hits"]
+    assert n_hit > 500
+    expected = math.pi * math.sin(am) ** 2
+    assert abs(ch.sum() / expected - 1) < 5 / math.sqrt(n_hit)
+    assert abs(hist.sum() / ch.sum() - 1) < 1e-12
+    for cell in np.flatnonzero(hist.sum((0, 1))):
+        a0, b0 = (cell % 32) / 32.0, (cell // 32) / 32.0
+        th = min(math.acos(oracle.hemisphere(a0 + da / 32.0, b0 + db / 32.0)[2])
+                 for da in np.linspace(0, 1, 6) for db in np.linspace(0, 1, 6))
+        assert th <= am + 1e-9, (cell, th)
+
+
 # ------------------------------------------------------ pulse (Eq. 14)
 def test_pulse_taps_closed_form(oracle, golden):
     g = golden["pulse"]
