@@ -34,7 +34,7 @@ PEAK_HBM = 8.0e12
 # Algorithmic FLOPs per counted unit of the trace kernel (add/sub/mul = 1,
 # fma = 2, div/sqrt/exp/acos = 1; compares, min/max and integer RNG work are
 # not counted).  Only the part of each test that always executes is counted.
-FP32_PER_NODE = 12          # slab test: 6 sub + 6 mul
+FP32_PER_NODE = 48          # four-wide node: four slab tests of 6 sub + 6 mul
 FP64_PER_CELL = 4           # DDA step: next crossing (fma) + advance
 FP64_PER_TRI_TEST = 24      # Moller-Trumbore up to the first barycentric test
 FP64_PER_SCAT_TEST = 8      # projection of the scatterer on the segment

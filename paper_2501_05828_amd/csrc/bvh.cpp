@@ -146,6 +146,92 @@ struct Builder {
 
 }  // namespace
 
+namespace {
+
+int as_int(float f) {
+    int v;
+    std::memcpy(&v, &f, sizeof(int));
+    return v;
+}
+
+struct Collapser {
+    const std::vector<BvhNode> &n2;
+    std::vector<Bvh4Node> out;
+
+    bool leaf(int i) const { return as_int(n2[i].hi[3]) >= 0; }
+    int second_child(int i) const { return as_int(n2[i + 1].lo[3]); }
+    double area(int i) const {
+        const double dx = (double)n2[i].hi[0] - n2[i].lo[0], dy = (double)n2[i].hi[1] - n2[i].lo[1],
+                     dz = (double)n2[i].hi[2] - n2[i].lo[2];
+        return dx * dy + dy * dz + dz * dx;
+    }
+
+    void set_child(int node, int k, int src, int child) {
+        Bvh4Node &q = out[node];
+        q.lo_x[k] = n2[src].lo[0];
+        q.lo_y[k] = n2[src].lo[1];
+        q.lo_z[k] = n2[src].lo[2];
+        q.hi_x[k] = n2[src].hi[0];
+        q.hi_y[k] = n2[src].hi[1];
+        q.hi_z[k] = n2[src].hi[2];
+        q.child[k] = child;
+    }
+
+    int make_node() {
+        Bvh4Node q;
+        for (int k = 0; k < 4; ++k) {
+            q.lo_x[k] = q.hi_x[k] = q.lo_y[k] = q.hi_y[k] = q.lo_z[k] = q.hi_z[k] = 1e30f;
+            q.child[k] = -1;
+            q.pad[k] = 0;
+        }
+        out.push_back(q);
+        return (int)out.size() - 1;
+    }
+
+    // r: inner node of the binary tree
+    int build(int r) {
+        const int node = make_node();
+        std::vector<int> ch = {r + 1, second_child(r)};
+        while (ch.size() < 4) {
+            int best = -1;
+            double ba = -1.0;
+            for (size_t k = 0; k < ch.size(); ++k)
+                if (!leaf(ch[k]) && area(ch[k]) > ba) {
+                    ba = area(ch[k]);
+                    best = (int)k;
+                }
+            if (best < 0) break;
+            const int c = ch[best];
+            ch.erase(ch.begin() + best);
+            ch.push_back(c + 1);
+            ch.push_back(second_child(c));
+        }
+        for (size_t k = 0; k < ch.size(); ++k) {
+            if (leaf(ch[k])) {
+                set_child(node, (int)k, ch[k], ~as_int(n2[ch[k]].hi[3]));
+            } else {
+                const int sub = build(ch[k]);
+                set_child(node, (int)k, ch[k], sub);
+            }
+        }
+        return node;
+    }
+};
+
+}  // namespace
+
+std::vector<Bvh4Node> collapse_bvh4(const std::vector<BvhNode> &nodes) {
+    Collapser c{nodes, {}};
+    if (nodes.empty()) return {};
+    if (c.leaf(0)) {
+        const int node = c.make_node();
+        c.set_child(node, 0, 0, ~as_int(nodes[0].hi[3]));
+    } else {
+        c.build(0);
+    }
+    return std::move(c.out);
+}
+
 BvhResult build_bvh(const std::vector<PrimBounds> &prims, int leaf_max, double dilate) {
     Builder b(prims, std::min(15, std::max(1, leaf_max)), dilate);
     if (!prims.empty()) b.emit(0, (int)prims.size(), 0);

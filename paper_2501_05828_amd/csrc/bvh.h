@@ -23,4 +23,10 @@ struct BvhResult {
 // `dilate` metres and rounded outward to FP32.
 BvhResult build_bvh(const std::vector<PrimBounds> &prims, int leaf_max, double dilate);
 
+// Collapses the binary tree of a threaded layout into four-wide nodes
+// (greedily opening the largest-area inner child until four children or
+// only leaves remain), in depth-first order with the root at 0.  Leaves and
+// primitive order are unchanged.  Empty for an empty tree.
+std::vector<Bvh4Node> collapse_bvh4(const std::vector<BvhNode> &nodes);
+
 }  // namespace ur

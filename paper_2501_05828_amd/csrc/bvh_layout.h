@@ -17,4 +17,16 @@ struct alignas(16) BvhNode {
     float hi[4];
 };
 
+// Four-wide node (128 bytes, one cache line) for ordered closest-hit
+// traversal: the boxes of up to four children, one axis per row, and the
+// children: >= 0 an inner node index, -1 an empty slot (box set to a far
+// point so the slab test fails), else ~((first << 4) | count) for a leaf.
+// The child boxes are the binary tree's node boxes, so the same
+// conservativeness holds.
+struct alignas(16) Bvh4Node {
+    float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+    int child[4];
+    int pad[4];
+};
+
 }  // namespace ur

@@ -106,9 +106,149 @@ struct Hit {
     int local;     // triangle slot in BVH order, sphere or plane index
 };
 
+// Per-lane traversal stack in LDS, entry-major (entry i of lane l at
+// base[i * stride]) so lanes at the same depth touch consecutive words.
+struct LdsStack {
+    int2 *base;
+    int stride;
+};
+constexpr int kStack = 16;
+
+// Escape-index walk over the binary tree: complete, stackless, fixed order.
+template <bool COUNT>
+__device__ __forceinline__ void walk_threaded(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                              const CullRay &cr, float &tmf, Hit &h, Counters &cnt) {
+    int ni = 0;
+    while (ni < P.n_tnodes) {
+        const Node n = load_node(P.tnodes, ni);
+        CNT(C_TRI_NODES);
+        if (!slab(n, cr, tmf)) {
+            ni = node_skip(n);
+            continue;
+        }
+        const int leaf = node_leaf(n);
+        if (leaf < 0) {
+            ++ni;
+            continue;
+        }
+        const int first = leaf >> 4, count = leaf & 15;
+        for (int k = first; k < first + count; ++k) {
+            const int id = P.tri_id[k];
+            if (id == skip) continue;
+            CNT(C_TRI_TESTS);
+            double t;
+            if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && id < h.id))) {
+                h.t = t;
+                h.id = id;
+                h.local = k;
+                tmf = cull_tmax(t);
+            }
+        }
+        ni = node_skip(n);
+    }
+}
+
+// Ordered walk over the four-wide tree: each visit tests four child boxes
+// from one 128-byte node, tests hit leaves at once, continues with the
+// nearest hit inner child and stacks the others (farthest first).  Popped
+// entries whose entry distance exceeds the current best are dropped.  If
+// the stack would overflow, the walk finishes and the escape-index walk
+// then re-visits the whole tree with the best hit so far, so the result is
+// always the exact closest hit (nearest t, lower id on ties).
+template <bool COUNT>
+__device__ __forceinline__ void walk_wide(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                          Hit &h, LdsStack stk, Counters &cnt) {
+    const CullRay cr = make_cull(o, d);
+    float tmf = cull_tmax(h.t);
+    int sp = 0, cur = 0;
+    bool overflow = false;
+    while (true) {
+        const float4 *q = reinterpret_cast<const float4 *>(P.tnodes4 + cur);
+        const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5];
+        const int4 ch = reinterpret_cast<const int4 *>(q)[6];
+        CNT(C_TRI_NODES);
+        const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
+        const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
+        const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
+        const int C[4] = {ch.x, ch.y, ch.z, ch.w};
+        float key[4];
+        int val[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float x0 = (LX[k] - cr.ox) * cr.ix, x1 = (HX[k] - cr.ox) * cr.ix;
+            const float y0 = (LY[k] - cr.oy) * cr.iy, y1 = (HY[k] - cr.oy) * cr.iy;
+            const float z0 = (LZ[k] - cr.oz) * cr.iz, z1 = (HZ[k] - cr.oz) * cr.iz;
+            const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+            const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
+            const bool hit = tn <= tf && C[k] != -1;
+            if (hit && C[k] < -1) {
+                const int code = ~C[k];
+                for (int j = code >> 4; j < (code >> 4) + (code & 15); ++j) {
+                    const int id = P.tri_id[j];
+                    if (id == skip) continue;
+                    CNT(C_TRI_TESTS);
+                    double t;
+                    if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT &&
+                        (t < h.t || (t == h.t && id < h.id))) {
+                        h.t = t;
+                        h.id = id;
+                        h.local = j;
+                        tmf = cull_tmax(t);
+                    }
+                }
+            }
+            key[k] = hit && C[k] >= 0 ? tn : INFINITY;
+            val[k] = C[k];
+        }
+        // sort the four (key, child) pairs ascending: 5 compare-exchanges
+        auto cx = [&](int a, int b) {
+            if (key[b] < key[a]) {
+                const float tk = key[a];
+                key[a] = key[b];
+                key[b] = tk;
+                const int tv = val[a];
+                val[a] = val[b];
+                val[b] = tv;
+            }
+        };
+        cx(0, 1);
+        cx(2, 3);
+        cx(0, 2);
+        cx(1, 3);
+        cx(1, 2);
+#pragma unroll
+        for (int k = 3; k >= 1; --k) {
+            if (key[k] <= tmf) {
+                if (sp < kStack) {
+                    stk.base[sp * stk.stride] = make_int2(val[k], __float_as_int(key[k]));
+                    ++sp;
+                } else {
+                    overflow = true;
+                }
+            }
+        }
+        if (key[0] <= tmf) {
+            cur = val[0];
+            continue;
+        }
+        bool found = false;
+        while (sp > 0) {
+            --sp;
+            const int2 e = stk.base[sp * stk.stride];
+            if (__int_as_float(e.y) <= tmf) {
+                cur = e.x;
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+    }
+    if (overflow) walk_threaded<COUNT>(P, o, d, skip, cr, tmf, h, cnt);
+}
+
 template <bool COUNT>
 __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o, const double *d, int64_t skip,
-                                           Counters &cnt) {
+                                           LdsStack stk, Counters &cnt) {
     Hit h;
     h.t = INFINITY;
     h.face = -1;
@@ -132,39 +272,7 @@ __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o
             h.face = fi;
         }
     }
-    if (P.n_tnodes > 0) {
-        const CullRay cr = make_cull(o, d);
-        float tmf = cull_tmax(h.t);
-        int ni = 0;
-        while (ni < P.n_tnodes) {
-            const Node n = load_node(P.tnodes, ni);
-            CNT(C_TRI_NODES);
-            if (!slab(n, cr, tmf)) {
-                ni = node_skip(n);
-                continue;
-            }
-            const int leaf = node_leaf(n);
-            if (leaf < 0) {
-                ++ni;
-                continue;
-            }
-            const int first = leaf >> 4, count = leaf & 15;
-            for (int k = first; k < first + count; ++k) {
-                const int id = P.tri_id[k];
-                if (id == skip) continue;
-                CNT(C_TRI_TESTS);
-                double t;
-                if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT &&
-                    (t < h.t || (t == h.t && id < h.id))) {
-                    h.t = t;
-                    h.id = id;
-                    h.local = k;
-                    tmf = cull_tmax(t);
-                }
-            }
-            ni = node_skip(n);
-        }
-    }
+    if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
     for (int j = 0; j < P.n_sph; ++j) {
         double t0, t1;
         if (!sph_roots(P.sph + 4 * j, o, d, t0, t1)) continue;
@@ -335,24 +443,49 @@ __device__ __forceinline__ void scatter_events(const TraceParams &P, const Event
                                                uint32_t ray, int seg, const double *o, const double *d, double w,
                                                double t, int med, double t_seg, int cell) {
     if (P.n_scat == 0) return;
+    // FP32 prefilter on 16-byte items: the rounding of positions, direction
+    // and products stays below ~6e-7 x the largest coordinate, well inside
+    // the widening pre_m of the interval and the radius, so every capture of
+    // the exact FP64 test below passes it
+    const float of[3] = {(float)o[0], (float)o[1], (float)o[2]};
+    const float df[3] = {(float)d[0], (float)d[1], (float)d[2]};
     dda_walk(P.grid, o, d, t_seg, [&](int gcell, double ta, double tb) {
         CNT(C_SCAT_CELLS);
         const int j1 = P.cell_start[gcell + 1];
-        for (int j = P.cell_start[gcell]; j < j1; ++j) {
-            CNT(C_SCAT_TESTS);
-            const double4 sk = P.items[j];
-            const double p[3] = {sk.x - o[0], sk.y - o[1], sk.z - o[2]};
-            const double s = dot3(p, d);
-            if (!(s >= ta && s < tb)) continue;
-            const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
-            if (dot3(pp, pp) > P.r_s2) continue;
-            NeeEntry c;
-            if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, o, d, w, t, med, s, cell, c)) continue;
-            if constexpr (LOG || MODE == kInlineNeeOnly) {
-                nee_cast<COUNT, LOG>(P, L, cnt, c);
-            } else {
-                const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
-                if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;
+        const float taf = (float)ta - P.pre_m, tbf = (float)tb + P.pre_m;
+        for (int jb = P.cell_start[gcell]; jb < j1; jb += 4) {
+            // four independent loads in flight, then the four prefilter tests
+            float4 f[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                f[k] = jb + k < j1 ? P.items_f[jb + k] : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+            unsigned pass = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float pf[3] = {f[k].x - of[0], f[k].y - of[1], f[k].z - of[2]};
+                const float sf = pf[0] * df[0] + pf[1] * df[1] + pf[2] * df[2];
+                const float qf[3] = {pf[0] - sf * df[0], pf[1] - sf * df[1], pf[2] - sf * df[2]};
+                if (sf >= taf && sf <= tbf && qf[0] * qf[0] + qf[1] * qf[1] + qf[2] * qf[2] <= P.pre_r2)
+                    pass |= 1u << k;
+            }
+            if constexpr (COUNT) cnt.v[C_SCAT_TESTS] += (uint32_t)min(4, j1 - jb);
+            while (pass) {
+                const int j = jb + __builtin_ctz(pass);
+                pass &= pass - 1;
+                const double4 sk = P.items[j];
+                const double p[3] = {sk.x - o[0], sk.y - o[1], sk.z - o[2]};
+                const double s = dot3(p, d);
+                if (!(s >= ta && s < tb)) continue;
+                const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
+                if (dot3(pp, pp) > P.r_s2) continue;
+                NeeEntry c;
+                if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, o, d, w, t, med, s, cell, c)) continue;
+                if constexpr (LOG || MODE == kInlineNeeOnly) {
+                    nee_cast<COUNT, LOG>(P, L, cnt, c);
+                } else {
+                    const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
+                    if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;
+                }
             }
         }
         return true;
@@ -377,11 +510,11 @@ struct RayState {
 // The ray also ends past max_path (segment clipped there) or when its time
 // leaves the record window.  Returns false when the ray has ended.
 template <bool COUNT, bool LOG, int MODE>
-__device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R) {
+__device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R, LdsStack stk) {
     const int b = R.seg;
     double *o = R.o, *d = R.d;
     CNT(C_SEGMENTS);
-    const Hit h = closest_hit<COUNT>(P, o, d, R.last, cnt);
+    const Hit h = closest_hit<COUNT>(P, o, d, R.last, stk, cnt);
     double t_seg = h.t;
     bool clipped = false;
     if (R.len + t_seg > P.max_path) {
@@ -534,6 +667,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int k = 0; k < kNumStats; ++k) cnt.v[k] = 0;
     }
     const EventLog L{};
+    __shared__ int2 s_stack[kStack * 256];
+    const LdsStack stk{s_stack + threadIdx.x, 256};
     const int lane = threadIdx.x & 63;
     const unsigned long long n_range = (unsigned long long)(P.work_end - P.work_begin);
     RayState R;
@@ -569,7 +704,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
         if (__ballot(active) == 0ull) break;
-        if (active) active = advance<COUNT, false, MODE>(P, L, cnt, R);
+        if (active) active = advance<COUNT, false, MODE>(P, L, cnt, R, stk);
     }
     flush_counters<COUNT>(P, cnt);
 }
@@ -593,6 +728,8 @@ __global__ __launch_bounds__(256) void k_nee(TraceParams P) {
 }
 
 __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *rays, int64_t n, EventLog L) {
+    __shared__ int2 s_stack[kStack * 64];
+    const LdsStack stk{s_stack + threadIdx.x, 64};
     Counters cnt;
 #pragma unroll
     for (int k = 0; k < kNumStats; ++k) cnt.v[k] = 0;
@@ -615,7 +752,7 @@ __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *
         R.ray = (uint32_t)r.ray;
         R.cell = -1;
         ++cnt.v[C_RAYS];
-        while (advance<true, true, kDeferNee>(P, L, cnt, R)) {
+        while (advance<true, true, kDeferNee>(P, L, cnt, R, stk)) {
         }
     }
     flush_counters<true>(P, cnt);

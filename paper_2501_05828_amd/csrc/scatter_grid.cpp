@@ -3,6 +3,11 @@
 
 #include <algorithm>
 
+#ifndef UR_GRID_ITEMS_PER_CELL
+#define UR_GRID_ITEMS_PER_CELL 2.0   // mean scatterers per cell (before the capture-ball overlap); the walk
+                                     // tests a cell's items four at a time, so fuller cells pay off
+#endif
+
 namespace ur {
 
 ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_scat, double r_s, double margin) {
@@ -13,7 +18,7 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
         vol *= ext[k];
     }
     const double rho = n_scat > 0 ? (double)n_scat / vol : 1.0 / vol;
-    double h = std::cbrt(0.5 / rho);
+    double h = std::cbrt(UR_GRID_ITEMS_PER_CELL / rho);
     h = std::max(h, 4.0 * r_s);
     h = std::max(h, std::cbrt(vol / (double)(1 << 24)) * 1.0001);
     for (int k = 0; k < 3; ++k) {

@@ -101,7 +101,7 @@ UR_HD int dda_walk(const GridInfo &g, const double *o, const double *d, double t
     return visited;
 }
 
-// Host build: cell edge chosen for about half a scatterer per cell (never
+// Host build: cell edge chosen for about two scatterers per cell (never
 // below four capture radii), at most 2^24 cells.
 struct ScatterGrid {
     GridInfo info;

@@ -41,13 +41,13 @@ struct ur_context {
     double box[6] = {0};
     int top_medium = 0;
     int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
-    int n_tnodes = 0;
+    int n_tnodes = 0, n_tnodes4 = 0;
     std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer grid
     std::vector<double> sph;               // [n_sph][4]
     std::vector<int32_t> item_order;       // scatterer index of each grid item
     GridInfo grid{};
-    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_cell_start, d_items,
-        d_item_id, d_work;
+    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_tnodes4, d_cell_start, d_items,
+        d_items_f, d_item_id, d_work;
     // setup
     bool has_setup = false;
     ur_probe_desc probe{};
@@ -201,11 +201,21 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.tri_mat = (const int *)c->d_tri_mat.p;
     P.tri_id = (const int *)c->d_tri_id.p;
     P.tnodes = (const BvhNode *)c->d_tnodes.p;
+    P.tnodes4 = (const Bvh4Node *)c->d_tnodes4.p;
+    P.n_tnodes4 = c->n_tnodes4;
     P.n_tri = (int)c->n_tri;
     P.n_tnodes = c->n_tnodes;
     P.grid = c->grid;
     P.cell_start = (const int *)c->d_cell_start.p;
     P.items = (const double4 *)c->d_items.p;
+    P.items_f = (const float4 *)c->d_items_f.p;
+    {
+        double ext = 0.0;
+        for (int i = 0; i < 6; ++i) ext = std::max(ext, std::fabs(c->box[i]));
+        const double m = 1e-6 + 4e-6 * ext, r = std::sqrt(P.r_s2) + m;
+        P.pre_m = (float)m;
+        P.pre_r2 = (float)(r * r * (1.0 + 1e-5));
+    }
     P.item_id = (const int *)c->d_item_id.p;
     P.n_scat = (int)c->n_scat;
     P.work_next = (unsigned long long *)c->d_work.p;
@@ -263,7 +273,7 @@ UR_API void ur_context_destroy(ur_context *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
-                      &c->d_tri_id, &c->d_tnodes, &c->d_cell_start, &c->d_items, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
+                      &c->d_tri_id, &c->d_tnodes, &c->d_tnodes4, &c->d_cell_start, &c->d_items, &c->d_items_f, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
                       &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
@@ -358,6 +368,9 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                 tid[k] = o;
             }
             c->n_tnodes = (int)r.nodes.size();
+            const std::vector<Bvh4Node> wide = collapse_bvh4(r.nodes);
+            c->n_tnodes4 = (int)wide.size();
+            if ((st = upload(c, c->d_tnodes4, wide))) return st;
             if ((st = upload(c, c->d_tri, tri))) return st;
             if ((st = upload(c, c->d_tri_mat, tm))) return st;
             if ((st = upload(c, c->d_tri_id, tid))) return st;
@@ -503,14 +516,17 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         {
             ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6);
             std::vector<double4> items(g.items.size());
+            std::vector<float4> items_f(g.items.size());
             for (size_t k = 0; k < g.items.size(); ++k) {
                 const double *q = c->scat.data() + 4 * (int64_t)g.items[k];
                 items[k] = make_double4(q[0], q[1], q[2], q[3]);
+                items_f[k] = make_float4((float)q[0], (float)q[1], (float)q[2], 0.0f);
             }
             c->grid = g.info;
             c->item_order = g.items;
             if ((st = upload(c, c->d_cell_start, g.cell_start))) return st;
             if ((st = upload(c, c->d_items, items))) return st;
+            if ((st = upload(c, c->d_items_f, items_f))) return st;
             if ((st = upload(c, c->d_item_id, g.items))) return st;
             if ((st = alloc(c, c->d_work, 256))) return st;
         }

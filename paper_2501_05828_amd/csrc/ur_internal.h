@@ -74,13 +74,17 @@ struct TraceParams {
     const double *tri;                // [n_tri][9]
     const int *tri_mat;               // [n_tri][2]
     const int *tri_id;                // original index (tie-break, exclusion)
-    const BvhNode *tnodes;
-    int n_tri, n_tnodes;
+    const BvhNode *tnodes;            // threaded binary tree (any-hit walks, fallback)
+    const Bvh4Node *tnodes4;          // four-wide tree (closest hit)
+    int n_tri, n_tnodes, n_tnodes4;
     // scatterers: uniform grid, items grouped by cell (copies of position +
     // amplitude, and the original index that keys the RNG counter)
     GridInfo grid;
     const int *cell_start;            // [cells + 1]
     const double4 *items;             // [n_items]
+    const float4 *items_f;            // [n_items] positions rounded to FP32, for the conservative prefilter
+    float pre_m;                      // prefilter widening [m]: 1 um + 4e-6 x the largest box coordinate
+    float pre_r2;                     // prefilter capture radius^2, (r_s + pre_m)^2 rounded up
     const int *item_id;               // [n_items]
     int n_scat;
     // outputs and work distribution

@@ -1,7 +1,8 @@
 // Host self-check of the BVH builder used by the HIP library: structure
 // (skip indices, leaf ranges, containment) and conservative FP32 culling.
-// The traversal loop mirrors the device's stackless escape-index walk; the
-// reference is a brute-force FP64 closest hit.
+// The traversal loops mirror the device's stackless escape-index walk and
+// its ordered four-wide walk with a bounded stack (falling back to the
+// escape-index walk on overflow); the reference is brute-force FP64.
 // usage: bvh_selfcheck <prims.bin> <n> <kind: tri|pt> <dilate> <radius> <n_rays> <seed>
 #include <cmath>
 #include <cstdint>
@@ -138,5 +139,108 @@ int main(int argc, char **argv) {
         for (int w : want) if (!reached[w]) ++missed;
     }
     std::printf("nodes %d depth %d visits/ray %.1f missed %ld\n", nn, r.max_depth, nrays ? (double)visits / nrays : 0.0, missed);
-    return missed ? 1 : 0;
+    if (missed) return 1;
+    if (!tri) return 0;
+    // ---- four-wide layout: structure
+    std::vector<Bvh4Node> q4 = collapse_bvh4(r.nodes);
+    std::vector<int> seen4(n, 0);
+    std::vector<int> todo = {0};
+    int n4 = 0;
+    while (!todo.empty()) {
+        const int i = todo.back();
+        todo.pop_back();
+        ++n4;
+        const Bvh4Node &b = q4[i];
+        for (int k = 0; k < 4; ++k) {
+            const int c = b.child[k];
+            if (c == -1) continue;
+            if (c >= 0) {
+                if (c <= i || c >= (int)q4.size()) { std::puts("bad bvh4 child"); return 1; }
+                todo.push_back(c);
+            } else {
+                const int code = ~c, first = code >> 4, cnt = code & 15;
+                if (cnt < 1 || first + cnt > n) { std::puts("bad bvh4 leaf"); return 1; }
+                for (int s = first; s < first + cnt; ++s) {
+                    seen4[r.order[s]]++;
+                    const PrimBounds &p = pb[r.order[s]];
+                    if (!(b.lo_x[k] <= p.lo[0] && b.lo_y[k] <= p.lo[1] && b.lo_z[k] <= p.lo[2] && b.hi_x[k] >= p.hi[0] &&
+                          b.hi_y[k] >= p.hi[1] && b.hi_z[k] >= p.hi[2])) { std::puts("bvh4 leaf box"); return 1; }
+                }
+            }
+        }
+    }
+    if (n4 != (int)q4.size()) { std::puts("unreachable bvh4 nodes"); return 1; }
+    for (long i = 0; i < n; ++i) if (seen4[i] != 1) { std::printf("bvh4: prim %ld seen %d times\n", i, seen4[i]); return 1; }
+    // ---- ordered closest hit with a 16-entry stack vs brute force
+    std::mt19937_64 g2(std::atol(argv[7]) + 1);
+    long wrong = 0, overflows = 0, v4 = 0;
+    for (long q = 0; q < nrays; ++q) {
+        double o[3], d[3];
+        for (int k = 0; k < 3; ++k) o[k] = lo[k] + (hi[k] - lo[k]) * (1.4 * U(g2) - 0.2);
+        double l = 0; for (int k = 0; k < 3; ++k) { d[k] = N(g2); l += d[k] * d[k]; }
+        l = std::sqrt(l); for (int k = 0; k < 3; ++k) d[k] /= l;
+        const double tmax = 0.05 + 0.1 * U(g2);
+        double tb = tmax; int hb = -1;
+        for (long i = 0; i < n; ++i) {
+            double t;
+            if (tri_isect(&P[9 * i], o, d, t) && t > 1e-9 && (t < tb || (t == tb && i < hb))) { tb = t; hb = (int)i; }
+        }
+        double tg = tmax; int hg = -1;
+        auto test_leaf = [&](int code, float &tmf) {
+            for (int s = code >> 4; s < (code >> 4) + (code & 15); ++s) {
+                double t; const int id = r.order[s];
+                if (tri_isect(&P[9 * id], o, d, t) && t > 1e-9 && (t < tg || (t == tg && id < hg))) {
+                    tg = t; hg = id; tmf = (float)(t * (1.0 + 1e-6) + 1e-6);
+                }
+            }
+        };
+        float of[3] = {(float)o[0], (float)o[1], (float)o[2]}, inv[3] = {safe_inv(d[0]), safe_inv(d[1]), safe_inv(d[2])};
+        float tmf = (float)(tmax * (1.0 + 1e-6) + 1e-6);
+        int stk_n[16]; float stk_t[16]; int sp = 0, cur = 0; bool overflow = false;
+        while (true) {
+            const Bvh4Node &b = q4[cur];
+            ++v4;
+            float tn[4]; bool hit[4];
+            for (int k = 0; k < 4; ++k) {
+                const float bl[3] = {b.lo_x[k], b.lo_y[k], b.lo_z[k]}, bh[3] = {b.hi_x[k], b.hi_y[k], b.hi_z[k]};
+                float a0 = 0.0f, a1 = tmf;
+                for (int j = 0; j < 3; ++j) {
+                    const float x0 = (bl[j] - of[j]) * inv[j], x1 = (bh[j] - of[j]) * inv[j];
+                    a0 = std::fmax(a0, std::fmin(x0, x1)); a1 = std::fmin(a1, std::fmax(x0, x1));
+                }
+                tn[k] = a0; hit[k] = a0 <= a1 && b.child[k] != -1;
+            }
+            for (int k = 0; k < 4; ++k) if (hit[k] && b.child[k] < -1) test_leaf(~b.child[k], tmf);
+            int ord[4], m = 0;
+            for (int k = 0; k < 4; ++k) if (hit[k] && b.child[k] >= 0 && tn[k] <= tmf) ord[m++] = k;
+            for (int a = 1; a < m; ++a) for (int c = a; c > 0 && tn[ord[c]] < tn[ord[c - 1]]; --c) std::swap(ord[c], ord[c - 1]);
+            if (m > 0) {
+                for (int a = m - 1; a >= 1; --a) {
+                    if (sp < 16) { stk_n[sp] = b.child[ord[a]]; stk_t[sp] = tn[ord[a]]; ++sp; }
+                    else overflow = true;
+                }
+                cur = b.child[ord[0]];
+                continue;
+            }
+            bool found = false;
+            while (sp > 0) { --sp; if (stk_t[sp] <= tmf) { cur = stk_n[sp]; found = true; break; } }
+            if (!found) break;
+        }
+        if (overflow) {
+            ++overflows;
+            int i = 0;
+            while (i < nn) {
+                const BvhNode &bb = r.nodes[i];
+                if (!slab(bb, of, inv, tmf)) { i = as_int(bb.lo[3]); continue; }
+                const int leaf = as_int(bb.hi[3]);
+                if (leaf < 0) { ++i; continue; }
+                test_leaf(leaf, tmf);
+                i = as_int(bb.lo[3]);
+            }
+        }
+        if (hg != hb || tg != tb) ++wrong;
+    }
+    std::printf("bvh4 nodes %zu visits/ray %.2f overflows %ld wrong %ld\n", q4.size(), nrays ? (double)v4 / nrays : 0.0,
+                overflows, wrong);
+    return wrong ? 1 : 0;
 }
