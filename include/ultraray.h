@@ -185,12 +185,14 @@ UR_API ur_status ur_set_proposal(ur_context *ctx, const float *pdf_dev, const fl
 UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
 
-/* Work-size limits of later ur_trace calls: at most rays_per_launch rays are
- * traced per kernel launch, and up to nee_queue_capacity transducer-sampling
- * candidates (64 bytes each, library-owned device memory) are queued per
- * launch before their secondary rays are cast.  If a launch produces more
- * candidates than fit, that launch's range is traced again with the
- * secondary rays cast inline, so results never depend on these limits.
+/* Work-size limits of later ur_trace calls: at most min(rays_per_launch,
+ * 2^22) rays are traced per launch range, and up to nee_queue_capacity
+ * transducer-sampling candidates (72 bytes each, library-owned device
+ * memory) are queued per range before their secondary rays are cast.  If a
+ * range produces more candidates than fit, that range is traced again with
+ * the secondary rays cast inline, so results never depend on these limits.
+ * Each range also queues its primary-ray segments for the scatterer walk in
+ * library-owned memory of 96 bytes x (rays x (max_bounces + 1) + 2^18).
  * Defaults: 2^30 rays, 2^22 candidates. */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
@@ -209,11 +211,18 @@ UR_API ur_status ur_beamform(ur_context *ctx, const ur_grid_desc *grid, const fl
                              float *env_dev, float *bmode_dev, void *stream);
 
 /* Device time in milliseconds, between HIP events recorded on the call's
- * stream immediately around each kernel launch: the trace-kernel launches of
- * the last ur_trace call (summed; secondary-ray casting and pulse shaping
- * excluded) and the delay-and-sum kernel of the last ur_beamform call; -1
- * where no such call was made.  Waits for those events. */
+ * stream immediately around each kernel launch: the trace kernels of the
+ * last ur_trace call (extend + scatter, summed over launch ranges; secondary
+ * rays and pulse shaping excluded) and the delay-and-sum kernel of the last
+ * ur_beamform call; -1 where no such call was made.  Waits for those
+ * events. */
 UR_API ur_status ur_last_kernel_ms(ur_context *ctx, double *trace_ms, double *das_ms);
+
+/* The trace kernels of the last ur_trace call separately (milliseconds,
+ * summed over launch ranges): extend (emission, closest hits, interface
+ * events, direct hits), scatter (scatterer captures) and sampling (secondary
+ * rays of the captures); -1 if no call was made.  Any pointer may be NULL. */
+UR_API ur_status ur_last_trace_kernels_ms(ur_context *ctx, double *extend_ms, double *scatter_ms, double *sampling_ms);
 
 /* Test and debugging aid: traces the given host rays one by one with the
  * same device code path as ur_trace and returns their path logs (host

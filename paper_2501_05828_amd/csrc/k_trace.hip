@@ -113,6 +113,27 @@ struct LdsStack {
     int stride;
 };
 constexpr int kStack = 16;
+constexpr int kChunk = 1024;   // work items a wave takes from the range at a time (largest chunk)
+
+// Guided self-scheduling: a wavefront takes about 1/8 of its share of the
+// work still left (seen at its last grab), between 64 and kChunk items, so
+// the end of a range is shared out in small pieces.
+__device__ __forceinline__ unsigned long long guided_chunk(unsigned long long left) {
+    const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
+    const unsigned long long c = left / (8ull * waves);
+    return c < 64ull ? 64ull : (c > (unsigned long long)kChunk ? (unsigned long long)kChunk : c);
+}
+// lanes that must be waiting before a wavefront shades finished queries and
+// starts new rays (extend), or refills segments (scatter): batching the
+// divergent shading / refill code amortises it over many lanes
+#ifndef UR_BATCH_EXTEND
+#define UR_BATCH_EXTEND 32
+#endif
+#ifndef UR_BATCH_SCATTER
+#define UR_BATCH_SCATTER 16
+#endif
+constexpr int kBatchExtend = UR_BATCH_EXTEND;
+constexpr int kBatchScatter = UR_BATCH_SCATTER;
 
 // Escape-index walk over the binary tree: complete, stackless, fixed order.
 template <bool COUNT>
@@ -155,6 +176,98 @@ __device__ __forceinline__ void walk_threaded(const TraceParams &P, const double
 // the stack would overflow, the walk finishes and the escape-index walk
 // then re-visits the whole tree with the best hit so far, so the result is
 // always the exact closest hit (nearest t, lower id on ties).
+// One visit of the ordered four-wide walk: tests the four child boxes of
+// node `cur` from one 128-byte node, tests hit leaves at once, continues with
+// the nearest hit inner child and stacks the others (farthest first).
+// Popped entries whose entry distance exceeds the current best are dropped.
+// A push that finds the stack full sets `overflow` (the caller then re-walks
+// the tree with the escape-index walk).  Returns false when the walk is done.
+template <bool COUNT>
+__device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                          const CullRay &cr, float &tmf, Hit &h, int &cur, int &sp, bool &overflow,
+                                          LdsStack stk, Counters &cnt) {
+    const float4 *q = reinterpret_cast<const float4 *>(P.tnodes4 + cur);
+    const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5];
+    const int4 ch = reinterpret_cast<const int4 *>(q)[6];
+    CNT(C_TRI_NODES);
+    const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
+    const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
+    const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
+    const int C[4] = {ch.x, ch.y, ch.z, ch.w};
+    float key[4];
+    int val[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float x0 = (LX[k] - cr.ox) * cr.ix, x1 = (HX[k] - cr.ox) * cr.ix;
+        const float y0 = (LY[k] - cr.oy) * cr.iy, y1 = (HY[k] - cr.oy) * cr.iy;
+        const float z0 = (LZ[k] - cr.oz) * cr.iz, z1 = (HZ[k] - cr.oz) * cr.iz;
+        const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+        const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
+        const bool hit = tn <= tf && C[k] != -1;
+        if (hit && C[k] < -1) {
+            const int code = ~C[k];
+            for (int j = code >> 4; j < (code >> 4) + (code & 15); ++j) {
+                const int id = P.tri_id[j];
+                if (id == skip) continue;
+                CNT(C_TRI_TESTS);
+                double t;
+                if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT &&
+                    (t < h.t || (t == h.t && id < h.id))) {
+                    h.t = t;
+                    h.id = id;
+                    h.local = j;
+                    tmf = cull_tmax(t);
+                }
+            }
+        }
+        key[k] = hit && C[k] >= 0 ? tn : INFINITY;
+        val[k] = C[k];
+    }
+    // sort the four (key, child) pairs ascending: 5 compare-exchanges
+    auto cx = [&](int a, int b) {
+        if (key[b] < key[a]) {
+            const float tk = key[a];
+            key[a] = key[b];
+            key[b] = tk;
+            const int tv = val[a];
+            val[a] = val[b];
+            val[b] = tv;
+        }
+    };
+    cx(0, 1);
+    cx(2, 3);
+    cx(0, 2);
+    cx(1, 3);
+    cx(1, 2);
+#pragma unroll
+    for (int k = 3; k >= 1; --k) {
+        if (key[k] <= tmf) {
+            if (sp < kStack) {
+                stk.base[sp * stk.stride] = make_int2(val[k], __float_as_int(key[k]));
+                ++sp;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    if (key[0] <= tmf) {
+        cur = val[0];
+        return true;
+    }
+    while (sp > 0) {
+        --sp;
+        const int2 e = stk.base[sp * stk.stride];
+        if (__int_as_float(e.y) <= tmf) {
+            cur = e.x;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Complete ordered walk; the result is always the exact closest hit
+// (nearest t, lower id on ties): after a stack overflow the escape-index
+// walk re-visits the whole tree with the best hit so far.
 template <bool COUNT>
 __device__ __forceinline__ void walk_wide(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                           Hit &h, LdsStack stk, Counters &cnt) {
@@ -162,93 +275,13 @@ __device__ __forceinline__ void walk_wide(const TraceParams &P, const double *o,
     float tmf = cull_tmax(h.t);
     int sp = 0, cur = 0;
     bool overflow = false;
-    while (true) {
-        const float4 *q = reinterpret_cast<const float4 *>(P.tnodes4 + cur);
-        const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5];
-        const int4 ch = reinterpret_cast<const int4 *>(q)[6];
-        CNT(C_TRI_NODES);
-        const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
-        const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
-        const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
-        const int C[4] = {ch.x, ch.y, ch.z, ch.w};
-        float key[4];
-        int val[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float x0 = (LX[k] - cr.ox) * cr.ix, x1 = (HX[k] - cr.ox) * cr.ix;
-            const float y0 = (LY[k] - cr.oy) * cr.iy, y1 = (HY[k] - cr.oy) * cr.iy;
-            const float z0 = (LZ[k] - cr.oz) * cr.iz, z1 = (HZ[k] - cr.oz) * cr.iz;
-            const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
-            const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
-            const bool hit = tn <= tf && C[k] != -1;
-            if (hit && C[k] < -1) {
-                const int code = ~C[k];
-                for (int j = code >> 4; j < (code >> 4) + (code & 15); ++j) {
-                    const int id = P.tri_id[j];
-                    if (id == skip) continue;
-                    CNT(C_TRI_TESTS);
-                    double t;
-                    if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT &&
-                        (t < h.t || (t == h.t && id < h.id))) {
-                        h.t = t;
-                        h.id = id;
-                        h.local = j;
-                        tmf = cull_tmax(t);
-                    }
-                }
-            }
-            key[k] = hit && C[k] >= 0 ? tn : INFINITY;
-            val[k] = C[k];
-        }
-        // sort the four (key, child) pairs ascending: 5 compare-exchanges
-        auto cx = [&](int a, int b) {
-            if (key[b] < key[a]) {
-                const float tk = key[a];
-                key[a] = key[b];
-                key[b] = tk;
-                const int tv = val[a];
-                val[a] = val[b];
-                val[b] = tv;
-            }
-        };
-        cx(0, 1);
-        cx(2, 3);
-        cx(0, 2);
-        cx(1, 3);
-        cx(1, 2);
-#pragma unroll
-        for (int k = 3; k >= 1; --k) {
-            if (key[k] <= tmf) {
-                if (sp < kStack) {
-                    stk.base[sp * stk.stride] = make_int2(val[k], __float_as_int(key[k]));
-                    ++sp;
-                } else {
-                    overflow = true;
-                }
-            }
-        }
-        if (key[0] <= tmf) {
-            cur = val[0];
-            continue;
-        }
-        bool found = false;
-        while (sp > 0) {
-            --sp;
-            const int2 e = stk.base[sp * stk.stride];
-            if (__int_as_float(e.y) <= tmf) {
-                cur = e.x;
-                found = true;
-                break;
-            }
-        }
-        if (!found) break;
+    while (wide_step<COUNT>(P, o, d, skip, cr, tmf, h, cur, sp, overflow, stk, cnt)) {
     }
     if (overflow) walk_threaded<COUNT>(P, o, d, skip, cr, tmf, h, cnt);
 }
 
-template <bool COUNT>
-__device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o, const double *d, int64_t skip,
-                                           LdsStack stk, Counters &cnt) {
+// Nearest exit through the box faces (the starting candidate).
+__device__ __forceinline__ Hit box_exit(const TraceParams &P, const double *o, const double *d) {
     Hit h;
     h.t = INFINITY;
     h.face = -1;
@@ -272,7 +305,13 @@ __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o
             h.face = fi;
         }
     }
-    if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
+    return h;
+}
+
+// Spheres and planes, after the triangles (the order does not matter: the
+// nearest t wins, the lower id on ties).
+__device__ __forceinline__ void analytic_hits(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                              Hit &h) {
     for (int j = 0; j < P.n_sph; ++j) {
         double t0, t1;
         if (!sph_roots(P.sph + 4 * j, o, d, t0, t1)) continue;
@@ -296,6 +335,14 @@ __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o
             h.local = j;
         }
     }
+}
+
+template <bool COUNT>
+__device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                           LdsStack stk, Counters &cnt) {
+    Hit h = box_exit(P, o, d);
+    if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
+    analytic_hits(P, o, d, skip, h);
     return h;
 }
 
@@ -501,27 +548,80 @@ struct RayState {
     int cell;          // emission direction cell (32 x 32 grid), -1 for explicit rays
 };
 
-// Advances a primary ray by one segment (Sec. 2.3 "Ray Traversal"): closest
-// hit; scatterer captures on the segment; transport (attenuation
-// exp(-alpha f d), delay d/c, path length); then the hit: leaving the box
-// through the transducer aperture records weight x directivity into the
-// element hit, any other box exit absorbs, an impedance boundary draws
-// reflect-or-transmit (Eqs. 7-11) unless the interaction limit is reached.
-// The ray also ends past max_path (segment clipped there) or when its time
-// leaves the record window.  Returns false when the ray has ended.
-template <bool COUNT, bool LOG, int MODE>
-__device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R, LdsStack stk) {
+// Appends the segment [0, t_seg) of R to the segment queue.  Called by the
+// lanes of a wavefront that finish a closest-hit query in the same step: the
+// first of them hands out the rest of the wavefront's current chunk of slots
+// and, if that runs short, takes a new chunk of kSegChunk with one atomic for
+// the remaining lanes; each lane writes its entry.  No slot is skipped except
+// at the end of a wavefront's last chunk (marked unused by the kernel).
+__device__ __forceinline__ void push_segment(const TraceParams &P, const RayState &R, double t_seg,
+                                             volatile unsigned long long *chunk) {
+    const unsigned long long mask = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    const int n = __popcll(mask);
+    unsigned long long beg = 0, fresh = 0, rem = 0;
+    if (lane == leader) {
+        beg = chunk[0];
+        const unsigned long long end = chunk[1];
+        rem = end - beg;
+        if (rem < (unsigned long long)n) {
+            fresh = atomicAdd(P.seg_count, (unsigned long long)kSegChunk);
+            chunk[0] = fresh + (n - rem);
+            chunk[1] = fresh + kSegChunk;
+        } else {
+            chunk[0] = beg + n;
+        }
+    }
+    auto bcast = [&](unsigned long long v) {
+        const uint32_t lo = __shfl((uint32_t)v, leader), hi = __shfl((uint32_t)(v >> 32), leader);
+        return ((unsigned long long)hi << 32) | lo;
+    };
+    beg = bcast(beg);
+    fresh = bcast(fresh);
+    rem = bcast(rem);
+    const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
+    const unsigned long long slot = rank < rem ? beg + rank : fresh + (rank - rem);
+    if ((int64_t)slot >= P.seg_cap) {
+        atomicAdd(P.seg_lost, 1ull);
+        return;
+    }
+    SegEntry &E = P.segq[slot];
+    for (int k = 0; k < 3; ++k) {
+        E.o[k] = R.o[k];
+        E.d[k] = R.d[k];
+    }
+    E.w = R.w;
+    E.t = R.t;
+    E.t_seg = t_seg;
+    E.med = R.med;
+    E.seg = R.seg;
+    E.tx = R.tx;
+    E.e = R.e;
+    E.ray = R.ray;
+    E.cell = R.cell;
+}
+
+// The rest of a segment once its closest hit h is known: scatterer captures
+// on [0, t_seg) (inline, or queued for the scatter kernel when SPLIT), then
+// transport and the hit itself (see advance).  Returns false when the ray
+// has ended.
+template <bool COUNT, bool LOG, int MODE, bool SPLIT>
+__device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R,
+                                          const Hit &h, volatile unsigned long long *chunk) {
     const int b = R.seg;
     double *o = R.o, *d = R.d;
-    CNT(C_SEGMENTS);
-    const Hit h = closest_hit<COUNT>(P, o, d, R.last, stk, cnt);
     double t_seg = h.t;
     bool clipped = false;
     if (R.len + t_seg > P.max_path) {
         t_seg = P.max_path - R.len;
         clipped = true;
     }
-    scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg, R.cell);
+    if constexpr (SPLIT) {
+        if (P.n_scat > 0 && t_seg > 0.0) push_segment(P, R, t_seg, chunk);
+    } else {
+        scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg, R.cell);
+    }
     const Material M = P.mat[R.med];
     R.w *= exp(-M.ka * t_seg);
     R.t += t_seg * M.inv_c;
@@ -635,6 +735,21 @@ __device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, 
     return true;
 }
 
+// Advances a primary ray by one segment (Sec. 2.3 "Ray Traversal"): closest
+// hit; scatterer captures on the segment; transport (attenuation
+// exp(-alpha f d), delay d/c, path length); then the hit: leaving the box
+// through the transducer aperture records weight x directivity into the
+// element hit, any other box exit absorbs, an impedance boundary draws
+// reflect-or-transmit (Eqs. 7-11) unless the interaction limit is reached.
+// The ray also ends past max_path (segment clipped there) or when its time
+// leaves the record window.  Returns false when the ray has ended.
+template <bool COUNT, bool LOG, int MODE>
+__device__ bool advance(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R, LdsStack stk) {
+    CNT(C_SEGMENTS);
+    const Hit h = closest_hit<COUNT>(P, R.o, R.d, R.last, stk, cnt);
+    return after_hit<COUNT, LOG, MODE, false>(P, L, cnt, R, h, nullptr);
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void flush_counters(const TraceParams &P, Counters &cnt) {
     if constexpr (COUNT) {
@@ -651,7 +766,9 @@ __device__ __forceinline__ void flush_counters(const TraceParams &P, Counters &c
 
 // Persistent trace kernel: wavefronts refill finished lanes with the next
 // rays of the launch's work range (work item i -> transmit, element, ray with
-// the ray index fastest) until the range is exhausted.  In the overflow
+// the ray index fastest) until the range is exhausted; each wave takes the
+// range in chunks of kChunk items, so the shared counter sees one atomic per
+// chunk instead of one per refill.  In the overflow
 // re-trace mode the kernel does nothing unless the deferred run of the same
 // range overflowed the transducer-sampling queue.  The register budget is
 // capped at four wavefronts per SIMD: the loop is bound by the latency of
@@ -673,19 +790,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const unsigned long long n_range = (unsigned long long)(P.work_end - P.work_begin);
     RayState R;
     bool active = false, exhausted = false;
+    // wave-private chunk [cbeg, cend) of the range, refilled with one atomic
+    // per kChunk work items (identical in every lane of the wave)
+    unsigned long long cbeg = 0, cend = 0;
     while (true) {
         if (!exhausted) {
             const unsigned long long need = __ballot(!active);
             if (need) {
-                const int leader = __ffsll((long long)need) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(P.work_next, (unsigned long long)__popcll(need));
-                const uint32_t lo = __shfl((uint32_t)base, leader), hi = __shfl((uint32_t)(base >> 32), leader);
-                base = ((unsigned long long)hi << 32) | lo;
-                if (base >= n_range) exhausted = true;
-                if (!active) {
-                    const unsigned long long r = base + __popcll(need & ((1ull << lane) - 1ull));
-                    if (r < n_range) {
+                if (cbeg >= cend) {
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(P.work_next, (unsigned long long)kChunk);
+                    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+                    base = ((unsigned long long)hi << 32) | lo;
+                    if (base >= n_range) {
+                        exhausted = true;
+                    } else {
+                        cbeg = base;
+                        cend = base + kChunk < n_range ? base + kChunk : n_range;
+                    }
+                }
+                if (!exhausted) {
+                    const unsigned long long r = cbeg + __popcll(need & ((1ull << lane) - 1ull));
+                    if (!active && r < cend) {
                         const int64_t i = P.work_begin + (int64_t)r;
                         const int64_t q = i / P.per_el;
                         R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
@@ -700,11 +826,240 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         active = true;
                         CNT(C_RAYS);
                     }
+                    const unsigned long long served = cbeg + __popcll(need);
+                    cbeg = served < cend ? served : cend;
                 }
             }
         }
         if (__ballot(active) == 0ull) break;
         if (active) active = advance<COUNT, false, MODE>(P, L, cnt, R, stk);
+    }
+    flush_counters<COUNT>(P, cnt);
+}
+
+// Extend kernel: the primary-ray side of a launch range.  Lanes refill
+// independently (wave-private chunks of the range) and each step performs
+// one four-wide node visit of the lane's current closest-hit query; a lane
+// whose query completed shades the hit in the same step (Eqs. 7-11, direct
+// hits, termination), queues the finished segment for the scatter kernel and
+// starts its next query.  So no lane waits for the longest traversal of its
+// wavefront, and the scatterer walk runs elsewhere with its own balance.
+template <bool COUNT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_extend(TraceParams P) {
+    Counters cnt;
+    if constexpr (COUNT) {
+#pragma unroll
+        for (int k = 0; k < kNumStats; ++k) cnt.v[k] = 0;
+    }
+    const EventLog L{};
+    __shared__ int2 s_stack[kStack * 256];
+    __shared__ unsigned long long s_chunk[8];
+    if (threadIdx.x < 8) s_chunk[threadIdx.x] = 0ull;
+    __syncthreads();
+    volatile unsigned long long *chunk = s_chunk + 2 * (threadIdx.x >> 6);
+    const LdsStack stk{s_stack + threadIdx.x, 256};
+    const int lane = threadIdx.x & 63;
+    const unsigned long long n_range = (unsigned long long)(P.work_end - P.work_begin);
+    RayState R;
+    Hit h;
+    CullRay cr;
+    float tmf = 0.0f;
+    int cur = 0, sp = 0;
+    bool active = false, trav = false, overflow = false, exhausted = false;
+    unsigned long long cbeg = 0, cend = 0;
+    auto start_segment = [&]() {
+        CNT(C_SEGMENTS);
+        h = box_exit(P, R.o, R.d);
+        cr = make_cull(R.o, R.d);
+        tmf = cull_tmax(h.t);
+        cur = 0;
+        sp = 0;
+        overflow = false;
+        trav = P.n_tnodes4 > 0;
+    };
+    while (true) {
+        const unsigned long long busy = __ballot(active && trav);
+        if (!exhausted) {
+            const unsigned long long need = __ballot(!active);
+            if (need && (__popcll(need) >= kBatchExtend || busy == 0ull)) {
+                if (cbeg >= cend) {
+                    const unsigned long long want = guided_chunk(n_range > cend ? n_range - cend : 0ull);
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(P.work_next, want);
+                    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+                    base = ((unsigned long long)hi << 32) | lo;
+                    if (base >= n_range) {
+                        exhausted = true;
+                    } else {
+                        cbeg = base;
+                        cend = base + want < n_range ? base + want : n_range;
+                    }
+                }
+                if (!exhausted) {
+                    const unsigned long long r = cbeg + __popcll(need & ((1ull << lane) - 1ull));
+                    if (!active && r < cend) {
+                        const int64_t i = P.work_begin + (int64_t)r;
+                        const int64_t q = i / P.per_el;
+                        R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
+                        R.e = (int)(q % P.E);
+                        R.tx = (int)(q / P.E);
+                        emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
+                        R.t = P.tau[(int64_t)R.tx * P.E + R.e];
+                        R.len = 0.0;
+                        R.last = -1;
+                        R.med = P.top_medium;
+                        R.seg = 0;
+                        active = true;
+                        CNT(C_RAYS);
+                        start_segment();
+                    }
+                    const unsigned long long served = cbeg + __popcll(need);
+                    cbeg = served < cend ? served : cend;
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) break;
+        if (active && trav) trav = wide_step<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cur, sp, overflow, stk, cnt);
+        const unsigned long long done = __ballot(active && !trav);
+        if (__popcll(done) < kBatchExtend && __ballot(active && trav) != 0ull) continue;
+        if (active && !trav) {
+            if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
+            analytic_hits(P, R.o, R.d, R.last, h);
+            active = after_hit<COUNT, false, kDeferNee, true>(P, L, cnt, R, h, chunk);
+            if (active) start_segment();
+        }
+    }
+    // the unused tail of this wavefront's last chunk of the segment queue
+    const unsigned long long beg = chunk[0], end = chunk[1];
+    for (unsigned long long k = beg + lane; k < end; k += 64)
+        if ((int64_t)k < P.seg_cap) P.segq[k].med = -1;
+    flush_counters<COUNT>(P, cnt);
+}
+
+// Scatter kernel: captures on the queued segments (Sec. 2.3 "Transducer
+// Sampling" candidates).  Lanes refill independently from the queue; each
+// step either moves a lane's grid walk to its next cell or tests the next
+// four items of its current cell (FP32 prefilter, then the exact FP64 test),
+// with the same cell intervals as the inline walk, so each capture is found
+// exactly once.  Candidates go to the transducer-sampling queue.
+template <bool COUNT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scatter(TraceParams P) {
+    Counters cnt;
+    if constexpr (COUNT) {
+#pragma unroll
+        for (int k = 0; k < kNumStats; ++k) cnt.v[k] = 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long reserved = *P.seg_count;
+    const unsigned long long n_seg = reserved < (unsigned long long)P.seg_cap ? reserved : (unsigned long long)P.seg_cap;
+    const int limit = P.grid.n[0] + P.grid.n[1] + P.grid.n[2] + 3;
+    double o[3], d[3], w = 0.0, t = 0.0, t_seg = 0.0, tb = 0.0;
+    float of[3], df[3], taf = 0.0f, tbf = 0.0f;
+    int med = 0, seg = 0, tx = 0, e = 0, cell = 0, j = 0, j1 = 0, visited = 0;
+    uint32_t ray = 0;
+    DdaIter it;
+    bool has = false, exhausted = false;
+    unsigned long long cbeg = 0, cend = 0;
+    auto enter_cell = [&]() {
+        if (tb > it.ta) {
+            CNT(C_SCAT_CELLS);
+            j = P.cell_start[it.cell];
+            j1 = P.cell_start[it.cell + 1];
+            taf = (float)it.ta - P.pre_m;
+            tbf = (float)tb + P.pre_m;
+        } else {
+            j = j1 = 0;
+        }
+    };
+    while (true) {
+        if (!exhausted) {
+            const unsigned long long need = __ballot(!has);
+            if (need && (__popcll(need) >= kBatchScatter || need == ~0ull)) {
+                if (cbeg >= cend) {
+                    const unsigned long long want = guided_chunk(n_seg > cend ? n_seg - cend : 0ull);
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(P.seg_next, want);
+                    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+                    base = ((unsigned long long)hi << 32) | lo;
+                    if (base >= n_seg) {
+                        exhausted = true;
+                    } else {
+                        cbeg = base;
+                        cend = base + want < n_seg ? base + want : n_seg;
+                    }
+                }
+                if (!exhausted) {
+                    const unsigned long long r = cbeg + __popcll(need & ((1ull << lane) - 1ull));
+                    if (!has && r < cend) {
+                        const SegEntry &E = P.segq[r];
+                        med = E.med;
+                        if (med >= 0) {
+                            for (int k = 0; k < 3; ++k) {
+                                o[k] = E.o[k];
+                                d[k] = E.d[k];
+                                of[k] = (float)o[k];
+                                df[k] = (float)d[k];
+                            }
+                            w = E.w;
+                            t = E.t;
+                            t_seg = E.t_seg;
+                            seg = E.seg;
+                            tx = E.tx;
+                            e = E.e;
+                            ray = E.ray;
+                            cell = E.cell;
+                            it.init(P.grid, o, d);
+                            tb = it.bound(t_seg);
+                            visited = 1;
+                            enter_cell();
+                            has = true;
+                        }
+                    }
+                    const unsigned long long served = cbeg + __popcll(need);
+                    cbeg = served < cend ? served : cend;
+                }
+            }
+        }
+        if (__ballot(has) == 0ull) break;
+        if (!has) continue;
+        if (j < j1) {
+            float4 f[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                f[k] = j + k < j1 ? P.items_f[j + k] : make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+            unsigned pass = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float pf[3] = {f[k].x - of[0], f[k].y - of[1], f[k].z - of[2]};
+                const float sf = pf[0] * df[0] + pf[1] * df[1] + pf[2] * df[2];
+                const float qf[3] = {pf[0] - sf * df[0], pf[1] - sf * df[1], pf[2] - sf * df[2]};
+                if (sf >= taf && sf <= tbf && qf[0] * qf[0] + qf[1] * qf[1] + qf[2] * qf[2] <= P.pre_r2)
+                    pass |= 1u << k;
+            }
+            if constexpr (COUNT) cnt.v[C_SCAT_TESTS] += (uint32_t)min(4, j1 - j);
+            while (pass) {
+                const int jj = j + __builtin_ctz(pass);
+                pass &= pass - 1;
+                const double4 sk = P.items[jj];
+                const double p[3] = {sk.x - o[0], sk.y - o[1], sk.z - o[2]};
+                const double s = dot3(p, d);
+                if (!(s >= it.ta && s < tb)) continue;
+                const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
+                if (dot3(pp, pp) > P.r_s2) continue;
+                NeeEntry c;
+                if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[jj], sk.w, o, d, w, t, med, s, cell, c))
+                    continue;
+                const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
+                if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;
+            }
+            j += 4;
+        } else if (tb >= t_seg || visited >= limit || !it.step(P.grid, o, tb)) {
+            has = false;
+        } else {
+            tb = it.bound(t_seg);
+            ++visited;
+            enter_cell();
+        }
     }
     flush_counters<COUNT>(P, cnt);
 }
@@ -800,6 +1155,35 @@ hipError_t ur_launch_trace(const ur::TraceParams &p, bool count, int mode, hipSt
         else UR_LAUNCH(false, ur::kInlineNeeOnly);
     }
 #undef UR_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t ur_launch_extend(const ur::TraceParams &p, bool count, hipStream_t s) {
+    const int64_t needed = (p.work_end - p.work_begin + 255) / 256;
+    if (needed <= 0) return hipSuccess;
+    unsigned blocks = 0;
+    hipError_t e = count ? resident_blocks(k_extend<true>, needed, blocks) : resident_blocks(k_extend<false>, needed, blocks);
+    if (e != hipSuccess) return e;
+    if (count) hipLaunchKernelGGL(k_extend<true>, dim3(blocks), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL(k_extend<false>, dim3(blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+int64_t ur_extend_max_waves() {
+    unsigned blocks = 0;
+    if (resident_blocks(k_extend<true>, int64_t(1) << 40, blocks) != hipSuccess) return -1;
+    unsigned b2 = 0;
+    if (resident_blocks(k_extend<false>, int64_t(1) << 40, b2) != hipSuccess) return -1;
+    return 4 * (int64_t)(blocks > b2 ? blocks : b2);
+}
+
+hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s) {
+    unsigned blocks = 0;
+    const int64_t needed = (p.seg_cap + 255) / 256;
+    hipError_t e = count ? resident_blocks(k_scatter<true>, needed, blocks) : resident_blocks(k_scatter<false>, needed, blocks);
+    if (e != hipSuccess) return e;
+    if (count) hipLaunchKernelGGL(k_scatter<true>, dim3(blocks), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL(k_scatter<false>, dim3(blocks), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

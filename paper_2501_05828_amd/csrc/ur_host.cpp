@@ -55,7 +55,7 @@ struct ur_context {
     std::vector<double> angles;
     int K = 0;
     DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
-        d_nee, d_counters;
+        d_nee, d_counters, d_segq;
     int64_t rays_per_launch = int64_t(1) << 30;
     // proposal network (rows = transmits x elements of the current setup)
     bool mlp_ready = false;
@@ -66,7 +66,7 @@ struct ur_context {
     RecordEntry *rec = nullptr;
     unsigned long long *rec_count = nullptr;
     int64_t rec_cap = 0;
-    std::vector<hipEvent_t> tev;           // [2 * launches] around each trace-kernel launch
+    std::vector<hipEvent_t> tev;           // [4 * launches]: before extend, after extend, after scatter, after sampling
     int n_tev = 0;
     int64_t nee_cap = int64_t(1) << 22;
     const float *pdf = nullptr, *cdf = nullptr;
@@ -578,30 +578,60 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, st2, kNumStats);
             HIP_TRY(c, hipGetLastError());
         }
-        const int64_t launches = (P.n_work + c->rays_per_launch - 1) / c->rays_per_launch;
-        while ((int64_t)c->tev.size() < 2 * launches) {
+        // launch ranges: the segment queue between the extend and scatter
+        // kernels holds the worst case of one range (every ray using all
+        // B + 1 segments) plus one partly used chunk per wavefront.  Ranges
+        // are as long as possible (fewer kernel tails) while the queue stays
+        // within 1/8 of the device memory.
+        int64_t range = std::max<int64_t>(1, std::min<int64_t>(c->rays_per_launch, kSplitRays));
+        if (c->n_scat > 0) {
+            size_t free_b = 0, total_b = 0;
+            HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
+            const int64_t fit = (int64_t)(total_b / 8 / (sizeof(SegEntry) * (size_t)(P.B + 1)));
+            range = std::max<int64_t>(int64_t(1) << 16, std::min(range, fit));
+        }
+        if (c->n_scat > 0) {
+            const int64_t waves = ur_extend_max_waves();
+            if (waves < 0) return c->fail(UR_ERR_HIP, "occupancy query failed");
+            const int64_t cap = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1)) * (int64_t)(P.B + 1) +
+                                waves * kSegChunk;
+            if ((st = alloc(c, c->d_segq, (size_t)cap * sizeof(SegEntry)))) return st;
+            P.segq = (SegEntry *)c->d_segq.p;
+            P.seg_cap = cap;
+        }
+        const int64_t launches = (P.n_work + range - 1) / range;
+        while ((int64_t)c->tev.size() < 4 * launches) {
             hipEvent_t e;
             HIP_TRY(c, hipEventCreate(&e));
             c->tev.push_back(e);
         }
         c->n_tev = 0;
         c->trace_timed = false;
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr + 6, 1);
+        P.seg_lost = ctr + 6;
         HIP_TRY(c, hipEventRecord(c->ev[0], s));
-        // Work is launched in ranges: trace with queued transducer sampling,
-        // cast the queue, then (only if the queue overflowed) re-trace the
-        // range casting the sampling rays inline without direct hits.
-        for (int64_t begin = 0; begin < P.n_work; begin += c->rays_per_launch) {
+        // Work is launched in ranges: extend (closest hits, shading, segment
+        // queue), scatter (captures into the transducer-sampling queue), cast
+        // the sampling queue, then (only if that queue overflowed) re-trace
+        // the range casting the sampling rays inline without direct hits.
+        for (int64_t begin = 0; begin < P.n_work; begin += range) {
             P.work_begin = begin;
-            P.work_end = std::min(P.n_work, begin + c->rays_per_launch);
-            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 3);
+            P.work_end = std::min(P.n_work, begin + range);
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 6);
             HIP_TRY(c, hipGetLastError());
             P.work_next = ctr;
+            P.seg_count = ctr + 3;
+            P.seg_next = ctr + 4;
             P.stats = st1;
-            HIP_TRY(c, hipEventRecord(c->tev[2 * c->n_tev], s));
-            HIP_TRY(c, ur_launch_trace(P, stats != nullptr, kDeferNee, s));
-            HIP_TRY(c, hipEventRecord(c->tev[2 * c->n_tev + 1], s));
-            ++c->n_tev;
+            hipEvent_t *ev = &c->tev[4 * c->n_tev];
+            HIP_TRY(c, hipEventRecord(ev[0], s));
+            HIP_TRY(c, ur_launch_extend(P, stats != nullptr, s));
+            HIP_TRY(c, hipEventRecord(ev[1], s));
+            if (c->n_scat > 0) HIP_TRY(c, ur_launch_scatter(P, stats != nullptr, s));
+            HIP_TRY(c, hipEventRecord(ev[2], s));
             HIP_TRY(c, ur_launch_nee(P, stats != nullptr, s));
+            HIP_TRY(c, hipEventRecord(ev[3], s));
+            ++c->n_tev;
             TraceParams P2 = P;
             P2.work_next = ctr + 1;
             P2.stats = st2;
@@ -615,7 +645,10 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             unsigned long long h[kNumStats], h2[kNumStats];
             HIP_TRY(c, hipMemcpyAsync(h, st1, sizeof(h), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipMemcpyAsync(h2, st2, sizeof(h2), hipMemcpyDeviceToHost, s));
+            unsigned long long lost = 0;
+            HIP_TRY(c, hipMemcpyAsync(&lost, ctr + 6, sizeof(lost), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipStreamSynchronize(s));
+            if (lost) return c->fail(UR_ERR_CAPACITY, "segment queue overflow (%llu segments lost)", lost);
             // the overflow re-trace contributes only its transducer-sampling work
             uint64_t *dst = &stats->rays;
             for (int k = 0; k < kNumStats; ++k) dst[k] = h[k];
@@ -711,8 +744,8 @@ UR_API ur_status ur_last_kernel_ms(ur_context *c, double *trace_ms, double *das_
             if (c->trace_timed) {
                 double sum = 0.0;
                 for (int i = 0; i < c->n_tev; ++i) {
-                    HIP_TRY(c, hipEventSynchronize(c->tev[2 * i + 1]));
-                    HIP_TRY(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
+                    HIP_TRY(c, hipEventSynchronize(c->tev[4 * i + 2]));
+                    HIP_TRY(c, hipEventElapsedTime(&ms, c->tev[4 * i], c->tev[4 * i + 2]));
                     sum += ms;
                 }
                 *trace_ms = sum;
@@ -726,6 +759,28 @@ UR_API ur_status ur_last_kernel_ms(ur_context *c, double *trace_ms, double *das_
                 *das_ms = ms;
             }
         }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_last_trace_kernels_ms(ur_context *c, double *extend_ms, double *scatter_ms, double *sampling_ms) {
+    return guarded(c, [&]() -> ur_status {
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (!c->trace_timed) {
+            acc[0] = acc[1] = acc[2] = -1.0;
+        } else {
+            for (int i = 0; i < c->n_tev; ++i) {
+                HIP_TRY(c, hipEventSynchronize(c->tev[4 * i + 3]));
+                for (int k = 0; k < 3; ++k) {
+                    float ms = 0.f;
+                    HIP_TRY(c, hipEventElapsedTime(&ms, c->tev[4 * i + k], c->tev[4 * i + k + 1]));
+                    acc[k] += ms;
+                }
+            }
+        }
+        if (extend_ms) *extend_ms = acc[0];
+        if (scatter_ms) *scatter_ms = acc[1];
+        if (sampling_ms) *sampling_ms = acc[2];
         return UR_OK;
     });
 }

@@ -16,6 +16,8 @@ constexpr int kMaxPln = 64;
 constexpr int kCells = 1024;          // 32 x 32 emission-direction cells
 constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
 constexpr int kNumStats = 24;
+constexpr int kSegChunk = 256;   // segment-queue slots a wavefront reserves at a time
+constexpr int64_t kSplitRays = int64_t(1) << 25;   // most rays per launch range
 
 // Per-material constants, FP64: impedance, amplitude attenuation [Np/m] at
 // the centre frequency, slowness [s/m].
@@ -25,6 +27,19 @@ struct Material {
 
 // Transducer-sampling candidate: a scatterer capture whose chosen element
 // passes the receive cut-off; the secondary ray is cast by a later kernel.
+// One primary-ray segment waiting for its scatterer walk (96 bytes): the
+// state at the segment start, its length, and what the captures need.
+// med < 0 marks an unused slot.
+struct SegEntry {
+    double o[3], d[3];
+    double w, t, t_seg;
+    int med, seg, tx, e;
+    uint32_t ray;
+    int cell;
+};
+
+static_assert(sizeof(SegEntry) == 96, "segment entry layout");
+
 struct NeeEntry {
     double q[3];       // capture point on the primary segment
     double wq;         // primary weight at q times the scatterer amplitude
@@ -92,6 +107,11 @@ struct TraceParams {
     unsigned long long *stats;        // [kNumStats] or null
     unsigned long long *work_next;    // persistent-kernel work counter (zeroed before launch)
     int64_t work_begin, work_end;     // work items [begin, end) of this launch
+    SegEntry *segq;                   // segment queue between the extend and scatter kernels
+    unsigned long long *seg_count;    // slots reserved (chunks of kSegChunk)
+    unsigned long long *seg_next;     // scatter-kernel work counter
+    unsigned long long *seg_lost;     // segments that found no slot (must stay 0)
+    int64_t seg_cap;
     NeeEntry *nee;                    // transducer-sampling queue
     unsigned long long *nee_count;    // entries written (may exceed capacity)
     int64_t nee_cap;
@@ -123,6 +143,9 @@ struct DasParams {
 // kernel launchers (defined in the .hip files)
 hipError_t ur_launch_trace(const ur::TraceParams &p, bool count, int mode, hipStream_t s);
 hipError_t ur_launch_nee(const ur::TraceParams &p, bool count, hipStream_t s);
+hipError_t ur_launch_extend(const ur::TraceParams &p, bool count, hipStream_t s);
+hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s);
+int64_t ur_extend_max_waves();   // wavefronts of a full extend launch (bounds the queue's chunk slack)
 hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
                                 hipStream_t s);
 hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
