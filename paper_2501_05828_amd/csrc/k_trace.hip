@@ -586,20 +586,22 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
         atomicAdd(P.seg_lost, 1ull);
         return;
     }
+    // streaming (non-temporal) stores: the queue is read once, by another
+    // kernel, and should not displace the tree and grid from the L2
     SegEntry &E = P.segq[slot];
     for (int k = 0; k < 3; ++k) {
-        E.o[k] = R.o[k];
-        E.d[k] = R.d[k];
+        __builtin_nontemporal_store(R.o[k], &E.o[k]);
+        __builtin_nontemporal_store(R.d[k], &E.d[k]);
     }
-    E.w = R.w;
-    E.t = R.t;
-    E.t_seg = t_seg;
-    E.med = R.med;
-    E.seg = R.seg;
-    E.tx = R.tx;
-    E.e = R.e;
-    E.ray = R.ray;
-    E.cell = R.cell;
+    __builtin_nontemporal_store(R.w, &E.w);
+    __builtin_nontemporal_store(R.t, &E.t);
+    __builtin_nontemporal_store(t_seg, &E.t_seg);
+    __builtin_nontemporal_store(R.med, &E.med);
+    __builtin_nontemporal_store(R.seg, &E.seg);
+    __builtin_nontemporal_store(R.tx, &E.tx);
+    __builtin_nontemporal_store(R.e, &E.e);
+    __builtin_nontemporal_store(R.ray, &E.ray);
+    __builtin_nontemporal_store(R.cell, &E.cell);
 }
 
 // The rest of a segment once its closest hit h is known: scatterer captures
@@ -932,7 +934,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // the unused tail of this wavefront's last chunk of the segment queue
     const unsigned long long beg = chunk[0], end = chunk[1];
     for (unsigned long long k = beg + lane; k < end; k += 64)
-        if ((int64_t)k < P.seg_cap) P.segq[k].med = -1;
+        if ((int64_t)k < P.seg_cap) __builtin_nontemporal_store(-1, &P.segq[k].med);
     flush_counters<COUNT>(P, cnt);
 }
 
@@ -992,22 +994,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     const unsigned long long r = cbeg + __popcll(need & ((1ull << lane) - 1ull));
                     if (!has && r < cend) {
                         const SegEntry &E = P.segq[r];
-                        med = E.med;
+                        med = __builtin_nontemporal_load(&E.med);
                         if (med >= 0) {
                             for (int k = 0; k < 3; ++k) {
-                                o[k] = E.o[k];
-                                d[k] = E.d[k];
+                                o[k] = __builtin_nontemporal_load(&E.o[k]);
+                                d[k] = __builtin_nontemporal_load(&E.d[k]);
                                 of[k] = (float)o[k];
                                 df[k] = (float)d[k];
                             }
-                            w = E.w;
-                            t = E.t;
-                            t_seg = E.t_seg;
-                            seg = E.seg;
-                            tx = E.tx;
-                            e = E.e;
-                            ray = E.ray;
-                            cell = E.cell;
+                            w = __builtin_nontemporal_load(&E.w);
+                            t = __builtin_nontemporal_load(&E.t);
+                            t_seg = __builtin_nontemporal_load(&E.t_seg);
+                            seg = __builtin_nontemporal_load(&E.seg);
+                            tx = __builtin_nontemporal_load(&E.tx);
+                            e = __builtin_nontemporal_load(&E.e);
+                            ray = __builtin_nontemporal_load(&E.ray);
+                            cell = __builtin_nontemporal_load(&E.cell);
                             it.init(P.grid, o, d);
                             tb = it.bound(t_seg);
                             visited = 1;
@@ -1022,6 +1024,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         if (__ballot(has) == 0ull) break;
         if (!has) continue;
+        // the next four items of the current cell, then (once the cell is
+        // exhausted) the move to the next cell, in the same step
         if (j < j1) {
             float4 f[4];
 #pragma unroll
@@ -1053,12 +1057,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;
             }
             j += 4;
-        } else if (tb >= t_seg || visited >= limit || !it.step(P.grid, o, tb)) {
-            has = false;
-        } else {
-            tb = it.bound(t_seg);
-            ++visited;
-            enter_cell();
+        }
+        if (j >= j1) {
+            if (tb >= t_seg || visited >= limit || !it.step(P.grid, o, tb)) {
+                has = false;
+            } else {
+                tb = it.bound(t_seg);
+                ++visited;
+                enter_cell();
+            }
         }
     }
     flush_counters<COUNT>(P, cnt);
