@@ -232,6 +232,73 @@ std::vector<Bvh4Node> collapse_bvh4(const std::vector<BvhNode> &nodes) {
     return std::move(c.out);
 }
 
+namespace {
+
+// fl(o + q * 2^(e - 127)) in FP32: the product is exact, the sum rounds once
+float decode1(float o, int q, int e) {
+    volatile float prod = std::ldexp((float)q, e - 127);
+    volatile float sum = o + prod;
+    return sum;
+}
+
+}  // namespace
+
+void decode_bvh4q(const Bvh4NodeQ &n, int k, float lo[3], float hi[3]) {
+    int ebits;
+    std::memcpy(&ebits, &n.org[3], sizeof(int));
+    for (int a = 0; a < 3; ++a) {
+        const int e = (ebits >> (8 * a)) & 255;
+        lo[a] = decode1(n.org[a], n.q[4 * a + k], e);
+        hi[a] = decode1(n.org[a], n.q[12 + 4 * a + k], e);
+    }
+}
+
+std::vector<Bvh4NodeQ> quantize_bvh4(const std::vector<Bvh4Node> &nodes) {
+    std::vector<Bvh4NodeQ> out(nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Bvh4Node &n = nodes[i];
+        Bvh4NodeQ &q = out[i];
+        std::memset(&q, 0, sizeof(q));
+        const float *L[3] = {n.lo_x, n.lo_y, n.lo_z}, *H[3] = {n.hi_x, n.hi_y, n.hi_z};
+        int ebits = 0;
+        for (int a = 0; a < 3; ++a) {
+            float ulo = INFINITY, uhi = -INFINITY;
+            for (int k = 0; k < 4; ++k)
+                if (n.child[k] != -1) {
+                    ulo = std::min(ulo, L[a][k]);
+                    uhi = std::max(uhi, H[a][k]);
+                }
+            if (!(ulo <= uhi)) ulo = uhi = 0.0f;   // no children (never for a built tree)
+            const float o = std::nextafter(ulo, -INFINITY);
+            q.org[a] = o;
+            // smallest step 2^(e-127) with 254 steps covering the extent (one
+            // step of room for the outward rounding)
+            int e = 1;
+            while (e < 254 && (double)std::ldexp(1.0f, e - 127) * 254.0 < (double)uhi - (double)o) ++e;
+            ebits |= e << (8 * a);
+            for (int k = 0; k < 4; ++k) {
+                if (n.child[k] == -1) {
+                    q.q[4 * a + k] = 255;
+                    q.q[12 + 4 * a + k] = 0;
+                    continue;
+                }
+                const double s = std::ldexp(1.0, e - 127);
+                int lo_q = (int)std::floor(((double)L[a][k] - (double)o) / s);
+                int hi_q = (int)std::ceil(((double)H[a][k] - (double)o) / s);
+                lo_q = std::max(0, std::min(255, lo_q));
+                hi_q = std::max(0, std::min(255, hi_q));
+                while (lo_q > 0 && decode1(o, lo_q, e) > L[a][k]) --lo_q;
+                while (hi_q < 255 && decode1(o, hi_q, e) < H[a][k]) ++hi_q;
+                q.q[4 * a + k] = (unsigned char)lo_q;
+                q.q[12 + 4 * a + k] = (unsigned char)hi_q;
+            }
+        }
+        std::memcpy(&q.org[3], &ebits, sizeof(int));
+        for (int k = 0; k < 4; ++k) q.child[k] = n.child[k];
+    }
+    return out;
+}
+
 BvhResult build_bvh(const std::vector<PrimBounds> &prims, int leaf_max, double dilate) {
     Builder b(prims, std::min(15, std::max(1, leaf_max)), dilate);
     if (!prims.empty()) b.emit(0, (int)prims.size(), 0);

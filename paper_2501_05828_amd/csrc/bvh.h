@@ -29,4 +29,10 @@ BvhResult build_bvh(const std::vector<PrimBounds> &prims, int leaf_max, double d
 // primitive order are unchanged.  Empty for an empty tree.
 std::vector<Bvh4Node> collapse_bvh4(const std::vector<BvhNode> &nodes);
 
+// Quantises four-wide nodes to the 64-byte layout (conservative decode).
+std::vector<Bvh4NodeQ> quantize_bvh4(const std::vector<Bvh4Node> &nodes);
+
+// FP32 decode of child k of a quantised node, as the device evaluates it.
+void decode_bvh4q(const Bvh4NodeQ &n, int k, float lo[3], float hi[3]);
+
 }  // namespace ur

@@ -29,4 +29,19 @@ struct alignas(16) Bvh4Node {
     int pad[4];
 };
 
+// The same node quantised to 64 bytes (half a cache line): child boxes are
+// 8-bit offsets from the node origin in steps of a power of two per axis,
+//   lo = origin + qlo * 2^(e - 127),  hi = origin + qhi * 2^(e - 127),
+// rounded outward so that, evaluated in FP32 (the product is exact, the sum
+// rounds once), every decoded box contains the FP32 box it replaces.
+//   org = (origin.x, origin.y, origin.z, ex | ey << 8 | ez << 16 as int bits)
+//   q[0..3] = qlo_x, q[4..7] = qlo_y, q[8..11] = qlo_z,
+//   q[12..15] = qhi_x, q[16..19] = qhi_y, q[20..23] = qhi_z (child k at +k)
+struct alignas(16) Bvh4NodeQ {
+    float org[4];
+    unsigned char q[32];
+    int child[4];
+};
+static_assert(sizeof(Bvh4NodeQ) == 64, "quantised node layout");
+
 }  // namespace ur

@@ -177,7 +177,7 @@ __device__ __forceinline__ void walk_threaded(const TraceParams &P, const double
 // then re-visits the whole tree with the best hit so far, so the result is
 // always the exact closest hit (nearest t, lower id on ties).
 // One visit of the ordered four-wide walk: tests the four child boxes of
-// node `cur` from one 128-byte node, tests hit leaves at once, continues with
+// node `cur` from one 64-byte quantised node, tests hit leaves at once, continues with
 // the nearest hit inner child and stacks the others (farthest first).
 // Popped entries whose entry distance exceeds the current best are dropped.
 // A push that finds the stack full sets `overflow` (the caller then re-walks
@@ -186,21 +186,27 @@ template <bool COUNT>
 __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                           const CullRay &cr, float &tmf, Hit &h, int &cur, int &sp, bool &overflow,
                                           LdsStack stk, Counters &cnt) {
-    const float4 *q = reinterpret_cast<const float4 *>(P.tnodes4 + cur);
-    const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5];
-    const int4 ch = reinterpret_cast<const int4 *>(q)[6];
+    const uint4 *q = reinterpret_cast<const uint4 *>(P.tnodes4 + cur);
+    const uint4 org = q[0], w0 = q[1], w1 = q[2];
+    const int4 ch = reinterpret_cast<const int4 *>(q)[3];
     CNT(C_TRI_NODES);
-    const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
-    const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
-    const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
+    // child box planes as t = q * (step * inv) + (origin - o) * inv per axis
+    const float sx = __int_as_float((int)((org.w & 255u) << 23)), sy = __int_as_float((int)(((org.w >> 8) & 255u) << 23));
+    const float sz = __int_as_float((int)(((org.w >> 16) & 255u) << 23));
+    const float ax = sx * cr.ix, ay = sy * cr.iy, az = sz * cr.iz;
+    const float bx = (__uint_as_float(org.x) - cr.ox) * cr.ix, by = (__uint_as_float(org.y) - cr.oy) * cr.iy;
+    const float bz = (__uint_as_float(org.z) - cr.oz) * cr.iz;
     const int C[4] = {ch.x, ch.y, ch.z, ch.w};
     float key[4];
     int val[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float x0 = (LX[k] - cr.ox) * cr.ix, x1 = (HX[k] - cr.ox) * cr.ix;
-        const float y0 = (LY[k] - cr.oy) * cr.iy, y1 = (HY[k] - cr.oy) * cr.iy;
-        const float z0 = (LZ[k] - cr.oz) * cr.iz, z1 = (HZ[k] - cr.oz) * cr.iz;
+        const float x0 = fmaf((float)((w0.x >> (8 * k)) & 255u), ax, bx);
+        const float y0 = fmaf((float)((w0.y >> (8 * k)) & 255u), ay, by);
+        const float z0 = fmaf((float)((w0.z >> (8 * k)) & 255u), az, bz);
+        const float x1 = fmaf((float)((w0.w >> (8 * k)) & 255u), ax, bx);
+        const float y1 = fmaf((float)((w1.x >> (8 * k)) & 255u), ay, by);
+        const float z1 = fmaf((float)((w1.y >> (8 * k)) & 255u), az, bz);
         const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
         const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
         const bool hit = tn <= tf && C[k] != -1;

@@ -201,7 +201,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.tri_mat = (const int *)c->d_tri_mat.p;
     P.tri_id = (const int *)c->d_tri_id.p;
     P.tnodes = (const BvhNode *)c->d_tnodes.p;
-    P.tnodes4 = (const Bvh4Node *)c->d_tnodes4.p;
+    P.tnodes4 = (const Bvh4NodeQ *)c->d_tnodes4.p;
     P.n_tnodes4 = c->n_tnodes4;
     P.n_tri = (int)c->n_tri;
     P.n_tnodes = c->n_tnodes;
@@ -368,7 +368,7 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                 tid[k] = o;
             }
             c->n_tnodes = (int)r.nodes.size();
-            const std::vector<Bvh4Node> wide = collapse_bvh4(r.nodes);
+            const std::vector<Bvh4NodeQ> wide = quantize_bvh4(collapse_bvh4(r.nodes));
             c->n_tnodes4 = (int)wide.size();
             if ((st = upload(c, c->d_tnodes4, wide))) return st;
             if ((st = upload(c, c->d_tri, tri))) return st;

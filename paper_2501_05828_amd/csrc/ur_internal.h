@@ -90,7 +90,7 @@ struct TraceParams {
     const int *tri_mat;               // [n_tri][2]
     const int *tri_id;                // original index (tie-break, exclusion)
     const BvhNode *tnodes;            // threaded binary tree (any-hit walks, fallback)
-    const Bvh4Node *tnodes4;          // four-wide tree (closest hit)
+    const Bvh4NodeQ *tnodes4;         // four-wide tree, quantised (closest hit)
     int n_tri, n_tnodes, n_tnodes4;
     // scatterers: uniform grid, items grouped by cell (copies of position +
     // amplitude, and the original index that keys the RNG counter)

@@ -170,6 +170,25 @@ int main(int argc, char **argv) {
         }
     }
     if (n4 != (int)q4.size()) { std::puts("unreachable bvh4 nodes"); return 1; }
+    // quantised nodes: every decoded child box contains the FP32 box
+    const std::vector<Bvh4NodeQ> qq = collapse_bvh4(r.nodes).empty() ? std::vector<Bvh4NodeQ>() : quantize_bvh4(q4);
+    for (size_t i = 0; i < qq.size(); ++i)
+        for (int k = 0; k < 4; ++k) {
+            if (q4[i].child[k] == -1) continue;
+            float dl[3], dh[3];
+            decode_bvh4q(qq[i], k, dl, dh);
+            const float bl[3] = {q4[i].lo_x[k], q4[i].lo_y[k], q4[i].lo_z[k]}, bh[3] = {q4[i].hi_x[k], q4[i].hi_y[k], q4[i].hi_z[k]};
+            for (int a = 0; a < 3; ++a)
+                if (!(dl[a] <= bl[a] && dh[a] >= bh[a]) || qq[i].child[k] != q4[i].child[k]) {
+                    std::printf("quantised box %zu/%d axis %d does not contain the node box\n", i, k, a); return 1;
+                }
+            int ebits;
+            std::memcpy(&ebits, &qq[i].org[3], sizeof(int));
+            for (int a = 0; a < 3; ++a) {   // and stays within three steps of it
+                const double step = std::ldexp(1.0, ((ebits >> (8 * a)) & 255) - 127);
+                if ((double)dh[a] - dl[a] > (double)bh[a] - bl[a] + 3.0 * step) { std::puts("quantised box too loose"); return 1; }
+            }
+        }
     for (long i = 0; i < n; ++i) if (seen4[i] != 1) { std::printf("bvh4: prim %ld seen %d times\n", i, seen4[i]); return 1; }
     // ---- ordered closest hit with a 16-entry stack vs brute force
     std::mt19937_64 g2(std::atol(argv[7]) + 1);
@@ -202,7 +221,8 @@ int main(int argc, char **argv) {
             ++v4;
             float tn[4]; bool hit[4];
             for (int k = 0; k < 4; ++k) {
-                const float bl[3] = {b.lo_x[k], b.lo_y[k], b.lo_z[k]}, bh[3] = {b.hi_x[k], b.hi_y[k], b.hi_z[k]};
+                float bl[3], bh[3];
+                decode_bvh4q(qq[cur], k, bl, bh);
                 float a0 = 0.0f, a1 = tmf;
                 for (int j = 0; j < 3; ++j) {
                     const float x0 = (bl[j] - of[j]) * inv[j], x1 = (bh[j] - of[j]) * inv[j];
