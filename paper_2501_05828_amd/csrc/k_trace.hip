@@ -127,10 +127,10 @@ __device__ __forceinline__ unsigned long long guided_chunk(unsigned long long le
 // starts new rays (extend), or refills segments (scatter): batching the
 // divergent shading / refill code amortises it over many lanes
 #ifndef UR_BATCH_EXTEND
-#define UR_BATCH_EXTEND 32
+#define UR_BATCH_EXTEND 24
 #endif
 #ifndef UR_BATCH_SCATTER
-#define UR_BATCH_SCATTER 16
+#define UR_BATCH_SCATTER 32
 #endif
 constexpr int kBatchExtend = UR_BATCH_EXTEND;
 constexpr int kBatchScatter = UR_BATCH_SCATTER;

@@ -600,6 +600,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             P.seg_cap = cap;
         }
         const int64_t launches = (P.n_work + range - 1) / range;
+        if (launches > 1) range = (P.n_work + launches - 1) / launches;   // equal ranges
         while ((int64_t)c->tev.size() < 4 * launches) {
             hipEvent_t e;
             HIP_TRY(c, hipEventCreate(&e));
