@@ -7,12 +7,15 @@ and bin every ray, pulse-shape the channel data, delay-and-sum to a 512x512
 compounded image, envelope and log compression.  Inputs are resident on the
 GPU before timing starts; each step draws a fresh Philox key.
 
-Prints one JSON line.  The roofline entry is for the trace kernel (the
-dominant kernel): algorithmic FLOPs of one launch (per-unit costs below x
+Prints one JSON line.  The roofline entry is for the extend kernel (the
+dominant kernel of the trace): algorithmic FLOPs (per-unit costs below x
 unit counts from an instrumented pass over the same workload) divided by its
-average duration, measured with HIP events that the library records on the
-stream it launches on.  The CPU baseline is the FP64 oracle timed on a
-bounded, evenly strided sample of the same rays.
+duration, both per frame; a frame launches the kernel once per launch range
+of equal size, so this equals FLOPs per launch over the average launch
+duration.  Durations come from HIP events that the library records on the
+stream it launches on.  The scatter kernel is reported beside it.  The CPU
+baseline is the FP64 oracle timed on a bounded, evenly strided sample of the
+same rays.
 """
 from __future__ import annotations
 
@@ -31,33 +34,37 @@ PEAK_FP32 = 157.3e12      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk 
 PEAK_FP64 = 78.6e12       # MI355X vector FP64 (256 CU x 2.4 GHz x 128 FLOP/clk)
 PEAK_HBM = 8.0e12
 
-# Algorithmic FLOPs per counted unit of the trace kernel (add/sub/mul = 1,
-# fma = 2, div/sqrt/exp/acos = 1; compares, min/max and integer RNG work are
-# not counted).  Only the part of each test that always executes is counted.
-FP32_PER_NODE = 48          # four-wide node: four slab tests of 6 sub + 6 mul
-FP64_PER_CELL = 4           # DDA step: next crossing (fma) + advance
+# Algorithmic FLOPs per counted unit (add/sub/mul = 1, fma = 2,
+# div/sqrt/exp/acos = 1; compares, min/max and integer RNG work are not
+# counted).  Only the part of each test that always executes is counted.
+# Extend kernel (emission, closest hits, interfaces):
+FP32_PER_NODE = 48          # four-wide node: four slab tests of 6 fma (child planes from 8-bit offsets)
 FP64_PER_TRI_TEST = 24      # Moller-Trumbore up to the first barycentric test
-FP64_PER_SCAT_TEST = 8      # projection of the scatterer on the segment
 FP64_PER_SEGMENT = 16       # box exit (6) + transport (10)
-FP64_PER_PLANE = 12         # per plane per segment / secondary ray
-FP64_PER_SPHERE = 20        # per sphere per segment / secondary ray
+FP64_PER_PLANE = 12         # per plane per segment
+FP64_PER_SPHERE = 20        # per sphere per segment
 FP64_PER_INTERFACE = 60     # normal, Eqs. 7-11, new direction, renormalisation
-FP64_PER_EVENT = 25         # projection point, element choice geometry, directivity
 FP64_PER_RAY = 40           # emission: origin, hemisphere map, weight
+# Scatter kernel (captures):
+FP64_PER_CELL = 4           # grid walk step: next crossing (fma) + advance
+FP32_PER_SCAT_TEST = 16     # FP32 prefilter: offset (3), projection, perpendicular and its length (fma)
+FP64_PER_EVENT = 33         # exact capture test (8) + projection point, element geometry, directivity (25)
 
 
-def trace_flops(st, n_pln, n_sph):
-    """FLOPs of the trace kernel proper (the secondary rays are cast by a
-    separate kernel and are excluded)."""
+def extend_flops(st, n_pln, n_sph):
+    """FP32 and FP64 FLOPs of the extend kernel for one frame."""
     f32 = FP32_PER_NODE * st["tri_nodes"]
     f64 = (FP64_PER_TRI_TEST * st["tri_tests"]
-           + FP64_PER_CELL * st["scat_cells"]
-           + FP64_PER_SCAT_TEST * st["scat_tests"]
            + st["segments"] * (FP64_PER_SEGMENT + FP64_PER_PLANE * n_pln + FP64_PER_SPHERE * n_sph)
            + FP64_PER_INTERFACE * (st["reflect"] + st["transmit"] + st["tir"])
-           + FP64_PER_EVENT * st["scatter_events"]
            + FP64_PER_RAY * st["rays"])
     return float(f32), float(f64)
+
+
+def scatter_flops(st):
+    """FP32 and FP64 FLOPs of the scatter kernel for one frame."""
+    return (float(FP32_PER_SCAT_TEST * st["scat_tests"]),
+            float(FP64_PER_CELL * st["scat_cells"] + FP64_PER_EVENT * st["scatter_events"]))
 
 
 TRACE_SOURCES = ["k_trace.hip", "trace_device.h", "scatter_grid.h", "bvh_layout.h", "philox.h", "ur_internal.h"]
@@ -74,8 +81,9 @@ def kernel_hash():
 
 
 def load_traffic(workload, n_launch_bytes_hint=None):
-    """HBM bytes per trace launch from committed rocprofv3 PMC summaries, or
-    None if absent or taken on a different kernel source."""
+    """HBM bytes of the extend kernel per frame (summed over its launch
+    ranges) from the committed rocprofv3 PMC summary, or None if absent or
+    taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", f"pmc_trace_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -249,32 +257,38 @@ def main():
     n_rays = acq.n_rays
     print(f"[bench] {w.name}: {n_rays:.3e} rays/frame, grid {grid.nx}x{grid.nz}", file=sys.stderr, flush=True)
 
-    # instrumented pass: unit counts for the algorithmic FLOPs of one launch
+    # instrumented pass: unit counts for the algorithmic FLOPs of one frame
     st = sim.trace(seed=w.seed, stats=True)
-    f32, f64 = trace_flops(st, len(w.scene.pln), len(w.scene.sph))
+    xf32, xf64 = extend_flops(st, len(w.scene.pln), len(w.scene.sph))
+    sf32, sf64 = scatter_flops(st)
     print(f"[bench] counting pass: {st['kernel_ms']:.1f} ms, records {st['records']}", file=sys.stderr, flush=True)
     print(f"[bench] counts {json.dumps(st)}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         sim.step(seed=w.seed + 1000 + i)
     torch.cuda.synchronize()
-    trace_ms, das_ms = [], []
+    trace_ms, das_ms, ext_ms, sca_ms = [], [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
         sim.step(seed=w.seed + i)
         tm, dm = sim.kernel_ms()
+        xm, sm, _, launches = sim.ctx.ur_last_trace_kernels_ms()
         trace_ms.append(tm)
         das_ms.append(dm)
+        ext_ms.append(xm)
+        sca_ms.append(sm)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
-    t_trace = sum(trace_ms) / len(trace_ms) * 1e-3
-    t_das = sum(das_ms) / len(das_ms) * 1e-3
-    print(f"[bench] {ms_step:.1f} ms/step, trace kernel {1e3 * t_trace:.1f} ms, DAS {1e3 * t_das:.3f} ms",
-          file=sys.stderr, flush=True)
+    mean = lambda v: sum(v) / len(v) * 1e-3
+    t_trace, t_das, t_ext, t_sca = mean(trace_ms), mean(das_ms), mean(ext_ms), mean(sca_ms)
+    print(f"[bench] {ms_step:.1f} ms/step, trace {1e3 * t_trace:.1f} ms (extend {1e3 * t_ext:.1f}, "
+          f"scatter {1e3 * t_sca:.1f}), DAS {1e3 * t_das:.3f} ms", file=sys.stderr, flush=True)
 
-    achieved = (f32 + f64) / t_trace
-    peak = (f32 + f64) / (f32 / PEAK_FP32 + f64 / PEAK_FP64)
+    # roofline of the dominant kernel (extend): FLOPs of one frame over its
+    # launch time summed over the frame's launch ranges
+    achieved = (xf32 + xf64) / t_ext
+    peak = (xf32 + xf64) / (xf32 / PEAK_FP32 + xf64 / PEAK_FP64)
     traffic = load_traffic(w.name)
     out = {
         "metric": METRIC,
@@ -302,17 +316,27 @@ def main():
         "frames_per_s": args.steps / elapsed,
         "das_frames_per_s": 1.0 / t_das,
         "trace_kernel_ms": 1e3 * t_trace,
+        "extend_kernel_ms": 1e3 * t_ext,
+        "scatter_kernel_ms": 1e3 * t_sca,
         "das_kernel_ms": 1e3 * t_das,
         "roofline": {
-            "kernel": "k_trace",
+            "kernel": "k_extend",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": traffic,
-            "flops_fp32": f32,
-            "flops_fp64": f64,
+            "flops_fp32": xf32,
+            "flops_fp64": xf64,
+            "launches_per_frame": launches,
+            "kernel_ms_per_launch": 1e3 * t_ext / launches,
+        },
+        "scatter_kernel": {
+            "ms": 1e3 * t_sca,
+            "achieved_tflops": (sf32 + sf64) / t_sca / 1e12 if t_sca > 0 else None,
+            "flops_fp32": sf32,
+            "flops_fp64": sf64,
         },
     }
     if not args.no_cpu_baseline:

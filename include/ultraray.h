@@ -221,8 +221,11 @@ UR_API ur_status ur_last_kernel_ms(ur_context *ctx, double *trace_ms, double *da
 /* The trace kernels of the last ur_trace call separately (milliseconds,
  * summed over launch ranges): extend (emission, closest hits, interface
  * events, direct hits), scatter (scatterer captures) and sampling (secondary
- * rays of the captures); -1 if no call was made.  Any pointer may be NULL. */
-UR_API ur_status ur_last_trace_kernels_ms(ur_context *ctx, double *extend_ms, double *scatter_ms, double *sampling_ms);
+ * rays of the captures); -1 if no call was made.  launches receives the
+ * number of launch ranges (each kernel ran once per range).  Any pointer may
+ * be NULL. */
+UR_API ur_status ur_last_trace_kernels_ms(ur_context *ctx, double *extend_ms, double *scatter_ms, double *sampling_ms,
+                                          int64_t *launches);
 
 /* Test and debugging aid: traces the given host rays one by one with the
  * same device code path as ur_trace and returns their path logs (host

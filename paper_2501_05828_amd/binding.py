@@ -96,7 +96,7 @@ SIGNATURES = [
     ("ur_pulse", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_last_kernel_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double)]),
-    ("ur_last_trace_kernels_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double), P(C.c_double)]),
+    ("ur_last_trace_kernels_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int64)]),
     ("ur_trace_rays", C.c_int, [_CTX, C.c_uint64, P(Ray), C.c_int64, P(Event), C.c_int64, P(C.c_int64),
                                 C.c_void_p, C.c_void_p]),
     ("ur_philox", C.c_int, [_CTX, P(C.c_uint32), C.c_int64, C.c_uint32, C.c_uint32, P(C.c_uint32)]),
@@ -288,10 +288,11 @@ class Context:
         return a.value, b.value
 
     def ur_last_trace_kernels_ms(self):
-        a, b, c = C.c_double(), C.c_double(), C.c_double()
-        self.check(self.lib.ur_last_trace_kernels_ms(self.h, C.byref(a), C.byref(b), C.byref(c)),
+        """(extend_ms, scatter_ms, sampling_ms, launch_ranges) of the last trace."""
+        a, b, c, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        self.check(self.lib.ur_last_trace_kernels_ms(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)),
                    "ur_last_trace_kernels_ms")
-        return a.value, b.value, c.value
+        return a.value, b.value, c.value, n.value
 
     def ur_trace_rays(self, seed, rays, cap=4096, ch_raw=None, stream=None):
         arr = (Ray * max(1, len(rays)))()

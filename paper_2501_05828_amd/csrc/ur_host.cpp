@@ -764,7 +764,8 @@ UR_API ur_status ur_last_kernel_ms(ur_context *c, double *trace_ms, double *das_
     });
 }
 
-UR_API ur_status ur_last_trace_kernels_ms(ur_context *c, double *extend_ms, double *scatter_ms, double *sampling_ms) {
+UR_API ur_status ur_last_trace_kernels_ms(ur_context *c, double *extend_ms, double *scatter_ms, double *sampling_ms,
+                                          int64_t *launches) {
     return guarded(c, [&]() -> ur_status {
         double acc[3] = {0.0, 0.0, 0.0};
         if (!c->trace_timed) {
@@ -782,6 +783,7 @@ UR_API ur_status ur_last_trace_kernels_ms(ur_context *c, double *extend_ms, doub
         if (extend_ms) *extend_ms = acc[0];
         if (scatter_ms) *scatter_ms = acc[1];
         if (sampling_ms) *sampling_ms = acc[2];
+        if (launches) *launches = c->trace_timed ? c->n_tev : 0;
         return UR_OK;
     });
 }
