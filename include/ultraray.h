@@ -279,9 +279,29 @@ UR_API ur_status ur_mlp_proposal_tables(ur_context *ctx, float eps, float *pdf_d
  * records that did not fit).  rec_dev = NULL stops recording. */
 UR_API ur_status ur_set_record(ur_context *ctx, void *rec_dev, int64_t cap, unsigned long long *count_dev);
 
+/* Path-cost histogram for a cost-aware proposal: while cost_dev (device,
+ * float [rows][1024], zeroed by the caller) is set, every primary ray of
+ * later ur_trace calls adds its cost to the cell it was emitted in, with
+ * cost = four-wide node visits + 2 per segment + 1.5 per scatterer-grid
+ * cell edge of path length (a model of the time the ray takes in the
+ * extend and scatter kernels).  NULL stops it. */
+UR_API ur_status ur_set_cost_histogram(ur_context *ctx, float *cost_dev);
+
+/* Cost-aware training target: replaces the |c| of every record in
+ * rec_dev[0, n_rec) by c^2 / sqrt(S2 x mean cost) of its bin, where S2 is
+ * the sum of c^2 over the bin's records and mean cost = cost_dev[bin] x 1024
+ * / rays_per_row (uniform emission gives each cell rays_per_row / 1024 rays
+ * in expectation).  The minibatch histograms of ur_record_histogram then
+ * have expectation proportional to sqrt(S2 / mean cost) per cell, the
+ * emission density that minimises variance x time for the recorded paths
+ * (importance sampling with per-sample cost).  Async. */
+UR_API ur_status ur_record_reweight(ur_context *ctx, void *rec_dev, int64_t n_rec, const float *cost_dev,
+                                    double rays_per_row, void *stream);
+
 /* Minibatch target: hist_dev [rows][1024] is zeroed, then `batch` records
  * drawn uniformly with replacement from rec_dev[0, n_rec) (Philox with key
- * `seed`, counter (draw, step)) add their |c| to their bins. */
+ * `seed`, counter (draw, step)) add their value (|c|, or the weight set by
+ * ur_record_reweight) to their bins. */
 UR_API ur_status ur_record_histogram(ur_context *ctx, const void *rec_dev, int64_t n_rec, int64_t batch,
                                      uint64_t seed, uint32_t step, float *hist_dev, void *stream);
 
@@ -320,6 +340,9 @@ UR_API ur_status ur_beamform_adjoint(ur_context *ctx, const ur_grid_desc *grid, 
  *                                   (at most 8 materials)
  *   Z          double [n_mat]       dL/d acoustic impedance [per MRayl]
  *   sph_center double [n_sph][3]    dL/d sphere centre coordinates [per m]
+ *   value      double [1]           J = sum of g(t) c over the contributions,
+ *                                   accumulated in FP64 (the functional whose
+ *                                   derivatives the other outputs are)
  * frozen_choice = 0: the reflect-or-transmit choice of Eqs. 7-11 keeps its
  * probability attached to the weight (R / value(R), (1 - R) / value(1 - R)),
  * which adds the derivative of the choice probability (the gradient of the
@@ -330,6 +353,7 @@ typedef struct ur_grad_desc {
     double *alpha;
     double *Z;
     double *sph_center;
+    double *value;          /* [1] or NULL: J = sum g(t) c over the replayed contributions (FP64) */
     int32_t frozen_choice;
 } ur_grad_desc;
 

@@ -75,7 +75,7 @@ class Ray(C.Structure):
 
 class GradDesc(C.Structure):
     _fields_ = [("amp", C.c_void_p), ("alpha", C.c_void_p), ("Z", C.c_void_p), ("sph_center", C.c_void_p),
-                ("frozen_choice", C.c_int32)]
+                ("value", C.c_void_p), ("frozen_choice", C.c_int32)]
 
 
 EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end"}
@@ -109,6 +109,8 @@ SIGNATURES = [
     ("ur_set_record", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_void_p]),
     ("ur_record_histogram", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.c_uint32, C.c_void_p,
                                       C.c_void_p]),
+    ("ur_set_cost_histogram", C.c_int, [_CTX, C.c_void_p]),
+    ("ur_record_reweight", C.c_int, [_CTX, C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p]),
     ("ur_scene_update", C.c_int, [_CTX, P(C.c_double), P(C.c_double), P(C.c_double)]),
     ("ur_pulse_adjoint", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform_adjoint", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -247,6 +249,13 @@ class Context:
                                   _stream_ptr(stream))
         self.check(rc, "ur_beamform")
 
+    def ur_set_cost_histogram(self, cost):
+        self.check(self.lib.ur_set_cost_histogram(self.h, _ptr(cost)), "ur_set_cost_histogram")
+
+    def ur_record_reweight(self, rec, n_rec, cost, rays_per_row, stream=None):
+        self.check(self.lib.ur_record_reweight(self.h, _ptr(rec), int(n_rec), _ptr(cost), float(rays_per_row),
+                                               _stream_ptr(stream)), "ur_record_reweight")
+
     def ur_scene_update(self, mat=None, scat_amp=None, sph=None):
         keep = []
 
@@ -274,9 +283,9 @@ class Context:
                                           _stream_ptr(stream))
         self.check(rc, "ur_beamform_adjoint")
 
-    def ur_trace_adjoint(self, seed, g_raw, amp=None, alpha=None, Z=None, sph_center=None, frozen_choice=False,
-                         ray_stride=1, ray_offset=0, stream=None):
-        d = GradDesc(amp=_ptr(amp), alpha=_ptr(alpha), Z=_ptr(Z), sph_center=_ptr(sph_center),
+    def ur_trace_adjoint(self, seed, g_raw, amp=None, alpha=None, Z=None, sph_center=None, value=None,
+                         frozen_choice=False, ray_stride=1, ray_offset=0, stream=None):
+        d = GradDesc(amp=_ptr(amp), alpha=_ptr(alpha), Z=_ptr(Z), sph_center=_ptr(sph_center), value=_ptr(value),
                      frozen_choice=1 if frozen_choice else 0)
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))

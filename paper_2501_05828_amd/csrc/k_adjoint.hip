@@ -67,6 +67,7 @@ struct AdjParams {
     float *grad_amp;         // [n_scat] or null (value pass)
     double *grad_alpha;      // [n_mat] or null (value pass)
     double *grad_out;        // [1] tangent-pass result
+    double *value_out;       // [1] sum of g(t) c over the replayed contributions, or null
     double kappa;            // d ka / d alpha [Np/m per dB/(cm MHz)]
     int attach_choice;       // 1: keep R / value(R) on the path weight
 };
@@ -103,6 +104,7 @@ __device__ __forceinline__ bool adj_at(const AdjParams &A, int tx, int e, double
 }
 
 struct Acc {
+    double val;               // sum of g(t) c
     double tan;               // tangent-pass accumulator
     double alpha[kAdjMat];    // value pass: dJ/d alpha_m
 };
@@ -220,6 +222,7 @@ __device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx,
                                            double c_unit, const double *len_path, const double *len_sh) {
     double g, gs;
     if (!adj_at(A, tx, er, t.v, g, gs)) return;
+    acc.val += g * c.v;
     if (A.tan.kind != 0) {
         acc.tan += g * c.t + gs * c.v * t.t;
         return;
@@ -487,6 +490,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
 
 __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     Acc acc;
+    acc.val = 0.0;
     acc.tan = 0.0;
     for (int m = 0; m < kAdjMat; ++m) acc.alpha[m] = 0.0;
     const TraceParams &P = A.P;
@@ -498,6 +502,11 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     }
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;
+    if (A.value_out) {
+        double v = acc.val;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && v != 0.0) atomicAdd(A.value_out, v);
+    }
     if (A.tan.kind != 0) {
         double v = acc.tan;
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -525,7 +534,8 @@ hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s) {
 }
 
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
-                            double *grad_alpha, double *grad_out, double kappa, int attach_choice, hipStream_t s) {
+                            double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
+                            hipStream_t s) {
     AdjParams A;
     A.P = p;
     A.tan = Tangent{kind, index, coord};
@@ -533,6 +543,7 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int c
     A.grad_amp = grad_amp;
     A.grad_alpha = grad_alpha;
     A.grad_out = grad_out;
+    A.value_out = value_out;
     A.kappa = kappa;
     A.attach_choice = attach_choice;
     if (kind != 0) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, grad_out, 1);

@@ -224,6 +224,28 @@ __global__ void k_record_hist(const RecordEntry *rec, int64_t n_rec, int64_t bat
     }
 }
 
+// Second moment of the recorded contributions per bin.
+__global__ void k_record_s2(const RecordEntry *rec, int64_t n_rec, int64_t n_bins, float *s2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rec; i += (int64_t)gridDim.x * blockDim.x) {
+        const RecordEntry e = rec[i];
+        if ((int64_t)e.bin < n_bins) atomicAdd(s2 + e.bin, e.value * e.value);
+    }
+}
+
+// value := c^2 / sqrt(S2 * mean cost): summed over a bin this gives
+// sqrt(S2 / mean cost), the density that minimises variance x time.
+__global__ void k_record_weight(RecordEntry *rec, int64_t n_rec, int64_t n_bins, const float *s2, const float *cost,
+                                float inv_rays_per_cell) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rec; i += (int64_t)gridDim.x * blockDim.x) {
+        RecordEntry e = rec[i];
+        if ((int64_t)e.bin >= n_bins) continue;
+        const float mc = fmaxf(cost[e.bin] * inv_rays_per_cell, 1.0f);
+        const float q = s2[e.bin];
+        e.value = q > 0.f ? e.value * e.value / sqrtf(q * mc) : 0.f;
+        rec[i] = e;
+    }
+}
+
 dim3 blocks_for(int64_t n, int per = 256) { return dim3((unsigned)std::min<int64_t>((n + per - 1) / per, 4096)); }
 
 }  // namespace
@@ -284,5 +306,15 @@ hipError_t ur_mlp_record_hist(const ur::RecordEntry *rec, int64_t n_rec, int64_t
     if (e != hipSuccess || n_rec <= 0 || batch <= 0) return e;
     hipLaunchKernelGGL(k_record_hist, blocks_for(batch), dim3(256), 0, s, rec, n_rec, batch, (uint32_t)seed,
                        (uint32_t)(seed >> 32), step, n_bins, hist);
+    return hipGetLastError();
+}
+
+hipError_t ur_mlp_record_reweight(ur::RecordEntry *rec, int64_t n_rec, const float *cost, double rays_per_row,
+                                  float *s2, int64_t n_bins, hipStream_t s) {
+    hipError_t e = ur_mlp_fill(s2, n_bins, 0.f, s);
+    if (e != hipSuccess || n_rec <= 0) return e;
+    hipLaunchKernelGGL(k_record_s2, blocks_for(n_rec), dim3(256), 0, s, rec, n_rec, n_bins, s2);
+    hipLaunchKernelGGL(k_record_weight, blocks_for(n_rec), dim3(256), 0, s, rec, n_rec, n_bins, s2, cost,
+                       (float)((double)ur::kCells / rays_per_row));
     return hipGetLastError();
 }

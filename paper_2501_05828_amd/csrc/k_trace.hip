@@ -872,7 +872,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     Hit h;
     CullRay cr;
     float tmf = 0.0f;
-    int cur = 0, sp = 0;
+    int cur = 0, sp = 0, visits = 0;
     bool active = false, trav = false, overflow = false, exhausted = false;
     unsigned long long cbeg = 0, cend = 0;
     auto start_segment = [&]() {
@@ -918,6 +918,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.med = P.top_medium;
                         R.seg = 0;
                         active = true;
+                        visits = 0;
                         CNT(C_RAYS);
                         start_segment();
                     }
@@ -927,14 +928,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
         if (__ballot(active) == 0ull) break;
-        if (active && trav) trav = wide_step<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cur, sp, overflow, stk, cnt);
+        if (active && trav) {
+            trav = wide_step<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cur, sp, overflow, stk, cnt);
+            ++visits;
+        }
         const unsigned long long done = __ballot(active && !trav);
         if (__popcll(done) < kBatchExtend && __ballot(active && trav) != 0ull) continue;
         if (active && !trav) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             analytic_hits(P, R.o, R.d, R.last, h);
             active = after_hit<COUNT, false, kDeferNee, true>(P, L, cnt, R, h, chunk);
-            if (active) start_segment();
+            if (active) {
+                start_segment();
+            } else if (P.cost && R.cell >= 0) {
+                // cost model of one path for a cost-aware proposal: node
+                // visits + 2 per segment + 1.5 per grid cell of path length
+                float c = (float)visits + 2.0f * (float)(R.seg + 1);
+                if (P.n_scat > 0) c += 1.5f * (float)(R.len * P.grid.inv_h);
+                atomicAdd(P.cost + ((int64_t)R.tx * P.E + R.e) * kCells + R.cell, c);
+            }
         }
     }
     // the unused tail of this wavefront's last chunk of the segment queue

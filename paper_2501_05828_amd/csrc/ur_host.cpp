@@ -64,6 +64,8 @@ struct ur_context {
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
     RecordEntry *rec = nullptr;
+    float *cost = nullptr;                 // per-cell path-cost histogram (optional)
+    DevBuf d_s2;
     unsigned long long *rec_count = nullptr;
     int64_t rec_cap = 0;
     std::vector<hipEvent_t> tev;           // [4 * launches]: before extend, after extend, after scatter, after sampling
@@ -219,6 +221,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.item_id = (const int *)c->d_item_id.p;
     P.n_scat = (int)c->n_scat;
     P.work_next = (unsigned long long *)c->d_work.p;
+    P.cost = c->cost;
     return UR_OK;
 }
 
@@ -273,7 +276,7 @@ UR_API void ur_context_destroy(ur_context *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
-                      &c->d_tri_id, &c->d_tnodes, &c->d_tnodes4, &c->d_cell_start, &c->d_items, &c->d_items_f, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
+                      &c->d_tri_id, &c->d_tnodes, &c->d_tnodes4, &c->d_cell_start, &c->d_items, &c->d_items_f, &c->d_s2, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
                       &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
@@ -918,8 +921,8 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
     return guarded(c, [&]() -> ur_status {
         if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
         if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
-        if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center)
-            return c->fail(UR_ERR_INVALID_ARG, "no gradient requested");
+        if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center && !grads->value)
+            return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
             return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
         const int n_mat = (int)(c->mat.size() / 3);
@@ -936,17 +939,19 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         const double kappa = c->probe.f_c * 1e-6 * 100.0 * std::log(10.0) / 20.0;
         if (grads->amp) HIP_TRY(c, zero_f32(grads->amp, c->n_scat, s));
         if (grads->alpha) HIP_TRY(c, ur_launch_zero_f64(grads->alpha, n_mat, s));
-        if (grads->amp || grads->alpha)
-            HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, kappa, 1, s));
+        if (grads->value) HIP_TRY(c, ur_launch_zero_f64(grads->value, 1, s));
+        if (grads->amp || grads->alpha || grads->value)
+            HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, grads->value, kappa,
+                                        1, s));
         if (grads->Z)
             for (int m = 0; m < n_mat; ++m)
-                HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, kappa,
+                HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, nullptr, kappa,
                                             !grads->frozen_choice, s));
         if (grads->sph_center)
             for (int j = 0; j < (int)c->n_sph; ++j)
                 for (int k = 0; k < 3; ++k)
                     HIP_TRY(c, ur_launch_replay(P, 2, j, k, g_raw_dev, nullptr, nullptr, grads->sph_center + 3 * j + k,
-                                                kappa, !grads->frozen_choice, s));
+                                                nullptr, kappa, !grads->frozen_choice, s));
         return UR_OK;
     });
 }
@@ -1108,6 +1113,28 @@ UR_API ur_status ur_set_record(ur_context *c, void *rec_dev, int64_t cap, unsign
         c->rec = (RecordEntry *)rec_dev;
         c->rec_cap = rec_dev ? cap : 0;
         c->rec_count = rec_dev ? count_dev : nullptr;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_set_cost_histogram(ur_context *c, float *cost_dev) {
+    return guarded(c, [&]() -> ur_status {
+        c->cost = cost_dev;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_record_reweight(ur_context *c, void *rec_dev, int64_t n_rec, const float *cost_dev,
+                                    double rays_per_row, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if ((n_rec > 0 && !rec_dev) || n_rec < 0 || !cost_dev || !(rays_per_row > 0))
+            return c->fail(UR_ERR_INVALID_ARG, "need records, a cost histogram and rays_per_row > 0");
+        const int64_t bins = c->acq.n_tx * c->probe.n_elements * kOut;
+        ur_status st;
+        if ((st = alloc(c, c->d_s2, (size_t)bins * sizeof(float)))) return st;
+        HIP_TRY(c, ur_mlp_record_reweight((RecordEntry *)rec_dev, n_rec, cost_dev, rays_per_row, (float *)c->d_s2.p,
+                                          bins, (hipStream_t)stream));
         return UR_OK;
     });
 }

@@ -107,6 +107,7 @@ struct TraceParams {
     unsigned long long *stats;        // [kNumStats] or null
     unsigned long long *work_next;    // persistent-kernel work counter (zeroed before launch)
     int64_t work_begin, work_end;     // work items [begin, end) of this launch
+    float *cost;                      // [T*E][1024] per-emission-cell path cost, or null
     SegEntry *segq;                   // segment queue between the extend and scatter kernels
     unsigned long long *seg_count;    // slots reserved (chunks of kSegChunk)
     unsigned long long *seg_next;     // scatter-kernel work counter
@@ -165,6 +166,8 @@ hipError_t ur_mlp_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t ur_mlp_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps,
                        float c1, float c2, hipStream_t s);
 hipError_t ur_mlp_tables(const float *Q, int R, float eps, float *pdf, float *cdf, hipStream_t s);
+hipError_t ur_mlp_record_reweight(ur::RecordEntry *rec, int64_t n_rec, const float *cost, double rays_per_row,
+                                  float *s2, int64_t n_bins, hipStream_t s);
 hipError_t ur_mlp_record_hist(const ur::RecordEntry *rec, int64_t n_rec, int64_t batch, uint64_t seed, uint32_t step,
                               int64_t n_bins, float *hist, hipStream_t s);
 hipError_t ur_launch_env_adj(const float2 *iq, const float *g_env, float2 *g_iq, int64_t n, hipStream_t s);
@@ -173,6 +176,7 @@ hipError_t ur_launch_pulse_adj(const float2 *g_rf, float *g_raw, const float2 *t
                                hipStream_t s);
 hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s);
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
-                            double *grad_alpha, double *grad_out, double kappa, int attach_choice, hipStream_t s);
+                            double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
+                            hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);

@@ -1,8 +1,11 @@
 """Learned emission proposal driven through the C ABI.
 
 record(): trace with uniform emission while the library appends every binned
-contribution (row, emission cell, |c|).  train(): Adam steps on minibatch
-histograms drawn from those records.  enable(): the network's direction
+contribution (row, emission cell, |c|); with cost_aware, also the cost of
+every path per emission cell, after which each record is reweighted so that
+the training target per cell is sqrt(sum c^2 / mean path cost) -- the
+density that minimises variance x time -- instead of sum |c|.  train(): Adam
+steps on minibatch histograms drawn from those records.  enable(): the network's direction
 distribution, mixed with eps of uniform, becomes the emission pdf of later
 traces (weights 1/pdf keep the estimator unbiased).
 """
@@ -29,21 +32,29 @@ class Proposal:
         self.rec = None
         self.n_rec = 0
 
-    def record(self, n_traces: int, cap: int = 1 << 22, seed0: int = 0x1234_0000):
+    def record(self, n_traces: int, cap: int = 1 << 22, seed0: int = 0x1234_0000, cost_aware: bool = False):
         """Records contributions of n_traces uniform traces of the current
         acquisition; returns (records kept, records offered)."""
         dev = self.sim.dev
         self.rec = torch.empty((cap, 2), dtype=torch.int32, device=dev)
         count = torch.zeros(1, dtype=torch.int64, device=dev)
+        cost = torch.zeros((self.rows, 1024), dtype=torch.float32, device=dev) if cost_aware else None
         self.ctx.ur_set_proposal(None, None)
         self.ctx.ur_set_record(self.rec, count)
+        if cost_aware:
+            self.ctx.ur_set_cost_histogram(cost)
         try:
             for i in range(n_traces):
                 self.sim.trace(seed=seed0 + i, pulse=False)
         finally:
             self.ctx.ur_set_record(None)
+            self.ctx.ur_set_cost_histogram(None)
         offered = int(count.item())
         self.n_rec = min(offered, cap)
+        if cost_aware and self.n_rec:
+            rays_per_row = float(self.sim.w.acq.rays_per_element) * n_traces
+            self.ctx.ur_record_reweight(self.rec, self.n_rec, cost, rays_per_row)
+        self.cost = cost
         return self.n_rec, offered
 
     def train(self, steps: int = 2000, batch: int = 1 << 16, lr: float = 1e-3, seed: int = 11,

@@ -320,3 +320,132 @@ def test_autograd_envelope_loss(torch_gpu):
     got = float(amp.grad @ v)
     print(f"[adjoint] autograd amp dir: grad={got:.6e} fd={fd:.6e}", flush=True)
     assert abs(got - fd) <= 2e-3 * abs(fd)
+
+
+def test_large_scene_gradients_on_64_parameters(torch_gpu):
+    """The differentiable large scene at full size (192 elements, 21 plane
+    waves, two 250k-triangle tubes, 4 spheres, 1e6 scatterers, linear
+    binning), every 96th ray of each (transmit, element) row (5.2e6 rays).
+    The replayed FP64 functional J = sum g c equals sum g * ch_raw of the
+    forward trace (itself oracle-checked).  64 parameters -- the 6
+    attenuations, the 12 sphere-centre coordinates (frozen choice), 40
+    scatterer amplitudes and the 6 impedances (frozen choice) -- are checked
+    against central differences of J; a step counts only if the forward's
+    integer counters and its number of non-empty bins are unchanged at both
+    ends.  With 1e6 scatterers, an impedance step as small as 1e-10 MRayl
+    already moves some refracted segment across a capture boundary, so the
+    impedances are checked with every amplitude set to zero (captures then
+    add nothing to J, and their counters are left out of the check)."""
+    torch = torch_gpu
+    w = scenes.large()
+    stride = 96
+    s = _sim(w)
+    A = w.acq
+    g = _smooth_adjoint((A.n_tx, A.n_elements, A.n_samples), 41)
+    gt = torch.from_numpy(g).cuda()
+    sc = w.scene
+    n_mat, n_sph, K = len(sc.materials), len(sc.sph), len(sc.scat)
+    mat0, sph0, amp0 = sc.materials.copy(), sc.sph.copy(), sc.scat[:, 3].copy()
+    no_capture = ["rays", "segments", "reflect", "transmit", "tir", "direct_hits", "dropped", "term_box",
+                  "term_bounce", "term_time", "term_path"]
+
+    def forward_key(keys):
+        st = s.trace(stats=True, ray_stride=stride, pulse=False)
+        nz = torch.count_nonzero(s.ch_raw).item()
+        return ({k: st[k] for k in keys}, nz), float((s.ch_raw.double() * gt.double()).sum())
+
+    last = {}
+
+    def update(mat, sph, amp):
+        """Uploads only the arrays that differ from the last upload."""
+        arg = {}
+        for name, a in (("mat", mat), ("sph", sph), ("scat_amp", amp)):
+            if name not in last or last[name] is not a:
+                arg[name] = a
+                last[name] = a
+        if arg:
+            s.ctx.ur_scene_update(**arg)
+
+    def replay_J(mat, sph, amp, keys):
+        update(mat, sph, amp)
+        v = torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.ctx.ur_trace_adjoint(w.seed, gt, value=v, ray_stride=stride)
+        return float(v.item()), (forward_key(keys)[0] if keys else None)
+
+    def fd(make, h0, key0, keys, tries=5):
+        h = h0
+        for _ in range(tries):
+            jp, kp = replay_J(*make(h), keys)
+            jm, km = replay_J(*make(-h), keys)
+            if not keys or (kp == key0 and km == key0):
+                return (jp - jm) / (2 * h), h
+            h *= 0.1
+        return None, h
+
+    def gradients(amp, frozen=True):
+        update(mat0, sph0, amp)
+        Zg = torch.empty(n_mat, dtype=torch.float64, device="cuda")
+        al = torch.empty(n_mat, dtype=torch.float64, device="cuda")
+        cg = torch.empty((n_sph, 3), dtype=torch.float64, device="cuda")
+        ag = torch.empty(K, device="cuda")
+        s.ctx.ur_trace_adjoint(w.seed, gt, amp=ag, alpha=al, Z=Zg, sph_center=cg, frozen_choice=frozen,
+                               ray_stride=stride)
+        return Zg.cpu().numpy(), al.cpu().numpy(), cg.cpu().numpy().ravel(), ag.double().cpu().numpy()
+
+    update(mat0, sph0, amp0)
+    key0, jf = forward_key(EXACT_STATS)
+    J0, _ = replay_J(mat0, sph0, amp0, None)
+    print(f"[adjoint-large] J replay {J0:.9e} forward {jf:.9e} records {key0[0]['records']}", flush=True)
+    assert abs(J0 - jf) <= 1e-5 * abs(J0)
+    Zg, al, cg, ag = gradients(amp0)
+    checked = {"Z": 0, "alpha": 0, "centre": 0, "amp": 0}
+    for m in range(n_mat):
+        def mk(h, m=m):
+            mat = mat0.copy()
+            mat[m, 1] += h
+            return mat, sph0, amp0
+        f, _ = fd(mk, 1e-4, key0, None)   # no decision depends on attenuation
+        print(f"[adjoint-large] dJ/dalpha[{m}] gpu {al[m]:.6e} fd {f:.6e}", flush=True)
+        assert abs(al[m] - f) <= 1e-5 * max(np.max(np.abs(al)), abs(f)) + 1e-4 * abs(f)
+        checked["alpha"] += 1
+    for c in range(3 * n_sph):
+        def mk(h, c=c):
+            sph = sph0.copy()
+            sph[c // 3, c % 3] += h
+            return mat0, sph, amp0
+        f, h = fd(mk, 1e-10, key0, EXACT_STATS, tries=4)
+        print(f"[adjoint-large] dJ/dcentre[{c}] gpu {cg[c]:.6e} fd {f} h {h:.1e}", flush=True)
+        if f is not None:
+            assert abs(cg[c] - f) <= 1e-4 * max(np.max(np.abs(cg)), abs(f))
+            checked["centre"] += 1
+    nonzero = np.flatnonzero(ag)
+    rng = np.random.default_rng(17)
+    picks = list(rng.choice(nonzero, size=min(30, len(nonzero)), replace=False))
+    picks += list(rng.choice(np.flatnonzero(ag == 0), size=40 - len(picks), replace=False))
+    for k in picks:
+        def mk(h, k=k):
+            amp = amp0.copy()
+            amp[k] += h
+            return mat0, sph0, amp
+        f, _ = fd(mk, 1.0, key0, None)   # J is linear in the amplitudes
+        assert abs(ag[k] - f) <= 1e-5 * np.max(np.abs(ag)) + 1e-4 * abs(f), (k, ag[k], f)
+        checked["amp"] += 1
+    # impedances with the captures silenced
+    zero = np.zeros_like(amp0)
+    update(mat0, sph0, zero)
+    keyz, _ = forward_key(no_capture)
+    Zz = gradients(zero)[0]
+    for m in range(n_mat):
+        def mk(h, m=m):
+            mat = mat0.copy()
+            mat[m, 0] += h
+            return mat, sph0, zero
+        f, h = fd(mk, 1e-8 * mat0[m, 0], keyz, no_capture, tries=4)
+        print(f"[adjoint-large] dJ/dZ[{m}] (no captures) gpu {Zz[m]:.6e} fd {f} h {h:.1e}", flush=True)
+        if f is not None:
+            assert abs(Zz[m] - f) <= 1e-4 * max(np.max(np.abs(Zz)), abs(f))
+            checked["Z"] += 1
+    s.ctx.ur_scene_update(mat=mat0, sph=sph0, scat_amp=amp0)
+    print(f"[adjoint-large] checked {checked}", flush=True)
+    assert checked["Z"] >= n_mat - 1 and checked["centre"] >= 3 * n_sph - 4
+    assert sum(checked.values()) >= 58
