@@ -449,7 +449,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
         CNT(C_NEE_ZERO);
         return false;
     }
-    c.wq = w * exp(-M.ka * s) * amp;
+    c.wq = w * atten(-M.ka * s) * amp;
     c.tq = t + s * M.inv_c;
     c.tx = tx;
     c.er = er;
@@ -482,7 +482,7 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
         CNT(C_NEE_BLOCKED);
         return;
     }
-    const double att = exp(-(M.ka * dist + sum_a));
+    const double att = atten(-(M.ka * dist + sum_a));
     const double tc = c.tq + dist * M.inv_c + sum_c;
     const double val = c.wq * (double)P.E * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
     record<COUNT, LOG>(P, L, cnt, 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
@@ -631,7 +631,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg, R.cell);
     }
     const Material M = P.mat[R.med];
-    R.w *= exp(-M.ka * t_seg);
+    R.w *= atten(-M.ka * t_seg);
     R.t += t_seg * M.inv_c;
     R.len += t_seg;
     o[0] += t_seg * d[0];
