@@ -179,3 +179,46 @@ def test_learned_emission_is_unbiased_and_exact():
     se = math.sqrt(np.var(tot_l, ddof=1) / 24 + np.var(tot_u, ddof=1) / 24)
     print(f"[proposal] learned {ml:.4e} uniform {mu:.4e} se {se:.2e}")
     assert abs(ml - mu) < 4.5 * se
+
+
+def test_cost_histogram_and_cost_aware_weights():
+    """Path-cost histogram: every emission cell that received a recorded
+    contribution has a positive cost, and the total is bounded by the trace
+    counters (at least 2 per segment, the node visits on top).  Reweighted
+    records: per bin their weights sum to sqrt(S2 / mean cost), with S2 the
+    sum of c^2 of the bin's records."""
+    import torch
+    from paper_2501_05828_amd.proposal import Proposal
+    from paper_2501_05828_amd.sim import Simulator
+    w = scenes.tiny(rays_per_element=512)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45)))
+    sim = Simulator(w)
+    st = sim.trace(stats=True, pulse=False)
+    prop = Proposal(sim)
+    n, _ = prop.record(2, cost_aware=False)
+    before = prop.rec[:n].cpu().numpy().copy()
+    n2, _ = prop.record(2, cost_aware=True)
+    assert n2 == n
+    after = prop.rec[:n].cpu().numpy()
+    # same records (appended in a different order): the same multiset of bins
+    assert np.array_equal(np.sort(before[:, 0].view(np.uint32)), np.sort(after[:, 0].view(np.uint32)))
+    cost = prop.cost.cpu().numpy().ravel().astype(np.float64)
+    bins = before[:, 0].view(np.uint32).astype(np.int64)
+    c = before[:, 1].view(np.float32).astype(np.float64)
+    wgt = after[:, 1].view(np.float32).astype(np.float64)
+    wbins = after[:, 0].view(np.uint32).astype(np.int64)
+    assert np.all(cost[np.unique(bins)] > 0)
+    total = cost.sum()
+    segs = 2 * st["segments"]                              # two traces of the same size
+    assert 2.0 * segs <= total <= 2.0 * segs + 2 * st["tri_nodes"] + 1.5 * 2 * st["segments"] * 64
+    s2 = np.zeros(cost.size)
+    np.add.at(s2, bins, c * c)
+    rays_per_row = 2.0 * w.acq.rays_per_element
+    mean_cost = np.maximum(cost * 1024.0 / rays_per_row, 1.0)
+    want = np.zeros(cost.size)
+    np.add.at(want, bins, c * c / np.sqrt(s2[bins] * mean_cost[bins]))
+    got = np.zeros(cost.size)
+    np.add.at(got, wbins, wgt)
+    nz = s2 > 0
+    assert np.allclose(got[nz], np.sqrt(s2[nz] / mean_cost[nz]), rtol=1e-4)
+    assert np.allclose(got, want, rtol=1e-4, atol=0)
