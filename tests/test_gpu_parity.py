@@ -118,9 +118,43 @@ def test_bone_reduced(torch_gpu, oracle):
 
 def test_bone_full_size_sampled(torch_gpu, oracle):
     """Full bone-phantom workload (1e7 rays per transmit, same launch code):
-    every 39063rd ray of each element is traced on both sides."""
+    every 2000th ray of each (transmit, element) row is traced on both sides."""
     w = scenes.bone()
-    _compare_trace(oracle, w, stride=39063, label="bone-full-sampled")
+    _, _, _, st, _ = _compare_trace(oracle, w, stride=2000, label="bone-full-sampled")
+    assert st["rays"] == 11 * 128 * 40 and st["records"] >= 20
+
+
+def test_batched_full_size_sampled(torch_gpu, oracle):
+    """Batched workload at full size (21 plane waves -20..20 deg, 2e7 rays
+    per transmit, launch ranges as timed): 2 rays of each (transmit,
+    element) row traced on both sides; and its 1024 x 1024 compounded DAS of
+    point echoes on 400 sampled pixels."""
+    import torch
+    w = scenes.batched()
+    _, _, _, st, _ = _compare_trace(oracle, w, stride=4000, label="batched-full-sampled")
+    assert st["records"] >= 40
+    acq, grid = w.acq, w.grid
+    pts = [(0.0, 0.3 * grid.z1), (0.4 * grid.x1, 0.7 * grid.z1)]
+    rf = _point_echo_channels(acq, pts, 13).astype(np.complex64)
+    s = _sim(w)
+    rf_t = torch.from_numpy(np.stack([rf.real, rf.imag], -1).astype(np.float32)).cuda()
+    s.ctx.ur_beamform(grid, rf_t, iq=s.iq, env=s.env)
+    g = s.iq.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(4)
+    ix, iz = rng.integers(0, grid.nx, 400), rng.integers(0, grid.nz, 400)
+    xs = grid.x0 + ix * (grid.x1 - grid.x0) / (grid.nx - 1)
+    zs = grid.z0 + iz * (grid.z1 - grid.z0) / (grid.nz - 1)
+    ref = oracle.das_points(acq, np.stack([xs, zs], 1), rf.astype(np.complex128))
+    assert rel_l2(g[ix, iz, 0] + 1j * g[ix, iz, 1], ref) <= TOL_SIG
+
+
+def test_large_full_size_sampled(torch_gpu, oracle):
+    """Differentiable large scene at full size (192 elements, 21 plane
+    waves, 500k triangles, 4 spheres, 1e6 scatterers, linear binning): one
+    ray in 41336 of each (transmit, element) row traced on both sides."""
+    w = scenes.large()
+    _, _, _, st, _ = _compare_trace(oracle, w, stride=41336, label="large-full-sampled")
+    assert st["records"] >= 30
 
 
 def test_ray_subsets_sum_to_full_trace(torch_gpu):
