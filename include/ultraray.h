@@ -185,14 +185,16 @@ UR_API ur_status ur_set_proposal(ur_context *ctx, const float *pdf_dev, const fl
 UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
 
-/* Work-size limits of later ur_trace calls: at most min(rays_per_launch,
- * 2^22) rays are traced per launch range, and up to nee_queue_capacity
- * transducer-sampling candidates (72 bytes each, library-owned device
- * memory) are queued per range before their secondary rays are cast.  If a
- * range produces more candidates than fit, that range is traced again with
- * the secondary rays cast inline, so results never depend on these limits.
- * Each range also queues its primary-ray segments for the scatterer walk in
- * library-owned memory of 96 bytes x (rays x (max_bounces + 1) + 2^18).
+/* Work-size limits of later ur_trace calls.  A trace is cut into equal
+ * launch ranges of at most min(rays_per_launch, 2^25) rays; with scatterers
+ * present a range is also cut so that its segment queue (below) stays within
+ * 1/8 of the device memory (but not below 2^16 rays).  Each range queues its
+ * primary-ray segments for the scatterer walk in library-owned device memory
+ * of 96 bytes x (rays x (max_bounces + 1) + 256 x resident wavefronts), and
+ * up to nee_queue_capacity transducer-sampling candidates (72 bytes each,
+ * library-owned) before their secondary rays are cast.  If a range produces
+ * more candidates than fit, that range is traced again with the secondary
+ * rays cast inline, so results never depend on these limits.
  * Defaults: 2^30 rays, 2^22 candidates. */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 

@@ -198,7 +198,8 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
     const float bz = (__uint_as_float(org.z) - cr.oz) * cr.iz;
     const int C[4] = {ch.x, ch.y, ch.z, ch.w};
     float key[4];
-    int val[4];
+    int val[4], lj[4], lc[4];
+    unsigned leaves = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float x0 = fmaf((float)((w0.x >> (8 * k)) & 255u), ax, bx);
@@ -210,24 +211,36 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
         const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
         const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
         const bool hit = tn <= tf && C[k] != -1;
-        if (hit && C[k] < -1) {
-            const int code = ~C[k];
-            for (int j = code >> 4; j < (code >> 4) + (code & 15); ++j) {
-                const int id = P.tri_id[j];
-                if (id == skip) continue;
-                CNT(C_TRI_TESTS);
-                double t;
-                if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT &&
-                    (t < h.t || (t == h.t && id < h.id))) {
-                    h.t = t;
-                    h.id = id;
-                    h.local = j;
-                    tmf = cull_tmax(t);
-                }
-            }
-        }
+        lj[k] = (~C[k]) >> 4;
+        lc[k] = (~C[k]) & 15;
+        if (hit && C[k] < -1) leaves |= 1u << k;
         key[k] = hit && C[k] >= 0 ? tn : INFINITY;
         val[k] = C[k];
+    }
+    // the triangles of every leaf child that the ray enters, in one loop, so
+    // that a wavefront runs the FP64 test once per triangle position rather
+    // than once per child slot
+    int j = 0, je = 0;
+    while (true) {
+        while (j >= je && leaves) {
+            const int k = __builtin_ctz(leaves);
+            leaves &= leaves - 1;
+            j = k == 0 ? lj[0] : (k == 1 ? lj[1] : (k == 2 ? lj[2] : lj[3]));
+            je = j + (k == 0 ? lc[0] : (k == 1 ? lc[1] : (k == 2 ? lc[2] : lc[3])));
+        }
+        if (j >= je) break;
+        const int id = P.tri_id[j];
+        if (id != skip) {
+            CNT(C_TRI_TESTS);
+            double t;
+            if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && id < h.id))) {
+                h.t = t;
+                h.id = id;
+                h.local = j;
+                tmf = cull_tmax(t);
+            }
+        }
+        ++j;
     }
     // sort the four (key, child) pairs ascending: 5 compare-exchanges
     auto cx = [&](int a, int b) {

@@ -591,7 +591,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             size_t free_b = 0, total_b = 0;
             HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
             const int64_t fit = (int64_t)(total_b / 8 / (sizeof(SegEntry) * (size_t)(P.B + 1)));
-            range = std::max<int64_t>(int64_t(1) << 16, std::min(range, fit));
+            range = std::min(range, std::max<int64_t>(int64_t(1) << 16, fit));
         }
         if (c->n_scat > 0) {
             const int64_t waves = ur_extend_max_waves();

@@ -310,6 +310,22 @@ def test_abi_errors(torch_gpu):
         ctx.ur_trace_rays(1, [dict(o=[0, 0, -1.0], d=[0, 0, 1.0])])
 
 
+def test_ragged_launch_ranges(torch_gpu, oracle):
+    """32,000 rays cut into eleven launch ranges of 2,910 rays with a ragged
+    last range of 2,900: stats exact and channel data equal to the oracle's."""
+    w = scenes.tiny(rays_per_element=500)
+    s = _sim(w)
+    s.ctx.ur_set_limits(3000, 1 << 22)
+    st = s.trace(stats=True, pulse=False)
+    g = s.ch_raw.cpu().numpy()
+    ref, ost = oracle.trace(w)
+    assert ost["rays"] == 32000
+    for k in EXACT_STATS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert rel_l2(g, ref) <= TOL_CH
+    assert s.ctx.ur_last_trace_kernels_ms()[3] == 11
+
+
 def test_sampling_queue_overflow_retrace(torch_gpu, oracle):
     """A transducer-sampling queue far too small for the launch: the range is
     traced again with inline secondary rays and the result is unchanged."""
