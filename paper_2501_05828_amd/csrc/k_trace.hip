@@ -448,6 +448,19 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     c.q[0] = o[0] + s * d[0];
     c.q[1] = o[1] + s * d[1];
     c.q[2] = o[2] + s * d[2];
+    const double cc = P.cos_alpha_c;
+    if (cc >= 0.0) {
+        // The cut-off test below only gets easier to meet as the lateral
+        // offset vx^2 to the drawn element grows.  If it holds already at
+        // vx = 0 (with a relative margin far above the rounding of either
+        // side) it holds for every element, and the element draw is skipped.
+        const double vy = c.q[1], mvz = c.q[2];
+        if (mvz < 0.0 || mvz * mvz < cc * cc * (vy * vy + mvz * mvz) * (1.0 - 1e-9)) {
+            CNT(C_SCAT_EVENTS);
+            CNT(C_NEE_ZERO);
+            return false;
+        }
+    }
     uint32_t x[4];
     draw(P, ray, e, tx, seg, 2, (uint32_t)k, x);
     const int er = (int)(((uint64_t)x[0] * (uint64_t)P.E) >> 32);
@@ -455,7 +468,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     // alpha > alpha_c  <=>  cos(alpha) = -v_z / |v| < cos(alpha_c)
     const double vx = P.xe[er] - c.q[0], vy = c.q[1], mvz = c.q[2];
     const double r2 = vx * vx + vy * vy + mvz * mvz;
-    const double cc = P.cos_alpha_c, lhs = mvz * mvz, rhs = cc * cc * r2;
+    const double lhs = mvz * mvz, rhs = cc * cc * r2;
     const bool cut = cc >= 0.0 ? (mvz < 0.0 || lhs < rhs) : (mvz < 0.0 && lhs > rhs);
     CNT(C_SCAT_EVENTS);
     if (cut) {
@@ -573,6 +586,21 @@ struct RayState {
 // and, if that runs short, takes a new chunk of kSegChunk with one atomic for
 // the remaining lanes; each lane writes its entry.  No slot is skipped except
 // at the end of a wavefront's last chunk (marked unused by the kernel).
+// Whether the segment o + t d, t in [0, t_end], can pass through the
+// scatterer grid box: an FP32 slab test (the segment's culling origin and
+// reciprocals) against the box grown by 10 um.  The FP32 rounding moves the
+// slab parameters by well under 1 um over the scene, so a segment that
+// reaches the grid box is never dropped; a zero direction component has a
+// reciprocal of +-1e20, which keeps the slab test exact in sign.
+__device__ __forceinline__ bool meets_grid(const TraceParams &P, const CullRay &cr, double t_end) {
+    const float ax = (P.grid_lo_f[0] - cr.ox) * cr.ix, bx = (P.grid_hi_f[0] - cr.ox) * cr.ix;
+    const float ay = (P.grid_lo_f[1] - cr.oy) * cr.iy, by = (P.grid_hi_f[1] - cr.oy) * cr.iy;
+    const float az = (P.grid_lo_f[2] - cr.oz) * cr.iz, bz = (P.grid_hi_f[2] - cr.oz) * cr.iz;
+    const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), cull_tmax(t_end) + 1e-5f));
+    return t0 <= t1;
+}
+
 __device__ __forceinline__ void push_segment(const TraceParams &P, const RayState &R, double t_seg,
                                              volatile unsigned long long *chunk) {
     const unsigned long long mask = __ballot(1);
@@ -629,7 +657,7 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
 // has ended.
 template <bool COUNT, bool LOG, int MODE, bool SPLIT>
 __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R,
-                                          const Hit &h, volatile unsigned long long *chunk) {
+                                          const Hit &h, volatile unsigned long long *chunk, bool near_grid = true) {
     const int b = R.seg;
     double *o = R.o, *d = R.d;
     double t_seg = h.t;
@@ -639,7 +667,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         clipped = true;
     }
     if constexpr (SPLIT) {
-        if (P.n_scat > 0 && t_seg > 0.0) push_segment(P, R, t_seg, chunk);
+        if (near_grid && t_seg > 0.0) push_segment(P, R, t_seg, chunk);
     } else {
         scatter_events<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, b, o, d, R.w, R.t, R.med, t_seg, R.cell);
     }
@@ -886,13 +914,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     CullRay cr;
     float tmf = 0.0f;
     int cur = 0, sp = 0, visits = 0;
-    bool active = false, trav = false, overflow = false, exhausted = false;
+    bool active = false, trav = false, overflow = false, exhausted = false, near_grid = false;
     unsigned long long cbeg = 0, cend = 0;
     auto start_segment = [&]() {
         CNT(C_SEGMENTS);
         h = box_exit(P, R.o, R.d);
         cr = make_cull(R.o, R.d);
         tmf = cull_tmax(h.t);
+        near_grid = P.n_scat > 0 && meets_grid(P, cr, h.t);   // up to the box exit, the longest it can be
         cur = 0;
         sp = 0;
         overflow = false;
@@ -950,7 +979,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (active && !trav) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             analytic_hits(P, R.o, R.d, R.last, h);
-            active = after_hit<COUNT, false, kDeferNee, true>(P, L, cnt, R, h, chunk);
+            active = after_hit<COUNT, false, kDeferNee, true>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
                 start_segment();
             } else if (P.cost && R.cell >= 0) {
@@ -1041,11 +1070,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             e = __builtin_nontemporal_load(&E.e);
                             ray = __builtin_nontemporal_load(&E.ray);
                             cell = __builtin_nontemporal_load(&E.cell);
-                            it.init(P.grid, o, d);
-                            tb = it.bound(t_seg);
-                            visited = 1;
-                            enter_cell();
-                            has = true;
+                            // the walk covers the part of the segment inside
+                            // the grid box; t_seg becomes the end of that part
+                            if (it.init(P.grid, o, d, t_seg, t_seg)) {
+                                tb = it.bound(t_seg);
+                                visited = 1;
+                                enter_cell();
+                                has = true;
+                            }
                         }
                     }
                     const unsigned long long served = cbeg + __popcll(need);

@@ -10,26 +10,48 @@
 
 namespace ur {
 
-ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_scat, double r_s, double margin) {
+ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_scat, double r_s, double margin,
+                               const RxCone *rx) {
     ScatterGrid g;
+    const double r = r_s + margin;
+    // the scatterers kept and the bounding box of their grown capture balls
+    std::vector<char> keep((size_t)n_scat, 1);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (long i = 0; i < n_scat; ++i) {
+        const double *p = scat + 4 * i;
+        if (rx && !rx_may_hear(*rx, p, r)) {
+            keep[(size_t)i] = 0;
+            continue;
+        }
+        ++g.kept;
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k] - r - margin);
+            hi[k] = std::max(hi[k], p[k] + r + margin);
+        }
+    }
     double ext[3], vol = 1.0;
     for (int k = 0; k < 3; ++k) {
-        ext[k] = box[3 + k] - box[k];
+        lo[k] = std::max(lo[k], box[k] - margin);
+        hi[k] = std::min(hi[k], box[3 + k] + margin);
+        if (!(hi[k] > lo[k])) {   // nothing kept: one empty cell over the box
+            lo[k] = box[k];
+            hi[k] = box[3 + k];
+        }
+        ext[k] = hi[k] - lo[k];
         vol *= ext[k];
     }
-    const double rho = n_scat > 0 ? (double)n_scat / vol : 1.0 / vol;
+    const double rho = g.kept > 0 ? (double)g.kept / vol : 1.0 / vol;
     double h = std::cbrt(UR_GRID_ITEMS_PER_CELL / rho);
     h = std::max(h, 4.0 * r_s);
     h = std::max(h, std::cbrt(vol / (double)(1 << 24)) * 1.0001);
     for (int k = 0; k < 3; ++k) {
-        g.info.lo[k] = box[k];
+        g.info.lo[k] = lo[k];
         g.info.n[k] = std::max(1, (int)std::ceil(ext[k] / h));
     }
     g.info.h = h;
     g.info.inv_h = 1.0 / h;
     const long cells = (long)g.info.n[0] * g.info.n[1] * g.info.n[2];
     g.cell_start.assign(cells + 1, 0);
-    const double r = r_s + margin;
     auto range = [&](const double *p, int k, int &a, int &b) {
         a = (int)std::floor((p[k] - r - g.info.lo[k]) * g.info.inv_h);
         b = (int)std::floor((p[k] + r - g.info.lo[k]) * g.info.inv_h);
@@ -43,11 +65,13 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
             for (int y = a[1]; y <= b[1]; ++y)
                 for (int x = a[0]; x <= b[0]; ++x) fn((long)(z * g.info.n[1] + y) * g.info.n[0] + x);
     };
-    for (long i = 0; i < n_scat; ++i) for_cells(scat + 4 * i, [&](long c) { ++g.cell_start[c + 1]; });
+    for (long i = 0; i < n_scat; ++i)
+        if (keep[(size_t)i]) for_cells(scat + 4 * i, [&](long c) { ++g.cell_start[c + 1]; });
     for (long c = 0; c < cells; ++c) g.cell_start[c + 1] += g.cell_start[c];
     g.items.resize(g.cell_start[cells]);
     std::vector<int> fill(g.cell_start.begin(), g.cell_start.end() - 1);
-    for (long i = 0; i < n_scat; ++i) for_cells(scat + 4 * i, [&](long c) { g.items[fill[c]++] = (int)i; });
+    for (long i = 0; i < n_scat; ++i)
+        if (keep[(size_t)i]) for_cells(scat + 4 * i, [&](long c) { g.items[fill[c]++] = (int)i; });
     return g;
 }
 

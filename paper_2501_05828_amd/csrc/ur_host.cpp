@@ -208,6 +208,14 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.n_tri = (int)c->n_tri;
     P.n_tnodes = c->n_tnodes;
     P.grid = c->grid;
+    for (int k = 0; k < 3; ++k) {
+        const double lo = c->grid.lo[k] - 1e-5, hi = c->grid.lo[k] + (double)c->grid.n[k] * c->grid.h + 1e-5;
+        float fl = (float)lo, fh = (float)hi;
+        if ((double)fl > lo) fl = std::nextafter(fl, -INFINITY);
+        if ((double)fh < hi) fh = std::nextafter(fh, INFINITY);
+        P.grid_lo_f[k] = fl;
+        P.grid_hi_f[k] = fh;
+    }
     P.cell_start = (const int *)c->d_cell_start.p;
     P.items = (const double4 *)c->d_items.p;
     P.items_f = (const float4 *)c->d_items_f.p;
@@ -219,7 +227,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
         P.pre_r2 = (float)(r * r * (1.0 + 1e-5));
     }
     P.item_id = (const int *)c->d_item_id.p;
-    P.n_scat = (int)c->n_scat;
+    P.n_scat = c->item_order.empty() ? 0 : (int)c->n_scat;   // no registered scatterer: no captures
     P.work_next = (unsigned long long *)c->d_work.p;
     P.cost = c->cost;
     return UR_OK;
@@ -515,9 +523,14 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         c->has_setup = true;
         if ((st = upload_materials(c))) return st;
         // scatterers: uniform grid; each registered in the cells its capture
-        // ball (radius r_s plus a 1 um margin) overlaps
+        // ball (radius r_s plus a 1 um margin) overlaps.  Scatterers that no
+        // element can hear (Eq. 13 zero over the whole grown ball for every
+        // element) are left out: their captures only ever yield zero-valued
+        // secondary rays.
         {
-            ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6);
+            const RxCone rx{xe[0], xe[E - 1], a->alpha_c};
+            ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6,
+                                               &rx);
             std::vector<double4> items(g.items.size());
             std::vector<float4> items_f(g.items.size());
             for (size_t k = 0; k < g.items.size(); ++k) {
@@ -587,13 +600,13 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         // are as long as possible (fewer kernel tails) while the queue stays
         // within 1/8 of the device memory.
         int64_t range = std::max<int64_t>(1, std::min<int64_t>(c->rays_per_launch, kSplitRays));
-        if (c->n_scat > 0) {
+        if (P.n_scat > 0) {
             size_t free_b = 0, total_b = 0;
             HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
             const int64_t fit = (int64_t)(total_b / 8 / (sizeof(SegEntry) * (size_t)(P.B + 1)));
             range = std::min(range, std::max<int64_t>(int64_t(1) << 16, fit));
         }
-        if (c->n_scat > 0) {
+        if (P.n_scat > 0) {
             const int64_t waves = ur_extend_max_waves();
             if (waves < 0) return c->fail(UR_ERR_HIP, "occupancy query failed");
             const int64_t cap = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1)) * (int64_t)(P.B + 1) +
@@ -631,7 +644,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             HIP_TRY(c, hipEventRecord(ev[0], s));
             HIP_TRY(c, ur_launch_extend(P, stats != nullptr, s));
             HIP_TRY(c, hipEventRecord(ev[1], s));
-            if (c->n_scat > 0) HIP_TRY(c, ur_launch_scatter(P, stats != nullptr, s));
+            if (P.n_scat > 0) HIP_TRY(c, ur_launch_scatter(P, stats != nullptr, s));
             HIP_TRY(c, hipEventRecord(ev[2], s));
             HIP_TRY(c, ur_launch_nee(P, stats != nullptr, s));
             HIP_TRY(c, hipEventRecord(ev[3], s));

@@ -1,7 +1,11 @@
 // Host self-check of the scatterer grid and the DDA walk used on the device
 // (same header): for random segments inside the box, the captures found by
 // the walk with interval ownership equal the brute-force set, each once.
-// usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed>
+// With a receive cone (x_lo x_hi alpha_c), scatterers no element can hear are
+// left out of the grid: the walk must then find exactly the captures of the
+// kept scatterers, and every capture point of a left-out one must lie outside
+// the acceptance cone of every element centre.
+// usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed> [x_lo x_hi alpha_c]
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
@@ -24,9 +28,19 @@ int main(int argc, char **argv) {
     std::fclose(f);
     double rs = std::atof(argv[4]);
     long nseg = std::atol(argv[5]);
-    ScatterGrid g = build_scatter_grid(box.data(), S.data(), n, rs, rs * 1e-5 + 1e-6);
-    // structure: every scatterer registered in the cell that holds its centre
+    const bool cull = argc >= 10;
+    RxCone rx{0.0, 0.0, M_PI};
+    if (cull) rx = RxCone{std::atof(argv[7]), std::atof(argv[8]), std::atof(argv[9])};
+    ScatterGrid g = build_scatter_grid(box.data(), S.data(), n, rs, rs * 1e-5 + 1e-6, cull ? &rx : nullptr);
+    std::vector<char> kept(n, 0);
+    for (int i : g.items) kept[i] = 1;
+    long n_kept = 0;
+    for (long i = 0; i < n; ++i) n_kept += kept[i];
+    if (n_kept != g.kept) { std::printf("kept count %ld != %ld\n", n_kept, g.kept); return 1; }
+    if (!cull && n_kept != n) { std::printf("scatterers missing without a cull\n"); return 1; }
+    // structure: every kept scatterer registered in the cell that holds its centre
     for (long i = 0; i < n; ++i) {
+        if (!kept[i]) continue;
         int c[3];
         bool inside = true;
         for (int k = 0; k < 3; ++k) {
@@ -42,7 +56,8 @@ int main(int argc, char **argv) {
     std::mt19937_64 rng(std::atol(argv[6]));
     std::uniform_real_distribution<double> U(0, 1);
     std::normal_distribution<double> N(0, 1);
-    long bad = 0, events = 0, cells = 0, tests = 0;
+    long bad = 0, events = 0, cells = 0, tests = 0, culled_events = 0, heard_culled = 0;
+    const int n_el = 128;
     for (long q = 0; q < nseg; ++q) {
         double o[3], d[3], l = 0;
         for (int k = 0; k < 3; ++k) o[k] = box[k] + (box[3 + k] - box[k]) * U(rng);
@@ -64,7 +79,20 @@ int main(int argc, char **argv) {
             double s = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
             if (!(s >= 0 && s < tend)) continue;
             double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
-            if (pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2] <= rs * rs) want.push_back((int)i);
+            if (!(pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2] <= rs * rs)) continue;
+            if (kept[i]) {
+                want.push_back((int)i);
+                continue;
+            }
+            // a left-out capture: its point must be outside every element's cone
+            ++culled_events;
+            const double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+            for (int e = 0; e < n_el; ++e) {
+                const double xe = rx.x_lo + (rx.x_hi - rx.x_lo) * e / (n_el - 1);
+                const double v[3] = {xe - q[0], -q[1], -q[2]};
+                const double cosa = -v[2] / std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (cosa >= std::cos(rx.alpha_c)) ++heard_culled;
+            }
         }
         cells += dda_walk(g.info, o, d, tend, [&](int cell, double ta, double tb) {
             for (int j = g.cell_start[cell]; j < g.cell_start[cell + 1]; ++j) {
@@ -83,8 +111,9 @@ int main(int argc, char **argv) {
         if (want != got) ++bad;
         events += (long)want.size();
     }
-    std::printf("grid %dx%dx%d h=%.3g items=%zu segments=%ld events=%ld cells/seg=%.1f tests/seg=%.1f bad=%ld\n",
-                g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, g.items.size(), nseg, events,
-                (double)cells / nseg, (double)tests / nseg, bad);
-    return bad ? 1 : 0;
+    std::printf("grid %dx%dx%d h=%.3g kept=%ld items=%zu segments=%ld events=%ld culled_events=%ld "
+                "cells/seg=%.1f tests/seg=%.1f bad=%ld heard_culled=%ld\n",
+                g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, n_kept, g.items.size(), nseg, events, culled_events,
+                (double)cells / nseg, (double)tests / nseg, bad, heard_culled);
+    return bad || heard_culled ? 1 : 0;
 }

@@ -68,12 +68,14 @@ def grid_checker(tmp_path_factory):
     return exe, d
 
 
-def _run_grid(grid_checker, scat, box, r_s, n_seg, seed=1):
+def _run_grid(grid_checker, scat, box, r_s, n_seg, seed=1, rx=None):
     exe, d = grid_checker
     sp, bp = str(d / "s.bin"), str(d / "b.bin")
     np.ascontiguousarray(scat, np.float64).tofile(sp)
     np.ascontiguousarray(box, np.float64).tofile(bp)
-    r = subprocess.run([exe, sp, str(len(scat)), bp, repr(r_s), str(n_seg), str(seed)], capture_output=True, text=True)
+    extra = [repr(float(v)) for v in rx] if rx is not None else []
+    r = subprocess.run([exe, sp, str(len(scat)), bp, repr(r_s), str(n_seg), str(seed)] + extra,
+                       capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return r.stdout
 
@@ -99,3 +101,25 @@ def test_scatter_grid_edge_cases(grid_checker):
     assert "bad=0" in out
     out = _run_grid(grid_checker, scat[:1], box, 1.5e-4, 100)
     assert "bad=0" in out
+
+
+def _field(out, name):
+    return float(out.split(name + "=")[1].split()[0])
+
+
+@pytest.mark.parametrize("alpha_c_deg,r_s", [(2.0, 1.54e-4), (2.0, 2e-3), (20.0, 1e-3), (89.0, 1e-3), (90.0, 1e-3)])
+def test_scatter_grid_audibility_cull(grid_checker, alpha_c_deg, r_s):
+    """Scatterers left out of the grid because no element hears them: every
+    capture point of a left-out scatterer lies outside the acceptance cone of
+    all 128 element centres, and the walk over the smaller (clipped) grid
+    finds exactly the captures of the kept scatterers."""
+    w = scenes.bone(rays_per_element=1, n_scatterers=20000)
+    xe = (np.arange(128) - 63.5) * w.acq.pitch
+    rx = (xe[0], xe[-1], np.radians(alpha_c_deg))
+    out = _run_grid(grid_checker, w.scene.scat, w.scene.box, r_s, 1500, seed=3, rx=rx)
+    assert "bad=0" in out and "heard_culled=0" in out, out
+    kept = _field(out, "kept")
+    if alpha_c_deg >= 90.0:
+        assert kept == 20000
+    if alpha_c_deg == 2.0:
+        assert kept < 0.25 * 20000 and _field(out, "culled_events") > 0, out

@@ -19,9 +19,22 @@ pytestmark = pytest.mark.gpu
 
 TOL_CH = 1e-4          # channel data, relative L2
 TOL_SIG = 2e-5         # FP32 pulse / DAS on identical inputs: ~1e-6 expected from FP32 taps and sums
-EXACT_STATS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
+EXACT_STATS = ["rays", "segments", "reflect", "transmit", "tir", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
                "term_time", "term_path", "media_mismatch"]
+
+
+def assert_stats(st, ost):
+    """Path statistics equal to the oracle's.  The library leaves scatterers
+    that no element can hear out of its grid and so does not count their
+    captures: the captures whose sampled element lies inside the acceptance
+    cone (scatter_events - nee_zero) must match exactly, and the library's
+    capture count can only be lower."""
+    for k in EXACT_STATS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    heard, oheard = st["scatter_events"] - st["nee_zero"], ost["scatter_events"] - ost["nee_zero"]
+    assert heard == oheard, ("heard captures", heard, oheard)
+    assert st["scatter_events"] <= ost["scatter_events"]
 
 
 def rel_l2(a, b):
@@ -49,8 +62,7 @@ def _compare_trace(oracle, w, stride=1, label=""):
     st = s.trace(stats=True, ray_stride=stride, pulse=False)
     g = s.ch_raw.cpu().numpy().astype(np.float64)
     ref, ost = oracle.trace(w, ray_stride=stride)
-    for k in EXACT_STATS:
-        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert_stats(st, ost)
     assert np.array_equal(g != 0, ref != 0)
     err = rel_l2(g, ref)
     print(f"[parity] {label} records={ost['records']} rel_l2={err:.3e}", flush=True)
@@ -88,7 +100,9 @@ def test_explicit_rays_same_events(torch_gpu, oracle):
     for a, b in zip(ev_g, ev_o):
         assert (a["kind"], a["seg"], a["id"], a["elem"]) == (b["kind"], b["seg"], b["id"], b["elem"])
         assert abs(a["t"] - b["t"]) <= 1e-15 + 1e-12 * abs(b["t"])
-        assert abs(a["value"] - b["value"]) <= 1e-12 * abs(b["value"]) + 1e-300
+        # values carry FP32 attenuation factors exp(x): about 1.2e-7 + 6e-8 |x|
+        # relative each, at most max_bounces + 3 of them per record
+        assert abs(a["value"] - b["value"]) <= 1e-5 * abs(b["value"]) + 1e-300
         n_rec += a["kind"] in ("direct", "scatter")
     assert n_rec > 0
 
@@ -188,8 +202,7 @@ def test_proposal_table_sampling(torch_gpu, oracle):
     st = s.trace(stats=True, pulse=False)
     g = s.ch_raw.cpu().numpy()
     ref, ost = oracle.trace(w, pdf=pdf, cdf=cdf)
-    for k in EXACT_STATS:
-        assert st[k] == ost[k], k
+    assert_stats(st, ost)
     assert rel_l2(g, ref) <= TOL_CH
 
 
@@ -320,8 +333,7 @@ def test_ragged_launch_ranges(torch_gpu, oracle):
     g = s.ch_raw.cpu().numpy()
     ref, ost = oracle.trace(w)
     assert ost["rays"] == 32000
-    for k in EXACT_STATS:
-        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert_stats(st, ost)
     assert rel_l2(g, ref) <= TOL_CH
     assert s.ctx.ur_last_trace_kernels_ms()[3] == 11
 
@@ -336,6 +348,5 @@ def test_sampling_queue_overflow_retrace(torch_gpu, oracle):
     st = s.trace(stats=True, pulse=False)
     g = s.ch_raw.cpu().numpy()
     ref, ost = oracle.trace(w)
-    for k in EXACT_STATS:
-        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert_stats(st, ost)
     assert rel_l2(g, ref) <= TOL_CH
