@@ -308,17 +308,10 @@ __device__ __forceinline__ Hit box_exit(const TraceParams &P, const double *o, c
     h.local = -1;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        double t;
-        int fi;
-        if (d[i] > 0.0) {
-            t = (P.box[3 + i] - o[i]) / d[i];
-            fi = 3 + i;
-        } else if (d[i] < 0.0) {
-            t = (P.box[i] - o[i]) / d[i];
-            fi = i;
-        } else {
-            continue;
-        }
+        if (d[i] == 0.0) continue;
+        // face chosen first, one quotient per axis whatever the lane's sign
+        const int fi = d[i] > 0.0 ? 3 + i : i;
+        const double t = ((d[i] > 0.0 ? P.box[3 + i] : P.box[i]) - o[i]) / d[i];
         if (t < h.t) {
             h.t = t;
             h.face = fi;
@@ -689,7 +682,10 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         return false;
     }
     if (h.id == P.id_box) {
-        if (h.face == 2 && fabs(o[0]) <= P.half_ap && fabs(o[1]) <= 0.5 * P.elev) {
+        // (the acos is skipped where the cosine is clearly below cos alpha_c:
+        // Eq. 13 is zero there, and the margin is far above acos's rounding)
+        if (h.face == 2 && fabs(o[0]) <= P.half_ap && fabs(o[1]) <= 0.5 * P.elev &&
+            -d[2] >= P.cos_alpha_c - 1e-9) {
             int er = (int)floor((o[0] + P.half_ap) / P.pitch);
             er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
             const double ca = fmin(1.0, fmax(-1.0, -d[2]));

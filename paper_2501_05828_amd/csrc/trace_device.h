@@ -183,14 +183,13 @@ __device__ __forceinline__ void hemisphere(double a, double b, double *d) {
         d[2] = 1.0;
         return;
     }
-    double r, sp, cp;
-    if (fabs(sa) > fabs(sb)) {
-        r = sa;
-        sincos_quarter((M_PI / 4.0) * (sb / sa), sp, cp);
-    } else {
-        r = sb;
-        sincos_quarter((M_PI / 4.0) * (sa / sb), cp, sp);   // cos(pi/2 - x) = sin x
-    }
+    // one quotient and one polynomial pair for either half of the square, so
+    // the lanes of a wavefront do not run both
+    const bool xa = fabs(sa) > fabs(sb);
+    const double r = xa ? sa : sb, q = xa ? sb : sa;
+    double s1, c1;
+    sincos_quarter((M_PI / 4.0) * (q / r), s1, c1);
+    const double sp = xa ? s1 : c1, cp = xa ? c1 : s1;   // cos(pi/2 - x) = sin x
     const double r2 = r * r, sc = sqrt(2.0 - r2);
     d[0] = r * cp * sc;
     d[1] = r * sp * sc;
