@@ -243,15 +243,14 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
         ++j;
     }
     // sort the four (key, child) pairs ascending: 5 compare-exchanges
-    auto cx = [&](int a, int b) {
-        if (key[b] < key[a]) {
-            const float tk = key[a];
-            key[a] = key[b];
-            key[b] = tk;
-            const int tv = val[a];
-            val[a] = val[b];
-            val[b] = tv;
-        }
+    auto cx = [&](int a, int b) {   // selects, not a branch per exchange
+        const bool sw = key[b] < key[a];
+        const float ka = key[a], kb = key[b];
+        const int va = val[a], vb = val[b];
+        key[a] = sw ? kb : ka;
+        key[b] = sw ? ka : kb;
+        val[a] = sw ? vb : va;
+        val[b] = sw ? va : vb;
     };
     cx(0, 1);
     cx(2, 3);

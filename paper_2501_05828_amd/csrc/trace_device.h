@@ -87,12 +87,16 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
     if (det == 0.0) return false;
     const double t0 = o[0] - v0[0], t1 = o[1] - v0[1], t2 = o[2] - v0[2];
     const double un = t0 * p0 + t1 * p1 + t2 * p2;
-    if (det > 0.0 ? (un < 0.0 || un > det) : (un > 0.0 || un < det)) return false;
+    // the bounds tests for either sign of det, as one test on the values
+    // multiplied by sign(det) (exact), so lanes of both signs share one path
+    const double sg = det > 0.0 ? 1.0 : -1.0, ad = fabs(det), us = un * sg;
+    if (us < 0.0 || us > ad) return false;
     const double q0 = t1 * e1[2] - t2 * e1[1];
     const double q1 = t2 * e1[0] - t0 * e1[2];
     const double q2 = t0 * e1[1] - t1 * e1[0];
     const double vn = d[0] * q0 + d[1] * q1 + d[2] * q2;
-    if (det > 0.0 ? (vn < 0.0 || un + vn > det) : (vn > 0.0 || un + vn < det)) return false;
+    const double vs = vn * sg;
+    if (vs < 0.0 || (un + vn) * sg > ad) return false;
     t = (e2[0] * q0 + e2[1] * q1 + e2[2] * q2) / det;
     return true;
 }
