@@ -178,7 +178,7 @@ __device__ bool shadow_d(const AdjParams &A, const D *q, const D *vh, D dist, in
                                  tq[0] * dd(e1[1]) - tq[1] * dd(e1[0])};
                 const D t = ddot(qq, e2) / det;
                 double nv[3];
-                tri_normal(tr, nv);
+                tri_normal(P, k, nv);
                 const D ng[3] = {dd(nv[0]), dd(nv[1]), dd(nv[2])};
                 cross_at(t, ng, P.tri_mat[2 * k], P.tri_mat[2 * k + 1]);
                 if (T.v == 0.0) return false;
@@ -431,7 +431,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         int mf, mb;
         if (hid < P.id_sph0) {
             double nv[3];
-            tri_normal(P.tri + 9 * (int64_t)hloc, nv);
+            tri_normal(P, hloc, nv);
             for (int i = 0; i < 3; ++i) ng[i] = dd(nv[i]);
             mf = P.tri_mat[2 * hloc];
             mb = P.tri_mat[2 * hloc + 1];

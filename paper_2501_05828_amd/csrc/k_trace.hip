@@ -399,7 +399,7 @@ __device__ __forceinline__ bool shadow(const TraceParams &P, const double *q, co
                 const double *tr = P.tri + 9 * (int64_t)k;
                 if (tri_isect(tr, q, vh, t) && t > lo && t < hi) {
                     double ng[3];
-                    tri_normal(tr, ng);
+                    tri_normal(P, k, ng);
                     cross_at(t, ng, P.tri_mat[2 * k], P.tri_mat[2 * k + 1]);
                     if (T == 0.0) return false;
                 }
@@ -707,7 +707,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
     double ng[3];
     int mf, mb;
     if (h.id < P.id_sph0) {
-        tri_normal(P.tri + 9 * (int64_t)h.local, ng);
+        tri_normal(P, h.local, ng);
         mf = P.tri_mat[2 * h.local];
         mb = P.tri_mat[2 * h.local + 1];
     } else if (h.id < P.id_pln0) {

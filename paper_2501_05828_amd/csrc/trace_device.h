@@ -26,11 +26,12 @@ struct CullRay {
     float ox, oy, oz, ix, iy, iz;
 };
 
-// FP32 reciprocal for the culling slab tests (the boxes are dilated by
-// 1 um, far more than its rounding moves a slab plane along the ray)
+// FP32 reciprocal for the culling slab tests: the hardware estimate (about
+// 1 ulp).  Over a 0.3 m scene it moves a slab plane along the ray by under
+// 0.1 um, far inside the 1 um dilation of the boxes.
 __device__ __forceinline__ float safe_inv(double d) {
     const float a = fabs(d) < 1e-20 ? copysignf(1e-20f, (float)d) : (float)d;
-    return 1.0f / a;
+    return __builtin_amdgcn_rcpf(a);
 }
 
 // Attenuation factor of a ray weight.  Weights decide nothing (every
@@ -101,15 +102,12 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
     return true;
 }
 
-__device__ __forceinline__ void tri_normal(const double *tr, double *n) {
-    const double *e1 = tr + 3, *e2 = tr + 6;
-    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
-    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
-    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
-    const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    n[0] /= l;
-    n[1] /= l;
-    n[2] /= l;
+// Unit geometric normal of triangle k, computed once on the host in FP64
+__device__ __forceinline__ void tri_normal(const TraceParams &P, int64_t k, double *n) {
+    const double4 v = P.tri_n[k];
+    n[0] = v.x;
+    n[1] = v.y;
+    n[2] = v.z;
 }
 
 __device__ __forceinline__ bool sph_roots(const double *s, const double *o, const double *d, double &t0,

@@ -46,7 +46,7 @@ struct ur_context {
     std::vector<double> sph;               // [n_sph][4]
     std::vector<int32_t> item_order;       // scatterer index of each grid item
     GridInfo grid{};
-    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_mat, d_tri_id, d_tnodes, d_tnodes4, d_cell_start, d_items,
+    DevBuf d_mat, d_sph, d_sph_mat, d_pln, d_pln_mat, d_tri, d_tri_n, d_tri_mat, d_tri_id, d_tnodes, d_tnodes4, d_cell_start, d_items,
         d_items_f, d_item_id, d_work;
     // setup
     bool has_setup = false;
@@ -200,6 +200,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.pln = (const double *)c->d_pln.p;
     P.pln_mat = (const int *)c->d_pln_mat.p;
     P.tri = (const double *)c->d_tri.p;
+    P.tri_n = (const double4 *)c->d_tri_n.p;
     P.tri_mat = (const int *)c->d_tri_mat.p;
     P.tri_id = (const int *)c->d_tri_id.p;
     P.tnodes = (const BvhNode *)c->d_tnodes.p;
@@ -283,7 +284,7 @@ UR_API void ur_context_destroy(ur_context *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_mat,
+    for (DevBuf *b : {&c->d_mat, &c->d_sph, &c->d_sph_mat, &c->d_pln, &c->d_pln_mat, &c->d_tri, &c->d_tri_n, &c->d_tri_mat,
                       &c->d_tri_id, &c->d_tnodes, &c->d_tnodes4, &c->d_cell_start, &c->d_items, &c->d_items_f, &c->d_s2, &c->d_item_id, &c->d_work, &c->d_xe, &c->d_tau,
                       &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
@@ -366,6 +367,7 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
             BvhResult r = build_bvh(pb, 4, 1e-6);
             std::vector<double> tri(9 * s->n_tri);
             std::vector<int32_t> tm(2 * s->n_tri), tid(s->n_tri);
+            std::vector<double4> tn(s->n_tri);
             for (int64_t k = 0; k < s->n_tri; ++k) {
                 const int o = r.order[k];
                 const double *v = s->tri + 9 * (int64_t)o;
@@ -374,6 +376,13 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                     tri[9 * k + 3 + j] = v[3 + j] - v[j];
                     tri[9 * k + 6 + j] = v[6 + j] - v[j];
                 }
+                // unit normal: (e1 x e2) / |e1 x e2| in FP64
+                const double *e1 = &tri[9 * k + 3], *e2 = &tri[9 * k + 6];
+                const double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+                const double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+                const double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+                const double l = std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                tn[k] = make_double4(n0 / l, n1 / l, n2 / l, 0.0);
                 tm[2 * k] = s->tri_mat[2 * o];
                 tm[2 * k + 1] = s->tri_mat[2 * o + 1];
                 tid[k] = o;
@@ -383,6 +392,7 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
             c->n_tnodes4 = (int)wide.size();
             if ((st = upload(c, c->d_tnodes4, wide))) return st;
             if ((st = upload(c, c->d_tri, tri))) return st;
+            if ((st = upload(c, c->d_tri_n, tn))) return st;
             if ((st = upload(c, c->d_tri_mat, tm))) return st;
             if ((st = upload(c, c->d_tri_id, tid))) return st;
             if ((st = upload(c, c->d_tnodes, r.nodes))) return st;

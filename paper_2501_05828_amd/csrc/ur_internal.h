@@ -87,6 +87,7 @@ struct TraceParams {
     const int *pln_mat;               // [n_pln][2]
     // triangles in BVH leaf order: v0, e1 = v1 - v0, e2 = v2 - v0
     const double *tri;                // [n_tri][9]
+    const double4 *tri_n;             // [n_tri] unit geometric normal (e1 x e2) / |e1 x e2|, .w unused
     const int *tri_mat;               // [n_tri][2]
     const int *tri_id;                // original index (tie-break, exclusion)
     const BvhNode *tnodes;            // threaded binary tree (any-hit walks, fallback)
