@@ -578,18 +578,32 @@ struct RayState {
 // and, if that runs short, takes a new chunk of kSegChunk with one atomic for
 // the remaining lanes; each lane writes its entry.  No slot is skipped except
 // at the end of a wavefront's last chunk (marked unused by the kernel).
-// Whether the segment o + t d, t in [0, t_end], can pass through the
-// scatterer grid box: an FP32 slab test (the segment's culling origin and
-// reciprocals) against the box grown by 10 um.  The FP32 rounding moves the
-// slab parameters by well under 1 um over the scene, so a segment that
-// reaches the grid box is never dropped; a zero direction component has a
-// reciprocal of +-1e20, which keeps the slab test exact in sign.
-__device__ __forceinline__ bool meets_grid(const TraceParams &P, const CullRay &cr, double t_end) {
+// Whether the segment o + t d, t in [0, t_end], can pass through the part of
+// the scatterer grid box inside its acceptance wedge: FP32 slab and
+// half-space tests (the segment's culling origin and reciprocals) against the
+// box grown by 10 um and the wedge grown by 50 um.  The FP32 rounding moves
+// the clip parameters by well under 1 um over the scene, so a segment that
+// can capture a scatterer some element hears is never dropped; a zero
+// direction component has a reciprocal of +-1e20, which keeps the slab test
+// exact in sign.
+__device__ __forceinline__ bool meets_grid(const TraceParams &P, const CullRay &cr, const double *d, double t_end) {
     const float ax = (P.grid_lo_f[0] - cr.ox) * cr.ix, bx = (P.grid_hi_f[0] - cr.ox) * cr.ix;
     const float ay = (P.grid_lo_f[1] - cr.oy) * cr.iy, by = (P.grid_hi_f[1] - cr.oy) * cr.iy;
     const float az = (P.grid_lo_f[2] - cr.oz) * cr.iz, bz = (P.grid_hi_f[2] - cr.oz) * cr.iz;
-    const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
-    const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), cull_tmax(t_end) + 1e-5f));
+    float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), cull_tmax(t_end) + 1e-5f));
+    if (P.grid_wb_f >= 0.0f) {
+        const float dy = (float)d[1], dz = (float)d[2];
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const float c0 = (float)sgn * cr.oy - P.grid_wb_f * cr.oz - P.grid_wa_f;
+            const float c1 = (float)sgn * dy - P.grid_wb_f * dz;
+            const float tb = -c0 * __builtin_amdgcn_rcpf(c1);
+            t1 = c1 > 0.0f ? fminf(t1, tb) : t1;
+            t0 = c1 < 0.0f ? fmaxf(t0, tb) : t0;
+            if (c1 == 0.0f && c0 > 0.0f) t1 = -1.0f;
+        }
+    }
     return t0 <= t1;
 }
 
@@ -916,7 +930,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         h = box_exit(P, R.o, R.d);
         cr = make_cull(R.o, R.d);
         tmf = cull_tmax(h.t);
-        near_grid = P.n_scat > 0 && meets_grid(P, cr, h.t);   // up to the box exit, the longest it can be
+        near_grid = P.n_scat > 0 && meets_grid(P, cr, R.d, h.t);   // up to the box exit, the longest it can be
         cur = 0;
         sp = 0;
         overflow = false;

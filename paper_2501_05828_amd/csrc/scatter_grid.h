@@ -14,7 +14,9 @@
 // Scatterers that no receiving element can hear (Eq. 13 is zero for every
 // point of their capture ball and every element) may be left out of the grid:
 // each of their captures would yield a zero-valued secondary ray, and a
-// capture changes nothing else on the path.
+// capture changes nothing else on the path.  For the same reason the walk may
+// be clipped to a wedge around the acceptance cones: a capture point outside
+// every cone yields a zero-valued secondary ray too.
 #pragma once
 #include <cmath>
 #include <vector>
@@ -32,6 +34,9 @@ struct GridInfo {
     double lo[3];       // grid origin (box minimum)
     double h, inv_h;    // cell edge [m]
     int n[3];           // cells per axis
+    // acceptance wedge |y| <= wy_a + wy_b z that holds every point some
+    // element can hear (the walk is clipped to it); wy_b < 0: no wedge
+    double wy_a, wy_b;
 };
 
 // Receiving aperture for the audibility cull: element centres on the x axis
@@ -84,6 +89,16 @@ struct DdaIter {
                 t1 = fmin(t1, fmax(a, b));
             } else if (!(o[k] >= lo && o[k] <= hi)) {
                 return false;
+            }
+        }
+        if (g.wy_b >= 0.0) {
+            // the two half-spaces +-y - wy_b z - wy_a <= 0 along the ray
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double c0 = (double)sgn * o[1] - g.wy_b * o[2] - g.wy_a;
+                const double c1 = (double)sgn * d[1] - g.wy_b * d[2];
+                if (c1 > 0.0) t1 = fmin(t1, -c0 / c1);
+                else if (c1 < 0.0) t0 = fmax(t0, -c0 / c1);
+                else if (c0 > 0.0) return false;
             }
         }
         if (!(t0 < t1)) return false;
@@ -155,7 +170,9 @@ UR_HD int dda_walk(const GridInfo &g, const double *o, const double *d, double t
 // the scene box grown by the margin): cell edge chosen for about two
 // registered scatterers per cell (never below four capture radii), at most
 // 2^24 cells.  With rx, scatterers whose capture ball (grown by the margin)
-// no element can hear are left out.
+// no element can hear are left out, and walks are clipped to the wedge
+// |y| <= z tan(alpha_c) + 10 um around the acceptance cones (alpha_c < 80
+// degrees).
 struct ScatterGrid {
     GridInfo info;
     std::vector<int> cell_start;   // [cells + 1]

@@ -217,6 +217,8 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
         P.grid_lo_f[k] = fl;
         P.grid_hi_f[k] = fh;
     }
+    P.grid_wa_f = std::nextafter((float)(c->grid.wy_a + 5e-5), INFINITY);
+    P.grid_wb_f = c->grid.wy_b < 0.0 ? -1.0f : std::nextafter((float)(c->grid.wy_b * (1.0 + 1e-6)), INFINITY);
     P.cell_start = (const int *)c->d_cell_start.p;
     P.items = (const double4 *)c->d_items.p;
     P.items_f = (const float4 *)c->d_items_f.p;

@@ -97,6 +97,7 @@ struct TraceParams {
     // amplitude, and the original index that keys the RNG counter)
     GridInfo grid;
     float grid_lo_f[3], grid_hi_f[3]; // grid box grown by 10 um, rounded outward to FP32 (segment cull)
+    float grid_wa_f, grid_wb_f;       // the grid's acceptance wedge grown by 50 um, FP32 (wb < 0: none)
     const int *cell_start;            // [cells + 1]
     const double4 *items;             // [n_items]
     const float4 *items_f;            // [n_items] positions rounded to FP32, for the conservative prefilter

@@ -2,9 +2,11 @@
 // (same header): for random segments inside the box, the captures found by
 // the walk with interval ownership equal the brute-force set, each once.
 // With a receive cone (x_lo x_hi alpha_c), scatterers no element can hear are
-// left out of the grid: the walk must then find exactly the captures of the
-// kept scatterers, and every capture point of a left-out one must lie outside
-// the acceptance cone of every element centre.
+// left out of the grid and the walk is clipped to a wedge around the cones:
+// every capture point of a left-out scatterer must lie outside the acceptance
+// cone of every element centre, every capture whose point lies inside some
+// cone must be found exactly once, and the walk may report no other pair
+// than a real capture of a kept scatterer (each at most once).
 // usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed> [x_lo x_hi alpha_c]
 #include <cstdio>
 #include <cstdlib>
@@ -56,8 +58,17 @@ int main(int argc, char **argv) {
     std::mt19937_64 rng(std::atol(argv[6]));
     std::uniform_real_distribution<double> U(0, 1);
     std::normal_distribution<double> N(0, 1);
-    long bad = 0, events = 0, cells = 0, tests = 0, culled_events = 0, heard_culled = 0;
+    long bad = 0, events = 0, cells = 0, tests = 0, culled_events = 0, heard_culled = 0, heard = 0;
     const int n_el = 128;
+    auto heard_at = [&](const double *q) {
+        for (int e = 0; e < n_el; ++e) {
+            const double xe = rx.x_lo + (rx.x_hi - rx.x_lo) * e / (n_el - 1);
+            const double v[3] = {xe - q[0], -q[1], -q[2]};
+            const double cosa = -v[2] / std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (cosa >= std::cos(rx.alpha_c)) return true;
+        }
+        return false;
+    };
     for (long q = 0; q < nseg; ++q) {
         double o[3], d[3], l = 0;
         for (int k = 0; k < 3; ++k) o[k] = box[k] + (box[3 + k] - box[k]) * U(rng);
@@ -73,26 +84,24 @@ int main(int argc, char **argv) {
             if (d[k] < 0) tend = std::fmin(tend, (box[k] - o[k]) / d[k]);
         }
         tend *= U(rng) < 0.3 ? U(rng) : 1.0;
-        std::vector<int> want, got;
+        std::vector<int> want, must, got;   // kept captures; captures some element hears
         for (long i = 0; i < n; ++i) {
             double p[3] = {S[4 * i] - o[0], S[4 * i + 1] - o[1], S[4 * i + 2] - o[2]};
             double s = p[0] * d[0] + p[1] * d[1] + p[2] * d[2];
             if (!(s >= 0 && s < tend)) continue;
             double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
             if (!(pp[0] * pp[0] + pp[1] * pp[1] + pp[2] * pp[2] <= rs * rs)) continue;
+            const double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+            const bool h = cull && heard_at(q);
+            heard += h;
             if (kept[i]) {
                 want.push_back((int)i);
+                if (!cull || h) must.push_back((int)i);
                 continue;
             }
             // a left-out capture: its point must be outside every element's cone
             ++culled_events;
-            const double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
-            for (int e = 0; e < n_el; ++e) {
-                const double xe = rx.x_lo + (rx.x_hi - rx.x_lo) * e / (n_el - 1);
-                const double v[3] = {xe - q[0], -q[1], -q[2]};
-                const double cosa = -v[2] / std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (cosa >= std::cos(rx.alpha_c)) ++heard_culled;
-            }
+            heard_culled += h;
         }
         cells += dda_walk(g.info, o, d, tend, [&](int cell, double ta, double tb) {
             for (int j = g.cell_start[cell]; j < g.cell_start[cell + 1]; ++j) {
@@ -107,13 +116,17 @@ int main(int argc, char **argv) {
             return true;
         });
         std::sort(want.begin(), want.end());
+        std::sort(must.begin(), must.end());
         std::sort(got.begin(), got.end());
-        if (want != got) ++bad;
+        if (std::adjacent_find(got.begin(), got.end()) != got.end()) ++bad;             // twice
+        else if (!std::includes(want.begin(), want.end(), got.begin(), got.end())) ++bad;  // not a capture
+        else if (!std::includes(got.begin(), got.end(), must.begin(), must.end())) ++bad;  // heard, missed
+        else if (!cull && got != want) ++bad;
         events += (long)want.size();
     }
-    std::printf("grid %dx%dx%d h=%.3g kept=%ld items=%zu segments=%ld events=%ld culled_events=%ld "
+    std::printf("grid %dx%dx%d h=%.3g kept=%ld items=%zu segments=%ld events=%ld culled_events=%ld heard=%ld "
                 "cells/seg=%.1f tests/seg=%.1f bad=%ld heard_culled=%ld\n",
                 g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, n_kept, g.items.size(), nseg, events, culled_events,
-                (double)cells / nseg, (double)tests / nseg, bad, heard_culled);
+                heard, (double)cells / nseg, (double)tests / nseg, bad, heard_culled);
     return bad || heard_culled ? 1 : 0;
 }

@@ -111,14 +111,16 @@ def _field(out, name):
 def test_scatter_grid_audibility_cull(grid_checker, alpha_c_deg, r_s):
     """Scatterers left out of the grid because no element hears them: every
     capture point of a left-out scatterer lies outside the acceptance cone of
-    all 128 element centres, and the walk over the smaller (clipped) grid
-    finds exactly the captures of the kept scatterers."""
+    all 128 element centres, and the walk over the smaller grid, clipped to
+    the wedge around the cones, finds every capture whose point some element
+    hears exactly once and reports nothing that is not a capture."""
     w = scenes.bone(rays_per_element=1, n_scatterers=20000)
     xe = (np.arange(128) - 63.5) * w.acq.pitch
     rx = (xe[0], xe[-1], np.radians(alpha_c_deg))
     out = _run_grid(grid_checker, w.scene.scat, w.scene.box, r_s, 1500, seed=3, rx=rx)
     assert "bad=0" in out and "heard_culled=0" in out, out
     kept = _field(out, "kept")
+    assert _field(out, "heard") > 0, out
     if alpha_c_deg >= 90.0:
         assert kept == 20000
     if alpha_c_deg == 2.0:
