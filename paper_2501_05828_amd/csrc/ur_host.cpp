@@ -366,7 +366,9 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                     pb[i].hi[k] = std::max(v[k], std::max(v[3 + k], v[6 + k]));
                 }
             }
-            BvhResult r = build_bvh(pb, 4, 1e-6);
+            // one triangle per leaf: a four-wide FP32 node visit costs less
+            // than the FP64 triangle tests a larger leaf would add
+            BvhResult r = build_bvh(pb, 1, 1e-6);
             std::vector<double> tri(9 * s->n_tri);
             std::vector<int32_t> tm(2 * s->n_tri), tid(s->n_tri);
             std::vector<double4> tn(s->n_tri);

@@ -67,7 +67,8 @@ int main(int argc, char **argv) {
                 pb[i].hi[k] = P[4 * i + k] + rad;
             }
         }
-    BvhResult r = build_bvh(pb, tri ? 4 : 8, dil);
+    const int leaf_max = argc > 8 ? std::atoi(argv[8]) : (tri ? 1 : 8);
+    BvhResult r = build_bvh(pb, leaf_max, dil);
     const int nn = (int)r.nodes.size();
     std::vector<int> seen(n, 0), slot_of(n, -1);
     for (long k = 0; k < n; ++k) slot_of[r.order[k]] = (int)k;

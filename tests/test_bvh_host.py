@@ -26,19 +26,22 @@ def checker(tmp_path_factory):
     return exe, d
 
 
-def _run(checker, arr, kind, dilate, radius, n_rays, seed=1):
+def _run(checker, arr, kind, dilate, radius, n_rays, seed=1, leaf_max=None):
     exe, d = checker
     path = str(d / f"{kind}.bin")
     np.ascontiguousarray(arr, np.float64).tofile(path)
-    r = subprocess.run([exe, path, str(len(arr)), kind, repr(dilate), repr(radius), str(n_rays), str(seed)],
+    extra = [str(leaf_max)] if leaf_max is not None else []
+    r = subprocess.run([exe, path, str(len(arr)), kind, repr(dilate), repr(radius), str(n_rays), str(seed)] + extra,
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return r.stdout
 
 
-def test_triangle_bvh_bone_mesh(checker):
+@pytest.mark.parametrize("leaf_max", [1, 4])
+def test_triangle_bvh_bone_mesh(checker, leaf_max):
+    """The library's single-triangle leaves, and leaves of up to four."""
     w = scenes.bone(rays_per_element=1)
-    out = _run(checker, w.scene.tri, "tri", 1e-6, 0.0, 300)
+    out = _run(checker, w.scene.tri, "tri", 1e-6, 0.0, 300, leaf_max=leaf_max)
     assert "missed 0" in out
 
 
