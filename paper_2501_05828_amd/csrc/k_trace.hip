@@ -430,22 +430,20 @@ __device__ __forceinline__ bool shadow(const TraceParams &P, const double *q, co
 
 // Scatterer k captured at distance s along the segment (Sec. 2.3
 // "Transducer Sampling"): the capture re-radiates toward a uniformly chosen
-// element centre.  Fills the candidate and returns true if the receive
-// directivity (Eq. 13) of that element is non-zero.
+// element centre.  In two steps.  nee_point places the capture point q and
+// returns false (a zero-valued capture) when no element at all can accept it:
+// the cut-off test of nee_candidate only gets easier to meet as the lateral
+// offset vx^2 to the drawn element grows, so if it holds already at vx = 0
+// (with a relative margin far above the rounding of either side) it holds for
+// every element, and the element draw is skipped.
 template <bool COUNT>
-__device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cnt, int tx, int e, uint32_t ray,
-                                              int seg, int k, double amp, const double *o, const double *d,
-                                              double w, double t, int med, double s, int cell, NeeEntry &c) {
-    const Material M = P.mat[med];
+__device__ __forceinline__ bool nee_point(const TraceParams &P, Counters &cnt, const double *o, const double *d,
+                                          double s, NeeEntry &c) {
     c.q[0] = o[0] + s * d[0];
     c.q[1] = o[1] + s * d[1];
     c.q[2] = o[2] + s * d[2];
     const double cc = P.cos_alpha_c;
     if (cc >= 0.0) {
-        // The cut-off test below only gets easier to meet as the lateral
-        // offset vx^2 to the drawn element grows.  If it holds already at
-        // vx = 0 (with a relative margin far above the rounding of either
-        // side) it holds for every element, and the element draw is skipped.
         const double vy = c.q[1], mvz = c.q[2];
         if (mvz < 0.0 || mvz * mvz < cc * cc * (vy * vy + mvz * mvz) * (1.0 - 1e-9)) {
             CNT(C_SCAT_EVENTS);
@@ -453,6 +451,17 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
             return false;
         }
     }
+    return true;
+}
+
+// The element draw and the receive directivity (Eq. 13) for a capture point
+// placed by nee_point.  Fills the candidate and returns true if the
+// directivity of the drawn element is non-zero.
+template <bool COUNT>
+__device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cnt, int tx, int e, uint32_t ray,
+                                              int seg, int k, double amp, double w, double t, int med, double s,
+                                              int cell, NeeEntry &c) {
+    const double cc = P.cos_alpha_c;
     uint32_t x[4];
     draw(P, ray, e, tx, seg, 2, (uint32_t)k, x);
     const int er = (int)(((uint64_t)x[0] * (uint64_t)P.E) >> 32);
@@ -467,6 +476,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
         CNT(C_NEE_ZERO);
         return false;
     }
+    const Material M = P.mat[med];
     c.wq = w * atten(-M.ka * s) * amp;
     c.tq = t + s * M.inv_c;
     c.tx = tx;
@@ -550,7 +560,9 @@ __device__ __forceinline__ void scatter_events(const TraceParams &P, const Event
                 const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
                 if (dot3(pp, pp) > P.r_s2) continue;
                 NeeEntry c;
-                if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, o, d, w, t, med, s, cell, c)) continue;
+                if (!nee_point<COUNT>(P, cnt, o, d, s, c) ||
+                    !nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[j], sk.w, w, t, med, s, cell, c))
+                    continue;
                 if constexpr (LOG || MODE == kInlineNeeOnly) {
                     nee_cast<COUNT, LOG>(P, L, cnt, c);
                 } else {
@@ -641,20 +653,20 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
     }
     // streaming (non-temporal) stores: the queue is read once, by another
     // kernel, and should not displace the tree and grid from the L2
-    SegEntry &E = P.segq[slot];
+    SegHot &E = P.segq[slot];
     for (int k = 0; k < 3; ++k) {
         __builtin_nontemporal_store(R.o[k], &E.o[k]);
         __builtin_nontemporal_store(R.d[k], &E.d[k]);
     }
-    __builtin_nontemporal_store(R.w, &E.w);
-    __builtin_nontemporal_store(R.t, &E.t);
     __builtin_nontemporal_store(t_seg, &E.t_seg);
-    __builtin_nontemporal_store(R.med, &E.med);
-    __builtin_nontemporal_store(R.seg, &E.seg);
-    __builtin_nontemporal_store(R.tx, &E.tx);
-    __builtin_nontemporal_store(R.e, &E.e);
     __builtin_nontemporal_store(R.ray, &E.ray);
-    __builtin_nontemporal_store(R.cell, &E.cell);
+    __builtin_nontemporal_store(((uint32_t)R.tx << 16) | (uint32_t)R.e, &E.txe);
+    SegCold &C = P.segc[slot];
+    __builtin_nontemporal_store(R.w, &C.w);
+    __builtin_nontemporal_store(R.t, &C.t);
+    __builtin_nontemporal_store(R.med, &C.med);
+    __builtin_nontemporal_store(R.seg, &C.seg);
+    __builtin_nontemporal_store(R.cell, &C.cell);
 }
 
 // The rest of a segment once its closest hit h is known: scatterer captures
@@ -1003,7 +1015,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // the unused tail of this wavefront's last chunk of the segment queue
     const unsigned long long beg = chunk[0], end = chunk[1];
     for (unsigned long long k = beg + lane; k < end; k += 64)
-        if ((int64_t)k < P.seg_cap) __builtin_nontemporal_store(-1, &P.segq[k].med);
+        if ((int64_t)k < P.seg_cap) __builtin_nontemporal_store(kSegUnused, &P.segq[k].txe);
     flush_counters<COUNT>(P, cnt);
 }
 
@@ -1024,10 +1036,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const unsigned long long reserved = *P.seg_count;
     const unsigned long long n_seg = reserved < (unsigned long long)P.seg_cap ? reserved : (unsigned long long)P.seg_cap;
     const int limit = P.grid.n[0] + P.grid.n[1] + P.grid.n[2] + 3;
-    double o[3], d[3], w = 0.0, t = 0.0, t_seg = 0.0, tb = 0.0;
+    double o[3], d[3], t_seg = 0.0, tb = 0.0;
     float of[3], df[3], taf = 0.0f, tbf = 0.0f;
-    int med = 0, seg = 0, tx = 0, e = 0, cell = 0, j = 0, j1 = 0, visited = 0;
-    uint32_t ray = 0;
+    int j = 0, j1 = 0, visited = 0;
+    uint32_t ray = 0, txe = 0;
+    unsigned long long qslot = 0;
     DdaIter it;
     bool has = false, exhausted = false;
     unsigned long long cbeg = 0, cend = 0;
@@ -1062,23 +1075,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (!exhausted) {
                     const unsigned long long r = cbeg + __popcll(need & ((1ull << lane) - 1ull));
                     if (!has && r < cend) {
-                        const SegEntry &E = P.segq[r];
-                        med = __builtin_nontemporal_load(&E.med);
-                        if (med >= 0) {
+                        const SegHot &E = P.segq[r];
+                        txe = __builtin_nontemporal_load(&E.txe);
+                        if (txe != kSegUnused) {
                             for (int k = 0; k < 3; ++k) {
                                 o[k] = __builtin_nontemporal_load(&E.o[k]);
                                 d[k] = __builtin_nontemporal_load(&E.d[k]);
                                 of[k] = (float)o[k];
                                 df[k] = (float)d[k];
                             }
-                            w = __builtin_nontemporal_load(&E.w);
-                            t = __builtin_nontemporal_load(&E.t);
                             t_seg = __builtin_nontemporal_load(&E.t_seg);
-                            seg = __builtin_nontemporal_load(&E.seg);
-                            tx = __builtin_nontemporal_load(&E.tx);
-                            e = __builtin_nontemporal_load(&E.e);
                             ray = __builtin_nontemporal_load(&E.ray);
-                            cell = __builtin_nontemporal_load(&E.cell);
+                            qslot = r;
                             // the walk covers the part of the segment inside
                             // the grid box; t_seg becomes the end of that part
                             if (it.init(P.grid, o, d, t_seg, t_seg)) {
@@ -1123,7 +1131,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const double pp[3] = {p[0] - s * d[0], p[1] - s * d[1], p[2] - s * d[2]};
                 if (dot3(pp, pp) > P.r_s2) continue;
                 NeeEntry c;
-                if (!nee_candidate<COUNT>(P, cnt, tx, e, ray, seg, P.item_id[jj], sk.w, o, d, w, t, med, s, cell, c))
+                if (!nee_point<COUNT>(P, cnt, o, d, s, c)) continue;
+                // the capture-only part of the segment, read only here
+                const SegCold &C = P.segc[qslot];
+                if (!nee_candidate<COUNT>(P, cnt, (int)(txe >> 16), (int)(txe & 0xffffu), ray, C.seg, P.item_id[jj],
+                                          sk.w, C.w, C.t, C.med, s, C.cell, c))
                     continue;
                 const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
                 if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;

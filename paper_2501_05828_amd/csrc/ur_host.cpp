@@ -55,7 +55,7 @@ struct ur_context {
     std::vector<double> angles;
     int K = 0;
     DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
-        d_nee, d_counters, d_segq;
+        d_nee, d_counters, d_segq, d_segc;
     int64_t rays_per_launch = int64_t(1) << 30;
     // proposal network (rows = transmits x elements of the current setup)
     bool mlp_ready = false;
@@ -291,7 +291,8 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_taps, &c->d_apod, &c->d_txc, &c->d_stats, &c->d_stats2, &c->d_maxbits, &c->d_env,
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
-                      &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal})
+                      &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal, &c->d_segq, &c->d_segc,
+                      &c->d_giq})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -617,7 +618,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         if (P.n_scat > 0) {
             size_t free_b = 0, total_b = 0;
             HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
-            const int64_t fit = (int64_t)(total_b / 8 / (sizeof(SegEntry) * (size_t)(P.B + 1)));
+            const int64_t fit = (int64_t)(total_b / 8 / ((sizeof(SegHot) + sizeof(SegCold)) * (size_t)(P.B + 1)));
             range = std::min(range, std::max<int64_t>(int64_t(1) << 16, fit));
         }
         if (P.n_scat > 0) {
@@ -625,8 +626,10 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             if (waves < 0) return c->fail(UR_ERR_HIP, "occupancy query failed");
             const int64_t cap = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1)) * (int64_t)(P.B + 1) +
                                 waves * kSegChunk;
-            if ((st = alloc(c, c->d_segq, (size_t)cap * sizeof(SegEntry)))) return st;
-            P.segq = (SegEntry *)c->d_segq.p;
+            if ((st = alloc(c, c->d_segq, (size_t)cap * sizeof(SegHot)))) return st;
+            if ((st = alloc(c, c->d_segc, (size_t)cap * sizeof(SegCold)))) return st;
+            P.segq = (SegHot *)c->d_segq.p;
+            P.segc = (SegCold *)c->d_segc.p;
             P.seg_cap = cap;
         }
         const int64_t launches = (P.n_work + range - 1) / range;

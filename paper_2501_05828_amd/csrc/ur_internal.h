@@ -27,18 +27,23 @@ struct Material {
 
 // Transducer-sampling candidate: a scatterer capture whose chosen element
 // passes the receive cut-off; the secondary ray is cast by a later kernel.
-// One primary-ray segment waiting for its scatterer walk (96 bytes): the
-// state at the segment start, its length, and what the captures need.
-// med < 0 marks an unused slot.
-struct SegEntry {
+// One primary-ray segment waiting for its scatterer walk, in two arrays: the
+// part every walk reads (64 bytes: start, direction, length, ray and
+// transmit/element) and the part only a capture that some element may hear
+// reads (32 bytes: weight, time, medium, segment index, emission cell).
+// txe = transmit << 16 | element; kSegUnused marks an unused slot.
+struct SegHot {
     double o[3], d[3];
-    double w, t, t_seg;
-    int med, seg, tx, e;
-    uint32_t ray;
-    int cell;
+    double t_seg;
+    uint32_t ray, txe;
 };
+struct SegCold {
+    double w, t;
+    int med, seg, cell, pad;
+};
+constexpr uint32_t kSegUnused = 0xffffffffu;
 
-static_assert(sizeof(SegEntry) == 96, "segment entry layout");
+static_assert(sizeof(SegHot) == 64 && sizeof(SegCold) == 32, "segment entry layout");
 
 struct NeeEntry {
     double q[3];       // capture point on the primary segment
@@ -111,7 +116,8 @@ struct TraceParams {
     unsigned long long *work_next;    // persistent-kernel work counter (zeroed before launch)
     int64_t work_begin, work_end;     // work items [begin, end) of this launch
     float *cost;                      // [T*E][1024] per-emission-cell path cost, or null
-    SegEntry *segq;                   // segment queue between the extend and scatter kernels
+    SegHot *segq;                     // segment queue between the extend and scatter kernels
+    SegCold *segc;                    // its capture-only part, same slots
     unsigned long long *seg_count;    // slots reserved (chunks of kSegChunk)
     unsigned long long *seg_next;     // scatter-kernel work counter
     unsigned long long *seg_lost;     // segments that found no slot (must stay 0)

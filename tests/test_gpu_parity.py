@@ -338,6 +338,32 @@ def test_ragged_launch_ranges(torch_gpu, oracle):
     assert s.ctx.ur_last_trace_kernels_ms()[3] == 11
 
 
+def test_context_destroy_returns_device_memory(torch_gpu):
+    """Contexts that traced (segment queue, secondary-ray queue, grid) give
+    all their device memory back when destroyed."""
+    from paper_2501_05828_amd import binding
+    w = scenes.tiny(rays_per_element=512)
+
+    def one():
+        ctx = binding.Context(0)
+        ctx.ur_scene_upload(w.scene)
+        ctx.ur_transmit_setup(w.acq)
+        buf = torch_gpu.zeros((1, w.acq.n_elements, w.acq.n_samples), device="cuda")
+        ctx.ur_trace(w.seed, buf)
+        torch_gpu.cuda.synchronize()
+        ctx.close()
+        del buf
+
+    one()
+    torch_gpu.cuda.empty_cache()
+    free0 = torch_gpu.cuda.mem_get_info()[0]
+    for _ in range(4):
+        one()
+    torch_gpu.cuda.empty_cache()
+    free1 = torch_gpu.cuda.mem_get_info()[0]
+    assert free0 - free1 < 8 << 20, (free0, free1)
+
+
 def test_sampling_queue_overflow_retrace(torch_gpu, oracle):
     """A transducer-sampling queue far too small for the launch: the range is
     traced again with inline secondary rays and the result is unchanged."""
