@@ -281,6 +281,92 @@ int or_interface(const double d[3], const double n[3], double z_front, double z_
     return fresnel_step(d, n, z_front, z_back, y, out_d, R, &ff);
 }
 
+/* ------------------------------------------ rough interfaces (Eq. 12, GGX) */
+/* A boundary between two materials is as rough as the rougher of them.  At a
+ * rough boundary a microfacet normal h is drawn around the macro normal n
+ * (facing the incoming ray) with density D(h) (n.h), D the GGX distribution
+ * of Eq. 12 (Walter et al. 2007, Eqs. 33, 35, 36); Eqs. 7-11 then act with h
+ * in place of n.  The weight factor is Walter et al.'s Eq. 41 with the
+ * separable Smith masking of Eq. 34: |i.h| G1(i) G1(o) / (|i.n| |h.n|).  A
+ * microfacet facing away from the ray, or a new direction on the wrong side
+ * of the macro surface, absorbs the ray. */
+
+/* Orthonormal basis (t, b) completing a unit n: the branch-free
+ * construction of Duff et al., "Building an Orthonormal Basis, Revisited"
+ * (JCGT 6(1), 2017). */
+void or_onb(const double n[3], double t[3], double b[3])
+{
+    double sg = copysign(1.0, n[2]);
+    double a = -1.0 / (sg + n[2]);
+    double c = n[0] * n[1] * a;
+    t[0] = 1.0 + sg * n[0] * n[0] * a;
+    t[1] = sg * c;
+    t[2] = -sg * n[0];
+    b[0] = c;
+    b[1] = sg + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+/* Eq. 12 as printed, in terms of cos(theta_h) = n.h */
+double or_ggx_d(double alpha, double cos_h)
+{
+    double a2 = alpha * alpha;
+    double q = cos_h * cos_h * (a2 - 1.0) + 1.0;
+    return a2 / (PI * q * q);
+}
+
+/* h with density D(h) (n.h): tan^2(theta) = alpha^2 xi1 / (1 - xi1), phi = 2 pi xi2 */
+void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, double h[3])
+{
+    double t[3], b[3];
+    or_onb(n, t, b);
+    double q = 1.0 - xi1 + alpha * alpha * xi1;
+    double ct = sqrt((1.0 - xi1) / q), st = alpha * sqrt(xi1 / q);
+    double ph = 2.0 * PI * xi2;
+    double cp = cos(ph), sp = sin(ph);
+    for (int i = 0; i < 3; ++i) h[i] = st * cp * t[i] + st * sp * b[i] + ct * n[i];
+}
+
+/* Smith masking for GGX (Walter et al. Eq. 34) at cos(theta_v) = v.n > 0 */
+double or_ggx_g1(double alpha, double cos_v)
+{
+    double tan2 = (1.0 - cos_v * cos_v) / (cos_v * cos_v);
+    return 2.0 / (1.0 + sqrt(1.0 + alpha * alpha * tan2));
+}
+
+static int rough_step(const double d[3], const double ng[3], double z_front, double z_back, double alpha,
+                      double y, double xi1, double xi2, double od[3], double *R_out, int *from_front,
+                      double *wf)
+{
+    double n[3] = {ng[0], ng[1], ng[2]};
+    double z1, z2;
+    if (dot3(d, n) < 0.0) {
+        z1 = z_front; z2 = z_back; *from_front = 1;
+    } else {
+        z1 = z_back; z2 = z_front; *from_front = 0;
+        n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2];
+    }
+    *wf = 0.0;
+    *R_out = 0.0;
+    double h[3];
+    or_ggx_sample(n, alpha, xi1, xi2, h);
+    double ci = -dot3(d, h), cn = -dot3(d, n);
+    if (!(ci > 0.0)) return -1;                 /* the microfacet faces away */
+    int dummy;
+    int refl = fresnel_step(d, h, z1, z2, y, od, R_out, &dummy);   /* Eqs. 7-11 about h */
+    double co = dot3(od, n);
+    if (refl ? !(co > 0.0) : !(co < 0.0)) return -1;               /* wrong side of the surface */
+    *wf = ci * or_ggx_g1(alpha, cn) * or_ggx_g1(alpha, fabs(co)) / (cn * dot3(h, n));
+    return refl;
+}
+
+int or_interface_rough(const double d[3], const double n[3], double z_front, double z_back, double alpha,
+                       double y, double xi1, double xi2, double out_d[3], double *R, double *wf)
+{
+    int ff;
+    return rough_step(d, n, z_front, z_back, alpha, y, xi1, xi2, out_d, R, &ff, wf);
+}
+
 /* Transmitted intensity fraction 1 - A_r^2 for a straight (unbent) crossing. */
 static double transmit_fraction(double z1, double z2, double cos_r)
 {
@@ -706,8 +792,22 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
         uint32_t x[4];
         draw(C, ray, e, tx, b, 1, 0, x);
         double y = unif(x[0]), R, nd[3];
-        int from_front;
-        int refl = fresnel_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], y, nd, &R, &from_front);
+        int from_front, refl;
+        double alpha = 0.0;
+        if (sc->rough) alpha = sc->rough[mf] > sc->rough[mb] ? sc->rough[mf] : sc->rough[mb];
+        if (alpha > 0.0) {
+            double wf;
+            refl = rough_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], alpha, y, unif(x[1]), unif(x[2]), nd, &R,
+                              &from_front, &wf);
+            if (refl < 0) {
+                K->st.term_rough++;
+                log_event(K, 4, tx, e, b, -5, t, w, o);
+                return;
+            }
+            w *= wf;
+        } else {
+            refl = fresnel_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], y, nd, &R, &from_front);
+        }
         int64_t before = from_front ? mf : mb, after = from_front ? mb : mf;
         if (before != med) K->st.media_mismatch++;
         if (refl) {

@@ -43,12 +43,13 @@ typedef struct {
     const double *pln;         /* [n_pln][4]: n, d with n.x = d  */
     const int32_t *pln_mat;    /* [n_pln][2]: front, back        */
     const double *scat;        /* [n_scat][4]: position, amplitude */
+    const double *rough;       /* [n_mat]: GGX roughness alpha (Eq. 12), 0 = smooth; NULL: all smooth */
 } or_scene;
 
 typedef struct {
     int64_t rays, segments, reflect, transmit, tir, scatter_events, nee_zero, nee_cast,
             nee_blocked, direct_hits, records, dropped, edge_band, term_box, term_bounce,
-            term_time, term_path, media_mismatch;
+            term_time, term_path, media_mismatch, term_rough;
 } or_stats;
 
 /* One entry of a path log (explicit-ray tracing). */
@@ -87,6 +88,13 @@ void or_hemisphere(double a, double b, double d[3]);
 double or_directivity(double alpha, double alpha_m, double alpha_c);
 int or_interface(const double d[3], const double n[3], double z_front, double z_back, double y,
                  double out_d[3], double *R);
+/* Rough boundary (Eq. 12): returns 1 reflect, 0 transmit, -1 absorbed; *wf the weight factor. */
+int or_interface_rough(const double d[3], const double n[3], double z_front, double z_back, double alpha,
+                       double y, double xi1, double xi2, double out_d[3], double *R, double *wf);
+void or_onb(const double n[3], double t[3], double b[3]);
+void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, double h[3]);
+double or_ggx_d(double alpha, double cos_h);
+double or_ggx_g1(double alpha, double cos_v);
 double or_delay(const or_acq *a, int64_t tx, int64_t e);
 int64_t or_closest_hit(const or_scene *s, const double o[3], const double d[3], int64_t skip,
                        double *t_hit);

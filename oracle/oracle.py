@@ -45,12 +45,12 @@ class SceneS(C.Structure):
                 ("tri", C.POINTER(C.c_double)), ("tri_mat", C.POINTER(C.c_int32)),
                 ("sph", C.POINTER(C.c_double)), ("sph_mat", C.POINTER(C.c_int32)),
                 ("pln", C.POINTER(C.c_double)), ("pln_mat", C.POINTER(C.c_int32)),
-                ("scat", C.POINTER(C.c_double))]
+                ("scat", C.POINTER(C.c_double)), ("rough", C.POINTER(C.c_double))]
 
 
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
-               "term_time", "term_path", "media_mismatch"]
+               "term_time", "term_path", "media_mismatch", "term_rough"]
 
 
 class Stats(C.Structure):
@@ -100,6 +100,15 @@ def lib():
         L.or_directivity.restype = C.c_double
         L.or_interface.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
                                    P(C.c_double), P(C.c_double)]
+        L.or_interface_rough.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.c_double, P(C.c_double), P(C.c_double),
+                                         P(C.c_double)]
+        L.or_onb.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.or_ggx_sample.argtypes = [P(C.c_double), C.c_double, C.c_double, C.c_double, P(C.c_double)]
+        L.or_ggx_d.argtypes = [C.c_double, C.c_double]
+        L.or_ggx_d.restype = C.c_double
+        L.or_ggx_g1.argtypes = [C.c_double, C.c_double]
+        L.or_ggx_g1.restype = C.c_double
         L.or_delay.argtypes = [P(Acq), C.c_int64, C.c_int64]
         L.or_delay.restype = C.c_double
         L.or_closest_hit.argtypes = [P(SceneS), P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double)]
@@ -167,10 +176,14 @@ def make_scene(sc, keep):
     sph = keep.f64(sc.sph, 4)
     pln = keep.f64(sc.pln, 4)
     scat = keep.f64(sc.scat, 4)
-    return SceneS(n_mat=len(mat), n_tri=len(tri), n_sph=len(sph), n_pln=len(pln), n_scat=len(scat),
-                  top_medium=int(sc.top_medium), mat=_dp(mat), box=_dp(box), tri=_dp(tri),
-                  tri_mat=_ip(keep.i32(sc.tri_mat)), sph=_dp(sph), sph_mat=_ip(keep.i32(sc.sph_mat)),
-                  pln=_dp(pln), pln_mat=_ip(keep.i32(sc.pln_mat)), scat=_dp(scat))
+    rough = getattr(sc, "rough", None)
+    s = SceneS(n_mat=len(mat), n_tri=len(tri), n_sph=len(sph), n_pln=len(pln), n_scat=len(scat),
+               top_medium=int(sc.top_medium), mat=_dp(mat), box=_dp(box), tri=_dp(tri),
+               tri_mat=_ip(keep.i32(sc.tri_mat)), sph=_dp(sph), sph_mat=_ip(keep.i32(sc.sph_mat)),
+               pln=_dp(pln), pln_mat=_ip(keep.i32(sc.pln_mat)), scat=_dp(scat))
+    if rough is not None:
+        s.rough = _dp(keep.f64(rough))
+    return s
 
 
 def trace(workload, n_threads: int = 0, ray_stride: int = 1, seed=None, pdf=None, cdf=None, rec_hist=False):
@@ -312,6 +325,39 @@ def interface(d, n, z_front, z_back, y):
     R = C.c_double(0)
     refl = lib().or_interface(dd, nn, float(z_front), float(z_back), float(y), out, C.byref(R))
     return bool(refl), np.array(out[:]), R.value
+
+
+def interface_rough(d, n, z_front, z_back, alpha, y, xi1, xi2):
+    """(kind, new direction, A_r^2, weight factor); kind 1 reflect, 0 transmit, -1 absorbed."""
+    dd = (C.c_double * 3)(*map(float, d))
+    nn = (C.c_double * 3)(*map(float, n))
+    out = (C.c_double * 3)()
+    R, wf = C.c_double(0), C.c_double(0)
+    k = lib().or_interface_rough(dd, nn, float(z_front), float(z_back), float(alpha), float(y), float(xi1),
+                                 float(xi2), out, C.byref(R), C.byref(wf))
+    return int(k), np.array(out[:]), R.value, wf.value
+
+
+def onb(n):
+    nn = (C.c_double * 3)(*map(float, n))
+    t, b = (C.c_double * 3)(), (C.c_double * 3)()
+    lib().or_onb(nn, t, b)
+    return np.array(t[:]), np.array(b[:])
+
+
+def ggx_sample(n, alpha, xi1, xi2):
+    nn = (C.c_double * 3)(*map(float, n))
+    h = (C.c_double * 3)()
+    lib().or_ggx_sample(nn, float(alpha), float(xi1), float(xi2), h)
+    return np.array(h[:])
+
+
+def ggx_d(alpha, cos_h):
+    return lib().or_ggx_d(float(alpha), float(cos_h))
+
+
+def ggx_g1(alpha, cos_v):
+    return lib().or_ggx_g1(float(alpha), float(cos_v))
 
 
 def delay(acq, tx, e):

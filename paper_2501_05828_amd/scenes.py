@@ -39,6 +39,7 @@ class Scene:
     pln: np.ndarray              # (NP,4) float64: unit normal n, offset d (n.x = d)
     pln_mat: np.ndarray          # (NP,2) int32: front (n side) / back material
     scat: np.ndarray             # (K,4) float64: position xyz, amplitude
+    rough: np.ndarray = None     # (M,) float64: GGX roughness alpha (Eq. 12) per material; None: all smooth
 
     def counts(self) -> dict:
         return dict(materials=len(self.materials), triangles=len(self.tri),

@@ -567,3 +567,106 @@ def test_full_trace_tiny_invariants(oracle):
     assert np.allclose(ch, ch2, rtol=1e-12, atol=1e-20)
     ch3, _ = oracle.trace(w, seed=w.seed + 1)
     assert not np.allclose(ch, ch3)
+
+
+# ---------------------------------------------------- rough interfaces (Eq. 12)
+
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 0.5, 1.0, 2.0])
+def test_ggx_distribution_is_normalised(oracle, alpha):
+    """Eq. 12 as printed is a density of microfacet normals projected on the
+    macro surface: the integral of D(h) (n.h) over the hemisphere is 1."""
+    from scipy.integrate import quad
+    val, _ = quad(lambda th: oracle.ggx_d(alpha, math.cos(th)) * math.cos(th) * math.sin(th), 0.0, math.pi / 2,
+                  limit=400, points=[math.atan(alpha)])
+    assert abs(2.0 * math.pi * val - 1.0) < 1e-8
+
+
+def test_ggx_onb_is_orthonormal_and_right_handed(oracle):
+    rng = np.random.default_rng(21)
+    ns = rng.normal(size=(200, 3))
+    ns = np.vstack([ns, [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0], [1.0, 0.0, -0.0], [1e-9, 0.0, -1.0]]])
+    for n in ns:
+        n = n / np.linalg.norm(n)
+        t, b = oracle.onb(n)
+        assert abs(t @ n) < 1e-14 and abs(b @ n) < 1e-14 and abs(t @ b) < 1e-14
+        assert abs(t @ t - 1) < 1e-14 and abs(b @ b - 1) < 1e-14
+        assert np.allclose(np.cross(t, b), n, atol=1e-14)
+
+
+@pytest.mark.parametrize("alpha", [0.2, 0.7])
+def test_ggx_sampler_follows_the_density(oracle, alpha):
+    """Sampled microfacet normals have P(theta_h <= th) = tan^2 th / (alpha^2 +
+    tan^2 th) (the integral of D(h) (n.h) of Eq. 12 over the cap), a uniform
+    azimuth, unit length, and the same law about any macro normal."""
+    from scipy import stats
+    rng = np.random.default_rng(5)
+    xi = rng.random((6000, 2))
+    n = np.array([0.3, -0.5, 0.8])
+    n /= np.linalg.norm(n)
+    t, b = oracle.onb(n)
+    hs = np.array([oracle.ggx_sample(n, alpha, a, c) for a, c in xi])
+    assert np.allclose(np.linalg.norm(hs, axis=1), 1.0, atol=1e-14)
+    th = np.arccos(np.clip(hs @ n, -1, 1))
+    cdf = lambda x: np.tan(x) ** 2 / (alpha ** 2 + np.tan(x) ** 2)
+    assert stats.kstest(th, cdf).pvalue > 1e-3
+    ph = np.mod(np.arctan2(hs @ b, hs @ t), 2 * np.pi) / (2 * np.pi)
+    assert stats.kstest(ph, "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("alpha", [0.2, 0.6, 1.0])
+@pytest.mark.parametrize("theta_deg", [0.0, 30.0, 60.0, 80.0])
+def test_ggx_smith_masking_projected_area(oracle, alpha, theta_deg):
+    """The Smith masking G1 and D satisfy the projected-area identity
+    G1(o) * integral of max(0, o.m) D(m) dm = o.n (visible microfacet area
+    seen from o equals the macro surface's), by 2-D quadrature."""
+    from scipy.integrate import dblquad
+    th_o = math.radians(theta_deg)
+    o = np.array([math.sin(th_o), 0.0, math.cos(th_o)])
+
+    def f(ph, th):
+        m = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        return max(0.0, o @ m) * oracle.ggx_d(alpha, math.cos(th)) * math.sin(th)
+
+    val, _ = dblquad(f, 0.0, math.pi / 2, 0.0, 2 * math.pi, epsabs=1e-10, epsrel=1e-8)
+    assert abs(oracle.ggx_g1(alpha, math.cos(th_o)) * val - math.cos(th_o)) < 2e-6
+
+
+def test_rough_interface_smooth_limit(oracle):
+    """At roughness 1e-13 the rough boundary reproduces Eqs. 7-11 at the
+    macro normal: the same choice, the same direction, weight factor 1."""
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        zf, zb = rng.uniform(1.0, 8.0, size=2)
+        y, x1, x2 = rng.random(3)
+        k, od, R, wf = oracle.interface_rough(d, n, zf, zb, 1e-13, y, x1, x2)
+        refl, od0, R0 = oracle.interface(d, n, zf, zb, y)
+        if abs(y - R0) < 1e-6:
+            continue
+        assert k == int(refl)
+        assert np.allclose(od, od0, atol=1e-8) and abs(R - R0) < 1e-8 and abs(wf - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("alpha,theta_deg", [(0.3, 0.0), (0.3, 50.0), (0.8, 30.0), (0.8, 70.0)])
+def test_rough_matched_interface_mean_weight(oracle, alpha, theta_deg):
+    """Through a matched boundary (Z1 = Z2: no reflection, no bending) the
+    weight factor |i.h| G1(i) G1(o) / (|i.n| |h.n|) averaged over microfacets
+    drawn with density D(h) (n.h) equals G1(i), by the projected-area identity;
+    Monte Carlo within 5 standard errors."""
+    th = math.radians(theta_deg)
+    d = np.array([math.sin(th), 0.0, -math.cos(th)])
+    n = np.array([0.0, 0.0, 1.0])
+    rng = np.random.default_rng(13)
+    xi = rng.random((40000, 2))
+    w = np.empty(len(xi))
+    for i, (a, c) in enumerate(xi):
+        k, od, R, wf = oracle.interface_rough(d, n, 1.5, 1.5, alpha, 0.5, a, c)
+        assert k in (0, -1)
+        if k == 0:
+            assert np.allclose(od, d, atol=1e-10)
+        w[i] = wf if k == 0 else 0.0
+    want = oracle.ggx_g1(alpha, math.cos(th))
+    assert abs(w.mean() - want) < 5 * w.std() / math.sqrt(len(w)) + 1e-12
