@@ -71,6 +71,10 @@ typedef struct {
     const double *pln;        /* [n_pln][4] unit normal n and d, plane n.x = d; n_pln <= 64    */
     const int32_t *pln_mat;   /* [n_pln][2] front (n side), back                               */
     const double *scat;       /* [n_scat][4] position, amplitude                               */
+    const double *rough;      /* [n_mat] GGX roughness alpha of Eq. 12 per material, 0 = smooth,
+                               * at most 10; NULL: all smooth.  A boundary is as rough as the
+                               * rougher of its two materials (microfacet normal drawn from D(h),
+                               * Walter et al. 2007 weight factor); not supported by the adjoint */
 } ur_scene_desc;
 
 /* Linear array (Sec. 2.3 "Ray Emission": number of lateral elements and
@@ -117,6 +121,8 @@ typedef struct {
              direct_hits, records, dropped, edge_band, term_box, term_bounce, term_time, term_path,
              media_mismatch;
     uint64_t tri_nodes, tri_tests, scat_cells, scat_tests, shadow_nodes, shadow_tri_tests;
+    uint64_t term_rough;      /* rays absorbed at a rough boundary (microfacet facing away, or new
+                               * direction on the wrong side of the surface) */
     double kernel_ms;         /* time of the whole trace stage between HIP events on the call's stream */
 } ur_trace_stats;
 

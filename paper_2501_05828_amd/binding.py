@@ -29,7 +29,7 @@ class SceneDesc(C.Structure):
                 ("n_scat", C.c_int64), ("top_medium", C.c_int64),
                 ("mat", P(C.c_double)), ("box", P(C.c_double)), ("tri", P(C.c_double)), ("tri_mat", P(C.c_int32)),
                 ("sph", P(C.c_double)), ("sph_mat", P(C.c_int32)), ("pln", P(C.c_double)),
-                ("pln_mat", P(C.c_int32)), ("scat", P(C.c_double))]
+                ("pln_mat", P(C.c_int32)), ("scat", P(C.c_double)), ("rough", P(C.c_double))]
 
 
 class ProbeDesc(C.Structure):
@@ -51,7 +51,7 @@ class GridDesc(C.Structure):
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
                "term_time", "term_path", "media_mismatch", "tri_nodes", "tri_tests", "scat_cells", "scat_tests",
-               "shadow_nodes", "shadow_tri_tests"]
+               "shadow_nodes", "shadow_tri_tests", "term_rough"]
 
 
 class TraceStats(C.Structure):
@@ -209,6 +209,10 @@ class Context:
                       top_medium=int(scene.top_medium), mat=dp(mat), box=dp(box), tri=dp(tri),
                       tri_mat=ip(i32(scene.tri_mat)), sph=dp(sph), sph_mat=ip(i32(scene.sph_mat)), pln=dp(pln),
                       pln_mat=ip(i32(scene.pln_mat)), scat=dp(scat))
+        rough = getattr(scene, "rough", None)
+        if rough is not None:
+            rough = np.ascontiguousarray(np.asarray(rough, np.float64).reshape(-1))
+            d.rough = dp(rough)
         self.check(self.lib.ur_scene_upload(self.h, C.byref(d)), "ur_scene_upload")
         self.scene_sizes = {"mat": 3 * len(mat), "scat_amp": len(scat), "sph": 4 * len(sph)}
 

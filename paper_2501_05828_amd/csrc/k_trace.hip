@@ -32,7 +32,7 @@ struct Counters {
 enum {
     C_RAYS, C_SEGMENTS, C_REFLECT, C_TRANSMIT, C_TIR, C_SCAT_EVENTS, C_NEE_ZERO, C_NEE_CAST, C_NEE_BLOCKED,
     C_DIRECT, C_RECORDS, C_DROPPED, C_EDGE, C_TERM_BOX, C_TERM_BOUNCE, C_TERM_TIME, C_TERM_PATH, C_MISMATCH,
-    C_TRI_NODES, C_TRI_TESTS, C_SCAT_CELLS, C_SCAT_TESTS, C_SHADOW_NODES, C_SHADOW_TRI_TESTS
+    C_TRI_NODES, C_TRI_TESTS, C_SCAT_CELLS, C_SCAT_TESTS, C_SHADOW_NODES, C_SHADOW_TRI_TESTS, C_TERM_ROUGH
 };
 
 #define CNT(k)                  \
@@ -673,7 +673,7 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
 // on [0, t_seg) (inline, or queued for the scatter kernel when SPLIT), then
 // transport and the hit itself (see advance).  Returns false when the ray
 // has ended.
-template <bool COUNT, bool LOG, int MODE, bool SPLIT>
+template <bool COUNT, bool LOG, int MODE, bool SPLIT, bool ROUGH = true>
 __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R,
                                           const Hit &h, volatile unsigned long long *chunk, bool near_grid = true) {
     const int b = R.seg;
@@ -750,6 +750,11 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         mb = P.pln_mat[2 * h.local + 1];
     }
     // Eqs. 7-11 with eta = Z_before / Z_after and the reflect-or-transmit draw
+    // (first word).  A boundary as rough as the rougher of its materials
+    // (Eq. 12) acts about a microfacet normal mn drawn from the second and
+    // third words, with weight factor |i.mn| G1(i) G1(o) / (|i.n| |mn.n|)
+    // (Walter et al. 2007, Eq. 41); a microfacet facing away, or a new
+    // direction on the wrong side of the surface, absorbs the ray.
     int before, after;
     if (dot3(d, ng) < 0.0) {
         before = mf;
@@ -761,9 +766,21 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         ng[1] = -ng[1];
         ng[2] = -ng[2];
     }
-    if (before != R.med) CNT(C_MISMATCH);
+    uint32_t x[4];
+    draw(P, R.ray, R.e, R.tx, b, 1, 0, x);
+    // (ROUGH = false: a kernel variant for scenes without rough materials)
+    const double alpha = ROUGH ? fmax(P.mat[mf].rough, P.mat[mb].rough) : 0.0;
+    double mn[3] = {ng[0], ng[1], ng[2]};
+    if (ROUGH && alpha > 0.0) {
+        ggx_sample(ng, alpha, u01(x[1]), u01(x[2]), mn);
+        if (!(-dot3(d, mn) > 0.0)) {
+            CNT(C_TERM_ROUGH);
+            log_event<LOG>(L, 4, R.tx, R.e, b, -5, R.t, R.w, o);
+            return false;
+        }
+    }
     const double z1 = P.mat[before].Z, z2 = P.mat[after].Z;
-    const double cos_r = -dot3(d, ng);
+    const double cos_r = -dot3(d, mn);
     const double eta = z1 / z2;
     const double rad = 1.0 - eta * eta * (1.0 - cos_r * cos_r);
     double R2, cos_t = 0.0;
@@ -779,26 +796,40 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
             R2 = A * A;
         }
     }
-    uint32_t x[4];
-    draw(P, R.ray, R.e, R.tx, b, 1, 0, x);
     const double y = u01(x[0]);
     double nd[3];
     const bool refl = y < R2;
     if (refl) {
-        for (int i = 0; i < 3; ++i) nd[i] = d[i] + 2.0 * cos_r * ng[i];
+        for (int i = 0; i < 3; ++i) nd[i] = d[i] + 2.0 * cos_r * mn[i];
+    } else {
+        const double f = eta * cos_r - cos_t;
+        for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * mn[i];
+    }
+    const double l = sqrt(dot3(nd, nd));
+    nd[0] = nd[0] / l;
+    nd[1] = nd[1] / l;
+    nd[2] = nd[2] / l;
+    if (ROUGH && alpha > 0.0) {
+        const double co = dot3(nd, ng), cn = -dot3(d, ng);
+        if (refl ? !(co > 0.0) : !(co < 0.0)) {
+            CNT(C_TERM_ROUGH);
+            log_event<LOG>(L, 4, R.tx, R.e, b, -5, R.t, R.w, o);
+            return false;
+        }
+        R.w *= cos_r * ggx_g1(alpha, cn) * ggx_g1(alpha, fabs(co)) / (cn * dot3(mn, ng));
+    }
+    if (before != R.med) CNT(C_MISMATCH);
+    if (refl) {
         if (R2 >= 1.0) CNT(C_TIR);
         else CNT(C_REFLECT);
         R.med = before;
     } else {
-        const double f = eta * cos_r - cos_t;
-        for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * ng[i];
         CNT(C_TRANSMIT);
         R.med = after;
     }
-    const double l = sqrt(dot3(nd, nd));
-    d[0] = nd[0] / l;
-    d[1] = nd[1] / l;
-    d[2] = nd[2] / l;
+    d[0] = nd[0];
+    d[1] = nd[1];
+    d[2] = nd[2];
     log_event<LOG>(L, refl ? 2 : 3, R.tx, R.e, b, h.id, R.t, R.w, o);
     R.last = (h.id < P.id_sph0 || h.id >= P.id_pln0) ? h.id : -1;
     R.seg = b + 1;
@@ -914,7 +945,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // hits, termination), queues the finished segment for the scatter kernel and
 // starts its next query.  So no lane waits for the longest traversal of its
 // wavefront, and the scatterer walk runs elsewhere with its own balance.
-template <bool COUNT>
+template <bool COUNT, bool ROUGH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_extend(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
@@ -1000,7 +1031,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (active && !trav) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             analytic_hits(P, R.o, R.d, R.last, h);
-            active = after_hit<COUNT, false, kDeferNee, true>(P, L, cnt, R, h, chunk, near_grid);
+            active = after_hit<COUNT, false, kDeferNee, true, ROUGH>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
                 start_segment();
             } else if (P.cost && R.cell >= 0) {
@@ -1253,19 +1284,36 @@ hipError_t ur_launch_extend(const ur::TraceParams &p, bool count, hipStream_t s)
     const int64_t needed = (p.work_end - p.work_begin + 255) / 256;
     if (needed <= 0) return hipSuccess;
     unsigned blocks = 0;
-    hipError_t e = count ? resident_blocks(k_extend<true>, needed, blocks) : resident_blocks(k_extend<false>, needed, blocks);
-    if (e != hipSuccess) return e;
-    if (count) hipLaunchKernelGGL(k_extend<true>, dim3(blocks), dim3(256), 0, s, p);
-    else hipLaunchKernelGGL(k_extend<false>, dim3(blocks), dim3(256), 0, s, p);
+    hipError_t e;
+#define UR_EXTEND(C, RG)                                                   \
+    do {                                                                   \
+        e = resident_blocks(k_extend<C, RG>, needed, blocks);              \
+        if (e != hipSuccess) return e;                                     \
+        hipLaunchKernelGGL((k_extend<C, RG>), dim3(blocks), dim3(256), 0, s, p); \
+    } while (0)
+    if (count) {
+        if (p.any_rough) UR_EXTEND(true, true);
+        else UR_EXTEND(true, false);
+    } else {
+        if (p.any_rough) UR_EXTEND(false, true);
+        else UR_EXTEND(false, false);
+    }
+#undef UR_EXTEND
     return hipGetLastError();
 }
 
 int64_t ur_extend_max_waves() {
-    unsigned blocks = 0;
-    if (resident_blocks(k_extend<true>, int64_t(1) << 40, blocks) != hipSuccess) return -1;
-    unsigned b2 = 0;
-    if (resident_blocks(k_extend<false>, int64_t(1) << 40, b2) != hipSuccess) return -1;
-    return 4 * (int64_t)(blocks > b2 ? blocks : b2);
+    unsigned most = 0;
+    for (int v = 0; v < 4; ++v) {
+        unsigned b = 0;
+        const hipError_t e = v == 0 ? resident_blocks(k_extend<true, true>, int64_t(1) << 40, b)
+                             : v == 1 ? resident_blocks(k_extend<true, false>, int64_t(1) << 40, b)
+                             : v == 2 ? resident_blocks(k_extend<false, true>, int64_t(1) << 40, b)
+                                      : resident_blocks(k_extend<false, false>, int64_t(1) << 40, b);
+        if (e != hipSuccess) return -1;
+        most = b > most ? b : most;
+    }
+    return 4 * (int64_t)most;
 }
 
 hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s) {

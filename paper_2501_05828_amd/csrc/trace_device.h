@@ -102,6 +102,41 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
     return true;
 }
 
+// Rough boundaries (Eq. 12).  Orthonormal basis (t, b) completing a unit n:
+// the branch-free construction of Duff et al., "Building an Orthonormal
+// Basis, Revisited" (JCGT 6(1), 2017).
+__device__ __forceinline__ void onb(const double *n, double *t, double *b) {
+    const double sg = copysign(1.0, n[2]);
+    const double a = -1.0 / (sg + n[2]);
+    const double c = n[0] * n[1] * a;
+    t[0] = 1.0 + sg * n[0] * n[0] * a;
+    t[1] = sg * c;
+    t[2] = -sg * n[0];
+    b[0] = c;
+    b[1] = sg + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+// Microfacet normal about n with density D(h) (n.h), D the GGX distribution
+// of Eq. 12: tan^2(theta_h) = alpha^2 xi1 / (1 - xi1), phi_h = 2 pi xi2
+// (Walter et al. 2007, Eqs. 35-36).
+__device__ __forceinline__ void ggx_sample(const double *n, double alpha, double xi1, double xi2, double *h) {
+    double t[3], b[3];
+    onb(n, t, b);
+    const double q = 1.0 - xi1 + alpha * alpha * xi1;
+    const double ct = sqrt((1.0 - xi1) / q), st = alpha * sqrt(xi1 / q);
+    double sp, cp;
+    sincos(2.0 * M_PI * xi2, &sp, &cp);
+    for (int i = 0; i < 3; ++i) h[i] = st * cp * t[i] + st * sp * b[i] + ct * n[i];
+}
+
+// Smith masking of the GGX distribution at cos(theta_v) = v.n > 0 (Walter et
+// al. 2007, Eq. 34).
+__device__ __forceinline__ double ggx_g1(double alpha, double cv) {
+    const double tan2 = (1.0 - cv * cv) / (cv * cv);
+    return 2.0 / (1.0 + sqrt(1.0 + alpha * alpha * tan2));
+}
+
 // Unit geometric normal of triangle k, computed once on the host in FP64
 __device__ __forceinline__ void tri_normal(const TraceParams &P, int64_t k, double *n) {
     const double4 v = P.tri_n[k];

@@ -38,6 +38,7 @@ struct ur_context {
     // scene (host copies of what later calls need)
     bool has_scene = false;
     std::vector<double> mat;               // [n_mat][3]
+    std::vector<double> rough;             // [n_mat] GGX roughness (0 = smooth)
     double box[6] = {0};
     int top_medium = 0;
     int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
@@ -138,7 +139,7 @@ ur_status upload_materials(ur_context *c) {
         m[i].Z = c->mat[3 * i];
         m[i].ka = c->mat[3 * i + 1] * fmhz * 100.0 * std::log(10.0) / 20.0;   // dB/(cm MHz) -> Np/m
         m[i].inv_c = 1.0 / c->mat[3 * i + 2];
-        m[i].pad = 0.0;
+        m[i].rough = i < (int64_t)c->rough.size() ? c->rough[i] : 0.0;
     }
     return upload(c, c->d_mat, m);
 }
@@ -231,6 +232,8 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     }
     P.item_id = (const int *)c->d_item_id.p;
     P.n_scat = c->item_order.empty() ? 0 : (int)c->n_scat;   // no registered scatterer: no captures
+    P.any_rough = 0;
+    for (double r : c->rough) P.any_rough |= r > 0.0;
     P.work_next = (unsigned long long *)c->d_work.p;
     P.cost = c->cost;
     return UR_OK;
@@ -323,6 +326,10 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
         for (int64_t m = 0; m < s->n_mat; ++m)
             if (!(s->mat[3 * m] > 0) || !(s->mat[3 * m + 1] >= 0) || !(s->mat[3 * m + 2] > 0))
                 return c->fail(UR_ERR_SCENE, "material %lld needs Z > 0, alpha >= 0, c > 0", (long long)m);
+        if (s->rough)
+            for (int64_t m = 0; m < s->n_mat; ++m)
+                if (!(s->rough[m] >= 0.0 && s->rough[m] <= 10.0))
+                    return c->fail(UR_ERR_SCENE, "material %lld roughness must be in [0, 10]", (long long)m);
         for (int i = 0; i < 3; ++i)
             if (!(s->box[i] < s->box[3 + i])) return c->fail(UR_ERR_SCENE, "box min must be below max");
         if (s->box[2] != 0.0) return c->fail(UR_ERR_SCENE, "the box face z = box[2] must be the transducer plane z = 0");
@@ -343,6 +350,8 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
         }
         c->has_scene = false;
         c->mat.assign(s->mat, s->mat + 3 * s->n_mat);
+        if (s->rough) c->rough.assign(s->rough, s->rough + s->n_mat);
+        else c->rough.assign((size_t)s->n_mat, 0.0);
         std::memcpy(c->box, s->box, sizeof(c->box));
         c->top_medium = (int)s->top_medium;
         c->n_tri = s->n_tri;
@@ -951,6 +960,8 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
     return guarded(c, [&]() -> ur_status {
         if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
         if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
+        for (double r : c->rough)
+            if (r > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint does not support rough boundaries");
         if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center && !grads->value)
             return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)

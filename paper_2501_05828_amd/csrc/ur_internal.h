@@ -15,14 +15,14 @@ constexpr int kMaxSph = 64;
 constexpr int kMaxPln = 64;
 constexpr int kCells = 1024;          // 32 x 32 emission-direction cells
 constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
-constexpr int kNumStats = 24;
+constexpr int kNumStats = 25;
 constexpr int kSegChunk = 256;   // segment-queue slots a wavefront reserves at a time
 constexpr int64_t kSplitRays = int64_t(1) << 25;   // most rays per launch range
 
 // Per-material constants, FP64: impedance, amplitude attenuation [Np/m] at
 // the centre frequency, slowness [s/m].
 struct Material {
-    double Z, ka, inv_c, pad;
+    double Z, ka, inv_c, rough;   // rough: GGX alpha of Eq. 12, 0 = smooth
 };
 
 // Transducer-sampling candidate: a scatterer capture whose chosen element
@@ -110,6 +110,7 @@ struct TraceParams {
     float pre_r2;                     // prefilter capture radius^2, (r_s + pre_m)^2 rounded up
     const int *item_id;               // [n_items]
     int n_scat;
+    int any_rough;                    // some material has a GGX roughness > 0
     // outputs and work distribution
     float *ch_raw;                    // [T][E][S]
     unsigned long long *stats;        // [kNumStats] or null
