@@ -610,9 +610,36 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
     double wq = w * exp(-C->ka[med] * s);
     double tq = t + s * C->inv_c[med];
+    /* Element choice.  Uniform over all E element centres (Sec. 2.3), or,
+     * with element_choice = 1, uniform over the K elements whose centre can
+     * lie inside the acceptance cone of q (Eq. 13 is zero for the others):
+     * |x_e - q_x| <= rho with rho^2 = q_z^2 tan^2(alpha_c) - q_y^2, the
+     * interval widened by a relative 1e-9 so that rounding never drops an
+     * element.  The contribution carries 1/p = E or K. */
+    int64_t e_lo = 0, n_e = a->n_elements;
+    if (a->element_choice == 1 && a->alpha_c < 0.5 * PI) {
+        double tc = tan(a->alpha_c);
+        double rho2 = q[2] * q[2] * tc * tc - q[1] * q[1];
+        double lo_f = 0.0, hi_f = -1.0;
+        if (q[2] > 0.0 && rho2 >= 0.0) {
+            double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
+            double half = 0.5 * (double)(a->n_elements - 1);
+            lo_f = ceil((q[0] - rho) / a->pitch + half);
+            hi_f = floor((q[0] + rho) / a->pitch + half);
+            if (lo_f < 0.0) lo_f = 0.0;
+            if (hi_f > (double)(a->n_elements - 1)) hi_f = (double)(a->n_elements - 1);
+        }
+        if (hi_f < lo_f) {
+            K->st.scatter_events++;
+            K->st.nee_zero++;
+            return;
+        }
+        e_lo = (int64_t)lo_f;
+        n_e = (int64_t)hi_f - e_lo + 1;
+    }
     uint32_t x[4];
     draw(C, ray, e, tx, seg, 2, (uint32_t)k, x);
-    int64_t er = (int64_t)(((uint64_t)x[0] * (uint64_t)a->n_elements) >> 32);
+    int64_t er = e_lo + (int64_t)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
     double v[3] = {C->xe[er] - q[0], 0.0 - q[1], 0.0 - q[2]};
     double dist = sqrt(dot3(v, v));
     double vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
@@ -684,7 +711,7 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     double att = exp(-(C->ka[med] * dist + sum_a));
     double tc = tq + dist * C->inv_c[med] + sum_c;
     double amp = sc->scat[4 * k + 3];
-    double c = wq * amp * (double)a->n_elements * C->area_e * cos_a * fdir / (4.0 * PI * dist * dist) * T * att;
+    double c = wq * amp * (double)n_e * C->area_e * cos_a * fdir / (4.0 * PI * dist * dist) * T * att;
     record(C, K, 1, tx, er, seg, k, tc, c, q, e, cell);
 }
 

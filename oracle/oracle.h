@@ -30,6 +30,8 @@ typedef struct {
     const double *angles;      /* [n_tx] steering angles, rad                         */
     const float *pdf;          /* [n_tx][n_elements][1024] mixed proposal q', or NULL */
     const float *cdf;          /* [n_tx][n_elements][1024] inclusive CDF of q', or NULL */
+    int64_t element_choice;    /* transducer sampling: 0 uniform over all elements, 1 uniform over the
+                                * elements whose centre the capture point's cone can reach */
 } or_acq;
 
 typedef struct {

@@ -35,7 +35,7 @@ class Acq(C.Structure):
                 ("c0", C.c_double), ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double),
                 ("alpha_m", C.c_double), ("alpha_c", C.c_double), ("seed", C.c_uint64),
                 ("angles", C.POINTER(C.c_double)), ("pdf", C.POINTER(C.c_float)),
-                ("cdf", C.POINTER(C.c_float))]
+                ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64)]
 
 
 class SceneS(C.Structure):
@@ -162,7 +162,8 @@ def make_acq(acq, seed, keep, pdf=None, cdf=None):
             rays_per_element=acq.rays_per_element, max_bounces=acq.max_bounces, binning=acq.binning,
             pitch=acq.pitch, elevation=acq.elevation, f_c=acq.f_c, f_s=acq.f_s, c0=acq.c0,
             n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
-            alpha_c=acq.alpha_c, seed=int(seed) & 0xFFFFFFFFFFFFFFFF, angles=_dp(ang))
+            alpha_c=acq.alpha_c, seed=int(seed) & 0xFFFFFFFFFFFFFFFF, angles=_dp(ang),
+            element_choice=int(getattr(acq, "element_choice", 0)))
     if pdf is not None:
         s.pdf = _fp(keep.f32(pdf))
         s.cdf = _fp(keep.f32(cdf))

@@ -47,6 +47,9 @@ class Scene:
                     scatterers=len(self.scat))
 
 
+ELEMENT_UNIFORM, ELEMENT_CONE = 0, 1
+
+
 @dataclass
 class Acquisition:
     n_elements: int
@@ -65,6 +68,7 @@ class Acquisition:
     n_cycles: float              # pulse length in cycles
     r_s: float                   # scatterer capture radius [m]
     binning: int = NEAREST
+    element_choice: int = 0      # transducer sampling: 0 uniform over all elements, 1 over those in the cone
 
     @property
     def n_tx(self) -> int:
