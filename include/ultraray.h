@@ -103,7 +103,15 @@ typedef struct {
     double max_path;          /* maximum path length [m]                                   */
     double alpha_m, alpha_c;  /* receive main-beam and cut-off angles (Eq. 13) [rad]       */
     const double *angles;     /* [n_tx] steering angles [rad] (host)                       */
+    int64_t element_choice;   /* transducer sampling (Sec. 2.3): UR_ELEMENT_UNIFORM draws the
+                               * target uniformly over all E element centres (weight E);
+                               * UR_ELEMENT_CONE uniformly over the K elements whose centre the
+                               * capture point's acceptance cone can reach (weight K, the same
+                               * expectation, lower variance)                                 */
 } ur_acq_desc;
+
+#define UR_ELEMENT_UNIFORM 0
+#define UR_ELEMENT_CONE 1
 
 #define UR_APOD_NONE 0
 #define UR_APOD_HANN 1

@@ -40,7 +40,7 @@ class AcqDesc(C.Structure):
     _fields_ = [("n_tx", C.c_int64), ("n_samples", C.c_int64), ("rays_per_element", C.c_int64),
                 ("max_bounces", C.c_int64), ("binning", C.c_int64), ("f_s", C.c_double), ("c0", C.c_double),
                 ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double), ("alpha_m", C.c_double),
-                ("alpha_c", C.c_double), ("angles", P(C.c_double))]
+                ("alpha_c", C.c_double), ("angles", P(C.c_double)), ("element_choice", C.c_int64)]
 
 
 class GridDesc(C.Structure):
@@ -222,7 +222,8 @@ class Context:
         a = AcqDesc(n_tx=len(ang), n_samples=acq.n_samples, rays_per_element=acq.rays_per_element,
                     max_bounces=acq.max_bounces, binning=acq.binning, f_s=acq.f_s, c0=acq.c0,
                     n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
-                    alpha_c=acq.alpha_c, angles=ang.ctypes.data_as(P(C.c_double)))
+                    alpha_c=acq.alpha_c, angles=ang.ctypes.data_as(P(C.c_double)),
+                    element_choice=int(getattr(acq, "element_choice", 0)))
         self.check(self.lib.ur_transmit_setup(self.h, C.byref(p), C.byref(a)), "ur_transmit_setup")
         self.acq = acq
 

@@ -369,12 +369,14 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                     const double pp[3] = {p[0] - s * dv[0], p[1] - s * dv[1], p[2] - s * dv[2]};
                     if (dot3(pp, pp) > P.r_s2) continue;
                     const int k = P.item_id[j];
-                    uint32_t x[4];
-                    draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
-                    const int er = (int)(((uint64_t)x[0] * (uint64_t)P.E) >> 32);
                     const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
                     const D sd = ddot(pd, d);
                     const D q[3] = {o[0] + sd * d[0], o[1] + sd * d[1], o[2] + sd * d[2]};
+                    int e_lo, n_e;
+                    if (!elem_range(P, q[0].v, q[1].v, q[2].v, e_lo, n_e)) continue;
+                    uint32_t x[4];
+                    draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
+                    const int er = e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
                     const D v[3] = {dd(P.xe[er]) - q[0], -q[1], -q[2]};
                     const D dist = dsqrt(ddot(v, v));
                     const D vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
@@ -391,7 +393,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                     const D tq = t + M.inv_c * sd;
                     const D att = dexp(-(M.ka * dist + sa));
                     const D tc = tq + M.inv_c * dist + sc2;
-                    const D cu = wq * dd((double)P.E * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
+                    const D cu = wq * dd((double)n_e * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
                     const D cval = sk.w * cu;
                     if (A.tan.kind == 0) {
                         double lp[kAdjMat];

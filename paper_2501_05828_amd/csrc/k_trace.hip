@@ -462,9 +462,15 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
                                               int seg, int k, double amp, double w, double t, int med, double s,
                                               int cell, NeeEntry &c) {
     const double cc = P.cos_alpha_c;
+    int e_lo, n_e;
+    if (!elem_range(P, c.q[0], c.q[1], c.q[2], e_lo, n_e)) {
+        CNT(C_SCAT_EVENTS);
+        CNT(C_NEE_ZERO);
+        return false;
+    }
     uint32_t x[4];
     draw(P, ray, e, tx, seg, 2, (uint32_t)k, x);
-    const int er = (int)(((uint64_t)x[0] * (uint64_t)P.E) >> 32);
+    const int er = e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
     // cut-off of Eq. 13 without acos or sqrt: with v = element - q,
     // alpha > alpha_c  <=>  cos(alpha) = -v_z / |v| < cos(alpha_c)
     const double vx = P.xe[er] - c.q[0], vy = c.q[1], mvz = c.q[2];
@@ -487,6 +493,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     c.e = e;
     c.ray = ray;
     c.cell = cell;
+    c.ne = n_e;
     return true;
 }
 
@@ -512,7 +519,7 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
     }
     const double att = atten(-(M.ka * dist + sum_a));
     const double tc = c.tq + dist * M.inv_c + sum_c;
-    const double val = c.wq * (double)P.E * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
+    const double val = c.wq * (double)c.ne * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
     record<COUNT, LOG>(P, L, cnt, 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
 }
 

@@ -102,6 +102,31 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
     return true;
 }
 
+// Elements a transducer-sampling target is drawn from for capture point q
+// (Sec. 2.3): all E, or with the cone-restricted choice the K whose centre
+// x_e = (e - (E-1)/2) pitch satisfies |x_e - q_x| <= rho, rho^2 = q_z^2
+// tan^2(alpha_c) - q_y^2 (Eq. 13 is zero for the others), the interval
+// widened by a relative 1e-9 so that rounding never drops an element.
+// Returns false when no element is left.
+__device__ __forceinline__ bool elem_range(const TraceParams &P, double qx, double qy, double qz, int &e_lo,
+                                           int &n_e) {
+    e_lo = 0;
+    n_e = P.E;
+    if (P.elem_choice != UR_ELEMENT_CONE) return true;
+    const double tc = P.tan_alpha_c;
+    const double rho2 = qz * qz * tc * tc - qy * qy;
+    if (!(qz > 0.0 && rho2 >= 0.0)) return false;
+    const double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
+    const double half = 0.5 * (double)(P.E - 1);
+    double lo = ceil((qx - rho) / P.pitch + half), hi = floor((qx + rho) / P.pitch + half);
+    lo = lo < 0.0 ? 0.0 : lo;
+    hi = hi > (double)(P.E - 1) ? (double)(P.E - 1) : hi;
+    if (hi < lo) return false;
+    e_lo = (int)lo;
+    n_e = (int)hi - e_lo + 1;
+    return true;
+}
+
 // Rough boundaries (Eq. 12).  Orthonormal basis (t, b) completing a unit n:
 // the branch-free construction of Duff et al., "Building an Orthonormal
 // Basis, Revisited" (JCGT 6(1), 2017).

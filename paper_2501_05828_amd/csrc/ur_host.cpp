@@ -179,6 +179,11 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.alpha_m = a.alpha_m;
     P.alpha_c = a.alpha_c;
     P.cos_alpha_c = std::cos(a.alpha_c);
+    // the cone-restricted choice needs alpha_c < 90 degrees; above that every
+    // element can receive and the uniform choice is the same thing
+    P.elem_choice = a.element_choice == UR_ELEMENT_CONE && a.alpha_c < 0.5 * M_PI ? UR_ELEMENT_CONE
+                                                                                   : UR_ELEMENT_UNIFORM;
+    P.tan_alpha_c = std::tan(a.alpha_c);
     P.r_s2 = a.r_s * a.r_s;
     P.n_per_tx = (double)pr.n_elements * (double)a.rays_per_element;
     P.half_ap = 0.5 * (double)pr.n_elements * pr.pitch;
@@ -481,6 +486,8 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         for (double x : v)
             if (!(x > 0) || !std::isfinite(x)) return c->fail(UR_ERR_INVALID_ARG, "f_s, c0, n_cycles and max_path must be positive");
         if (!(a->r_s >= 0) || !std::isfinite(a->r_s)) return c->fail(UR_ERR_INVALID_ARG, "r_s must be >= 0");
+        if (a->element_choice != UR_ELEMENT_UNIFORM && a->element_choice != UR_ELEMENT_CONE)
+            return c->fail(UR_ERR_INVALID_ARG, "element_choice must be UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE");
         if (!(a->alpha_m >= 0) || !(a->alpha_c >= a->alpha_m) || !(a->alpha_c <= M_PI))
             return c->fail(UR_ERR_INVALID_ARG, "need 0 <= alpha_m <= alpha_c <= pi");
         for (int64_t t = 0; t < a->n_tx; ++t)

@@ -6,6 +6,7 @@
 
 #include "bvh_layout.h"
 #include "scatter_grid.h"
+#include "ultraray.h"
 
 namespace ur {
 
@@ -53,6 +54,7 @@ struct NeeEntry {
     int k, e;          // scatterer (original index) and emitting element
     uint32_t ray;
     int cell;          // emission direction cell of the primary ray
+    int ne, pad;       // elements the target was drawn from (weight of the choice)
 };
 
 // Recorded contribution for training the emission proposal:
@@ -78,6 +80,8 @@ struct TraceParams {
     int64_t stride, offset, per_el, n_work;
     double pitch, elev, fs, t_max, max_path, alpha_m, alpha_c, r_s2, n_per_tx, half_ap, area_e;
     double cos_alpha_c;               // cosine of the receive cut-off angle
+    double tan_alpha_c;               // its tangent (element choice restricted to the cone)
+    int elem_choice;                  // UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE
     const double *xe;                 // [E]
     const double *tau;                // [T][E]
     const float *pdf, *cdf;           // [T][E][1024] or null
