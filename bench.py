@@ -132,6 +132,8 @@ def learned_experiment(args):
     from paper_2501_05828_amd.sim import Simulator
 
     w = scenes.learned()
+    if args.element_choice == "cone":
+        w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=scenes.ELEMENT_CONE))
     acq0 = w.acq
     E, T = acq0.n_elements, acq0.n_tx
     sim = Simulator(w)
@@ -210,7 +212,8 @@ def learned_experiment(args):
               "efficiency_gain": (u["mse"] * u["gpu_s"]) / (l["mse"] * l["gpu_s"])}
              for u, l in zip(curves["uniform"], curves["learned"])]
     out = {"metric": "channel MSE at equal GPU time, learned vs uniform", "workload": "bone phantom (learned)",
-           "target": args.target, "reps": args.reps, "min_depth_mm": args.min_depth_mm, "efficiency_gain": gains,
+           "target": args.target, "element_choice": args.element_choice, "reps": args.reps,
+           "min_depth_mm": args.min_depth_mm, "efficiency_gain": gains,
            "reference_rays_per_tx": args.ref_rays_per_tx, "records": n_rec, "records_offered": offered,
            "train_steps": args.train_steps, "train_s": t_train, "loss_log": losses, "curves": curves,
            "learned_time_over_uniform_time_at_equal_mse": ratios}
@@ -236,6 +239,8 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="independent traces per budget (MSE averaged)")
     ap.add_argument("--min-depth-mm", type=float, default=5.0, help="MSE over samples at this round-trip depth and beyond")
     ap.add_argument("--budgets", default="1e6,3e6,1e7,3e7", help="rays per transmit, comma-separated")
+    ap.add_argument("--element-choice", choices=["uniform", "cone"], default="uniform",
+                    help="transducer-sampling target: uniform over all elements, or over those in the cone")
     ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")

@@ -205,11 +205,11 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
  * 1/8 of the device memory (but not below 2^16 rays).  Each range queues its
  * primary-ray segments for the scatterer walk in library-owned device memory
  * of 96 bytes x (rays x (max_bounces + 1) + 256 x resident wavefronts), and
- * up to nee_queue_capacity transducer-sampling candidates (72 bytes each,
+ * up to nee_queue_capacity transducer-sampling candidates (80 bytes each,
  * library-owned) before their secondary rays are cast.  If a range produces
  * more candidates than fit, that range is traced again with the secondary
  * rays cast inline, so results never depend on these limits.
- * Defaults: 2^30 rays, 2^22 candidates. */
+ * Defaults: 2^30 rays, 2^25 candidates (80 bytes each). */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
 /* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse

@@ -71,7 +71,7 @@ struct ur_context {
     int64_t rec_cap = 0;
     std::vector<hipEvent_t> tev;           // [4 * launches]: before extend, after extend, after scatter, after sampling
     int n_tev = 0;
-    int64_t nee_cap = int64_t(1) << 22;
+    int64_t nee_cap = int64_t(1) << 25;      // 80 B each: 2.7 GB (the cone choice casts nearly every capture)
     const float *pdf = nullptr, *cdf = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool trace_timed = false, das_timed = false;
