@@ -126,7 +126,7 @@ static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
         C->xe[e] = ((double)e - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
     for (int64_t tx = 0; tx < a->n_tx; ++tx)
         for (int64_t e = 0; e < a->n_elements; ++e)
-            C->tau[tx * a->n_elements + e] = or_delay(a, tx, e);
+            C->tau[tx * a->n_elements + e] = a->scheme == 1 ? 0.0 : or_delay(a, tx, e);
     C->area_e = a->pitch * a->elevation;
     C->n_per_tx = (double)a->n_elements * (double)a->rays_per_element;
     C->t_max = (double)a->n_samples / a->f_s;
@@ -145,7 +145,9 @@ static void ctx_free(octx *C)
 static void draw(const octx *C, uint32_t ray, int64_t e, int64_t tx, int64_t seg, uint32_t purpose,
                  uint32_t k, uint32_t out[4])
 {
-    uint32_t ctr[4] = {ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k};
+    /* synthetic aperture: every transmit draws as transmit 0 (one element each) */
+    uint32_t txr = C->a->scheme == 1 ? 0u : (uint32_t)tx;
+    uint32_t ctr[4] = {ray, (uint32_t)e | (txr << 16), (uint32_t)seg | (purpose << 16), k};
     uint32_t key[2] = {(uint32_t)C->a->seed, (uint32_t)(C->a->seed >> 32)};
     or_philox(ctr, key, out);
 }
@@ -862,7 +864,8 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
                       double *rec_hist, or_stats *st_out)
 {
     if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
-        a->rays_per_element < 0 || a->max_bounces < 0 || a->max_bounces > 65535 || stride <= 0)
+        a->rays_per_element < 0 || a->max_bounces < 0 || a->max_bounces > 65535 || stride <= 0 ||
+        (a->scheme == 1 && a->n_tx != a->n_elements))
         return -1;
     octx C;
     if (ctx_init(&C, a, s)) return -2;
@@ -886,7 +889,8 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
         }
     }
     int64_t per_el = (a->rays_per_element + stride - 1) / stride;
-    int64_t n_work = a->n_tx * a->n_elements * per_el;
+    /* synthetic aperture: transmit t is element t alone */
+    int64_t n_work = (a->scheme == 1 ? 1 : a->n_tx) * a->n_elements * per_el;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(nt)
 #endif
@@ -897,7 +901,7 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
 #endif
         int64_t rr = (i % per_el) * stride;
         int64_t e = (i / per_el) % a->n_elements;
-        int64_t tx = i / (per_el * a->n_elements);
+        int64_t tx = a->scheme == 1 ? e : i / (per_el * a->n_elements);
         double o[3], d[3], w;
         int64_t cell = -1;
         emit(&C, tx, e, (uint32_t)rr, o, d, &w, &cell);
@@ -1051,6 +1055,39 @@ static int das_tables(const or_acq *a, double **xe, double **apod)
         (*xe)[e] = ((double)e - 0.5 * (double)(E - 1)) * a->pitch;
         (*apod)[e] = 0.5 - 0.5 * cos(2.0 * PI * ((double)e + 0.5) / (double)E);
     }
+    return 0;
+}
+
+/* ---------------------------------------------- synthetic-aperture synthesis */
+/* A steered plane wave is the sum over elements of each element's own
+ * transmit delayed by its steering delay (Sec. 2.3 "Ray Emission", Fig. 3):
+ * with synthetic-aperture data, element e's channels are shifted by
+ * tau_k(e) fs samples, linearly interpolated between samples. */
+int or_synthesize(const or_acq *a, const double *ch_sa, const double *angles, int64_t n_ang, double *out)
+{
+    const int64_t E = a->n_elements, S = a->n_samples;
+    or_acq b = *a;
+    b.angles = angles;
+    b.n_tx = n_ang;
+    b.scheme = 0;
+    memset(out, 0, sizeof(double) * (size_t)(n_ang * E * S));
+    for (int64_t k = 0; k < n_ang; ++k)
+        for (int64_t e = 0; e < E; ++e) {
+            double sh = or_delay(&b, k, e) * a->f_s;
+            for (int64_t er = 0; er < E; ++er) {
+                const double *x = ch_sa + (e * E + er) * S;
+                double *y = out + (k * E + er) * S;
+                for (int64_t s = 0; s < S; ++s) {
+                    double u = (double)s - sh;
+                    double f0 = floor(u);
+                    int64_t i0 = (int64_t)f0;
+                    double f = u - f0;
+                    double v0 = (i0 >= 0 && i0 < S) ? x[i0] : 0.0;
+                    double v1 = (i0 + 1 >= 0 && i0 + 1 < S) ? x[i0 + 1] : 0.0;
+                    y[s] += (1.0 - f) * v0 + f * v1;
+                }
+            }
+        }
     return 0;
 }
 

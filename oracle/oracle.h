@@ -32,6 +32,9 @@ typedef struct {
     const float *cdf;          /* [n_tx][n_elements][1024] inclusive CDF of q', or NULL */
     int64_t element_choice;    /* transducer sampling: 0 uniform over all elements, 1 uniform over the
                                 * elements whose centre the capture point's cone can reach */
+    int64_t scheme;            /* 0 steered plane waves; 1 synthetic aperture: n_tx = n_elements,
+                                * transmit t fires element t alone without delay, its rays drawn
+                                * with the counters of transmit 0 */
 } or_acq;
 
 typedef struct {
@@ -79,6 +82,10 @@ int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t r
 
 int or_pulse_taps(const or_acq *a, double *taps, int64_t cap);   /* returns K, taps [2K+1][2] */
 int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf);
+/* Plane waves synthesised from synthetic-aperture data ch_sa [E][E][S]:
+ * out[k][er][s] = sum over e of ch_sa[e][er] at s - tau_k(e) fs (linear
+ * interpolation, zero outside), tau_k the delays of angle k (or_delay). */
+int or_synthesize(const or_acq *a, const double *ch_sa, const double *angles, int64_t n_ang, double *out);
 int or_das(const or_acq *a, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
            const double *ch_rf, int n_threads, double *iq);
 int or_das_points(const or_acq *a, const double *xz, int64_t n, const double *ch_rf, double *iq);

@@ -35,7 +35,7 @@ class Acq(C.Structure):
                 ("c0", C.c_double), ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double),
                 ("alpha_m", C.c_double), ("alpha_c", C.c_double), ("seed", C.c_uint64),
                 ("angles", C.POINTER(C.c_double)), ("pdf", C.POINTER(C.c_float)),
-                ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64)]
+                ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64), ("scheme", C.c_int64)]
 
 
 class SceneS(C.Structure):
@@ -100,6 +100,7 @@ def lib():
         L.or_directivity.restype = C.c_double
         L.or_interface.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
                                    P(C.c_double), P(C.c_double)]
+        L.or_synthesize.argtypes = [P(Acq), P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double)]
         L.or_interface_rough.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, C.c_double, P(C.c_double), P(C.c_double),
                                          P(C.c_double)]
@@ -163,7 +164,7 @@ def make_acq(acq, seed, keep, pdf=None, cdf=None):
             pitch=acq.pitch, elevation=acq.elevation, f_c=acq.f_c, f_s=acq.f_s, c0=acq.c0,
             n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
             alpha_c=acq.alpha_c, seed=int(seed) & 0xFFFFFFFFFFFFFFFF, angles=_dp(ang),
-            element_choice=int(getattr(acq, "element_choice", 0)))
+            element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)))
     if pdf is not None:
         s.pdf = _fp(keep.f32(pdf))
         s.cdf = _fp(keep.f32(cdf))
@@ -326,6 +327,19 @@ def interface(d, n, z_front, z_back, y):
     R = C.c_double(0)
     refl = lib().or_interface(dd, nn, float(z_front), float(z_back), float(y), out, C.byref(R))
     return bool(refl), np.array(out[:]), R.value
+
+
+def synthesize(acq, ch_sa, angles):
+    """Plane-wave channel data [n_ang][E][S] synthesised from synthetic-aperture
+    data [E][E][S] (float64)."""
+    keep = _Keep()
+    a = make_acq(acq, 0, keep)
+    x = np.ascontiguousarray(np.asarray(ch_sa, np.float64))
+    ang = np.ascontiguousarray(np.asarray(angles, np.float64))
+    out = np.zeros((len(ang), acq.n_elements, acq.n_samples))
+    rc = lib().or_synthesize(C.byref(a), _dp(x), _dp(ang), len(ang), _dp(out))
+    assert rc == 0
+    return out
 
 
 def interface_rough(d, n, z_front, z_back, alpha, y, xi1, xi2):

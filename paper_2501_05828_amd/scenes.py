@@ -48,6 +48,7 @@ class Scene:
 
 
 ELEMENT_UNIFORM, ELEMENT_CONE = 0, 1
+SCHEME_PLANE_WAVE, SCHEME_SYNTHETIC = 0, 1
 
 
 @dataclass
@@ -69,6 +70,7 @@ class Acquisition:
     r_s: float                   # scatterer capture radius [m]
     binning: int = NEAREST
     element_choice: int = 0      # transducer sampling: 0 uniform over all elements, 1 over those in the cone
+    scheme: int = 0              # 0 steered plane waves; 1 synthetic aperture (transmit t = element t alone)
 
     @property
     def n_tx(self) -> int:
@@ -299,3 +301,11 @@ CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "
 
 def make(name: str, **kw) -> Workload:
     return CONFIGS[name](**kw)
+
+
+def synthetic_aperture(w: Workload) -> Workload:
+    """The same scene and probe acquired element by element: transmit t fires
+    element t alone without delay (n_tx = n_elements; the angles are unused),
+    its rays drawn as in transmit 0 of a plane-wave set."""
+    acq = dataclasses.replace(w.acq, scheme=SCHEME_SYNTHETIC, angles=np.zeros(w.acq.n_elements))
+    return dataclasses.replace(w, name=w.name + "-sa", acq=acq)

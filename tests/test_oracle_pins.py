@@ -741,3 +741,54 @@ def test_element_choice_expectation_closed_form(oracle, choice):
     assert want > 0 and abs(vals.mean() - want) < 5 * se + 1e-15
     if choice == 1:
         assert len(recs) > 0.5 * n      # most cone draws land on a receiving element
+
+
+# ------------------------------------------------ synthetic-aperture acquisition
+
+def test_synthetic_aperture_sums_to_the_unsteered_plane_wave(oracle):
+    """Element-by-element transmits drawn with transmit 0's counters: their
+    channel data summed over the emitting element is the 0-degree plane-wave
+    trace (every delay zero), path by path."""
+    w = scenes.tiny(rays_per_element=256)
+    pw, spw = oracle.trace(w)
+    sa, ssa = oracle.trace(scenes.synthetic_aperture(w))
+    assert sa.shape == (w.acq.n_elements, w.acq.n_elements, w.acq.n_samples)
+    for k in ("rays", "segments", "reflect", "transmit", "records", "direct_hits", "nee_cast"):
+        assert spw[k] == ssa[k], k
+    assert np.allclose(sa.sum(0), pw[0], rtol=1e-12, atol=1e-12 * np.abs(pw).max())
+
+
+def test_synthesis_with_whole_sample_delays_is_the_steered_trace(oracle):
+    """At the steering angle whose delays are whole samples per element
+    (sin theta = c0 / (pitch fs)) the synthesised plane wave equals the
+    steered plane-wave trace."""
+    w = scenes.tiny(rays_per_element=256)
+    acq = w.acq
+    th = math.asin(acq.c0 / (acq.pitch * acq.f_s))
+    for ang in (th, -th):
+        ws = dataclasses.replace(w, acq=dataclasses.replace(acq, angles=np.array([ang])))
+        pw, _ = oracle.trace(ws)
+        sa, _ = oracle.trace(scenes.synthetic_aperture(w))
+        syn = oracle.synthesize(acq, sa, [ang])
+        assert np.allclose(syn, pw, rtol=1e-9, atol=1e-9 * np.abs(pw).max()), ang
+
+
+def test_synthesis_fractional_shift_closed_form(oracle):
+    """One impulse in element 5's data moves by its delay tau fs = 5 pitch
+    sin(theta) fs / c0 samples, split between the two neighbouring samples
+    in proportion (linear interpolation)."""
+    w = scenes.tiny()
+    acq = w.acq
+    E, S = acq.n_elements, acq.n_samples
+    sa = np.zeros((E, E, S))
+    sa[5, 7, 100] = 2.0
+    ang = math.radians(3.0)
+    out = oracle.synthesize(acq, sa, [ang])
+    sh = 5 * acq.pitch * math.sin(ang) * acq.f_s / acq.c0
+    i0 = math.floor(100 + sh)
+    f = 100 + sh - i0
+    want = np.zeros(S)
+    want[i0] = 2.0 * (1 - f)
+    want[i0 + 1] = 2.0 * f
+    assert np.allclose(out[0, 7], want, atol=1e-14)
+    assert not out[0, np.arange(E) != 7].any()
