@@ -108,10 +108,17 @@ typedef struct {
                                * UR_ELEMENT_CONE uniformly over the K elements whose centre the
                                * capture point's acceptance cone can reach (weight K, the same
                                * expectation, lower variance)                                 */
+    int64_t scheme;           /* UR_SCHEME_PLANE_WAVE: n_tx steered plane waves (angles);
+                               * UR_SCHEME_SYNTHETIC: synthetic aperture, n_tx = n_elements and
+                               * transmit t fires element t alone without delay (angles unused),
+                               * its rays drawn as in transmit 0 with the weights of a full-array
+                               * transmit; see ur_synthesize                                   */
 } ur_acq_desc;
 
 #define UR_ELEMENT_UNIFORM 0
 #define UR_ELEMENT_CONE 1
+#define UR_SCHEME_PLANE_WAVE 0
+#define UR_SCHEME_SYNTHETIC 1
 
 #define UR_APOD_NONE 0
 #define UR_APOD_HANN 1
@@ -211,6 +218,18 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
  * rays cast inline, so results never depend on these limits.
  * Defaults: 2^30 rays, 2^25 candidates (80 bytes each). */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
+
+/* Steered plane waves synthesised from synthetic-aperture channel data
+ * (any acquisition scheme from one set of traces, Sec. 1; delays of
+ * Sec. 2.3 / Fig. 3):
+ * out[k][er][s] = sum over emitting elements e of ch_sa[e][er] at sample
+ * s - tau_k(e) fs, linearly interpolated (zero outside [0, n_samples)), with
+ * tau_k(e) = (x_e - x_ref) sin(theta_k) / c0 the plane-wave delays of the
+ * current setup's probe.  ch_sa_dev [E][E][n_samples] FP32 (device, as traced
+ * with UR_SCHEME_SYNTHETIC), angles [n_ang] (host), out_dev [n_ang][E][n_samples]
+ * FP32 (device, overwritten), n_ang <= 128.  Accumulates in FP64.  Async on `stream`. */
+UR_API ur_status ur_synthesize(ur_context *ctx, const float *ch_sa_dev, const double *angles, int64_t n_ang,
+                               float *out_dev, void *stream);
 
 /* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
  * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at

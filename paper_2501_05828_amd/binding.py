@@ -40,7 +40,8 @@ class AcqDesc(C.Structure):
     _fields_ = [("n_tx", C.c_int64), ("n_samples", C.c_int64), ("rays_per_element", C.c_int64),
                 ("max_bounces", C.c_int64), ("binning", C.c_int64), ("f_s", C.c_double), ("c0", C.c_double),
                 ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double), ("alpha_m", C.c_double),
-                ("alpha_c", C.c_double), ("angles", P(C.c_double)), ("element_choice", C.c_int64)]
+                ("alpha_c", C.c_double), ("angles", P(C.c_double)), ("element_choice", C.c_int64),
+                ("scheme", C.c_int64)]
 
 
 class GridDesc(C.Structure):
@@ -90,6 +91,7 @@ SIGNATURES = [
     ("ur_scene_upload", C.c_int, [_CTX, P(SceneDesc)]),
     ("ur_transmit_setup", C.c_int, [_CTX, P(ProbeDesc), P(AcqDesc)]),
     ("ur_set_proposal", C.c_int, [_CTX, C.c_void_p, C.c_void_p]),
+    ("ur_synthesize", C.c_int, [_CTX, C.c_void_p, P(C.c_double), C.c_int64, C.c_void_p, C.c_void_p]),
     ("ur_trace", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, P(TraceStats),
                            C.c_void_p]),
     ("ur_set_limits", C.c_int, [_CTX, C.c_int64, C.c_int64]),
@@ -223,7 +225,7 @@ class Context:
                     max_bounces=acq.max_bounces, binning=acq.binning, f_s=acq.f_s, c0=acq.c0,
                     n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
                     alpha_c=acq.alpha_c, angles=ang.ctypes.data_as(P(C.c_double)),
-                    element_choice=int(getattr(acq, "element_choice", 0)))
+                    element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)))
         self.check(self.lib.ur_transmit_setup(self.h, C.byref(p), C.byref(a)), "ur_transmit_setup")
         self.acq = acq
 
@@ -295,6 +297,11 @@ class Context:
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
         self.check(rc, "ur_trace_adjoint")
+
+    def ur_synthesize(self, ch_sa, angles, out, stream=None):
+        ang = np.ascontiguousarray(np.asarray(angles, np.float64))
+        self.check(self.lib.ur_synthesize(self.h, _ptr(ch_sa), ang.ctypes.data_as(P(C.c_double)), len(ang), _ptr(out),
+                                          _stream_ptr(stream)), "ur_synthesize")
 
     def ur_last_kernel_ms(self):
         a, b = C.c_double(), C.c_double()

@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     if (i < P.n_work) {
         const int64_t q = i / P.per_el;
         const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        replay_path(A, acc, (int)(q / P.E), (int)(q % P.E), ray);
+        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray);
     }
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;

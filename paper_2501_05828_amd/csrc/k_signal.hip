@@ -232,3 +232,52 @@ hipError_t ur_launch_bmode(const float *env, float *bmode, int64_t n, float dr_d
                        max_bits);
     return hipGetLastError();
 }
+
+// ------------------------------------------- synthetic-aperture synthesis
+// Steered plane waves from element-by-element data: each output sample sums
+// over the emitting elements the element's channel shifted by its steering
+// delay tau = (x_e - x_ref) sin(theta) / c0 (Sec. 2.3, Fig. 3) times fs,
+// linearly interpolated, in FP64.  One thread per output sample; for each
+// emitting element the threads of a block read neighbouring samples of one
+// channel.
+namespace {
+constexpr int kSynthMaxAngles = 128;   // 2 KB of kernel arguments
+struct SynthAngles {
+    double st[kSynthMaxAngles];     // sin(theta_k)
+    double xref[kSynthMaxAngles];   // x of the first-firing element
+};
+
+__global__ __launch_bounds__(256) void k_synth(const float *sa, int E, int S, double pitch, double c0, double fs,
+                                               SynthAngles A, float *out) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int er = blockIdx.y, k = blockIdx.z;
+    if (s >= S) return;
+    double acc = 0.0;
+    for (int e = 0; e < E; ++e) {
+        const double xe = ((double)e - 0.5 * (double)(E - 1)) * pitch;
+        const double sh = (xe - A.xref[k]) * A.st[k] / c0 * fs;
+        const double u = (double)s - sh, f0 = floor(u), f = u - f0;
+        const int i0 = (int)f0;
+        const float *x = sa + ((int64_t)e * E + er) * S;
+        const double v0 = (i0 >= 0 && i0 < S) ? (double)x[i0] : 0.0;
+        const double v1 = (i0 + 1 >= 0 && i0 + 1 < S) ? (double)x[i0 + 1] : 0.0;
+        acc += (1.0 - f) * v0 + f * v1;
+    }
+    out[((int64_t)k * E + er) * S + s] = (float)acc;
+}
+}  // namespace
+
+hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S, double pitch,
+                                  double c0, double fs, float *out, hipStream_t s) {
+    if (n_ang <= 0 || E <= 0 || S <= 0) return hipSuccess;
+    if (n_ang > kSynthMaxAngles || E > 65535) return hipErrorInvalidValue;
+    SynthAngles A;
+    const double x0 = (0.0 - 0.5 * (double)(E - 1)) * pitch, xl = ((double)(E - 1) - 0.5 * (double)(E - 1)) * pitch;
+    for (int k = 0; k < n_ang; ++k) {
+        A.st[k] = std::sin(angles[k]);
+        A.xref[k] = A.st[k] >= 0 ? x0 : xl;
+    }
+    dim3 grid((unsigned)((S + 255) / 256), (unsigned)E, (unsigned)n_ang);
+    hipLaunchKernelGGL(k_synth, grid, dim3(256), 0, s, sa, E, S, pitch, c0, fs, A, out);
+    return hipGetLastError();
+}

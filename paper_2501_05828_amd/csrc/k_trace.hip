@@ -923,8 +923,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         const int64_t i = P.work_begin + (int64_t)r;
                         const int64_t q = i / P.per_el;
                         R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-                        R.e = (int)(q % P.E);
-                        R.tx = (int)(q / P.E);
+                        R.e = P.sa ? (int)q : (int)(q % P.E);   // synthetic aperture: transmit q is element q
+                        R.tx = P.sa ? (int)q : (int)(q / P.E);
                         emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;
@@ -1010,8 +1010,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         const int64_t i = P.work_begin + (int64_t)r;
                         const int64_t q = i / P.per_el;
                         R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-                        R.e = (int)(q % P.E);
-                        R.tx = (int)(q / P.E);
+                        R.e = P.sa ? (int)q : (int)(q % P.E);   // synthetic aperture: transmit q is element q
+                        R.tx = P.sa ? (int)q : (int)(q / P.E);
                         emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;

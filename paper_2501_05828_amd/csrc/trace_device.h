@@ -9,10 +9,12 @@
 namespace ur {
 namespace dev {
 
-// counter = (ray, element | tx << 16, segment | purpose << 16, k)
+// counter = (ray, element | tx << 16, segment | purpose << 16, k); with the
+// synthetic-aperture scheme every transmit draws as transmit 0
 __device__ __forceinline__ void draw(const TraceParams &P, uint32_t ray, int e, int tx, int seg, uint32_t purpose,
                                      uint32_t k, uint32_t out[4]) {
-    philox4x32_10(ray, (uint32_t)e | ((uint32_t)tx << 16), (uint32_t)seg | (purpose << 16), k, P.key0, P.key1, out);
+    const uint32_t txr = P.sa ? 0u : (uint32_t)tx;
+    philox4x32_10(ray, (uint32_t)e | (txr << 16), (uint32_t)seg | (purpose << 16), k, P.key0, P.key1, out);
 }
 
 __device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }

@@ -184,6 +184,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.elem_choice = a.element_choice == UR_ELEMENT_CONE && a.alpha_c < 0.5 * M_PI ? UR_ELEMENT_CONE
                                                                                    : UR_ELEMENT_UNIFORM;
     P.tan_alpha_c = std::tan(a.alpha_c);
+    P.sa = a.scheme == UR_SCHEME_SYNTHETIC;
     P.r_s2 = a.r_s * a.r_s;
     P.n_per_tx = (double)pr.n_elements * (double)a.rays_per_element;
     P.half_ap = 0.5 * (double)pr.n_elements * pr.pitch;
@@ -486,6 +487,10 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         for (double x : v)
             if (!(x > 0) || !std::isfinite(x)) return c->fail(UR_ERR_INVALID_ARG, "f_s, c0, n_cycles and max_path must be positive");
         if (!(a->r_s >= 0) || !std::isfinite(a->r_s)) return c->fail(UR_ERR_INVALID_ARG, "r_s must be >= 0");
+        if (a->scheme != UR_SCHEME_PLANE_WAVE && a->scheme != UR_SCHEME_SYNTHETIC)
+            return c->fail(UR_ERR_INVALID_ARG, "scheme must be UR_SCHEME_PLANE_WAVE or UR_SCHEME_SYNTHETIC");
+        if (a->scheme == UR_SCHEME_SYNTHETIC && a->n_tx != p->n_elements)
+            return c->fail(UR_ERR_INVALID_ARG, "the synthetic-aperture scheme needs n_tx = n_elements");
         if (a->element_choice != UR_ELEMENT_UNIFORM && a->element_choice != UR_ELEMENT_CONE)
             return c->fail(UR_ERR_INVALID_ARG, "element_choice must be UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE");
         if (!(a->alpha_m >= 0) || !(a->alpha_c >= a->alpha_m) || !(a->alpha_c <= M_PI))
@@ -512,7 +517,8 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         for (int64_t t = 0; t < T; ++t) {
             const double st = std::sin(c->angles[t]);
             const double xref = st >= 0 ? xe[0] : xe[E - 1];
-            for (int64_t e = 0; e < E; ++e) tau[t * E + e] = (xe[e] - xref) * st / a->c0;
+            for (int64_t e = 0; e < E; ++e)
+                tau[t * E + e] = a->scheme == UR_SCHEME_SYNTHETIC ? 0.0 : (xe[e] - xref) * st / a->c0;
         }
         // analytic pulse taps (Eq. 14), Gaussian with FWHM of n_cycles periods
         std::vector<float2> taps(2 * K + 1);
@@ -605,7 +611,7 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         P.stride = ray_stride;
         P.offset = ray_offset;
         P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
-        P.n_work = (int64_t)P.T * P.E * P.per_el;
+        P.n_work = (int64_t)(P.sa ? 1 : P.T) * P.E * P.per_el;   // synthetic aperture: one element per transmit
         P.ch_raw = ch_raw_dev;
         const int64_t n_ch = (int64_t)P.T * P.E * P.S;
         ur_status st;
@@ -724,6 +730,22 @@ UR_API ur_status ur_set_limits(ur_context *c, int64_t rays_per_launch, int64_t n
         c->rays_per_launch = rays_per_launch;
         c->nee_cap = nee_queue_capacity;
         c->d_nee.release();
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_synthesize(ur_context *c, const float *ch_sa_dev, const double *angles, int64_t n_ang,
+                               float *out_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!ch_sa_dev || !out_dev || !angles) return c->fail(UR_ERR_INVALID_ARG, "NULL buffer");
+        if (n_ang < 1 || n_ang > 128) return c->fail(UR_ERR_INVALID_ARG, "need 1 <= n_ang <= 128");
+        for (int64_t k = 0; k < n_ang; ++k)
+            if (!std::isfinite(angles[k]) || std::fabs(angles[k]) >= M_PI / 2)
+                return c->fail(UR_ERR_INVALID_ARG, "angle %lld must be finite and within (-pi/2, pi/2)", (long long)k);
+        HIP_TRY(c, ur_launch_synth_angles(ch_sa_dev, angles, (int)n_ang, (int)c->probe.n_elements,
+                                          (int)c->acq.n_samples, c->probe.pitch, c->acq.c0, c->acq.f_s, out_dev,
+                                          (hipStream_t)stream));
         return UR_OK;
     });
 }
@@ -983,7 +1005,7 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         P.stride = ray_stride;
         P.offset = ray_offset;
         P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
-        P.n_work = (int64_t)P.T * P.E * P.per_el;
+        P.n_work = (int64_t)(P.sa ? 1 : P.T) * P.E * P.per_el;   // synthetic aperture: one element per transmit
         const double kappa = c->probe.f_c * 1e-6 * 100.0 * std::log(10.0) / 20.0;
         if (grads->amp) HIP_TRY(c, zero_f32(grads->amp, c->n_scat, s));
         if (grads->alpha) HIP_TRY(c, ur_launch_zero_f64(grads->alpha, n_mat, s));

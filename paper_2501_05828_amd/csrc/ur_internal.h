@@ -82,6 +82,7 @@ struct TraceParams {
     double cos_alpha_c;               // cosine of the receive cut-off angle
     double tan_alpha_c;               // its tangent (element choice restricted to the cone)
     int elem_choice;                  // UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE
+    int sa;                           // synthetic aperture: transmit t = element t, counters of transmit 0
     const double *xe;                 // [E]
     const double *tau;                // [T][E]
     const float *pdf, *cdf;           // [T][E][1024] or null
@@ -163,6 +164,8 @@ hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s
 int64_t ur_extend_max_waves();   // wavefronts of a full extend launch (bounds the queue's chunk slack)
 hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
                                 hipStream_t s);
+hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S, double pitch,
+                                  double c0, double fs, float *out, hipStream_t s);
 hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
                            hipStream_t s);
 hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s);
