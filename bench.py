@@ -33,6 +33,8 @@ METRIC = "traced rays/s + DAS frames/s; channel MSE at equal GPU time, learned v
 PEAK_FP32 = 157.3e12      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk with packed FMA)
 PEAK_FP64 = 78.6e12       # MI355X vector FP64 (256 CU x 2.4 GHz x 128 FLOP/clk)
 PEAK_HBM = 8.0e12
+N_CU = 256
+CLOCK_HZ = 2.4e9
 
 # Algorithmic FLOPs per counted unit (add/sub/mul = 1, fma = 2,
 # div/sqrt/exp/acos = 1; compares, min/max and integer RNG work are not
@@ -80,10 +82,9 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, n_launch_bytes_hint=None):
-    """HBM bytes of the extend kernel per frame (summed over its launch
-    ranges) from the committed rocprofv3 PMC summary, or None if absent or
-    taken on a different kernel source."""
+def load_pmc(workload):
+    """The committed rocprofv3 PMC summary of the extend kernel, or None if
+    absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", f"pmc_trace_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -91,7 +92,18 @@ def load_traffic(workload, n_launch_bytes_hint=None):
         d = json.load(f)
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d["fetch_bytes"] / d["copy_fetch_factor"] + d["write_bytes"] / d["copy_write_factor"]
+    return d
+
+
+def load_traffic(workload):
+    """HBM bytes per launch of the extend kernel (the frame's total over its
+    equal launch ranges, divided by their number) from the committed
+    rocprofv3 PMC summary, or None."""
+    d = load_pmc(workload)
+    if d is None:
+        return None
+    per_frame = d["fetch_bytes"] / d["copy_fetch_factor"] + d["write_bytes"] / d["copy_write_factor"]
+    return per_frame / d["launches_per_frame"]
 
 
 def cpu_threads():
@@ -311,6 +323,15 @@ def main():
     achieved = (xf32 + xf64) / t_ext
     peak = (xf32 + xf64) / (xf32 / PEAK_FP32 + xf64 / PEAK_FP64)
     traffic = load_traffic(w.name)
+    pmc = load_pmc(w.name)
+    valu = None
+    if pmc is not None and "valu" in pmc:
+        # a wave64 VALU instruction occupies one 16-lane SIMD for 4 cycles:
+        # 4 SIMDs per CU issue at most one wave instruction per CU per cycle
+        insts = pmc["valu"]["insts_per_frame"]
+        valu = {"insts_per_frame": insts,
+                "issue_frac": insts / (N_CU * CLOCK_HZ * t_ext),
+                "lanes_active_frac": pmc["valu"]["active_lanes_per_inst"] / 64.0}
     out = {
         "metric": METRIC,
         "value": n_rays * args.steps / elapsed,
@@ -352,6 +373,7 @@ def main():
             "flops_fp64": xf64,
             "launches_per_frame": launches,
             "kernel_ms_per_launch": 1e3 * t_ext / launches,
+            "valu": valu,
         },
         "scatter_kernel": {
             "ms": 1e3 * t_sca,
