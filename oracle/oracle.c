@@ -80,8 +80,11 @@ typedef struct {
     double *ka;      /* amplitude attenuation per material [Np/m] at f_c */
     double *inv_c;   /* 1/c per material [s/m]                           */
     double *xe;      /* element centres along x [m]                      */
+    double *ze;      /* element centres along z [m] (0 for a linear array) */
+    double *sne;     /* sin of the element's normal angle (0 linear)      */
+    double *cne;     /* cos of the element's normal angle (1 linear)      */
     double *tau;     /* [tx][e] transmit delays [s]                      */
-    double area_e, n_per_tx, t_max, half_ap;
+    double area_e, n_per_tx, t_max, half_ap, dphi, half_arc;
     int64_t id_sph0, id_pln0, id_box;
 } octx;
 
@@ -93,12 +96,48 @@ typedef struct {
     or_stats st;
 } sink;
 
+/* Element e's centre (x, z) and the sine and cosine of the angle of its
+ * outward normal from +z (Sec. 2.3 "Ray Emission": lateral elements on a
+ * circle of the given radius; infinite radius = linear array).  A convex
+ * array of radius R has its centre of curvature at (0, 0, -R); the pitch is
+ * the arc length between neighbouring centres, so element e sits at angle
+ * phi_e = (e - (E-1)/2) pitch / R, at R (sin phi_e, 0, cos phi_e) from the
+ * centre; the middle of the array touches z = 0.  z = R cos phi - R is
+ * evaluated as -2 R sin^2(phi/2). */
+void or_element_geometry(const or_acq *a, int64_t e, double out[4])
+{
+    double off = (double)e - 0.5 * (double)(a->n_elements - 1);
+    if (a->radius > 0.0) {
+        double ph = off * a->pitch / a->radius, h = sin(0.5 * ph);
+        out[0] = a->radius * sin(ph);
+        out[1] = -2.0 * a->radius * h * h;
+        out[2] = sin(ph);
+        out[3] = cos(ph);
+    } else {
+        out[0] = off * a->pitch;
+        out[1] = 0.0;
+        out[2] = 0.0;
+        out[3] = 1.0;
+    }
+}
+
 double or_delay(const or_acq *a, int64_t tx, int64_t e)
 {
-    /* Plane-wave steering (Sec. 2.3 "Ray Emission", Fig. 3): the element
-     * delay grows linearly along the array with the sine of the angle,
-     * referenced to the element that fires first so that all delays are
-     * non-negative. */
+    /* Plane-wave steering (Sec. 2.3 "Ray Emission", Fig. 3): each element
+     * fires when the steered plane front k = (sin theta, 0, cos theta)
+     * passes its centre, k.c_e / c0, referenced to the element that fires
+     * first so that all delays are non-negative.  On a linear array this is
+     * x_e sin(theta) / c0 up to the reference. */
+    if (a->radius > 0.0) {
+        double st = sin(a->angles[tx]), ct = cos(a->angles[tx]), g[4], ref = INFINITY;
+        for (int64_t j = 0; j < a->n_elements; ++j) {
+            or_element_geometry(a, j, g);
+            double v = g[0] * st + g[1] * ct;
+            if (v < ref) ref = v;
+        }
+        or_element_geometry(a, e, g);
+        return (g[0] * st + g[1] * ct - ref) / a->c0;
+    }
     double xe = ((double)e - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
     double x0 = (0.0 - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
     double xl = ((double)(a->n_elements - 1) - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
@@ -115,15 +154,31 @@ static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
     C->ka = (double *)malloc(sizeof(double) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
     C->inv_c = (double *)malloc(sizeof(double) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
     C->xe = (double *)malloc(sizeof(double) * (size_t)a->n_elements);
+    C->ze = (double *)malloc(sizeof(double) * (size_t)a->n_elements);
+    C->sne = (double *)malloc(sizeof(double) * (size_t)a->n_elements);
+    C->cne = (double *)malloc(sizeof(double) * (size_t)a->n_elements);
     C->tau = (double *)malloc(sizeof(double) * (size_t)(a->n_elements * a->n_tx));
-    if (!C->ka || !C->inv_c || !C->xe || !C->tau) return -1;
+    if (!C->ka || !C->inv_c || !C->xe || !C->ze || !C->sne || !C->cne || !C->tau) return -2;
+    /* a convex array: its face must lie inside the box (which absorbs at its
+     * top face), and the cone-restricted element choice is for linear arrays */
+    if (a->radius < 0.0) return -1;
+    if (a->radius > 0.0) {
+        double hp = 0.5 * (double)a->n_elements * a->pitch / a->radius, h = sin(0.5 * hp);
+        if (hp >= 0.5 * PI || a->element_choice != 0 || s->box[2] > -2.0 * a->radius * h * h) return -1;
+    }
     for (int64_t m = 0; m < s->n_mat; ++m) {
         /* alpha [dB/(cm MHz)] * f [MHz] * 100 cm/m * ln(10)/20 Np/dB */
         C->ka[m] = s->mat[3 * m + 1] * (a->f_c * 1e-6) * 100.0 * log(10.0) / 20.0;
         C->inv_c[m] = 1.0 / s->mat[3 * m + 2];
     }
-    for (int64_t e = 0; e < a->n_elements; ++e)
-        C->xe[e] = ((double)e - 0.5 * (double)(a->n_elements - 1)) * a->pitch;
+    for (int64_t e = 0; e < a->n_elements; ++e) {
+        double g[4];
+        or_element_geometry(a, e, g);
+        C->xe[e] = g[0];
+        C->ze[e] = g[1];
+        C->sne[e] = g[2];
+        C->cne[e] = g[3];
+    }
     for (int64_t tx = 0; tx < a->n_tx; ++tx)
         for (int64_t e = 0; e < a->n_elements; ++e)
             C->tau[tx * a->n_elements + e] = a->scheme == 1 ? 0.0 : or_delay(a, tx, e);
@@ -131,6 +186,8 @@ static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
     C->n_per_tx = (double)a->n_elements * (double)a->rays_per_element;
     C->t_max = (double)a->n_samples / a->f_s;
     C->half_ap = 0.5 * (double)a->n_elements * a->pitch;
+    C->dphi = a->radius > 0.0 ? a->pitch / a->radius : 0.0;
+    C->half_arc = 0.5 * (double)a->n_elements * C->dphi;
     C->id_sph0 = s->n_tri;
     C->id_pln0 = s->n_tri + s->n_sph;
     C->id_box = s->n_tri + s->n_sph + s->n_pln;
@@ -139,7 +196,7 @@ static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
 
 static void ctx_free(octx *C)
 {
-    free(C->ka); free(C->inv_c); free(C->xe); free(C->tau);
+    free(C->ka); free(C->inv_c); free(C->xe); free(C->ze); free(C->sne); free(C->cne); free(C->tau);
 }
 
 static void draw(const octx *C, uint32_t ray, int64_t e, int64_t tx, int64_t seg, uint32_t purpose,
@@ -188,9 +245,20 @@ static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3]
     uint32_t x[4];
     draw(C, ray, e, tx, 0, 0, 0, x);
     double u0 = unif(x[0]), u1 = unif(x[1]), u2 = unif(x[2]), u3 = unif(x[3]);
-    o[0] = C->xe[e] + (u0 - 0.5) * a->pitch;
+    /* on a convex array the origin lies on the element's arc and the
+     * direction is drawn about the outward normal there */
+    double sp = 0.0, cp = 1.0;
+    if (a->radius > 0.0) {
+        double ph = ((double)e - 0.5 * (double)(a->n_elements - 1) + (u0 - 0.5)) * C->dphi, h = sin(0.5 * ph);
+        sp = sin(ph);
+        cp = cos(ph);
+        o[0] = a->radius * sp;
+        o[2] = -2.0 * a->radius * h * h;
+    } else {
+        o[0] = C->xe[e] + (u0 - 0.5) * a->pitch;
+        o[2] = 0.0;
+    }
     o[1] = (u1 - 0.5) * a->elevation;
-    o[2] = 0.0;
     double ca, cb, pdf;
     if (a->cdf == NULL) {
         ca = u2;
@@ -214,8 +282,17 @@ static void emit(const octx *C, int64_t tx, int64_t e, uint32_t ray, double o[3]
         cb = ((double)(cell / 32) + u3) / 32.0;
         pdf = (double)a->pdf[(tx * a->n_elements + e) * NCELL + cell] * (double)NCELL / (2.0 * PI);
     }
-    or_hemisphere(ca, cb, d);
-    *w = d[2] / (C->n_per_tx * pdf);
+    double hl[3];
+    or_hemisphere(ca, cb, hl);
+    /* local frame: tangent (cos phi, 0, -sin phi), y, normal (sin phi, 0, cos phi) */
+    if (a->radius > 0.0) {
+        d[0] = hl[0] * cp + hl[2] * sp;
+        d[1] = hl[1];
+        d[2] = hl[2] * cp - hl[0] * sp;
+    } else {
+        d[0] = hl[0]; d[1] = hl[1]; d[2] = hl[2];
+    }
+    *w = hl[2] / (C->n_per_tx * pdf);
 }
 
 /* ------------------------------------------------------ directivity (Eq. 13) */
@@ -477,12 +554,39 @@ static void consider(hit *h, double t, int64_t id)
 /* Closest hit over every primitive with t > EPS_T.  The flat primitive the
  * ray has just left (skip) is excluded; the box exit always exists and loses
  * ties because its id is the largest. */
+/* The face of a convex array is the cylinder of radius R about the y axis
+ * through (0, 0, -R); it absorbs like the box faces (face 6).  A ray from
+ * outside meets it where |(o_x, o_z + R) + t (d_x, d_z)| = R: with
+ * b = (o_x, o_z + R).(d_x, d_z) < 0 (moving towards the axis), the nearer
+ * root t = c / (-b + sqrt(b^2 - a c)), a = d_x^2 + d_z^2,
+ * c = o_x^2 + o_z (o_z + 2R) (the squared distance minus R^2, written
+ * without cancellation). */
+static double probe_face(const or_acq *a, const double o[3], const double d[3])
+{
+    double R = a->radius;
+    double aa = d[0] * d[0] + d[2] * d[2];
+    double b = o[0] * d[0] + (o[2] + R) * d[2];
+    double c = o[0] * o[0] + o[2] * (o[2] + 2.0 * R);
+    if (!(b < 0.0) || aa == 0.0) return INFINITY;
+    double disc = b * b - aa * c;
+    if (disc < 0.0) return INFINITY;
+    double t = c / (-b + sqrt(disc));
+    return t > EPS_T ? t : INFINITY;
+}
+
 static hit closest(const octx *C, const double o[3], const double d[3], int64_t skip)
 {
     const or_scene *s = C->s;
     hit h;
     h.t = box_exit(s->box, o, d, &h.face);
     h.id = C->id_box;
+    if (C->a && C->a->radius > 0.0) {
+        double tp = probe_face(C->a, o, d);
+        if (tp < h.t) {
+            h.t = tp;
+            h.face = 6;
+        }
+    }
     for (int64_t i = 0; i < s->n_tri; ++i) {
         double t;
         if (i == skip) continue;
@@ -642,10 +746,10 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     uint32_t x[4];
     draw(C, ray, e, tx, seg, 2, (uint32_t)k, x);
     int64_t er = e_lo + (int64_t)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
-    double v[3] = {C->xe[er] - q[0], 0.0 - q[1], 0.0 - q[2]};
+    double v[3] = {C->xe[er] - q[0], 0.0 - q[1], C->ze[er] - q[2]};
     double dist = sqrt(dot3(v, v));
     double vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
-    double cos_a = -vh[2];
+    double cos_a = a->radius > 0.0 ? -(vh[0] * C->sne[er] + vh[2] * C->cne[er]) : -vh[2];
     double ca = cos_a > 1.0 ? 1.0 : (cos_a < -1.0 ? -1.0 : cos_a);
     double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
     K->st.scatter_events++;
@@ -779,7 +883,24 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
             return;
         }
         if (h.id == C->id_box) {
-            if (h.face == 2 && fabs(o[0]) <= C->half_ap && fabs(o[1]) <= 0.5 * a->elevation) {
+            if (h.face == 6 && fabs(o[1]) <= 0.5 * a->elevation) {
+                /* convex array: the element whose arc holds the landing point;
+                 * the receive angle is taken to that element's normal */
+                double ph = atan2(o[0], o[2] + a->radius);
+                if (fabs(ph) <= C->half_arc) {
+                    int64_t er = (int64_t)floor(ph / C->dphi + 0.5 * (double)a->n_elements);
+                    if (er < 0) er = 0;
+                    if (er > a->n_elements - 1) er = a->n_elements - 1;
+                    double ca = -(d[0] * C->sne[er] + d[2] * C->cne[er]);
+                    ca = ca > 1.0 ? 1.0 : (ca < -1.0 ? -1.0 : ca);
+                    double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
+                    if (fdir > 0.0) {
+                        K->st.direct_hits++;
+                        record(C, K, 0, tx, er, b, -1, t, w * fdir, o, e, cell);
+                    }
+                }
+            }
+            if (a->radius == 0.0 && h.face == 2 && fabs(o[0]) <= C->half_ap && fabs(o[1]) <= 0.5 * a->elevation) {
                 int64_t er = (int64_t)floor((o[0] + C->half_ap) / a->pitch);
                 if (er < 0) er = 0;
                 if (er > a->n_elements - 1) er = a->n_elements - 1;
@@ -868,7 +989,11 @@ static int trace_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t
         (a->scheme == 1 && a->n_tx != a->n_elements))
         return -1;
     octx C;
-    if (ctx_init(&C, a, s)) return -2;
+    int rc_init = ctx_init(&C, a, s);
+    if (rc_init) {
+        ctx_free(&C);
+        return rc_init;
+    }
     int nt = n_threads;
 #ifdef _OPENMP
     if (nt <= 0) nt = omp_get_max_threads();
@@ -943,7 +1068,11 @@ int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_
                   int64_t *n_ev, double *ch_raw, or_stats *st_out)
 {
     octx C;
-    if (ctx_init(&C, a, s)) return -2;
+    int rc_init = ctx_init(&C, a, s);
+    if (rc_init) {
+        ctx_free(&C);
+        return rc_init;
+    }
     sink K;
     memset(&K, 0, sizeof(K));
     K.ev = ev;
@@ -1019,18 +1148,27 @@ int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *
  * channel signal is linearly interpolated (zero outside [0, S-1)), weighted
  * by a Hann window over the receive aperture and summed over elements and
  * transmits. */
-static void das_point(const or_acq *a, const double *xe, const double *apod, double x, double z,
-                      const double *ch_rf, double out[2])
+static void das_point(const or_acq *a, const double *xe, const double *ze, const double *apod, double x,
+                      double z, const double *ch_rf, double out[2])
 {
     int64_t E = a->n_elements, S = a->n_samples;
     double re = 0.0, im = 0.0;
     for (int64_t tx = 0; tx < a->n_tx; ++tx) {
         double st = sin(a->angles[tx]), ct = cos(a->angles[tx]);
-        double xref = st >= 0 ? xe[0] : xe[E - 1];
-        double ttx = ((x - xref) * st + z * ct) / a->c0;
+        double ttx;
+        if (a->radius > 0.0) {
+            /* convex array: the plane front k.p, referenced like its delays */
+            double ref = INFINITY;
+            for (int64_t e = 0; e < E; ++e)
+                if (xe[e] * st + ze[e] * ct < ref) ref = xe[e] * st + ze[e] * ct;
+            ttx = (x * st + z * ct - ref) / a->c0;
+        } else {
+            double xref = st >= 0 ? xe[0] : xe[E - 1];
+            ttx = ((x - xref) * st + z * ct) / a->c0;
+        }
         for (int64_t e = 0; e < E; ++e) {
-            double dx = x - xe[e];
-            double trx = sqrt(dx * dx + z * z) / a->c0;
+            double dx = x - xe[e], dz = z - ze[e];
+            double trx = sqrt(dx * dx + dz * dz) / a->c0;
             double idx = (ttx + trx) * a->f_s - 0.5;
             double f0 = floor(idx);
             int64_t i0 = (int64_t)f0;
@@ -1045,14 +1183,18 @@ static void das_point(const or_acq *a, const double *xe, const double *apod, dou
     out[1] = im;
 }
 
-static int das_tables(const or_acq *a, double **xe, double **apod)
+static int das_tables(const or_acq *a, double **xe, double **ze, double **apod)
 {
     int64_t E = a->n_elements;
     *xe = (double *)malloc(sizeof(double) * (size_t)E);
+    *ze = (double *)malloc(sizeof(double) * (size_t)E);
     *apod = (double *)malloc(sizeof(double) * (size_t)E);
-    if (!*xe || !*apod) return -2;
+    if (!*xe || !*ze || !*apod) return -2;
     for (int64_t e = 0; e < E; ++e) {
-        (*xe)[e] = ((double)e - 0.5 * (double)(E - 1)) * a->pitch;
+        double g[4];
+        or_element_geometry(a, e, g);
+        (*xe)[e] = g[0];
+        (*ze)[e] = g[1];
         (*apod)[e] = 0.5 - 0.5 * cos(2.0 * PI * ((double)e + 0.5) / (double)E);
     }
     return 0;
@@ -1094,8 +1236,8 @@ int or_synthesize(const or_acq *a, const double *ch_sa, const double *angles, in
 int or_das(const or_acq *a, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
            const double *ch_rf, int n_threads, double *iq)
 {
-    double *xe, *apod;
-    if (das_tables(a, &xe, &apod)) return -2;
+    double *xe, *ze, *apod;
+    if (das_tables(a, &xe, &ze, &apod)) return -2;
     double dx = nx > 1 ? (x1 - x0) / (double)(nx - 1) : 0.0;
     double dz = nz > 1 ? (z1 - z0) / (double)(nz - 1) : 0.0;
     int nt = n_threads;
@@ -1105,20 +1247,22 @@ int or_das(const or_acq *a, int64_t nx, int64_t nz, double x0, double x1, double
 #endif
     for (int64_t ix = 0; ix < nx; ++ix) {
         for (int64_t iz = 0; iz < nz; ++iz)
-            das_point(a, xe, apod, x0 + (double)ix * dx, z0 + (double)iz * dz, ch_rf, iq + 2 * (ix * nz + iz));
+            das_point(a, xe, ze, apod, x0 + (double)ix * dx, z0 + (double)iz * dz, ch_rf, iq + 2 * (ix * nz + iz));
     }
     (void)nt;
     free(xe);
+    free(ze);
     free(apod);
     return 0;
 }
 
 int or_das_points(const or_acq *a, const double *xz, int64_t n, const double *ch_rf, double *iq)
 {
-    double *xe, *apod;
-    if (das_tables(a, &xe, &apod)) return -2;
-    for (int64_t i = 0; i < n; ++i) das_point(a, xe, apod, xz[2 * i], xz[2 * i + 1], ch_rf, iq + 2 * i);
+    double *xe, *ze, *apod;
+    if (das_tables(a, &xe, &ze, &apod)) return -2;
+    for (int64_t i = 0; i < n; ++i) das_point(a, xe, ze, apod, xz[2 * i], xz[2 * i + 1], ch_rf, iq + 2 * i);
     free(xe);
+    free(ze);
     free(apod);
     return 0;
 }
@@ -1136,5 +1280,55 @@ int or_envelope(int64_t n, const double *iq, double dr_db, double *env, double *
         double db = (mx > 0.0 && env[i] > 0.0) ? 20.0 * log10(env[i] / mx) : -dr_db;
         bmode[i] = db < -dr_db ? -dr_db : db;
     }
+    return 0;
+}
+
+/* ------------------------------------------------ sector grids (convex array) */
+/* Pixel (i, j) of a sector grid sits at angle phi_i = p0 + i (p1 - p0)/(np - 1)
+ * from +z and depth r_j = r0 + j (r1 - r0)/(nr - 1) below the array face,
+ * along the ray from the centre of curvature (0, 0, -R):
+ * (x, z) = (R + r) (sin phi, cos phi) - (0, R).  R = 0 gives a sector about
+ * the origin. */
+int or_sector_points(double radius, int64_t np, int64_t nr, double p0, double p1, double r0, double r1, double *xz)
+{
+    if (np < 1 || nr < 1 || radius < 0.0) return -1;
+    double dp = np > 1 ? (p1 - p0) / (double)(np - 1) : 0.0, dr = nr > 1 ? (r1 - r0) / (double)(nr - 1) : 0.0;
+    for (int64_t i = 0; i < np; ++i)
+        for (int64_t j = 0; j < nr; ++j) {
+            double ph = p0 + (double)i * dp, r = radius + r0 + (double)j * dr;
+            xz[2 * (i * nr + j)] = r * sin(ph);
+            xz[2 * (i * nr + j) + 1] = r * cos(ph) - radius;
+        }
+    return 0;
+}
+
+/* Scan conversion of a sector image img[np][nr] (grid as above) onto the
+ * Cartesian grid x_k = x0 + k (x1 - x0)/(nx - 1), z_l likewise: each pixel
+ * takes its polar coordinates about (0, 0, -R), phi = atan2(x, z + R) and
+ * r = |(x, z + R)| - R, and interpolates the image bilinearly in (phi, r)
+ * between the four surrounding samples; pixels outside the sector's closed
+ * (phi, r) rectangle take `fill`. */
+int or_scan_convert(double radius, int64_t np, int64_t nr, double p0, double p1, double r0, double r1,
+                    const double *img, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
+                    double fill, double *out)
+{
+    if (np < 2 || nr < 2 || nx < 1 || nz < 1 || radius < 0.0 || !(p1 > p0) || !(r1 > r0)) return -1;
+    double dp = (p1 - p0) / (double)(np - 1), dr = (r1 - r0) / (double)(nr - 1);
+    double dx = nx > 1 ? (x1 - x0) / (double)(nx - 1) : 0.0, dz = nz > 1 ? (z1 - z0) / (double)(nz - 1) : 0.0;
+    for (int64_t k = 0; k < nx; ++k)
+        for (int64_t l = 0; l < nz; ++l) {
+            double x = x0 + (double)k * dx, zc = z0 + (double)l * dz + radius;
+            double fi = (atan2(x, zc) - p0) / dp, fj = (sqrt(x * x + zc * zc) - radius - r0) / dr;
+            double v = fill;
+            if (fi >= 0.0 && fi <= (double)(np - 1) && fj >= 0.0 && fj <= (double)(nr - 1)) {
+                int64_t i0 = (int64_t)floor(fi), j0 = (int64_t)floor(fj);
+                if (i0 > np - 2) i0 = np - 2;
+                if (j0 > nr - 2) j0 = nr - 2;
+                double a = fi - (double)i0, b = fj - (double)j0;
+                v = (1.0 - a) * ((1.0 - b) * img[i0 * nr + j0] + b * img[i0 * nr + j0 + 1]) +
+                    a * ((1.0 - b) * img[(i0 + 1) * nr + j0] + b * img[(i0 + 1) * nr + j0 + 1]);
+            }
+            out[k * nz + l] = v;
+        }
     return 0;
 }

@@ -12,7 +12,8 @@
  * plain definition of "closest hit" / "every crossing".
  *
  * Units: metres, seconds, m/s; Z in MRayl; alpha in dB/(cm MHz).
- * Frame: x lateral, y elevation, z depth; transducer face z = 0 facing +z.
+ * Frame: x lateral, y elevation, z depth; a linear transducer face lies on
+ * z = 0 facing +z, a convex one on a cylinder about the y axis touching z = 0.
  */
 #ifndef UR_ORACLE_H
 #define UR_ORACLE_H
@@ -35,6 +36,9 @@ typedef struct {
     int64_t scheme;            /* 0 steered plane waves; 1 synthetic aperture: n_tx = n_elements,
                                 * transmit t fires element t alone without delay, its rays drawn
                                 * with the counters of transmit 0 */
+    double radius;             /* 0: linear array on z = 0; > 0: convex array of this radius, centre of
+                                * curvature (0, 0, -radius), pitch = arc length; the box top must lie
+                                * at or above the array's ends and element_choice must be 0 */
 } or_acq;
 
 typedef struct {
@@ -105,6 +109,15 @@ void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, doub
 double or_ggx_d(double alpha, double cos_h);
 double or_ggx_g1(double alpha, double cos_v);
 double or_delay(const or_acq *a, int64_t tx, int64_t e);
+/* Element e's centre x, z and the sine, cosine of its normal's angle from +z. */
+void or_element_geometry(const or_acq *a, int64_t e, double out[4]);
+/* Sector grid [np][nr] pixel positions (x, z) about the centre of curvature. */
+int or_sector_points(double radius, int64_t np, int64_t nr, double p0, double p1, double r0, double r1,
+                     double *xz);
+/* Bilinear scan conversion of a sector image [np][nr] onto a Cartesian grid [nx][nz]. */
+int or_scan_convert(double radius, int64_t np, int64_t nr, double p0, double p1, double r0, double r1,
+                    const double *img, int64_t nx, int64_t nz, double x0, double x1, double z0, double z1,
+                    double fill, double *out);
 int64_t or_closest_hit(const or_scene *s, const double o[3], const double d[3], int64_t skip,
                        double *t_hit);
 int64_t or_crossings(const or_scene *s, const double o[3], const double d[3], double t_max,

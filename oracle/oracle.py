@@ -35,7 +35,8 @@ class Acq(C.Structure):
                 ("c0", C.c_double), ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double),
                 ("alpha_m", C.c_double), ("alpha_c", C.c_double), ("seed", C.c_uint64),
                 ("angles", C.POINTER(C.c_double)), ("pdf", C.POINTER(C.c_float)),
-                ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64), ("scheme", C.c_int64)]
+                ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64), ("scheme", C.c_int64),
+                ("radius", C.c_double)]
 
 
 class SceneS(C.Structure):
@@ -117,6 +118,12 @@ def lib():
         L.or_crossings.argtypes = [P(SceneS), P(C.c_double), P(C.c_double), C.c_double, P(C.c_double),
                                    C.c_int64]
         L.or_crossings.restype = C.c_int64
+        L.or_element_geometry.argtypes = [P(Acq), C.c_int64, P(C.c_double)]
+        L.or_sector_points.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, P(C.c_double)]
+        L.or_scan_convert.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, P(C.c_double), C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, P(C.c_double)]
         _lib = L
     return _lib
 
@@ -164,7 +171,8 @@ def make_acq(acq, seed, keep, pdf=None, cdf=None):
             pitch=acq.pitch, elevation=acq.elevation, f_c=acq.f_c, f_s=acq.f_s, c0=acq.c0,
             n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
             alpha_c=acq.alpha_c, seed=int(seed) & 0xFFFFFFFFFFFFFFFF, angles=_dp(ang),
-            element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)))
+            element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)),
+            radius=float(getattr(acq, "radius", 0.0)))
     if pdf is not None:
         s.pdf = _fp(keep.f32(pdf))
         s.cdf = _fp(keep.f32(cdf))
@@ -399,3 +407,32 @@ def crossings(scene, o, d, t_max, cap=256):
     ts = np.zeros(cap)
     n = lib().or_crossings(C.byref(s), oo, dd, float(t_max), _dp(ts), cap)
     return np.sort(ts[:min(n, cap)])
+
+
+def element_geometry(acq):
+    """(E, 4) array: element centre x, z and sin, cos of its normal's angle."""
+    keep = _Keep()
+    a = make_acq(acq, 0, keep)
+    out = np.zeros((acq.n_elements, 4))
+    for e in range(acq.n_elements):
+        lib().or_element_geometry(C.byref(a), e, _dp(out[e]))
+    return out
+
+
+def sector_points(radius, grid):
+    """(nx*nz, 2) pixel positions of a sector grid (x0, x1 angles; z0, z1 depths)."""
+    xz = np.zeros((grid.nx * grid.nz, 2))
+    if lib().or_sector_points(float(radius), grid.nx, grid.nz, grid.x0, grid.x1, grid.z0, grid.z1, _dp(xz)) != 0:
+        raise RuntimeError("or_sector_points failed")
+    return xz
+
+
+def scan_convert(radius, sector, img, cart, fill):
+    """Bilinear scan conversion of img[nx][nz] on the sector grid onto the Cartesian grid."""
+    src = np.ascontiguousarray(np.asarray(img, np.float64).reshape(sector.nx, sector.nz))
+    out = np.zeros((cart.nx, cart.nz))
+    rc = lib().or_scan_convert(float(radius), sector.nx, sector.nz, sector.x0, sector.x1, sector.z0, sector.z1,
+                               _dp(src), cart.nx, cart.nz, cart.x0, cart.x1, cart.z0, cart.z1, float(fill), _dp(out))
+    if rc != 0:
+        raise RuntimeError("or_scan_convert failed")
+    return out

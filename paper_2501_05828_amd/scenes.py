@@ -7,7 +7,9 @@ the CPU oracle can be fed from it without sharing any method code.
 
 Units are SI (metres, seconds, m/s) except impedance Z in MRayl and
 attenuation alpha in dB/(cm MHz).  Frame: x lateral, y elevation, z depth;
-the transducer face is the plane z = 0 and faces +z.
+a linear transducer's face is the plane z = 0 and faces +z; a convex one's is
+a cylinder about the y axis that touches z = 0 at its middle, with its centre
+of curvature at (0, 0, -radius).
 
 The phantoms stand in for the paper's CT-derived vertebra in water (Sec. 4):
 the real mesh and acquisitions are not available, so procedural tubes with
@@ -71,6 +73,7 @@ class Acquisition:
     binning: int = NEAREST
     element_choice: int = 0      # transducer sampling: 0 uniform over all elements, 1 over those in the cone
     scheme: int = 0              # 0 steered plane waves; 1 synthetic aperture (transmit t = element t alone)
+    radius: float = 0.0          # 0 linear array; > 0 convex array of this radius (pitch = arc length)
 
     @property
     def n_tx(self) -> int:
@@ -89,6 +92,7 @@ class Grid:
     x1: float
     z0: float
     z1: float
+    sector: bool = False         # x0, x1 angles [rad] and z0, z1 depths below a convex array's face
 
 
 @dataclass
@@ -296,7 +300,75 @@ def proposal_init(seed: int = 7):
     return np.concatenate(parts).astype(np.float32), rff.astype(np.float32)
 
 
-CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "large": large}
+def convex_probe(w: Workload, radius: float, margin: float = 1 * MM) -> Workload:
+    """The same scene seen through a convex array of the given radius (same
+    element count and pitch, the pitch now the arc length).  The box top is
+    raised above the array's ends by `margin`, and the image grid becomes a
+    sector grid spanning the array's angles and the box depth."""
+    half = 0.5 * w.acq.n_elements * w.acq.pitch / radius
+    box = np.array(w.scene.box, np.float64).copy()
+    box[2] = -radius * (1.0 - np.cos(half)) - margin
+    scene = dataclasses.replace(w.scene, box=box)
+    acq = dataclasses.replace(w.acq, radius=float(radius))
+    grid = Grid(w.grid.nx, w.grid.nz, -half, half, 1 * MM, float(w.scene.box[5]) - 1 * MM, sector=True)
+    out = dataclasses.replace(w, name=w.name + "-convex", scene=scene, acq=acq, grid=grid, extra=dict(w.extra))
+    r_max = radius + grid.z1
+    out.extra["cart_grid"] = Grid(w.grid.nx, w.grid.nz, -r_max * np.sin(half), r_max * np.sin(half),
+                                  float(box[2]), float(w.scene.box[5]))
+    return out
+
+
+def tiny_convex(scene_seed: int = 1, rays_per_element: int = 1024, n_scatterers: int = 2000) -> Workload:
+    """The tiny scene through a 64-element convex array of radius 20 mm
+    (55 degrees of arc), receive angles alpha_m = 4, alpha_c = 10 deg (wider
+    than the paper's 2 deg so that a small case records direct hits off the
+    flat reflector)."""
+    w = convex_probe(tiny(scene_seed, rays_per_element, n_scatterers), 20 * MM)
+    w.acq = dataclasses.replace(w.acq, alpha_m=np.deg2rad(4.0), alpha_c=np.deg2rad(10.0))
+    w.name = "tiny_convex"
+    return w
+
+
+def convex(scene_seed: int = 1, rays_per_element: int = 100_000, n_phi: int = 300, n_y: int = 100,
+           n_scatterers: int = 200_000, radius: float = 50 * MM) -> Workload:
+    """The paper's acquisition settings (Sec. 4) on a synthetic phantom: a
+    128-element convex array of radius 50 mm spanning 70 degrees, 25 plane
+    waves over -30..30 deg, 5 MHz, 5 cycles, fs 50 MHz, 10 bounces, 20 cm
+    maximum path, alpha_m = alpha_c = 2 deg, 1e5 rays per element
+    (1.28e7 per transmit, 3.2e8 per frame).  The phantom is the bone scene's
+    recipe (three seeded soft-tissue slabs, a 60k-triangle noisy tube at
+    35-45 mm, lognormal scatterers at the same density) in a box wide enough
+    for the sector: x +-85 mm, y +-20 mm, z from above the array's ends to
+    100 mm.  Sector grid 256 angles x 512 depths (1-90 mm), scan converted to
+    512 x 512."""
+    rng = np.random.default_rng(scene_seed)
+    E, opening = 128, np.deg2rad(70.0)
+    pitch = radius * opening / E
+    box = np.array([-85 * MM, -20 * MM, -radius * (1.0 - np.cos(0.5 * opening)) - 1 * MM, 85 * MM, 20 * MM, 100 * MM])
+    mats, pln, pln_mat, _ = _layers(rng, box)
+    mats.append([7.8, 10.0, 1540.0])        # 3: bone
+    ax = rng.uniform(-5, 5) * MM
+    az = rng.uniform(35, 45) * MM
+    tri = tube_mesh(rng, ax, az, n_phi, n_y, 25 * MM, 8 * MM, 2 * MM)
+    tri_mat = np.tile(np.array([[2, 3]], np.int32), (len(tri), 1))
+    pos = rng.uniform(box[:3], box[3:], size=(n_scatterers, 3))
+    amp = np.exp(0.5 * rng.normal(size=(n_scatterers, 1)))
+    scene = Scene(_f64(mats, 3), box, 0, tri, _i32(tri_mat), np.zeros((0, 4)), _empty_i2(),
+                  _f64(pln, 4), _i32(pln_mat), _f64(np.hstack([pos, amp]), 4))
+    acq = Acquisition(E, pitch, 4 * MM, 5e6, 50e6, 6912, np.deg2rad(np.linspace(-30.0, 30.0, 25)),
+                      rays_per_element, 10, 0.2, np.deg2rad(2.0), np.deg2rad(2.0),
+                      1540.0, 5.0, 1540.0 / (2 * 5e6), radius=float(radius))
+    half = 0.5 * opening
+    grid = Grid(256, 512, -half, half, 1 * MM, 90 * MM, sector=True)
+    w = Workload("convex", scene, acq, grid, scene_seed=scene_seed)
+    r_max = radius + 90 * MM
+    w.extra.update(tube_axis=(ax, az),
+                   cart_grid=Grid(512, 512, -r_max * np.sin(half), r_max * np.sin(half), float(box[2]), 90 * MM))
+    return w
+
+
+CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "large": large,
+           "tiny_convex": tiny_convex, "convex": convex}
 
 
 def make(name: str, **kw) -> Workload:
