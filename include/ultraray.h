@@ -58,12 +58,14 @@ typedef struct ur_context ur_context;
  * "front" material (the side its geometric normal points to) from a "back"
  * material; a sphere's front is its outside.  Triangles use the normal
  * (v1 - v0) x (v2 - v0).  The axis-aligned box absorbs every ray that leaves
- * it; its face z = box[2] must be the transducer plane z = 0.  Scatterers are
- * points with a signed re-radiation amplitude. */
+ * it; its face z = box[2] must be the transducer plane z = 0 for a linear
+ * array and lie at or above the ends of a convex one (checked by
+ * ur_transmit_setup).  Scatterers are points with a signed re-radiation
+ * amplitude. */
 typedef struct {
     int64_t n_mat, n_tri, n_sph, n_pln, n_scat, top_medium;
     const double *mat;        /* [n_mat][3] Z [MRayl], alpha [dB/(cm MHz)], c [m/s]; n_mat <= 16 */
-    const double *box;        /* [6] xmin, ymin, zmin(=0), xmax, ymax, zmax                  */
+    const double *box;        /* [6] xmin, ymin, zmin (<= 0), xmax, ymax, zmax               */
     const double *tri;        /* [n_tri][9] v0, v1, v2                                         */
     const int32_t *tri_mat;   /* [n_tri][2] front, back                                        */
     const double *sph;        /* [n_sph][4] centre, radius; n_sph <= 64                        */
@@ -77,13 +79,24 @@ typedef struct {
                                * Walter et al. 2007 weight factor); not supported by the adjoint */
 } ur_scene_desc;
 
-/* Linear array (Sec. 2.3 "Ray Emission": number of lateral elements and
- * elevational extent; a linear array has infinite radius). */
+/* Transducer array (Sec. 2.3 "Ray Emission": number of lateral elements,
+ * elevational extent and radius; a linear array has infinite radius, given
+ * here as radius = 0).  Linear: element centres on the x axis at
+ * (e - (E-1)/2) pitch, all facing +z.  Convex: centre of curvature at
+ * (0, 0, -radius), element e at angle phi_e = (e - (E-1)/2) pitch / radius
+ * (pitch = arc length), centre (radius sin phi_e, 0, radius cos phi_e -
+ * radius), facing (sin phi_e, 0, cos phi_e); rays start on the element's arc
+ * and leave about the local outward normal, the array's cylinder absorbs the
+ * rays that reach it, and the receive angle of Eq. 13 is taken to the normal
+ * of the element hit or sampled.  The array must span less than 180 degrees.
+ * Convex arrays support neither the cone-restricted element choice nor the
+ * adjoint. */
 typedef struct {
     int64_t n_elements;       /* 1 .. 65535                        */
-    double pitch;             /* element pitch [m]                 */
+    double pitch;             /* element pitch [m] (arc length on a convex array) */
     double elevation;         /* element height along y [m]        */
     double f_c;               /* centre frequency [Hz]             */
+    double radius;            /* 0: linear array; > 0: convex array radius [m] */
 } ur_probe_desc;
 
 #define UR_BIN_NEAREST 0      /* a record adds to the sample whose interval holds its time   */
@@ -123,11 +136,17 @@ typedef struct {
 #define UR_APOD_NONE 0
 #define UR_APOD_HANN 1
 
-/* Image grid: pixel (i, j) sits at x = x0 + i (x1-x0)/(nx-1), z = z0 + j (z1-z0)/(nz-1). */
+/* Image grid: pixel (i, j) sits at x = x0 + i (x1-x0)/(nx-1), z = z0 + j (z1-z0)/(nz-1).
+ * A sector grid (sector = 1, for convex arrays) places pixel (i, j) at angle
+ * phi = x0 + i (x1-x0)/(nx-1) [rad] from +z and depth r = z0 + j (z1-z0)/(nz-1)
+ * below the array face along the ray from the centre of curvature:
+ * (x, z) = (R + r)(sin phi, cos phi) - (0, R), R the array radius (0: about the
+ * origin).  Images are stored [nx][nz]. */
 typedef struct {
     int64_t nx, nz, apod;
     double x0, x1, z0, z1;
     double dynamic_range_db;  /* log compression range for the B-mode output (90 dB in Sec. 4) */
+    int64_t sector;           /* 0 Cartesian, 1 sector                                        */
 } ur_grid_desc;
 
 /* Counters of one trace call (filled only when requested). */
@@ -235,6 +254,18 @@ UR_API ur_status ur_synthesize(ur_context *ctx, const float *ch_sa_dev, const do
  * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at
  * half maximum n_cycles / f_c, taps |m| <= ceil(3 sigma f_s), zero outside the
  * record.  Layouts as in ur_trace. */
+/* Scan conversion for display of a sector image (Sec. 4's convex-probe
+ * images): img_dev [sector->nx][sector->nz] (device, FP32, e.g. a B-mode
+ * image from ur_beamform on that sector grid) resampled onto the Cartesian
+ * grid `cart` into out_dev [cart->nx][cart->nz] (device).  Each output pixel
+ * takes its angle and depth about the array's centre of curvature and
+ * interpolates bilinearly between the four surrounding sector samples; pixels
+ * outside the sector get `fill`.  Needs sector->sector = 1 with at least 2 x 2
+ * samples and increasing x and z ranges, and cart->sector = 0.  Asynchronous
+ * on `stream`. */
+UR_API ur_status ur_scan_convert(ur_context *ctx, const ur_grid_desc *sector, const float *img_dev,
+                                 const ur_grid_desc *cart, float fill, float *out_dev, void *stream);
+
 UR_API ur_status ur_pulse(ur_context *ctx, const float *ch_raw_dev, float *ch_rf_dev, void *stream);
 
 /* Plane-wave delay-and-sum with coherent compounding over transmits,

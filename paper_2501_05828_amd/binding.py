@@ -33,7 +33,8 @@ class SceneDesc(C.Structure):
 
 
 class ProbeDesc(C.Structure):
-    _fields_ = [("n_elements", C.c_int64), ("pitch", C.c_double), ("elevation", C.c_double), ("f_c", C.c_double)]
+    _fields_ = [("n_elements", C.c_int64), ("pitch", C.c_double), ("elevation", C.c_double), ("f_c", C.c_double),
+                ("radius", C.c_double)]
 
 
 class AcqDesc(C.Structure):
@@ -44,9 +45,14 @@ class AcqDesc(C.Structure):
                 ("scheme", C.c_int64)]
 
 
+def _grid_desc(grid, apod, dynamic_range_db):
+    return GridDesc(nx=grid.nx, nz=grid.nz, apod=apod, x0=grid.x0, x1=grid.x1, z0=grid.z0, z1=grid.z1,
+                    dynamic_range_db=dynamic_range_db, sector=1 if getattr(grid, "sector", False) else 0)
+
+
 class GridDesc(C.Structure):
     _fields_ = [("nx", C.c_int64), ("nz", C.c_int64), ("apod", C.c_int64), ("x0", C.c_double), ("x1", C.c_double),
-                ("z0", C.c_double), ("z1", C.c_double), ("dynamic_range_db", C.c_double)]
+                ("z0", C.c_double), ("z1", C.c_double), ("dynamic_range_db", C.c_double), ("sector", C.c_int64)]
 
 
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
@@ -92,6 +98,7 @@ SIGNATURES = [
     ("ur_transmit_setup", C.c_int, [_CTX, P(ProbeDesc), P(AcqDesc)]),
     ("ur_set_proposal", C.c_int, [_CTX, C.c_void_p, C.c_void_p]),
     ("ur_synthesize", C.c_int, [_CTX, C.c_void_p, P(C.c_double), C.c_int64, C.c_void_p, C.c_void_p]),
+    ("ur_scan_convert", C.c_int, [_CTX, P(GridDesc), C.c_void_p, P(GridDesc), C.c_float, C.c_void_p, C.c_void_p]),
     ("ur_trace", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, P(TraceStats),
                            C.c_void_p]),
     ("ur_set_limits", C.c_int, [_CTX, C.c_int64, C.c_int64]),
@@ -220,7 +227,8 @@ class Context:
 
     def ur_transmit_setup(self, acq):
         ang = np.ascontiguousarray(np.asarray(acq.angles, np.float64))
-        p = ProbeDesc(n_elements=acq.n_elements, pitch=acq.pitch, elevation=acq.elevation, f_c=acq.f_c)
+        p = ProbeDesc(n_elements=acq.n_elements, pitch=acq.pitch, elevation=acq.elevation, f_c=acq.f_c,
+                      radius=float(getattr(acq, "radius", 0.0)))
         a = AcqDesc(n_tx=len(ang), n_samples=acq.n_samples, rays_per_element=acq.rays_per_element,
                     max_bounces=acq.max_bounces, binning=acq.binning, f_s=acq.f_s, c0=acq.c0,
                     n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
@@ -250,8 +258,7 @@ class Context:
 
     def ur_beamform(self, grid, ch_rf, iq=None, env=None, bmode=None, apod=UR_APOD_HANN, dynamic_range_db=90.0,
                     stream=None):
-        g = GridDesc(nx=grid.nx, nz=grid.nz, apod=apod, x0=grid.x0, x1=grid.x1, z0=grid.z0, z1=grid.z1,
-                     dynamic_range_db=dynamic_range_db)
+        g = _grid_desc(grid, apod, dynamic_range_db)
         rc = self.lib.ur_beamform(self.h, C.byref(g), _ptr(ch_rf), _ptr(iq), _ptr(env), _ptr(bmode),
                                   _stream_ptr(stream))
         self.check(rc, "ur_beamform")
@@ -284,8 +291,7 @@ class Context:
         self.check(self.lib.ur_pulse_adjoint(self.h, _ptr(g_rf), _ptr(g_raw), _stream_ptr(stream)), "ur_pulse_adjoint")
 
     def ur_beamform_adjoint(self, grid, g_rf, iq=None, g_env=None, g_iq=None, apod=UR_APOD_HANN, stream=None):
-        g = GridDesc(nx=grid.nx, nz=grid.nz, apod=apod, x0=grid.x0, x1=grid.x1, z0=grid.z0, z1=grid.z1,
-                     dynamic_range_db=90.0)
+        g = _grid_desc(grid, apod, 90.0)
         rc = self.lib.ur_beamform_adjoint(self.h, C.byref(g), _ptr(iq), _ptr(g_env), _ptr(g_iq), _ptr(g_rf),
                                           _stream_ptr(stream))
         self.check(rc, "ur_beamform_adjoint")
@@ -297,6 +303,11 @@ class Context:
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
         self.check(rc, "ur_trace_adjoint")
+
+    def ur_scan_convert(self, sector, img, cart, out, fill=0.0, stream=None):
+        gs, gc = _grid_desc(sector, UR_APOD_NONE, 90.0), _grid_desc(cart, UR_APOD_NONE, 90.0)
+        self.check(self.lib.ur_scan_convert(self.h, C.byref(gs), _ptr(img), C.byref(gc), float(fill), _ptr(out),
+                                            _stream_ptr(stream)), "ur_scan_convert")
 
     def ur_synthesize(self, ch_sa, angles, out, stream=None):
         ang = np.ascontiguousarray(np.asarray(angles, np.float64))

@@ -49,17 +49,35 @@ __global__ __launch_bounds__(kFirTile) void k_pulse(const float *__restrict__ ra
 // transmit loop; the fractional sample index is formed in FP64 so that the
 // interpolation weight and sample match the reference index exactly; the
 // interpolation and accumulation are FP32.
+// Pixel position: a Cartesian grid point, or on a sector grid the point at
+// angle x0 + ix dx and depth z0 + iz dz along the ray from the centre of
+// curvature (0, 0, -R): (R + r) (sin phi, cos phi) - (0, R).
+__device__ __forceinline__ void das_pixel(const DasParams &p, int ix, int iz, double &x, double &z) {
+    if (p.sector) {
+        double sp, cp;
+        sincos(p.x0 + (double)ix * p.dx, &sp, &cp);
+        const double r = p.radius + (p.z0 + (double)iz * p.dz);
+        x = r * sp;
+        z = r * cp - p.radius;
+    } else {
+        x = p.x0 + (double)ix * p.dx;
+        z = p.z0 + (double)iz * p.dz;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_das(DasParams p) {
     const int iz = blockIdx.x * blockDim.x + threadIdx.x;
     const int ix = blockIdx.y;
     if (iz >= p.nz) return;
-    const double x = p.x0 + (double)ix * p.dx;
-    const double z = p.z0 + (double)iz * p.dz;
+    double x, z;
+    das_pixel(p, ix, iz, x, z);
     const double zz = z * z;
     float re = 0.0f, im = 0.0f;
     for (int e = 0; e < p.E; ++e) {
         const double dxe = x - p.xe[e];
-        const double trx = sqrt(dxe * dxe + zz) * p.fs_over_c0;
+        // (elements off z = 0 only on a convex array)
+        const double dze = p.ze ? z - p.ze[e] : 0.0;
+        const double trx = sqrt(dxe * dxe + (p.ze ? dze * dze : zz)) * p.fs_over_c0;
         const float a = p.apod[e];
         const float2 *ch = p.rf + (int64_t)e * p.S;
         float er = 0.0f, ei = 0.0f;
@@ -129,12 +147,13 @@ __global__ __launch_bounds__(256) void k_das_adj(DasParams p, const float2 *g_iq
     if (iz >= p.nz) return;
     const float2 g = g_iq[(int64_t)ix * p.nz + iz];
     if (g.x == 0.f && g.y == 0.f) return;
-    const double x = p.x0 + (double)ix * p.dx;
-    const double z = p.z0 + (double)iz * p.dz;
+    double x, z;
+    das_pixel(p, ix, iz, x, z);
     const double zz = z * z;
     for (int e = 0; e < p.E; ++e) {
         const double dxe = x - p.xe[e];
-        const double trx = sqrt(dxe * dxe + zz) * p.fs_over_c0;
+        const double dze = p.ze ? z - p.ze[e] : 0.0;
+        const double trx = sqrt(dxe * dxe + (p.ze ? dze * dze : zz)) * p.fs_over_c0;
         const float a = p.apod[e];
         for (int tx = 0; tx < p.T; ++tx) {
             const double4 c = p.txc[tx];
@@ -236,26 +255,30 @@ hipError_t ur_launch_bmode(const float *env, float *bmode, int64_t n, float dr_d
 // ------------------------------------------- synthetic-aperture synthesis
 // Steered plane waves from element-by-element data: each output sample sums
 // over the emitting elements the element's channel shifted by its steering
-// delay tau = (x_e - x_ref) sin(theta) / c0 (Sec. 2.3, Fig. 3) times fs,
-// linearly interpolated, in FP64.  One thread per output sample; for each
+// delay (Sec. 2.3, Fig. 3) times fs, linearly interpolated, in FP64.  The
+// delay is (x_e - x_ref) sin(theta) / c0 on a linear array and
+// (x_e sin(theta) + z_e cos(theta) - min over elements) / c0 on a convex one.  One thread per output sample; for each
 // emitting element the threads of a block read neighbouring samples of one
 // channel.
 namespace {
 constexpr int kSynthMaxAngles = 128;   // 2 KB of kernel arguments
 struct SynthAngles {
     double st[kSynthMaxAngles];     // sin(theta_k)
-    double xref[kSynthMaxAngles];   // x of the first-firing element
+    double ct[kSynthMaxAngles];     // cos(theta_k)
+    double ref[kSynthMaxAngles];    // linear: x of the first-firing element; convex: min_e k.c_e
 };
 
-__global__ __launch_bounds__(256) void k_synth(const float *sa, int E, int S, double pitch, double c0, double fs,
-                                               SynthAngles A, float *out) {
+__global__ __launch_bounds__(256) void k_synth(const float *sa, int E, int S, const double *xe_tab,
+                                               const double *ze_tab, double c0, double fs, SynthAngles A,
+                                               float *out) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int er = blockIdx.y, k = blockIdx.z;
     if (s >= S) return;
     double acc = 0.0;
     for (int e = 0; e < E; ++e) {
-        const double xe = ((double)e - 0.5 * (double)(E - 1)) * pitch;
-        const double sh = (xe - A.xref[k]) * A.st[k] / c0 * fs;
+        const double xe = xe_tab[e];
+        const double sh = ze_tab ? (xe * A.st[k] + ze_tab[e] * A.ct[k] - A.ref[k]) / c0 * fs
+                                 : (xe - A.ref[k]) * A.st[k] / c0 * fs;
         const double u = (double)s - sh, f0 = floor(u), f = u - f0;
         const int i0 = (int)f0;
         const float *x = sa + ((int64_t)e * E + er) * S;
@@ -267,17 +290,82 @@ __global__ __launch_bounds__(256) void k_synth(const float *sa, int E, int S, do
 }
 }  // namespace
 
-hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S, double pitch,
-                                  double c0, double fs, float *out, hipStream_t s) {
+hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S,
+                                  const double *xe_host, const double *ze_host, const double *xe_dev,
+                                  const double *ze_dev, double c0, double fs, float *out, hipStream_t s) {
     if (n_ang <= 0 || E <= 0 || S <= 0) return hipSuccess;
     if (n_ang > kSynthMaxAngles || E > 65535) return hipErrorInvalidValue;
     SynthAngles A;
-    const double x0 = (0.0 - 0.5 * (double)(E - 1)) * pitch, xl = ((double)(E - 1) - 0.5 * (double)(E - 1)) * pitch;
     for (int k = 0; k < n_ang; ++k) {
         A.st[k] = std::sin(angles[k]);
-        A.xref[k] = A.st[k] >= 0 ? x0 : xl;
+        A.ct[k] = std::cos(angles[k]);
+        if (ze_host) {
+            double ref = INFINITY;
+            for (int e = 0; e < E; ++e) ref = std::min(ref, xe_host[e] * A.st[k] + ze_host[e] * A.ct[k]);
+            A.ref[k] = ref;
+        } else {
+            A.ref[k] = A.st[k] >= 0 ? xe_host[0] : xe_host[E - 1];
+        }
     }
     dim3 grid((unsigned)((S + 255) / 256), (unsigned)E, (unsigned)n_ang);
-    hipLaunchKernelGGL(k_synth, grid, dim3(256), 0, s, sa, E, S, pitch, c0, fs, A, out);
+    hipLaunchKernelGGL(k_synth, grid, dim3(256), 0, s, sa, E, S, xe_dev, ze_host ? ze_dev : nullptr, c0, fs, A, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- scan conversion
+// Sector image [np][nr] (angle-major, as the sector grid of k_das) resampled
+// onto a Cartesian grid [nx][nz]: each pixel's polar coordinates about the
+// centre of curvature (0, 0, -R), phi = atan2(x, z + R) and
+// r = |(x, z + R)| - R, index the sector grid; the value is the bilinear
+// blend of the four surrounding samples (weights and blend in FP64), and
+// pixels outside the sector's closed (phi, r) rectangle take `fill`.  One
+// lane per pixel, lanes of a wavefront down one column.
+namespace {
+struct ScanParams {
+    int np, nr, nx, nz;
+    double radius, p0, dp, r0, dr, x0, dx, z0, dz;
+    float fill;
+};
+
+__global__ __launch_bounds__(256) void k_scan_convert(ScanParams q, const float *__restrict__ img,
+                                                      float *__restrict__ out) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (l >= q.nz) return;
+    const double x = q.x0 + (double)k * q.dx, zc = q.z0 + (double)l * q.dz + q.radius;
+    const double fi = (atan2(x, zc) - q.p0) / q.dp, fj = (sqrt(x * x + zc * zc) - q.radius - q.r0) / q.dr;
+    float v = q.fill;
+    if (fi >= 0.0 && fi <= (double)(q.np - 1) && fj >= 0.0 && fj <= (double)(q.nr - 1)) {
+        const int i0 = min((int)floor(fi), q.np - 2), j0 = min((int)floor(fj), q.nr - 2);
+        const double a = fi - (double)i0, b = fj - (double)j0;
+        const float *s0 = img + (int64_t)i0 * q.nr + j0, *s1 = s0 + q.nr;
+        v = (float)((1.0 - a) * ((1.0 - b) * (double)s0[0] + b * (double)s0[1]) +
+                    a * ((1.0 - b) * (double)s1[0] + b * (double)s1[1]));
+    }
+    out[(int64_t)k * q.nz + l] = v;
+}
+}  // namespace
+
+hipError_t ur_launch_scan_convert(double radius, int np, int nr, double p0, double p1, double r0, double r1,
+                                  const float *img, int nx, int nz, double x0, double x1, double z0, double z1,
+                                  float fill, float *out, hipStream_t s) {
+    if (np < 2 || nr < 2 || nx < 1 || nz < 1) return hipErrorInvalidValue;
+    ScanParams q;
+    q.np = np;
+    q.nr = nr;
+    q.nx = nx;
+    q.nz = nz;
+    q.radius = radius;
+    q.p0 = p0;
+    q.dp = (p1 - p0) / (double)(np - 1);
+    q.r0 = r0;
+    q.dr = (r1 - r0) / (double)(nr - 1);
+    q.x0 = x0;
+    q.dx = nx > 1 ? (x1 - x0) / (double)(nx - 1) : 0.0;
+    q.z0 = z0;
+    q.dz = nz > 1 ? (z1 - z0) / (double)(nz - 1) : 0.0;
+    q.fill = fill;
+    dim3 grid((unsigned)((nz + 255) / 256), (unsigned)nx);
+    hipLaunchKernelGGL(k_scan_convert, grid, dim3(256), 0, s, q, img, out);
     return hipGetLastError();
 }

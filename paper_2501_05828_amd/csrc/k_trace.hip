@@ -298,7 +298,25 @@ __device__ __forceinline__ void walk_wide(const TraceParams &P, const double *o,
     if (overflow) walk_threaded<COUNT>(P, o, d, skip, cr, tmf, h, cnt);
 }
 
-// Nearest exit through the box faces (the starting candidate).
+// Face of a convex array: the cylinder of radius R about the y axis through
+// (0, 0, -R), met from outside while moving towards the axis
+// (b = (o_x, o_z + R).(d_x, d_z) < 0) at the nearer root
+// t = c / (-b + sqrt(b^2 - a c)), a = d_x^2 + d_z^2, c = o_x^2 + o_z (o_z + 2R)
+// (squared distance minus R^2 without cancellation).  +inf if missed.
+__device__ __forceinline__ double probe_face(const TraceParams &P, const double *o, const double *d) {
+    const double R = P.radius;
+    const double aa = d[0] * d[0] + d[2] * d[2];
+    const double b = o[0] * d[0] + (o[2] + R) * d[2];
+    const double c = o[0] * o[0] + o[2] * (o[2] + 2.0 * R);
+    const double disc = b * b - aa * c;
+    if (!(b < 0.0) || aa == 0.0 || disc < 0.0) return INFINITY;
+    const double t = c / (-b + sqrt(disc));
+    return t > kEpsT ? t : INFINITY;
+}
+
+// Nearest exit through the box faces or, on a convex array, its face (face 6)
+// (the starting candidate).  CONVEX = false: a kernel variant for linear arrays.
+template <bool CONVEX = true>
 __device__ __forceinline__ Hit box_exit(const TraceParams &P, const double *o, const double *d) {
     Hit h;
     h.t = INFINITY;
@@ -314,6 +332,13 @@ __device__ __forceinline__ Hit box_exit(const TraceParams &P, const double *o, c
         if (t < h.t) {
             h.t = t;
             h.face = fi;
+        }
+    }
+    if (CONVEX && P.convex) {
+        const double tp = probe_face(P, o, d);
+        if (tp < h.t) {
+            h.t = tp;
+            h.face = 6;
         }
     }
     return h;
@@ -443,7 +468,7 @@ __device__ __forceinline__ bool nee_point(const TraceParams &P, Counters &cnt, c
     c.q[1] = o[1] + s * d[1];
     c.q[2] = o[2] + s * d[2];
     const double cc = P.cos_alpha_c;
-    if (cc >= 0.0) {
+    if (cc >= 0.0 && !P.convex) {
         const double vy = c.q[1], mvz = c.q[2];
         if (mvz < 0.0 || mvz * mvz < cc * cc * (vy * vy + mvz * mvz) * (1.0 - 1e-9)) {
             CNT(C_SCAT_EVENTS);
@@ -471,10 +496,21 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     uint32_t x[4];
     draw(P, ray, e, tx, seg, 2, (uint32_t)k, x);
     const int er = e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
-    // cut-off of Eq. 13 without acos or sqrt: with v = element - q,
-    // alpha > alpha_c  <=>  cos(alpha) = -v_z / |v| < cos(alpha_c)
-    const double vx = P.xe[er] - c.q[0], vy = c.q[1], mvz = c.q[2];
-    const double r2 = vx * vx + vy * vy + mvz * mvz;
+    // cut-off of Eq. 13 without acos or sqrt: with v = element - q and n the
+    // element normal, alpha > alpha_c  <=>  cos(alpha) = -v.n / |v| < cos(alpha_c)
+    // (n = +z on a linear array: -v.n = q_z)
+    const double vy = c.q[1];
+    double mvz, r2;
+    if (P.convex) {
+        const double4 g = P.elem[er];
+        const double vx = g.x - c.q[0], vz = g.y - c.q[2];
+        mvz = -(vx * g.z + vz * g.w);
+        r2 = vx * vx + vy * vy + vz * vz;
+    } else {
+        const double vx = P.xe[er] - c.q[0];
+        mvz = c.q[2];
+        r2 = vx * vx + vy * vy + mvz * mvz;
+    }
     const double lhs = mvz * mvz, rhs = cc * cc * r2;
     const bool cut = cc >= 0.0 ? (mvz < 0.0 || lhs < rhs) : (mvz < 0.0 && lhs > rhs);
     CNT(C_SCAT_EVENTS);
@@ -505,10 +541,11 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
 template <bool COUNT, bool LOG>
 __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L, Counters &cnt, const NeeEntry &c) {
     const Material M = P.mat[c.med];
-    const double v[3] = {P.xe[c.er] - c.q[0], 0.0 - c.q[1], 0.0 - c.q[2]};
+    const double4 g = P.convex ? P.elem[c.er] : make_double4(P.xe[c.er], 0.0, 0.0, 1.0);
+    const double v[3] = {g.x - c.q[0], 0.0 - c.q[1], g.y - c.q[2]};
     const double dist = sqrt(dot3(v, v));
     const double vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
-    const double cos_a = -vh[2];
+    const double cos_a = P.convex ? -(vh[0] * g.z + vh[2] * g.w) : -vh[2];
     const double fdir = directivity(acos(fmin(1.0, fmax(-1.0, cos_a))), P.alpha_m, P.alpha_c);
     if (fdir <= 0.0) return;   // exactly at the cut-off
     CNT(C_NEE_CAST);
@@ -680,7 +717,7 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
 // on [0, t_seg) (inline, or queued for the scatter kernel when SPLIT), then
 // transport and the hit itself (see advance).  Returns false when the ray
 // has ended.
-template <bool COUNT, bool LOG, int MODE, bool SPLIT, bool ROUGH = true>
+template <bool COUNT, bool LOG, int MODE, bool SPLIT, bool ROUGH = true, bool CONVEX = true>
 __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R,
                                           const Hit &h, volatile unsigned long long *chunk, bool near_grid = true) {
     const int b = R.seg;
@@ -716,8 +753,25 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
     if (h.id == P.id_box) {
         // (the acos is skipped where the cosine is clearly below cos alpha_c:
         // Eq. 13 is zero there, and the margin is far above acos's rounding)
-        if (h.face == 2 && fabs(o[0]) <= P.half_ap && fabs(o[1]) <= 0.5 * P.elev &&
-            -d[2] >= P.cos_alpha_c - 1e-9) {
+        if (CONVEX && P.convex) {
+            // the element whose arc holds the landing point; the receive
+            // angle is taken to that element's normal
+            if (h.face == 6 && fabs(o[1]) <= 0.5 * P.elev) {
+                const double ph = atan2(o[0], o[2] + P.radius);
+                if (fabs(ph) <= P.half_arc) {
+                    int er = (int)floor(ph / P.dphi + 0.5 * (double)P.E);
+                    er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+                    const double4 g = P.elem[er];
+                    const double ca = fmin(1.0, fmax(-1.0, -(d[0] * g.z + d[2] * g.w)));
+                    const double fdir = directivity(acos(ca), P.alpha_m, P.alpha_c);
+                    if (MODE != kInlineNeeOnly && fdir > 0.0) {
+                        CNT(C_DIRECT);
+                        record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t, R.w * fdir, o, R.e, R.cell);
+                    }
+                }
+            }
+        } else if (h.face == 2 && fabs(o[0]) <= P.half_ap && fabs(o[1]) <= 0.5 * P.elev &&
+                   -d[2] >= P.cos_alpha_c - 1e-9) {
             int er = (int)floor((o[0] + P.half_ap) / P.pitch);
             er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
             const double ca = fmin(1.0, fmax(-1.0, -d[2]));
@@ -952,7 +1006,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // hits, termination), queues the finished segment for the scatter kernel and
 // starts its next query.  So no lane waits for the longest traversal of its
 // wavefront, and the scatterer walk runs elsewhere with its own balance.
-template <bool COUNT, bool ROUGH>
+template <bool COUNT, bool ROUGH, bool CONVEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_extend(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
@@ -977,7 +1031,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     unsigned long long cbeg = 0, cend = 0;
     auto start_segment = [&]() {
         CNT(C_SEGMENTS);
-        h = box_exit(P, R.o, R.d);
+        h = box_exit<CONVEX>(P, R.o, R.d);
         cr = make_cull(R.o, R.d);
         tmf = cull_tmax(h.t);
         near_grid = P.n_scat > 0 && meets_grid(P, cr, R.d, h.t);   // up to the box exit, the longest it can be
@@ -1012,7 +1066,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
                         R.e = P.sa ? (int)q : (int)(q % P.E);   // synthetic aperture: transmit q is element q
                         R.tx = P.sa ? (int)q : (int)(q / P.E);
-                        emit(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
+                        emit<CONVEX>(P, R.tx, R.e, R.ray, R.o, R.d, R.w, R.cell);
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;
                         R.last = -1;
@@ -1038,7 +1092,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (active && !trav) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             analytic_hits(P, R.o, R.d, R.last, h);
-            active = after_hit<COUNT, false, kDeferNee, true, ROUGH>(P, L, cnt, R, h, chunk, near_grid);
+            active = after_hit<COUNT, false, kDeferNee, true, ROUGH, CONVEX>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
                 start_segment();
             } else if (P.cost && R.cell >= 0) {
@@ -1292,32 +1346,38 @@ hipError_t ur_launch_extend(const ur::TraceParams &p, bool count, hipStream_t s)
     if (needed <= 0) return hipSuccess;
     unsigned blocks = 0;
     hipError_t e;
-#define UR_EXTEND(C, RG)                                                   \
-    do {                                                                   \
-        e = resident_blocks(k_extend<C, RG>, needed, blocks);              \
-        if (e != hipSuccess) return e;                                     \
-        hipLaunchKernelGGL((k_extend<C, RG>), dim3(blocks), dim3(256), 0, s, p); \
+#define UR_EXTEND(C, RG, CV)                                                   \
+    do {                                                                       \
+        e = resident_blocks(k_extend<C, RG, CV>, needed, blocks);              \
+        if (e != hipSuccess) return e;                                         \
+        hipLaunchKernelGGL((k_extend<C, RG, CV>), dim3(blocks), dim3(256), 0, s, p); \
+    } while (0)
+#define UR_EXTEND_CV(C, RG)                  \
+    do {                                     \
+        if (p.convex) UR_EXTEND(C, RG, true); \
+        else UR_EXTEND(C, RG, false);        \
     } while (0)
     if (count) {
-        if (p.any_rough) UR_EXTEND(true, true);
-        else UR_EXTEND(true, false);
+        if (p.any_rough) UR_EXTEND_CV(true, true);
+        else UR_EXTEND_CV(true, false);
     } else {
-        if (p.any_rough) UR_EXTEND(false, true);
-        else UR_EXTEND(false, false);
+        if (p.any_rough) UR_EXTEND_CV(false, true);
+        else UR_EXTEND_CV(false, false);
     }
+#undef UR_EXTEND_CV
 #undef UR_EXTEND
     return hipGetLastError();
 }
 
 int64_t ur_extend_max_waves() {
     unsigned most = 0;
-    for (int v = 0; v < 4; ++v) {
+    const void *variants[] = {(const void *)k_extend<true, true, true>,   (const void *)k_extend<true, true, false>,
+                              (const void *)k_extend<true, false, true>,  (const void *)k_extend<true, false, false>,
+                              (const void *)k_extend<false, true, true>,  (const void *)k_extend<false, true, false>,
+                              (const void *)k_extend<false, false, true>, (const void *)k_extend<false, false, false>};
+    for (const void *k : variants) {
         unsigned b = 0;
-        const hipError_t e = v == 0 ? resident_blocks(k_extend<true, true>, int64_t(1) << 40, b)
-                             : v == 1 ? resident_blocks(k_extend<true, false>, int64_t(1) << 40, b)
-                             : v == 2 ? resident_blocks(k_extend<false, true>, int64_t(1) << 40, b)
-                                      : resident_blocks(k_extend<false, false>, int64_t(1) << 40, b);
-        if (e != hipSuccess) return -1;
+        if (resident_blocks(k, int64_t(1) << 40, b) != hipSuccess) return -1;
         most = b > most ? b : most;
     }
     return 4 * (int64_t)most;

@@ -262,15 +262,28 @@ __device__ __forceinline__ void hemisphere(double a, double b, double *d) {
 
 // Emission (Eqs. 4 and 6): origin uniform on the element face, direction from
 // the uniform or tabulated proposal on the equal-area map, weight
-// cos(theta) / (rays per transmit * pdf).
+// cos(theta) / (rays per transmit * pdf).  On a convex array the face is the
+// element's arc, angle phi = (e - (E-1)/2 + u0 - 1/2) dphi about the centre
+// of curvature (0, 0, -R), and the direction is drawn in the frame of the
+// outward normal there: tangent (cos phi, 0, -sin phi), y, normal
+// (sin phi, 0, cos phi).  CONVEX = false: a kernel variant for linear arrays.
+template <bool CONVEX = true>
 __device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32_t ray, double *o, double *d,
                                      double &w, int &cell_out) {
     uint32_t x[4];
     draw(P, ray, e, tx, 0, 0, 0, x);
     const double u0 = u01(x[0]), u1 = u01(x[1]), u2 = u01(x[2]), u3 = u01(x[3]);
-    o[0] = P.xe[e] + (u0 - 0.5) * P.pitch;
+    double sp = 0.0, cp = 1.0;
+    if (CONVEX && P.convex) {
+        const double ph = ((double)e - 0.5 * (double)(P.E - 1) + (u0 - 0.5)) * P.dphi, h = sin(0.5 * ph);
+        sincos(ph, &sp, &cp);
+        o[0] = P.radius * sp;
+        o[2] = -2.0 * P.radius * h * h;
+    } else {
+        o[0] = P.xe[e] + (u0 - 0.5) * P.pitch;
+        o[2] = 0.0;
+    }
     o[1] = (u1 - 0.5) * P.elev;
-    o[2] = 0.0;
     double ca, cb, pdf;
     if (!P.proposal) {
         ca = u2;
@@ -297,6 +310,11 @@ __device__ __forceinline__ void emit(const TraceParams &P, int tx, int e, uint32
     }
     hemisphere(ca, cb, d);
     w = d[2] / (P.n_per_tx * pdf);
+    if (CONVEX && P.convex) {
+        const double hx = d[0], hz = d[2];
+        d[0] = hx * cp + hz * sp;
+        d[2] = hz * cp - hx * sp;
+    }
 }
 
 }  // namespace dev

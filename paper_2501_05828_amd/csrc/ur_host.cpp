@@ -54,6 +54,7 @@ struct ur_context {
     ur_probe_desc probe{};
     ur_acq_desc acq{};
     std::vector<double> angles;
+    std::vector<double> xe_h, ze_h;        // element centres x, z (host copies)
     int K = 0;
     DevBuf d_xe, d_tau, d_taps, d_apod, d_txc, d_stats, d_stats2, d_maxbits, d_env, d_rays, d_events, d_evcount, d_ctr,
         d_nee, d_counters, d_segq, d_segc;
@@ -62,6 +63,7 @@ struct ur_context {
     bool mlp_ready = false;
     int mlp_rows = 0, mlp_step = 0;
     DevBuf d_giq;                          // adjoint of IQ inside ur_beamform_adjoint
+    DevBuf d_elem, d_ze;                   // convex arrays: element centre / normal table, centre depths
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
     RecordEntry *rec = nullptr;
@@ -185,6 +187,11 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
                                                                                    : UR_ELEMENT_UNIFORM;
     P.tan_alpha_c = std::tan(a.alpha_c);
     P.sa = a.scheme == UR_SCHEME_SYNTHETIC;
+    P.convex = pr.radius > 0.0;
+    P.radius = pr.radius;
+    P.dphi = P.convex ? pr.pitch / pr.radius : 0.0;
+    P.half_arc = 0.5 * (double)pr.n_elements * P.dphi;
+    P.elem = (const double4 *)c->d_elem.p;
     P.r_s2 = a.r_s * a.r_s;
     P.n_per_tx = (double)pr.n_elements * (double)a.rays_per_element;
     P.half_ap = 0.5 * (double)pr.n_elements * pr.pitch;
@@ -301,7 +308,7 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
                       &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal, &c->d_segq, &c->d_segc,
-                      &c->d_giq})
+                      &c->d_giq, &c->d_elem, &c->d_ze})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -338,7 +345,8 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                     return c->fail(UR_ERR_SCENE, "material %lld roughness must be in [0, 10]", (long long)m);
         for (int i = 0; i < 3; ++i)
             if (!(s->box[i] < s->box[3 + i])) return c->fail(UR_ERR_SCENE, "box min must be below max");
-        if (s->box[2] != 0.0) return c->fail(UR_ERR_SCENE, "the box face z = box[2] must be the transducer plane z = 0");
+        if (!(s->box[2] <= 0.0))
+            return c->fail(UR_ERR_SCENE, "the box top z = box[2] must be at or above the array (z <= 0)");
         if (s->top_medium < 0 || s->top_medium >= s->n_mat) return c->fail(UR_ERR_SCENE, "top_medium out of range");
         auto bad_mat = [&](const int32_t *m, int64_t n) {
             for (int64_t i = 0; i < 2 * n; ++i)
@@ -477,6 +485,19 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         if (!(p->pitch > 0) || !(p->elevation > 0) || !(p->f_c > 0) || !std::isfinite(p->pitch) ||
             !std::isfinite(p->elevation) || !std::isfinite(p->f_c))
             return c->fail(UR_ERR_INVALID_ARG, "pitch, elevation and f_c must be positive");
+        if (!(p->radius >= 0.0) || !std::isfinite(p->radius))
+            return c->fail(UR_ERR_INVALID_ARG, "radius must be 0 (linear) or positive (convex)");
+        if (p->radius > 0.0) {
+            const double hp = 0.5 * (double)p->n_elements * p->pitch / p->radius, h = std::sin(0.5 * hp);
+            if (!(hp < 0.5 * M_PI)) return c->fail(UR_ERR_INVALID_ARG, "a convex array must span less than 180 degrees");
+            if (!(c->box[2] <= -2.0 * p->radius * h * h))
+                return c->fail(UR_ERR_SCENE, "the box top z = %g must lie at or above the convex array's ends (z = %g)",
+                               c->box[2], -2.0 * p->radius * h * h);
+            if (a->element_choice != UR_ELEMENT_UNIFORM)
+                return c->fail(UR_ERR_UNSUPPORTED, "the cone-restricted element choice needs a linear array");
+        } else if (c->box[2] != 0.0) {
+            return c->fail(UR_ERR_SCENE, "with a linear array the box top z = box[2] must be the array plane z = 0");
+        }
         if (a->n_tx < 1 || a->n_tx > 65535) return c->fail(UR_ERR_INVALID_ARG, "n_tx must be in [1, 65535]");
         if (a->n_samples < 2 || a->n_samples > (1 << 24)) return c->fail(UR_ERR_INVALID_ARG, "n_samples must be in [2, 2^24]");
         if (a->rays_per_element < 0 || a->rays_per_element > 0xFFFFFFFFll)
@@ -511,14 +532,42 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         c->acq.angles = nullptr;
         c->K = K;
         const int64_t E = p->n_elements, T = a->n_tx;
-        // element centres and plane-wave delays referenced to the first-firing element
-        std::vector<double> xe(E), tau(T * E);
-        for (int64_t e = 0; e < E; ++e) xe[e] = ((double)e - 0.5 * (double)(E - 1)) * p->pitch;
+        // element centres and plane-wave delays referenced to the first-firing
+        // element.  A convex array of radius R has its centre of curvature at
+        // (0, 0, -R) and the pitch is the arc length: element e sits at angle
+        // phi_e = (e - (E-1)/2) pitch / R, at (R sin phi_e, -2 R sin^2(phi_e/2)),
+        // facing (sin phi_e, 0, cos phi_e); it fires when the plane front
+        // k = (sin theta, 0, cos theta) passes its centre.
+        const bool convex = p->radius > 0.0;
+        std::vector<double> xe(E), ze(E), tau(T * E), kref(T);
+        std::vector<double4> elem(E);
+        for (int64_t e = 0; e < E; ++e) {
+            const double off = (double)e - 0.5 * (double)(E - 1);
+            if (convex) {
+                const double ph = off * p->pitch / p->radius, h = std::sin(0.5 * ph);
+                xe[e] = p->radius * std::sin(ph);
+                ze[e] = -2.0 * p->radius * h * h;
+                elem[e] = make_double4(xe[e], ze[e], std::sin(ph), std::cos(ph));
+            } else {
+                xe[e] = off * p->pitch;
+                ze[e] = 0.0;
+                elem[e] = make_double4(xe[e], 0.0, 0.0, 1.0);
+            }
+        }
         for (int64_t t = 0; t < T; ++t) {
-            const double st = std::sin(c->angles[t]);
-            const double xref = st >= 0 ? xe[0] : xe[E - 1];
-            for (int64_t e = 0; e < E; ++e)
-                tau[t * E + e] = a->scheme == UR_SCHEME_SYNTHETIC ? 0.0 : (xe[e] - xref) * st / a->c0;
+            const double st = std::sin(c->angles[t]), ct = std::cos(c->angles[t]);
+            if (convex) {
+                double ref = INFINITY;
+                for (int64_t e = 0; e < E; ++e) ref = std::min(ref, xe[e] * st + ze[e] * ct);
+                kref[t] = ref;
+                for (int64_t e = 0; e < E; ++e)
+                    tau[t * E + e] = a->scheme == UR_SCHEME_SYNTHETIC ? 0.0 : (xe[e] * st + ze[e] * ct - ref) / a->c0;
+            } else {
+                const double xref = st >= 0 ? xe[0] : xe[E - 1];
+                kref[t] = xref * st;
+                for (int64_t e = 0; e < E; ++e)
+                    tau[t * E + e] = a->scheme == UR_SCHEME_SYNTHETIC ? 0.0 : (xe[e] - xref) * st / a->c0;
+            }
         }
         // analytic pulse taps (Eq. 14), Gaussian with FWHM of n_cycles periods
         std::vector<float2> taps(2 * K + 1);
@@ -533,8 +582,12 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         const double k = a->f_s / a->c0;
         for (int64_t t = 0; t < T; ++t) {
             const double st = std::sin(c->angles[t]), ct = std::cos(c->angles[t]);
-            const double xref = st >= 0 ? xe[0] : xe[E - 1];
-            txc[t] = make_double4(st * k, ct * k, -xref * st * k - 0.5, 0.0);
+            if (convex) {
+                txc[t] = make_double4(st * k, ct * k, -kref[t] * k - 0.5, 0.0);
+            } else {
+                const double xref = st >= 0 ? xe[0] : xe[E - 1];
+                txc[t] = make_double4(st * k, ct * k, -xref * st * k - 0.5, 0.0);
+            }
         }
         // receive apodisation tables: [0, E) uniform, [E, 2E) Hann over the full aperture
         std::vector<float> apod(2 * E);
@@ -544,7 +597,11 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         }
         ur_status st;
         if ((st = upload(c, c->d_apod, apod))) return st;
+        c->xe_h = xe;
+        c->ze_h = ze;
         if ((st = upload(c, c->d_xe, xe))) return st;
+        if ((st = upload(c, c->d_ze, ze))) return st;
+        if ((st = upload(c, c->d_elem, elem))) return st;
         if ((st = upload(c, c->d_tau, tau))) return st;
         if ((st = upload(c, c->d_taps, taps))) return st;
         if ((st = upload(c, c->d_txc, txc))) return st;
@@ -565,9 +622,10 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         // element) are left out: their captures only ever yield zero-valued
         // secondary rays.
         {
+            // (the cull and the wedge assume a linear array on z = 0)
             const RxCone rx{xe[0], xe[E - 1], a->alpha_c};
             ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6,
-                                               &rx);
+                                               convex ? nullptr : &rx);
             std::vector<double4> items(g.items.size());
             std::vector<float4> items_f(g.items.size());
             for (size_t k = 0; k < g.items.size(); ++k) {
@@ -743,9 +801,32 @@ UR_API ur_status ur_synthesize(ur_context *c, const float *ch_sa_dev, const doub
         for (int64_t k = 0; k < n_ang; ++k)
             if (!std::isfinite(angles[k]) || std::fabs(angles[k]) >= M_PI / 2)
                 return c->fail(UR_ERR_INVALID_ARG, "angle %lld must be finite and within (-pi/2, pi/2)", (long long)k);
+        const bool convex = c->probe.radius > 0.0;
         HIP_TRY(c, ur_launch_synth_angles(ch_sa_dev, angles, (int)n_ang, (int)c->probe.n_elements,
-                                          (int)c->acq.n_samples, c->probe.pitch, c->acq.c0, c->acq.f_s, out_dev,
-                                          (hipStream_t)stream));
+                                          (int)c->acq.n_samples, c->xe_h.data(), convex ? c->ze_h.data() : nullptr,
+                                          (const double *)c->d_xe.p, (const double *)c->d_ze.p, c->acq.c0,
+                                          c->acq.f_s, out_dev, (hipStream_t)stream));
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_scan_convert(ur_context *c, const ur_grid_desc *sector, const float *img_dev,
+                                 const ur_grid_desc *cart, float fill, float *out_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+        if (!sector || !cart || !img_dev || !out_dev) return c->fail(UR_ERR_INVALID_ARG, "NULL argument");
+        if (sector->sector != 1 || cart->sector != 0)
+            return c->fail(UR_ERR_INVALID_ARG, "need a sector source grid and a Cartesian target grid");
+        if (sector->nx < 2 || sector->nz < 2 || sector->nx > 65535 || sector->nz > (1 << 24) || cart->nx < 1 ||
+            cart->nz < 1 || cart->nx > 65535 || cart->nz > (1 << 24))
+            return c->fail(UR_ERR_INVALID_ARG, "grid size out of range");
+        const double gv[] = {sector->x0, sector->x1, sector->z0, sector->z1, cart->x0, cart->x1, cart->z0, cart->z1};
+        if (!finite_all(gv, 8) || !std::isfinite(fill)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
+        if (!(sector->x1 > sector->x0) || !(sector->z1 > sector->z0))
+            return c->fail(UR_ERR_INVALID_ARG, "the sector grid needs x1 > x0 and z1 > z0");
+        HIP_TRY(c, ur_launch_scan_convert(c->probe.radius, (int)sector->nx, (int)sector->nz, sector->x0, sector->x1,
+                                          sector->z0, sector->z1, img_dev, (int)cart->nx, (int)cart->nz, cart->x0,
+                                          cart->x1, cart->z0, cart->z1, fill, out_dev, (hipStream_t)stream));
         return UR_OK;
     });
 }
@@ -760,6 +841,35 @@ UR_API ur_status ur_pulse(ur_context *c, const float *ch_raw_dev, float *ch_rf_d
     });
 }
 
+// Delay-and-sum constants of an image grid.  A sector grid places pixel
+// (i, j) at angle x0 + i dx and depth z0 + j dz along the ray from the
+// array's centre of curvature (the origin for a linear array).
+static DasParams das_params(const ur_context *c, const ur_grid_desc *g) {
+    const int64_t E = c->probe.n_elements;
+    DasParams P;
+    P.E = (int)E;
+    P.T = (int)c->acq.n_tx;
+    P.S = (int)c->acq.n_samples;
+    P.nx = (int)g->nx;
+    P.nz = (int)g->nz;
+    P.sector = g->sector != 0;
+    P.radius = c->probe.radius;
+    P.x0 = g->x0;
+    P.dx = g->nx > 1 ? (g->x1 - g->x0) / (double)(g->nx - 1) : 0.0;
+    P.z0 = g->z0;
+    P.dz = g->nz > 1 ? (g->z1 - g->z0) / (double)(g->nz - 1) : 0.0;
+    P.fs_over_c0 = c->acq.f_s / c->acq.c0;
+    P.fs = c->acq.f_s;
+    P.xe = (const double *)c->d_xe.p;
+    P.ze = c->probe.radius > 0.0 ? (const double *)c->d_ze.p : nullptr;
+    P.apod = (const float *)c->d_apod.p + (g->apod == UR_APOD_HANN ? E : 0);
+    P.txc = (const double4 *)c->d_txc.p;
+    P.rf = nullptr;
+    P.iq = nullptr;
+    P.env = nullptr;
+    return P;
+}
+
 UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, float *iq_dev, float *env_dev,
                              float *bmode_dev, void *stream) {
     return guarded(c, [&]() -> ur_status {
@@ -772,6 +882,7 @@ UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *
         if (!finite_all(gv, 5)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
         if (bmode_dev && !(g->dynamic_range_db > 0)) return c->fail(UR_ERR_INVALID_ARG, "dynamic range must be > 0");
         if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
+        if (g->sector != 0 && g->sector != 1) return c->fail(UR_ERR_INVALID_ARG, "sector must be 0 or 1");
         hipStream_t s = (hipStream_t)stream;
         const int64_t E = c->probe.n_elements, npx = g->nx * g->nz;
         ur_status st;
@@ -780,21 +891,7 @@ UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *
             if ((st = alloc(c, c->d_env, npx * sizeof(float)))) return st;
             env = (float *)c->d_env.p;
         }
-        DasParams P;
-        P.E = (int)E;
-        P.T = (int)c->acq.n_tx;
-        P.S = (int)c->acq.n_samples;
-        P.nx = (int)g->nx;
-        P.nz = (int)g->nz;
-        P.x0 = g->x0;
-        P.dx = g->nx > 1 ? (g->x1 - g->x0) / (double)(g->nx - 1) : 0.0;
-        P.z0 = g->z0;
-        P.dz = g->nz > 1 ? (g->z1 - g->z0) / (double)(g->nz - 1) : 0.0;
-        P.fs_over_c0 = c->acq.f_s / c->acq.c0;
-        P.fs = c->acq.f_s;
-        P.xe = (const double *)c->d_xe.p;
-        P.apod = (const float *)c->d_apod.p + (g->apod == UR_APOD_HANN ? E : 0);
-        P.txc = (const double4 *)c->d_txc.p;
+        DasParams P = das_params(c, g);
         P.rf = (const float2 *)ch_rf_dev;
         P.iq = (float2 *)iq_dev;
         P.env = env;
@@ -951,6 +1048,7 @@ UR_API ur_status ur_beamform_adjoint(ur_context *c, const ur_grid_desc *g, const
         const double gv[] = {g->x0, g->x1, g->z0, g->z1};
         if (!finite_all(gv, 4)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
         if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
+        if (g->sector != 0 && g->sector != 1) return c->fail(UR_ERR_INVALID_ARG, "sector must be 0 or 1");
         hipStream_t s = (hipStream_t)stream;
         const int64_t E = c->probe.n_elements, npx = g->nx * g->nz;
         const float2 *giq = (const float2 *)g_iq_dev;
@@ -960,21 +1058,7 @@ UR_API ur_status ur_beamform_adjoint(ur_context *c, const ur_grid_desc *g, const
             HIP_TRY(c, ur_launch_env_adj((const float2 *)iq_dev, g_env_dev, (float2 *)c->d_giq.p, npx, s));
             giq = (const float2 *)c->d_giq.p;
         }
-        DasParams P;
-        P.E = (int)E;
-        P.T = (int)c->acq.n_tx;
-        P.S = (int)c->acq.n_samples;
-        P.nx = (int)g->nx;
-        P.nz = (int)g->nz;
-        P.x0 = g->x0;
-        P.dx = g->nx > 1 ? (g->x1 - g->x0) / (double)(g->nx - 1) : 0.0;
-        P.z0 = g->z0;
-        P.dz = g->nz > 1 ? (g->z1 - g->z0) / (double)(g->nz - 1) : 0.0;
-        P.fs_over_c0 = c->acq.f_s / c->acq.c0;
-        P.fs = c->acq.f_s;
-        P.xe = (const double *)c->d_xe.p;
-        P.apod = (const float *)c->d_apod.p + (g->apod == UR_APOD_HANN ? E : 0);
-        P.txc = (const double4 *)c->d_txc.p;
+        DasParams P = das_params(c, g);
         P.rf = nullptr;
         P.iq = nullptr;
         P.env = nullptr;
@@ -991,6 +1075,7 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
         for (double r : c->rough)
             if (r > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint does not support rough boundaries");
+        if (c->probe.radius > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint supports linear arrays only");
         if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center && !grads->value)
             return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)

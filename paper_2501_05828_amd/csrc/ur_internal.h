@@ -83,6 +83,9 @@ struct TraceParams {
     double tan_alpha_c;               // its tangent (element choice restricted to the cone)
     int elem_choice;                  // UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE
     int sa;                           // synthetic aperture: transmit t = element t, counters of transmit 0
+    int convex;                       // elements on an arc of radius `radius` (else a line on z = 0)
+    double radius, dphi, half_arc;    // convex: radius, angle per element (pitch / radius), E dphi / 2
+    const double4 *elem;              // convex: [E] centre x, centre z, sin and cos of the normal's angle
     const double *xe;                 // [E]
     const double *tau;                // [T][E]
     const float *pdf, *cdf;           // [T][E][1024] or null
@@ -145,8 +148,11 @@ struct EventLog {
 
 struct DasParams {
     int E, T, S, nx, nz;
+    int sector;                       // pixel (ix, iz) at angle x0 + ix dx, depth z0 + iz dz (convex arrays)
     double x0, dx, z0, dz, fs_over_c0, fs;
+    double radius;                    // centre of curvature (0, 0, -radius) of sector grids
     const double *xe;                 // [E]
+    const double *ze;                 // [E] element depths (convex arrays) or null (all on z = 0)
     const float *apod;                // [E]
     const double4 *txc;               // [T]: (sin*fs/c0, cos*fs/c0, -xref*sin*fs/c0 - 1/2, 0)
     const float2 *rf;                 // [T][E][S]
@@ -164,8 +170,12 @@ hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s
 int64_t ur_extend_max_waves();   // wavefronts of a full extend launch (bounds the queue's chunk slack)
 hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
                                 hipStream_t s);
-hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S, double pitch,
-                                  double c0, double fs, float *out, hipStream_t s);
+hipError_t ur_launch_scan_convert(double radius, int np, int nr, double p0, double p1, double r0, double r1,
+                                  const float *img, int nx, int nz, double x0, double x1, double z0, double z1,
+                                  float fill, float *out, hipStream_t s);
+hipError_t ur_launch_synth_angles(const float *sa, const double *angles, int n_ang, int E, int S,
+                                  const double *xe_host, const double *ze_host, const double *xe_dev,
+                                  const double *ze_dev, double c0, double fs, float *out, hipStream_t s);
 hipError_t ur_launch_pulse(const float *raw, float2 *rf, const float2 *taps, int K, int64_t n_ch, int S,
                            hipStream_t s);
 hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s);

@@ -27,6 +27,11 @@ class Simulator:
         self.iq = torch.empty((g.nx, g.nz, 2), dtype=torch.float32, device=self.dev)
         self.env = torch.empty((g.nx, g.nz), dtype=torch.float32, device=self.dev)
         self.bmode = torch.empty((g.nx, g.nz), dtype=torch.float32, device=self.dev)
+        # a sector image is scan converted to its Cartesian display grid
+        self.cart_grid = workload.extra.get("cart_grid") if getattr(g, "sector", False) else None
+        self.cart = None
+        if self.cart_grid is not None:
+            self.cart = torch.empty((self.cart_grid.nx, self.cart_grid.nz), dtype=torch.float32, device=self.dev)
 
     def set_acquisition(self, acq):
         self.ctx.ur_transmit_setup(acq)
@@ -42,10 +47,16 @@ class Simulator:
         self.ctx.ur_beamform(self.w.grid, self.ch_rf, iq=self.iq, env=self.env,
                              bmode=self.bmode if bmode else None, apod=apod, dynamic_range_db=dynamic_range_db)
 
+    def scan_convert(self, dynamic_range_db=90.0):
+        self.ctx.ur_scan_convert(self.w.grid, self.bmode, self.cart_grid, self.cart, fill=-dynamic_range_db)
+
     def step(self, seed=None):
-        """One pass of the hot path: trace + bin, pulse, DAS, envelope, log."""
+        """One pass of the hot path: trace + bin, pulse, DAS, envelope, log
+        (and, on a sector grid, scan conversion of the B-mode image)."""
         self.trace(seed)
         self.beamform()
+        if self.cart is not None:
+            self.scan_convert()
         return self.env
 
     def kernel_ms(self):

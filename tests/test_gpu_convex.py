@@ -1,0 +1,223 @@
+"""Convex arrays on the GPU against the FP64 oracle: the same paths (exact
+counters), the same events and channel data, delay-and-sum on sector grids,
+scan conversion, synthetic-aperture synthesis with convex delays, and the
+paper's acquisition settings (Sec. 4) sampled at full size."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_05828_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+MM = 1e-3
+TOL_CH = 1e-4          # channel data, relative L2 (FP32 weights and float atomics)
+TOL_SIG = 2e-5         # FP32 DAS / resampling on identical inputs
+EXACT = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast", "nee_blocked",
+         "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce", "term_time", "term_path",
+         "media_mismatch"]
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    a = a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _compare(oracle, w, stride=1, label=""):
+    from paper_2501_05828_amd.sim import Simulator
+    print(f"[convex] {label} rays/el={w.acq.rays_per_element} stride={stride}", flush=True)
+    s = Simulator(w)
+    st = s.trace(stats=True, ray_stride=stride, pulse=False)
+    g = s.ch_raw.cpu().numpy().astype(np.float64)
+    ref, ost = oracle.trace(w, ray_stride=stride)
+    # no audibility cull on a convex array: every capture is counted on both sides
+    for k in EXACT:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    err = rel_l2(g, ref)
+    print(f"[convex] {label} records={ost['records']} direct={ost['direct_hits']} nee={ost['nee_cast']} "
+          f"rel_l2={err:.3e}", flush=True)
+    assert err <= TOL_CH
+    return st, ost
+
+
+def test_convex_tiny_channel_data(torch_gpu, oracle):
+    st, ost = _compare(oracle, scenes.tiny_convex(), label="tiny-convex")
+    assert ost["direct_hits"] > 20 and ost["nee_cast"] > 50
+
+
+def test_convex_tiny_steered_narrow_cone(torch_gpu, oracle):
+    """The paper's 2 degree cone and steering over -30..30 degrees."""
+    w = scenes.tiny_convex(rays_per_element=2048)
+    acq = dataclasses.replace(w.acq, angles=np.deg2rad([-30.0, -7.5, 0.0, 15.0, 30.0]), alpha_m=math.radians(2.0),
+                              alpha_c=math.radians(2.0))
+    _compare(oracle, dataclasses.replace(w, acq=acq), label="tiny-convex-steered")
+
+
+def test_convex_tiny_wide_cone_linear_binning(torch_gpu, oracle):
+    w = scenes.tiny_convex(rays_per_element=512)
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(15.0), alpha_c=math.radians(50.0), binning=scenes.LINEAR)
+    st, ost = _compare(oracle, dataclasses.replace(w, acq=acq), label="tiny-convex-wide")
+    assert ost["nee_cast"] > 500
+
+
+def test_convex_paper_settings_reduced(torch_gpu, oracle):
+    """The paper's acquisition (25 plane waves over -30..30 deg, fs 50 MHz,
+    10 bounces, 20 cm path, 2 deg cone) through a 50 mm convex array on the
+    tube phantom, 6 rays per element and transmit, fewer scatterers."""
+    w = scenes.convex(rays_per_element=6, n_scatterers=20_000)
+    _compare(oracle, w, label="convex-reduced")
+
+
+def test_convex_paper_settings_full_size_sampled(torch_gpu, oracle):
+    """The full configuration (1e5 rays per element, 200k scatterers) traced
+    on every 20000th ray of each (transmit, element) row, in the launch
+    configuration of a full frame."""
+    w = scenes.convex()
+    st, ost = _compare(oracle, w, stride=20000, label="convex-full-sampled")
+    assert st["rays"] == 25 * 128 * 5
+
+
+def test_convex_explicit_rays_same_events(torch_gpu, oracle):
+    """Rays from points of the arc in random directions: the same events,
+    element by element, as the oracle."""
+    w = scenes.tiny_convex()
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(20.0), alpha_c=math.radians(60.0))
+    w = dataclasses.replace(w, acq=acq)
+    R = acq.radius
+    rng = np.random.default_rng(23)
+    rays = []
+    for r in range(3000):
+        ph = rng.uniform(-0.45, 0.45)
+        o = [R * math.sin(ph), rng.uniform(-2, 2) * MM, R * math.cos(ph) - R]
+        th, az = math.acos(rng.uniform(0.8, 1.0)), rng.uniform(0, 2 * math.pi)
+        loc = [math.sin(th) * math.cos(az), math.sin(th) * math.sin(az), math.cos(th)]
+        d = [loc[0] * math.cos(ph) + loc[2] * math.sin(ph), loc[1], loc[2] * math.cos(ph) - loc[0] * math.sin(ph)]
+        rays.append(dict(o=o, d=d, w=1.0, t=1e-7 * r, ray=r, elem=r % 64))
+    from paper_2501_05828_amd.sim import Simulator
+    s = Simulator(w)
+    ev_g, n_g = s.ctx.ur_trace_rays(w.seed, rays, cap=100000)
+    ev_o, _, _ = oracle.trace_rays(w, rays, cap=100000)
+    assert n_g == len(ev_o)
+    key = lambda e: (e["tx"], e["kind"], e["seg"], e["id"], e["elem"], round(e["t"] * 1e12))
+    ev_g, ev_o = sorted(ev_g, key=key), sorted(ev_o, key=key)
+    kinds = set()
+    for a, b in zip(ev_g, ev_o):
+        assert (a["kind"], a["seg"], a["id"], a["elem"]) == (b["kind"], b["seg"], b["id"], b["elem"])
+        assert abs(a["t"] - b["t"]) <= 1e-15 + 1e-12 * abs(b["t"])
+        assert abs(a["value"] - b["value"]) <= 1e-5 * abs(b["value"]) + 1e-300
+        kinds.add(a["kind"])
+    assert {"direct", "scatter", "reflect", "transmit", "end"} <= kinds
+
+
+def test_sector_das_parity(torch_gpu, oracle):
+    """Delay-and-sum on the sector grid of a convex array against the
+    oracle at the same pixel positions, on seeded random channel data."""
+    import torch
+    w = scenes.tiny_convex()
+    acq = dataclasses.replace(w.acq, angles=np.deg2rad([-20.0, 0.0, 11.0]))
+    w = dataclasses.replace(w, acq=acq, grid=dataclasses.replace(w.grid, nx=96, nz=200))
+    from paper_2501_05828_amd.sim import Simulator
+    s = Simulator(w)
+    rng = np.random.default_rng(5)
+    rf = (rng.normal(size=(acq.n_tx, acq.n_elements, acq.n_samples))
+          + 1j * rng.normal(size=(acq.n_tx, acq.n_elements, acq.n_samples))).astype(np.complex64)
+    rf_t = torch.from_numpy(np.stack([rf.real, rf.imag], -1).astype(np.float32)).cuda()
+    s.ctx.ur_beamform(w.grid, rf_t, iq=s.iq, env=s.env)
+    torch.cuda.synchronize()
+    g = s.iq.cpu().numpy().astype(np.float64)
+    giq = (g[..., 0] + 1j * g[..., 1]).ravel()
+    pts = oracle.sector_points(acq.radius, w.grid)
+    idx = rng.choice(len(pts), 600, replace=False)
+    ref = oracle.das_points(acq, pts[idx], rf.astype(np.complex128))
+    assert rel_l2(giq[idx], ref) <= TOL_SIG
+
+
+def test_scan_conversion_parity(torch_gpu, oracle):
+    import torch
+    w = scenes.tiny_convex()
+    from paper_2501_05828_amd.sim import Simulator
+    s = Simulator(w)
+    rng = np.random.default_rng(9)
+    img = rng.normal(size=(w.grid.nx, w.grid.nz)).astype(np.float32)
+    cart = dataclasses.replace(w.extra["cart_grid"], nx=301, nz=257)
+    out = torch.empty((cart.nx, cart.nz), dtype=torch.float32, device="cuda")
+    s.ctx.ur_scan_convert(w.grid, torch.from_numpy(img).cuda(), cart, out, fill=-90.0)
+    torch.cuda.synchronize()
+    ref = oracle.scan_convert(w.acq.radius, w.grid, img.astype(np.float64), cart, -90.0)
+    got = out.cpu().numpy()
+    assert np.array_equal(got == -90.0, ref == -90.0)
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.abs(img).max()
+    assert (ref != -90.0).sum() > 0.3 * ref.size
+
+
+def test_convex_frame_and_display(torch_gpu):
+    """One step of the convex workload: trace, pulse, DAS on the sector grid,
+    B-mode and scan conversion into the display grid."""
+    from paper_2501_05828_amd.sim import Simulator
+    w = scenes.tiny_convex(rays_per_element=256)
+    s = Simulator(w)
+    s.step()
+    import torch
+    torch.cuda.synchronize()
+    cart = s.cart.cpu().numpy()
+    bm = s.bmode.cpu().numpy()
+    assert bm.max() == 0.0 and cart.max() <= 0.0 and cart.min() >= -90.0 and (cart > -90.0).mean() > 0.2
+
+
+def test_convex_synthesis_parity(torch_gpu, oracle):
+    """Plane waves synthesised from element-by-element data with the convex
+    array's delays, against the oracle on seeded random data."""
+    import torch
+    w = scenes.tiny_convex(rays_per_element=4)
+    from paper_2501_05828_amd.sim import Simulator
+    s = Simulator(scenes.synthetic_aperture(w))
+    E, S = w.acq.n_elements, w.acq.n_samples
+    rng = np.random.default_rng(3)
+    sa = rng.normal(size=(E, E, S)).astype(np.float32)
+    ang = np.deg2rad([-25.0, -3.0, 0.0, 12.0])
+    out = torch.empty((len(ang), E, S), dtype=torch.float32, device="cuda")
+    s.ctx.ur_synthesize(torch.from_numpy(sa).cuda(), ang, out)
+    torch.cuda.synchronize()
+    ref = oracle.synthesize(w.acq, sa.astype(np.float64), ang)
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-6
+
+
+def test_convex_synthetic_aperture_trace(torch_gpu, oracle):
+    w = scenes.synthetic_aperture(scenes.tiny_convex(rays_per_element=64))
+    _compare(oracle, w, label="tiny-convex-sa")
+
+
+def test_convex_refusals(torch_gpu):
+    from paper_2501_05828_amd import binding
+    from paper_2501_05828_amd.sim import Simulator
+    w = scenes.tiny_convex(rays_per_element=8)
+    with pytest.raises(binding.URError, match="UNSUPPORTED"):
+        Simulator(dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=1)))
+    box = np.array(w.scene.box).copy()
+    box[2] = -0.5 * MM
+    with pytest.raises(binding.URError, match="SCENE"):
+        Simulator(dataclasses.replace(w, scene=dataclasses.replace(w.scene, box=box)))
+    # a linear array needs the box top on its plane
+    lin = scenes.tiny(rays_per_element=8)
+    with pytest.raises(binding.URError, match="SCENE"):
+        Simulator(dataclasses.replace(lin, scene=dataclasses.replace(lin.scene, box=box)))
+    s = Simulator(w)
+    g = torch_gpu_zeros((1, w.acq.n_elements, w.acq.n_samples))
+    with pytest.raises(binding.URError, match="UNSUPPORTED"):
+        s.ctx.ur_trace_adjoint(w.seed, g, value=torch_gpu_zeros((1,), f64=True))
+
+
+def torch_gpu_zeros(shape, f64=False):
+    import torch
+    return torch.zeros(shape, dtype=torch.float64 if f64 else torch.float32, device="cuda")
