@@ -237,7 +237,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny"])
+    ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=150000)
     ap.add_argument("--experiment", choices=["learned"], default=None,
@@ -346,12 +346,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{w.name} phantom: {acq.n_elements} elements, {acq.n_tx} plane waves "
+            "workload": f"{w.name} phantom: {acq.n_elements} elements"
+                        + (f" on a {acq.radius * 1e3:.0f} mm convex arc" if acq.radius > 0 else "")
+                        + f", {acq.n_tx} plane waves "
                         f"{round(float(acq.angles[0]) * 57.29578)}..{round(float(acq.angles[-1]) * 57.29578)} deg, "
                         f"{acq.n_elements * acq.rays_per_element:.2e} rays/transmit, {acq.max_bounces} bounces, "
                         f"{len(w.scene.tri)} triangles, {len(w.scene.pln)} planes, {len(w.scene.sph)} spheres, "
                         f"{len(w.scene.scat)} scatterers, {acq.n_samples} samples at {acq.f_s / 1e6:.0f} MHz, "
-                        f"DAS {grid.nx}x{grid.nz}",
+                        + (f"DAS on a {grid.nx}x{grid.nz} sector grid, scan converted to "
+                         f"{w.extra['cart_grid'].nx}x{w.extra['cart_grid'].nz}" if grid.sector
+                         else f"DAS {grid.nx}x{grid.nz}"),
             "rays_per_frame": n_rays,
             "scene_seed": w.scene_seed,
         },

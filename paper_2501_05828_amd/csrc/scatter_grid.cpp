@@ -50,11 +50,14 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
     }
     g.info.h = h;
     g.info.inv_h = 1.0 / h;
-    // Every cone lies in |y| <= z tan(alpha_c): its axis is +z through a
-    // point with y = 0.  The 10 um margin dwarfs the rounding of a capture
-    // point and of the clip itself.
+    // Every cone of a linear array lies in |y| <= z tan(alpha_c): its axis is
+    // +z through a point with y = 0.  The 10 um margin dwarfs the rounding of
+    // a capture point and of the clip itself.  (A convex array's cones have
+    // tilted axes: no wedge; the grid box of its kept scatterers bounds the
+    // walks instead.)
     g.info.wy_a = 1e-5;
-    g.info.wy_b = rx && rx->alpha_c < 80.0 * M_PI / 180.0 ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : -1.0;
+    g.info.wy_b = rx && rx->radius == 0.0 && rx->alpha_c < 80.0 * M_PI / 180.0
+                      ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : -1.0;
     const long cells = (long)g.info.n[0] * g.info.n[1] * g.info.n[2];
     g.cell_start.assign(cells + 1, 0);
     auto range = [&](const double *p, int k, int &a, int &b) {

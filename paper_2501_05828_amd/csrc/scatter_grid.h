@@ -43,7 +43,9 @@ struct GridInfo {
 // within [x_lo, x_hi] at y = z = 0, normals +z, acceptance half-angle
 // alpha_c (Eq. 13 is zero beyond it).
 struct RxCone {
-    double x_lo, x_hi, alpha_c;
+    double x_lo, x_hi, alpha_c;       // linear array: element centres on [x_lo, x_hi] of the x axis, facing +z
+    double radius = 0.0;              // convex array: arc radius (centre of curvature (0, 0, -radius)) ...
+    double phi_lo = 0.0, phi_hi = 0.0; // ... and the angles of its end elements' centres
 };
 
 // Whether some point within distance r of p lies in the acceptance cone of an
@@ -51,11 +53,32 @@ struct RxCone {
 // false answer is final).  The distance from p to the cone with apex a is
 // that of the point (axial h, radial rho) to the half-line at angle alpha_c
 // from the axis, and rho is smallest at the apex nearest in x.
+//
+// Convex array: apexes on the arc at angle phi in [phi_lo, phi_hi], axes
+// radial.  For a point at distance s > R from the centre of curvature and at
+// angle psi about it, both the angle to the axis of the apex at phi and the
+// distance to that apex grow with |psi - phi| (d/dc of (s c - R) / |q - a| is
+// s (s (s - R c) + y^2) / |q - a|^3 > 0, c = cos(psi - phi)), so the nearest
+// cone is the one whose apex angle is nearest psi.  Points within r + R of
+// the centre are kept.
 inline bool rx_may_hear(const RxCone &rx, const double *p, double r) {
     if (!(rx.alpha_c < 0.5 * M_PI)) return true;
-    const double xa = p[0] < rx.x_lo ? rx.x_lo : (p[0] > rx.x_hi ? rx.x_hi : p[0]);
-    const double rho = std::hypot(p[0] - xa, p[1]), h = p[2];
     const double ca = std::cos(rx.alpha_c), sa = std::sin(rx.alpha_c);
+    double h, rho;
+    if (rx.radius > 0.0) {
+        const double R = rx.radius, zc = p[2] + R;
+        if (std::hypot(p[0], zc) <= R + r) return true;
+        double ph = std::atan2(p[0], zc);
+        ph = ph < rx.phi_lo ? rx.phi_lo : (ph > rx.phi_hi ? rx.phi_hi : ph);
+        const double sp = std::sin(ph), cp = std::cos(ph);
+        const double vx = p[0] - R * sp, vz = zc - R * cp;
+        h = vx * sp + vz * cp;
+        rho = std::hypot(vx * cp - vz * sp, p[1]);
+    } else {
+        const double xa = p[0] < rx.x_lo ? rx.x_lo : (p[0] > rx.x_hi ? rx.x_hi : p[0]);
+        rho = std::hypot(p[0] - xa, p[1]);
+        h = p[2];
+    }
     if (h * ca + rho * sa >= 0.0) return rho * ca - h * sa <= r;
     return std::hypot(h, rho) <= r;
 }

@@ -622,10 +622,14 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
         // element) are left out: their captures only ever yield zero-valued
         // secondary rays.
         {
-            // (the cull and the wedge assume a linear array on z = 0)
-            const RxCone rx{xe[0], xe[E - 1], a->alpha_c};
+            RxCone rx{xe[0], xe[E - 1], a->alpha_c};
+            if (convex) {
+                rx.radius = p->radius;
+                rx.phi_lo = (0.0 - 0.5 * (double)(E - 1)) * p->pitch / p->radius;
+                rx.phi_hi = ((double)(E - 1) - 0.5 * (double)(E - 1)) * p->pitch / p->radius;
+            }
             ScatterGrid g = build_scatter_grid(c->box, c->scat.data(), (long)c->n_scat, a->r_s, a->r_s * 1e-5 + 1e-6,
-                                               convex ? nullptr : &rx);
+                                               &rx);
             std::vector<double4> items(g.items.size());
             std::vector<float4> items_f(g.items.size());
             for (size_t k = 0; k < g.items.size(); ++k) {

@@ -6,8 +6,11 @@
 // every capture point of a left-out scatterer must lie outside the acceptance
 // cone of every element centre, every capture whose point lies inside some
 // cone must be found exactly once, and the walk may report no other pair
-// than a real capture of a kept scatterer (each at most once).
-// usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed> [x_lo x_hi alpha_c]
+// than a real capture of a kept scatterer (each at most once).  With a
+// radius, the elements sit on a convex arc (centre of curvature (0, 0, -R),
+// end elements at angles phi_lo, phi_hi, each facing along its radius).
+// usage: grid_selfcheck <scat.bin> <n> <box.bin> <r_s> <n_segments> <seed>
+//                       [x_lo x_hi alpha_c [radius phi_lo phi_hi]]
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
@@ -33,6 +36,11 @@ int main(int argc, char **argv) {
     const bool cull = argc >= 10;
     RxCone rx{0.0, 0.0, M_PI};
     if (cull) rx = RxCone{std::atof(argv[7]), std::atof(argv[8]), std::atof(argv[9])};
+    if (argc >= 13) {
+        rx.radius = std::atof(argv[10]);
+        rx.phi_lo = std::atof(argv[11]);
+        rx.phi_hi = std::atof(argv[12]);
+    }
     ScatterGrid g = build_scatter_grid(box.data(), S.data(), n, rs, rs * 1e-5 + 1e-6, cull ? &rx : nullptr);
     std::vector<char> kept(n, 0);
     for (int i : g.items) kept[i] = 1;
@@ -62,9 +70,16 @@ int main(int argc, char **argv) {
     const int n_el = 128;
     auto heard_at = [&](const double *q) {
         for (int e = 0; e < n_el; ++e) {
-            const double xe = rx.x_lo + (rx.x_hi - rx.x_lo) * e / (n_el - 1);
-            const double v[3] = {xe - q[0], -q[1], -q[2]};
-            const double cosa = -v[2] / std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            double c[3] = {rx.x_lo + (rx.x_hi - rx.x_lo) * e / (n_el - 1), 0.0, 0.0}, n[3] = {0.0, 0.0, 1.0};
+            if (rx.radius > 0.0) {
+                const double ph = rx.phi_lo + (rx.phi_hi - rx.phi_lo) * e / (n_el - 1);
+                c[0] = rx.radius * std::sin(ph);
+                c[2] = rx.radius * std::cos(ph) - rx.radius;
+                n[0] = std::sin(ph);
+                n[2] = std::cos(ph);
+            }
+            const double v[3] = {q[0] - c[0], q[1] - c[1], q[2] - c[2]};
+            const double cosa = (v[0] * n[0] + v[1] * n[1] + v[2] * n[2]) / std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             if (cosa >= std::cos(rx.alpha_c)) return true;
         }
         return false;

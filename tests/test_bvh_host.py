@@ -128,3 +128,22 @@ def test_scatter_grid_audibility_cull(grid_checker, alpha_c_deg, r_s):
         assert kept == 20000
     if alpha_c_deg == 2.0:
         assert kept < 0.25 * 20000 and _field(out, "culled_events") > 0, out
+
+
+@pytest.mark.parametrize("alpha_c_deg,r_s", [(2.0, 1.54e-4), (2.0, 2e-3), (15.0, 1e-3), (90.0, 1e-3)])
+def test_scatter_grid_audibility_cull_convex(grid_checker, alpha_c_deg, r_s):
+    """The same guarantees for a 128-element convex array of radius 50 mm
+    spanning 70 degrees (apexes on the arc, radial axes): no capture that an
+    element centre's cone holds is lost, and the walk reports nothing else."""
+    w = scenes.convex(rays_per_element=1, n_scatterers=20000)
+    R, E = w.acq.radius, w.acq.n_elements
+    half = 0.5 * (E - 1) * w.acq.pitch / R
+    rx = (0.0, 0.0, np.radians(alpha_c_deg), R, -half, half)
+    out = _run_grid(grid_checker, w.scene.scat, w.scene.box, r_s, 1500, seed=5, rx=rx)
+    assert "bad=0" in out and "heard_culled=0" in out, out
+    kept = _field(out, "kept")
+    assert _field(out, "heard") > 0, out
+    if alpha_c_deg >= 90.0:
+        assert kept == 20000
+    if alpha_c_deg == 2.0:
+        assert kept < 0.25 * 20000 and _field(out, "culled_events") > 0, out
