@@ -58,6 +58,10 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
     g.info.wy_a = 1e-5;
     g.info.wy_b = rx && rx->radius == 0.0 && rx->alpha_c < 80.0 * M_PI / 180.0
                       ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : -1.0;
+    // (for a convex array: |y| <= |q - c| sin(alpha) <= tan(alpha) (q - c).n
+    // <= tan(alpha_c) (s - R), with (q - c).n = (x, z + R).n - R <= s - R)
+    g.info.cv_r = rx && rx->radius > 0.0 && rx->alpha_c < 80.0 * M_PI / 180.0 ? rx->radius : 0.0;
+    g.info.cv_tan = g.info.cv_r > 0.0 ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : 0.0;
     const long cells = (long)g.info.n[0] * g.info.n[1] * g.info.n[2];
     g.cell_start.assign(cells + 1, 0);
     auto range = [&](const double *p, int k, int &a, int &b) {

@@ -37,11 +37,16 @@ struct GridInfo {
     // acceptance wedge |y| <= wy_a + wy_b z that holds every point some
     // element can hear (the walk is clipped to it); wy_b < 0: no wedge
     double wy_a, wy_b;
+    // convex array (cv_r > 0): a point at distance s from the centre of
+    // curvature (0, 0, -cv_r) that some element hears has
+    // |y| <= wy_a + cv_tan (s - cv_r); s is convex along a segment, so each
+    // walk is clipped to |y| <= wy_a + cv_tan (max of s at its ends - cv_r)
+    double cv_r, cv_tan;
 };
 
 // Receiving aperture for the audibility cull: element centres on the x axis
-// within [x_lo, x_hi] at y = z = 0, normals +z, acceptance half-angle
-// alpha_c (Eq. 13 is zero beyond it).
+// within [x_lo, x_hi] at y = z = 0, normals +z, or on a convex arc, and the
+// acceptance half-angle alpha_c (Eq. 13 is zero beyond it).
 struct RxCone {
     double x_lo, x_hi, alpha_c;       // linear array: element centres on [x_lo, x_hi] of the x axis, facing +z
     double radius = 0.0;              // convex array: arc radius (centre of curvature (0, 0, -radius)) ...
@@ -114,11 +119,21 @@ struct DdaIter {
                 return false;
             }
         }
-        if (g.wy_b >= 0.0) {
-            // the two half-spaces +-y - wy_b z - wy_a <= 0 along the ray
+        if (g.wy_b >= 0.0 || g.cv_r > 0.0) {
+            // the two half-spaces +-y - wb z - wa <= 0 along the ray: the
+            // linear array's wedge, or the convex array's slab of this segment
+            double wa = g.wy_a, wb = g.wy_b;
+            if (g.cv_r > 0.0) {
+                if (!(t0 < t1)) return false;
+                const double za = o[2] + g.cv_r + t0 * d[2], zb = o[2] + g.cv_r + t1 * d[2];
+                const double xa = o[0] + t0 * d[0], xb = o[0] + t1 * d[0];
+                const double s = fmax(sqrt(xa * xa + za * za), sqrt(xb * xb + zb * zb));
+                wa += g.cv_tan * fmax(0.0, s - g.cv_r);
+                wb = 0.0;
+            }
             for (int sgn = -1; sgn <= 1; sgn += 2) {
-                const double c0 = (double)sgn * o[1] - g.wy_b * o[2] - g.wy_a;
-                const double c1 = (double)sgn * d[1] - g.wy_b * d[2];
+                const double c0 = (double)sgn * o[1] - wb * o[2] - wa;
+                const double c1 = (double)sgn * d[1] - wb * d[2];
                 if (c1 > 0.0) t1 = fmin(t1, -c0 / c1);
                 else if (c1 < 0.0) t0 = fmax(t0, -c0 / c1);
                 else if (c0 > 0.0) return false;
