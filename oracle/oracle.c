@@ -164,7 +164,7 @@ static int ctx_init(octx *C, const or_acq *a, const or_scene *s)
     if (a->radius < 0.0) return -1;
     if (a->radius > 0.0) {
         double hp = 0.5 * (double)a->n_elements * a->pitch / a->radius, h = sin(0.5 * hp);
-        if (hp >= 0.5 * PI || a->element_choice != 0 || s->box[2] > -2.0 * a->radius * h * h) return -1;
+        if (hp >= 0.5 * PI || s->box[2] > -2.0 * a->radius * h * h) return -1;
     }
     for (int64_t m = 0; m < s->n_mat; ++m) {
         /* alpha [dB/(cm MHz)] * f [MHz] * 100 cm/m * ln(10)/20 Np/dB */
@@ -697,6 +697,55 @@ static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, 
     }
 }
 
+/* Element choice for transducer sampling (Sec. 2.3).  Uniform over all E
+ * element centres, or, with element_choice = 1, uniform over the K elements
+ * whose centre can lie inside the acceptance cone of q (Eq. 13 is zero for
+ * the others); the contribution carries 1/p = E or K.  Sets [*e_lo,
+ * *e_lo + *n_e) and returns 0 when no element can hear q.
+ * Linear array: |x_e - q_x| <= rho with rho^2 = q_z^2 tan^2(alpha_c) - q_y^2.
+ * Convex array: with q at distance s > R from the centre of curvature, angle
+ * psi about it and elevation y, the cosine of the angle between q - c(phi)
+ * and the normal at phi grows with c = cos(psi - phi) (for c >= R/s), and
+ * reaches cos(alpha_c) at
+ * c* = (R sin^2 alpha_c + cos alpha_c sqrt(s^2 + y^2 - R^2 sin^2 alpha_c)) / s,
+ * the larger root of (s c - R)^2 = cos^2(alpha_c) |q - c(phi)|^2: the
+ * elements with |phi_e - psi| <= acos(c*), none if c* > 1.
+ * Both intervals are widened by a relative 1e-9 so that rounding never drops
+ * an element. */
+int or_cone_elements(const or_acq *a, const double q[3], int64_t *e_lo, int64_t *n_e)
+{
+    *e_lo = 0;
+    *n_e = a->n_elements;
+    if (a->element_choice != 1 || !(a->alpha_c < 0.5 * PI)) return 1;
+    double half = 0.5 * (double)(a->n_elements - 1), lo_f = 0.0, hi_f = -1.0;
+    if (a->radius > 0.0) {
+        double R = a->radius, zc = q[2] + R;
+        double sq = sqrt(q[0] * q[0] + zc * zc), sa = sin(a->alpha_c), ca = cos(a->alpha_c);
+        if (sq > R) {
+            double cs = (R * sa * sa + ca * sqrt(sq * sq + q[1] * q[1] - R * R * sa * sa)) / sq;
+            if (cs <= 1.0) {
+                double dl = acos(cs) * (1.0 + 1e-9) + 1e-12, psi = atan2(q[0], zc), dphi = a->pitch / R;
+                lo_f = ceil((psi - dl) / dphi + half);
+                hi_f = floor((psi + dl) / dphi + half);
+            }
+        }
+    } else {
+        double tc = tan(a->alpha_c);
+        double rho2 = q[2] * q[2] * tc * tc - q[1] * q[1];
+        if (q[2] > 0.0 && rho2 >= 0.0) {
+            double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
+            lo_f = ceil((q[0] - rho) / a->pitch + half);
+            hi_f = floor((q[0] + rho) / a->pitch + half);
+        }
+    }
+    if (lo_f < 0.0) lo_f = 0.0;
+    if (hi_f > (double)(a->n_elements - 1)) hi_f = (double)(a->n_elements - 1);
+    if (hi_f < lo_f) return 0;
+    *e_lo = (int64_t)lo_f;
+    *n_e = (int64_t)hi_f - *e_lo + 1;
+    return 1;
+}
+
 /* ------------------------------------------ transducer sampling at scatterers */
 /* A point scatterer k whose capture capsule (radius r_s) contains the primary
  * segment re-radiates isotropically with signed albedo a_k.  A secondary ray
@@ -716,32 +765,11 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     double q[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
     double wq = w * exp(-C->ka[med] * s);
     double tq = t + s * C->inv_c[med];
-    /* Element choice.  Uniform over all E element centres (Sec. 2.3), or,
-     * with element_choice = 1, uniform over the K elements whose centre can
-     * lie inside the acceptance cone of q (Eq. 13 is zero for the others):
-     * |x_e - q_x| <= rho with rho^2 = q_z^2 tan^2(alpha_c) - q_y^2, the
-     * interval widened by a relative 1e-9 so that rounding never drops an
-     * element.  The contribution carries 1/p = E or K. */
     int64_t e_lo = 0, n_e = a->n_elements;
-    if (a->element_choice == 1 && a->alpha_c < 0.5 * PI) {
-        double tc = tan(a->alpha_c);
-        double rho2 = q[2] * q[2] * tc * tc - q[1] * q[1];
-        double lo_f = 0.0, hi_f = -1.0;
-        if (q[2] > 0.0 && rho2 >= 0.0) {
-            double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
-            double half = 0.5 * (double)(a->n_elements - 1);
-            lo_f = ceil((q[0] - rho) / a->pitch + half);
-            hi_f = floor((q[0] + rho) / a->pitch + half);
-            if (lo_f < 0.0) lo_f = 0.0;
-            if (hi_f > (double)(a->n_elements - 1)) hi_f = (double)(a->n_elements - 1);
-        }
-        if (hi_f < lo_f) {
-            K->st.scatter_events++;
-            K->st.nee_zero++;
-            return;
-        }
-        e_lo = (int64_t)lo_f;
-        n_e = (int64_t)hi_f - e_lo + 1;
+    if (a->element_choice == 1 && !or_cone_elements(a, q, &e_lo, &n_e)) {
+        K->st.scatter_events++;
+        K->st.nee_zero++;
+        return;
     }
     uint32_t x[4];
     draw(C, ray, e, tx, seg, 2, (uint32_t)k, x);

@@ -38,7 +38,7 @@ typedef struct {
                                 * with the counters of transmit 0 */
     double radius;             /* 0: linear array on z = 0; > 0: convex array of this radius, centre of
                                 * curvature (0, 0, -radius), pitch = arc length; the box top must lie
-                                * at or above the array's ends and element_choice must be 0 */
+                                * at or above the array's ends */
 } or_acq;
 
 typedef struct {
@@ -109,6 +109,8 @@ void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, doub
 double or_ggx_d(double alpha, double cos_h);
 double or_ggx_g1(double alpha, double cos_v);
 double or_delay(const or_acq *a, int64_t tx, int64_t e);
+/* Elements a capture point can hear (cone-restricted choice); 0 if none. */
+int or_cone_elements(const or_acq *a, const double q[3], int64_t *e_lo, int64_t *n_e);
 /* Element e's centre x, z and the sine, cosine of its normal's angle from +z. */
 void or_element_geometry(const or_acq *a, int64_t e, double out[4]);
 /* Sector grid [np][nr] pixel positions (x, z) about the centre of curvature. */

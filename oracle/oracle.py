@@ -119,6 +119,7 @@ def lib():
                                    C.c_int64]
         L.or_crossings.restype = C.c_int64
         L.or_element_geometry.argtypes = [P(Acq), C.c_int64, P(C.c_double)]
+        L.or_cone_elements.argtypes = [P(Acq), P(C.c_double), P(C.c_int64), P(C.c_int64)]
         L.or_sector_points.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
                                        C.c_double, P(C.c_double)]
         L.or_scan_convert.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -436,3 +437,13 @@ def scan_convert(radius, sector, img, cart, fill):
     if rc != 0:
         raise RuntimeError("or_scan_convert failed")
     return out
+
+
+def cone_elements(acq, q):
+    """(e_lo, n_e) of the cone-restricted element choice at point q, or None."""
+    keep = _Keep()
+    a = make_acq(acq, 0, keep)
+    qq = (C.c_double * 3)(*map(float, q))
+    lo, n = C.c_int64(0), C.c_int64(0)
+    ok = lib().or_cone_elements(C.byref(a), qq, C.byref(lo), C.byref(n))
+    return (lo.value, n.value) if ok else None

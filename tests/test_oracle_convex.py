@@ -167,10 +167,8 @@ def test_large_radius_reproduces_the_linear_array(oracle):
     assert np.allclose(ch_c, ch_l, rtol=0, atol=1e-6 * np.abs(ch_l).max())
 
 
-def test_convex_rejects_what_it_does_not_support(oracle):
+def test_convex_rejects_a_box_through_the_array(oracle):
     w = scenes.tiny_convex(rays_per_element=4)
-    with pytest.raises(RuntimeError):      # cone-restricted element choice
-        oracle.trace(dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=1)))
     box = np.array(w.scene.box).copy()
     box[2] = -0.5 * MM                     # box top cuts through the array
     with pytest.raises(RuntimeError):
@@ -242,3 +240,79 @@ def test_convex_das_focuses_point_echo(oracle):
     env = np.abs(oracle.das_points(acq, np.array([[x, z] for x in xs for z in zs]), rf)).reshape(13, 13)
     i, j = np.unravel_index(env.argmax(), env.shape)
     assert abs(xs[i] - x0) <= 0.1 * MM and abs(zs[j] - z0) <= 0.05 * MM
+
+
+@pytest.mark.parametrize("radius", [0.0, 20 * MM, 50 * MM])
+def test_cone_elements_are_exactly_the_hearing_ones(oracle, radius):
+    """The cone-restricted element range (R40 for linear, its convex form of
+    R42) against brute force over every element centre: it holds every
+    element whose acceptance cone contains the point, and nothing else
+    beyond elements at the cut-off to within 1e-7 rad."""
+    ac = math.radians(6.0)
+    acq = _convex_acq(E=128, pitch=0.45 * MM, radius=radius, alpha_m=math.radians(2.0), alpha_c=ac,
+                      element_choice=1)
+    g = oracle.element_geometry(acq)
+    rng = np.random.default_rng(11)
+    n_hit = n_none = 0
+    for _ in range(3000):
+        q = np.array([rng.uniform(-40, 40) * MM, rng.normal(0, 1.5) * MM, rng.uniform(0.5, 90) * MM])
+        v = q[None, :] - np.stack([g[:, 0], np.zeros(len(g)), g[:, 1]], 1)
+        cosa = (v[:, 0] * g[:, 2] + v[:, 2] * g[:, 3]) / np.linalg.norm(v, axis=1)
+        al = np.arccos(np.clip(cosa, -1, 1))
+        heard = np.nonzero(al <= ac)[0]
+        r = oracle.cone_elements(acq, q)
+        if r is None:
+            assert len(heard) == 0 or np.all(np.abs(al[heard] - ac) < 1e-7)
+            n_none += 1
+            continue
+        lo, n = r
+        rng_set = np.arange(lo, lo + n)
+        assert set(heard) <= set(rng_set)
+        extra = np.setdiff1d(rng_set, heard)
+        assert np.all(np.abs(al[extra] - ac) < 1e-7), (q, al[extra] - ac)
+        n_hit += 1
+    assert n_hit > 300 and n_none > 100
+
+
+@pytest.mark.parametrize("choice", [0, 1])
+def test_convex_element_choice_expectation_closed_form(oracle, choice):
+    """One scatterer in attenuating water under a convex array: the mean
+    recorded contribution equals the closed-form sum over all elements of the
+    Eq. 13-weighted, attenuated re-radiation toward each centre (normal of
+    each element), for the uniform (weight E) and the cone choice (weight K)
+    alike; within 5 standard errors."""
+    alpha, c, R = 0.7, 1500.0, 20 * MM
+    p = np.array([1.3 * MM, 0.05 * MM, 15 * MM])
+    amp = 1.3
+    box = np.array([-30 * MM, -20 * MM, -4 * MM, 30 * MM, 20 * MM, 40 * MM])
+    sc = scenes.Scene(np.array([[1.5, alpha, c]]), box, 0, np.zeros((0, 9)), np.zeros((0, 2), np.int32),
+                      np.zeros((0, 4)), np.zeros((0, 2), np.int32), np.zeros((0, 4)), np.zeros((0, 2), np.int32),
+                      np.array([[p[0], p[1], p[2], amp]]))
+    acq = _convex_acq(radius=R, alpha_m=math.radians(2.0), alpha_c=math.radians(5.0), element_choice=choice)
+    w = dataclasses.replace(scenes.tiny(), scene=sc, acq=acq)
+    g = oracle.element_geometry(acq)
+    o = np.array([0.3 * MM, 0.0, -1 * MM])
+    d = p - o
+    d[1] = 0.0
+    d /= np.linalg.norm(d)
+    n = 3000
+    rays = [dict(o=o, d=d, w=2.0, t=1e-6, ray=r, elem=3) for r in range(n)]
+    ev, _, _ = oracle.trace_rays(w, rays, cap=4 * n)
+    s = np.dot(p - o, d)
+    q = o + s * d
+    ka = alpha * 5 * 100 * math.log(10) / 20
+    want = 0.0
+    for k in range(acq.n_elements):
+        ce = np.array([g[k, 0], 0.0, g[k, 1]])
+        v = q - ce
+        r = np.linalg.norm(v)
+        cos_a = (v[0] * g[k, 2] + v[2] * g[k, 3]) / r
+        al = math.acos(min(1.0, cos_a))
+        f = 1.0 if al <= acq.alpha_m else (0.0 if al > acq.alpha_c else (acq.alpha_c - al) / (acq.alpha_c - acq.alpha_m))
+        want += 2.0 * math.exp(-ka * (s + r)) * amp * acq.pitch * acq.elevation * cos_a * f / (4 * math.pi * r * r)
+    recs = [e["value"] for e in ev if e["kind"] == "scatter"]
+    vals = np.array(recs + [0.0] * (n - len(recs)))
+    se = vals.std(ddof=1) / math.sqrt(n)
+    assert want > 0 and abs(vals.mean() - want) < 5 * se + 1e-15
+    if choice == 1:
+        assert len(recs) > 0.5 * n
