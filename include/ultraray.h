@@ -89,8 +89,7 @@ typedef struct {
  * and leave about the local outward normal, the array's cylinder absorbs the
  * rays that reach it, and the receive angle of Eq. 13 is taken to the normal
  * of the element hit or sampled.  The array must span less than 180 degrees.
- * Convex arrays support neither the cone-restricted element choice nor the
- * adjoint. */
+ * Convex arrays are not supported by the adjoint. */
 typedef struct {
     int64_t n_elements;       /* 1 .. 65535                        */
     double pitch;             /* element pitch [m] (arc length on a convex array) */

@@ -109,18 +109,37 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
 // x_e = (e - (E-1)/2) pitch satisfies |x_e - q_x| <= rho, rho^2 = q_z^2
 // tan^2(alpha_c) - q_y^2 (Eq. 13 is zero for the others), the interval
 // widened by a relative 1e-9 so that rounding never drops an element.
+// Convex array: q at distance s > R from the centre of curvature, at angle
+// psi about it and elevation y.  The cosine of the angle between q - c(phi)
+// and the normal at phi grows with c = cos(psi - phi) (c >= R/s) and equals
+// cos(alpha_c) at c* = (R sin^2 alpha_c + cos alpha_c sqrt(s^2 + y^2 -
+// R^2 sin^2 alpha_c)) / s, so the elements that can hear q have
+// |phi_e - psi| <= acos(c*) (none if c* > 1), widened the same way.
 // Returns false when no element is left.
 __device__ __forceinline__ bool elem_range(const TraceParams &P, double qx, double qy, double qz, int &e_lo,
                                            int &n_e) {
     e_lo = 0;
     n_e = P.E;
     if (P.elem_choice != UR_ELEMENT_CONE) return true;
-    const double tc = P.tan_alpha_c;
-    const double rho2 = qz * qz * tc * tc - qy * qy;
-    if (!(qz > 0.0 && rho2 >= 0.0)) return false;
-    const double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
     const double half = 0.5 * (double)(P.E - 1);
-    double lo = ceil((qx - rho) / P.pitch + half), hi = floor((qx + rho) / P.pitch + half);
+    double lo, hi;
+    if (P.convex) {
+        const double R = P.radius, zc = qz + P.radius;
+        const double sq = sqrt(qx * qx + zc * zc), sa = P.sin_alpha_c, ca = P.cos_alpha_c;
+        if (!(sq > R)) return false;
+        const double cs = (R * sa * sa + ca * sqrt(sq * sq + qy * qy - R * R * sa * sa)) / sq;
+        if (!(cs <= 1.0)) return false;
+        const double dl = acos(cs) * (1.0 + 1e-9) + 1e-12, psi = atan2(qx, zc);
+        lo = ceil((psi - dl) / P.dphi + half);
+        hi = floor((psi + dl) / P.dphi + half);
+    } else {
+        const double tc = P.tan_alpha_c;
+        const double rho2 = qz * qz * tc * tc - qy * qy;
+        if (!(qz > 0.0 && rho2 >= 0.0)) return false;
+        const double rho = sqrt(rho2) * (1.0 + 1e-9) + 1e-12;
+        lo = ceil((qx - rho) / P.pitch + half);
+        hi = floor((qx + rho) / P.pitch + half);
+    }
     lo = lo < 0.0 ? 0.0 : lo;
     hi = hi > (double)(P.E - 1) ? (double)(P.E - 1) : hi;
     if (hi < lo) return false;

@@ -186,6 +186,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.elem_choice = a.element_choice == UR_ELEMENT_CONE && a.alpha_c < 0.5 * M_PI ? UR_ELEMENT_CONE
                                                                                    : UR_ELEMENT_UNIFORM;
     P.tan_alpha_c = std::tan(a.alpha_c);
+    P.sin_alpha_c = std::sin(a.alpha_c);
     P.sa = a.scheme == UR_SCHEME_SYNTHETIC;
     P.convex = pr.radius > 0.0;
     P.radius = pr.radius;
@@ -493,8 +494,6 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
             if (!(c->box[2] <= -2.0 * p->radius * h * h))
                 return c->fail(UR_ERR_SCENE, "the box top z = %g must lie at or above the convex array's ends (z = %g)",
                                c->box[2], -2.0 * p->radius * h * h);
-            if (a->element_choice != UR_ELEMENT_UNIFORM)
-                return c->fail(UR_ERR_UNSUPPORTED, "the cone-restricted element choice needs a linear array");
         } else if (c->box[2] != 0.0) {
             return c->fail(UR_ERR_SCENE, "with a linear array the box top z = box[2] must be the array plane z = 0");
         }

@@ -81,6 +81,7 @@ struct TraceParams {
     double pitch, elev, fs, t_max, max_path, alpha_m, alpha_c, r_s2, n_per_tx, half_ap, area_e;
     double cos_alpha_c;               // cosine of the receive cut-off angle
     double tan_alpha_c;               // its tangent (element choice restricted to the cone)
+    double sin_alpha_c;               // and its sine (the same on a convex array)
     int elem_choice;                  // UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE
     int sa;                           // synthetic aperture: transmit t = element t, counters of transmit 0
     int convex;                       // elements on an arc of radius `radius` (else a line on z = 0)

@@ -195,6 +195,19 @@ def test_convex_synthesis_parity(torch_gpu, oracle):
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["tiny_convex", "convex"])
+def test_convex_cone_element_choice(torch_gpu, oracle, name):
+    """Transducer sampling restricted to the elements whose cones can hold
+    the capture point (the convex form of the cone choice)."""
+    if name == "tiny_convex":
+        w = scenes.tiny_convex()
+    else:
+        w = scenes.convex(rays_per_element=6, n_scatterers=20_000)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=1))
+    st, ost = _compare(oracle, w, label=name + "-cone")
+    assert ost["nee_cast"] > 0
+
+
 def test_convex_synthetic_aperture_trace(torch_gpu, oracle):
     w = scenes.synthetic_aperture(scenes.tiny_convex(rays_per_element=64))
     _compare(oracle, w, label="tiny-convex-sa")
@@ -204,8 +217,6 @@ def test_convex_refusals(torch_gpu):
     from paper_2501_05828_amd import binding
     from paper_2501_05828_amd.sim import Simulator
     w = scenes.tiny_convex(rays_per_element=8)
-    with pytest.raises(binding.URError, match="UNSUPPORTED"):
-        Simulator(dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=1)))
     box = np.array(w.scene.box).copy()
     box[2] = -0.5 * MM
     with pytest.raises(binding.URError, match="SCENE"):
