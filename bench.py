@@ -143,7 +143,9 @@ def learned_experiment(args):
     from paper_2501_05828_amd.proposal import Proposal
     from paper_2501_05828_amd.sim import Simulator
 
-    w = scenes.learned()
+    # the bone phantom (linear array), or the paper's acquisition settings on
+    # the convex array with --workload convex
+    w = scenes.convex() if args.workload == "convex" else scenes.learned()
     if args.element_choice == "cone":
         w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=scenes.ELEMENT_CONE))
     acq0 = w.acq
@@ -178,7 +180,12 @@ def learned_experiment(args):
     prop = Proposal(sim)
     set_rays(1e7)
     t0 = time.perf_counter()
-    n_rec, offered = prop.record(args.record_traces, cost_aware=args.target == "cost")
+    n_rec, offered = prop.record(args.record_traces, cap=args.record_cap, cost_aware=args.target == "cost")
+    if offered > n_rec:
+        # the buffer keeps the first records written (the first launch
+        # ranges): later transmits would go untrained
+        print(f"[learned] warning: {offered} records offered, {n_rec} kept; raise --record-cap",
+              file=sys.stderr, flush=True)
     losses = prop.train(steps=args.train_steps, batch=1 << 16, lr=1e-3, log_every=500)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -223,7 +230,8 @@ def learned_experiment(args):
     gains = [{"rays_per_tx": u["rays_per_tx"],
               "efficiency_gain": (u["mse"] * u["gpu_s"]) / (l["mse"] * l["gpu_s"])}
              for u, l in zip(curves["uniform"], curves["learned"])]
-    out = {"metric": "channel MSE at equal GPU time, learned vs uniform", "workload": "bone phantom (learned)",
+    wl_name = "convex array, the paper's acquisition settings" if args.workload == "convex" else "bone phantom (learned)"
+    out = {"metric": "channel MSE at equal GPU time, learned vs uniform", "workload": wl_name,
            "target": args.target, "element_choice": args.element_choice, "reps": args.reps,
            "min_depth_mm": args.min_depth_mm, "efficiency_gain": gains,
            "reference_rays_per_tx": args.ref_rays_per_tx, "records": n_rec, "records_offered": offered,
@@ -245,6 +253,7 @@ def main():
     ap.add_argument("--ref-rays-per-tx", type=float, default=1e9)
     ap.add_argument("--ref-parts", type=int, default=10)
     ap.add_argument("--record-traces", type=int, default=8)
+    ap.add_argument("--record-cap", type=int, default=1 << 27, help="contribution records kept (8 B each)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--target", choices=["abs", "cost"], default="cost",
                     help="proposal target per cell: sum |c|, or sqrt(sum c^2 / path cost)")
