@@ -446,6 +446,57 @@ int or_interface_rough(const double d[3], const double n[3], double z_front, dou
     return rough_step(d, n, z_front, z_back, alpha, y, xi1, xi2, out_d, R, &ff, wf);
 }
 
+/* The rough boundary's scattering toward a given direction o, as implied by
+ * the sampler of rough_step (R43).  wi = -d is the reversed incident
+ * direction and n the normal on its side, z1 (incident side) and z2 the
+ * impedances, eta = z1/z2 the refraction ratio of Eq. 9.  The microfacet
+ * normal that sends wi to o is h = wi + o when o lies on the incident side
+ * (reflection) and +-(eta wi + o) otherwise (refraction, Eq. 9 about h),
+ * normalised with n.h > 0.  The sampler draws h with density D(h) (n.h),
+ * reflects with the Fresnel probability R_h of Eq. 11 about h and maps h to o
+ * with |dh/do| = 1/(4 |o.h|) (reflection) or |o.h| / (eta wi.h + o.h)^2
+ * (refraction, Walter et al. 2007); so the direction density is
+ * p(o) = D (n.h) P J with P = R_h or 1 - R_h.  Its weight (rough_step)
+ * times p(o) is the returned f(wi, o) |n.o| = (wi.h) G1(wi) G1(o) D P J / (n.wi).
+ * Returns 0 (and *pdf = 0) for directions the sampler cannot produce. */
+double or_rough_fcos(const double wi[3], const double n[3], double z1, double z2, double alpha, const double o[3],
+                     double *pdf)
+{
+    *pdf = 0.0;
+    double cni = dot3(wi, n), cno = dot3(o, n), eta = z1 / z2, h[3];
+    if (!(cni > 0.0) || cno == 0.0) return 0.0;
+    int refl = cno > 0.0;
+    for (int k = 0; k < 3; ++k) h[k] = refl ? wi[k] + o[k] : eta * wi[k] + o[k];
+    double hl = sqrt(dot3(h, h));
+    if (!(hl > 0.0)) return 0.0;
+    double sg = dot3(h, n) < 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < 3; ++k) h[k] *= sg / hl;
+    double ci = dot3(wi, h), co = dot3(o, h), chn = dot3(h, n);
+    if (!(ci > 0.0) || !(chn > 0.0)) return 0.0;
+    if (refl ? !(co > 0.0) : !(co < 0.0)) return 0.0;
+    /* Fresnel reflectance about h (Eqs. 8, 11; total internal reflection: 1) */
+    double rad = 1.0 - eta * eta * (1.0 - ci * ci), Rh = 1.0;
+    if (rad >= 0.0) {
+        double ct = sqrt(rad), den = z1 * ci + z2 * ct;
+        if (den != 0.0) {
+            double A = (z1 * ci - z2 * ct) / den;
+            Rh = A * A;
+        }
+    }
+    double P = refl ? Rh : 1.0 - Rh;
+    double J;
+    if (refl) {
+        J = 1.0 / (4.0 * co);
+    } else {
+        double den = eta * ci + co;
+        if (den == 0.0) return 0.0;
+        J = -co / (den * den);
+    }
+    double D = or_ggx_d(alpha, chn);
+    *pdf = D * chn * P * J;
+    return ci * or_ggx_g1(alpha, cni) * or_ggx_g1(alpha, fabs(cno)) * D * P * J / cni;
+}
+
 /* Transmitted intensity fraction 1 - A_r^2 for a straight (unbent) crossing. */
 static double transmit_fraction(double z1, double z2, double cos_r)
 {
@@ -697,6 +748,74 @@ static void record(const octx *C, sink *K, int64_t kind, int64_t tx, int64_t e, 
     }
 }
 
+/* Every crossing of a straight secondary ray from q along vh over the open
+ * interval (EPS_T, dist - EPS_T), in any order: the product T of transmitted
+ * fractions (zero on total internal reflection) and the changes of
+ * attenuation and slowness it picks up (R6).  Returns the number of
+ * crossings. */
+static int64_t shadow_cast(const octx *C, const double q[3], const double vh[3], double dist, double *T_out,
+                           double *sa_out, double *sc_out)
+{
+    const or_scene *sc = C->s;
+    double T = 1.0, sum_a = 0.0, sum_c = 0.0;
+    int64_t n_cross = 0;
+    double lo = EPS_T, hi = dist - EPS_T;
+    for (int64_t pid = 0; pid < sc->n_tri + sc->n_sph + sc->n_pln; ++pid) {
+        double ts[2];
+        int nt = 0;
+        double ng[2][3];
+        int64_t mf, mb;
+        if (pid < sc->n_tri) {
+            double tt;
+            if (tri_isect(sc->tri + 9 * pid, q, vh, &tt) && tt > lo && tt < hi) {
+                ts[nt] = tt;
+                tri_normal(sc->tri + 9 * pid, ng[nt]);
+                ++nt;
+            }
+            mf = sc->tri_mat[2 * pid];
+            mb = sc->tri_mat[2 * pid + 1];
+        } else if (pid < sc->n_tri + sc->n_sph) {
+            int64_t j = pid - sc->n_tri;
+            const double *sp = sc->sph + 4 * j;
+            double t0, t1;
+            if (sph_roots(sp, q, vh, &t0, &t1)) {
+                double tr[2] = {t0, t1};
+                for (int r = 0; r < 2; ++r) {
+                    if (tr[r] > lo && tr[r] < hi) {
+                        ts[nt] = tr[r];
+                        for (int i = 0; i < 3; ++i) ng[nt][i] = (q[i] + tr[r] * vh[i] - sp[i]) / sp[3];
+                        ++nt;
+                    }
+                }
+            }
+            mf = sc->sph_mat[2 * j];
+            mb = sc->sph_mat[2 * j + 1];
+        } else {
+            int64_t p = pid - sc->n_tri - sc->n_sph;
+            double tt;
+            if (pln_isect(sc->pln + 4 * p, q, vh, &tt) && tt > lo && tt < hi) {
+                ts[nt] = tt;
+                for (int i = 0; i < 3; ++i) ng[nt][i] = sc->pln[4 * p + i];
+                ++nt;
+            }
+            mf = sc->pln_mat[2 * p];
+            mb = sc->pln_mat[2 * p + 1];
+        }
+        for (int c = 0; c < nt; ++c) {
+            double dn = dot3(vh, ng[c]);
+            int64_t before = dn < 0.0 ? mf : mb, after = dn < 0.0 ? mb : mf;
+            T *= transmit_fraction(sc->mat[3 * before], sc->mat[3 * after], fabs(dn));
+            ++n_cross;
+            sum_a += (C->ka[after] - C->ka[before]) * (dist - ts[c]);
+            sum_c += (C->inv_c[after] - C->inv_c[before]) * (dist - ts[c]);
+        }
+    }
+    *T_out = T;
+    *sa_out = sum_a;
+    *sc_out = sum_c;
+    return n_cross;
+}
+
 /* Element choice for transducer sampling (Sec. 2.3).  Uniform over all E
  * element centres, or, with element_choice = 1, uniform over the K elements
  * whose centre can lie inside the acceptance cone of q (Eq. 13 is zero for
@@ -786,58 +905,8 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
         return;
     }
     K->st.nee_cast++;
-    /* every crossing of the secondary ray, in any order */
-    double T = 1.0, sum_a = 0.0, sum_c = 0.0;
-    double lo = EPS_T, hi = dist - EPS_T;
-    for (int64_t pid = 0; pid < sc->n_tri + sc->n_sph + sc->n_pln; ++pid) {
-        double ts[2];
-        int nt = 0;
-        double ng[2][3];
-        int64_t mf, mb;
-        if (pid < sc->n_tri) {
-            double tt;
-            if (tri_isect(sc->tri + 9 * pid, q, vh, &tt) && tt > lo && tt < hi) {
-                ts[nt] = tt;
-                tri_normal(sc->tri + 9 * pid, ng[nt]);
-                ++nt;
-            }
-            mf = sc->tri_mat[2 * pid];
-            mb = sc->tri_mat[2 * pid + 1];
-        } else if (pid < sc->n_tri + sc->n_sph) {
-            int64_t j = pid - sc->n_tri;
-            const double *sp = sc->sph + 4 * j;
-            double t0, t1;
-            if (sph_roots(sp, q, vh, &t0, &t1)) {
-                double tr[2] = {t0, t1};
-                for (int r = 0; r < 2; ++r) {
-                    if (tr[r] > lo && tr[r] < hi) {
-                        ts[nt] = tr[r];
-                        for (int i = 0; i < 3; ++i) ng[nt][i] = (q[i] + tr[r] * vh[i] - sp[i]) / sp[3];
-                        ++nt;
-                    }
-                }
-            }
-            mf = sc->sph_mat[2 * j];
-            mb = sc->sph_mat[2 * j + 1];
-        } else {
-            int64_t p = pid - sc->n_tri - sc->n_sph;
-            double tt;
-            if (pln_isect(sc->pln + 4 * p, q, vh, &tt) && tt > lo && tt < hi) {
-                ts[nt] = tt;
-                for (int i = 0; i < 3; ++i) ng[nt][i] = sc->pln[4 * p + i];
-                ++nt;
-            }
-            mf = sc->pln_mat[2 * p];
-            mb = sc->pln_mat[2 * p + 1];
-        }
-        for (int c = 0; c < nt; ++c) {
-            double dn = dot3(vh, ng[c]);
-            int64_t before = dn < 0.0 ? mf : mb, after = dn < 0.0 ? mb : mf;
-            T *= transmit_fraction(sc->mat[3 * before], sc->mat[3 * after], fabs(dn));
-            sum_a += (C->ka[after] - C->ka[before]) * (dist - ts[c]);
-            sum_c += (C->inv_c[after] - C->inv_c[before]) * (dist - ts[c]);
-        }
-    }
+    double T, sum_a, sum_c;
+    shadow_cast(C, q, vh, dist, &T, &sum_a, &sum_c);
     if (T == 0.0) {
         K->st.nee_blocked++;
         return;
@@ -847,6 +916,66 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     double amp = sc->scat[4 * k + 3];
     double c = wq * amp * (double)n_e * C->area_e * cos_a * fdir / (4.0 * PI * dist * dist) * T * att;
     record(C, K, 1, tx, er, seg, k, tc, c, q, e, cell);
+}
+
+/* Transducer sampling at a rough boundary (R43): when a primary ray meets a
+ * rough boundary it first sends a secondary ray from the hit point x to the
+ * centre of an element drawn as for scatterers (purpose 4 of the counters),
+ * weighted by the boundary's scattering toward that direction,
+ * f(wi, o) |n.o| (or_rough_fcos), by the element's solid angle
+ * A cos(alpha) / r^2 and Eq. 13, by 1/p of the element choice, and, like the
+ * scatterers' secondary rays, by the transmitted fractions, attenuation and
+ * delays along the straight path (R6).  It starts in the medium on o's side.
+ * When the straight path crosses no boundary, the same arrival can also be
+ * found by the continuing primary ray as a direct hit: both are weighted by
+ * the balance heuristic, this one by p_nee / (p_nee + p(o)) with
+ * p_nee = r^2 / (K A cos(alpha)) the density, per solid angle, of drawing a
+ * point of the element's face. */
+static void surface_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg, int64_t id,
+                        const double x[3], const double d[3], const double n[3], int64_t m_in, int64_t m_out,
+                        double alpha, double w, double t, int64_t cell)
+{
+    const or_acq *a = C->a;
+    const or_scene *sc = C->s;
+    int64_t e_lo = 0, n_e = a->n_elements;
+    K->st.surface_events++;
+    if (!or_cone_elements(a, x, &e_lo, &n_e)) {
+        K->st.surface_zero++;
+        return;
+    }
+    uint32_t xr[4];
+    draw(C, ray, e, tx, seg, 4, 0, xr);
+    int64_t er = e_lo + (int64_t)(((uint64_t)xr[0] * (uint64_t)n_e) >> 32);
+    double v[3] = {C->xe[er] - x[0], 0.0 - x[1], C->ze[er] - x[2]};
+    double dist = sqrt(dot3(v, v));
+    double o[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
+    double cos_a = a->radius > 0.0 ? -(o[0] * C->sne[er] + o[2] * C->cne[er]) : -o[2];
+    double ca = cos_a > 1.0 ? 1.0 : (cos_a < -1.0 ? -1.0 : cos_a);
+    double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
+    double wi[3] = {-d[0], -d[1], -d[2]}, pdf;
+    double fc = fdir > 0.0 ? or_rough_fcos(wi, n, sc->mat[3 * m_in], sc->mat[3 * m_out], alpha, o, &pdf) : 0.0;
+    if (!(fc > 0.0)) {
+        K->st.surface_zero++;
+        return;
+    }
+    K->st.nee_cast++;
+    int64_t med = dot3(o, n) > 0.0 ? m_in : m_out;
+    double T, sum_a, sum_c;
+    int64_t nc = shadow_cast(C, x, o, dist, &T, &sum_a, &sum_c);
+    if (T == 0.0) {
+        K->st.nee_blocked++;
+        return;
+    }
+    double area = C->area_e * cos_a;
+    double mis = 1.0;
+    if (nc == 0) {
+        double p_nee = dist * dist / ((double)n_e * area);
+        mis = p_nee / (p_nee + pdf);
+    }
+    double att = exp(-(C->ka[med] * dist + sum_a));
+    double tc = t + dist * C->inv_c[med] + sum_c;
+    double c = w * fc * area / (dist * dist) * fdir * (double)n_e * mis * T * att;
+    record(C, K, 5, tx, er, seg, id, tc, c, x, e, cell);
 }
 
 /* All scatterers whose capture capsule the segment [0, t_seg) passes:
@@ -885,6 +1014,12 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
     double o[3] = {o_in[0], o_in[1], o_in[2]}, d[3] = {d_in[0], d_in[1], d_in[2]};
     double len = 0.0;
     int64_t last = -1;
+    /* the last interaction, if rough: the density of the direction the ray
+     * left it in and its element range, for the balance heuristic of a direct
+     * hit on the next segment (R43) */
+    int prev_rough = 0;
+    double prev_pdf = 0.0;
+    int64_t prev_lo = 0, prev_n = 0;
     K->st.rays++;
     for (int64_t b = 0; b <= a->max_bounces; ++b) {
         K->st.segments++;
@@ -923,8 +1058,13 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
                     ca = ca > 1.0 ? 1.0 : (ca < -1.0 ? -1.0 : ca);
                     double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
                     if (fdir > 0.0) {
+                        double mis = 1.0;
+                        if (prev_rough && er >= prev_lo && er < prev_lo + prev_n) {
+                            double p_nee = t_seg * t_seg / ((double)prev_n * C->area_e * ca);
+                            mis = prev_pdf / (prev_pdf + p_nee);
+                        }
                         K->st.direct_hits++;
-                        record(C, K, 0, tx, er, b, -1, t, w * fdir, o, e, cell);
+                        record(C, K, 0, tx, er, b, -1, t, w * fdir * mis, o, e, cell);
                     }
                 }
             }
@@ -936,8 +1076,13 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
                 ca = ca > 1.0 ? 1.0 : (ca < -1.0 ? -1.0 : ca);
                 double fdir = or_directivity(acos(ca), a->alpha_m, a->alpha_c);
                 if (fdir > 0.0) {
+                    double mis = 1.0;
+                    if (prev_rough && er >= prev_lo && er < prev_lo + prev_n) {
+                        double p_nee = t_seg * t_seg / ((double)prev_n * C->area_e * ca);
+                        mis = prev_pdf / (prev_pdf + p_nee);
+                    }
                     K->st.direct_hits++;
-                    record(C, K, 0, tx, er, b, -1, t, w * fdir, o, e, cell);
+                    record(C, K, 0, tx, er, b, -1, t, w * fdir * mis, o, e, cell);
                 }
             }
             K->st.term_box++;
@@ -974,6 +1119,11 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
         double alpha = 0.0;
         if (sc->rough) alpha = sc->rough[mf] > sc->rough[mb] ? sc->rough[mf] : sc->rough[mb];
         if (alpha > 0.0) {
+            /* transducer sampling first, then the boundary's own draw */
+            int fr = dot3(d, ng) < 0.0;
+            double nn[3] = {fr ? ng[0] : -ng[0], fr ? ng[1] : -ng[1], fr ? ng[2] : -ng[2]};
+            int64_t m_in = fr ? mf : mb, m_out = fr ? mb : mf;
+            if (!a->rough_direct_only) surface_nee(C, K, tx, e, ray, b, h.id, o, d, nn, m_in, m_out, alpha, w, t, cell);
             double wf;
             refl = rough_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], alpha, y, unif(x[1]), unif(x[2]), nd, &R,
                               &from_front, &wf);
@@ -983,8 +1133,13 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
                 return;
             }
             w *= wf;
+            double wi[3] = {-d[0], -d[1], -d[2]};
+            or_rough_fcos(wi, nn, sc->mat[3 * m_in], sc->mat[3 * m_out], alpha, nd, &prev_pdf);
+            prev_rough = !a->rough_direct_only;
+            if (!or_cone_elements(a, o, &prev_lo, &prev_n)) prev_n = 0;
         } else {
             refl = fresnel_step(d, ng, sc->mat[3 * mf], sc->mat[3 * mb], y, nd, &R, &from_front);
+            prev_rough = 0;
         }
         int64_t before = from_front ? mf : mb, after = from_front ? mb : mf;
         if (before != med) K->st.media_mismatch++;

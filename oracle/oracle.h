@@ -39,6 +39,8 @@ typedef struct {
     double radius;             /* 0: linear array on z = 0; > 0: convex array of this radius, centre of
                                 * curvature (0, 0, -radius), pitch = arc length; the box top must lie
                                 * at or above the array's ends */
+    int64_t rough_direct_only; /* 0: transducer sampling at rough boundaries, balanced with the direct hits
+                                * that follow them (R43); 1: direct hits only */
 } or_acq;
 
 typedef struct {
@@ -58,12 +60,13 @@ typedef struct {
 typedef struct {
     int64_t rays, segments, reflect, transmit, tir, scatter_events, nee_zero, nee_cast,
             nee_blocked, direct_hits, records, dropped, edge_band, term_box, term_bounce,
-            term_time, term_path, media_mismatch, term_rough;
+            term_time, term_path, media_mismatch, term_rough, surface_events, surface_zero;
 } or_stats;
 
 /* One entry of a path log (explicit-ray tracing). */
 typedef struct {
-    int64_t kind;   /* 0 direct-hit record, 1 scatter (NEE) record, 2 reflect, 3 transmit, 4 end */
+    int64_t kind;   /* 0 direct-hit record, 1 scatter (NEE) record, 2 reflect, 3 transmit, 4 end,
+                     * 5 rough-boundary (NEE) record */
     int64_t tx, elem, seg, id;  /* elem: receiving element for records; id: scatterer or primitive */
     double t, value, x, y, z;   /* t: arrival / event time; value: contribution or weight */
 } or_event;
@@ -108,6 +111,9 @@ void or_onb(const double n[3], double t[3], double b[3]);
 void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, double h[3]);
 double or_ggx_d(double alpha, double cos_h);
 double or_ggx_g1(double alpha, double cos_v);
+/* f(wi, o) |n.o| of a rough boundary and the sampler's density of o (R43). */
+double or_rough_fcos(const double wi[3], const double n[3], double z1, double z2, double alpha, const double o[3],
+                     double *pdf);
 double or_delay(const or_acq *a, int64_t tx, int64_t e);
 /* Elements a capture point can hear (cone-restricted choice); 0 if none. */
 int or_cone_elements(const or_acq *a, const double q[3], int64_t *e_lo, int64_t *n_e);

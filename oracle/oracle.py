@@ -36,7 +36,7 @@ class Acq(C.Structure):
                 ("alpha_m", C.c_double), ("alpha_c", C.c_double), ("seed", C.c_uint64),
                 ("angles", C.POINTER(C.c_double)), ("pdf", C.POINTER(C.c_float)),
                 ("cdf", C.POINTER(C.c_float)), ("element_choice", C.c_int64), ("scheme", C.c_int64),
-                ("radius", C.c_double)]
+                ("radius", C.c_double), ("rough_direct_only", C.c_int64)]
 
 
 class SceneS(C.Structure):
@@ -51,7 +51,7 @@ class SceneS(C.Structure):
 
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
-               "term_time", "term_path", "media_mismatch", "term_rough"]
+               "term_time", "term_path", "media_mismatch", "term_rough", "surface_events", "surface_zero"]
 
 
 class Stats(C.Structure):
@@ -72,7 +72,7 @@ class Ray(C.Structure):
                 ("tx", C.c_int64), ("elem", C.c_int64), ("ray", C.c_int64), ("medium", C.c_int64)]
 
 
-EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end"}
+EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end", 5: "surface"}
 
 _lib = None
 
@@ -120,6 +120,9 @@ def lib():
         L.or_crossings.restype = C.c_int64
         L.or_element_geometry.argtypes = [P(Acq), C.c_int64, P(C.c_double)]
         L.or_cone_elements.argtypes = [P(Acq), P(C.c_double), P(C.c_int64), P(C.c_int64)]
+        L.or_rough_fcos.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
+                                    P(C.c_double), P(C.c_double)]
+        L.or_rough_fcos.restype = C.c_double
         L.or_sector_points.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
                                        C.c_double, P(C.c_double)]
         L.or_scan_convert.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -173,7 +176,8 @@ def make_acq(acq, seed, keep, pdf=None, cdf=None):
             n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
             alpha_c=acq.alpha_c, seed=int(seed) & 0xFFFFFFFFFFFFFFFF, angles=_dp(ang),
             element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)),
-            radius=float(getattr(acq, "radius", 0.0)))
+            radius=float(getattr(acq, "radius", 0.0)),
+            rough_direct_only=int(getattr(acq, "rough_direct_only", 0)))
     if pdf is not None:
         s.pdf = _fp(keep.f32(pdf))
         s.cdf = _fp(keep.f32(cdf))
@@ -447,3 +451,13 @@ def cone_elements(acq, q):
     lo, n = C.c_int64(0), C.c_int64(0)
     ok = lib().or_cone_elements(C.byref(a), qq, C.byref(lo), C.byref(n))
     return (lo.value, n.value) if ok else None
+
+
+def rough_fcos(wi, n, z1, z2, alpha, o):
+    """(f(wi, o) |n.o|, density of o) of a rough boundary's sampler."""
+    a = (C.c_double * 3)(*map(float, wi))
+    b = (C.c_double * 3)(*map(float, n))
+    c = (C.c_double * 3)(*map(float, o))
+    pdf = C.c_double(0)
+    v = lib().or_rough_fcos(a, b, float(z1), float(z2), float(alpha), c, C.byref(pdf))
+    return v, pdf.value

@@ -74,6 +74,7 @@ class Acquisition:
     element_choice: int = 0      # transducer sampling: 0 uniform over all elements, 1 over those in the cone
     scheme: int = 0              # 0 steered plane waves; 1 synthetic aperture (transmit t = element t alone)
     radius: float = 0.0          # 0 linear array; > 0 convex array of this radius (pitch = arc length)
+    rough_direct_only: int = 0   # 1: no transducer sampling at rough boundaries (direct hits only)
 
     @property
     def n_tx(self) -> int:
