@@ -125,6 +125,10 @@ typedef struct {
                                * transmit t fires element t alone without delay (angles unused),
                                * its rays drawn as in transmit 0 with the weights of a full-array
                                * transmit; see ur_synthesize                                   */
+    int64_t rough_direct_only; /* 0: at every rough boundary a secondary ray goes to an element centre
+                               * drawn as for scatterers, weighted by the boundary's scattering toward
+                               * it (Sec. 2.3 transducer sampling at interaction points), balanced with
+                               * the direct hit that may follow (balance heuristic); 1: direct hits only */
 } ur_acq_desc;
 
 #define UR_ELEMENT_UNIFORM 0
@@ -156,12 +160,16 @@ typedef struct {
     uint64_t tri_nodes, tri_tests, scat_cells, scat_tests, shadow_nodes, shadow_tri_tests;
     uint64_t term_rough;      /* rays absorbed at a rough boundary (microfacet facing away, or new
                                * direction on the wrong side of the surface) */
+    uint64_t surface_events;  /* transducer-sampling draws at rough boundaries                     */
+    uint64_t surface_zero;    /* ... of them with zero weight (no element in the cone, or the drawn
+                               * element outside it, or a direction the boundary cannot scatter to) */
     double kernel_ms;         /* time of the whole trace stage between HIP events on the call's stream */
 } ur_trace_stats;
 
 /* One entry of an explicit-ray path log (ur_trace_rays). */
 typedef struct {
-    int64_t kind;             /* 0 direct-hit record, 1 scatterer record, 2 reflect, 3 transmit, 4 end */
+    int64_t kind;             /* 0 direct-hit record, 1 scatterer record, 2 reflect, 3 transmit, 4 end,
+                               * 5 rough-boundary record (transducer sampling at a rough boundary) */
     int64_t tx, elem, seg, id;
     double t, value, x, y, z;
 } ur_event;

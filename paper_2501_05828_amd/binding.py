@@ -42,7 +42,7 @@ class AcqDesc(C.Structure):
                 ("max_bounces", C.c_int64), ("binning", C.c_int64), ("f_s", C.c_double), ("c0", C.c_double),
                 ("n_cycles", C.c_double), ("r_s", C.c_double), ("max_path", C.c_double), ("alpha_m", C.c_double),
                 ("alpha_c", C.c_double), ("angles", P(C.c_double)), ("element_choice", C.c_int64),
-                ("scheme", C.c_int64)]
+                ("scheme", C.c_int64), ("rough_direct_only", C.c_int64)]
 
 
 def _grid_desc(grid, apod, dynamic_range_db):
@@ -58,7 +58,7 @@ class GridDesc(C.Structure):
 STAT_FIELDS = ["rays", "segments", "reflect", "transmit", "tir", "scatter_events", "nee_zero", "nee_cast",
                "nee_blocked", "direct_hits", "records", "dropped", "edge_band", "term_box", "term_bounce",
                "term_time", "term_path", "media_mismatch", "tri_nodes", "tri_tests", "scat_cells", "scat_tests",
-               "shadow_nodes", "shadow_tri_tests", "term_rough"]
+               "shadow_nodes", "shadow_tri_tests", "term_rough", "surface_events", "surface_zero"]
 
 
 class TraceStats(C.Structure):
@@ -85,7 +85,7 @@ class GradDesc(C.Structure):
                 ("value", C.c_void_p), ("frozen_choice", C.c_int32)]
 
 
-EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end"}
+EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end", 5: "surface"}
 
 # (name, restype, argtypes) for every entry point declared in include/ultraray.h
 _CTX = C.c_void_p
@@ -233,7 +233,8 @@ class Context:
                     max_bounces=acq.max_bounces, binning=acq.binning, f_s=acq.f_s, c0=acq.c0,
                     n_cycles=acq.n_cycles, r_s=acq.r_s, max_path=acq.max_path, alpha_m=acq.alpha_m,
                     alpha_c=acq.alpha_c, angles=ang.ctypes.data_as(P(C.c_double)),
-                    element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)))
+                    element_choice=int(getattr(acq, "element_choice", 0)), scheme=int(getattr(acq, "scheme", 0)),
+                    rough_direct_only=int(getattr(acq, "rough_direct_only", 0)))
         self.check(self.lib.ur_transmit_setup(self.h, C.byref(p), C.byref(a)), "ur_transmit_setup")
         self.acq = acq
 

@@ -32,7 +32,8 @@ struct Counters {
 enum {
     C_RAYS, C_SEGMENTS, C_REFLECT, C_TRANSMIT, C_TIR, C_SCAT_EVENTS, C_NEE_ZERO, C_NEE_CAST, C_NEE_BLOCKED,
     C_DIRECT, C_RECORDS, C_DROPPED, C_EDGE, C_TERM_BOX, C_TERM_BOUNCE, C_TERM_TIME, C_TERM_PATH, C_MISMATCH,
-    C_TRI_NODES, C_TRI_TESTS, C_SCAT_CELLS, C_SCAT_TESTS, C_SHADOW_NODES, C_SHADOW_TRI_TESTS, C_TERM_ROUGH
+    C_TRI_NODES, C_TRI_TESTS, C_SCAT_CELLS, C_SCAT_TESTS, C_SHADOW_NODES, C_SHADOW_TRI_TESTS, C_TERM_ROUGH,
+    C_SURF_EVENTS, C_SURF_ZERO
 };
 
 #define CNT(k)                  \
@@ -388,16 +389,18 @@ __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o
 // every crossing in (eps, dist - eps).  Returns false if blocked (T = 0).
 template <bool COUNT>
 __device__ __forceinline__ bool shadow(const TraceParams &P, const double *q, const double *vh, double dist,
-                                       double &T, double &sum_a, double &sum_c, Counters &cnt) {
+                                       double &T, double &sum_a, double &sum_c, int &n_cross, Counters &cnt) {
     T = 1.0;
     sum_a = 0.0;
     sum_c = 0.0;
+    n_cross = 0;
     const double lo = kEpsT, hi = dist - kEpsT;
     auto cross_at = [&](double t, const double *ng, int mf, int mb) {
         const double dn = dot3(vh, ng);
         const int before = dn < 0.0 ? mf : mb, after = dn < 0.0 ? mb : mf;
         const Material A = P.mat[before], Bm = P.mat[after];
         T *= transmit_fraction(A.Z, Bm.Z, fabs(dn));
+        ++n_cross;
         sum_a += (Bm.ka - A.ka) * (dist - t);
         sum_c += (Bm.inv_c - A.inv_c) * (dist - t);
     };
@@ -530,6 +533,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     c.ray = ray;
     c.cell = cell;
     c.ne = n_e;
+    c.mis = -1.0f;
     return true;
 }
 
@@ -550,14 +554,79 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
     if (fdir <= 0.0) return;   // exactly at the cut-off
     CNT(C_NEE_CAST);
     double T, sum_a, sum_c;
-    if (!shadow<COUNT>(P, c.q, vh, dist, T, sum_a, sum_c, cnt)) {
+    int n_cross;
+    if (!shadow<COUNT>(P, c.q, vh, dist, T, sum_a, sum_c, n_cross, cnt)) {
         CNT(C_NEE_BLOCKED);
         return;
     }
     const double att = atten(-(M.ka * dist + sum_a));
     const double tc = c.tq + dist * M.inv_c + sum_c;
-    const double val = c.wq * (double)c.ne * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
-    record<COUNT, LOG>(P, L, cnt, 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
+    double val = c.wq * (double)c.ne * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
+    // a rough boundary's secondary ray that crosses nothing shares its path
+    // with the direct hits: balance-heuristic weight
+    if (c.mis >= 0.0f && n_cross == 0) val *= (double)c.mis;
+    record<COUNT, LOG>(P, L, cnt, c.mis >= 0.0f ? 5 : 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
+}
+
+// Transducer sampling at a rough boundary (Sec. 2.3: at a boundary the
+// primary ray first sends a secondary ray, then the boundary draws its own
+// continuation).  The target is drawn as for scatterers (purpose 4 of the
+// counters); the entry carries the boundary's scattering toward it
+// (rough_fcos), times 4 pi so that nee_cast's isotropic 1/(4 pi) cancels,
+// starts in the medium on the target's side, and carries the balance
+// heuristic p_nee / (p_nee + p) with p_nee = r^2 / (K A cos(alpha)) the
+// density, per solid angle, of drawing a point of the element's face and p
+// the boundary sampler's density of the same direction.  n is the normal on
+// the incident side, m_in and m_out the materials on its two sides.
+template <bool COUNT, bool LOG, int MODE>
+__device__ void surface_nee(const TraceParams &P, const EventLog &L, Counters &cnt, int tx, int e, uint32_t ray,
+                            int cell, int seg, int id, const double *x, const double *d, const double *n, int m_in,
+                            int m_out, double alpha, double w, double t) {
+    CNT(C_SURF_EVENTS);
+    int e_lo, n_e;
+    if (!elem_range(P, x[0], x[1], x[2], e_lo, n_e)) {
+        CNT(C_SURF_ZERO);
+        return;
+    }
+    uint32_t xr[4];
+    draw(P, ray, e, tx, seg, 4, 0, xr);
+    const int er = e_lo + (int)(((uint64_t)xr[0] * (uint64_t)n_e) >> 32);
+    const double4 g = P.convex ? P.elem[er] : make_double4(P.xe[er], 0.0, 0.0, 1.0);
+    const double v[3] = {g.x - x[0], 0.0 - x[1], g.y - x[2]};
+    const double dist = sqrt(dot3(v, v));
+    const double od[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
+    const double cos_a = P.convex ? -(od[0] * g.z + od[2] * g.w) : -od[2];
+    const double fdir = directivity(acos(fmin(1.0, fmax(-1.0, cos_a))), P.alpha_m, P.alpha_c);
+    const double wi[3] = {-d[0], -d[1], -d[2]};
+    double pdf = 0.0;
+    const double fc = fdir > 0.0 ? rough_fcos(wi, n, P.mat[m_in].Z, P.mat[m_out].Z, alpha, od, pdf) : 0.0;
+    if (!(fc > 0.0)) {
+        CNT(C_SURF_ZERO);
+        return;
+    }
+    const double p_nee = dist * dist / ((double)n_e * P.area_e * cos_a);
+    NeeEntry c;
+    c.q[0] = x[0];
+    c.q[1] = x[1];
+    c.q[2] = x[2];
+    c.wq = w * fc * (4.0 * M_PI);
+    c.tq = t;
+    c.tx = tx;
+    c.er = er;
+    c.med = dot3(od, n) > 0.0 ? m_in : m_out;
+    c.seg = seg;
+    c.k = id;
+    c.e = e;
+    c.ray = ray;
+    c.cell = cell;
+    c.ne = n_e;
+    c.mis = (float)(p_nee / (p_nee + pdf));
+    if constexpr (LOG || MODE == kInlineNeeOnly) {
+        nee_cast<COUNT, LOG>(P, L, cnt, c);
+    } else {
+        const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
+        if ((int64_t)slot < P.nee_cap) P.nee[slot] = c;
+    }
 }
 
 // Captures on the segment [0, t_seg) from the scatterer grid.  Candidates are
@@ -626,6 +695,11 @@ struct RayState {
     int med, seg, tx, e;
     uint32_t ray;
     int cell;          // emission direction cell (32 x 32 grid), -1 for explicit rays
+    // after a rough boundary with transducer sampling: the sampler's density of
+    // the direction taken and the element range of its secondary ray (ne_prev
+    // = 0 otherwise), for the balance heuristic of a direct hit that follows
+    double pdf_prev;
+    int lo_prev, ne_prev;
 };
 
 // Appends the segment [0, t_seg) of R to the segment queue.  Called by the
@@ -717,6 +791,18 @@ __device__ __forceinline__ void push_segment(const TraceParams &P, const RayStat
 // on [0, t_seg) (inline, or queued for the scatter kernel when SPLIT), then
 // transport and the hit itself (see advance).  Returns false when the ray
 // has ended.
+// Balance-heuristic weight of a direct hit into element er at distance r
+// (the segment just traced) and receive cosine ca, when the segment started
+// at a rough boundary whose secondary ray could have drawn er: p / (p +
+// p_nee) with p the boundary sampler's density of the direction taken and
+// p_nee = r^2 / (K A ca).  1 otherwise.
+template <bool ROUGH>
+__device__ __forceinline__ double direct_mis(const TraceParams &P, const RayState &R, int er, double r, double ca) {
+    if (!ROUGH || R.ne_prev == 0 || er < R.lo_prev || er >= R.lo_prev + R.ne_prev) return 1.0;
+    const double p_nee = r * r / ((double)R.ne_prev * P.area_e * ca);
+    return R.pdf_prev / (R.pdf_prev + p_nee);
+}
+
 template <bool COUNT, bool LOG, int MODE, bool SPLIT, bool ROUGH = true, bool CONVEX = true>
 __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &L, Counters &cnt, RayState &R,
                                           const Hit &h, volatile unsigned long long *chunk, bool near_grid = true) {
@@ -766,7 +852,8 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
                     const double fdir = directivity(acos(ca), P.alpha_m, P.alpha_c);
                     if (MODE != kInlineNeeOnly && fdir > 0.0) {
                         CNT(C_DIRECT);
-                        record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t, R.w * fdir, o, R.e, R.cell);
+                        record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t,
+                                           R.w * fdir * direct_mis<ROUGH>(P, R, er, t_seg, ca), o, R.e, R.cell);
                     }
                 }
             }
@@ -778,7 +865,8 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
             const double fdir = directivity(acos(ca), P.alpha_m, P.alpha_c);
             if (MODE != kInlineNeeOnly && fdir > 0.0) {
                 CNT(C_DIRECT);
-                record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t, R.w * fdir, o, R.e, R.cell);
+                record<COUNT, LOG>(P, L, cnt, 0, R.tx, er, b, -1, R.t,
+                                   R.w * fdir * direct_mis<ROUGH>(P, R, er, t_seg, ca), o, R.e, R.cell);
             }
         }
         CNT(C_TERM_BOX);
@@ -833,6 +921,10 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
     const double alpha = ROUGH ? fmax(P.mat[mf].rough, P.mat[mb].rough) : 0.0;
     double mn[3] = {ng[0], ng[1], ng[2]};
     if (ROUGH && alpha > 0.0) {
+        // transducer sampling first, then the boundary's own draw
+        if (P.rough_nee)
+            surface_nee<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, R.cell, b, (int)h.id, o, d, ng, before, after,
+                                          alpha, R.w, R.t);
         ggx_sample(ng, alpha, u01(x[1]), u01(x[2]), mn);
         if (!(-dot3(d, mn) > 0.0)) {
             CNT(C_TERM_ROUGH);
@@ -878,6 +970,15 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
             return false;
         }
         R.w *= cos_r * ggx_g1(alpha, cn) * ggx_g1(alpha, fabs(co)) / (cn * dot3(mn, ng));
+        if (P.rough_nee) {
+            const double wi[3] = {-d[0], -d[1], -d[2]};
+            rough_fcos(wi, ng, z1, z2, alpha, nd, R.pdf_prev);
+            if (!elem_range(P, o[0], o[1], o[2], R.lo_prev, R.ne_prev)) R.ne_prev = 0;
+        } else {
+            R.ne_prev = 0;
+        }
+    } else {
+        R.ne_prev = 0;
     }
     if (before != R.med) CNT(C_MISMATCH);
     if (refl) {
@@ -983,6 +1084,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;
                         R.last = -1;
+                        R.ne_prev = 0;
                         R.med = P.top_medium;
                         R.seg = 0;
                         active = true;
@@ -1070,6 +1172,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.t = P.tau[(int64_t)R.tx * P.E + R.e];
                         R.len = 0.0;
                         R.last = -1;
+                        R.ne_prev = 0;
                         R.med = P.top_medium;
                         R.seg = 0;
                         active = true;
@@ -1283,6 +1386,7 @@ __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *
         R.t = r.t;
         R.len = 0.0;
         R.last = -1;
+        R.ne_prev = 0;
         R.med = (int)r.medium;
         R.seg = 0;
         R.tx = (int)r.tx;

@@ -183,6 +183,57 @@ __device__ __forceinline__ double ggx_g1(double alpha, double cv) {
     return 2.0 / (1.0 + sqrt(1.0 + alpha * alpha * tan2));
 }
 
+// A rough boundary's scattering toward direction o as implied by the
+// sampler of after_hit (transducer sampling at rough boundaries).  wi = -d,
+// n the normal on the incident side, z1 incident and z2 far impedance,
+// eta = z1 / z2.  The microfacet normal sending wi to o is wi + o when o is
+// on the incident side (reflection), else +-(eta wi + o) (refraction about
+// it, Eq. 9), normalised with n.h > 0.  The sampler draws h with density
+// D(h) (n.h) (Eq. 12), reflects with the Fresnel probability R_h of Eq. 11
+// about h and maps h to o with |dh/do| = 1 / (4 |o.h|) or
+// |o.h| / (eta wi.h + o.h)^2 (Walter et al. 2007).  pdf receives the
+// direction density D (n.h) P J (P = R_h or 1 - R_h); the result,
+// f |n.o| = (wi.h) G1(wi) G1(o) D P J / (n.wi), is the sampler's weight
+// times pdf.  Zero for directions the sampler cannot produce.
+__device__ __forceinline__ double rough_fcos(const double *wi, const double *n, double z1, double z2, double alpha,
+                                             const double *o, double &pdf) {
+    pdf = 0.0;
+    const double cni = dot3(wi, n), cno = dot3(o, n), eta = z1 / z2;
+    if (!(cni > 0.0) || cno == 0.0) return 0.0;
+    const bool refl = cno > 0.0;
+    double h[3];
+    for (int k = 0; k < 3; ++k) h[k] = refl ? wi[k] + o[k] : eta * wi[k] + o[k];
+    const double hl = sqrt(dot3(h, h));
+    if (!(hl > 0.0)) return 0.0;
+    const double sg = dot3(h, n) < 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < 3; ++k) h[k] = h[k] * sg / hl;
+    const double ci = dot3(wi, h), co = dot3(o, h), chn = dot3(h, n);
+    if (!(ci > 0.0) || !(chn > 0.0)) return 0.0;
+    if (refl ? !(co > 0.0) : !(co < 0.0)) return 0.0;
+    const double rad = 1.0 - eta * eta * (1.0 - ci * ci);
+    double Rh = 1.0;
+    if (rad >= 0.0) {
+        const double ct = sqrt(rad), den = z1 * ci + z2 * ct;
+        if (den != 0.0) {
+            const double A = (z1 * ci - z2 * ct) / den;
+            Rh = A * A;
+        }
+    }
+    const double Pl = refl ? Rh : 1.0 - Rh;
+    double J;
+    if (refl) {
+        J = 1.0 / (4.0 * co);
+    } else {
+        const double den = eta * ci + co;
+        if (den == 0.0) return 0.0;
+        J = -co / (den * den);
+    }
+    const double a2 = alpha * alpha, q = chn * chn * (a2 - 1.0) + 1.0;
+    const double D = a2 / (M_PI * q * q);
+    pdf = D * chn * Pl * J;
+    return ci * ggx_g1(alpha, cni) * ggx_g1(alpha, fabs(cno)) * D * Pl * J / cni;
+}
+
 // Unit geometric normal of triangle k, computed once on the host in FP64
 __device__ __forceinline__ void tri_normal(const TraceParams &P, int64_t k, double *n) {
     const double4 v = P.tri_n[k];

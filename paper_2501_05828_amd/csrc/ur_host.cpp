@@ -189,6 +189,7 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.sin_alpha_c = std::sin(a.alpha_c);
     P.sa = a.scheme == UR_SCHEME_SYNTHETIC;
     P.convex = pr.radius > 0.0;
+    P.rough_nee = a.rough_direct_only == 0;
     P.radius = pr.radius;
     P.dphi = P.convex ? pr.pitch / pr.radius : 0.0;
     P.half_arc = 0.5 * (double)pr.n_elements * P.dphi;
@@ -511,6 +512,8 @@ UR_API ur_status ur_transmit_setup(ur_context *c, const ur_probe_desc *p, const 
             return c->fail(UR_ERR_INVALID_ARG, "scheme must be UR_SCHEME_PLANE_WAVE or UR_SCHEME_SYNTHETIC");
         if (a->scheme == UR_SCHEME_SYNTHETIC && a->n_tx != p->n_elements)
             return c->fail(UR_ERR_INVALID_ARG, "the synthetic-aperture scheme needs n_tx = n_elements");
+        if (a->rough_direct_only != 0 && a->rough_direct_only != 1)
+            return c->fail(UR_ERR_INVALID_ARG, "rough_direct_only must be 0 or 1");
         if (a->element_choice != UR_ELEMENT_UNIFORM && a->element_choice != UR_ELEMENT_CONE)
             return c->fail(UR_ERR_INVALID_ARG, "element_choice must be UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE");
         if (!(a->alpha_m >= 0) || !(a->alpha_c >= a->alpha_m) || !(a->alpha_c <= M_PI))

@@ -16,7 +16,7 @@ constexpr int kMaxSph = 64;
 constexpr int kMaxPln = 64;
 constexpr int kCells = 1024;          // 32 x 32 emission-direction cells
 constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
-constexpr int kNumStats = 25;
+constexpr int kNumStats = 27;
 constexpr int kSegChunk = 256;   // segment-queue slots a wavefront reserves at a time
 constexpr int64_t kSplitRays = int64_t(1) << 25;   // most rays per launch range
 
@@ -47,14 +47,17 @@ constexpr uint32_t kSegUnused = 0xffffffffu;
 static_assert(sizeof(SegHot) == 64 && sizeof(SegCold) == 32, "segment entry layout");
 
 struct NeeEntry {
-    double q[3];       // capture point on the primary segment
-    double wq;         // primary weight at q times the scatterer amplitude
+    double q[3];       // capture point on the primary segment (or the rough boundary's hit point)
+    double wq;         // primary weight at q times the scatterer amplitude (rough boundary: times
+                       // its scattering toward the element, times 4 pi)
     double tq;         // arrival time at q
     int tx, er, med, seg;
-    int k, e;          // scatterer (original index) and emitting element
+    int k, e;          // scatterer (original index) or boundary id, and emitting element
     uint32_t ray;
     int cell;          // emission direction cell of the primary ray
-    int ne, pad;       // elements the target was drawn from (weight of the choice)
+    int ne;            // elements the target was drawn from (weight of the choice)
+    float mis;         // < 0: a scatterer's entry; else a rough boundary's, with its balance-heuristic
+                       // weight (applied when the straight path crosses no boundary)
 };
 
 // Recorded contribution for training the emission proposal:
@@ -85,6 +88,7 @@ struct TraceParams {
     int elem_choice;                  // UR_ELEMENT_UNIFORM or UR_ELEMENT_CONE
     int sa;                           // synthetic aperture: transmit t = element t, counters of transmit 0
     int convex;                       // elements on an arc of radius `radius` (else a line on z = 0)
+    int rough_nee;                    // transducer sampling at rough boundaries (with the balance heuristic)
     double radius, dphi, half_arc;    // convex: radius, angle per element (pitch / radius), E dphi / 2
     const double4 *elem;              // convex: [E] centre x, centre z, sin and cos of the normal's angle
     const double *xe;                 // [E]

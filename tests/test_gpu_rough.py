@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 TOL_CH = 1e-4
 EXACT = ["rays", "segments", "reflect", "transmit", "tir", "nee_cast", "nee_blocked", "direct_hits", "records",
-         "dropped", "edge_band", "term_box", "term_bounce", "term_time", "term_path", "media_mismatch", "term_rough"]
+         "dropped", "edge_band", "term_box", "term_bounce", "term_time", "term_path", "media_mismatch", "term_rough",
+         "surface_events", "surface_zero"]
 
 
 @pytest.fixture(scope="module")
@@ -55,6 +56,25 @@ def test_rough_tiny_channel_data(torch_gpu, oracle):
     w = _rough(scenes.tiny(), [0.0, 0.3, 0.5])
     st, ost = _compare(oracle, w, label="tiny-rough")
     assert ost["term_rough"] > 0 and ost["reflect"] > 0 and ost["records"] > 100
+    # transducer sampling at the rough boundaries (most of the records)
+    assert ost["surface_events"] > 1000 and ost["surface_events"] - ost["surface_zero"] > 100
+
+
+def test_rough_direct_hits_only(torch_gpu, oracle):
+    """Without transducer sampling at rough boundaries (direct hits only)."""
+    w = _rough(scenes.tiny(), [0.0, 0.3, 0.5])
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, rough_direct_only=1))
+    st, ost = _compare(oracle, w, label="tiny-rough-direct-only")
+    assert ost["surface_events"] == 0 and st["surface_events"] == 0
+
+
+def test_rough_convex_cone_choice(torch_gpu, oracle):
+    """Rough boundaries seen through the convex array with the cone-restricted
+    element choice for the rough boundaries' secondary rays too."""
+    w = _rough(scenes.tiny_convex(), [0.0, 0.4, 0.6])
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=1))
+    st, ost = _compare(oracle, w, label="tiny-convex-rough")
+    assert ost["surface_events"] > 1000
 
 
 def test_rough_very_rough_boundaries(torch_gpu, oracle):
