@@ -116,6 +116,7 @@ __device__ __forceinline__ bool tri_isect(const double *tr, const double *o, con
 // R^2 sin^2 alpha_c)) / s, so the elements that can hear q have
 // |phi_e - psi| <= acos(c*) (none if c* > 1), widened the same way.
 // Returns false when no element is left.
+template <bool CONVEX = true>
 __device__ __forceinline__ bool elem_range(const TraceParams &P, double qx, double qy, double qz, int &e_lo,
                                            int &n_e) {
     e_lo = 0;
@@ -123,7 +124,7 @@ __device__ __forceinline__ bool elem_range(const TraceParams &P, double qx, doub
     if (P.elem_choice != UR_ELEMENT_CONE) return true;
     const double half = 0.5 * (double)(P.E - 1);
     double lo, hi;
-    if (P.convex) {
+    if (CONVEX && P.convex) {
         const double R = P.radius, zc = qz + P.radius;
         const double sq = sqrt(qx * qx + zc * zc), sa = P.sin_alpha_c, ca = P.cos_alpha_c;
         if (!(sq > R)) return false;
