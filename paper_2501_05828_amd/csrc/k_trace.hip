@@ -583,6 +583,14 @@ __device__ void surface_nee(const TraceParams &P, const EventLog &L, Counters &c
                             int cell, int seg, int id, const double *x, const double *d, const double *n, int m_in,
                             int m_out, double alpha, double w, double t) {
     CNT(C_SURF_EVENTS);
+    // (a linear array hears x only if its nearest element centre in x does:
+    // the same conservative test as for scatterer captures, no draw needed)
+    const double cc = P.cos_alpha_c;
+    if (cc >= 0.0 && !P.convex &&
+        (x[2] < 0.0 || x[2] * x[2] < cc * cc * (x[1] * x[1] + x[2] * x[2]) * (1.0 - 1e-9))) {
+        CNT(C_SURF_ZERO);
+        return;
+    }
     int e_lo, n_e;
     if (!elem_range(P, x[0], x[1], x[2], e_lo, n_e)) {
         CNT(C_SURF_ZERO);
