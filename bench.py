@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex"])
+    ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex", "bone_rough", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=150000)
     ap.add_argument("--experiment", choices=["learned"], default=None,
@@ -361,7 +361,10 @@ def main():
                         f"{round(float(acq.angles[0]) * 57.29578)}..{round(float(acq.angles[-1]) * 57.29578)} deg, "
                         f"{acq.n_elements * acq.rays_per_element:.2e} rays/transmit, {acq.max_bounces} bounces, "
                         f"{len(w.scene.tri)} triangles, {len(w.scene.pln)} planes, {len(w.scene.sph)} spheres, "
-                        f"{len(w.scene.scat)} scatterers, {acq.n_samples} samples at {acq.f_s / 1e6:.0f} MHz, "
+                        f"{len(w.scene.scat)} scatterers, "
+                        + (f"GGX roughness {max(w.scene.rough):g} on the bone, " if w.scene.rough is not None
+                           and max(w.scene.rough) > 0 else "")
+                        + f"{acq.n_samples} samples at {acq.f_s / 1e6:.0f} MHz, "
                         + (f"DAS on a {grid.nx}x{grid.nz} sector grid, scan converted to "
                          f"{w.extra['cart_grid'].nx}x{w.extra['cart_grid'].nz}" if grid.sector
                          else f"DAS {grid.nx}x{grid.nz}"),

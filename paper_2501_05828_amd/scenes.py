@@ -368,8 +368,29 @@ def convex(scene_seed: int = 1, rays_per_element: int = 100_000, n_phi: int = 30
     return w
 
 
+def _rough_bone(w: Workload, name: str, alpha: float = 0.5) -> Workload:
+    rough = np.zeros(len(w.scene.materials))
+    rough[3] = alpha                        # the tube's bone material
+    out = dataclasses.replace(w, name=name, scene=dataclasses.replace(w.scene, rough=rough))
+    return out
+
+
+def bone_rough(scene_seed: int = 1, rays_per_element: int = 78125) -> Workload:
+    """The bone workload with the bone's GGX roughness 0.5, the value the
+    paper settles on for its vertebra (Sec. 4); the soft-tissue boundaries
+    stay smooth."""
+    return _rough_bone(bone(scene_seed, rays_per_element), "bone_rough")
+
+
+def paper(scene_seed: int = 1, rays_per_element: int = 100_000, n_scatterers: int = 200_000) -> Workload:
+    """The convex workload (the paper's acquisition settings) with the bone's
+    roughness 0.5 as well: the whole of the paper's simulation set-up on the
+    synthetic phantom."""
+    return _rough_bone(convex(scene_seed, rays_per_element, n_scatterers=n_scatterers), "paper")
+
+
 CONFIGS = {"tiny": tiny, "bone": bone, "batched": batched, "learned": learned, "large": large,
-           "tiny_convex": tiny_convex, "convex": convex}
+           "tiny_convex": tiny_convex, "convex": convex, "bone_rough": bone_rough, "paper": paper}
 
 
 def make(name: str, **kw) -> Workload:

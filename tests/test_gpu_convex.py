@@ -90,6 +90,15 @@ def test_convex_paper_settings_full_size_sampled(torch_gpu, oracle):
     assert st["rays"] == 25 * 128 * 5
 
 
+def test_paper_settings_with_rough_bone_full_size_sampled(torch_gpu, oracle):
+    """The paper's whole set-up (convex array, its acquisition settings and
+    the bone's roughness 0.5, with transducer sampling at the rough bone)
+    at full size, every 20000th ray of each (transmit, element) row."""
+    w = scenes.paper()
+    st, ost = _compare(oracle, w, stride=20000, label="paper-full-sampled")
+    assert ost["surface_events"] > 0
+
+
 def test_convex_explicit_rays_same_events(torch_gpu, oracle):
     """Rays from points of the arc in random directions: the same events,
     element by element, as the oracle."""
