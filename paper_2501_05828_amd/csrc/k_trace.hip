@@ -485,13 +485,15 @@ __device__ __forceinline__ bool nee_point(const TraceParams &P, Counters &cnt, c
 // The element draw and the receive directivity (Eq. 13) for a capture point
 // placed by nee_point.  Fills the candidate and returns true if the
 // directivity of the drawn element is non-zero.
-template <bool COUNT, bool CONVEX = true>
+// CONE_CONVEX = false: a variant without the convex array's cone-restricted
+// element range (linear arrays, or the uniform choice)
+template <bool COUNT, bool CONE_CONVEX = true>
 __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cnt, int tx, int e, uint32_t ray,
                                               int seg, int k, double amp, double w, double t, int med, double s,
                                               int cell, NeeEntry &c) {
     const double cc = P.cos_alpha_c;
     int e_lo, n_e;
-    if (!elem_range<CONVEX>(P, c.q[0], c.q[1], c.q[2], e_lo, n_e)) {
+    if (!elem_range<CONE_CONVEX>(P, c.q[0], c.q[1], c.q[2], e_lo, n_e)) {
         CNT(C_SCAT_EVENTS);
         CNT(C_NEE_ZERO);
         return false;
@@ -504,7 +506,7 @@ __device__ __forceinline__ bool nee_candidate(const TraceParams &P, Counters &cn
     // (n = +z on a linear array: -v.n = q_z)
     const double vy = c.q[1];
     double mvz, r2;
-    if (CONVEX && P.convex) {
+    if (P.convex) {
         const double4 g = P.elem[er];
         const double vx = g.x - c.q[0], vz = g.y - c.q[2];
         mvz = -(vx * g.z + vz * g.w);
@@ -1228,7 +1230,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // four items of its current cell (FP32 prefilter, then the exact FP64 test),
 // with the same cell intervals as the inline walk, so each capture is found
 // exactly once.  Candidates go to the transducer-sampling queue.
-template <bool COUNT, bool CONVEX>
+template <bool COUNT, bool CONE_CONVEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scatter(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
@@ -1337,7 +1339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 if (!nee_point<COUNT>(P, cnt, o, d, s, c)) continue;
                 // the capture-only part of the segment, read only here
                 const SegCold &C = P.segc[qslot];
-                if (!nee_candidate<COUNT, CONVEX>(P, cnt, (int)(txe >> 16), (int)(txe & 0xffffu), ray, C.seg, P.item_id[jj],
+                if (!nee_candidate<COUNT, CONE_CONVEX>(P, cnt, (int)(txe >> 16), (int)(txe & 0xffffu), ray, C.seg, P.item_id[jj],
                                           sk.w, C.w, C.t, C.med, s, C.cell, c))
                     continue;
                 const unsigned long long slot = atomicAdd(P.nee_count, 1ull);
@@ -1498,18 +1500,20 @@ int64_t ur_extend_max_waves() {
 hipError_t ur_launch_scatter(const ur::TraceParams &p, bool count, hipStream_t s) {
     unsigned blocks = 0;
     const int64_t needed = (p.seg_cap + 255) / 256;
-    // (CONVEX = false: a variant for linear arrays without the convex cone choice)
+    // (CONE_CONVEX = false: a variant without the convex array's cone-restricted
+    // element range, whose registers slow the walk by a sixth)
 #define UR_SCATTER(C, CV)                                                        \
     do {                                                                         \
         hipError_t e = resident_blocks(k_scatter<C, CV>, needed, blocks);        \
         if (e != hipSuccess) return e;                                           \
         hipLaunchKernelGGL((k_scatter<C, CV>), dim3(blocks), dim3(256), 0, s, p); \
     } while (0)
+    const bool cc = p.convex && p.elem_choice == UR_ELEMENT_CONE;
     if (count) {
-        if (p.convex) UR_SCATTER(true, true);
+        if (cc) UR_SCATTER(true, true);
         else UR_SCATTER(true, false);
     } else {
-        if (p.convex) UR_SCATTER(false, true);
+        if (cc) UR_SCATTER(false, true);
         else UR_SCATTER(false, false);
     }
 #undef UR_SCATTER
