@@ -88,8 +88,7 @@ typedef struct {
  * radius), facing (sin phi_e, 0, cos phi_e); rays start on the element's arc
  * and leave about the local outward normal, the array's cylinder absorbs the
  * rays that reach it, and the receive angle of Eq. 13 is taken to the normal
- * of the element hit or sampled.  The array must span less than 180 degrees.
- * Convex arrays are not supported by the adjoint. */
+ * of the element hit or sampled.  The array must span less than 180 degrees. */
 typedef struct {
     int64_t n_elements;       /* 1 .. 65535                        */
     double pitch;             /* element pitch [m] (arc length on a convex array) */

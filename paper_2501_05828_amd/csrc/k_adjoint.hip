@@ -269,6 +269,19 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                 face = fi;
             }
         }
+        if (P.convex) {
+            // the convex array's cylinder (face 6), by value as in the trace
+            const double R = P.radius, aa = dv[0] * dv[0] + dv[2] * dv[2];
+            const double bq = ov[0] * dv[0] + (ov[2] + R) * dv[2];
+            const double cq = ov[0] * ov[0] + ov[2] * (ov[2] + 2.0 * R), disc = bq * bq - aa * cq;
+            if (bq < 0.0 && aa != 0.0 && disc >= 0.0) {
+                const double tt = cq / (-bq + sqrt(disc));
+                if (tt > kEpsT && tt < tbest) {
+                    tbest = tt;
+                    face = 6;
+                }
+            }
+        }
         int64_t hid = P.id_box;
         int hloc = -1;
         if (P.n_tnodes > 0) {
@@ -327,7 +340,12 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         D th;
         D sc[3];
         double srad = 0.0;
-        if (hid == P.id_box) {
+        if (hid == P.id_box && face == 6) {
+            const D R = dd(P.radius);
+            const D aa = d[0] * d[0] + d[2] * d[2], bq = o[0] * d[0] + (o[2] + R) * d[2];
+            const D cq = o[0] * o[0] + o[2] * (o[2] + dd(2.0) * R);
+            th = cq / (-bq + dsqrt(bq * bq - aa * cq));
+        } else if (hid == P.id_box) {
             const int ax = face % 3;
             th = (dd(P.box[face]) - o[ax]) / d[ax];
         } else if (hid < P.id_sph0) {
@@ -377,10 +395,11 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                     uint32_t x[4];
                     draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
                     const int er = e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
-                    const D v[3] = {dd(P.xe[er]) - q[0], -q[1], -q[2]};
+                    const double4 g = P.convex ? P.elem[er] : make_double4(P.xe[er], 0.0, 0.0, 1.0);
+                    const D v[3] = {dd(g.x) - q[0], -q[1], dd(g.y) - q[2]};
                     const D dist = dsqrt(ddot(v, v));
                     const D vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
-                    const D cos_a = -vh[2];
+                    const D cos_a = P.convex ? -(vh[0] * dd(g.z) + vh[2] * dd(g.w)) : -vh[2];
                     const D al = dacos(cos_a);
                     D f;
                     if (al.v > P.alpha_c) continue;
@@ -416,6 +435,22 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         for (int i = 0; i < 3; ++i) o[i] = o[i] + tseg * d[i];
         if (clipped || t.v >= P.t_max) return;
         if (hid == P.id_box) {
+            if (P.convex) {
+                if (face == 6 && fabs(o[1].v) <= 0.5 * P.elev) {
+                    const double ph = atan2(o[0].v, o[2].v + P.radius);
+                    if (fabs(ph) <= P.half_arc) {
+                        int er = (int)floor(ph / P.dphi + 0.5 * (double)P.E);
+                        er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+                        const double4 g = P.elem[er];
+                        const D al = dacos(-(d[0] * dd(g.z) + d[2] * dd(g.w)));
+                        if (al.v <= P.alpha_c) {
+                            const D f = al.v <= P.alpha_m ? dd(1.0) : (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
+                            contribute(A, acc, tx, er, w * f, t, -1, 0.0, len_m, nullptr);
+                        }
+                    }
+                }
+                return;
+            }
             if (face == 2 && fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev) {
                 int er = (int)floor((o[0].v + P.half_ap) / P.pitch);
                 er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);

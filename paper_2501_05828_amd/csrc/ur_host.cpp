@@ -1081,7 +1081,6 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
         for (double r : c->rough)
             if (r > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint does not support rough boundaries");
-        if (c->probe.radius > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint supports linear arrays only");
         if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center && !grads->value)
             return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)

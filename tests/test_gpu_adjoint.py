@@ -245,6 +245,57 @@ def test_trace_adjoint_impedance_and_sphere(oracle, tiny_adj):
     assert checked >= nm + 1
 
 
+def test_trace_adjoint_convex_array(oracle, torch_gpu):
+    """The adjoint on a convex array (the array's cylinder as the exit face,
+    element normals in the receive angle): attenuation, impedance and
+    sphere-centre gradients against central differences of the oracle."""
+    torch = torch_gpu
+    w = scenes.convex_probe(_workload(), 20e-3)
+    g = _smooth_adjoint((w.acq.n_tx, w.acq.n_elements, w.acq.n_samples), 22)
+    s = _sim(w)
+    gt = torch.from_numpy(g).cuda()
+    nm = len(w.scene.materials)
+    al = torch.empty(nm, dtype=torch.float64, device="cuda")
+    Z = torch.empty(nm, dtype=torch.float64, device="cuda")
+    sc = torch.empty((len(w.scene.sph), 3), dtype=torch.float64, device="cuda")
+    s.ctx.ur_trace_adjoint(w.seed, gt, alpha=al, Z=Z, sph_center=sc, frozen_choice=True)
+    ga, gz, gs = al.cpu().numpy(), Z.cpu().numpy(), sc.cpu().numpy().ravel()
+    assert np.count_nonzero(ga) > 0
+    checked = 0
+    for m in range(nm):
+        def perturb(ww, h, m=m):
+            mat = ww.scene.materials.copy()
+            mat[m, 1] += h
+            return _with_scene(ww, materials=mat)
+        fd, h = _fd(oracle, w, g, perturb, 1e-4)
+        print(f"[adjoint] convex dJ/dalpha[{m}]: gpu={ga[m]:.9e} fd={fd} (h={h:g})", flush=True)
+        assert fd is not None
+        assert abs(ga[m] - fd) <= 1e-5 * np.max(np.abs(ga)) + 1e-6 * abs(fd)
+    for m in range(nm):
+        def perturb(ww, h, m=m):
+            mat = ww.scene.materials.copy()
+            mat[m, 0] += h
+            return _with_scene(ww, materials=mat)
+        fd, h = _fd(oracle, w, g, perturb, 1e-6)
+        print(f"[adjoint] convex dJ/dZ[{m}]: gpu={gz[m]:.9e} fd={fd} (h={h:g})", flush=True)
+        if fd is None:
+            continue
+        checked += 1
+        assert abs(gz[m] - fd) <= 1e-4 * max(np.max(np.abs(gz)), abs(fd))
+    for c in range(gs.size):
+        def perturb(ww, h, c=c):
+            sph = ww.scene.sph.copy()
+            sph[c // 3, c % 3] += h
+            return _with_scene(ww, sph=sph)
+        fd, h = _fd(oracle, w, g, perturb, 1e-9)
+        print(f"[adjoint] convex dJ/dcentre[{c}]: gpu={gs[c]:.9e} fd={fd} (h={h:g})", flush=True)
+        if fd is None:
+            continue
+        checked += 1
+        assert abs(gs[c] - fd) <= 1e-4 * max(np.max(np.abs(gs)), abs(fd))
+    assert checked >= nm + 1
+
+
 def test_choice_probability_term_is_unbiased(torch_gpu):
     """Scatterers above a single reflector and no sphere: the impedance of
     the reflector changes only the reflect-or-transmit probability of the

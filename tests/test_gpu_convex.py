@@ -234,10 +234,6 @@ def test_convex_refusals(torch_gpu):
     lin = scenes.tiny(rays_per_element=8)
     with pytest.raises(binding.URError, match="SCENE"):
         Simulator(dataclasses.replace(lin, scene=dataclasses.replace(lin.scene, box=box)))
-    s = Simulator(w)
-    g = torch_gpu_zeros((1, w.acq.n_elements, w.acq.n_samples))
-    with pytest.raises(binding.URError, match="UNSUPPORTED"):
-        s.ctx.ur_trace_adjoint(w.seed, g, value=torch_gpu_zeros((1,), f64=True))
 
 
 def torch_gpu_zeros(shape, f64=False):
