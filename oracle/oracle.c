@@ -447,7 +447,7 @@ int or_interface_rough(const double d[3], const double n[3], double z_front, dou
 }
 
 /* The rough boundary's scattering toward a given direction o, as implied by
- * the sampler of rough_step (R43).  wi = -d is the reversed incident
+ * the sampler of rough_step.  wi = -d is the reversed incident
  * direction and n the normal on its side, z1 (incident side) and z2 the
  * impedances, eta = z1/z2 the refraction ratio of Eq. 9.  The microfacet
  * normal that sends wi to o is h = wi + o when o lies on the incident side
@@ -918,7 +918,7 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     record(C, K, 1, tx, er, seg, k, tc, c, q, e, cell);
 }
 
-/* Transducer sampling at a rough boundary (R43): when a primary ray meets a
+/* Transducer sampling at a rough boundary: when a primary ray meets a
  * rough boundary it first sends a secondary ray from the hit point x to the
  * centre of an element drawn as for scatterers (purpose 4 of the counters),
  * weighted by the boundary's scattering toward that direction,
@@ -1016,7 +1016,7 @@ static void trace_path(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t r
     int64_t last = -1;
     /* the last interaction, if rough: the density of the direction the ray
      * left it in and its element range, for the balance heuristic of a direct
-     * hit on the next segment (R43) */
+     * hit on the next segment */
     int prev_rough = 0;
     double prev_pdf = 0.0;
     int64_t prev_lo = 0, prev_n = 0;

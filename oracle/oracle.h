@@ -40,7 +40,7 @@ typedef struct {
                                 * curvature (0, 0, -radius), pitch = arc length; the box top must lie
                                 * at or above the array's ends */
     int64_t rough_direct_only; /* 0: transducer sampling at rough boundaries, balanced with the direct hits
-                                * that follow them (R43); 1: direct hits only */
+                                * that follow them; 1: direct hits only */
 } or_acq;
 
 typedef struct {
@@ -111,7 +111,7 @@ void or_onb(const double n[3], double t[3], double b[3]);
 void or_ggx_sample(const double n[3], double alpha, double xi1, double xi2, double h[3]);
 double or_ggx_d(double alpha, double cos_h);
 double or_ggx_g1(double alpha, double cos_v);
-/* f(wi, o) |n.o| of a rough boundary and the sampler's density of o (R43). */
+/* f(wi, o) |n.o| of a rough boundary and the sampler's density of o. */
 double or_rough_fcos(const double wi[3], const double n[3], double z1, double z2, double alpha, const double o[3],
                      double *pdf);
 double or_delay(const or_acq *a, int64_t tx, int64_t e);

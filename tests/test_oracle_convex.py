@@ -244,8 +244,8 @@ def test_convex_das_focuses_point_echo(oracle):
 
 @pytest.mark.parametrize("radius", [0.0, 20 * MM, 50 * MM])
 def test_cone_elements_are_exactly_the_hearing_ones(oracle, radius):
-    """The cone-restricted element range (R40 for linear, its convex form of
-    R42) against brute force over every element centre: it holds every
+    """The cone-restricted element range (linear arrays, and its form for
+    convex arrays) against brute force over every element centre: it holds every
     element whose acceptance cone contains the point, and nothing else
     beyond elements at the cut-off to within 1e-7 rad."""
     ac = math.radians(6.0)
