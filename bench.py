@@ -240,6 +240,61 @@ def learned_experiment(args):
     print(json.dumps(out))
 
 
+def rough_nee_experiment(args):
+    """Channel-data MSE against GPU time on the bone phantom with the bone's
+    roughness 0.5, with and without transducer sampling at the rough
+    boundaries (direct hits only): reference = mean of traces with it,
+    --ref-rays-per-tx in total; MSE of Re(ch_rf) beyond --min-depth-mm;
+    time = device time of trace + pulse."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.bone_rough()
+    if args.element_choice == "cone":
+        w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, element_choice=scenes.ELEMENT_CONE))
+    acq0 = w.acq
+    E = acq0.n_elements
+    sim = Simulator(w)
+
+    def run(per_tx, direct_only, seed):
+        sim.set_acquisition(dataclasses.replace(acq0, rays_per_element=max(1, int(per_tx) // E),
+                                                rough_direct_only=direct_only))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sim.trace(seed=seed, pulse=True)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    n0 = int(np.ceil(2.0 * args.min_depth_mm * 1e-3 / acq0.c0 * acq0.f_s))
+    ref = torch.zeros_like(sim.ch_rf[..., n0:, 0], dtype=torch.float64)
+    for k in range(args.ref_parts):
+        run(args.ref_rays_per_tx / args.ref_parts, 0, 0xAB000000 + k)
+        ref += sim.ch_rf[..., n0:, 0].double()
+    ref /= args.ref_parts
+    curves = {"direct_only": [], "with_rough_sampling": []}
+    for mode, direct_only in (("direct_only", 1), ("with_rough_sampling", 0)):
+        for bi, per_tx in enumerate(float(b) for b in args.budgets.split(",")):
+            mse, tg = 0.0, 0.0
+            for r in range(args.reps):
+                tg += run(per_tx, direct_only, 0xCD000000 + 97 * bi + r + 50000 * direct_only)
+                mse += float(((sim.ch_rf[..., n0:, 0].double() - ref) ** 2).mean())
+            curves[mode].append({"rays_per_tx": per_tx, "mse": mse / args.reps, "gpu_s": tg / args.reps})
+            print(f"[rough-nee] {mode} {per_tx:.0e}/tx: mse {mse / args.reps:.4e} time {tg / args.reps:.4f} s",
+                  file=sys.stderr, flush=True)
+    gains = [{"rays_per_tx": a["rays_per_tx"], "efficiency_gain": (a["mse"] * a["gpu_s"]) / (b["mse"] * b["gpu_s"])}
+             for a, b in zip(curves["direct_only"], curves["with_rough_sampling"])]
+    print(json.dumps({"metric": "channel MSE at equal GPU time, rough-boundary transducer sampling vs direct hits only",
+                      "workload": "bone phantom, bone roughness 0.5", "element_choice": args.element_choice,
+                      "reps": args.reps, "min_depth_mm": args.min_depth_mm,
+                      "reference_rays_per_tx": args.ref_rays_per_tx, "efficiency_gain": gains, "curves": curves}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,8 +303,8 @@ def main():
     ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex", "bone_rough", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=150000)
-    ap.add_argument("--experiment", choices=["learned"], default=None,
-                    help="learned: channel MSE vs GPU time, learned vs uniform emission")
+    ap.add_argument("--experiment", choices=["learned", "rough-nee"], default=None,
+                    help="learned: channel MSE vs GPU time, learned vs uniform emission; rough-nee: with vs 'without transducer sampling at the rough bone")
     ap.add_argument("--ref-rays-per-tx", type=float, default=1e9)
     ap.add_argument("--ref-parts", type=int, default=10)
     ap.add_argument("--record-traces", type=int, default=8)
@@ -280,6 +335,9 @@ def main():
         sys.exit(2)
     if args.experiment == "learned":
         learned_experiment(args)
+        return
+    if args.experiment == "rough-nee":
+        rough_nee_experiment(args)
         return
     if args.copy_calibration:
         a = torch.ones(1 << 28, device="cuda")
