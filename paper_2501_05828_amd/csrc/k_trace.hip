@@ -580,7 +580,7 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
 // density, per solid angle, of drawing a point of the element's face and p
 // the boundary sampler's density of the same direction.  n is the normal on
 // the incident side, m_in and m_out the materials on its two sides.
-template <bool COUNT, bool LOG, int MODE>
+template <bool COUNT, bool LOG, int MODE, bool CONVEX = true>
 __device__ void surface_nee(const TraceParams &P, const EventLog &L, Counters &cnt, int tx, int e, uint32_t ray,
                             int cell, int seg, int id, const double *x, const double *d, const double *n, int m_in,
                             int m_out, double alpha, double w, double t) {
@@ -594,7 +594,7 @@ __device__ void surface_nee(const TraceParams &P, const EventLog &L, Counters &c
         return;
     }
     int e_lo, n_e;
-    if (!elem_range(P, x[0], x[1], x[2], e_lo, n_e)) {
+    if (!elem_range<CONVEX>(P, x[0], x[1], x[2], e_lo, n_e)) {
         CNT(C_SURF_ZERO);
         return;
     }
@@ -933,7 +933,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
     if (ROUGH && alpha > 0.0) {
         // transducer sampling first, then the boundary's own draw
         if (P.rough_nee)
-            surface_nee<COUNT, LOG, MODE>(P, L, cnt, R.tx, R.e, R.ray, R.cell, b, (int)h.id, o, d, ng, before, after,
+            surface_nee<COUNT, LOG, MODE, CONVEX>(P, L, cnt, R.tx, R.e, R.ray, R.cell, b, (int)h.id, o, d, ng, before, after,
                                           alpha, R.w, R.t);
         ggx_sample(ng, alpha, u01(x[1]), u01(x[2]), mn);
         if (!(-dot3(d, mn) > 0.0)) {
@@ -983,7 +983,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
         if (P.rough_nee) {
             const double wi[3] = {-d[0], -d[1], -d[2]};
             rough_fcos(wi, ng, z1, z2, alpha, nd, R.pdf_prev);
-            if (!elem_range(P, o[0], o[1], o[2], R.lo_prev, R.ne_prev)) R.ne_prev = 0;
+            if (!elem_range<CONVEX>(P, o[0], o[1], o[2], R.lo_prev, R.ne_prev)) R.ne_prev = 0;
         } else {
             R.ne_prev = 0;
         }
