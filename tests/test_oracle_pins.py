@@ -293,6 +293,117 @@ def test_attenuation_matched_impedance_slab(oracle):
     assert abs(end["t"] - (12 * MM / 1540 + 28 * MM / 1600)) < 1e-18
 
 
+def _tent(x, n_samples):
+    """The linear reconstruction filter by its definition: sample m is
+    centred at (m + 1/2)/fs and receives the fraction 1 - |t fs - (m + 1/2)|
+    (clipped at zero) of an arrival at t."""
+    m = np.arange(n_samples)
+    return np.maximum(0.0, 1.0 - np.abs(x - (m + 0.5)))
+
+
+@pytest.mark.parametrize("x", [0.2, 0.5, 0.8, 1.5, 1.8, 1000.5, 1000.8, 1001.499, 2046.5, 2046.8, 2047.3,
+                               2047.5, 2047.9])
+def test_linear_binning_tent_weights(oracle, x):
+    """LINEAR binning (the differentiable workload's reconstruction filter):
+    an explicit ray arriving head-on at element 32 at t = x / fs puts
+    (1 - f) w into sample n and f w into sample n + 1, with n + 1/2 + f = x
+    (the tent centred on each sample), including the first and the last
+    sample of the record; an arrival at or after S / fs records nothing."""
+    sc = homogeneous(alpha=0.0)
+    w = with_scene(sc, binning=scenes.LINEAR)
+    fs, S, c = w.acq.f_s, w.acq.n_samples, 1540.0
+    z0 = 5 * MM
+    t0 = x / fs - z0 / c
+    ev, st, hist = oracle.trace_rays(w, [dict(o=[0.15 * MM, 0, z0], d=[0, 0, -1], w=0.75, t=t0, ray=3)],
+                                     with_hist=True)
+    rec = [e for e in ev if e["kind"] == "direct"]
+    assert len(rec) == 1 and rec[0]["elem"] == 32 and rec[0]["value"] == 0.75
+    assert rec[0]["t"] == pytest.approx(x / fs, rel=1e-14)
+    expected = 0.75 * _tent(rec[0]["t"] * fs, S)
+    assert np.allclose(hist[0, 32], expected, rtol=0, atol=1e-12)
+    assert np.count_nonzero(hist[0, :32]) == 0 and np.count_nonzero(hist[0, 33:]) == 0
+    # the two weights: (1 - f) into n, f into n + 1
+    n = int(math.floor(x - 0.5))
+    f = (x - 0.5) - n
+    if 0 <= n < S:
+        assert hist[0, 32, n] == pytest.approx(0.75 * (1 - f), abs=1e-12)
+    if 0 <= n + 1 < S:
+        assert hist[0, 32, n + 1] == pytest.approx(0.75 * f, abs=1e-12)
+    assert hist.sum() == pytest.approx(0.75 * ((1 - f) * (0 <= n < S) + f * (0 <= n + 1 < S)), abs=1e-12)
+    # NEAREST binning of the same arrival: all of it in floor(x)
+    w0 = with_scene(sc)
+    _, _, h0 = oracle.trace_rays(w0, [dict(o=[0.15 * MM, 0, z0], d=[0, 0, -1], w=0.75, t=t0, ray=3)],
+                                 with_hist=True)
+    assert h0[0, 32, int(math.floor(x))] == 0.75 and np.count_nonzero(h0) == 1
+
+
+def test_arrival_at_the_end_of_the_record_is_dropped(oracle):
+    sc = homogeneous(alpha=0.0)
+    for binning in (scenes.NEAREST, scenes.LINEAR):
+        w = with_scene(sc, binning=binning)
+        x = w.acq.n_samples + 0.25
+        t0 = x / w.acq.f_s - 5 * MM / 1540.0
+        ev, st, hist = oracle.trace_rays(w, [dict(o=[0.15 * MM, 0, 5 * MM], d=[0, 0, -1], t=t0, ray=3)],
+                                         with_hist=True)
+        # the time window ends the ray before its direct hit
+        assert st["term_time"] == 1 and st["direct_hits"] == 0 and st["records"] == 0
+        assert np.count_nonzero(hist) == 0
+        # just inside the window: recorded
+        t1 = (w.acq.n_samples - 0.25) / w.acq.f_s - 5 * MM / 1540.0
+        _, st1, h1 = oracle.trace_rays(w, [dict(o=[0.15 * MM, 0, 5 * MM], d=[0, 0, -1], t=t1, ray=3)],
+                                       with_hist=True)
+        assert st1["direct_hits"] == 1 and st1["records"] == 1 and h1[0, 32, -1] > 0
+
+
+def test_path_length_limit_clips_the_last_segment(oracle):
+    """A ray whose path would exceed max_path (0.2 m, Sec. 4) ends exactly
+    at 0.2 m of path: after a matched boundary at 20 mm (never reflects) it
+    stops at depth 0.2 m with time 0.02/c0 + 0.18/c1 and weight
+    exp(-k0 0.02 - k1 0.18), k_m = alpha_m ln10/20 f_c in Np per metre."""
+    mats = [[1.5, 0.5, 1540.0], [1.5, 2.0, 1500.0]]
+    sc = homogeneous(planes=[[0, 0, 1, 20 * MM]], pln_mat=[[1, 0]], mats=mats, box=(-20, -20, 0, 20, 20, 300))
+    w = with_scene(sc, n_samples=8192, max_path=0.2)
+    ev, st, _ = oracle.trace_rays(w, [dict(o=[0, 0, 0], d=[0, 0, 1], w=1.0, ray=9)])
+    assert [e["kind"] for e in ev] == ["transmit", "end"]
+    end = ev[-1]
+    assert end["id"] == -3 and end["seg"] == 1
+    assert end["pos"][2] == pytest.approx(0.2, abs=1e-15) and end["pos"][0] == 0.0
+    k = lambda a: a * math.log(10) / 20 * 5.0 * 100.0       # dB/(cm MHz) at 5 MHz -> Np/m
+    assert end["value"] == pytest.approx(math.exp(-k(0.5) * 0.02 - k(2.0) * 0.18), rel=1e-13)
+    assert end["t"] == pytest.approx(0.02 / 1540.0 + 0.18 / 1500.0, rel=1e-14)
+    assert st["term_path"] == 1 and st["term_box"] == 0 and st["segments"] == 2
+    # a shorter limit clips the first segment instead
+    w2 = with_scene(sc, n_samples=8192, max_path=0.015)
+    ev2, st2, _ = oracle.trace_rays(w2, [dict(o=[0, 0, 0], d=[0, 0, 1], w=1.0, ray=9)])
+    assert [e["kind"] for e in ev2] == ["end"] and ev2[0]["pos"][2] == pytest.approx(0.015, abs=1e-15)
+    assert st2["term_path"] == 1 and st2["segments"] == 1
+
+
+@pytest.mark.parametrize("bounces", [2, 3])
+def test_bounce_limit_ends_the_ray_at_the_next_interface(oracle, bounces):
+    """At most B interface interactions (Sec. 2.3's interaction limit, 10 in
+    Sec. 4): three matched planes at 10, 20, 30 mm.  With B = 2 the ray is
+    transmitted twice and ends on reaching the third plane (two interactions
+    logged, term_bounce); with B = 3 it crosses all three and leaves through
+    the box."""
+    mats = [[1.5, 0.5, 1540.0], [1.5, 0.5, 1500.0], [1.5, 0.5, 1560.0], [1.5, 0.5, 1520.0]]
+    planes = [[0, 0, 1, 10 * MM], [0, 0, 1, 20 * MM], [0, 0, 1, 30 * MM]]
+    sc = homogeneous(planes=planes, pln_mat=[[1, 0], [2, 1], [3, 2]], mats=mats)
+    w = with_scene(sc, max_bounces=bounces)
+    ev, st, _ = oracle.trace_rays(w, [dict(o=[0, 0, 0], d=[0, 0, 1], w=1.0, ray=4)])
+    kinds = [e["kind"] for e in ev]
+    if bounces == 2:
+        assert kinds == ["transmit", "transmit", "end"]
+        assert ev[-1]["id"] == -4 and ev[-1]["seg"] == 2
+        assert ev[-1]["pos"][2] == pytest.approx(30 * MM, abs=1e-15)
+        assert ev[-1]["t"] == pytest.approx(10 * MM / 1540 + 10 * MM / 1500 + 10 * MM / 1560, rel=1e-14)
+        assert st["term_bounce"] == 1 and st["transmit"] == 2 and st["segments"] == 3
+    else:
+        assert kinds == ["transmit", "transmit", "transmit", "end"]
+        assert ev[-1]["id"] == -1 and ev[-1]["pos"][2] == pytest.approx(40 * MM, abs=1e-15)
+        assert st["term_bounce"] == 0 and st["term_box"] == 1 and st["segments"] == 4
+
+
 def test_oblique_refraction_follows_snell_through_trace(oracle):
     mats = [[1.5, 0.0, 1540.0], [1.8, 0.0, 1540.0]]
     sc = homogeneous(planes=[[0, 0, 1, 10 * MM]], pln_mat=[[1, 0]], mats=mats)
