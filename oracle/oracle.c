@@ -926,11 +926,16 @@ static void scatter_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
  * A cos(alpha) / r^2 and Eq. 13, by 1/p of the element choice, and, like the
  * scatterers' secondary rays, by the transmitted fractions, attenuation and
  * delays along the straight path (R6).  It starts in the medium on o's side.
- * When the straight path crosses no boundary, the same arrival can also be
- * found by the continuing primary ray as a direct hit: both are weighted by
- * the balance heuristic, this one by p_nee / (p_nee + p(o)) with
+ * The same arrival can also be found by the continuing primary ray as a
+ * direct hit on the next segment: both are weighted by the balance
+ * heuristic, this one by p_nee / (p_nee + p(o)) with
  * p_nee = r^2 / (K A cos(alpha)) the density, per solid angle, of drawing a
- * point of the element's face. */
+ * point of the element's face.  A secondary ray whose straight path crosses
+ * a boundary records nothing (counted as blocked): the primary ray would
+ * interact at that boundary, so its only route to the element through it is
+ * the primary ray's own continuation, which the direct hits already count
+ * with full weight; a straight, transmission-weighted connection would count
+ * that echo a second time. */
 static void surface_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t ray, int64_t seg, int64_t id,
                         const double x[3], const double d[3], const double n[3], int64_t m_in, int64_t m_out,
                         double alpha, double w, double t, int64_t cell)
@@ -962,16 +967,13 @@ static void surface_nee(const octx *C, sink *K, int64_t tx, int64_t e, uint32_t 
     int64_t med = dot3(o, n) > 0.0 ? m_in : m_out;
     double T, sum_a, sum_c;
     int64_t nc = shadow_cast(C, x, o, dist, &T, &sum_a, &sum_c);
-    if (T == 0.0) {
+    if (nc > 0 || T == 0.0) {
         K->st.nee_blocked++;
         return;
     }
     double area = C->area_e * cos_a;
-    double mis = 1.0;
-    if (nc == 0) {
-        double p_nee = dist * dist / ((double)n_e * area);
-        mis = p_nee / (p_nee + pdf);
-    }
+    double p_nee = dist * dist / ((double)n_e * area);
+    double mis = p_nee / (p_nee + pdf);
     double att = exp(-(C->ka[med] * dist + sum_a));
     double tc = t + dist * C->inv_c[med] + sum_c;
     double c = w * fc * area / (dist * dist) * fdir * (double)n_e * mis * T * att;

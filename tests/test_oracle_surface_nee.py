@@ -12,7 +12,11 @@ carry the boundary's scattering toward that direction).
 - Transducer sampling balanced with the direct hits leaves the expected
   channel data unchanged: the per-element received signal with it equals
   the direct-hits-only signal within the statistical error, while most of
-  the signal now comes from the secondary rays.
+  the signal now comes from the secondary rays.  This holds too when a
+  smooth boundary (matched or mismatched in impedance) lies between the
+  rough boundary and the array, where the primary ray reaches the array only
+  through that boundary and a straight secondary ray would count the same
+  echo a second time.
 """
 import dataclasses
 import math
@@ -95,19 +99,35 @@ def _rough_floor_workload(alpha, direct_only, rays_per_element=512):
     return dataclasses.replace(w, scene=sc, acq=acq)
 
 
-@pytest.mark.parametrize("alpha", [0.3, 0.8])
-def test_transducer_sampling_at_rough_boundaries_is_unbiased(oracle, alpha):
-    """Per-element received signal (summed over time) with transducer
-    sampling + balance heuristic equals the direct-hits-only signal within
-    5 standard errors of their difference (16 independent ray subsets each)."""
-    parts = 16
+def _rough_floor_under_plane_workload(alpha, z_mid, direct_only, rays_per_element=512):
+    """Water, then a smooth plane at 10 mm into a layer of impedance z_mid
+    (1.5: matched, no bending and no loss; 1.6: mismatched), then the rough
+    reflector plane at 20 mm (Z 7.8).  Every echo of the rough floor crosses
+    the smooth plane on its way back, and up to three interactions are
+    followed (down through the plane, the floor, up through the plane)."""
+    mats = np.array([[1.5, 0.0, 1540.0], [z_mid, 0.0, 1540.0], [7.8, 0.0, 1540.0]])
+    pln = np.array([[0.0, 0.0, 1.0, 10 * MM], [0.0, 0.0, 1.0, 20 * MM]])
+    sc = scenes.Scene(mats, np.array([-20, -20, 0, 20, 20, 40.0]) * MM, 0, np.zeros((0, 9)),
+                      np.zeros((0, 2), np.int32), np.zeros((0, 4)), np.zeros((0, 2), np.int32), pln,
+                      np.array([[1, 0], [2, 1]], np.int32), np.zeros((0, 4)), rough=np.array([0.0, 0.0, alpha]))
+    w = scenes.tiny(rays_per_element=rays_per_element)
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(15.0), alpha_c=math.radians(45.0),
+                              rough_direct_only=direct_only, max_bounces=3)
+    return dataclasses.replace(w, scene=sc, acq=acq)
+
+
+def _signal_by_element(oracle, make, parts=16):
+    """Per-element received signal (summed over time) of `parts`
+    independent replicas (different Philox keys) of both estimators."""
     sums = {}
     for direct_only in (1, 0):
-        w = _rough_floor_workload(alpha, direct_only)
-        # independent replicas: different Philox keys
+        w = make(direct_only)
         ps = [oracle.trace(w, seed=0x5EED0001 + 7919 * k)[0].sum(2)[0] for k in range(parts)]
         sums[direct_only] = np.array(ps)
-    a, b = sums[1], sums[0]                       # [parts, E]
+    return sums[1], sums[0]                       # [parts, E]
+
+
+def _assert_same_expectation(a, b, parts=16):
     ma, mb = a.mean(0), b.mean(0)
     se = np.sqrt(a.var(0, ddof=1) / parts + b.var(0, ddof=1) / parts)
     tot_a, tot_b = a.sum(1), b.sum(1)
@@ -115,8 +135,35 @@ def test_transducer_sampling_at_rough_boundaries_is_unbiased(oracle, alpha):
     assert abs(tot_a.mean() - tot_b.mean()) < 5 * se_tot, (tot_a.mean(), tot_b.mean(), se_tot)
     bad = np.abs(ma - mb) > 5 * se + 1e-30
     assert bad.mean() < 0.05, (np.nonzero(bad)[0], ma[bad], mb[bad], se[bad])
+    return tot_a, tot_b
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.8])
+def test_transducer_sampling_at_rough_boundaries_is_unbiased(oracle, alpha):
+    """Per-element received signal (summed over time) with transducer
+    sampling + balance heuristic equals the direct-hits-only signal within
+    5 standard errors of their difference (16 independent ray subsets each)."""
+    a, b = _signal_by_element(oracle, lambda direct_only: _rough_floor_workload(alpha, direct_only))
+    tot_a, tot_b = _assert_same_expectation(a, b)
     # the secondary rays lower the variance of the total
     assert tot_b.std() < tot_a.std()
+
+
+@pytest.mark.parametrize("z_mid", [1.5, 1.6])
+def test_transducer_sampling_under_a_smooth_boundary_is_unbiased(oracle, z_mid):
+    """A smooth plane between the rough floor and the array: the balanced
+    estimator still equals the direct-hits-only one (a secondary ray that
+    crosses a boundary records nothing, so the echo is not counted twice),
+    and the totals agree within 5 standard errors, where double counting
+    would give about twice the signal."""
+    a, b = _signal_by_element(oracle, lambda direct_only: _rough_floor_under_plane_workload(0.5, z_mid,
+                                                                                            direct_only))
+    tot_a, tot_b = _assert_same_expectation(a, b)
+    assert tot_a.mean() > 0 and abs(tot_b.mean() / tot_a.mean() - 1.0) < 0.2
+    w = _rough_floor_under_plane_workload(0.5, z_mid, 0)
+    _, st = oracle.trace(w)
+    # every rough-boundary secondary ray that is cast crosses the plane
+    assert st["nee_cast"] > 1000 and st["nee_blocked"] == st["nee_cast"]
 
 
 def test_surface_records_in_the_event_log(oracle):
