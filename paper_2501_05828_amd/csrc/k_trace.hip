@@ -561,12 +561,19 @@ __device__ __forceinline__ void nee_cast(const TraceParams &P, const EventLog &L
         CNT(C_NEE_BLOCKED);
         return;
     }
+    // a rough boundary's secondary ray shares its path with the direct hits
+    // of the primary ray's next segment (balance-heuristic weight); if its
+    // straight path crosses a boundary, the primary ray would interact there
+    // instead, and the echo through that boundary reaches the element only as
+    // the primary ray's own continuation, already counted: it records nothing
+    if (c.mis >= 0.0f && n_cross > 0) {
+        CNT(C_NEE_BLOCKED);
+        return;
+    }
     const double att = atten(-(M.ka * dist + sum_a));
     const double tc = c.tq + dist * M.inv_c + sum_c;
     double val = c.wq * (double)c.ne * P.area_e * cos_a * fdir / (4.0 * M_PI * dist * dist) * T * att;
-    // a rough boundary's secondary ray that crosses nothing shares its path
-    // with the direct hits: balance-heuristic weight
-    if (c.mis >= 0.0f && n_cross == 0) val *= (double)c.mis;
+    if (c.mis >= 0.0f) val *= (double)c.mis;
     record<COUNT, LOG>(P, L, cnt, c.mis >= 0.0f ? 5 : 1, c.tx, c.er, c.seg, c.k, tc, val, c.q, c.e, c.cell);
 }
 

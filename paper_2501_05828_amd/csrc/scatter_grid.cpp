@@ -50,16 +50,18 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
     }
     g.info.h = h;
     g.info.inv_h = 1.0 / h;
-    // Every cone of a linear array lies in |y| <= z tan(alpha_c): its axis is
-    // +z through a point with y = 0.  The 10 um margin dwarfs the rounding of
-    // a capture point and of the clip itself.  (A convex array's cones have
-    // tilted axes: no wedge; the grid box of its kept scatterers bounds the
-    // walks instead.)
+    // Every cone of a linear array lies in the wedge |y| <= z tan(alpha_c):
+    // its axis is +z through a point with y = 0.  A convex array's cones have
+    // tilted axes in the xz-plane, so each lies in the slab
+    // |y| <= tan(alpha_c) (s - R), s the distance of the point from the centre
+    // of curvature: |y| <= |q - c| sin(alpha) <= tan(alpha) (q - c).n
+    // <= tan(alpha_c) (s - R), with (q - c).n = (x, z + R).n - R <= s - R.
+    // The walks are clipped to the wedge (wy_b) or the slab (cv_r, cv_tan);
+    // the 10 um margin wy_a dwarfs the rounding of a capture point and of the
+    // clip itself.
     g.info.wy_a = 1e-5;
     g.info.wy_b = rx && rx->radius == 0.0 && rx->alpha_c < 80.0 * M_PI / 180.0
                       ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : -1.0;
-    // (for a convex array: |y| <= |q - c| sin(alpha) <= tan(alpha) (q - c).n
-    // <= tan(alpha_c) (s - R), with (q - c).n = (x, z + R).n - R <= s - R)
     g.info.cv_r = rx && rx->radius > 0.0 && rx->alpha_c < 80.0 * M_PI / 180.0 ? rx->radius : 0.0;
     g.info.cv_tan = g.info.cv_r > 0.0 ? std::tan(rx->alpha_c) * (1.0 + 1e-9) : 0.0;
     const long cells = (long)g.info.n[0] * g.info.n[1] * g.info.n[2];

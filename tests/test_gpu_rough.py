@@ -94,6 +94,26 @@ def test_rough_bone_reduced(torch_gpu, oracle):
     _compare(oracle, _rough(w, rough), label="bone-rough")
 
 
+@pytest.mark.parametrize("z_mid", [1.5, 1.6])
+def test_rough_floor_under_a_smooth_boundary(torch_gpu, oracle, z_mid):
+    """A smooth plane at 10 mm (matched or mismatched impedance) between the
+    array and a rough floor at 20 mm: every rough-boundary secondary ray
+    crosses the plane and records nothing (the echo reaches the array as the
+    primary ray's own continuation); same paths, counters and data as the
+    oracle."""
+    MM = 1e-3
+    mats = np.array([[1.5, 0.0, 1540.0], [z_mid, 0.0, 1540.0], [7.8, 0.0, 1540.0]])
+    pln = np.array([[0.0, 0.0, 1.0, 10 * MM], [0.0, 0.0, 1.0, 20 * MM]])
+    sc = scenes.Scene(mats, np.array([-20, -20, 0, 20, 20, 40.0]) * MM, 0, np.zeros((0, 9)),
+                      np.zeros((0, 2), np.int32), np.zeros((0, 4)), np.zeros((0, 2), np.int32), pln,
+                      np.array([[1, 0], [2, 1]], np.int32), np.zeros((0, 4)), rough=np.array([0.0, 0.0, 0.5]))
+    w = scenes.tiny(rays_per_element=512)
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(15.0), alpha_c=math.radians(45.0), max_bounces=3)
+    w = dataclasses.replace(w, scene=sc, acq=acq)
+    st, ost = _compare(oracle, w, label=f"rough-under-plane-{z_mid}")
+    assert ost["nee_cast"] > 1000 and ost["nee_blocked"] == ost["nee_cast"] and ost["direct_hits"] > 100
+
+
 def test_rough_explicit_rays_same_events(torch_gpu, oracle):
     w = _rough(scenes.tiny(), [0.0, 0.4, 0.6], alpha_c_deg=40.0)
     rng = np.random.default_rng(17)
