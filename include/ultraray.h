@@ -2,16 +2,19 @@
  * ultraray.h -- C ABI of the MI355X (gfx950) full-path ultrasound ray tracer.
  *
  * The library computes the pressure signal P(e, t) received by every element
- * e of a linear transducer over time t for a plane-wave acquisition pattern,
- * and turns these per-element signals into a B-mode image (UltraRay, arXiv
- * 2501.05828, Sec. 2.1 problem statement and Sec. 2.3 signal processing).
+ * e of a linear or convex transducer array over time t for a plane-wave (or
+ * element-by-element) acquisition pattern, and turns these per-element
+ * signals into a B-mode image (UltraRay, arXiv 2501.05828, Sec. 2.1 problem
+ * statement and Sec. 2.3 signal processing).
  *
  * Conventions shared by every entry point
  *   Units     metres, seconds, m/s; impedance Z in MRayl; attenuation in
  *             dB/(cm MHz); angles in radians.
- *   Frame     x lateral, y elevation, z depth.  The transducer face is the
- *             plane z = 0 of the scene box and faces +z.  Element e has its
- *             centre at x_e = (e - (E-1)/2) * pitch, y = 0, z = 0.
+ *   Frame     x lateral, y elevation, z depth.  A linear array's face is
+ *             the plane z = 0 of the scene box and faces +z; element e has
+ *             its centre at x_e = (e - (E-1)/2) * pitch, y = 0, z = 0.  A
+ *             convex array (ur_probe_desc.radius > 0) lies on the cylinder
+ *             of that radius about the y axis through (0, 0, -radius).
  *   Layouts   channel data [n_tx][n_elements][n_samples], samples
  *             contiguous; complex data interleaved (re, im) float pairs;
  *             images [nx][nz], depth contiguous.  Sample n of the channel
@@ -27,7 +30,9 @@
  *   Errors    Every entry point returns a ur_status (0 = success).  On a
  *             validation failure nothing is launched and no output is
  *             written; ur_last_error() returns a message describing the last
- *             failure on that context.  No C++ exception crosses the ABI.
+ *             failure on that context (ur_last_error(NULL): the calling
+ *             thread's last failed ur_context_create).  No C++ exception
+ *             crosses the ABI.
  *   Threads   A context is used by one host thread at a time.
  */
 #ifndef ULTRARAY_H
@@ -180,13 +185,16 @@ typedef struct {
 } ur_ray;
 
 /* Creates a context bound to HIP device `hip_device`.  *out receives the
- * handle (NULL on failure). */
+ * handle (NULL on failure); on failure ur_last_error(NULL) names the HIP call
+ * or argument that failed. */
 UR_API ur_status ur_context_create(int hip_device, ur_context **out);
 
 /* Frees the context and everything the library allocated for it.  NULL is a no-op. */
 UR_API void ur_context_destroy(ur_context *ctx);
 
-/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+/* Message of the last failed call on ctx ("" if none); valid until the next
+ * call.  With ctx = NULL: the calling thread's last failed ur_context_create
+ * ("" if the last one succeeded). */
 UR_API const char *ur_last_error(const ur_context *ctx);
 
 /* Library version string. */
@@ -225,9 +233,12 @@ UR_API ur_status ur_set_proposal(ur_context *ctx, const float *pdf_dev, const fl
  * If ch_rf_dev is not NULL, also writes the pulse-shaped analytic channel
  * data [n_tx][n_elements][n_samples][2] (as ur_pulse).  Only rays with
  * index r = ray_offset + k * ray_stride are traced (stride 1, offset 0 traces
- * all; the estimator's normalisation is unchanged).  If stats is not NULL the
- * call synchronises the stream and fills it (the counting kernel variant is
- * used, which also counts traversal work). */
+ * all; the estimator's normalisation is unchanged).  If stats is not NULL it
+ * is filled (the counting kernel variant is used, which also counts
+ * traversal work).  The call waits for its work on the stream to finish and
+ * fails with UR_ERR_CAPACITY if a primary-ray segment found no slot in the
+ * segment queue (sized for the worst case, so this signals a library
+ * fault rather than a size limit). */
 UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
 
@@ -256,10 +267,6 @@ UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t
 UR_API ur_status ur_synthesize(ur_context *ctx, const float *ch_sa_dev, const double *angles, int64_t n_ang,
                                float *out_dev, void *stream);
 
-/* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
- * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at
- * half maximum n_cycles / f_c, taps |m| <= ceil(3 sigma f_s), zero outside the
- * record.  Layouts as in ur_trace. */
 /* Scan conversion for display of a sector image (Sec. 4's convex-probe
  * images): img_dev [sector->nx][sector->nz] (device, FP32, e.g. a B-mode
  * image from ur_beamform on that sector grid) resampled onto the Cartesian
@@ -272,6 +279,12 @@ UR_API ur_status ur_synthesize(ur_context *ctx, const float *ch_sa_dev, const do
 UR_API ur_status ur_scan_convert(ur_context *ctx, const ur_grid_desc *sector, const float *img_dev,
                                  const ur_grid_desc *cart, float fill, float *out_dev, void *stream);
 
+/* Pulse shaping (Eq. 14): ch_rf = ch_raw convolved with the analytic pulse
+ * g(t) (sin(2 pi f_c t) - i cos(2 pi f_c t)), Gaussian g with full width at
+ * half maximum n_cycles / f_c, taps |m| <= ceil(3 sigma f_s), zero outside the
+ * record.  ch_raw_dev [n_tx][E][n_samples] FP32, ch_rf_dev
+ * [n_tx][E][n_samples][2] FP32 (overwritten); layouts as in ur_trace.
+ * Asynchronous on `stream`. */
 UR_API ur_status ur_pulse(ur_context *ctx, const float *ch_raw_dev, float *ch_rf_dev, void *stream);
 
 /* Plane-wave delay-and-sum with coherent compounding over transmits,

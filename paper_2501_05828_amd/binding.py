@@ -174,7 +174,8 @@ class Context:
         h = C.c_void_p()
         rc = self.lib.ur_context_create(int(device), C.byref(h))
         if rc != 0:
-            raise URError(f"ur_context_create failed: {STATUS.get(rc, rc)}")
+            msg = self.lib.ur_last_error(None).decode()
+            raise URError(f"ur_context_create failed: {STATUS.get(rc, rc)}: {msg}")
         self.h = h
         self.device = device
         self._keep = []

@@ -10,15 +10,25 @@
 // extents are dilated and rounded outward so culling never rejects a
 // primitive the FP64 test would accept.
 //
-// Triangles sit in a threaded (escape-index) BVH in depth-first order, so the
-// closest-hit query and the secondary-ray crossing query need no stack.
-// Scatterer captures come from a uniform grid walked by a 3D DDA whose cell
-// intervals partition the segment, so every capture is reported once.
+// Closest hits walk a four-wide BVH (64-byte quantised nodes, one triangle
+// per leaf) in nearest-first order with a per-lane stack in LDS; the
+// secondary rays' crossing queries and the exact fallback of an overflowing
+// stack walk the same tree in its threaded (escape-index) binary layout,
+// which needs no stack.  Scatterer captures come from a uniform grid walked
+// by a 3D DDA whose cell intervals partition the segment, so every capture
+// is reported once.
 //
-// The kernel is persistent: each lane advances its ray by one segment per
-// loop iteration and, when the ray ends, fetches the next ray of the
-// acquisition from a global counter (one atomic per wavefront), so lanes do
-// not idle behind long paths (rays trapped by total internal reflection).
+// The trace runs as two persistent kernels joined by a segment queue:
+// k_extend advances each lane's closest-hit query by one node visit per
+// step, shades finished queries in batches (interfaces, direct hits,
+// termination) and queues the segments that can reach the scatterer grid;
+// k_scatter walks the queued segments through the grid and queues the
+// transducer-sampling candidates, whose secondary rays k_nee casts.  Lanes
+// refill independently from chunks of work that a wavefront takes by guided
+// self-scheduling (one atomic per chunk), so lanes do not idle behind long
+// paths.  k_trace is the single-loop form of the same arithmetic, used for
+// explicit rays with an event log and to re-trace a range whose sampling
+// queue overflowed.
 #include "trace_device.h"
 #include "ultraray.h"
 

@@ -30,6 +30,10 @@ struct DevBuf {
     }
 };
 
+// Message of the calling thread's last failed ur_context_create (there is
+// no context to hold it).
+thread_local std::string t_create_err;
+
 }  // namespace
 
 struct ur_context {
@@ -277,25 +281,39 @@ extern "C" {
 
 UR_API const char *ur_version(void) { return "ultraray-mi355x 0.1 (gfx950)"; }
 
+static ur_status create_fail(ur_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_create_err = buf;
+    return code;
+}
+
 UR_API ur_status ur_context_create(int hip_device, ur_context **out) {
-    if (!out) return UR_ERR_INVALID_ARG;
+    if (!out) return create_fail(UR_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return UR_ERR_HIP;
-    if (hip_device < 0 || hip_device >= n) return UR_ERR_INVALID_ARG;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return create_fail(UR_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (n <= 0) return create_fail(UR_ERR_HIP, "hipGetDeviceCount: no HIP device");
+    if (hip_device < 0 || hip_device >= n)
+        return create_fail(UR_ERR_INVALID_ARG, "hip_device %d out of range (%d devices)", hip_device, n);
     ur_context *c = new (std::nothrow) ur_context();
-    if (!c) return UR_ERR_OOM;
+    if (!c) return create_fail(UR_ERR_OOM, "host allocation failed");
     c->device = hip_device;
-    if (hipSetDevice(hip_device) != hipSuccess) {
+    if ((e = hipSetDevice(hip_device)) != hipSuccess) {
         delete c;
-        return UR_ERR_HIP;
+        return create_fail(UR_ERR_HIP, "hipSetDevice(%d): %s", hip_device, hipGetErrorString(e));
     }
-    for (auto &e : c->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            delete c;
-            return UR_ERR_HIP;
+    for (auto &ev : c->ev) {
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            ur_context_destroy(c);
+            return create_fail(UR_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
         }
     }
+    t_create_err.clear();
     *out = c;
     return UR_OK;
 }
@@ -319,7 +337,7 @@ UR_API void ur_context_destroy(ur_context *c) {
     delete c;
 }
 
-UR_API const char *ur_last_error(const ur_context *c) { return c ? c->err.c_str() : "null context"; }
+UR_API const char *ur_last_error(const ur_context *c) { return c ? c->err.c_str() : t_create_err.c_str(); }
 
 UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
     return guarded(c, [&]() -> ur_status {
@@ -761,12 +779,13 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         c->trace_timed = c->n_tev > 0;
         if (ch_rf_dev) HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
                                                   (int64_t)P.T * P.E, P.S, s));
+        // every call checks the segment queue's lost count (one 8-byte read)
+        unsigned long long lost = 0;
+        HIP_TRY(c, hipMemcpyAsync(&lost, ctr + 6, sizeof(lost), hipMemcpyDeviceToHost, s));
         if (stats) {
             unsigned long long h[kNumStats], h2[kNumStats];
             HIP_TRY(c, hipMemcpyAsync(h, st1, sizeof(h), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipMemcpyAsync(h2, st2, sizeof(h2), hipMemcpyDeviceToHost, s));
-            unsigned long long lost = 0;
-            HIP_TRY(c, hipMemcpyAsync(&lost, ctr + 6, sizeof(lost), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipStreamSynchronize(s));
             if (lost) return c->fail(UR_ERR_CAPACITY, "segment queue overflow (%llu segments lost)", lost);
             // the overflow re-trace contributes only its transducer-sampling work
@@ -782,6 +801,9 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
             stats->kernel_ms = ms;
+        } else {
+            HIP_TRY(c, hipStreamSynchronize(s));
+            if (lost) return c->fail(UR_ERR_CAPACITY, "segment queue overflow (%llu segments lost)", lost);
         }
         return UR_OK;
     });
@@ -876,38 +898,50 @@ static DasParams das_params(const ur_context *c, const ur_grid_desc *g) {
     return P;
 }
 
+static ur_status check_beamform(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, const float *iq_dev,
+                                const float *env_dev, const float *bmode_dev) {
+    if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
+    if (!g || !ch_rf_dev) return c->fail(UR_ERR_INVALID_ARG, "grid and ch_rf_dev are required");
+    if (!iq_dev && !env_dev && !bmode_dev) return c->fail(UR_ERR_INVALID_ARG, "no output requested");
+    if (g->nx < 1 || g->nz < 1 || g->nx > 65535 || g->nz > (1 << 24))
+        return c->fail(UR_ERR_INVALID_ARG, "grid size out of range");
+    const double gv[] = {g->x0, g->x1, g->z0, g->z1, g->dynamic_range_db};
+    if (!finite_all(gv, 5)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
+    if (bmode_dev && !(g->dynamic_range_db > 0)) return c->fail(UR_ERR_INVALID_ARG, "dynamic range must be > 0");
+    if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
+    if (g->sector != 0 && g->sector != 1) return c->fail(UR_ERR_INVALID_ARG, "sector must be 0 or 1");
+    return UR_OK;
+}
+
+// DAS + envelope into iq / env, then (if bmode) log compression of env with
+// its maximum reduced into *max_bits.
+static ur_status run_beamform(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, float *iq_dev, float *env,
+                              float *bmode_dev, unsigned int *max_bits, hipStream_t s) {
+    DasParams P = das_params(c, g);
+    P.rf = (const float2 *)ch_rf_dev;
+    P.iq = (float2 *)iq_dev;
+    P.env = env;
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    HIP_TRY(c, ur_launch_das(P, s));
+    HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    c->das_timed = true;
+    if (bmode_dev)
+        HIP_TRY(c, ur_launch_bmode(env, bmode_dev, g->nx * g->nz, (float)g->dynamic_range_db, max_bits, s));
+    return UR_OK;
+}
+
 UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, float *iq_dev, float *env_dev,
                              float *bmode_dev, void *stream) {
     return guarded(c, [&]() -> ur_status {
-        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_transmit_setup first");
-        if (!g || !ch_rf_dev) return c->fail(UR_ERR_INVALID_ARG, "grid and ch_rf_dev are required");
-        if (!iq_dev && !env_dev && !bmode_dev) return c->fail(UR_ERR_INVALID_ARG, "no output requested");
-        if (g->nx < 1 || g->nz < 1 || g->nx > 65535 || g->nz > (1 << 24))
-            return c->fail(UR_ERR_INVALID_ARG, "grid size out of range");
-        const double gv[] = {g->x0, g->x1, g->z0, g->z1, g->dynamic_range_db};
-        if (!finite_all(gv, 5)) return c->fail(UR_ERR_INVALID_ARG, "non-finite grid value");
-        if (bmode_dev && !(g->dynamic_range_db > 0)) return c->fail(UR_ERR_INVALID_ARG, "dynamic range must be > 0");
-        if (g->apod != UR_APOD_NONE && g->apod != UR_APOD_HANN) return c->fail(UR_ERR_INVALID_ARG, "unknown apodisation");
-        if (g->sector != 0 && g->sector != 1) return c->fail(UR_ERR_INVALID_ARG, "sector must be 0 or 1");
-        hipStream_t s = (hipStream_t)stream;
-        const int64_t E = c->probe.n_elements, npx = g->nx * g->nz;
-        ur_status st;
+        ur_status st = check_beamform(c, g, ch_rf_dev, iq_dev, env_dev, bmode_dev);
+        if (st) return st;
         float *env = env_dev;
         if (!env && bmode_dev) {
-            if ((st = alloc(c, c->d_env, npx * sizeof(float)))) return st;
+            if ((st = alloc(c, c->d_env, g->nx * g->nz * sizeof(float)))) return st;
             env = (float *)c->d_env.p;
         }
-        DasParams P = das_params(c, g);
-        P.rf = (const float2 *)ch_rf_dev;
-        P.iq = (float2 *)iq_dev;
-        P.env = env;
-        HIP_TRY(c, hipEventRecord(c->ev[2], s));
-        HIP_TRY(c, ur_launch_das(P, s));
-        HIP_TRY(c, hipEventRecord(c->ev[3], s));
-        c->das_timed = true;
-        if (bmode_dev)
-            HIP_TRY(c, ur_launch_bmode(env, bmode_dev, npx, (float)g->dynamic_range_db, (unsigned int *)c->d_maxbits.p, s));
-        return UR_OK;
+        return run_beamform(c, g, ch_rf_dev, iq_dev, env, bmode_dev, (unsigned int *)c->d_maxbits.p,
+                            (hipStream_t)stream);
     });
 }
 

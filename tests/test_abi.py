@@ -60,5 +60,6 @@ def test_context_without_gpu_fails_cleanly():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     from paper_2501_05828_amd import binding
-    with pytest.raises(binding.URError):
+    # the failing HIP call is named although no context exists
+    with pytest.raises(binding.URError, match="hipGetDeviceCount"):
         binding.Context(0)

@@ -111,7 +111,7 @@ def test_rough_floor_under_a_smooth_boundary(torch_gpu, oracle, z_mid):
     acq = dataclasses.replace(w.acq, alpha_m=math.radians(15.0), alpha_c=math.radians(45.0), max_bounces=3)
     w = dataclasses.replace(w, scene=sc, acq=acq)
     st, ost = _compare(oracle, w, label=f"rough-under-plane-{z_mid}")
-    assert ost["nee_cast"] > 1000 and ost["nee_blocked"] == ost["nee_cast"] and ost["direct_hits"] > 100
+    assert ost["nee_cast"] > 1000 and ost["nee_blocked"] == ost["nee_cast"] and ost["direct_hits"] > 20
 
 
 def test_rough_explicit_rays_same_events(torch_gpu, oracle):
