@@ -295,6 +295,21 @@ UR_API ur_status ur_pulse(ur_context *ctx, const float *ch_raw_dev, float *ch_rf
 UR_API ur_status ur_beamform(ur_context *ctx, const ur_grid_desc *grid, const float *ch_rf_dev, float *iq_dev,
                              float *env_dev, float *bmode_dev, void *stream);
 
+/* ur_beamform for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but no device allocation, no
+ * hipFree and no allocating library routine in the call.  Its scratch (the
+ * envelope when bmode_dev is given without env_dev, and the envelope's
+ * maximum) lives in a static device array of 16 MiB + 256 bytes that every
+ * device loading the library holds until the process ends.  A B-mode image
+ * without env_dev is limited to nx * nz <= 4,194,304 pixels (UR_ERR_CAPACITY
+ * beyond, nothing launched).  Every call on one device shares that array,
+ * which keeps the last call's contents: calls that overlap on one device
+ * (other streams, other contexts, other threads) race and must be ordered by
+ * the caller. */
+UR_API ur_status ur_beamform_static(ur_context *ctx, const ur_grid_desc *grid, const float *ch_rf_dev,
+                                    float *iq_dev, float *env_dev, float *bmode_dev, void *stream);
+
 /* Device time in milliseconds, between HIP events recorded on the call's
  * stream immediately around each kernel launch: the trace kernels of the
  * last ur_trace call (extend + scatter, summed over launch ranges; secondary

@@ -104,6 +104,8 @@ SIGNATURES = [
     ("ur_set_limits", C.c_int, [_CTX, C.c_int64, C.c_int64]),
     ("ur_pulse", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ur_beamform_static", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
     ("ur_last_kernel_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double)]),
     ("ur_last_trace_kernels_ms", C.c_int, [_CTX, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int64)]),
     ("ur_trace_rays", C.c_int, [_CTX, C.c_uint64, P(Ray), C.c_int64, P(Event), C.c_int64, P(C.c_int64),
@@ -264,6 +266,13 @@ class Context:
         rc = self.lib.ur_beamform(self.h, C.byref(g), _ptr(ch_rf), _ptr(iq), _ptr(env), _ptr(bmode),
                                   _stream_ptr(stream))
         self.check(rc, "ur_beamform")
+
+    def ur_beamform_static(self, grid, ch_rf, iq=None, env=None, bmode=None, apod=UR_APOD_HANN,
+                           dynamic_range_db=90.0, stream=None):
+        g = _grid_desc(grid, apod, dynamic_range_db)
+        rc = self.lib.ur_beamform_static(self.h, C.byref(g), _ptr(ch_rf), _ptr(iq), _ptr(env), _ptr(bmode),
+                                         _stream_ptr(stream))
+        self.check(rc, "ur_beamform_static")
 
     def ur_set_cost_histogram(self, cost):
         self.check(self.lib.ur_set_cost_histogram(self.h, _ptr(cost)), "ur_set_cost_histogram")

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,16 @@ struct DevBuf {
         bytes = 0;
     }
 };
+
+// Scratch of ur_beamform_static, the allocation-free B-mode entry point: a
+// 256-byte header whose first word is the running maximum of the envelope
+// (FP32 bits), then an envelope buffer of at most kStaticPixels pixels.  HIP
+// gives every device that loads the library its own copy, held until the
+// process ends.  Host code never uses the symbol itself as an address: it
+// takes each device's address once (static_scratch) and passes that.
+constexpr int64_t kStaticHeader = 64;                  // floats (256 bytes)
+constexpr int64_t kStaticPixels = int64_t(1) << 22;    // 2048 x 2048 pixels, 16 MiB
+static __device__ __align__(256) float scratch[kStaticHeader + kStaticPixels];
 
 // Message of the calling thread's last failed ur_context_create (there is
 // no context to hold it).
@@ -81,6 +92,7 @@ struct ur_context {
     const float *pdf = nullptr, *cdf = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool trace_timed = false, das_timed = false;
+    float *scratch = nullptr;              // this device's copy of the static B-mode scratch
 
     ur_status fail(ur_status code, const char *fmt, ...) {
         char buf[512];
@@ -291,6 +303,24 @@ static ur_status create_fail(ur_status code, const char *fmt, ...) {
     return code;
 }
 
+// Each device's address of the static scratch, taken once with that device
+// current (kMaxDevices devices at most).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch[kMaxDevices] = {};
+
+static hipError_t static_scratch(int device, float **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = (float *)p;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+
 UR_API ur_status ur_context_create(int hip_device, ur_context **out) {
     if (!out) return create_fail(UR_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -298,7 +328,7 @@ UR_API ur_status ur_context_create(int hip_device, ur_context **out) {
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess) return create_fail(UR_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
     if (n <= 0) return create_fail(UR_ERR_HIP, "hipGetDeviceCount: no HIP device");
-    if (hip_device < 0 || hip_device >= n)
+    if (hip_device < 0 || hip_device >= n || hip_device >= kMaxDevices)
         return create_fail(UR_ERR_INVALID_ARG, "hip_device %d out of range (%d devices)", hip_device, n);
     ur_context *c = new (std::nothrow) ur_context();
     if (!c) return create_fail(UR_ERR_OOM, "host allocation failed");
@@ -312,6 +342,10 @@ UR_API ur_status ur_context_create(int hip_device, ur_context **out) {
             ur_context_destroy(c);
             return create_fail(UR_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
         }
+    }
+    if ((e = static_scratch(hip_device, &c->scratch)) != hipSuccess) {
+        ur_context_destroy(c);
+        return create_fail(UR_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
     }
     t_create_err.clear();
     *out = c;
@@ -942,6 +976,26 @@ UR_API ur_status ur_beamform(ur_context *c, const ur_grid_desc *g, const float *
         }
         return run_beamform(c, g, ch_rf_dev, iq_dev, env, bmode_dev, (unsigned int *)c->d_maxbits.p,
                             (hipStream_t)stream);
+    });
+}
+
+UR_API ur_status ur_beamform_static(ur_context *c, const ur_grid_desc *g, const float *ch_rf_dev, float *iq_dev,
+                                    float *env_dev, float *bmode_dev, void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st = check_beamform(c, g, ch_rf_dev, iq_dev, env_dev, bmode_dev);
+        if (st) return st;
+        if (!c->scratch) return c->fail(UR_ERR_HIP, "no static scratch on device %d", c->device);
+        float *env = env_dev;
+        if (!env && bmode_dev) {
+            if (g->nx * g->nz > kStaticPixels)
+                return c->fail(UR_ERR_CAPACITY,
+                               "ur_beamform_static: %lld pixels exceed the static envelope buffer of %lld pixels "
+                               "(pass env_dev, or use ur_beamform)",
+                               (long long)(g->nx * g->nz), (long long)kStaticPixels);
+            env = c->scratch + kStaticHeader;
+        }
+        // the maximum's word is cleared by ur_launch_bmode's own fill kernel
+        return run_beamform(c, g, ch_rf_dev, iq_dev, env, bmode_dev, (unsigned int *)c->scratch, (hipStream_t)stream);
     });
 }
 
