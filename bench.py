@@ -69,30 +69,107 @@ def scatter_flops(st):
             float(FP64_PER_CELL * st["scat_cells"] + FP64_PER_EVENT * st["scatter_events"]))
 
 
+# Delay-and-sum (k_das), algorithmic work: per (pixel, transmit, element)
+# term the sample index (1 add), the linear interpolation of a complex sample
+# (2 x (2 mul + 1 add)) and its accumulation (2 adds); per (pixel, element)
+# the receive distance (dx, dx^2 + dz^2, sqrt, scale: 5) and the apodised
+# accumulation (complex fma: 4); per (pixel, transmit) the transmit delay
+# (2 fma); per pixel the envelope (3 + sqrt).  Bytes: the channel data read
+# once, IQ and envelope written once.
+DAS_FLOP_PER_TERM = 9
+DAS_FLOP_PER_PX_ELEM = 9
+DAS_FLOP_PER_PX_TX = 4
+DAS_FLOP_PER_PX = 4
+
 TRACE_SOURCES = ["k_trace.hip", "trace_device.h", "scatter_grid.h", "bvh_layout.h", "philox.h", "ur_internal.h"]
+DAS_SOURCES = ["k_signal.hip", "ur_internal.h"]
 
 
-def kernel_hash():
-    """Hash of the trace kernel's source (the .hip file and the headers it
-    includes), to tell whether stored counter readings still apply."""
+def kernel_hash(sources=TRACE_SOURCES):
+    """Hash of a kernel's source (the .hip file and the headers it includes),
+    to tell whether stored counter readings still apply."""
     h = hashlib.sha256()
-    for name in TRACE_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_2501_05828_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def load_pmc(workload):
-    """The committed rocprofv3 PMC summary of the extend kernel, or None if
-    absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"pmc_trace_{workload}.json")
+def load_pmc(workload, kind="trace", sources=TRACE_SOURCES):
+    """A committed rocprofv3 PMC summary (profiles/pmc_<kind>_<workload>.json),
+    or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kind}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(sources):
         return None
     return d
+
+
+def das_work(acq, grid):
+    """Algorithmic FLOPs and bytes of one compounded DAS frame."""
+    px = grid.nx * grid.nz
+    T, E, S = acq.n_tx, acq.n_elements, acq.n_samples
+    flops = px * (T * E * DAS_FLOP_PER_TERM + E * DAS_FLOP_PER_PX_ELEM + T * DAS_FLOP_PER_PX_TX + DAS_FLOP_PER_PX)
+    nbytes = T * E * S * 8 + px * (8 + 4)
+    return float(flops), float(nbytes), px * T * E
+
+
+def das_roofline(workload, acq, grid, t_das):
+    flops, nbytes, terms = das_work(acq, grid)
+    out = {"kernel": "k_das", "bound": "alu", "achieved": flops / t_das / 1e12, "peak": PEAK_FP32 / 1e12,
+           "unit": "TFLOP/s", "frac": flops / t_das / PEAK_FP32, "terms": terms,
+           "hbm_achieved_gbs": nbytes / t_das / 1e9, "hbm_frac": nbytes / t_das / PEAK_HBM,
+           "algorithmic_bytes": nbytes, "traffic": None, "valu": None}
+    pmc = load_pmc(workload, "das", DAS_SOURCES)
+    if pmc is not None:
+        out["traffic"] = pmc["fetch_bytes"] / pmc["copy_fetch_factor"] + pmc["write_bytes"] / pmc["copy_write_factor"]
+        v = pmc.get("valu")
+        if v:
+            out["valu"] = {"insts": v["insts"], "issue_frac": v["insts"] / (N_CU * CLOCK_HZ * t_das),
+                           "lanes_active_frac": v["active_lanes_per_inst"] / 64.0}
+    return out
+
+
+def c3_measure(reps_trace=2, reps_das=10):
+    """The batched workload (21 plane waves -20..20 deg, 2e7 rays per
+    transmit, 1024 x 1024 Hann-apodised compound): trace rays/s and the DAS
+    frame on its traced channel data, each from HIP events the library records
+    around its kernels."""
+    import torch
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.batched()
+    sim = Simulator(w)
+    sim.trace(seed=w.seed + 7000)              # warm-up; leaves channel data for the DAS timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = []
+    for i in range(reps_trace):
+        sim.trace(seed=w.seed + 7001 + i)
+        tr.append(sim.kernel_ms()[0])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps_trace
+    sim.beamform()
+    das = []
+    for _ in range(reps_das):
+        sim.beamform()
+        das.append(sim.kernel_ms()[1])
+    torch.cuda.synchronize()
+    t_das = sum(das) / len(das) * 1e-3
+    n_rays = w.acq.n_rays
+    print(f"[bench] batched: trace {sum(tr) / len(tr):.1f} ms ({wall * 1e3:.1f} ms wall incl. secondary rays "
+          f"and pulse), DAS {t_das * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    return {"workload": "batched: bone phantom, 128 elements, 21 plane waves -20..20 deg, "
+                        f"{w.acq.n_elements * w.acq.rays_per_element:.2e} rays/transmit, DAS "
+                        f"{w.grid.nx}x{w.grid.nz} Hann over 21x128x4096 channels",
+            "rays_per_frame": n_rays, "trace_rays_per_s": n_rays / wall, "trace_frame_ms": wall * 1e3,
+            "trace_kernel_ms": sum(tr) / len(tr), "das_kernel_ms": t_das * 1e3, "das_frames_per_s": 1.0 / t_das,
+            "das_roofline": das_roofline("batched", w.acq, w.grid, t_das)}
 
 
 def load_traffic(workload):
@@ -318,11 +395,13 @@ def main():
     ap.add_argument("--element-choice", choices=["uniform", "cone"], default="uniform",
                     help="transducer-sampling target: uniform over all elements, or over those in the cone")
     ap.add_argument("--print-kernel-hash", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched-workload trace and DAS measurement")
+    ap.add_argument("--c3-only", action="store_true", help="run only the batched-workload trace and DAS measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.print_kernel_hash:
-        print(kernel_hash())
+        print(json.dumps({"trace": kernel_hash(), "das": kernel_hash(DAS_SOURCES)}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (rays would shard by transmit "
@@ -338,6 +417,9 @@ def main():
         return
     if args.experiment == "rough-nee":
         rough_nee_experiment(args)
+        return
+    if args.c3_only:
+        print(json.dumps(c3_measure()))
         return
     if args.copy_calibration:
         a = torch.ones(1 << 28, device="cuda")
@@ -391,6 +473,7 @@ def main():
     peak = (xf32 + xf64) / (xf32 / PEAK_FP32 + xf64 / PEAK_FP64)
     traffic = load_traffic(w.name)
     pmc = load_pmc(w.name)
+    das_roof = das_roofline(w.name, acq, grid, t_das)
     valu = None
     if pmc is not None and "valu" in pmc:
         # a wave64 VALU instruction occupies one 16-lane SIMD for 4 cycles:
@@ -410,7 +493,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 decisions, f32 data",
         "data": "synthetic",
         "config": {
             "workload": f"{w.name} phantom: {acq.n_elements} elements"
@@ -455,7 +538,10 @@ def main():
             "flops_fp32": sf32,
             "flops_fp64": sf64,
         },
+        "das_roofline": das_roof,
     }
+    if not args.no_c3 and w.name == "bone":
+        out["batched"] = c3_measure()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)
     print(json.dumps(out))

@@ -42,13 +42,6 @@ __global__ __launch_bounds__(kFirTile) void k_pulse(const float *__restrict__ ra
     rf[ch * S + n] = make_float2(re, im);
 }
 
-// Delay-and-sum: one lane per pixel, lanes of a wavefront run down one image
-// column (depth contiguous), so for a fixed (transmit, element) the 64 lanes
-// gather from a short, monotone stretch of that channel.  The receive delay
-// (one FP64 square root per pixel and element) is hoisted out of the
-// transmit loop; the fractional sample index is formed in FP64 so that the
-// interpolation weight and sample match the reference index exactly; the
-// interpolation and accumulation are FP32.
 // Pixel position: a Cartesian grid point, or on a sector grid the point at
 // angle x0 + ix dx and depth z0 + iz dz along the ray from the centre of
 // curvature (0, 0, -R): (R + r) (sin phi, cos phi) - (0, R).
@@ -65,37 +58,112 @@ __device__ __forceinline__ void das_pixel(const DasParams &p, int ix, int iz, do
     }
 }
 
-__global__ __launch_bounds__(256) void k_das(DasParams p) {
-    const int iz = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ix = blockIdx.y;
-    if (iz >= p.nz) return;
-    double x, z;
-    das_pixel(p, ix, iz, x, z);
-    const double zz = z * z;
-    float re = 0.0f, im = 0.0f;
+// A fractional sample index split into its floor (exact, FP64) and its
+// fraction in [0, 1) (FP32).  Indices far outside any record are clamped,
+// so the conversion stays within int range; they fail the range test.
+struct SplitIdx {
+    int n;
+    float f;
+};
+__device__ __forceinline__ SplitIdx split_idx(double v) {
+    v = fmin(fmax(v, -1073741824.0), 1073741824.0);
+    const double fl = floor(v);
+    return SplitIdx{(int)fl, (float)(v - fl)};
+}
+
+// The DAS sample index of one (pixel, transmit, element) term is the sum of
+// a transmit part t_tx fs (per pixel and transmit) and a receive part
+// t_rx fs (per pixel and element), each split as above: floor parts add
+// exactly and the two fractions add in FP32 (error below 2.4e-7 samples), so
+// i0 = floor of the FP64 sum except within that distance of an integer,
+// where linear interpolation is continuous.  Returns the interpolation
+// weight of sample i0 + 1 and whether 0 <= i0 < S - 1.
+__device__ __forceinline__ bool das_term_index(SplitIdx rx, SplitIdx tx, int S, int &i0, float &fr) {
+    float f = rx.f + tx.f;
+    int n = rx.n + tx.n;
+    const bool up = f >= 1.0f;
+    fr = up ? f - 1.0f : f;
+    i0 = up ? n + 1 : n;
+    return (unsigned)i0 < (unsigned)(S - 1);
+}
+
+__device__ __forceinline__ SplitIdx das_rx(const DasParams &p, double x, double z, int e) {
+    const double dxe = x - p.xe[e];
+    // (elements off z = 0 only on a convex array)
+    const double dze = p.ze ? z - p.ze[e] : z;
+    return split_idx(sqrt(dxe * dxe + dze * dze) * p.fs_over_c0);
+}
+
+__device__ __forceinline__ SplitIdx das_tx(const DasParams &p, double x, double z, int tx) {
+    const double4 c = p.txc[tx];
+    return split_idx(x * c.x + z * c.y + c.z);
+}
+
+// Delay-and-sum over K transmits t0 .. t0 + K - 1 of one pixel: for every
+// element, the K gathers of the two neighbouring complex samples are issued
+// together (branch-free: an index outside the record reads sample 0 of the
+// same channel with weight 0), then interpolated and summed, and the sum is
+// weighted by the element's apodisation.
+template <int K>
+__device__ __forceinline__ void das_transmits(const DasParams &p, double x, double z, int t0, float &re, float &im) {
+    SplitIdx tt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tt[k] = das_tx(p, x, z, t0 + k);
+    const int64_t tstride = (int64_t)p.E * p.S;
     for (int e = 0; e < p.E; ++e) {
-        const double dxe = x - p.xe[e];
-        // (elements off z = 0 only on a convex array)
-        const double dze = p.ze ? z - p.ze[e] : 0.0;
-        const double trx = sqrt(dxe * dxe + (p.ze ? dze * dze : zz)) * p.fs_over_c0;
-        const float a = p.apod[e];
-        const float2 *ch = p.rf + (int64_t)e * p.S;
-        float er = 0.0f, ei = 0.0f;
-        for (int tx = 0; tx < p.T; ++tx) {
-            const double4 c = p.txc[tx];
-            const double idx = x * c.x + z * c.y + c.z + trx;
-            const double f0 = floor(idx);
-            const int i0 = (int)f0;
-            if (i0 < 0 || i0 >= p.S - 1) continue;
-            const float fr = (float)(idx - f0);
-            const float2 *s = ch + (int64_t)tx * p.E * p.S + i0;
-            const float2 v0 = s[0], v1 = s[1];
-            er += fmaf(fr, v1.x - v0.x, v0.x);
-            ei += fmaf(fr, v1.y - v0.y, v0.y);
+        const SplitIdx rx = das_rx(p, x, z, e);
+        const float2 *ch = p.rf + ((int64_t)t0 * p.E + e) * p.S;
+        float2 v0[K], v1[K], wt[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int i0;
+            float fr;
+            const bool in = das_term_index(rx, tt[k], p.S, i0, fr);
+            // channel base (the same for all lanes) + a 32-bit byte offset
+            const float2 *s = (const float2 *)((const char *)(ch + k * tstride) + (uint32_t)(in ? i0 : 0) * 8u);
+            v0[k] = s[0];
+            v1[k] = s[1];
+            wt[k] = in ? make_float2(1.0f - fr, fr) : make_float2(0.0f, 0.0f);
         }
+        float er = 0.0f, ei = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            er = fmaf(wt[k].x, v0[k].x, fmaf(wt[k].y, v1[k].x, er));
+            ei = fmaf(wt[k].x, v0[k].y, fmaf(wt[k].y, v1[k].y, ei));
+        }
+        const float a = p.apod[e];
         re = fmaf(a, er, re);
         im = fmaf(a, ei, im);
     }
+}
+
+// Delay-and-sum with coherent compounding (one lane per pixel).  A block of
+// 256 lanes covers a 16 x 16 tile of the image and each wavefront an 8 x 8
+// sub-tile (8 consecutive depths per lateral position), so the samples that
+// one gather of a wavefront touches lie within a few cache lines.  The
+// transmits are taken in register batches of up to 8; the receive delay (one
+// FP64 square root per pixel and element) is formed once per batch.  The
+// interpolation and accumulation are FP32.
+constexpr int kDasTile = 16;
+__global__ __launch_bounds__(256) void k_das(DasParams p) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int ix = blockIdx.y * kDasTile + (w & 1) * 8 + (l >> 3);
+    const int iz = blockIdx.x * kDasTile + (w >> 1) * 8 + (l & 7);
+    if (ix >= p.nx || iz >= p.nz) return;   // (no block-wide synchronisation below)
+    double x, z;
+    das_pixel(p, ix, iz, x, z);
+    float re = 0.0f, im = 0.0f;
+    int t0 = 0;
+    for (; t0 + 8 <= p.T; t0 += 8) das_transmits<8>(p, x, z, t0, re, im);
+    if (t0 + 4 <= p.T) {
+        das_transmits<4>(p, x, z, t0, re, im);
+        t0 += 4;
+    }
+    if (t0 + 2 <= p.T) {
+        das_transmits<2>(p, x, z, t0, re, im);
+        t0 += 2;
+    }
+    if (t0 < p.T) das_transmits<1>(p, x, z, t0, re, im);
     const int64_t o = (int64_t)ix * p.nz + iz;
     if (p.iq) p.iq[o] = make_float2(re, im);
     if (p.env) p.env[o] = sqrtf(re * re + im * im);
@@ -149,19 +217,13 @@ __global__ __launch_bounds__(256) void k_das_adj(DasParams p, const float2 *g_iq
     if (g.x == 0.f && g.y == 0.f) return;
     double x, z;
     das_pixel(p, ix, iz, x, z);
-    const double zz = z * z;
     for (int e = 0; e < p.E; ++e) {
-        const double dxe = x - p.xe[e];
-        const double dze = p.ze ? z - p.ze[e] : 0.0;
-        const double trx = sqrt(dxe * dxe + (p.ze ? dze * dze : zz)) * p.fs_over_c0;
+        const SplitIdx rx = das_rx(p, x, z, e);
         const float a = p.apod[e];
         for (int tx = 0; tx < p.T; ++tx) {
-            const double4 c = p.txc[tx];
-            const double idx = x * c.x + z * c.y + c.z + trx;
-            const double f0 = floor(idx);
-            const int i0 = (int)f0;
-            if (i0 < 0 || i0 >= p.S - 1) continue;
-            const float fr = (float)(idx - f0);
+            int i0;
+            float fr;
+            if (!das_term_index(rx, das_tx(p, x, z, tx), p.S, i0, fr)) continue;
             float *s = g_rf + 2 * (((int64_t)tx * p.E + e) * p.S + i0);
             const float w0 = a * (1.f - fr), w1 = a * fr;
             unsafeAtomicAdd(s, w0 * g.x);
@@ -237,7 +299,8 @@ hipError_t ur_launch_pulse_adj(const float2 *g_rf, float *g_raw, const float2 *t
 }
 
 hipError_t ur_launch_das(const ur::DasParams &p, hipStream_t s) {
-    dim3 grid((unsigned)((p.nz + 255) / 256), (unsigned)p.nx);
+    if (p.nx <= 0 || p.nz <= 0) return hipSuccess;
+    dim3 grid((unsigned)((p.nz + kDasTile - 1) / kDasTile), (unsigned)((p.nx + kDasTile - 1) / kDasTile));
     hipLaunchKernelGGL(k_das, grid, dim3(256), 0, s, p);
     return hipGetLastError();
 }
