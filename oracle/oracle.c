@@ -1274,6 +1274,607 @@ int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_
     return 0;
 }
 
+/* ================================================ gradient (forward mode) */
+/* Derivatives of the functional J = sum over records of g(t) c, where g is
+ * a given adjoint of the binned channel data, with respect to the scene's
+ * impedances Z_m, attenuation coefficients alpha_m, sphere centres and
+ * scatterer amplitudes a_k.  Every path of or_trace is replayed with the
+ * same decisions (closest primitive, captures, receiving elements,
+ * crossings, reflect or transmit, taken on the FP64 values exactly as in
+ * trace_path), and every continuous quantity along it -- position,
+ * direction, distance, weight, time, path length -- is carried as a dual
+ * number: a value and its partial derivatives along every parameter
+ * (forward-mode differentiation of the estimator's formulas).  A record of
+ * value c at time t adds g(t) dc + c g'(t) dt, with g'(t) the slope of g
+ * between the sample centres under linear binning and 0 under nearest
+ * binning.  dJ/da_k = sum over the captures of k of g(t) c / a_k.
+ *
+ * The reflect-or-transmit choice: with attach_choice = 0 the choice is
+ * frozen (the derivative of the fixed-seed estimator); with 1 the weight is
+ * multiplied after the choice by R / value(R) (reflection) or
+ * (1 - R) / value(1 - R) (transmission), which leaves its value unchanged
+ * and adds the derivative of the choice probability (a score term), so the
+ * result estimates the derivative of the expected data.  Geometry enters
+ * through interior derivatives only: a capture, an element or an aperture
+ * edge that appears or disappears under a change contributes no term.
+ * Rough boundaries are not supported (returns -3). */
+#define GRAD_MAX 64
+
+static int g_nt;   /* number of active tangent directions (set before a replay) */
+
+typedef struct {
+    double v;
+    double t[GRAD_MAX];
+} dnum;
+
+static dnum dn_c(double v)
+{
+    dnum r;
+    r.v = v;
+    for (int i = 0; i < g_nt; ++i) r.t[i] = 0.0;
+    return r;
+}
+static dnum dn_add(dnum a, dnum b)
+{
+    a.v = a.v + b.v;
+    for (int i = 0; i < g_nt; ++i) a.t[i] += b.t[i];
+    return a;
+}
+static dnum dn_sub(dnum a, dnum b)
+{
+    a.v = a.v - b.v;
+    for (int i = 0; i < g_nt; ++i) a.t[i] -= b.t[i];
+    return a;
+}
+static dnum dn_neg(dnum a)
+{
+    a.v = -a.v;
+    for (int i = 0; i < g_nt; ++i) a.t[i] = -a.t[i];
+    return a;
+}
+static dnum dn_mul(dnum a, dnum b)
+{
+    dnum r;
+    r.v = a.v * b.v;
+    for (int i = 0; i < g_nt; ++i) r.t[i] = a.t[i] * b.v + a.v * b.t[i];
+    return r;
+}
+/* a * s and s * a for a constant s */
+static dnum dn_mulc(dnum a, double s)
+{
+    a.v = a.v * s;
+    for (int i = 0; i < g_nt; ++i) a.t[i] *= s;
+    return a;
+}
+/* a / s for a constant s */
+static dnum dn_divc(dnum a, double s)
+{
+    a.v = a.v / s;
+    for (int i = 0; i < g_nt; ++i) a.t[i] /= s;
+    return a;
+}
+static dnum dn_div(dnum a, dnum b)
+{
+    dnum r;
+    r.v = a.v / b.v;
+    for (int i = 0; i < g_nt; ++i) r.t[i] = (a.t[i] * b.v - a.v * b.t[i]) / (b.v * b.v);
+    return r;
+}
+static dnum dn_sqrt(dnum a)
+{
+    dnum r;
+    r.v = sqrt(a.v);
+    for (int i = 0; i < g_nt; ++i) r.t[i] = a.t[i] / (2.0 * r.v);
+    return r;
+}
+static dnum dn_exp(dnum a)
+{
+    dnum r;
+    r.v = exp(a.v);
+    for (int i = 0; i < g_nt; ++i) r.t[i] = a.t[i] * r.v;
+    return r;
+}
+/* acos of a value clamped to [-1, 1] (as the forward clamps the cosine) */
+static dnum dn_acos(dnum a)
+{
+    dnum r;
+    double x = a.v > 1.0 ? 1.0 : (a.v < -1.0 ? -1.0 : a.v);
+    double s = sqrt(fmax(1.0 - x * x, 1e-300));
+    r.v = acos(x);
+    for (int i = 0; i < g_nt; ++i) r.t[i] = -a.t[i] / s;
+    return r;
+}
+static dnum dn_dot(const dnum *a, const dnum *b)
+{
+    return dn_add(dn_add(dn_mul(a[0], b[0]), dn_mul(a[1], b[1])), dn_mul(a[2], b[2]));
+}
+/* p . a for a constant vector p (in the order p0 a0 + p1 a1 + p2 a2) */
+static dnum dn_dotc(const double *p, const dnum *a)
+{
+    return dn_add(dn_add(dn_mulc(a[0], p[0]), dn_mulc(a[1], p[1])), dn_mulc(a[2], p[2]));
+}
+
+/* Receive directivity (Eq. 13) of a dual angle: 1 up to alpha_m, the linear
+ * ramp to zero at alpha_c (the caller has checked alpha <= alpha_c). */
+static dnum dn_directivity(dnum al, double alpha_m, double alpha_c)
+{
+    if (al.v <= alpha_m) return dn_c(1.0);
+    return dn_divc(dn_sub(dn_c(alpha_c), al), alpha_c - alpha_m);
+}
+
+typedef struct {
+    const octx *C;
+    const double *g;      /* [tx][e][n] adjoint of the binned channel data */
+    int attach;
+    int n_mat;
+    dnum *Z;              /* [n_mat] impedances (tangent m)                       */
+    dnum *ka;             /* [n_mat] attenuation in Np/m (tangent n_mat + m)      */
+    dnum *cen;            /* [n_sph][3] sphere centres (tangent 2 n_mat + 3 j + k) */
+} gctx;
+
+typedef struct {
+    double J;
+    double grad[GRAD_MAX];
+    double *amp;          /* [n_scat] */
+} gacc;
+
+/* One record of dual value c at dual time t into element er of transmit tx;
+ * c_unit (>= 0 index k) is its value per unit amplitude of scatterer k. */
+static void grad_record(const gctx *G, gacc *A, int64_t tx, int64_t er, dnum c, dnum t, int64_t k, double c_unit)
+{
+    const octx *C = G->C;
+    const or_acq *a = C->a;
+    if (!(t.v < C->t_max) || t.v < 0.0) return;
+    const double *ch = G->g + (tx * a->n_elements + er) * a->n_samples;
+    double x = t.v * a->f_s, gv, gs;
+    if (a->binning == 0) {
+        int64_t n = (int64_t)floor(x);
+        gv = (n >= 0 && n < a->n_samples) ? ch[n] : 0.0;
+        gs = 0.0;
+    } else {
+        double tau = x - 0.5, f0 = floor(tau), f = tau - f0;
+        int64_t n0 = (int64_t)f0;
+        double g0 = (n0 >= 0 && n0 < a->n_samples) ? ch[n0] : 0.0;
+        double g1 = (n0 + 1 >= 0 && n0 + 1 < a->n_samples) ? ch[n0 + 1] : 0.0;
+        gv = (1.0 - f) * g0 + f * g1;
+        gs = (g1 - g0) * a->f_s;
+    }
+    A->J += gv * c.v;
+    for (int i = 0; i < g_nt; ++i) A->grad[i] += gv * c.t[i] + gs * c.v * t.t[i];
+    if (k >= 0) A->amp[k] += gv * c_unit;
+}
+
+/* Transmitted fraction 1 - A_r^2 of a straight crossing, in duals. */
+static dnum dn_transmit_fraction(dnum z1, dnum z2, dnum cos_r)
+{
+    dnum eta = dn_div(z1, z2);
+    dnum rad = dn_sub(dn_c(1.0), dn_mul(dn_mul(eta, eta), dn_sub(dn_c(1.0), dn_mul(cos_r, cos_r))));
+    if (rad.v < 0.0) return dn_c(0.0);
+    dnum cos_t = dn_sqrt(rad);
+    dnum den = dn_add(dn_mul(z1, cos_r), dn_mul(z2, cos_t));
+    if (den.v == 0.0) return dn_c(0.0);
+    dnum A = dn_div(dn_sub(dn_mul(z1, cos_r), dn_mul(z2, cos_t)), den);
+    return dn_sub(dn_c(1.0), dn_mul(A, A));
+}
+
+/* Moller-Trumbore distance along (o, d) to triangle v, in duals (the
+ * triangle is fixed); the caller has found the hit by value. */
+static dnum dn_tri_t(const double *v, const dnum *o, const dnum *d)
+{
+    double e1[3], e2[3];
+    sub3(v + 3, v, e1);
+    sub3(v + 6, v, e2);
+    dnum p[3] = {dn_sub(dn_mulc(d[1], e2[2]), dn_mulc(d[2], e2[1])),
+                 dn_sub(dn_mulc(d[2], e2[0]), dn_mulc(d[0], e2[2])),
+                 dn_sub(dn_mulc(d[0], e2[1]), dn_mulc(d[1], e2[0]))};
+    dnum det = dn_add(dn_add(dn_mulc(p[0], e1[0]), dn_mulc(p[1], e1[1])), dn_mulc(p[2], e1[2]));
+    dnum tv[3] = {dn_sub(o[0], dn_c(v[0])), dn_sub(o[1], dn_c(v[1])), dn_sub(o[2], dn_c(v[2]))};
+    dnum q[3] = {dn_sub(dn_mulc(tv[1], e1[2]), dn_mulc(tv[2], e1[1])),
+                 dn_sub(dn_mulc(tv[2], e1[0]), dn_mulc(tv[0], e1[2])),
+                 dn_sub(dn_mulc(tv[0], e1[1]), dn_mulc(tv[1], e1[0]))};
+    return dn_div(dn_dotc(e2, q), det);
+}
+
+/* Secondary ray from q along vh over (EPS_T, dist - EPS_T), as shadow_cast,
+ * in duals: the crossings are found on the values in the same order; each
+ * crossing's distance and normal carry their derivatives.  Returns 0 if a
+ * crossing reflects totally (T = 0). */
+static int grad_shadow(const gctx *G, const dnum *q, const dnum *vh, dnum dist, dnum *T_out, dnum *sa_out,
+                       dnum *sc_out)
+{
+    const octx *C = G->C;
+    const or_scene *sc = C->s;
+    dnum T = dn_c(1.0), sum_a = dn_c(0.0), sum_c = dn_c(0.0);
+    double qv[3] = {q[0].v, q[1].v, q[2].v}, vv[3] = {vh[0].v, vh[1].v, vh[2].v};
+    double lo = EPS_T, hi = dist.v - EPS_T;
+    for (int64_t pid = 0; pid < sc->n_tri + sc->n_sph + sc->n_pln; ++pid) {
+        dnum ts[2], ng[2][3];
+        int nt = 0;
+        int64_t mf, mb;
+        if (pid < sc->n_tri) {
+            double tt;
+            if (tri_isect(sc->tri + 9 * pid, qv, vv, &tt) && tt > lo && tt < hi) {
+                ts[nt] = dn_tri_t(sc->tri + 9 * pid, q, vh);
+                ts[nt].v = tt;
+                double n[3];
+                tri_normal(sc->tri + 9 * pid, n);
+                for (int i = 0; i < 3; ++i) ng[nt][i] = dn_c(n[i]);
+                ++nt;
+            }
+            mf = sc->tri_mat[2 * pid];
+            mb = sc->tri_mat[2 * pid + 1];
+        } else if (pid < sc->n_tri + sc->n_sph) {
+            int64_t j = pid - sc->n_tri;
+            const dnum *c = G->cen + 3 * j;
+            double r = sc->sph[4 * j + 3];
+            dnum oc[3] = {dn_sub(q[0], c[0]), dn_sub(q[1], c[1]), dn_sub(q[2], c[2])};
+            dnum b = dn_dot(oc, vh);
+            dnum cc = dn_sub(dn_dot(oc, oc), dn_c(r * r));
+            dnum disc = dn_sub(dn_mul(b, b), cc);
+            if (disc.v >= 0.0) {
+                dnum sq = dn_sqrt(disc);
+                dnum tr[2] = {dn_sub(dn_neg(b), sq), dn_add(dn_neg(b), sq)};
+                for (int k = 0; k < 2; ++k) {
+                    if (tr[k].v > lo && tr[k].v < hi) {
+                        ts[nt] = tr[k];
+                        for (int i = 0; i < 3; ++i)
+                            ng[nt][i] = dn_divc(dn_sub(dn_add(q[i], dn_mul(tr[k], vh[i])), c[i]), r);
+                        ++nt;
+                    }
+                }
+            }
+            mf = sc->sph_mat[2 * j];
+            mb = sc->sph_mat[2 * j + 1];
+        } else {
+            int64_t p = pid - sc->n_tri - sc->n_sph;
+            const double *pl = sc->pln + 4 * p;
+            double tt;
+            if (pln_isect(pl, qv, vv, &tt) && tt > lo && tt < hi) {
+                ts[nt] = dn_div(dn_sub(dn_c(pl[3]), dn_dotc(pl, q)), dn_dotc(pl, vh));
+                ts[nt].v = tt;
+                for (int i = 0; i < 3; ++i) ng[nt][i] = dn_c(pl[i]);
+                ++nt;
+            }
+            mf = sc->pln_mat[2 * p];
+            mb = sc->pln_mat[2 * p + 1];
+        }
+        for (int c = 0; c < nt; ++c) {
+            dnum dn = dn_dot(vh, ng[c]);
+            int front = dn.v < 0.0;
+            int64_t before = front ? mf : mb, after = front ? mb : mf;
+            T = dn_mul(T, dn_transmit_fraction(G->Z[before], G->Z[after], front ? dn_neg(dn) : dn));
+            dnum rem = dn_sub(dist, ts[c]);
+            sum_a = dn_add(sum_a, dn_mul(dn_sub(G->ka[after], G->ka[before]), rem));
+            sum_c = dn_add(sum_c, dn_mulc(rem, C->inv_c[after] - C->inv_c[before]));
+        }
+    }
+    *T_out = T;
+    *sa_out = sum_a;
+    *sc_out = sum_c;
+    return T.v != 0.0;
+}
+
+/* Capture of scatterer k at dual parameter s along the segment, as
+ * scatter_nee. */
+static void grad_capture(const gctx *G, gacc *A, int64_t tx, int64_t e, uint32_t ray, int64_t seg, int64_t k,
+                         const dnum *o, const dnum *d, dnum w, dnum t, int64_t med)
+{
+    const octx *C = G->C;
+    const or_acq *a = C->a;
+    const double *sk = C->s->scat + 4 * k;
+    dnum p[3] = {dn_sub(dn_c(sk[0]), o[0]), dn_sub(dn_c(sk[1]), o[1]), dn_sub(dn_c(sk[2]), o[2])};
+    dnum s = dn_dot(p, d);
+    dnum q[3] = {dn_add(o[0], dn_mul(s, d[0])), dn_add(o[1], dn_mul(s, d[1])), dn_add(o[2], dn_mul(s, d[2]))};
+    dnum wq = dn_mul(w, dn_exp(dn_neg(dn_mul(G->ka[med], s))));
+    dnum tq = dn_add(t, dn_mulc(s, C->inv_c[med]));
+    double qv[3] = {q[0].v, q[1].v, q[2].v};
+    int64_t e_lo = 0, n_e = a->n_elements;
+    if (a->element_choice == 1 && !or_cone_elements(a, qv, &e_lo, &n_e)) return;
+    uint32_t x[4];
+    draw(C, ray, e, tx, seg, 2, (uint32_t)k, x);
+    int64_t er = e_lo + (int64_t)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
+    dnum v[3] = {dn_sub(dn_c(C->xe[er]), q[0]), dn_sub(dn_c(0.0), q[1]), dn_sub(dn_c(C->ze[er]), q[2])};
+    dnum dist = dn_sqrt(dn_dot(v, v));
+    dnum vh[3] = {dn_div(v[0], dist), dn_div(v[1], dist), dn_div(v[2], dist)};
+    dnum cos_a = a->radius > 0.0 ? dn_neg(dn_add(dn_mulc(vh[0], C->sne[er]), dn_mulc(vh[2], C->cne[er])))
+                                 : dn_neg(vh[2]);
+    dnum al = dn_acos(cos_a);
+    if (!(or_directivity(al.v, a->alpha_m, a->alpha_c) > 0.0)) return;
+    dnum fdir = dn_directivity(al, a->alpha_m, a->alpha_c);
+    dnum T, sum_a, sum_c;
+    if (!grad_shadow(G, q, vh, dist, &T, &sum_a, &sum_c)) return;
+    dnum att = dn_exp(dn_neg(dn_add(dn_mul(G->ka[med], dist), sum_a)));
+    dnum tc = dn_add(dn_add(tq, dn_mulc(dist, C->inv_c[med])), sum_c);
+    double amp = sk[3];
+    /* the same product as scatter_nee, factor by factor */
+    dnum geo = dn_mul(dn_mulc(dist, 4.0 * PI), dist);
+    dnum cu = dn_mulc(dn_mulc(wq, (double)n_e), C->area_e);
+    cu = dn_mul(dn_div(dn_mul(dn_mul(cu, cos_a), fdir), geo), T);
+    cu = dn_mul(cu, att);
+    dnum c = dn_mulc(dn_mulc(dn_mulc(wq, amp), (double)n_e), C->area_e);
+    c = dn_mul(dn_mul(dn_div(dn_mul(dn_mul(c, cos_a), fdir), geo), T), att);
+    grad_record(G, A, tx, er, c, tc, k, cu.v);
+}
+
+/* Dual distance along (o, d) to the primitive the value query chose (its
+ * value is set to the query's). */
+static dnum grad_distance(const gctx *G, const hit *h, const dnum *o, const dnum *d)
+{
+    const octx *C = G->C;
+    const or_scene *s = C->s;
+    dnum th;
+    if (h->id == C->id_box && h->face == 6) {
+        double R = C->a->radius;
+        dnum aa = dn_add(dn_mul(d[0], d[0]), dn_mul(d[2], d[2]));
+        dnum b = dn_add(dn_mul(o[0], d[0]), dn_mul(dn_add(o[2], dn_c(R)), d[2]));
+        dnum c = dn_add(dn_mul(o[0], o[0]), dn_mul(o[2], dn_add(o[2], dn_c(2.0 * R))));
+        th = dn_div(c, dn_add(dn_neg(b), dn_sqrt(dn_sub(dn_mul(b, b), dn_mul(aa, c)))));
+    } else if (h->id == C->id_box) {
+        int ax = h->face % 3;
+        th = dn_div(dn_sub(dn_c(s->box[h->face]), o[ax]), d[ax]);
+    } else if (h->id < C->id_sph0) {
+        th = dn_tri_t(s->tri + 9 * h->id, o, d);
+    } else if (h->id < C->id_pln0) {
+        int64_t j = h->id - C->id_sph0;
+        const dnum *c = G->cen + 3 * j;
+        double r = s->sph[4 * j + 3];
+        dnum oc[3] = {dn_sub(o[0], c[0]), dn_sub(o[1], c[1]), dn_sub(o[2], c[2])};
+        dnum b = dn_dot(oc, d);
+        dnum sq = dn_sqrt(dn_sub(dn_mul(b, b), dn_sub(dn_dot(oc, oc), dn_c(r * r))));
+        dnum t0 = dn_sub(dn_neg(b), sq);
+        th = t0.v > EPS_T ? t0 : dn_add(dn_neg(b), sq);
+    } else {
+        const double *pl = s->pln + 4 * (h->id - C->id_pln0);
+        th = dn_div(dn_sub(dn_c(pl[3]), dn_dotc(pl, o)), dn_dotc(pl, d));
+    }
+    th.v = h->t;
+    return th;
+}
+
+/* Replays one path of trace_path with dual numbers (smooth boundaries). */
+static void grad_path(const gctx *G, gacc *A, int64_t tx, int64_t e, uint32_t ray, const double o_in[3],
+                      const double d_in[3], double w0, double t0, int64_t med)
+{
+    const octx *C = G->C;
+    const or_acq *a = C->a;
+    const or_scene *sc = C->s;
+    dnum o[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        o[i] = dn_c(o_in[i]);
+        d[i] = dn_c(d_in[i]);
+    }
+    dnum w = dn_c(w0), t = dn_c(t0), len = dn_c(0.0);
+    int64_t last = -1;
+    double r2 = a->r_s * a->r_s;
+    for (int64_t b = 0; b <= a->max_bounces; ++b) {
+        double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
+        hit h = closest(C, ov, dv, last);
+        dnum tseg = grad_distance(G, &h, o, d);
+        int clipped = 0;
+        if (len.v + tseg.v > a->max_path) {
+            tseg = dn_sub(dn_c(a->max_path), len);
+            clipped = 1;
+        }
+        /* captures on [0, tseg), decided on the values as scatter_events */
+        for (int64_t k = 0; k < sc->n_scat; ++k) {
+            double p[3];
+            sub3(sc->scat + 4 * k, ov, p);
+            double sv = dot3(p, dv);
+            if (!(sv >= 0.0 && sv < tseg.v)) continue;
+            double perp[3] = {p[0] - sv * dv[0], p[1] - sv * dv[1], p[2] - sv * dv[2]};
+            if (dot3(perp, perp) > r2) continue;
+            grad_capture(G, A, tx, e, ray, b, k, o, d, w, t, med);
+        }
+        w = dn_mul(w, dn_exp(dn_neg(dn_mul(G->ka[med], tseg))));
+        t = dn_add(t, dn_mulc(tseg, C->inv_c[med]));
+        len = dn_add(len, tseg);
+        for (int i = 0; i < 3; ++i) o[i] = dn_add(o[i], dn_mul(tseg, d[i]));
+        if (clipped || t.v >= C->t_max) return;
+        if (h.id == C->id_box) {
+            int64_t er = -1;
+            dnum ca;
+            if (h.face == 6 && fabs(o[1].v) <= 0.5 * a->elevation) {
+                double ph = atan2(o[0].v, o[2].v + a->radius);
+                if (fabs(ph) <= C->half_arc) {
+                    er = (int64_t)floor(ph / C->dphi + 0.5 * (double)a->n_elements);
+                    if (er < 0) er = 0;
+                    if (er > a->n_elements - 1) er = a->n_elements - 1;
+                    ca = dn_neg(dn_add(dn_mulc(d[0], C->sne[er]), dn_mulc(d[2], C->cne[er])));
+                }
+            }
+            if (a->radius == 0.0 && h.face == 2 && fabs(o[0].v) <= C->half_ap &&
+                fabs(o[1].v) <= 0.5 * a->elevation) {
+                er = (int64_t)floor((o[0].v + C->half_ap) / a->pitch);
+                if (er < 0) er = 0;
+                if (er > a->n_elements - 1) er = a->n_elements - 1;
+                ca = dn_neg(d[2]);
+            }
+            if (er >= 0) {
+                dnum al = dn_acos(ca);
+                if (or_directivity(al.v, a->alpha_m, a->alpha_c) > 0.0)
+                    grad_record(G, A, tx, er, dn_mul(w, dn_directivity(al, a->alpha_m, a->alpha_c)), t, -1, 0.0);
+            }
+            return;
+        }
+        if (b == a->max_bounces) return;
+        /* impedance boundary, Eqs. 7-11 as fresnel_step */
+        dnum ng[3];
+        int64_t mf, mb;
+        if (h.id < C->id_sph0) {
+            double n[3];
+            tri_normal(sc->tri + 9 * h.id, n);
+            for (int i = 0; i < 3; ++i) ng[i] = dn_c(n[i]);
+            mf = sc->tri_mat[2 * h.id];
+            mb = sc->tri_mat[2 * h.id + 1];
+        } else if (h.id < C->id_pln0) {
+            int64_t j = h.id - C->id_sph0;
+            for (int i = 0; i < 3; ++i) ng[i] = dn_divc(dn_sub(o[i], G->cen[3 * j + i]), sc->sph[4 * j + 3]);
+            mf = sc->sph_mat[2 * j];
+            mb = sc->sph_mat[2 * j + 1];
+        } else {
+            const double *pl = sc->pln + 4 * (h.id - C->id_pln0);
+            for (int i = 0; i < 3; ++i) ng[i] = dn_c(pl[i]);
+            mf = sc->pln_mat[2 * (h.id - C->id_pln0)];
+            mb = sc->pln_mat[2 * (h.id - C->id_pln0) + 1];
+        }
+        int64_t before, after;
+        if (dn_dot(d, ng).v < 0.0) {
+            before = mf;
+            after = mb;
+        } else {
+            before = mb;
+            after = mf;
+            for (int i = 0; i < 3; ++i) ng[i] = dn_neg(ng[i]);
+        }
+        dnum z1 = G->Z[before], z2 = G->Z[after];
+        dnum cos_r = dn_neg(dn_dot(d, ng));
+        dnum eta = dn_div(z1, z2);
+        dnum rad = dn_sub(dn_c(1.0), dn_mul(dn_mul(eta, eta), dn_sub(dn_c(1.0), dn_mul(cos_r, cos_r))));
+        dnum R = dn_c(1.0), cos_t = dn_c(0.0);
+        if (rad.v >= 0.0) {
+            cos_t = dn_sqrt(rad);
+            dnum den = dn_add(dn_mul(z1, cos_r), dn_mul(z2, cos_t));
+            if (den.v != 0.0) {
+                dnum Ar = dn_div(dn_sub(dn_mul(z1, cos_r), dn_mul(z2, cos_t)), den);
+                R = dn_mul(Ar, Ar);
+            }
+        }
+        uint32_t x[4];
+        draw(C, ray, e, tx, b, 1, 0, x);
+        double y = unif(x[0]);
+        dnum nd[3];
+        if (y < R.v) {
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(d[i], dn_mul(dn_mulc(cos_r, 2.0), ng[i]));
+            if (G->attach) w = dn_mul(w, dn_divc(R, R.v));
+            med = before;
+        } else {
+            dnum f = dn_sub(dn_mul(eta, cos_r), cos_t);
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(dn_mul(eta, d[i]), dn_mul(f, ng[i]));
+            dnum Tr = dn_sub(dn_c(1.0), R);
+            if (G->attach) w = dn_mul(w, dn_divc(Tr, Tr.v));
+            med = after;
+        }
+        dnum l = dn_sqrt(dn_dot(nd, nd));
+        for (int i = 0; i < 3; ++i) d[i] = dn_div(nd[i], l);
+        last = (h.id < C->id_sph0 || h.id >= C->id_pln0) ? h.id : -1;
+    }
+}
+
+/* Emitted rays (every ray_stride-th of each row, rays == NULL) or the n_rays
+ * explicit rays. */
+static int grad_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const or_ray *rays,
+                     int64_t n_rays, const double *g, int attach_choice, double *J, double *grad_z,
+                     double *grad_alpha, double *grad_sph, double *grad_amp)
+{
+    if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
+        a->rays_per_element < 0 || a->max_bounces < 0 || ray_stride <= 0 || !g || a->cdf != NULL ||
+        (a->scheme == 1 && a->n_tx != a->n_elements))
+        return -1;
+    if (2 * s->n_mat + 3 * s->n_sph > GRAD_MAX) return -1;
+    if (s->rough)
+        for (int64_t m = 0; m < s->n_mat; ++m)
+            if (s->rough[m] > 0.0) return -3;
+    octx C;
+    int rc_init = ctx_init(&C, a, s);
+    if (rc_init) {
+        ctx_free(&C);
+        return rc_init;
+    }
+    g_nt = (int)(2 * s->n_mat + 3 * s->n_sph);
+    gctx G;
+    G.C = &C;
+    G.g = g;
+    G.attach = attach_choice;
+    G.n_mat = (int)s->n_mat;
+    G.Z = (dnum *)malloc(sizeof(dnum) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    G.ka = (dnum *)malloc(sizeof(dnum) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    G.cen = (dnum *)malloc(sizeof(dnum) * (size_t)(3 * s->n_sph + 1));
+    double kappa = (a->f_c * 1e-6) * 100.0 * log(10.0) / 20.0;   /* d ka / d alpha */
+    for (int64_t m = 0; m < s->n_mat; ++m) {
+        G.Z[m] = dn_c(s->mat[3 * m]);
+        G.Z[m].t[m] = 1.0;
+        G.ka[m] = dn_c(C.ka[m]);
+        G.ka[m].t[s->n_mat + m] = kappa;
+    }
+    for (int64_t j = 0; j < s->n_sph; ++j)
+        for (int k = 0; k < 3; ++k) {
+            G.cen[3 * j + k] = dn_c(s->sph[4 * j + k]);
+            G.cen[3 * j + k].t[2 * s->n_mat + 3 * j + k] = 1.0;
+        }
+    int nt = n_threads;
+#ifdef _OPENMP
+    if (nt <= 0) nt = omp_get_max_threads();
+#else
+    nt = 1;
+#endif
+    if (nt < 1) nt = 1;
+    gacc *acc = (gacc *)calloc((size_t)nt, sizeof(gacc));
+    for (int i = 0; i < nt; ++i) acc[i].amp = (double *)calloc((size_t)(s->n_scat > 0 ? s->n_scat : 1), sizeof(double));
+    int64_t per_el = (a->rays_per_element + ray_stride - 1) / ray_stride;
+    int64_t n_work = rays ? n_rays : (a->scheme == 1 ? 1 : a->n_tx) * a->n_elements * per_el;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+#endif
+    for (int64_t i = 0; i < n_work; ++i) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        if (rays) {
+            const or_ray *r = &rays[i];
+            grad_path(&G, &acc[tid], r->tx, r->elem, (uint32_t)r->ray, r->o, r->d, r->w, r->t, r->medium);
+            continue;
+        }
+        int64_t rr = (i % per_el) * ray_stride;
+        int64_t e = (i / per_el) % a->n_elements;
+        int64_t tx = a->scheme == 1 ? e : i / (per_el * a->n_elements);
+        double o[3], d[3], w;
+        int64_t cell = -1;
+        emit(&C, tx, e, (uint32_t)rr, o, d, &w, &cell);
+        grad_path(&G, &acc[tid], tx, e, (uint32_t)rr, o, d, w, C.tau[tx * a->n_elements + e], s->top_medium);
+    }
+    /* fixed-order merge */
+    double Jt = 0.0, gt[GRAD_MAX];
+    memset(gt, 0, sizeof(gt));
+    if (grad_amp) memset(grad_amp, 0, sizeof(double) * (size_t)s->n_scat);
+    for (int i = 0; i < nt; ++i) {
+        Jt += acc[i].J;
+        for (int k = 0; k < g_nt; ++k) gt[k] += acc[i].grad[k];
+        if (grad_amp)
+            for (int64_t k = 0; k < s->n_scat; ++k) grad_amp[k] += acc[i].amp[k];
+        free(acc[i].amp);
+    }
+    free(acc);
+    if (J) *J = Jt;
+    for (int64_t m = 0; m < s->n_mat; ++m) {
+        if (grad_z) grad_z[m] = gt[m];
+        if (grad_alpha) grad_alpha[m] = gt[s->n_mat + m];
+    }
+    if (grad_sph)
+        for (int64_t j = 0; j < 3 * s->n_sph; ++j) grad_sph[j] = gt[2 * s->n_mat + j];
+    free(G.Z);
+    free(G.ka);
+    free(G.cen);
+    ctx_free(&C);
+    return 0;
+}
+
+int or_trace_grad(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const double *g,
+                  int attach_choice, double *J, double *grad_z, double *grad_alpha, double *grad_sph,
+                  double *grad_amp)
+{
+    return grad_impl(a, s, n_threads, ray_stride, NULL, 0, g, attach_choice, J, grad_z, grad_alpha, grad_sph,
+                     grad_amp);
+}
+
+int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n, const double *g,
+                       int attach_choice, double *J, double *grad_z, double *grad_alpha, double *grad_sph,
+                       double *grad_amp)
+{
+    if (n < 0 || (n > 0 && !rays)) return -1;
+    return grad_impl(a, s, 1, 1, rays, n, g, attach_choice, J, grad_z, grad_alpha, grad_sph, grad_amp);
+}
+
 /* ---------------------------------------------------------------- pulse Eq. 14 */
 /* Analytic pulse h[m] = g(m/fs) (sin(2 pi fc m/fs) - i cos(2 pi fc m/fs)),
  * whose real part is Eq. 14 with the Gaussian written exp(-t^2/(2 sigma^2));

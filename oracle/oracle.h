@@ -87,6 +87,20 @@ int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_
 int or_trace_subset(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride,
                     double *ch_raw, double *rec_hist, or_stats *st);
 
+/* Forward-mode gradient of J = sum over records of g(t) c (g [n_tx][E][S]
+ * the adjoint of the binned channel data) along the same paths as
+ * or_trace_subset: grad_z, grad_alpha [n_mat], grad_sph [n_sph][3],
+ * grad_amp [n_scat] (each nullable), J the value.  attach_choice 0 freezes
+ * the reflect-or-transmit choice; 1 adds the derivative of its probability.
+ * Returns -3 for rough boundaries, -1 for bad arguments. */
+int or_trace_grad(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const double *g,
+                  int attach_choice, double *J, double *grad_z, double *grad_alpha, double *grad_sph,
+                  double *grad_amp);
+
+/* The same for explicit rays (as or_trace_rays). */
+int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n, const double *g,
+                       int attach_choice, double *J, double *grad_z, double *grad_alpha, double *grad_sph,
+                       double *grad_amp);
 int or_pulse_taps(const or_acq *a, double *taps, int64_t cap);   /* returns K, taps [2K+1][2] */
 int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf);
 /* Plane waves synthesised from synthetic-aperture data ch_sa [E][E][S]:

@@ -89,6 +89,10 @@ def lib():
                                       P(Stats)]
         L.or_trace_rays.argtypes = [P(Acq), P(SceneS), P(Ray), C.c_int64, P(Event), C.c_int64,
                                     P(C.c_int64), P(C.c_double), P(Stats)]
+        grad_args = [P(C.c_double), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double),
+                     P(C.c_double)]
+        L.or_trace_grad.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64] + grad_args
+        L.or_trace_rays_grad.argtypes = [P(Acq), P(SceneS), P(Ray), C.c_int64] + grad_args
         L.or_pulse_taps.argtypes = [P(Acq), P(C.c_double), C.c_int64]
         L.or_pulse.argtypes = [P(Acq), C.c_int64, P(C.c_double), P(C.c_double)]
         L.or_das.argtypes = [P(Acq), C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -248,6 +252,43 @@ def trace_rays(workload, rays, cap=4096, seed=None, with_hist=False):
                    t=ev[i].t, value=ev[i].value, pos=(ev[i].x, ev[i].y, ev[i].z))
               for i in range(min(n_ev.value, cap))]
     return events, st.as_dict(), hist
+
+
+def _ray_array(workload, rays):
+    arr = (Ray * max(1, len(rays)))()
+    for i, r in enumerate(rays):
+        arr[i].o[:] = list(map(float, r["o"]))
+        arr[i].d[:] = list(map(float, r["d"]))
+        arr[i].w = float(r.get("w", 1.0))
+        arr[i].t = float(r.get("t", 0.0))
+        arr[i].tx = int(r.get("tx", 0))
+        arr[i].elem = int(r.get("elem", 0))
+        arr[i].ray = int(r.get("ray", 0))
+        arr[i].medium = int(r.get("medium", workload.scene.top_medium))
+    return arr
+
+
+def trace_grad(workload, g, attach_choice=False, ray_stride=1, n_threads=0, seed=None, rays=None):
+    """Forward-mode gradient of J = sum g(t) c over the records of the same
+    paths as trace(..., ray_stride) (or of explicit `rays`): returns
+    dict(J, z [n_mat], alpha [n_mat], sph [n_sph][3], amp [n_scat])."""
+    keep = _Keep()
+    acq, sc = workload.acq, workload.scene
+    a = make_acq(acq, workload.seed if seed is None else seed, keep)
+    s = make_scene(sc, keep)
+    gg = keep.f64(np.ascontiguousarray(g, np.float64).reshape(acq.n_tx, acq.n_elements, acq.n_samples))
+    nm, ns, nk = len(sc.materials), len(sc.sph), len(sc.scat)
+    J = C.c_double()
+    gz, ga, gs, gk = np.zeros(nm), np.zeros(nm), np.zeros((ns, 3)), np.zeros(max(nk, 1))
+    tail = [_dp(gg), int(bool(attach_choice)), C.byref(J), _dp(gz), _dp(ga), _dp(gs), _dp(gk)]
+    if rays is None:
+        rc = lib().or_trace_grad(C.byref(a), C.byref(s), int(n_threads), int(ray_stride), *tail)
+    else:
+        arr = _ray_array(workload, rays)
+        rc = lib().or_trace_rays_grad(C.byref(a), C.byref(s), arr, len(rays), *tail)
+    if rc != 0:
+        raise RuntimeError(f"or_trace_grad failed ({rc})")
+    return dict(J=J.value, z=gz, alpha=ga, sph=gs, amp=gk[:nk])
 
 
 def pulse_taps(acq):
