@@ -16,6 +16,12 @@ The attached choice probability (the default) adds a score term whose mean
 is the derivative of the expected data; it is checked statistically against
 common-random-number differences of the GPU forward over many seeds in a
 scene where only that term is non-zero.
+
+Every gradient is also compared element by element with the oracle's FP64
+forward-mode gradient of the same paths (or_trace_grad, pinned on the CPU
+against finite differences of the oracle's forward trace): the small scene
+(frozen and attached choice), a convex array, the bone phantom, and the
+differentiable large scene at full size on a stride sample.
 """
 import dataclasses
 import math
@@ -294,6 +300,101 @@ def test_trace_adjoint_convex_array(oracle, torch_gpu):
         checked += 1
         assert abs(gs[c] - fd) <= 1e-4 * max(np.max(np.abs(gs)), abs(fd))
     assert checked >= nm + 1
+
+
+# ------------------------------------------------ against the FP64 oracle gradient
+def _gpu_grads(s, w, gt, stride=1, frozen=True):
+    import torch
+    sc = w.scene
+    nm, ns, K = len(sc.materials), len(sc.sph), len(sc.scat)
+    Z = torch.empty(nm, dtype=torch.float64, device="cuda")
+    al = torch.empty(nm, dtype=torch.float64, device="cuda")
+    cg = torch.empty((ns, 3), dtype=torch.float64, device="cuda") if ns else None
+    ag = torch.empty(K, device="cuda") if K else None
+    v = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.ctx.ur_trace_adjoint(w.seed, gt, amp=ag, alpha=al, Z=Z, sph_center=cg, value=v, frozen_choice=frozen,
+                           ray_stride=stride)
+    return dict(J=float(v.item()), z=Z.cpu().numpy(), alpha=al.cpu().numpy(),
+                sph=cg.cpu().numpy() if ns else np.zeros((0, 3)),
+                amp=ag.double().cpu().numpy() if K else np.zeros(0))
+
+
+def _assert_matches_oracle(got, ref, label):
+    """Element by element: the FP64 families (impedance, attenuation, sphere
+    centre; accumulated in FP64 on both sides, in another order) within 1e-8
+    of their largest oracle entry, the amplitude gradients (FP32 atomics on
+    the GPU) within 1e-6; entries the oracle leaves exactly zero (no replayed
+    path depends on them) are exactly zero on the GPU too."""
+    print(f"[adjoint-oracle] {label}: J gpu {got['J']:.12e} oracle {ref['J']:.12e}", flush=True)
+    assert abs(got["J"] - ref["J"]) <= 1e-9 * abs(ref["J"]) + 1e-300
+    for key, tol in (("z", 1e-8), ("alpha", 1e-8), ("sph", 1e-8), ("amp", 1e-6)):
+        a, b = np.asarray(got[key]).ravel(), np.asarray(ref[key]).ravel()
+        assert a.shape == b.shape
+        if b.size == 0:
+            continue
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        print(f"[adjoint-oracle] {label}: {key} max|oracle| {scale:.4e} max err {err:.3e} "
+              f"nonzero {np.count_nonzero(b)}/{b.size}", flush=True)
+        assert np.array_equal(a[b == 0], b[b == 0]), key
+        assert err <= tol * scale, (key, err, scale)
+
+
+@pytest.mark.parametrize("frozen", [True, False])
+def test_trace_adjoint_matches_oracle_gradient(oracle, tiny_adj, frozen):
+    """Every gradient of the small scene (6 impedances and attenuations,
+    3 sphere-centre coordinates, 2000 amplitudes) and J itself against the
+    oracle's forward-mode gradient of the same paths, with the choice frozen
+    and attached."""
+    torch, w, g, s, gt = tiny_adj
+    got = _gpu_grads(s, w, gt, frozen=frozen)
+    ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=not frozen)
+    assert np.count_nonzero(ref["sph"]) == 3 and np.count_nonzero(ref["amp"]) > 100
+    _assert_matches_oracle(got, ref, f"tiny frozen={frozen}")
+
+
+def test_trace_adjoint_matches_oracle_gradient_convex(oracle, torch_gpu):
+    w = scenes.convex_probe(_workload(), 20e-3)
+    g = _smooth_adjoint((w.acq.n_tx, w.acq.n_elements, w.acq.n_samples), 23)
+    s = _sim(w)
+    got = _gpu_grads(s, w, torch_gpu.from_numpy(g).cuda(), frozen=False)
+    ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=True)
+    assert np.count_nonzero(ref["alpha"]) > 0
+    _assert_matches_oracle(got, ref, "convex")
+
+
+def test_trace_adjoint_matches_oracle_gradient_bone_reduced(oracle, torch_gpu):
+    """Bone phantom (60k-triangle tube, three slabs, 50k scatterers), 11
+    plane waves, 6 rays per element, linear binning."""
+    w = scenes.bone(rays_per_element=6)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, binning=scenes.LINEAR))
+    g = _smooth_adjoint((w.acq.n_tx, w.acq.n_elements, w.acq.n_samples), 24)
+    s = _sim(w)
+    got = _gpu_grads(s, w, torch_gpu.from_numpy(g).cuda(), frozen=False)
+    ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=True)
+    assert np.count_nonzero(ref["z"]) >= 3
+    _assert_matches_oracle(got, ref, "bone-reduced")
+
+
+def test_large_scene_gradient_matches_oracle(oracle, torch_gpu):
+    """The differentiable large scene at full size (192 elements, 21 plane
+    waves, two 250k-triangle tubes, 4 spheres, 1e6 scatterers, linear
+    binning) on a stride sample the oracle can replay (every 8268th ray of
+    each (transmit, element) row, 15 rays per row): J, all 6 impedances, all 6
+    attenuations, all 12 sphere-centre coordinates (frozen choice) and all
+    1e6 amplitude gradients, element by element, against the oracle's
+    forward-mode gradient of the same paths."""
+    w = scenes.large()
+    stride = 8268
+    A = w.acq
+    g = _smooth_adjoint((A.n_tx, A.n_elements, A.n_samples), 41)
+    s = _sim(w)
+    print("[adjoint-oracle] large: GPU replay", flush=True)
+    got = _gpu_grads(s, w, torch_gpu.from_numpy(g).cuda(), stride=stride, frozen=True)
+    print("[adjoint-oracle] large: oracle replay", flush=True)
+    ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=False, ray_stride=stride)
+    assert np.count_nonzero(ref["amp"]) >= 150 and np.count_nonzero(ref["alpha"]) >= 3
+    _assert_matches_oracle(got, ref, "large")
 
 
 def test_choice_probability_term_is_unbiased(torch_gpu):
