@@ -372,6 +372,59 @@ def rough_nee_experiment(args):
                       "reference_rays_per_tx": args.ref_rays_per_tx, "efficiency_gain": gains, "curves": curves}))
 
 
+def binning_experiment(args):
+    """Records per frame and trace time of the bone frame under four receive
+    configurations: the uniform and the cone-restricted element choice at the
+    2-degree cone, the cone choice with a trained proposal, and a 45-degree
+    receive cone (alpha_m 15 degrees) with either choice.  Each record is one
+    float atomic into the channel data (two with linear binning)."""
+    import dataclasses
+    import math
+
+    import torch
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.proposal import Proposal
+    from paper_2501_05828_amd.sim import Simulator
+
+    w0 = scenes.bone()
+    base = w0.acq
+    wide = dict(alpha_m=math.radians(15), alpha_c=math.radians(45))
+    cfgs = [("uniform", base), ("cone", dataclasses.replace(base, element_choice=scenes.ELEMENT_CONE)),
+            ("cone_learned", dataclasses.replace(base, element_choice=scenes.ELEMENT_CONE)),
+            ("uniform_45deg", dataclasses.replace(base, **wide)),
+            ("cone_45deg", dataclasses.replace(base, element_choice=scenes.ELEMENT_CONE, **wide))]
+    sim = Simulator(w0)
+
+    def timed(seed):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sim.trace(seed=seed, pulse=False)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    out = {}
+    for name, acq in cfgs:
+        sim.set_acquisition(acq)
+        prop = None
+        if name == "cone_learned":
+            prop = Proposal(sim)
+            prop.record(8, cap=1 << 26, cost_aware=True)
+            prop.train(steps=2000)
+            prop.enable(0.1)
+        st = sim.trace(seed=5, stats=True, pulse=False)
+        timed(6)
+        ts = [timed(7 + i) for i in range(5)]
+        xm, sm, nm, _ = sim.ctx.ur_last_trace_kernels_ms()
+        out[name] = {"records_per_frame": st["records"], "trace_ms": sum(ts) / len(ts), "extend_ms": xm,
+                     "scatter_ms": sm, "secondary_ray_ms": nm}
+        if prop is not None:
+            prop.disable()
+        print(f"[binning] {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+    print(json.dumps({"experiment": "binning", "workload": "bone", "configs": out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,8 +433,10 @@ def main():
     ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex", "bone_rough", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=150000)
-    ap.add_argument("--experiment", choices=["learned", "rough-nee"], default=None,
-                    help="learned: channel MSE vs GPU time, learned vs uniform emission; rough-nee: with vs 'without transducer sampling at the rough bone")
+    ap.add_argument("--experiment", choices=["learned", "rough-nee", "binning"], default=None,
+                    help="learned: channel MSE vs GPU time, learned vs uniform emission; rough-nee: with vs "
+                         "without transducer sampling at the rough bone; binning: records per frame and trace time "
+                         "under four receive configurations")
     ap.add_argument("--ref-rays-per-tx", type=float, default=1e9)
     ap.add_argument("--ref-parts", type=int, default=10)
     ap.add_argument("--record-traces", type=int, default=8)
@@ -417,6 +472,9 @@ def main():
         return
     if args.experiment == "rough-nee":
         rough_nee_experiment(args)
+        return
+    if args.experiment == "binning":
+        binning_experiment(args)
         return
     if args.c3_only:
         print(json.dumps(c3_measure()))
