@@ -1297,7 +1297,11 @@ int or_trace_rays(const or_acq *a, const or_scene *s, const or_ray *rays, int64_
  * result estimates the derivative of the expected data.  Geometry enters
  * through interior derivatives only: a capture, an element or an aperture
  * edge that appears or disappears under a change contributes no term.
- * Rough boundaries are not supported (returns -3). */
+ * Rough boundaries (Eq. 12) are replayed with the estimator that receives
+ * their echoes by direct hits only (rough_direct_only = 1): the microfacet
+ * normal follows the dual macro normal for the same random numbers, and the
+ * weight factor is differentiated with it.  With transducer sampling at
+ * rough boundaries the call returns -3. */
 #define GRAD_MAX 64
 
 static int g_nt;   /* number of active tangent directions (set before a replay) */
@@ -1631,7 +1635,35 @@ static dnum grad_distance(const gctx *G, const hit *h, const dnum *o, const dnum
     return th;
 }
 
-/* Replays one path of trace_path with dual numbers (smooth boundaries). */
+/* Smith masking G1 of the GGX distribution at a dual cos(theta_v) (as
+ * or_ggx_g1). */
+static dnum dn_ggx_g1(double alpha, dnum cv)
+{
+    dnum c2 = dn_mul(cv, cv);
+    dnum tan2 = dn_div(dn_sub(dn_c(1.0), c2), c2);
+    return dn_div(dn_c(2.0), dn_add(dn_c(1.0), dn_sqrt(dn_add(dn_c(1.0), dn_mulc(tan2, alpha * alpha)))));
+}
+
+/* Microfacet normal of or_ggx_sample about a dual unit normal n: the
+ * random numbers fix the polar and azimuthal angles about n, the basis
+ * (or_onb) follows n. */
+static void dn_ggx_sample(const dnum *n, double alpha, double xi1, double xi2, dnum *h)
+{
+    double sg = copysign(1.0, n[2].v);
+    dnum a = dn_div(dn_c(-1.0), dn_add(dn_c(sg), n[2]));
+    dnum c = dn_mul(dn_mul(n[0], n[1]), a);
+    dnum t[3] = {dn_add(dn_c(1.0), dn_mul(dn_mul(dn_mulc(n[0], sg), n[0]), a)), dn_mulc(c, sg), dn_mulc(n[0], -sg)};
+    dnum b[3] = {c, dn_add(dn_c(sg), dn_mul(dn_mul(n[1], n[1]), a)), dn_neg(n[1])};
+    double q = 1.0 - xi1 + alpha * alpha * xi1;
+    double ct = sqrt((1.0 - xi1) / q), st = alpha * sqrt(xi1 / q);
+    double ph = 2.0 * PI * xi2;
+    double cp = cos(ph), sp = sin(ph);
+    for (int i = 0; i < 3; ++i)
+        h[i] = dn_add(dn_add(dn_mulc(t[i], st * cp), dn_mulc(b[i], st * sp)), dn_mulc(n[i], ct));
+}
+
+/* Replays one path of trace_path with dual numbers (smooth boundaries, and
+ * rough ones without their secondary rays). */
 static void grad_path(const gctx *G, gacc *A, int64_t tx, int64_t e, uint32_t ray, const double o_in[3],
                       const double d_in[3], double w0, double t0, int64_t med)
 {
@@ -1727,7 +1759,21 @@ static void grad_path(const gctx *G, gacc *A, int64_t tx, int64_t e, uint32_t ra
             for (int i = 0; i < 3; ++i) ng[i] = dn_neg(ng[i]);
         }
         dnum z1 = G->Z[before], z2 = G->Z[after];
-        dnum cos_r = dn_neg(dn_dot(d, ng));
+        uint32_t x[4];
+        draw(C, ray, e, tx, b, 1, 0, x);
+        double y = unif(x[0]);
+        double alpha = 0.0;
+        if (sc->rough) alpha = sc->rough[mf] > sc->rough[mb] ? sc->rough[mf] : sc->rough[mb];
+        dnum mn[3] = {ng[0], ng[1], ng[2]}, cn = dn_c(1.0);
+        if (alpha > 0.0) {
+            /* rough boundary (as rough_step): Eqs. 7-11 about the microfacet
+             * normal drawn with the second and third words */
+            dn_ggx_sample(ng, alpha, unif(x[1]), unif(x[2]), mn);
+            dnum ci = dn_neg(dn_dot(d, mn));
+            cn = dn_neg(dn_dot(d, ng));
+            if (!(ci.v > 0.0)) return;
+        }
+        dnum cos_r = dn_neg(dn_dot(d, mn));
         dnum eta = dn_div(z1, z2);
         dnum rad = dn_sub(dn_c(1.0), dn_mul(dn_mul(eta, eta), dn_sub(dn_c(1.0), dn_mul(cos_r, cos_r))));
         dnum R = dn_c(1.0), cos_t = dn_c(0.0);
@@ -1739,23 +1785,33 @@ static void grad_path(const gctx *G, gacc *A, int64_t tx, int64_t e, uint32_t ra
                 R = dn_mul(Ar, Ar);
             }
         }
-        uint32_t x[4];
-        draw(C, ray, e, tx, b, 1, 0, x);
-        double y = unif(x[0]);
         dnum nd[3];
-        if (y < R.v) {
-            for (int i = 0; i < 3; ++i) nd[i] = dn_add(d[i], dn_mul(dn_mulc(cos_r, 2.0), ng[i]));
+        int refl = y < R.v;
+        if (refl) {
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(d[i], dn_mul(dn_mulc(cos_r, 2.0), mn[i]));
+        } else {
+            dnum f = dn_sub(dn_mul(eta, cos_r), cos_t);
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(dn_mul(eta, d[i]), dn_mul(f, mn[i]));
+        }
+        dnum l = dn_sqrt(dn_dot(nd, nd));
+        for (int i = 0; i < 3; ++i) nd[i] = dn_div(nd[i], l);
+        if (alpha > 0.0) {
+            /* wrong side of the macro surface: absorbed; else the weight
+             * factor ci G1(i) G1(o) / (cn (mn.n)) */
+            dnum co = dn_dot(nd, ng);
+            if (refl ? !(co.v > 0.0) : !(co.v < 0.0)) return;
+            dnum wf = dn_mul(dn_mul(cos_r, dn_ggx_g1(alpha, cn)), dn_ggx_g1(alpha, co.v < 0.0 ? dn_neg(co) : co));
+            w = dn_mul(w, dn_div(wf, dn_mul(cn, dn_dot(mn, ng))));
+        }
+        if (refl) {
             if (G->attach) w = dn_mul(w, dn_divc(R, R.v));
             med = before;
         } else {
-            dnum f = dn_sub(dn_mul(eta, cos_r), cos_t);
-            for (int i = 0; i < 3; ++i) nd[i] = dn_add(dn_mul(eta, d[i]), dn_mul(f, ng[i]));
             dnum Tr = dn_sub(dn_c(1.0), R);
             if (G->attach) w = dn_mul(w, dn_divc(Tr, Tr.v));
             med = after;
         }
-        dnum l = dn_sqrt(dn_dot(nd, nd));
-        for (int i = 0; i < 3; ++i) d[i] = dn_div(nd[i], l);
+        for (int i = 0; i < 3; ++i) d[i] = nd[i];
         last = (h.id < C->id_sph0 || h.id >= C->id_pln0) ? h.id : -1;
     }
 }
@@ -1771,7 +1827,7 @@ static int grad_impl(const or_acq *a, const or_scene *s, int n_threads, int64_t 
         (a->scheme == 1 && a->n_tx != a->n_elements))
         return -1;
     if (2 * s->n_mat + 3 * s->n_sph > GRAD_MAX) return -1;
-    if (s->rough)
+    if (s->rough && !a->rough_direct_only)
         for (int64_t m = 0; m < s->n_mat; ++m)
             if (s->rough[m] > 0.0) return -3;
     octx C;
