@@ -465,7 +465,12 @@ typedef struct ur_grad_desc {
  * sample centres) is non-zero only with linear binning.  Amplitude and
  * attenuation gradients come from one replay; every impedance and every
  * sphere coordinate takes one forward-mode (dual number) replay.  The same
- * proposal tables as the forward call must be set.  Async on `stream`. */
+ * proposal tables as the forward call must be set.  Rough boundaries
+ * (Eq. 12) are supported when their echoes are received by direct hits only
+ * (ur_acq_desc.rough_direct_only = 1): the GGX microfacet normal follows the
+ * dual macro normal for the same random numbers and its weight factor is
+ * differentiated; with transducer sampling at rough boundaries the call
+ * returns UR_ERR_UNSUPPORTED.  Async on `stream`. */
 UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                                   const float *g_raw_dev, const ur_grad_desc *grads, void *stream);
 

@@ -54,6 +54,28 @@ __device__ __forceinline__ D ddot(const D *a, const double *b) {
     return b[0] * a[0] + b[1] * a[1] + b[2] * a[2];
 }
 
+// Smith masking G1 of the GGX distribution at a dual cos(theta_v) (as ggx_g1).
+__device__ __forceinline__ D dggx_g1(double alpha, D cv) {
+    const D c2 = cv * cv;
+    const D tan2 = (dd(1.0) - c2) / c2;
+    return dd(2.0) / (dd(1.0) + dsqrt(dd(1.0) + (alpha * alpha) * tan2));
+}
+
+// Microfacet normal of ggx_sample about a dual unit normal n: the random
+// numbers fix its polar and azimuthal angles about n; the basis (onb) follows n.
+__device__ __forceinline__ void dggx_sample(const D *n, double alpha, double xi1, double xi2, D *h) {
+    const double sg = copysign(1.0, n[2].v);
+    const D a = dd(-1.0) / (dd(sg) + n[2]);
+    const D c = n[0] * n[1] * a;
+    const D t[3] = {dd(1.0) + sg * n[0] * n[0] * a, sg * c, -sg * n[0]};
+    const D b[3] = {c, dd(sg) + n[1] * n[1] * a, -n[1]};
+    const double q = 1.0 - xi1 + alpha * alpha * xi1;
+    const double ct = sqrt((1.0 - xi1) / q), st = alpha * sqrt(xi1 / q);
+    double sp, cp;
+    sincos(2.0 * M_PI * xi2, &sp, &cp);
+    for (int i = 0; i < 3; ++i) h[i] = (st * cp) * t[i] + (st * sp) * b[i] + ct * n[i];
+}
+
 // Parameter direction of the tangent pass.
 struct Tangent {
     int kind;     // 0 value pass, 1 impedance of material `index`, 2 coordinate `coord` of sphere `index`
@@ -492,7 +514,19 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
             for (int i = 0; i < 3; ++i) ng[i] = -ng[i];
         }
         const D z1 = mat_Z(A, before), z2 = mat_Z(A, after);
-        const D cos_r = -ddot(d, ng);
+        uint32_t x[4];
+        draw(P, ray, e, tx, b, 1, 0, x);
+        const double y = u01(x[0]);
+        // a rough boundary (Eq. 12; its echoes by direct hits only): Eqs. 7-11
+        // about the microfacet normal drawn from the second and third words
+        const double alpha = fmax(P.mat[mf].rough, P.mat[mb].rough);
+        D mn[3] = {ng[0], ng[1], ng[2]}, cn = dd(1.0);
+        if (alpha > 0.0) {
+            dggx_sample(ng, alpha, u01(x[1]), u01(x[2]), mn);
+            cn = -ddot(d, ng);
+            if (!(-ddot(d, mn).v > 0.0)) return;
+        }
+        const D cos_r = -ddot(d, mn);
         const D eta = z1 / z2;
         const D rad = dd(1.0) - eta * eta * (dd(1.0) - cos_r * cos_r);
         D R = dd(1.0), cos_t = dd(0.0);
@@ -504,23 +538,32 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                 R = Ar * Ar;
             }
         }
-        uint32_t x[4];
-        draw(P, ray, e, tx, b, 1, 0, x);
-        const double y = u01(x[0]);
         D nd[3];
-        if (y < R.v) {
-            for (int i = 0; i < 3; ++i) nd[i] = d[i] + dd(2.0) * cos_r * ng[i];
+        const bool refl = y < R.v;
+        if (refl) {
+            for (int i = 0; i < 3; ++i) nd[i] = d[i] + dd(2.0) * cos_r * mn[i];
+        } else {
+            const D f = eta * cos_r - cos_t;
+            for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * mn[i];
+        }
+        const D l = dsqrt(ddot(nd, nd));
+        for (int i = 0; i < 3; ++i) nd[i] = nd[i] / l;
+        if (alpha > 0.0) {
+            // a new direction on the wrong side of the surface is absorbed;
+            // else the weight factor |i.mn| G1(i) G1(o) / (|i.n| |mn.n|)
+            const D co = ddot(nd, ng);
+            if (refl ? !(co.v > 0.0) : !(co.v < 0.0)) return;
+            w = w * (cos_r * dggx_g1(alpha, cn) * dggx_g1(alpha, co.v < 0.0 ? -co : co) / (cn * ddot(mn, ng)));
+        }
+        if (refl) {
             if (A.attach_choice) w = w * (R / dd(R.v));
             med = before;
         } else {
-            const D f = eta * cos_r - cos_t;
-            for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * ng[i];
             const D Tr = dd(1.0) - R;
             if (A.attach_choice) w = w * (Tr / dd(Tr.v));
             med = after;
         }
-        const D l = dsqrt(ddot(nd, nd));
-        for (int i = 0; i < 3; ++i) d[i] = nd[i] / l;
+        for (int i = 0; i < 3; ++i) d[i] = nd[i];
         last = (hid < P.id_sph0 || hid >= P.id_pln0) ? hid : -1;
     }
 }

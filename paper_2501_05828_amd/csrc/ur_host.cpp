@@ -1167,8 +1167,11 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
     return guarded(c, [&]() -> ur_status {
         if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
         if (!g_raw_dev || !grads) return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and grads are required");
-        for (double r : c->rough)
-            if (r > 0.0) return c->fail(UR_ERR_UNSUPPORTED, "the adjoint does not support rough boundaries");
+        if (!c->acq.rough_direct_only)
+            for (double r : c->rough)
+                if (r > 0.0)
+                    return c->fail(UR_ERR_UNSUPPORTED, "the adjoint supports rough boundaries only with their echoes "
+                                                       "received by direct hits (rough_direct_only = 1)");
         if (!grads->amp && !grads->alpha && !grads->Z && !grads->sph_center && !grads->value)
             return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
