@@ -132,9 +132,12 @@ SIGNATURES = [
 _lib = None
 
 
-def load(path: str = LIB_PATH):
+def load(path: str = None):
     """Loads libultraray.so and declares every entry point.  Raises if missing."""
     global _lib
+    if path is None:
+        # ULTRARAY_LIB names another build of the library (e.g. an installed copy)
+        path = os.environ.get("ULTRARAY_LIB", LIB_PATH)
     if _lib is None:
         # torch ships its own HIP runtime under the same soname; loading torch
         # first makes this library bind to that runtime instead of a second copy
