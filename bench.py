@@ -277,7 +277,7 @@ def learned_experiment(args):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             if mode == "learned":
-                prop.enable(0.1)
+                prop.enable(args.epsilon)
             else:
                 prop.disable()
             b.record()
@@ -309,7 +309,7 @@ def learned_experiment(args):
              for u, l in zip(curves["uniform"], curves["learned"])]
     wl_name = "convex array, the paper's acquisition settings" if args.workload == "convex" else "bone phantom (learned)"
     out = {"metric": "channel MSE at equal GPU time, learned vs uniform", "workload": wl_name,
-           "target": args.target, "element_choice": args.element_choice, "reps": args.reps,
+           "target": args.target, "element_choice": args.element_choice, "epsilon": args.epsilon, "reps": args.reps,
            "min_depth_mm": args.min_depth_mm, "efficiency_gain": gains,
            "reference_rays_per_tx": args.ref_rays_per_tx, "records": n_rec, "records_offered": offered,
            "train_steps": args.train_steps, "train_s": t_train, "loss_log": losses, "curves": curves,
@@ -320,9 +320,11 @@ def learned_experiment(args):
 def rough_nee_experiment(args):
     """Channel-data MSE against GPU time on the bone phantom with the bone's
     roughness 0.5, with and without transducer sampling at the rough
-    boundaries (direct hits only): reference = mean of traces with it,
-    --ref-rays-per-tx in total; MSE of Re(ch_rf) beyond --min-depth-mm;
-    time = device time of trace + pulse."""
+    boundaries (direct hits only): one reference per arm (mean of traces of
+    that arm, --ref-rays-per-tx in total), whose difference in total signal
+    is reported with its standard error; MSE of Re(ch_rf) beyond
+    --min-depth-mm against the arm's own reference; time = device time of
+    trace + pulse."""
     import dataclasses
 
     import numpy as np
@@ -349,18 +351,32 @@ def rough_nee_experiment(args):
         return a.elapsed_time(b) * 1e-3
 
     n0 = int(np.ceil(2.0 * args.min_depth_mm * 1e-3 / acq0.c0 * acq0.f_s))
-    ref = torch.zeros_like(sim.ch_rf[..., n0:, 0], dtype=torch.float64)
-    for k in range(args.ref_parts):
-        run(args.ref_rays_per_tx / args.ref_parts, 0, 0xAB000000 + k)
-        ref += sim.ch_rf[..., n0:, 0].double()
-    ref /= args.ref_parts
+    # one reference per arm: their difference (with its standard error from
+    # the spread of the parts) tests that both estimate the same data
+    refs, totals = {}, {}
+    for direct_only in (0, 1):
+        ref = torch.zeros_like(sim.ch_rf[..., n0:, 0], dtype=torch.float64)
+        tot = []
+        for k in range(args.ref_parts):
+            run(args.ref_rays_per_tx / args.ref_parts, direct_only, 0xAB000000 + k + 1000 * direct_only)
+            ref += sim.ch_rf[..., n0:, 0].double()
+            tot.append(float(sim.ch_raw.double().sum()))
+        refs[direct_only] = ref / args.ref_parts
+        totals[direct_only] = np.array(tot)
+    ref = refs[0]
+    t0, t1 = totals[0], totals[1]
+    bias = {"total_signal_with_rough_sampling": float(t0.mean()), "total_signal_direct_only": float(t1.mean()),
+            "difference": float(t0.mean() - t1.mean()),
+            "difference_se": float(np.sqrt(t0.var(ddof=1) / len(t0) + t1.var(ddof=1) / len(t1))),
+            "reference_mse_between_arms": float(((refs[0] - refs[1]) ** 2).mean())}
+    print(f"[rough-nee] references: {json.dumps(bias)}", file=sys.stderr, flush=True)
     curves = {"direct_only": [], "with_rough_sampling": []}
     for mode, direct_only in (("direct_only", 1), ("with_rough_sampling", 0)):
         for bi, per_tx in enumerate(float(b) for b in args.budgets.split(",")):
             mse, tg = 0.0, 0.0
             for r in range(args.reps):
                 tg += run(per_tx, direct_only, 0xCD000000 + 97 * bi + r + 50000 * direct_only)
-                mse += float(((sim.ch_rf[..., n0:, 0].double() - ref) ** 2).mean())
+                mse += float(((sim.ch_rf[..., n0:, 0].double() - refs[direct_only]) ** 2).mean())
             curves[mode].append({"rays_per_tx": per_tx, "mse": mse / args.reps, "gpu_s": tg / args.reps})
             print(f"[rough-nee] {mode} {per_tx:.0e}/tx: mse {mse / args.reps:.4e} time {tg / args.reps:.4f} s",
                   file=sys.stderr, flush=True)
@@ -369,7 +385,8 @@ def rough_nee_experiment(args):
     print(json.dumps({"metric": "channel MSE at equal GPU time, rough-boundary transducer sampling vs direct hits only",
                       "workload": "bone phantom, bone roughness 0.5", "element_choice": args.element_choice,
                       "reps": args.reps, "min_depth_mm": args.min_depth_mm,
-                      "reference_rays_per_tx": args.ref_rays_per_tx, "efficiency_gain": gains, "curves": curves}))
+                      "reference_rays_per_tx": args.ref_rays_per_tx, "references": bias, "efficiency_gain": gains,
+                      "curves": curves}))
 
 
 def binning_experiment(args):
@@ -445,6 +462,7 @@ def main():
     ap.add_argument("--target", choices=["abs", "cost"], default="cost",
                     help="proposal target per cell: sum |c|, or sqrt(sum c^2 / path cost)")
     ap.add_argument("--reps", type=int, default=3, help="independent traces per budget (MSE averaged)")
+    ap.add_argument("--epsilon", type=float, default=0.1, help="uniform share of the learned emission mixture")
     ap.add_argument("--min-depth-mm", type=float, default=5.0, help="MSE over samples at this round-trip depth and beyond")
     ap.add_argument("--budgets", default="1e6,3e6,1e7,3e7", help="rays per transmit, comma-separated")
     ap.add_argument("--element-choice", choices=["uniform", "cone"], default="uniform",
