@@ -355,8 +355,8 @@ __device__ __forceinline__ Hit box_exit(const TraceParams &P, const double *o, c
     return h;
 }
 
-// Spheres and planes, after the triangles (the order does not matter: the
-// nearest t wins, the lower id on ties).
+// Spheres and planes (tested before the triangles; the order does not
+// matter: the nearest t wins, the lower id on ties).
 __device__ __forceinline__ void analytic_hits(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                               Hit &h) {
     for (int j = 0; j < P.n_sph; ++j) {
@@ -388,8 +388,11 @@ template <bool COUNT>
 __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                            LdsStack stk, Counters &cnt) {
     Hit h = box_exit(P, o, d);
-    if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
+    // spheres and planes first: their nearest hit bounds the culling
+    // distance of the tree walk from its first node (the result is the same
+    // in any order: nearest t, lower id on ties)
     analytic_hits(P, o, d, skip, h);
+    if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
     return h;
 }
 
@@ -1160,10 +1163,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     unsigned long long cbeg = 0, cend = 0;
     auto start_segment = [&]() {
         CNT(C_SEGMENTS);
+        // the box exit, then spheres and planes: their nearest hit bounds the
+        // culling distance of the tree walk from its first node, and the
+        // segment's length for the grid test (no triangle can make it longer)
         h = box_exit<CONVEX>(P, R.o, R.d);
+        analytic_hits(P, R.o, R.d, R.last, h);
         cr = make_cull(R.o, R.d);
         tmf = cull_tmax(h.t);
-        near_grid = P.n_scat > 0 && meets_grid(P, cr, R.d, h.t);   // up to the box exit, the longest it can be
+        near_grid = P.n_scat > 0 && meets_grid(P, cr, R.d, h.t);
         cur = 0;
         sp = 0;
         overflow = false;
@@ -1221,7 +1228,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (__popcll(done) < kBatchExtend && __ballot(active && trav) != 0ull) continue;
         if (active && !trav) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
-            analytic_hits(P, R.o, R.d, R.last, h);
             active = after_hit<COUNT, false, kDeferNee, true, ROUGH, CONVEX>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
                 start_segment();
