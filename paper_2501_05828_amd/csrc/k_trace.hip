@@ -165,13 +165,12 @@ __device__ __forceinline__ void walk_threaded(const TraceParams &P, const double
         }
         const int first = leaf >> 4, count = leaf & 15;
         for (int k = first; k < first + count; ++k) {
-            const int id = P.tri_id[k];
-            if (id == skip) continue;
+            if (k == skip) continue;
             CNT(C_TRI_TESTS);
             double t;
-            if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && id < h.id))) {
+            if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && P.tri_id[k] < h.id))) {
                 h.t = t;
-                h.id = id;
+                h.id = P.tri_id[k];
                 h.local = k;
                 tmf = cull_tmax(t);
             }
@@ -240,13 +239,13 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
             je = j + (k == 0 ? lc[0] : (k == 1 ? lc[1] : (k == 2 ? lc[2] : lc[3])));
         }
         if (j >= je) break;
-        const int id = P.tri_id[j];
-        if (id != skip) {
+        // (the triangle's original id only for a closer hit or a tie)
+        if (j != skip) {
             CNT(C_TRI_TESTS);
             double t;
-            if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && id < h.id))) {
+            if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && P.tri_id[j] < h.id))) {
                 h.t = t;
-                h.id = id;
+                h.id = P.tri_id[j];
                 h.local = j;
                 tmf = cull_tmax(t);
             }
@@ -294,6 +293,18 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
     return false;
 }
 
+// Whether the segment [0, tmf] meets the box of every triangle (the binary
+// tree's root box, tested as the escape-index walk tests it): if not, no
+// node of either tree can hold a hit and the walk is skipped.
+__device__ __forceinline__ bool meets_tree(const TraceParams &P, const CullRay &cr, float tmf) {
+    const float ax = (P.tree_lo_f[0] - cr.ox) * cr.ix, bx = (P.tree_hi_f[0] - cr.ox) * cr.ix;
+    const float ay = (P.tree_lo_f[1] - cr.oy) * cr.iy, by = (P.tree_hi_f[1] - cr.oy) * cr.iy;
+    const float az = (P.tree_lo_f[2] - cr.oz) * cr.iz, bz = (P.tree_hi_f[2] - cr.oz) * cr.iz;
+    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmf));
+    return tn <= tf;
+}
+
 // Complete ordered walk; the result is always the exact closest hit
 // (nearest t, lower id on ties): after a stack overflow the escape-index
 // walk re-visits the whole tree with the best hit so far.
@@ -302,6 +313,7 @@ __device__ __forceinline__ void walk_wide(const TraceParams &P, const double *o,
                                           Hit &h, LdsStack stk, Counters &cnt) {
     const CullRay cr = make_cull(o, d);
     float tmf = cull_tmax(h.t);
+    if (!meets_tree(P, cr, tmf)) return;
     int sp = 0, cur = 0;
     bool overflow = false;
     while (wide_step<COUNT>(P, o, d, skip, cr, tmf, h, cur, sp, overflow, stk, cnt)) {
@@ -384,6 +396,8 @@ __device__ __forceinline__ void analytic_hits(const TraceParams &P, const double
     }
 }
 
+// Nearest hit along (o, d), excluding the flat primitive `skip` (a
+// triangle's slot in BVH order or a plane's id, -1 for none).
 template <bool COUNT>
 __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                            LdsStack stk, Counters &cnt) {
@@ -721,7 +735,8 @@ __device__ __forceinline__ void scatter_events(const TraceParams &P, const Event
 // ------------------------------------------------------------------ one path
 struct RayState {
     double o[3], d[3], w, t, len;
-    int64_t last;      // flat primitive just left (excluded from the next hit), -1 if none
+    int64_t last;      // flat primitive just left (excluded from the next hit): a triangle's
+                       // slot in BVH order, a plane's id; -1 if none
     int med, seg, tx, e;
     uint32_t ray;
     int cell;          // emission direction cell (32 x 32 grid), -1 for explicit rays
@@ -1023,7 +1038,7 @@ __device__ __forceinline__ bool after_hit(const TraceParams &P, const EventLog &
     d[1] = nd[1];
     d[2] = nd[2];
     log_event<LOG>(L, refl ? 2 : 3, R.tx, R.e, b, h.id, R.t, R.w, o);
-    R.last = (h.id < P.id_sph0 || h.id >= P.id_pln0) ? h.id : -1;
+    R.last = h.id < P.id_sph0 ? (int64_t)h.local : (h.id >= P.id_pln0 ? h.id : -1);
     R.seg = b + 1;
     return true;
 }
@@ -1174,7 +1189,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         cur = 0;
         sp = 0;
         overflow = false;
-        trav = P.n_tnodes4 > 0;
+        trav = P.n_tnodes4 > 0 && meets_tree(P, cr, tmf);
     };
     while (true) {
         const unsigned long long busy = __ballot(active && trav);

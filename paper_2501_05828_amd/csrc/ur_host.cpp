@@ -58,6 +58,7 @@ struct ur_context {
     int top_medium = 0;
     int64_t n_tri = 0, n_sph = 0, n_pln = 0, n_scat = 0;
     int n_tnodes = 0, n_tnodes4 = 0;
+    float tree_lo[3] = {0, 0, 0}, tree_hi[3] = {0, 0, 0};   // root box of the binary tree
     std::vector<double> scat;              // [n_scat][4], kept for the r_s-dependent scatterer grid
     std::vector<double> sph;               // [n_sph][4]
     std::vector<int32_t> item_order;       // scatterer index of each grid item
@@ -240,6 +241,10 @@ ur_status fill_params(ur_context *c, TraceParams &P, uint64_t seed) {
     P.n_tnodes4 = c->n_tnodes4;
     P.n_tri = (int)c->n_tri;
     P.n_tnodes = c->n_tnodes;
+    for (int k = 0; k < 3; ++k) {
+        P.tree_lo_f[k] = c->tree_lo[k];
+        P.tree_hi_f[k] = c->tree_hi[k];
+    }
     P.grid = c->grid;
     for (int k = 0; k < 3; ++k) {
         const double lo = c->grid.lo[k] - 1e-5, hi = c->grid.lo[k] + (double)c->grid.n[k] * c->grid.h + 1e-5;
@@ -470,6 +475,10 @@ UR_API ur_status ur_scene_upload(ur_context *c, const ur_scene_desc *s) {
                 tid[k] = o;
             }
             c->n_tnodes = (int)r.nodes.size();
+            for (int k = 0; k < 3 && !r.nodes.empty(); ++k) {
+                c->tree_lo[k] = r.nodes[0].lo[k];
+                c->tree_hi[k] = r.nodes[0].hi[k];
+            }
             const std::vector<Bvh4NodeQ> wide = quantize_bvh4(collapse_bvh4(r.nodes));
             c->n_tnodes4 = (int)wide.size();
             if ((st = upload(c, c->d_tnodes4, wide))) return st;

@@ -111,6 +111,7 @@ struct TraceParams {
     const BvhNode *tnodes;            // threaded binary tree (any-hit walks, fallback)
     const Bvh4NodeQ *tnodes4;         // four-wide tree, quantised (closest hit)
     int n_tri, n_tnodes, n_tnodes4;
+    float tree_lo_f[3], tree_hi_f[3]; // box of the binary tree's root (every triangle, dilated, FP32)
     // scatterers: uniform grid, items grouped by cell (copies of position +
     // amplitude, and the original index that keys the RNG counter)
     GridInfo grid;
