@@ -20,8 +20,8 @@
 //
 // The trace runs as two persistent kernels joined by a segment queue:
 // k_extend advances each lane's closest-hit query by one node visit per
-// step, shades finished queries in batches (interfaces, direct hits,
-// termination) and queues the segments that can reach the scatterer grid;
+// step, tests the triangles of entered leaves in batches, shades finished
+// queries in batches (interfaces, direct hits, termination) and queues the segments that can reach the scatterer grid;
 // k_scatter walks the queued segments through the grid and queues the
 // transducer-sampling candidates, whose secondary rays k_nee casts.  Lanes
 // refill independently from chunks of work that a wavefront takes by guided
@@ -143,8 +143,15 @@ __device__ __forceinline__ unsigned long long guided_chunk(unsigned long long le
 #ifndef UR_BATCH_SCATTER
 #define UR_BATCH_SCATTER 32
 #endif
+// lanes that must hold pending leaves before a wavefront of the extend
+// kernel tests their triangles (or no lane can visit a node without first
+// testing its pending leaves)
+#ifndef UR_BATCH_LEAF
+#define UR_BATCH_LEAF 16
+#endif
 constexpr int kBatchExtend = UR_BATCH_EXTEND;
 constexpr int kBatchScatter = UR_BATCH_SCATTER;
+constexpr int kBatchLeaf = UR_BATCH_LEAF;
 
 // Escape-index walk over the binary tree: complete, stackless, fixed order.
 template <bool COUNT>
@@ -179,23 +186,26 @@ __device__ __forceinline__ void walk_threaded(const TraceParams &P, const double
     }
 }
 
-// Ordered walk over the four-wide tree: each visit tests four child boxes
-// from one 128-byte node, tests hit leaves at once, continues with the
-// nearest hit inner child and stacks the others (farthest first).  Popped
-// entries whose entry distance exceeds the current best are dropped.  If
-// the stack would overflow, the walk finishes and the escape-index walk
-// then re-visits the whole tree with the best hit so far, so the result is
-// always the exact closest hit (nearest t, lower id on ties).
-// One visit of the ordered four-wide walk: tests the four child boxes of
-// node `cur` from one 64-byte quantised node, tests hit leaves at once, continues with
-// the nearest hit inner child and stacks the others (farthest first).
-// Popped entries whose entry distance exceeds the current best are dropped.
-// A push that finds the stack full sets `overflow` (the caller then re-walks
-// the tree with the escape-index walk).  Returns false when the walk is done.
+// Ordered walk over the four-wide tree.  A visit tests the four child boxes
+// of node `cur` from one 64-byte quantised node (wide_decode), hands the hit
+// leaf children back as a pending set, continues with the nearest hit inner
+// child and stacks the others, farthest first (wide_next).  Popped entries
+// whose entry distance exceeds the current best are dropped.  A push that
+// finds the stack full sets `overflow` (the caller then re-walks the tree
+// with the escape-index walk and the best hit so far).  The triangles of the
+// pending leaves are tested by test_leaves: at once in walk_wide, and in the
+// extend kernel once enough lanes of the wavefront hold some, so that the
+// FP64 test runs on many lanes together.  A later test only leaves the
+// culling distance longer for a while (more visits, never a missed hit), so
+// the result is always the exact closest hit (nearest t, lower id on ties).
+struct Pending {
+    unsigned mask;   // hit leaf children still to test (bit k: child k)
+    int c[4];        // the node's child words; a leaf is ~((first << 4) | count)
+};
+
 template <bool COUNT>
-__device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o, const double *d, int64_t skip,
-                                          const CullRay &cr, float &tmf, Hit &h, int &cur, int &sp, bool &overflow,
-                                          LdsStack stk, Counters &cnt) {
+__device__ __forceinline__ void wide_decode(const TraceParams &P, const CullRay &cr, float tmf, int cur, float key[4],
+                                            int val[4], Pending &pd, Counters &cnt) {
     const uint4 *q = reinterpret_cast<const uint4 *>(P.tnodes4 + cur);
     const uint4 org = q[0], w0 = q[1], w1 = q[2];
     const int4 ch = reinterpret_cast<const int4 *>(q)[3];
@@ -206,9 +216,10 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
     const float ax = sx * cr.ix, ay = sy * cr.iy, az = sz * cr.iz;
     const float bx = (__uint_as_float(org.x) - cr.ox) * cr.ix, by = (__uint_as_float(org.y) - cr.oy) * cr.iy;
     const float bz = (__uint_as_float(org.z) - cr.oz) * cr.iz;
-    const int C[4] = {ch.x, ch.y, ch.z, ch.w};
-    float key[4];
-    int val[4], lj[4], lc[4];
+    pd.c[0] = ch.x;
+    pd.c[1] = ch.y;
+    pd.c[2] = ch.z;
+    pd.c[3] = ch.w;
     unsigned leaves = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -220,26 +231,31 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
         const float z1 = fmaf((float)((w1.y >> (8 * k)) & 255u), az, bz);
         const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
         const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmf));
-        const bool hit = tn <= tf && C[k] != -1;
-        lj[k] = (~C[k]) >> 4;
-        lc[k] = (~C[k]) & 15;
-        if (hit && C[k] < -1) leaves |= 1u << k;
-        key[k] = hit && C[k] >= 0 ? tn : INFINITY;
-        val[k] = C[k];
+        const bool hit = tn <= tf && pd.c[k] != -1;
+        if (hit && pd.c[k] < -1) leaves |= 1u << k;
+        key[k] = hit && pd.c[k] >= 0 ? tn : INFINITY;
+        val[k] = pd.c[k];
     }
-    // the triangles of every leaf child that the ray enters, in one loop, so
-    // that a wavefront runs the FP64 test once per triangle position rather
-    // than once per child slot
+    pd.mask = leaves;
+}
+
+// The triangles of every pending leaf, in one loop, so that a wavefront runs
+// the FP64 test once per triangle position rather than once per child slot.
+// (A triangle's original id is loaded only for a closer hit or a tie.)
+template <bool COUNT>
+__device__ __forceinline__ void test_leaves(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                            float &tmf, Hit &h, const Pending &pd, Counters &cnt) {
+    unsigned leaves = pd.mask;
     int j = 0, je = 0;
     while (true) {
         while (j >= je && leaves) {
             const int k = __builtin_ctz(leaves);
             leaves &= leaves - 1;
-            j = k == 0 ? lj[0] : (k == 1 ? lj[1] : (k == 2 ? lj[2] : lj[3]));
-            je = j + (k == 0 ? lc[0] : (k == 1 ? lc[1] : (k == 2 ? lc[2] : lc[3])));
+            const int w = ~(k == 0 ? pd.c[0] : (k == 1 ? pd.c[1] : (k == 2 ? pd.c[2] : pd.c[3])));
+            j = w >> 4;
+            je = j + (w & 15);
         }
         if (j >= je) break;
-        // (the triangle's original id only for a closer hit or a tie)
         if (j != skip) {
             CNT(C_TRI_TESTS);
             double t;
@@ -252,6 +268,12 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
         }
         ++j;
     }
+}
+
+// Sorts the decoded children, stacks all but the nearest hit inner child and
+// continues there, else pops.  Returns false when the walk is done.
+__device__ __forceinline__ bool wide_next(float key[4], int val[4], float tmf, int &cur, int &sp, bool &overflow,
+                                          LdsStack stk) {
     // sort the four (key, child) pairs ascending: 5 compare-exchanges
     auto cx = [&](int a, int b) {   // selects, not a branch per exchange
         const bool sw = key[b] < key[a];
@@ -291,6 +313,20 @@ __device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o,
         }
     }
     return false;
+}
+
+// One visit with its leaves tested at once (the culling distance is then
+// already the new best for the children stacked).
+template <bool COUNT>
+__device__ __forceinline__ bool wide_step(const TraceParams &P, const double *o, const double *d, int64_t skip,
+                                          const CullRay &cr, float &tmf, Hit &h, int &cur, int &sp, bool &overflow,
+                                          LdsStack stk, Counters &cnt) {
+    float key[4];
+    int val[4];
+    Pending pd;
+    wide_decode<COUNT>(P, cr, tmf, cur, key, val, pd, cnt);
+    test_leaves<COUNT>(P, o, d, skip, tmf, h, pd, cnt);
+    return wide_next(key, val, tmf, cur, sp, overflow, stk);
 }
 
 // Whether the segment [0, tmf] meets the box of every triangle (the binary
@@ -1172,6 +1208,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     RayState R;
     Hit h;
     CullRay cr;
+    Pending pd;
+    pd.mask = 0u;
     float tmf = 0.0f;
     int cur = 0, sp = 0, visits = 0;
     bool active = false, trav = false, overflow = false, exhausted = false, near_grid = false;
@@ -1192,7 +1230,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         trav = P.n_tnodes4 > 0 && meets_tree(P, cr, tmf);
     };
     while (true) {
-        const unsigned long long busy = __ballot(active && trav);
+        const unsigned long long busy = __ballot(active && (trav || pd.mask != 0u));
         if (!exhausted) {
             const unsigned long long need = __ballot(!active);
             if (need && (__popcll(need) >= kBatchExtend || busy == 0ull)) {
@@ -1235,13 +1273,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
         }
         if (__ballot(active) == 0ull) break;
-        if (active && trav) {
-            trav = wide_step<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cur, sp, overflow, stk, cnt);
+        // a lane whose last visit entered leaves waits with them until enough
+        // lanes (or every lane that could go on) do: then their triangles
+        // are tested together
+        const unsigned long long pend = __ballot(active && pd.mask != 0u);
+        if (pend && (__popcll(pend) >= kBatchLeaf || __ballot(active && trav && pd.mask == 0u) == 0ull)) {
+            if (active && pd.mask != 0u) {
+                test_leaves<COUNT>(P, R.o, R.d, R.last, tmf, h, pd, cnt);
+                pd.mask = 0u;
+            }
+        }
+        if (active && trav && pd.mask == 0u) {
+            float key[4];
+            int val[4];
+            wide_decode<COUNT>(P, cr, tmf, cur, key, val, pd, cnt);
+            trav = wide_next(key, val, tmf, cur, sp, overflow, stk);
             ++visits;
         }
-        const unsigned long long done = __ballot(active && !trav);
-        if (__popcll(done) < kBatchExtend && __ballot(active && trav) != 0ull) continue;
-        if (active && !trav) {
+        const unsigned long long done = __ballot(active && !trav && pd.mask == 0u);
+        if (__popcll(done) < kBatchExtend && __ballot(active && (trav || pd.mask != 0u)) != 0ull) continue;
+        if (active && !trav && pd.mask == 0u) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             active = after_hit<COUNT, false, kDeferNee, true, ROUGH, CONVEX>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
