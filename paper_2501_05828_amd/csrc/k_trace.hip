@@ -147,7 +147,7 @@ __device__ __forceinline__ unsigned long long guided_chunk(unsigned long long le
 // kernel tests their triangles (or no lane can visit a node without first
 // testing its pending leaves)
 #ifndef UR_BATCH_LEAF
-#define UR_BATCH_LEAF 16
+#define UR_BATCH_LEAF 12
 #endif
 constexpr int kBatchExtend = UR_BATCH_EXTEND;
 constexpr int kBatchScatter = UR_BATCH_SCATTER;
