@@ -86,9 +86,11 @@ DAS_SOURCES = ["k_signal.hip", "ur_internal.h"]
 
 
 def kernel_hash(sources=TRACE_SOURCES):
-    """Hash of a kernel's source (the .hip file and the headers it includes),
-    to tell whether stored counter readings still apply."""
+    """Hash of a kernel's source (the .hip file, the headers it includes and
+    its compile flags), to tell whether stored counter readings still apply."""
+    from paper_2501_05828_amd import build as _build
     h = hashlib.sha256()
+    h.update(" ".join(_build.EXTRA.get(sources[0], [])).encode())
     for name in sources:
         with open(os.path.join(ROOT, "paper_2501_05828_amd", "csrc", name), "rb") as f:
             h.update(f.read())
