@@ -123,7 +123,10 @@ struct LdsStack {
     int2 *base;
     int stride;
 };
-constexpr int kStack = 16;
+#ifndef UR_STACK
+#define UR_STACK 16
+#endif
+constexpr int kStack = UR_STACK;   // entries per lane
 constexpr int kChunk = 1024;   // work items a wave takes from the range at a time (largest chunk)
 
 // Guided self-scheduling: a wavefront takes about 1/8 of its share of the
@@ -1190,7 +1193,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // starts its next query.  So no lane waits for the longest traversal of its
 // wavefront, and the scatterer walk runs elsewhere with its own balance.
 template <bool COUNT, bool ROUGH, bool CONVEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_extend(TraceParams P) {
+#ifndef UR_EXTEND_WAVES
+#define UR_EXTEND_WAVES 4
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_EXTEND_WAVES))) void k_extend(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
 #pragma unroll
