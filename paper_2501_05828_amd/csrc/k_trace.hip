@@ -117,6 +117,19 @@ struct Hit {
     int local;     // triangle slot in BVH order, sphere or plane index
 };
 
+// During a tree walk a triangle hit carries this id and its slot in
+// `local`; its original id (tri_id[local]) is looked up at ties and once the
+// walk is done (resolve_hit), not at every closer hit.
+constexpr int64_t kTriPending = -2;
+
+__device__ __forceinline__ int64_t best_id(const TraceParams &P, const Hit &h) {
+    return h.id == kTriPending ? (int64_t)P.tri_id[h.local] : h.id;
+}
+
+__device__ __forceinline__ void resolve_hit(const TraceParams &P, Hit &h) {
+    if (h.id == kTriPending) h.id = P.tri_id[h.local];
+}
+
 // Per-lane traversal stack in LDS, entry-major (entry i of lane l at
 // base[i * stride]) so lanes at the same depth touch consecutive words.
 struct LdsStack {
@@ -178,9 +191,10 @@ __device__ __forceinline__ void walk_threaded(const TraceParams &P, const double
             if (k == skip) continue;
             CNT(C_TRI_TESTS);
             double t;
-            if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && P.tri_id[k] < h.id))) {
+            if (tri_isect(P.tri + 9 * (int64_t)k, o, d, t) && t > kEpsT &&
+                (t < h.t || (t == h.t && P.tri_id[k] < best_id(P, h)))) {
                 h.t = t;
-                h.id = P.tri_id[k];
+                h.id = kTriPending;
                 h.local = k;
                 tmf = cull_tmax(t);
             }
@@ -244,7 +258,7 @@ __device__ __forceinline__ void wide_decode(const TraceParams &P, const CullRay 
 
 // The triangles of every pending leaf, in one loop, so that a wavefront runs
 // the FP64 test once per triangle position rather than once per child slot.
-// (A triangle's original id is loaded only for a closer hit or a tie.)
+// (A triangle's original id is loaded only at a tie; see kTriPending.)
 template <bool COUNT>
 __device__ __forceinline__ void test_leaves(const TraceParams &P, const double *o, const double *d, int64_t skip,
                                             float &tmf, Hit &h, const Pending &pd, Counters &cnt) {
@@ -262,9 +276,10 @@ __device__ __forceinline__ void test_leaves(const TraceParams &P, const double *
         if (j != skip) {
             CNT(C_TRI_TESTS);
             double t;
-            if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT && (t < h.t || (t == h.t && P.tri_id[j] < h.id))) {
+            if (tri_isect(P.tri + 9 * (int64_t)j, o, d, t) && t > kEpsT &&
+                (t < h.t || (t == h.t && P.tri_id[j] < best_id(P, h)))) {
                 h.t = t;
-                h.id = P.tri_id[j];
+                h.id = kTriPending;
                 h.local = j;
                 tmf = cull_tmax(t);
             }
@@ -446,6 +461,7 @@ __device__ __forceinline__ Hit closest_hit(const TraceParams &P, const double *o
     // in any order: nearest t, lower id on ties)
     analytic_hits(P, o, d, skip, h);
     if (P.n_tnodes4 > 0) walk_wide<COUNT>(P, o, d, skip, h, stk, cnt);
+    resolve_hit(P, h);
     return h;
 }
 
@@ -1300,6 +1316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_EXTEND_W
         if (__popcll(done) < kBatchExtend && __ballot(active && (trav || pd.mask != 0u)) != 0ull) continue;
         if (active && !trav && pd.mask == 0u) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
+            resolve_hit(P, h);
             active = after_hit<COUNT, false, kDeferNee, true, ROUGH, CONVEX>(P, L, cnt, R, h, chunk, near_grid);
             if (active) {
                 start_segment();
