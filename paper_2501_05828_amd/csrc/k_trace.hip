@@ -1212,7 +1212,10 @@ template <bool COUNT, bool ROUGH, bool CONVEX>
 #ifndef UR_EXTEND_WAVES
 #define UR_EXTEND_WAVES 4
 #endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_EXTEND_WAVES))) void k_extend(TraceParams P) {
+#ifndef UR_EXTEND_WAVES_ROUGH
+#define UR_EXTEND_WAVES_ROUGH 4
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_EXTEND_WAVES_ROUGH : UR_EXTEND_WAVES))) void k_extend(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
 #pragma unroll
