@@ -79,11 +79,10 @@ __device__ __forceinline__ SplitIdx split_idx(double v) {
 // where linear interpolation is continuous.  Returns the interpolation
 // weight of sample i0 + 1 and whether 0 <= i0 < S - 1.
 __device__ __forceinline__ bool das_term_index(SplitIdx rx, SplitIdx tx, int S, int &i0, float &fr) {
-    float f = rx.f + tx.f;
-    int n = rx.n + tx.n;
-    const bool up = f >= 1.0f;
-    fr = up ? f - 1.0f : f;
-    i0 = up ? n + 1 : n;
+    const float f = rx.f + tx.f;          // in [0, 2)
+    // (the hardware fraction f - floor(f): exact here, f or f - 1)
+    fr = __builtin_amdgcn_fractf(f);
+    i0 = rx.n + tx.n + (f >= 1.0f ? 1 : 0);
     return (unsigned)i0 < (unsigned)(S - 1);
 }
 
@@ -141,9 +140,9 @@ __device__ __forceinline__ void das_transmits(const DasParams &p, double x, doub
 // 256 lanes covers a 16 x 16 tile of the image and each wavefront an 8 x 8
 // sub-tile (8 consecutive depths per lateral position), so the samples that
 // one gather of a wavefront touches lie within a few cache lines.  The
-// transmits are taken in register batches of up to 8; the receive delay (one
-// FP64 square root per pixel and element) is formed once per batch.  The
-// interpolation and accumulation are FP32.
+// transmits are taken in register batches of 8 and one batch of the rest;
+// the receive delay (one FP64 square root per pixel and element) is formed
+// once per batch.  The interpolation and accumulation are FP32.
 constexpr int kDasTile = 16;
 __global__ __launch_bounds__(256) void k_das(DasParams p) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -155,15 +154,17 @@ __global__ __launch_bounds__(256) void k_das(DasParams p) {
     float re = 0.0f, im = 0.0f;
     int t0 = 0;
     for (; t0 + 8 <= p.T; t0 += 8) das_transmits<8>(p, x, z, t0, re, im);
-    if (t0 + 4 <= p.T) {
-        das_transmits<4>(p, x, z, t0, re, im);
-        t0 += 4;
+    // the remaining transmits in one batch (one receive delay per element)
+    switch (p.T - t0) {
+    case 7: das_transmits<7>(p, x, z, t0, re, im); break;
+    case 6: das_transmits<6>(p, x, z, t0, re, im); break;
+    case 5: das_transmits<5>(p, x, z, t0, re, im); break;
+    case 4: das_transmits<4>(p, x, z, t0, re, im); break;
+    case 3: das_transmits<3>(p, x, z, t0, re, im); break;
+    case 2: das_transmits<2>(p, x, z, t0, re, im); break;
+    case 1: das_transmits<1>(p, x, z, t0, re, im); break;
+    default: break;
     }
-    if (t0 + 2 <= p.T) {
-        das_transmits<2>(p, x, z, t0, re, im);
-        t0 += 2;
-    }
-    if (t0 < p.T) das_transmits<1>(p, x, z, t0, re, im);
     const int64_t o = (int64_t)ix * p.nz + iz;
     if (p.iq) p.iq[o] = make_float2(re, im);
     if (p.env) p.env[o] = sqrtf(re * re + im * im);
