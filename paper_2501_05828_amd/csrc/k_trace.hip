@@ -1346,7 +1346,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
 // with the same cell intervals as the inline walk, so each capture is found
 // exactly once.  Candidates go to the transducer-sampling queue.
 template <bool COUNT, bool CONE_CONVEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_scatter(TraceParams P) {
+#ifndef UR_SCATTER_WAVES
+#define UR_SCATTER_WAVES 4
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_SCATTER_WAVES))) void k_scatter(TraceParams P) {
     Counters cnt;
     if constexpr (COUNT) {
 #pragma unroll
