@@ -165,7 +165,13 @@ __device__ __forceinline__ unsigned long long guided_chunk(unsigned long long le
 #ifndef UR_BATCH_LEAF
 #define UR_BATCH_LEAF 12
 #endif
+// a second node visit in the same loop pass when this many lanes can take
+// one (fewer passes through the batch tests)
+#ifndef UR_SECOND_STEP
+#define UR_SECOND_STEP 16
+#endif
 constexpr int kBatchExtend = UR_BATCH_EXTEND;
+constexpr int kSecondStep = UR_SECOND_STEP;
 constexpr int kBatchScatter = UR_BATCH_SCATTER;
 constexpr int kBatchLeaf = UR_BATCH_LEAF;
 
@@ -1308,12 +1314,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
                 pd.mask = 0u;
             }
         }
-        if (active && trav && pd.mask == 0u) {
+        auto visit = [&]() {
             float key[4];
             int val[4];
             wide_decode<COUNT>(P, cr, tmf, cur, key, val, pd, cnt);
             trav = wide_next(key, val, tmf, cur, sp, overflow, stk);
             ++visits;
+        };
+        if (active && trav && pd.mask == 0u) visit();
+        if (__popcll(__ballot(active && trav && pd.mask == 0u)) >= kSecondStep) {
+            if (active && trav && pd.mask == 0u) visit();
         }
         const unsigned long long done = __ballot(active && !trav && pd.mask == 0u);
         if (__popcll(done) < kBatchExtend && __ballot(active && (trav || pd.mask != 0u)) != 0ull) continue;
