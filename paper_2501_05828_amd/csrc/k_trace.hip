@@ -10,18 +10,22 @@
 // extents are dilated and rounded outward so culling never rejects a
 // primitive the FP64 test would accept.
 //
-// Closest hits walk a four-wide BVH (64-byte quantised nodes, one triangle
-// per leaf) in nearest-first order with a per-lane stack in LDS; the
-// secondary rays' crossing queries and the exact fallback of an overflowing
-// stack walk the same tree in its threaded (escape-index) binary layout,
-// which needs no stack.  Scatterer captures come from a uniform grid walked
-// by a 3D DDA whose cell intervals partition the segment, so every capture
-// is reported once.
+// A closest-hit query first takes the box exit, the planes and the spheres
+// (so its culling distance is tight from the first node), skips the tree if
+// the segment misses the box of every triangle, and otherwise walks a
+// four-wide BVH (64-byte quantised nodes, one triangle per leaf) in
+// nearest-first order with a per-lane stack in LDS; the secondary rays'
+// crossing queries and the exact fallback of an overflowing stack walk the
+// same tree in its threaded (escape-index) binary layout, which needs no
+// stack.  Scatterer captures come from a uniform grid walked by a 3D DDA
+// whose cell intervals partition the segment, so every capture is reported
+// once.
 //
 // The trace runs as two persistent kernels joined by a segment queue:
-// k_extend advances each lane's closest-hit query by one node visit per
-// step, tests the triangles of entered leaves in batches, shades finished
-// queries in batches (interfaces, direct hits, termination) and queues the segments that can reach the scatterer grid;
+// k_extend advances each lane's closest-hit query by one or two node visits
+// per step, tests the triangles of entered leaves in batches, shades
+// finished queries in batches (interfaces, direct hits, termination) and
+// queues the segments that can reach the scatterer grid;
 // k_scatter walks the queued segments through the grid and queues the
 // transducer-sampling candidates, whose secondary rays k_nee casts.  Lanes
 // refill independently from chunks of work that a wavefront takes by guided
