@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libultraray.so")
-SOURCES = ["ur_host.cpp", "bvh.cpp", "scatter_grid.cpp", "k_trace.hip", "k_signal.hip", "k_mlp.hip", "k_adjoint.hip"]
+SOURCES = ["ur_host.cpp", "bvh.cpp", "scatter_grid.cpp", "k_trace.hip", "k_trace_rays.hip", "k_signal.hip", "k_mlp.hip",
+           "k_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
@@ -28,8 +29,11 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={
 # polynomial coefficients of emission and acos: two moves each) out of the
 # loop, where they no longer fit and spill to scratch, so that every use waits
 # on a scratch load.  Without that pass the extend kernel needs 111 registers
-# and no scratch, and runs about a tenth faster.
-EXTRA = {"k_trace.hip": ["-mllvm", "-disable-machine-licm"]}
+# and no scratch, and runs about a tenth faster.  The explicit-ray kernel
+# (k_trace_rays.hip, the event-log path) is built without loop unrolling as
+# well: with it, a call with many rays lost some direct-hit records.
+EXTRA = {"k_trace.hip": ["-mllvm", "-disable-machine-licm"],
+         "k_trace_rays.hip": ["-mllvm", "-disable-machine-licm", "-fno-unroll-loops"]}
 
 
 def flags_for(src: str) -> list:

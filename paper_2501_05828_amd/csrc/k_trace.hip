@@ -808,8 +808,8 @@ struct RayState {
     // after a rough boundary with transducer sampling: the sampler's density of
     // the direction taken and the element range of its secondary ray (ne_prev
     // = 0 otherwise), for the balance heuristic of a direct hit that follows
-    double pdf_prev;
-    int lo_prev, ne_prev;
+    double pdf_prev = 0.0;
+    int lo_prev = 0, ne_prev = 0;
 };
 
 // Appends the segment [0, t_seg) of R to the segment queue.  Called by the
@@ -1195,6 +1195,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         R.len = 0.0;
                         R.last = -1;
                         R.ne_prev = 0;
+                        R.lo_prev = 0;
+                        R.pdf_prev = 0.0;
                         R.med = P.top_medium;
                         R.seg = 0;
                         active = true;
@@ -1295,6 +1297,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
                         R.len = 0.0;
                         R.last = -1;
                         R.ne_prev = 0;
+                        R.lo_prev = 0;
+                        R.pdf_prev = 0.0;
                         R.med = P.top_medium;
                         R.seg = 0;
                         active = true;
@@ -1510,6 +1514,8 @@ __global__ __launch_bounds__(256) void k_nee(TraceParams P) {
     flush_counters<COUNT>(P, cnt);
 }
 
+// (k_trace_rays is compiled only in k_trace_rays.hip, with its own flags.)
+#ifdef UR_TRACE_RAYS_ONLY
 __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *rays, int64_t n, EventLog L) {
     __shared__ int2 s_stack[kStack * 64];
     const LdsStack stk{s_stack + threadIdx.x, 64};
@@ -1529,6 +1535,8 @@ __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *
         R.len = 0.0;
         R.last = -1;
         R.ne_prev = 0;
+        R.lo_prev = 0;
+        R.pdf_prev = 0.0;
         R.med = (int)r.medium;
         R.seg = 0;
         R.tx = (int)r.tx;
@@ -1541,6 +1549,7 @@ __global__ __launch_bounds__(64) void k_trace_rays(TraceParams P, const ur_ray *
     }
     flush_counters<true>(P, cnt);
 }
+#else
 
 __global__ void k_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1549,9 +1558,11 @@ __global__ void k_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t
     philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1, r);
     for (int j = 0; j < 4; ++j) out[4 * i + j] = r[j];
 }
+#endif  // UR_TRACE_RAYS_ONLY
 
 }  // namespace
 
+#ifndef UR_TRACE_RAYS_ONLY
 namespace {
 template <class K>
 hipError_t resident_blocks(K kernel, int64_t needed, unsigned &blocks) {
@@ -1662,6 +1673,14 @@ hipError_t ur_launch_nee(const ur::TraceParams &p, bool count, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctr, out, n, k0, k1);
+    return hipGetLastError();
+}
+#endif  // UR_TRACE_RAYS_ONLY
+
+#ifdef UR_TRACE_RAYS_ONLY
 hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, int64_t n, ur::EventLog log,
                                 hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -1669,9 +1688,4 @@ hipError_t ur_launch_trace_rays(const ur::TraceParams &p, const void *rays_dev, 
     hipLaunchKernelGGL(k_trace_rays, dim3((unsigned)blocks), dim3(64), 0, s, p, (const ur_ray *)rays_dev, n, log);
     return hipGetLastError();
 }
-
-hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctr, out, n, k0, k1);
-    return hipGetLastError();
-}
+#endif

@@ -107,3 +107,79 @@ def test_steered_transmits_off_centre(torch_gpu, oracle):
     acq = dataclasses.replace(w.acq, n_elements=63, angles=np.radians([-30.0, -7.0, 0.0, 25.0]),
                               alpha_m=math.radians(10), alpha_c=math.radians(30))
     _compare(oracle, dataclasses.replace(w, acq=acq), "steered")
+
+
+def _duplicated_floor(w, copies=3, seed=5):
+    """The tiny scene with its reflector plane replaced by a triangle floor at
+    z = 20 mm (two triangles over the whole box) given `copies` times, in a
+    shuffled order: every hit of the floor is a tie in t between copies, and
+    the diagonal is a tie between the two halves."""
+    mm = 1e-3
+    a = [[-20 * mm, -20 * mm, 20 * mm], [20 * mm, -20 * mm, 20 * mm], [20 * mm, 20 * mm, 20 * mm]]
+    b = [[-20 * mm, -20 * mm, 20 * mm], [20 * mm, 20 * mm, 20 * mm], [-20 * mm, 20 * mm, 20 * mm]]
+    tris = np.array([np.ravel(a), np.ravel(b)] * copies)
+    order = np.random.default_rng(seed).permutation(len(tris))
+    tris = tris[order]
+    # normal (e1 x e2) along +z: the reflector (material 1) on the front side
+    tri_mat = np.tile(np.array([[1, 0]], np.int32), (len(tris), 1))
+    sc = dataclasses.replace(w.scene, tri=tris, tri_mat=tri_mat, pln=np.zeros((0, 4)),
+                             pln_mat=np.zeros((0, 2), np.int32))
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(40))
+    return dataclasses.replace(w, scene=sc, acq=acq)
+
+
+def test_coincident_triangles_tie_to_the_lower_id(torch_gpu, oracle):
+    """Copies of the same two triangles (the halves of a square floor sharing
+    its diagonal), traced as explicit rays in one call:
+
+    - copies give equal t in any arithmetic, so the closest hit is the lowest
+      id among them on both sides, and the triangle just left is excluded
+      without its copies being hit again at t ~ 0;
+    - on the shared diagonal the two halves' t can differ in the last bit
+      between the two formulations of the triangle test (the kernel compares
+      the barycentric numerators with the determinant, the oracle multiplies
+      them by its reciprocal), so either half is a valid hit there: the events
+      must agree in everything but which half (time, position, value, kind
+      and the rest of the path);
+    - every direct-hit record of the one call is there (a call with many rays
+      once lost some).
+
+    The traced channel data match the oracle's too."""
+    from paper_2501_05828_amd.sim import Simulator
+    w = _duplicated_floor(scenes.tiny(rays_per_element=256))
+    rng = np.random.default_rng(12)
+    rays = []
+    for r in range(300):
+        o = [rng.uniform(-9, 9) * 1e-3, rng.uniform(-2, 2) * 1e-3, 0.0]
+        th, ph = math.acos(rng.uniform(0.3, 1.0)), rng.uniform(0, 2 * math.pi)
+        d = [math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)]
+        rays.append(dict(o=o, d=d, w=1.0, t=1e-7 * r, ray=r, elem=r % 64))
+    # and rays aimed at the shared diagonal x = y of the floor
+    for r in range(300, 340):
+        p = rng.uniform(-8, 8) * 1e-3
+        rays.append(dict(o=[p, p, 0.0], d=[0.0, 0.0, 1.0], w=1.0, t=0.0, ray=r, elem=r % 64))
+    s = Simulator(w)
+    ev_g, n_g = s.ctx.ur_trace_rays(w.seed, rays, cap=40000)
+    ev_o, _, _ = oracle.trace_rays(w, rays, cap=40000)
+    assert n_g == len(ev_o)
+    assert sum(e["kind"] == "direct" for e in ev_g) == sum(e["kind"] == "direct" for e in ev_o) >= 5
+    n_tri = len(w.scene.tri)
+    first = {}
+    for i, t in enumerate(map(tuple, w.scene.tri)):
+        first.setdefault(t, i)
+    floor_hits = 0
+    for ev in (ev_g, ev_o):
+        for e in ev:
+            if e["kind"] in ("reflect", "transmit") and 0 <= e["id"] < n_tri:
+                assert e["id"] == first[tuple(w.scene.tri[e["id"]])], e
+                floor_hits += 1
+    assert floor_hits > 200
+    label = lambda i: -10 if 0 <= i < n_tri else i          # any half of the floor
+    key = lambda e: (e["tx"], e["kind"], e["seg"], label(e["id"]), e["elem"], round(e["t"] * 1e12),
+                     tuple(round(x * 1e9) for x in e["pos"]))
+    for a, b in zip(sorted(ev_g, key=key), sorted(ev_o, key=key)):
+        assert (a["kind"], a["seg"], label(a["id"]), a["elem"]) == (b["kind"], b["seg"], label(b["id"]), b["elem"])
+        assert abs(a["t"] - b["t"]) <= 1e-15 + 1e-12 * abs(b["t"])
+        assert np.allclose(a["pos"], b["pos"], rtol=0, atol=1e-12)
+        assert abs(a["value"] - b["value"]) <= 1e-5 * abs(b["value"]) + 1e-300
+    _compare(oracle, w, "coincident triangles")
