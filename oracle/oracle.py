@@ -17,15 +17,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile oracle.c into liboracle.so (portable -O2, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-function", os.path.join(HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
+SAN_LIB_PATH = os.path.join(HERE, "liboracle_san.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (portable -O2, no FMA contraction),
+    or with sanitize into liboracle_san.so: AddressSanitizer and
+    UndefinedBehaviorSanitizer, every report fatal, serial (no OpenMP).  A
+    process that loads the sanitized library needs libasan preloaded."""
+    out = SAN_LIB_PATH if sanitize else LIB_PATH
+    opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+           if sanitize else ["-O2", "-fopenmp"])
+    cmd = ["gcc", *opt, "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+           "-Wall", "-Wno-unused-function", os.path.join(HERE, "oracle.c"), "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class Acq(C.Structure):
@@ -80,9 +89,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("ORACLE_LIB", LIB_PATH)   # another build (e.g. the sanitized one)
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         P = C.POINTER
         L.or_trace.argtypes = [P(Acq), P(SceneS), C.c_int, P(C.c_double), P(Stats)]
         L.or_trace_subset.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64, P(C.c_double), P(C.c_double),
