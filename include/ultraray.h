@@ -355,6 +355,18 @@ UR_API ur_status ur_mlp_init(ur_context *ctx, const float *params, const float *
 /* Copies the current parameters to host memory (77,120 floats).  Synchronous. */
 UR_API ur_status ur_mlp_get_params(ur_context *ctx, float *params);
 
+/* Training state, for checkpoints: state (host, 3 x 77,120 floats) receives
+ * the parameters, Adam's first moments and its second moments, in that
+ * order, and *step the number of Adam steps taken (the bias corrections of
+ * the next step depend on it).  Synchronous. */
+UR_API ur_status ur_mlp_get_state(ur_context *ctx, float *state, int64_t *step);
+
+/* Restores a state in the layout of ur_mlp_get_state (finite values, second
+ * moments >= 0, step >= 0) after ur_mlp_init for the same transmit setup; the
+ * Fourier matrix given to ur_mlp_init is kept.  UR_ERR_INVALID_ARG for a bad
+ * state.  Synchronous. */
+UR_API ur_status ur_mlp_set_state(ur_context *ctx, const float *state, int64_t step);
+
 /* q_dev [rows][1024]: the network's direction distribution for every row. */
 UR_API ur_status ur_mlp_forward(ur_context *ctx, float *q_dev, void *stream);
 

@@ -113,6 +113,8 @@ SIGNATURES = [
     ("ur_philox", C.c_int, [_CTX, P(C.c_uint32), C.c_int64, C.c_uint32, C.c_uint32, P(C.c_uint32)]),
     ("ur_mlp_init", C.c_int, [_CTX, P(C.c_float), P(C.c_float)]),
     ("ur_mlp_get_params", C.c_int, [_CTX, P(C.c_float)]),
+    ("ur_mlp_get_state", C.c_int, [_CTX, P(C.c_float), P(C.c_int64)]),
+    ("ur_mlp_set_state", C.c_int, [_CTX, P(C.c_float), C.c_int64]),
     ("ur_mlp_forward", C.c_int, [_CTX, C.c_void_p, C.c_void_p]),
     ("ur_mlp_loss_grad", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_mlp_train_step", C.c_int, [_CTX, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p]),
@@ -381,6 +383,20 @@ class Context:
         out = np.zeros(77120, np.float32)
         self.check(self.lib.ur_mlp_get_params(self.h, out.ctypes.data_as(P(C.c_float))), "ur_mlp_get_params")
         return out
+
+    def ur_mlp_get_state(self):
+        """(state [3][77120] float32: parameters, Adam m, Adam v; step)."""
+        out = np.zeros(3 * 77120, np.float32)
+        step = C.c_int64(0)
+        self.check(self.lib.ur_mlp_get_state(self.h, out.ctypes.data_as(P(C.c_float)), C.byref(step)),
+                   "ur_mlp_get_state")
+        return out.reshape(3, 77120), int(step.value)
+
+    def ur_mlp_set_state(self, state, step):
+        a = np.ascontiguousarray(state, np.float32).reshape(-1)
+        if a.size != 3 * 77120:
+            raise ValueError("state must hold 3 x 77120 floats")
+        self.check(self.lib.ur_mlp_set_state(self.h, a.ctypes.data_as(P(C.c_float)), int(step)), "ur_mlp_set_state")
 
     def ur_mlp_forward(self, q, stream=None):
         self.check(self.lib.ur_mlp_forward(self.h, _ptr(q), _stream_ptr(stream)), "ur_mlp_forward")

@@ -1314,6 +1314,41 @@ UR_API ur_status ur_mlp_get_params(ur_context *c, float *params) {
     });
 }
 
+UR_API ur_status ur_mlp_get_state(ur_context *c, float *state, int64_t *step) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!state || !step) return c->fail(UR_ERR_INVALID_ARG, "state and step are required");
+        HIP_TRY(c, hipDeviceSynchronize());
+        const size_t P = kParams * sizeof(float);
+        HIP_TRY(c, hipMemcpy(state, c->d_theta.p, P, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(state + kParams, c->d_m.p, P, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(state + 2 * kParams, c->d_v.p, P, hipMemcpyDeviceToHost));
+        *step = c->mlp_step;
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_mlp_set_state(ur_context *c, const float *state, int64_t step) {
+    return guarded(c, [&]() -> ur_status {
+        ur_status st;
+        if ((st = mlp_check(c))) return st;
+        if (!state) return c->fail(UR_ERR_INVALID_ARG, "state is NULL");
+        if (step < 0 || step > INT32_MAX) return c->fail(UR_ERR_INVALID_ARG, "step %lld out of range", (long long)step);
+        for (int i = 0; i < 3 * kParams; ++i)
+            if (!std::isfinite(state[i])) return c->fail(UR_ERR_INVALID_ARG, "non-finite state entry %d", i);
+        for (int i = 2 * kParams; i < 3 * kParams; ++i)
+            if (state[i] < 0.0f) return c->fail(UR_ERR_INVALID_ARG, "negative second moment at %d", i - 2 * kParams);
+        HIP_TRY(c, hipDeviceSynchronize());
+        const size_t P = kParams * sizeof(float);
+        HIP_TRY(c, hipMemcpy(c->d_theta.p, state, P, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_m.p, state + kParams, P, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_v.p, state + 2 * kParams, P, hipMemcpyHostToDevice));
+        c->mlp_step = (int)step;
+        return UR_OK;
+    });
+}
+
 UR_API ur_status ur_mlp_forward(ur_context *c, float *q_dev, void *stream) {
     return guarded(c, [&]() -> ur_status {
         ur_status st;

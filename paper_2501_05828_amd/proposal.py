@@ -7,7 +7,8 @@ the training target per cell is sqrt(sum c^2 / mean path cost) -- the
 density that minimises variance x time -- instead of sum |c|.  train(): Adam
 steps on minibatch histograms drawn from those records.  enable(): the network's direction
 distribution, mixed with eps of uniform, becomes the emission pdf of later
-traces (weights 1/pdf keep the estimator unbiased).
+traces (weights 1/pdf keep the estimator unbiased).  save()/load(): the
+training state (parameters, Adam moments, step) as an .npz checkpoint.
 """
 from __future__ import annotations
 
@@ -68,6 +69,19 @@ class Proposal:
             if log_every and (step % log_every == 0 or step == steps - 1):
                 losses.append((step, float(self.loss.item())))
         return losses
+
+    def save(self, path: str):
+        """Writes the training state (parameters, Adam moments, step) to an
+        .npz file."""
+        import numpy as np
+        state, step = self.ctx.ur_mlp_get_state()
+        np.savez(path, state=state, step=np.int64(step))
+
+    def load(self, path: str):
+        """Restores a state written by save() for the same transmit setup."""
+        import numpy as np
+        with np.load(path) as f:
+            self.ctx.ur_mlp_set_state(f["state"], int(f["step"]))
 
     def enable(self, eps: float = 0.1):
         self.ctx.ur_mlp_proposal_tables(eps, self.pdf, self.cdf)

@@ -97,6 +97,56 @@ def test_mlp_adam_steps(setup):
     assert np.median(diff) < 1e-2 * lr
 
 
+def test_mlp_training_resumes_from_a_saved_state(setup):
+    """A checkpoint of the training state (parameters, Adam moments, step)
+    taken after 3 steps and restored reproduces the next 2 steps of the
+    uninterrupted run; the state after the 3 steps also equals the FP64
+    reference Adam's m and v to the precision of the gradient, and a restore
+    with the step count reset gives other parameters (the bias corrections
+    depend on it)."""
+    torch, sim, params, rff, X, H = setup
+    ctx = sim.ctx
+    ctx.ur_mlp_init(params, rff)
+    Ht = torch.from_numpy(H).cuda()
+    lr = 1e-3
+    for _ in range(3):
+        ctx.ur_mlp_train_step(Ht, lr)
+    state, step = ctx.ur_mlp_get_state()
+    assert step == 3 and state.shape == (3, 77120)
+    assert np.array_equal(state[0], ctx.ur_mlp_get_params())
+    assert np.all(state[2] >= 0) and np.count_nonzero(state[1]) > 0.5 * state.shape[1]
+    for _ in range(2):
+        ctx.ur_mlp_train_step(Ht, lr)
+    straight = ctx.ur_mlp_get_params()
+    # a fresh start, then the checkpoint
+    ctx.ur_mlp_init(params, rff)
+    ctx.ur_mlp_set_state(state, step)
+    back, back_step = ctx.ur_mlp_get_state()
+    assert back_step == 3 and np.array_equal(back, state)
+    for _ in range(2):
+        ctx.ur_mlp_train_step(Ht, lr)
+    resumed = ctx.ur_mlp_get_params()
+    # (the loss normalisation is a float atomic sum, so the last bits of a
+    # step may differ: a few FP32 ulps of the parameters, against steps of ~lr)
+    gap = float(np.max(np.abs(resumed - straight)))
+    print(f"[proposal] resumed vs uninterrupted: max |diff| {gap:.3e} (lr {lr:g})")
+    assert gap <= 1e-2 * lr
+    assert np.mean(np.abs(resumed - params) > 0) > 0.5
+    # the step count matters
+    ctx.ur_mlp_set_state(state, 0)
+    for _ in range(2):
+        ctx.ur_mlp_train_step(Ht, lr)
+    assert np.max(np.abs(ctx.ur_mlp_get_params() - straight)) > 0.1 * lr
+    # invalid states are refused
+    from paper_2501_05828_amd.binding import URError
+    bad = state.copy()
+    bad[2, 5] = -1.0
+    with pytest.raises(URError):
+        ctx.ur_mlp_set_state(bad, 3)
+    with pytest.raises(URError):
+        ctx.ur_mlp_set_state(state, -1)
+
+
 def test_proposal_tables_parity(setup):
     torch, sim, params, rff, X, H = setup
     sim.ctx.ur_mlp_init(params, rff)
