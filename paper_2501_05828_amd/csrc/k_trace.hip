@@ -30,9 +30,9 @@
 // transducer-sampling candidates, whose secondary rays k_nee casts.  Lanes
 // refill independently from chunks of work that a wavefront takes by guided
 // self-scheduling (one atomic per chunk), so lanes do not idle behind long
-// paths.  k_trace is the single-loop form of the same arithmetic, used for
-// explicit rays with an event log and to re-trace a range whose sampling
-// queue overflowed.
+// paths.  k_trace is the single-loop form of the same arithmetic, used to
+// re-trace a range whose sampling queue overflowed; k_trace_rays (compiled in
+// k_trace_rays.hip) runs it for explicit rays with an event log.
 #include "trace_device.h"
 #include "ultraray.h"
 
