@@ -183,3 +183,20 @@ def test_coincident_triangles_tie_to_the_lower_id(torch_gpu, oracle):
         assert np.allclose(a["pos"], b["pos"], rtol=0, atol=1e-12)
         assert abs(a["value"] - b["value"]) <= 1e-5 * abs(b["value"]) + 1e-300
     _compare(oracle, w, "coincident triangles")
+
+
+def test_duplicated_tube_mesh(torch_gpu, oracle):
+    """The bone tube with every triangle given twice, the copies' ids
+    shuffled: every tube hit is a tie in t between copies (the lower id
+    wins), and the triangle just left must be excluded while its copy is
+    not hit again at t ~ 0.  The timed kernels (node visits with deferred
+    leaf tests, hit ids looked up at ties) against the oracle: exact
+    counters and the same channel data."""
+    w = scenes.bone(rays_per_element=12)
+    sc = w.scene
+    order = np.random.default_rng(4).permutation(2 * len(sc.tri))
+    sc = dataclasses.replace(sc, tri=np.concatenate([sc.tri, sc.tri])[order],
+                             tri_mat=np.concatenate([sc.tri_mat, sc.tri_mat])[order])
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(5), alpha_c=math.radians(30))
+    st, ost, _ = _compare(oracle, dataclasses.replace(w, scene=sc, acq=acq), "duplicated tube")
+    assert ost["reflect"] + ost["transmit"] > 10000
