@@ -459,7 +459,13 @@ UR_API ur_status ur_beamform_adjoint(ur_context *ctx, const ur_grid_desc *grid, 
  * probability attached to the weight (R / value(R), (1 - R) / value(1 - R)),
  * which adds the derivative of the choice probability (the gradient of the
  * expectation over the choice); 1: the choice counts as fixed, giving the
- * derivative of the fixed-seed estimator between decision changes. */
+ * derivative of the fixed-seed estimator between decision changes.
+ * record_paths: with Z or sph_center requested, the paths go in ranges of
+ * this many (0: as many as fit in 512 MiB of records); the value pass over
+ * a range keeps each segment's closest primitive (16 bytes a segment) and up
+ * to 8 contributing captures a path (8 bytes each), which the tangent passes
+ * over the range replay.  The context keeps these buffers (grown, never
+ * shrunk) until it is destroyed. */
 typedef struct ur_grad_desc {
     float *amp;
     double *alpha;
@@ -467,6 +473,7 @@ typedef struct ur_grad_desc {
     double *sph_center;
     double *value;          /* [1] or NULL: J = sum g(t) c over the replayed contributions (FP64) */
     int32_t frozen_choice;
+    int64_t record_paths;   /* >= 0; 0 = automatic */
 } ur_grad_desc;
 
 /* Path-replay adjoint of ur_trace for the same (seed, ray_stride,
@@ -482,7 +489,11 @@ typedef struct ur_grad_desc {
  * (ur_acq_desc.rough_direct_only = 1): the GGX microfacet normal follows the
  * dual macro normal for the same random numbers and its weight factor is
  * differentiated; with transducer sampling at rough boundaries the call
- * returns UR_ERR_UNSUPPORTED.  Async on `stream`. */
+ * returns UR_ERR_UNSUPPORTED.  Every decision (closest primitive, capture,
+ * element drawn) is taken on values, so it is the same in every pass; the
+ * tangent passes replay the value pass's record of them (record_paths).
+ * Errors: UR_ERR_INVALID_ARG (no output, record_paths < 0, stride/offset),
+ * UR_ERR_OOM (record buffers).  Async on `stream`. */
 UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                                   const float *g_raw_dev, const ur_grad_desc *grads, void *stream);
 

@@ -82,7 +82,7 @@ class Ray(C.Structure):
 
 class GradDesc(C.Structure):
     _fields_ = [("amp", C.c_void_p), ("alpha", C.c_void_p), ("Z", C.c_void_p), ("sph_center", C.c_void_p),
-                ("value", C.c_void_p), ("frozen_choice", C.c_int32)]
+                ("value", C.c_void_p), ("frozen_choice", C.c_int32), ("record_paths", C.c_int64)]
 
 
 EVENT_KINDS = {0: "direct", 1: "scatter", 2: "reflect", 3: "transmit", 4: "end", 5: "surface"}
@@ -313,9 +313,9 @@ class Context:
         self.check(rc, "ur_beamform_adjoint")
 
     def ur_trace_adjoint(self, seed, g_raw, amp=None, alpha=None, Z=None, sph_center=None, value=None,
-                         frozen_choice=False, ray_stride=1, ray_offset=0, stream=None):
+                         frozen_choice=False, ray_stride=1, ray_offset=0, record_paths=0, stream=None):
         d = GradDesc(amp=_ptr(amp), alpha=_ptr(alpha), Z=_ptr(Z), sph_center=_ptr(sph_center), value=_ptr(value),
-                     frozen_choice=1 if frozen_choice else 0)
+                     frozen_choice=1 if frozen_choice else 0, record_paths=int(record_paths))
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
         self.check(rc, "ur_trace_adjoint")

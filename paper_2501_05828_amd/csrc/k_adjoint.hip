@@ -17,6 +17,12 @@
 // gradients with respect to every scatterer amplitude (dc/da_k = c / a_k) and
 // every attenuation coefficient (d log c / d alpha_m = -kappa x path length in
 // material m).
+//
+// Every decision is taken on values, so it is the same in every pass.  The
+// value pass records, for a range of paths, each segment's closest primitive
+// and the captures that reach a contribution; the tangent passes over the
+// same range read them instead of walking the tree and the scatterer grid
+// again (a path with more captures than the record holds walks the grid).
 #include "trace_device.h"
 #include "ultraray.h"
 
@@ -92,6 +98,7 @@ struct AdjParams {
     double *value_out;       // [1] sum of g(t) c over the replayed contributions, or null
     double kappa;            // d ka / d alpha [Np/m per dB/(cm MHz)]
     int attach_choice;       // 1: keep R / value(R) on the path weight
+    AdjRecord rec;           // decisions kept from the value pass (the tangent passes replay them)
 };
 
 __device__ __forceinline__ D mat_Z(const AdjParams &A, int m) {
@@ -258,8 +265,18 @@ __device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx,
         }
 }
 
-__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray) {
+__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray, int64_t slot) {
     const TraceParams &P = A.P;
+    const bool record = A.rec.mode == 1, replay = A.rec.mode == 2;
+    AdjSeg *segs = A.rec.mode ? A.rec.seg + slot * (P.B + 1) : nullptr;
+    AdjCap *caps = A.rec.mode ? A.rec.cap + slot * kAdjCapRec : nullptr;
+    int ncap = 0;
+    bool walk_grid = true;
+    if (record) A.rec.ncap[slot] = 0;
+    if (replay && A.rec.ncap[slot] != kAdjCapOverflow) {
+        ncap = A.rec.ncap[slot];
+        walk_grid = false;
+    }
     double o0[3], d0[3], w0;
     int cell;
     emit(P, tx, e, ray, o0, d0, w0, cell);
@@ -270,93 +287,102 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
     int med = P.top_medium;
     int64_t last = -1;
     for (int b = 0; b <= P.B; ++b) {
-        // closest primitive by value
+        // closest primitive by value (or as the value pass recorded it)
         const double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
         double tbest = INFINITY;
         int face = -1;
-        for (int i = 0; i < 3; ++i) {
-            double tt;
-            int fi;
-            if (dv[i] > 0.0) {
-                tt = (P.box[3 + i] - ov[i]) / dv[i];
-                fi = 3 + i;
-            } else if (dv[i] < 0.0) {
-                tt = (P.box[i] - ov[i]) / dv[i];
-                fi = i;
-            } else {
-                continue;
-            }
-            if (tt < tbest) {
-                tbest = tt;
-                face = fi;
-            }
-        }
-        if (P.convex) {
-            // the convex array's cylinder (face 6), by value as in the trace
-            const double R = P.radius, aa = dv[0] * dv[0] + dv[2] * dv[2];
-            const double bq = ov[0] * dv[0] + (ov[2] + R) * dv[2];
-            const double cq = ov[0] * ov[0] + ov[2] * (ov[2] + 2.0 * R), disc = bq * bq - aa * cq;
-            if (bq < 0.0 && aa != 0.0 && disc >= 0.0) {
-                const double tt = cq / (-bq + sqrt(disc));
-                if (tt > kEpsT && tt < tbest) {
-                    tbest = tt;
-                    face = 6;
-                }
-            }
-        }
         int64_t hid = P.id_box;
         int hloc = -1;
-        if (P.n_tnodes > 0) {
-            const CullRay cr = make_cull(ov, dv);
-            float tmf = cull_tmax(tbest);
-            int ni = 0;
-            while (ni < P.n_tnodes) {
-                const Node n = load_node(P.tnodes, ni);
-                if (!slab(n, cr, tmf)) {
-                    ni = node_skip(n);
+        if (replay) {
+            const AdjSeg r = segs[b];
+            tbest = r.t;
+            hid = r.hid;
+            if (hid == P.id_box) face = r.aux;
+            else hloc = r.aux;
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                double tt;
+                int fi;
+                if (dv[i] > 0.0) {
+                    tt = (P.box[3 + i] - ov[i]) / dv[i];
+                    fi = 3 + i;
+                } else if (dv[i] < 0.0) {
+                    tt = (P.box[i] - ov[i]) / dv[i];
+                    fi = i;
+                } else {
                     continue;
                 }
-                const int leaf = node_leaf(n);
-                if (leaf < 0) {
-                    ++ni;
-                    continue;
+                if (tt < tbest) {
+                    tbest = tt;
+                    face = fi;
                 }
-                for (int k = leaf >> 4; k < (leaf >> 4) + (leaf & 15); ++k) {
-                    const int id = P.tri_id[k];
-                    if (id == last) continue;
-                    double tt;
-                    if (tri_isect(P.tri + 9 * (int64_t)k, ov, dv, tt) && tt > kEpsT &&
-                        (tt < tbest || (tt == tbest && id < hid))) {
+            }
+            if (P.convex) {
+                // the convex array's cylinder (face 6), by value as in the trace
+                const double R = P.radius, aa = dv[0] * dv[0] + dv[2] * dv[2];
+                const double bq = ov[0] * dv[0] + (ov[2] + R) * dv[2];
+                const double cq = ov[0] * ov[0] + ov[2] * (ov[2] + 2.0 * R), disc = bq * bq - aa * cq;
+                if (bq < 0.0 && aa != 0.0 && disc >= 0.0) {
+                    const double tt = cq / (-bq + sqrt(disc));
+                    if (tt > kEpsT && tt < tbest) {
                         tbest = tt;
-                        hid = id;
-                        hloc = k;
-                        tmf = cull_tmax(tt);
+                        face = 6;
                     }
                 }
-                ni = node_skip(n);
             }
-        }
-        for (int j = 0; j < P.n_sph; ++j) {
-            double t0, t1;
-            if (!sph_roots(P.sph + 4 * j, ov, dv, t0, t1)) continue;
-            const double tt = t0 > kEpsT ? t0 : t1;
-            if (!(tt > kEpsT)) continue;
-            const int64_t id = P.id_sph0 + j;
-            if (tt < tbest || (tt == tbest && id < hid)) {
-                tbest = tt;
-                hid = id;
-                hloc = j;
+            if (P.n_tnodes > 0) {
+                const CullRay cr = make_cull(ov, dv);
+                float tmf = cull_tmax(tbest);
+                int ni = 0;
+                while (ni < P.n_tnodes) {
+                    const Node n = load_node(P.tnodes, ni);
+                    if (!slab(n, cr, tmf)) {
+                        ni = node_skip(n);
+                        continue;
+                    }
+                    const int leaf = node_leaf(n);
+                    if (leaf < 0) {
+                        ++ni;
+                        continue;
+                    }
+                    for (int k = leaf >> 4; k < (leaf >> 4) + (leaf & 15); ++k) {
+                        const int id = P.tri_id[k];
+                        if (id == last) continue;
+                        double tt;
+                        if (tri_isect(P.tri + 9 * (int64_t)k, ov, dv, tt) && tt > kEpsT &&
+                            (tt < tbest || (tt == tbest && id < hid))) {
+                            tbest = tt;
+                            hid = id;
+                            hloc = k;
+                            tmf = cull_tmax(tt);
+                        }
+                    }
+                    ni = node_skip(n);
+                }
             }
-        }
-        for (int j = 0; j < P.n_pln; ++j) {
-            const int64_t id = P.id_pln0 + j;
-            double tt;
-            if (id == last || !pln_isect(P.pln + 4 * j, ov, dv, tt) || !(tt > kEpsT)) continue;
-            if (tt < tbest || (tt == tbest && id < hid)) {
-                tbest = tt;
-                hid = id;
-                hloc = j;
+            for (int j = 0; j < P.n_sph; ++j) {
+                double t0, t1;
+                if (!sph_roots(P.sph + 4 * j, ov, dv, t0, t1)) continue;
+                const double tt = t0 > kEpsT ? t0 : t1;
+                if (!(tt > kEpsT)) continue;
+                const int64_t id = P.id_sph0 + j;
+                if (tt < tbest || (tt == tbest && id < hid)) {
+                    tbest = tt;
+                    hid = id;
+                    hloc = j;
+                }
             }
+            for (int j = 0; j < P.n_pln; ++j) {
+                const int64_t id = P.id_pln0 + j;
+                double tt;
+                if (id == last || !pln_isect(P.pln + 4 * j, ov, dv, tt) || !(tt > kEpsT)) continue;
+                if (tt < tbest || (tt == tbest && id < hid)) {
+                    tbest = tt;
+                    hid = id;
+                    hloc = j;
+                }
+            }
+            if (record) segs[b] = AdjSeg{tbest, (int)hid, hid == P.id_box ? face : hloc};
         }
         // dual distance to the chosen primitive
         D th;
@@ -399,53 +425,84 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         // captures on [0, tseg) and their secondary rays
         if (P.n_scat > 0) {
             const Material M = P.mat[med];
-            dda_walk(P.grid, ov, dv, tseg.v, [&](int gcell, double ta, double tb) {
-                const int j1 = P.cell_start[gcell + 1];
-                for (int j = P.cell_start[gcell]; j < j1; ++j) {
-                    const double4 sk = P.items[j];
-                    const double p[3] = {sk.x - ov[0], sk.y - ov[1], sk.z - ov[2]};
-                    const double s = dot3(p, dv);
-                    if (!(s >= ta && s < tb)) continue;
-                    const double pp[3] = {p[0] - s * dv[0], p[1] - s * dv[1], p[2] - s * dv[2]};
-                    if (dot3(pp, pp) > P.r_s2) continue;
-                    const int k = P.item_id[j];
-                    const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
-                    const D sd = ddot(pd, d);
-                    const D q[3] = {o[0] + sd * d[0], o[1] + sd * d[1], o[2] + sd * d[2]};
-                    int e_lo, n_e;
-                    if (!elem_range(P, q[0].v, q[1].v, q[2].v, e_lo, n_e)) continue;
-                    uint32_t x[4];
-                    draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
-                    const int er = e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32);
-                    const double4 g = P.convex ? P.elem[er] : make_double4(P.xe[er], 0.0, 0.0, 1.0);
-                    const D v[3] = {dd(g.x) - q[0], -q[1], dd(g.y) - q[2]};
-                    const D dist = dsqrt(ddot(v, v));
-                    const D vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
-                    const D cos_a = P.convex ? -(vh[0] * dd(g.z) + vh[2] * dd(g.w)) : -vh[2];
-                    const D al = dacos(cos_a);
-                    D f;
-                    if (al.v > P.alpha_c) continue;
-                    if (al.v <= P.alpha_m) f = dd(1.0);
-                    else f = (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
-                    D T, sa, sc2;
-                    double lsh[kAdjMat];
-                    if (!shadow_d(A, q, vh, dist, med, T, sa, sc2, A.tan.kind == 0 ? lsh : nullptr)) continue;
-                    const D wq = w * dexp(-(M.ka * sd));
-                    const D tq = t + M.inv_c * sd;
-                    const D att = dexp(-(M.ka * dist + sa));
-                    const D tc = tq + M.inv_c * dist + sc2;
-                    const D cu = wq * dd((double)n_e * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
-                    const D cval = sk.w * cu;
-                    if (A.tan.kind == 0) {
-                        double lp[kAdjMat];
-                        for (int m = 0; m < kAdjMat; ++m) lp[m] = len_m[m] + (m == med ? sd.v : 0.0);
-                        contribute(A, acc, tx, er, cval, tc, k, cu.v, lp, lsh);
+            // one capture of item j whose secondary ray goes to element er of
+            // the n_e that could be drawn; recorded if it reaches a contribution
+            auto capture = [&](int j, int er, int n_e) {
+                const double4 sk = P.items[j];
+                const int k = P.item_id[j];
+                const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
+                const D sd = ddot(pd, d);
+                const D q[3] = {o[0] + sd * d[0], o[1] + sd * d[1], o[2] + sd * d[2]};
+                const double4 g = P.convex ? P.elem[er] : make_double4(P.xe[er], 0.0, 0.0, 1.0);
+                const D v[3] = {dd(g.x) - q[0], -q[1], dd(g.y) - q[2]};
+                const D dist = dsqrt(ddot(v, v));
+                const D vh[3] = {v[0] / dist, v[1] / dist, v[2] / dist};
+                const D cos_a = P.convex ? -(vh[0] * dd(g.z) + vh[2] * dd(g.w)) : -vh[2];
+                const D al = dacos(cos_a);
+                D f;
+                if (al.v > P.alpha_c) return;
+                if (al.v <= P.alpha_m) f = dd(1.0);
+                else f = (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
+                D T, sa, sc2;
+                double lsh[kAdjMat];
+                if (!shadow_d(A, q, vh, dist, med, T, sa, sc2, A.tan.kind == 0 ? lsh : nullptr)) return;
+                if (record) {
+                    if (ncap < kAdjCapRec) {
+                        caps[ncap] = AdjCap{j, (unsigned short)er, (unsigned short)b};
+                        A.rec.ncap[slot] = (unsigned char)++ncap;
                     } else {
-                        contribute(A, acc, tx, er, cval, tc, k, cu.v, nullptr, nullptr);
+                        A.rec.ncap[slot] = kAdjCapOverflow;
                     }
                 }
-                return true;
-            });
+                const D wq = w * dexp(-(M.ka * sd));
+                const D tq = t + M.inv_c * sd;
+                const D att = dexp(-(M.ka * dist + sa));
+                const D tc = tq + M.inv_c * dist + sc2;
+                const D cu = wq * dd((double)n_e * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
+                const D cval = sk.w * cu;
+                if (A.tan.kind == 0) {
+                    double lp[kAdjMat];
+                    for (int m = 0; m < kAdjMat; ++m) lp[m] = len_m[m] + (m == med ? sd.v : 0.0);
+                    contribute(A, acc, tx, er, cval, tc, k, cu.v, lp, lsh);
+                } else {
+                    contribute(A, acc, tx, er, cval, tc, k, cu.v, nullptr, nullptr);
+                }
+            };
+            if (walk_grid) {
+                dda_walk(P.grid, ov, dv, tseg.v, [&](int gcell, double ta, double tb) {
+                    const int j1 = P.cell_start[gcell + 1];
+                    for (int j = P.cell_start[gcell]; j < j1; ++j) {
+                        const double4 sk = P.items[j];
+                        const double p[3] = {sk.x - ov[0], sk.y - ov[1], sk.z - ov[2]};
+                        const double s = dot3(p, dv);
+                        if (!(s >= ta && s < tb)) continue;
+                        const double pp[3] = {p[0] - s * dv[0], p[1] - s * dv[1], p[2] - s * dv[2]};
+                        if (dot3(pp, pp) > P.r_s2) continue;
+                        const int k = P.item_id[j];
+                        const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
+                        const D sd = ddot(pd, d);
+                        int e_lo, n_e;
+                        if (!elem_range(P, o[0].v + sd.v * d[0].v, o[1].v + sd.v * d[1].v, o[2].v + sd.v * d[2].v,
+                                        e_lo, n_e))
+                            continue;
+                        uint32_t x[4];
+                        draw(P, ray, e, tx, b, 2, (uint32_t)k, x);
+                        capture(j, e_lo + (int)(((uint64_t)x[0] * (uint64_t)n_e) >> 32), n_e);
+                    }
+                    return true;
+                });
+            } else {
+                for (int c = 0; c < ncap; ++c) {
+                    const AdjCap r = caps[c];
+                    if (r.seg != b) continue;
+                    const double4 sk = P.items[r.item];
+                    const D pd[3] = {dd(sk.x) - o[0], dd(sk.y) - o[1], dd(sk.z) - o[2]};
+                    const D sd = ddot(pd, d);
+                    int e_lo, n_e;
+                    elem_range(P, o[0].v + sd.v * d[0].v, o[1].v + sd.v * d[1].v, o[2].v + sd.v * d[2].v, e_lo, n_e);
+                    capture(r.item, r.er, n_e);
+                }
+            }
         }
         // transport
         const Material M = P.mat[med];
@@ -574,11 +631,12 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     acc.tan = 0.0;
     for (int m = 0; m < kAdjMat; ++m) acc.alpha[m] = 0.0;
     const TraceParams &P = A.P;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n_work) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = A.rec.begin + slot;
+    if (i < A.rec.end) {
         const int64_t q = i / P.per_el;
         const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray);
+        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot);
     }
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;
@@ -615,7 +673,7 @@ hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s) {
 
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
                             double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
-                            hipStream_t s) {
+                            const AdjRecord &rec, hipStream_t s) {
     AdjParams A;
     A.P = p;
     A.tan = Tangent{kind, index, coord};
@@ -626,9 +684,10 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int c
     A.value_out = value_out;
     A.kappa = kappa;
     A.attach_choice = attach_choice;
-    if (kind != 0) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, grad_out, 1);
-    if (p.n_work <= 0) return hipGetLastError();
-    const int64_t blocks = (p.n_work + 255) / 256;
+    A.rec = rec;
+    const int64_t n = rec.end - rec.begin;
+    if (n <= 0) return hipGetLastError();
+    const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_replay, dim3((unsigned)blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }

@@ -37,6 +37,9 @@ struct DevBuf {
 // gives every device that loads the library its own copy, held until the
 // process ends.  Host code never uses the symbol itself as an address: it
 // takes each device's address once (static_scratch) and passes that.
+// Bound on the adjoint's record buffers (paths of one range times their decisions).
+constexpr size_t kAdjRecBytes = size_t(512) << 20;
+
 constexpr int64_t kStaticHeader = 64;                  // floats (256 bytes)
 constexpr int64_t kStaticPixels = int64_t(1) << 22;    // 2048 x 2048 pixels, 16 MiB
 static __device__ __align__(256) float scratch[kStaticHeader + kStaticPixels];
@@ -79,6 +82,7 @@ struct ur_context {
     bool mlp_ready = false;
     int mlp_rows = 0, mlp_step = 0;
     DevBuf d_giq;                          // adjoint of IQ inside ur_beamform_adjoint
+    DevBuf d_adj_seg, d_adj_cap, d_adj_ncap;   // decisions of the adjoint's value pass over a range of paths
     DevBuf d_elem, d_ze;                   // convex arrays: element centre / normal table, centre depths
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
@@ -367,7 +371,7 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
                       &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal, &c->d_segq, &c->d_segc,
-                      &c->d_giq, &c->d_elem, &c->d_ze})
+                      &c->d_giq, &c->d_elem, &c->d_ze, &c->d_adj_seg, &c->d_adj_cap, &c->d_adj_ncap})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1185,6 +1189,7 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
             return c->fail(UR_ERR_INVALID_ARG, "no output requested");
         if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
             return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
+        if (grads->record_paths < 0) return c->fail(UR_ERR_INVALID_ARG, "record_paths must be >= 0");
         const int n_mat = (int)(c->mat.size() / 3);
         if (grads->alpha && n_mat > kAdjMaxMat)
             return c->fail(UR_ERR_UNSUPPORTED, "attenuation gradients support at most %d materials", kAdjMaxMat);
@@ -1200,18 +1205,49 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         if (grads->amp) HIP_TRY(c, zero_f32(grads->amp, c->n_scat, s));
         if (grads->alpha) HIP_TRY(c, ur_launch_zero_f64(grads->alpha, n_mat, s));
         if (grads->value) HIP_TRY(c, ur_launch_zero_f64(grads->value, 1, s));
-        if (grads->amp || grads->alpha || grads->value)
-            HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, grads->value, kappa,
-                                        1, s));
-        if (grads->Z)
-            for (int m = 0; m < n_mat; ++m)
-                HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, nullptr, kappa,
-                                            !grads->frozen_choice, s));
-        if (grads->sph_center)
-            for (int j = 0; j < (int)c->n_sph; ++j)
-                for (int k = 0; k < 3; ++k)
-                    HIP_TRY(c, ur_launch_replay(P, 2, j, k, g_raw_dev, nullptr, nullptr, grads->sph_center + 3 * j + k,
-                                                nullptr, kappa, !grads->frozen_choice, s));
+        if (grads->Z) HIP_TRY(c, ur_launch_zero_f64(grads->Z, n_mat, s));
+        if (grads->sph_center) HIP_TRY(c, ur_launch_zero_f64(grads->sph_center, 3 * (int)c->n_sph, s));
+        const int n_tan = (grads->Z ? n_mat : 0) + (grads->sph_center ? 3 * (int)c->n_sph : 0);
+        const bool value_pass = grads->amp || grads->alpha || grads->value;
+        // With tangent passes the paths go in ranges: the value pass over a
+        // range records its decisions and the tangent passes replay them.
+        // Element and segment indices are kept in 16 bits.
+        ur_status st;
+        const bool use_rec = n_tan > 0 && P.E <= 65535 && P.B < 65535;
+        const size_t per_ray = (size_t)(P.B + 1) * sizeof(AdjSeg) + kAdjCapRec * sizeof(AdjCap) + 1;
+        const int64_t fit = std::max<int64_t>(1, (int64_t)(kAdjRecBytes / per_ray));
+        const int64_t range = !use_rec ? std::max<int64_t>(1, P.n_work)
+                                       : std::max<int64_t>(1, std::min(P.n_work, grads->record_paths > 0
+                                                                                      ? grads->record_paths
+                                                                                      : fit));
+        if (use_rec) {
+            if ((st = alloc(c, c->d_adj_seg, (size_t)range * (P.B + 1) * sizeof(AdjSeg)))) return st;
+            if ((st = alloc(c, c->d_adj_cap, (size_t)range * kAdjCapRec * sizeof(AdjCap)))) return st;
+            if ((st = alloc(c, c->d_adj_ncap, (size_t)range))) return st;
+        }
+        for (int64_t b0 = 0; b0 < P.n_work; b0 += range) {
+            AdjRecord rec{0, b0, std::min(P.n_work, b0 + range), nullptr, nullptr, nullptr};
+            if (use_rec) {
+                rec.seg = (AdjSeg *)c->d_adj_seg.p;
+                rec.cap = (AdjCap *)c->d_adj_cap.p;
+                rec.ncap = (unsigned char *)c->d_adj_ncap.p;
+                rec.mode = 1;
+            }
+            if (value_pass || use_rec)
+                HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, grads->value,
+                                            kappa, 1, rec, s));
+            if (use_rec) rec.mode = 2;
+            if (grads->Z)
+                for (int m = 0; m < n_mat; ++m)
+                    HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, nullptr, kappa,
+                                                !grads->frozen_choice, rec, s));
+            if (grads->sph_center)
+                for (int j = 0; j < (int)c->n_sph; ++j)
+                    for (int k = 0; k < 3; ++k)
+                        HIP_TRY(c, ur_launch_replay(P, 2, j, k, g_raw_dev, nullptr, nullptr,
+                                                    grads->sph_center + 3 * j + k, nullptr, kappa,
+                                                    !grads->frozen_choice, rec, s));
+        }
         return UR_OK;
     });
 }

@@ -208,8 +208,30 @@ hipError_t ur_launch_das_adj(const ur::DasParams &p, const float2 *g_iq, float *
 hipError_t ur_launch_pulse_adj(const float2 *g_rf, float *g_raw, const float2 *taps, int K, int64_t n_ch, int S,
                                hipStream_t s);
 hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s);
+// The decisions of the adjoint's value pass over a range of paths, kept for
+// its tangent passes: per path and segment the closest primitive and its
+// distance, and per path up to kAdjCapRec captures that reach a contribution.
+struct AdjSeg {
+    double t;       // distance to the closest primitive
+    int hid;        // its id
+    int aux;        // its triangle slot, sphere or plane index, or the box face
+};
+struct AdjCap {
+    int item;               // scatterer item (grid order)
+    unsigned short er;      // receiving element drawn
+    unsigned short seg;     // segment of the path
+};
+constexpr int kAdjCapRec = 8;
+constexpr unsigned char kAdjCapOverflow = 255;   // more captures than kAdjCapRec: walk the grid again
+struct AdjRecord {
+    int mode;               // 0 none, 1 record, 2 replay from the record
+    int64_t begin, end;     // work items of the range
+    AdjSeg *seg;            // [end - begin][B + 1]
+    AdjCap *cap;            // [end - begin][kAdjCapRec]
+    unsigned char *ncap;    // [end - begin]
+};
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
                             double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
-                            hipStream_t s);
+                            const AdjRecord &rec, hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);

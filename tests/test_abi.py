@@ -40,10 +40,11 @@ def test_struct_layouts_match_header(tmp_path):
     import ctypes
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ultraray.h"\nint main(void){\n'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ur_scene_desc),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ur_scene_desc),'
                     ' sizeof(ur_probe_desc), sizeof(ur_acq_desc), sizeof(ur_grid_desc), sizeof(ur_trace_stats),'
                     ' sizeof(ur_event), sizeof(ur_ray), offsetof(ur_trace_stats, kernel_ms),'
-                    ' offsetof(ur_acq_desc, angles), sizeof(ur_grad_desc), offsetof(ur_grad_desc, frozen_choice));\n'
+                    ' offsetof(ur_acq_desc, angles), sizeof(ur_grad_desc), offsetof(ur_grad_desc, frozen_choice),'
+                    ' offsetof(ur_grad_desc, record_paths));\n'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -51,7 +52,7 @@ def test_struct_layouts_match_header(tmp_path):
     want = [ctypes.sizeof(B.SceneDesc), ctypes.sizeof(B.ProbeDesc), ctypes.sizeof(B.AcqDesc),
             ctypes.sizeof(B.GridDesc), ctypes.sizeof(B.TraceStats), ctypes.sizeof(B.Event), ctypes.sizeof(B.Ray),
             B.TraceStats.kernel_ms.offset, B.AcqDesc.angles.offset, ctypes.sizeof(B.GradDesc),
-            B.GradDesc.frozen_choice.offset]
+            B.GradDesc.frozen_choice.offset, B.GradDesc.record_paths.offset]
     assert got == want
 
 

@@ -303,7 +303,7 @@ def test_trace_adjoint_convex_array(oracle, torch_gpu):
 
 
 # ------------------------------------------------ against the FP64 oracle gradient
-def _gpu_grads(s, w, gt, stride=1, frozen=True):
+def _gpu_grads(s, w, gt, stride=1, frozen=True, record_paths=0):
     import torch
     sc = w.scene
     nm, ns, K = len(sc.materials), len(sc.sph), len(sc.scat)
@@ -313,7 +313,7 @@ def _gpu_grads(s, w, gt, stride=1, frozen=True):
     ag = torch.empty(K, device="cuda") if K else None
     v = torch.zeros(1, dtype=torch.float64, device="cuda")
     s.ctx.ur_trace_adjoint(w.seed, gt, amp=ag, alpha=al, Z=Z, sph_center=cg, value=v, frozen_choice=frozen,
-                           ray_stride=stride)
+                           ray_stride=stride, record_paths=record_paths)
     return dict(J=float(v.item()), z=Z.cpu().numpy(), alpha=al.cpu().numpy(),
                 sph=cg.cpu().numpy() if ns else np.zeros((0, 3)),
                 amp=ag.double().cpu().numpy() if K else np.zeros(0))
@@ -351,6 +351,38 @@ def test_trace_adjoint_matches_oracle_gradient(oracle, tiny_adj, frozen):
     ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=not frozen)
     assert np.count_nonzero(ref["sph"]) == 3 and np.count_nonzero(ref["amp"]) > 100
     _assert_matches_oracle(got, ref, f"tiny frozen={frozen}")
+
+
+def test_trace_adjoint_record_ranges_and_capture_overflow(oracle, torch_gpu):
+    """The tangent passes replay the value pass's record of each path's
+    decisions, range by range.  120k scatterers packed in the slab the plane
+    wave crosses (x +-10 mm, y +-2 mm, z 1-19 mm) give about eight
+    contributing captures a path, so a large share of the paths overflow the
+    record's 8 captures and walk the scatterer grid again while the others
+    replay their recorded captures; ranges of 333 paths leave a ragged last
+    range.  Both range sizes match the oracle's gradient, and each other to
+    FP64 summation order."""
+    mm = 1e-3
+    w = _workload(rays=256)
+    rng = np.random.default_rng(5)
+    pos = rng.uniform([-10 * mm, -2 * mm, 1 * mm], [10 * mm, 2 * mm, 19 * mm], size=(120_000, 3))
+    w = _with_scene(w, scat=np.hstack([pos, rng.normal(size=(120_000, 1))]))
+    g = _smooth_adjoint((w.acq.n_tx, w.acq.n_elements, w.acq.n_samples), 27)
+    s = _sim(w)
+    st = s.trace(stats=True, pulse=False)
+    per_path = st["records"] / st["rays"]
+    print(f"[adjoint-record] records per path {per_path:.2f}", flush=True)
+    assert per_path > 5.0
+    gt = torch_gpu.from_numpy(g).cuda()
+    ranged = _gpu_grads(s, w, gt, frozen=False, record_paths=333)
+    whole = _gpu_grads(s, w, gt, frozen=False)
+    ref = oracle.trace_grad(w, g.astype(np.float64), attach_choice=True)
+    assert np.count_nonzero(ref["sph"]) == 3 and np.count_nonzero(ref["z"]) >= 3
+    _assert_matches_oracle(ranged, ref, "dense slab, ranges of 333 paths")
+    _assert_matches_oracle(whole, ref, "dense slab, one range")
+    for key in ("z", "sph"):
+        a, b = ranged[key].ravel(), whole[key].ravel()
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max(), key
 
 
 def test_trace_adjoint_matches_oracle_gradient_convex(oracle, torch_gpu):
