@@ -23,6 +23,7 @@
 // and the captures that reach a contribution; the tangent passes over the
 // same range read them instead of walking the tree and the scatterer grid
 // again (a path with more captures than the record holds walks the grid).
+#include "closest_hit.h"
 #include "trace_device.h"
 #include "ultraray.h"
 
@@ -265,7 +266,7 @@ __device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx,
         }
 }
 
-__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray, int64_t slot) {
+__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray, int64_t slot, LdsStack stk) {
     const TraceParams &P = A.P;
     const bool record = A.rec.mode == 1, replay = A.rec.mode == 2;
     AdjSeg *segs = A.rec.mode ? A.rec.seg + slot * (P.B + 1) : nullptr;
@@ -300,88 +301,13 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
             if (hid == P.id_box) face = r.aux;
             else hloc = r.aux;
         } else {
-            for (int i = 0; i < 3; ++i) {
-                double tt;
-                int fi;
-                if (dv[i] > 0.0) {
-                    tt = (P.box[3 + i] - ov[i]) / dv[i];
-                    fi = 3 + i;
-                } else if (dv[i] < 0.0) {
-                    tt = (P.box[i] - ov[i]) / dv[i];
-                    fi = i;
-                } else {
-                    continue;
-                }
-                if (tt < tbest) {
-                    tbest = tt;
-                    face = fi;
-                }
-            }
-            if (P.convex) {
-                // the convex array's cylinder (face 6), by value as in the trace
-                const double R = P.radius, aa = dv[0] * dv[0] + dv[2] * dv[2];
-                const double bq = ov[0] * dv[0] + (ov[2] + R) * dv[2];
-                const double cq = ov[0] * ov[0] + ov[2] * (ov[2] + 2.0 * R), disc = bq * bq - aa * cq;
-                if (bq < 0.0 && aa != 0.0 && disc >= 0.0) {
-                    const double tt = cq / (-bq + sqrt(disc));
-                    if (tt > kEpsT && tt < tbest) {
-                        tbest = tt;
-                        face = 6;
-                    }
-                }
-            }
-            if (P.n_tnodes > 0) {
-                const CullRay cr = make_cull(ov, dv);
-                float tmf = cull_tmax(tbest);
-                int ni = 0;
-                while (ni < P.n_tnodes) {
-                    const Node n = load_node(P.tnodes, ni);
-                    if (!slab(n, cr, tmf)) {
-                        ni = node_skip(n);
-                        continue;
-                    }
-                    const int leaf = node_leaf(n);
-                    if (leaf < 0) {
-                        ++ni;
-                        continue;
-                    }
-                    for (int k = leaf >> 4; k < (leaf >> 4) + (leaf & 15); ++k) {
-                        const int id = P.tri_id[k];
-                        if (id == last) continue;
-                        double tt;
-                        if (tri_isect(P.tri + 9 * (int64_t)k, ov, dv, tt) && tt > kEpsT &&
-                            (tt < tbest || (tt == tbest && id < hid))) {
-                            tbest = tt;
-                            hid = id;
-                            hloc = k;
-                            tmf = cull_tmax(tt);
-                        }
-                    }
-                    ni = node_skip(n);
-                }
-            }
-            for (int j = 0; j < P.n_sph; ++j) {
-                double t0, t1;
-                if (!sph_roots(P.sph + 4 * j, ov, dv, t0, t1)) continue;
-                const double tt = t0 > kEpsT ? t0 : t1;
-                if (!(tt > kEpsT)) continue;
-                const int64_t id = P.id_sph0 + j;
-                if (tt < tbest || (tt == tbest && id < hid)) {
-                    tbest = tt;
-                    hid = id;
-                    hloc = j;
-                }
-            }
-            for (int j = 0; j < P.n_pln; ++j) {
-                const int64_t id = P.id_pln0 + j;
-                double tt;
-                if (id == last || !pln_isect(P.pln + 4 * j, ov, dv, tt) || !(tt > kEpsT)) continue;
-                if (tt < tbest || (tt == tbest && id < hid)) {
-                    tbest = tt;
-                    hid = id;
-                    hloc = j;
-                }
-            }
+            // the trace's own query: box exit, spheres, planes, four-wide tree
+            Counters cnt;
+            const Hit h = closest_hit<false>(P, ov, dv, last, stk, cnt);
+            tbest = h.t;
+            hid = h.id;
+            face = h.face;
+            hloc = h.local;
             if (record) segs[b] = AdjSeg{tbest, (int)hid, hid == P.id_box ? face : hloc};
         }
         // dual distance to the chosen primitive
@@ -621,7 +547,8 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
             med = after;
         }
         for (int i = 0; i < 3; ++i) d[i] = nd[i];
-        last = (hid < P.id_sph0 || hid >= P.id_pln0) ? hid : -1;
+        // the flat primitive just left: a triangle by its slot, a plane by id
+        last = hid < P.id_sph0 ? hloc : (hid >= P.id_pln0 ? hid : -1);
     }
 }
 
@@ -631,12 +558,14 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     acc.tan = 0.0;
     for (int m = 0; m < kAdjMat; ++m) acc.alpha[m] = 0.0;
     const TraceParams &P = A.P;
+    __shared__ int2 s_stack[kStack * 256];
+    const LdsStack stk{s_stack + threadIdx.x, 256};
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = A.rec.begin + slot;
     if (i < A.rec.end) {
         const int64_t q = i / P.per_el;
         const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot);
+        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot, stk);
     }
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;
