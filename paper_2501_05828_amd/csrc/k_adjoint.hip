@@ -266,6 +266,9 @@ __device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx,
         }
 }
 
+// LEN: the value pass with attenuation gradients, which tracks the length
+// each path and secondary ray spends in every material.
+template <bool LEN>
 __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray, int64_t slot, LdsStack stk) {
     const TraceParams &P = A.P;
     const bool record = A.rec.mode == 1, replay = A.rec.mode == 2;
@@ -283,8 +286,8 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
     emit(P, tx, e, ray, o0, d0, w0, cell);
     D o[3] = {dd(o0[0]), dd(o0[1]), dd(o0[2])}, d[3] = {dd(d0[0]), dd(d0[1]), dd(d0[2])};
     D w = dd(w0), t = dd(P.tau[(int64_t)tx * P.E + e]), len = dd(0.0);
-    double len_m[kAdjMat];
-    for (int m = 0; m < kAdjMat; ++m) len_m[m] = 0.0;
+    double len_m[LEN ? kAdjMat : 1];
+    for (int m = 0; m < (LEN ? kAdjMat : 1); ++m) len_m[m] = 0.0;
     int med = P.top_medium;
     int64_t last = -1;
     for (int b = 0; b <= P.B; ++b) {
@@ -370,8 +373,8 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                 if (al.v <= P.alpha_m) f = dd(1.0);
                 else f = (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
                 D T, sa, sc2;
-                double lsh[kAdjMat];
-                if (!shadow_d(A, q, vh, dist, med, T, sa, sc2, A.tan.kind == 0 ? lsh : nullptr)) return;
+                double lsh[LEN ? kAdjMat : 1];
+                if (!shadow_d(A, q, vh, dist, med, T, sa, sc2, LEN ? lsh : nullptr)) return;
                 if (record) {
                     if (ncap < kAdjCapRec) {
                         caps[ncap] = AdjCap{j, (unsigned short)er, (unsigned short)b};
@@ -386,7 +389,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                 const D tc = tq + M.inv_c * dist + sc2;
                 const D cu = wq * dd((double)n_e * P.area_e / (4.0 * M_PI)) * cos_a * f / (dist * dist) * T * att;
                 const D cval = sk.w * cu;
-                if (A.tan.kind == 0) {
+                if constexpr (LEN) {
                     double lp[kAdjMat];
                     for (int m = 0; m < kAdjMat; ++m) lp[m] = len_m[m] + (m == med ? sd.v : 0.0);
                     contribute(A, acc, tx, er, cval, tc, k, cu.v, lp, lsh);
@@ -435,8 +438,9 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         w = w * dexp(-(M.ka * tseg));
         t = t + M.inv_c * tseg;
         len = len + tseg;
-        for (int m = 0; m < kAdjMat; ++m)
-            if (m == med) len_m[m] += tseg.v;
+        if constexpr (LEN)
+            for (int m = 0; m < kAdjMat; ++m)
+                if (m == med) len_m[m] += tseg.v;
         for (int i = 0; i < 3; ++i) o[i] = o[i] + tseg * d[i];
         if (clipped || t.v >= P.t_max) return;
         if (hid == P.id_box) {
@@ -450,7 +454,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                         const D al = dacos(-(d[0] * dd(g.z) + d[2] * dd(g.w)));
                         if (al.v <= P.alpha_c) {
                             const D f = al.v <= P.alpha_m ? dd(1.0) : (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
-                            contribute(A, acc, tx, er, w * f, t, -1, 0.0, len_m, nullptr);
+                            contribute(A, acc, tx, er, w * f, t, -1, 0.0, LEN ? len_m : nullptr, nullptr);
                         }
                     }
                 }
@@ -462,7 +466,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                 const D al = dacos(-d[2]);
                 if (al.v <= P.alpha_c) {
                     const D f = al.v <= P.alpha_m ? dd(1.0) : (dd(P.alpha_c) - al) / dd(P.alpha_c - P.alpha_m);
-                    contribute(A, acc, tx, er, w * f, t, -1, 0.0, len_m, nullptr);
+                    contribute(A, acc, tx, er, w * f, t, -1, 0.0, LEN ? len_m : nullptr, nullptr);
                 }
             }
             return;
@@ -552,7 +556,17 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
     }
 }
 
-__global__ __launch_bounds__(256) void k_replay(AdjParams A) {
+// Waves per SIMD the register allocation is held to: the dual-number state
+// needs about 300 registers a lane, so one wave fits without spilling; two
+// waves (256 registers and some spills to scratch) hide more latency and are
+// faster (measured: one 3.18 s, two 2.08 s, three 2.89 s for all gradients of
+// the large scene at every 4th ray).
+#ifndef UR_REPLAY_WAVES
+#define UR_REPLAY_WAVES 2
+#endif
+template <bool LEN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_REPLAY_WAVES, UR_REPLAY_WAVES))) void k_replay(
+    AdjParams A) {
     Acc acc;
     acc.val = 0.0;
     acc.tan = 0.0;
@@ -565,7 +579,7 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
     if (i < A.rec.end) {
         const int64_t q = i / P.per_el;
         const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        replay_path(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot, stk);
+        replay_path<LEN>(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot, stk);
     }
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;
@@ -578,7 +592,7 @@ __global__ __launch_bounds__(256) void k_replay(AdjParams A) {
         double v = acc.tan;
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0 && v != 0.0) atomicAdd(A.grad_out, v);
-    } else if (A.grad_alpha) {
+    } else if (LEN && A.grad_alpha) {
         for (int m = 0; m < kAdjMat && m < P.n_mat; ++m) {
             double v = acc.alpha[m];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -617,6 +631,9 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int c
     const int64_t n = rec.end - rec.begin;
     if (n <= 0) return hipGetLastError();
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_replay, dim3((unsigned)blocks), dim3(256), 0, s, A);
+    if (kind == 0 && grad_alpha)
+        hipLaunchKernelGGL(k_replay<true>, dim3((unsigned)blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_replay<false>, dim3((unsigned)blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
