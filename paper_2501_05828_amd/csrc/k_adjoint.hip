@@ -269,28 +269,71 @@ __device__ __forceinline__ void contribute(const AdjParams &A, Acc &acc, int tx,
 // LEN: the value pass with attenuation gradients, which tracks the length
 // each path and secondary ray spends in every material.
 template <bool LEN>
-__device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_t ray, int64_t slot, LdsStack stk) {
+__device__ void replay_paths(const AdjParams &A, Acc &acc, LdsStack stk) {
     const TraceParams &P = A.P;
     const bool record = A.rec.mode == 1, replay = A.rec.mode == 2;
-    AdjSeg *segs = A.rec.mode ? A.rec.seg + slot * (P.B + 1) : nullptr;
-    AdjCap *caps = A.rec.mode ? A.rec.cap + slot * kAdjCapRec : nullptr;
+    const int lane = threadIdx.x & 63;
+    // Persistent lanes: a lane whose path has ended takes the next one of the
+    // range (one atomic per wavefront and refill), so that a wavefront does
+    // not wait for its longest path; every iteration is one segment.
+    int tx = 0, e = 0;
+    uint32_t ray = 0;
+    int64_t slot = 0;
+    AdjSeg *segs = nullptr;
+    AdjCap *caps = nullptr;
     int ncap = 0;
     bool walk_grid = true;
-    if (record) A.rec.ncap[slot] = 0;
-    if (replay && A.rec.ncap[slot] != kAdjCapOverflow) {
-        ncap = A.rec.ncap[slot];
-        walk_grid = false;
-    }
-    double o0[3], d0[3], w0;
-    int cell;
-    emit(P, tx, e, ray, o0, d0, w0, cell);
-    D o[3] = {dd(o0[0]), dd(o0[1]), dd(o0[2])}, d[3] = {dd(d0[0]), dd(d0[1]), dd(d0[2])};
-    D w = dd(w0), t = dd(P.tau[(int64_t)tx * P.E + e]), len = dd(0.0);
+    D o[3], d[3], w, t, len;
     double len_m[LEN ? kAdjMat : 1];
-    for (int m = 0; m < (LEN ? kAdjMat : 1); ++m) len_m[m] = 0.0;
-    int med = P.top_medium;
+    int med = 0, b = 0;
     int64_t last = -1;
-    for (int b = 0; b <= P.B; ++b) {
+    bool live = false, done = false;
+    for (;;) {
+        const unsigned long long need = __ballot(!live && !done);
+        if (need) {
+            const int first = __ffsll((long long)need) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(A.rec.next, (unsigned long long)__popcll(need));
+            base = __shfl(base, first, 64);
+            if (!live && !done) {
+                const int64_t i = A.rec.begin + (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
+                if (i < A.rec.end) {
+                    slot = i - A.rec.begin;
+                    const int64_t q = i / P.per_el;
+                    ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
+                    tx = P.sa ? (int)q : (int)(q / P.E);
+                    e = P.sa ? (int)q : (int)(q % P.E);
+                    segs = A.rec.mode ? A.rec.seg + slot * (P.B + 1) : nullptr;
+                    caps = A.rec.mode ? A.rec.cap + slot * kAdjCapRec : nullptr;
+                    ncap = 0;
+                    walk_grid = true;
+                    if (record) A.rec.ncap[slot] = 0;
+                    if (replay && A.rec.ncap[slot] != kAdjCapOverflow) {
+                        ncap = A.rec.ncap[slot];
+                        walk_grid = false;
+                    }
+                    double o0[3], d0[3], w0;
+                    int cell;
+                    emit(P, tx, e, ray, o0, d0, w0, cell);
+                    for (int k = 0; k < 3; ++k) {
+                        o[k] = dd(o0[k]);
+                        d[k] = dd(d0[k]);
+                    }
+                    w = dd(w0);
+                    t = dd(P.tau[(int64_t)tx * P.E + e]);
+                    len = dd(0.0);
+                    for (int m = 0; m < (LEN ? kAdjMat : 1); ++m) len_m[m] = 0.0;
+                    med = P.top_medium;
+                    last = -1;
+                    b = 0;
+                    live = true;
+                } else {
+                    done = true;
+                }
+            }
+        }
+        if (!__any(live)) break;
+        if (!live) continue;
         // closest primitive by value (or as the value pass recorded it)
         const double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
         double tbest = INFINITY;
@@ -442,7 +485,10 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
             for (int m = 0; m < kAdjMat; ++m)
                 if (m == med) len_m[m] += tseg.v;
         for (int i = 0; i < 3; ++i) o[i] = o[i] + tseg * d[i];
-        if (clipped || t.v >= P.t_max) return;
+        if (clipped || t.v >= P.t_max) {
+            live = false;
+            continue;
+        }
         if (hid == P.id_box) {
             if (P.convex) {
                 if (face == 6 && fabs(o[1].v) <= 0.5 * P.elev) {
@@ -458,7 +504,8 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                         }
                     }
                 }
-                return;
+                live = false;
+                continue;
             }
             if (face == 2 && fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev) {
                 int er = (int)floor((o[0].v + P.half_ap) / P.pitch);
@@ -469,9 +516,13 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
                     contribute(A, acc, tx, er, w * f, t, -1, 0.0, LEN ? len_m : nullptr, nullptr);
                 }
             }
-            return;
+            live = false;
+            continue;
         }
-        if (b == P.B) return;
+        if (b == P.B) {
+            live = false;
+            continue;
+        }
         // interface: dual normal, Eqs. 7-11, attached choice probability
         D ng[3];
         int mf, mb;
@@ -511,7 +562,10 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         if (alpha > 0.0) {
             dggx_sample(ng, alpha, u01(x[1]), u01(x[2]), mn);
             cn = -ddot(d, ng);
-            if (!(-ddot(d, mn).v > 0.0)) return;
+            if (!(-ddot(d, mn).v > 0.0)) {
+                live = false;
+                continue;
+            }
         }
         const D cos_r = -ddot(d, mn);
         const D eta = z1 / z2;
@@ -539,7 +593,10 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
             // a new direction on the wrong side of the surface is absorbed;
             // else the weight factor |i.mn| G1(i) G1(o) / (|i.n| |mn.n|)
             const D co = ddot(nd, ng);
-            if (refl ? !(co.v > 0.0) : !(co.v < 0.0)) return;
+            if (refl ? !(co.v > 0.0) : !(co.v < 0.0)) {
+                live = false;
+                continue;
+            }
             w = w * (cos_r * dggx_g1(alpha, cn) * dggx_g1(alpha, co.v < 0.0 ? -co : co) / (cn * ddot(mn, ng)));
         }
         if (refl) {
@@ -553,6 +610,7 @@ __device__ void replay_path(const AdjParams &A, Acc &acc, int tx, int e, uint32_
         for (int i = 0; i < 3; ++i) d[i] = nd[i];
         // the flat primitive just left: a triangle by its slot, a plane by id
         last = hid < P.id_sph0 ? hloc : (hid >= P.id_pln0 ? hid : -1);
+        ++b;
     }
 }
 
@@ -574,13 +632,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UR_REPLAY_W
     const TraceParams &P = A.P;
     __shared__ int2 s_stack[kStack * 256];
     const LdsStack stk{s_stack + threadIdx.x, 256};
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = A.rec.begin + slot;
-    if (i < A.rec.end) {
-        const int64_t q = i / P.per_el;
-        const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        replay_path<LEN>(A, acc, P.sa ? (int)q : (int)(q / P.E), P.sa ? (int)q : (int)(q % P.E), ray, slot, stk);
-    }
+    replay_paths<LEN>(A, acc, stk);
     // wavefront sums, one atomic per wavefront and output
     const int lane = threadIdx.x & 63;
     if (A.value_out) {
@@ -614,6 +666,25 @@ hipError_t ur_launch_zero_f64(double *p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+// Blocks of 256 that stay resident at once (the persistent grid).
+template <class K>
+hipError_t replay_blocks(K kernel, int64_t needed, unsigned &blocks) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+    if (e != hipSuccess) return e;
+    const int64_t resident = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+    blocks = (unsigned)(needed < resident ? (needed > 0 ? needed : 1) : resident);
+    return hipSuccess;
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0) *p = 0ull;
+}
+}  // namespace
+
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
                             double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
                             const AdjRecord &rec, hipStream_t s) {
@@ -630,10 +701,16 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int c
     A.rec = rec;
     const int64_t n = rec.end - rec.begin;
     if (n <= 0) return hipGetLastError();
-    const int64_t blocks = (n + 255) / 256;
-    if (kind == 0 && grad_alpha)
-        hipLaunchKernelGGL(k_replay<true>, dim3((unsigned)blocks), dim3(256), 0, s, A);
+    if (!rec.next) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, rec.next);
+    const bool len = kind == 0 && grad_alpha;
+    unsigned blocks = 1;
+    const hipError_t e = len ? replay_blocks(k_replay<true>, (n + 255) / 256, blocks)
+                             : replay_blocks(k_replay<false>, (n + 255) / 256, blocks);
+    if (e != hipSuccess) return e;
+    if (len)
+        hipLaunchKernelGGL(k_replay<true>, dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL(k_replay<false>, dim3((unsigned)blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_replay<false>, dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }

@@ -83,6 +83,7 @@ struct ur_context {
     int mlp_rows = 0, mlp_step = 0;
     DevBuf d_giq;                          // adjoint of IQ inside ur_beamform_adjoint
     DevBuf d_adj_seg, d_adj_cap, d_adj_ncap;   // decisions of the adjoint's value pass over a range of paths
+    DevBuf d_adj_next;                     // work counter of the adjoint's persistent replay
     DevBuf d_elem, d_ze;                   // convex arrays: element centre / normal table, centre depths
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
@@ -371,7 +372,7 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
                       &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal, &c->d_segq, &c->d_segc,
-                      &c->d_giq, &c->d_elem, &c->d_ze, &c->d_adj_seg, &c->d_adj_cap, &c->d_adj_ncap})
+                      &c->d_giq, &c->d_elem, &c->d_ze, &c->d_adj_seg, &c->d_adj_cap, &c->d_adj_ncap, &c->d_adj_next})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1220,13 +1221,15 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
                                        : std::max<int64_t>(1, std::min(P.n_work, grads->record_paths > 0
                                                                                       ? grads->record_paths
                                                                                       : fit));
+        if ((st = alloc(c, c->d_adj_next, sizeof(unsigned long long)))) return st;
         if (use_rec) {
             if ((st = alloc(c, c->d_adj_seg, (size_t)range * (P.B + 1) * sizeof(AdjSeg)))) return st;
             if ((st = alloc(c, c->d_adj_cap, (size_t)range * kAdjCapRec * sizeof(AdjCap)))) return st;
             if ((st = alloc(c, c->d_adj_ncap, (size_t)range))) return st;
         }
         for (int64_t b0 = 0; b0 < P.n_work; b0 += range) {
-            AdjRecord rec{0, b0, std::min(P.n_work, b0 + range), nullptr, nullptr, nullptr};
+            AdjRecord rec{0, b0, std::min(P.n_work, b0 + range), nullptr, nullptr, nullptr,
+                          (unsigned long long *)c->d_adj_next.p};
             if (use_rec) {
                 rec.seg = (AdjSeg *)c->d_adj_seg.p;
                 rec.cap = (AdjCap *)c->d_adj_cap.p;

@@ -229,6 +229,7 @@ struct AdjRecord {
     AdjSeg *seg;            // [end - begin][B + 1]
     AdjCap *cap;            // [end - begin][kAdjCapRec]
     unsigned char *ncap;    // [end - begin]
+    unsigned long long *next;   // work counter of the persistent lanes (zeroed by the launcher)
 };
 hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
                             double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
