@@ -482,8 +482,9 @@ typedef struct ur_grad_desc {
  * cleared first) the derivative of L through every binned contribution c at
  * arrival time t: g(t) dc + c g'(t) dt, where g' (the slope of g between
  * sample centres) is non-zero only with linear binning.  Amplitude and
- * attenuation gradients come from one replay; every impedance and every
- * sphere coordinate takes one forward-mode (dual number) replay.  The same
+ * attenuation gradients come from one replay; the impedances and sphere
+ * coordinates come from forward-mode (dual number) replays, two parameter
+ * directions per replay.  The same
  * proposal tables as the forward call must be set.  Rough boundaries
  * (Eq. 12) are supported when their echoes are received by direct hits only
  * (ur_acq_desc.rough_direct_only = 1): the GGX microfacet normal follows the

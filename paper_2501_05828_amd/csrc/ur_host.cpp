@@ -1208,7 +1208,13 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         if (grads->value) HIP_TRY(c, ur_launch_zero_f64(grads->value, 1, s));
         if (grads->Z) HIP_TRY(c, ur_launch_zero_f64(grads->Z, n_mat, s));
         if (grads->sph_center) HIP_TRY(c, ur_launch_zero_f64(grads->sph_center, 3 * (int)c->n_sph, s));
-        const int n_tan = (grads->Z ? n_mat : 0) + (grads->sph_center ? 3 * (int)c->n_sph : 0);
+        std::vector<AdjTangent> tans;
+        if (grads->Z)
+            for (int m = 0; m < n_mat; ++m) tans.push_back(AdjTangent{1, m, 0, grads->Z + m});
+        if (grads->sph_center)
+            for (int j = 0; j < (int)c->n_sph; ++j)
+                for (int k = 0; k < 3; ++k) tans.push_back(AdjTangent{2, j, k, grads->sph_center + 3 * j + k});
+        const int n_tan = (int)tans.size();
         const bool value_pass = grads->amp || grads->alpha || grads->value;
         // With tangent passes the paths go in ranges: the value pass over a
         // range records its decisions and the tangent passes replay them.
@@ -1237,19 +1243,12 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
                 rec.mode = 1;
             }
             if (value_pass || use_rec)
-                HIP_TRY(c, ur_launch_replay(P, 0, 0, 0, g_raw_dev, grads->amp, grads->alpha, nullptr, grads->value,
-                                            kappa, 1, rec, s));
+                HIP_TRY(c, ur_launch_replay(P, 0, nullptr, g_raw_dev, grads->amp, grads->alpha, grads->value, kappa, 1,
+                                            rec, s));
             if (use_rec) rec.mode = 2;
-            if (grads->Z)
-                for (int m = 0; m < n_mat; ++m)
-                    HIP_TRY(c, ur_launch_replay(P, 1, m, 0, g_raw_dev, nullptr, nullptr, grads->Z + m, nullptr, kappa,
-                                                !grads->frozen_choice, rec, s));
-            if (grads->sph_center)
-                for (int j = 0; j < (int)c->n_sph; ++j)
-                    for (int k = 0; k < 3; ++k)
-                        HIP_TRY(c, ur_launch_replay(P, 2, j, k, g_raw_dev, nullptr, nullptr,
-                                                    grads->sph_center + 3 * j + k, nullptr, kappa,
-                                                    !grads->frozen_choice, rec, s));
+            if (!tans.empty())
+                HIP_TRY(c, ur_launch_replay(P, (int)tans.size(), tans.data(), g_raw_dev, nullptr, nullptr, nullptr,
+                                            kappa, !grads->frozen_choice, rec, s));
         }
         return UR_OK;
     });

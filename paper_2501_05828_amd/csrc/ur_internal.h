@@ -231,8 +231,17 @@ struct AdjRecord {
     unsigned char *ncap;    // [end - begin]
     unsigned long long *next;   // work counter of the persistent lanes (zeroed by the launcher)
 };
-hipError_t ur_launch_replay(const ur::TraceParams &p, int kind, int index, int coord, const float *g, float *grad_amp,
-                            double *grad_alpha, double *grad_out, double *value_out, double kappa, int attach_choice,
+// One parameter direction of a tangent pass and where its derivative is added.
+struct AdjTangent {
+    int kind;       // 1: impedance of material index; 2: coordinate coord of sphere index
+    int index, coord;
+    double *out;    // [1] device accumulator
+};
+// n_tan = 0: the value pass (amplitudes into grad_amp, attenuations into
+// grad_alpha, J into value_out; each nullable); else the tangent passes of
+// the n_tan directions in tans (host array), a few per launch.
+hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangent *tans, const float *g,
+                            float *grad_amp, double *grad_alpha, double *value_out, double kappa, int attach_choice,
                             const AdjRecord &rec, hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);
