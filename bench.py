@@ -174,6 +174,56 @@ def c3_measure(reps_trace=2, reps_das=10):
             "das_roofline": das_roofline("batched", w.acq, w.grid, t_das)}
 
 
+def backward_measure(ray_stride=1):
+    """The differentiable large scene (192 elements, 21 plane waves, two
+    250k-triangle tubes, 4 spheres, 1e6 scatterers, linear binning) at full
+    size: the forward trace and the path-replay adjoint of all gradient
+    families at once (1e6 scatterer amplitudes, 6 attenuations, 6
+    impedances, 12 sphere-centre coordinates) for a fixed random channel-data
+    adjoint, each timed from the host around a synchronised call."""
+    import numpy as np
+    import torch
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.large()
+    sim = Simulator(w)
+    A, sc = w.acq, w.scene
+    rng = np.random.default_rng(41)
+    g = torch.from_numpy(rng.normal(size=(A.n_tx, A.n_elements, A.n_samples)).astype(np.float32)).cuda()
+    nm, ns, K = len(sc.materials), len(sc.sph), len(sc.scat)
+    amp = torch.empty(K, device="cuda")
+    al = torch.empty(nm, dtype=torch.float64, device="cuda")
+    Z = torch.empty(nm, dtype=torch.float64, device="cuda")
+    cen = torch.empty((ns, 3), dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    fwd = lambda: sim.trace(pulse=False, ray_stride=ray_stride)
+    bwd = lambda: sim.ctx.ur_trace_adjoint(w.seed, g, amp=amp, alpha=al, Z=Z, sph_center=cen,
+                                           ray_stride=ray_stride, frozen_choice=True)
+    timed(fwd)
+    t_f = timed(fwd)
+    timed(bwd)
+    t_b = timed(bwd)
+    per_el = (A.rays_per_element + ray_stride - 1) // ray_stride
+    paths = A.n_tx * A.n_elements * per_el
+    print(f"[bench] backward: forward {t_f * 1e3:.1f} ms, adjoint {t_b * 1e3:.1f} ms ({t_b / t_f:.1f} x)",
+          file=sys.stderr, flush=True)
+    return {"workload": "differentiable large scene: 192 elements, 21 plane waves, two 250k-triangle tubes, "
+                        "4 spheres, 1e6 scatterers, linear binning, every path of the frame",
+            "paths": paths, "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+            "backward_paths_per_s": paths / t_b, "x_forward": t_b / t_f,
+            "gradients": {"amplitudes": K, "attenuations": nm, "impedances": nm, "sphere_coordinates": 3 * ns},
+            "directions_per_tangent_pass": 2}
+
+
 def load_traffic(workload):
     """HBM bytes per launch of the extend kernel (the frame's total over its
     equal launch ranges, divided by their number) from the committed
@@ -472,6 +522,8 @@ def main():
     ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the batched-workload trace and DAS measurement")
     ap.add_argument("--c3-only", action="store_true", help="run only the batched-workload trace and DAS measurement")
+    ap.add_argument("--no-backward", action="store_true", help="skip the adjoint measurement on the large scene")
+    ap.add_argument("--backward-only", action="store_true", help="run only the adjoint measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -495,6 +547,9 @@ def main():
         return
     if args.experiment == "binning":
         binning_experiment(args)
+        return
+    if args.backward_only:
+        print(json.dumps(backward_measure()))
         return
     if args.c3_only:
         print(json.dumps(c3_measure()))
@@ -620,6 +675,8 @@ def main():
     }
     if not args.no_c3 and w.name == "bone":
         out["batched"] = c3_measure()
+    if not args.no_backward and w.name == "bone":
+        out["backward"] = backward_measure()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rays)
     print(json.dumps(out))
