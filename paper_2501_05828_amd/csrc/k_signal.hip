@@ -98,11 +98,17 @@ __device__ __forceinline__ SplitIdx das_tx(const DasParams &p, double x, double 
     return split_idx(x * c.x + z * c.y + c.z);
 }
 
+// Buffer resource word 3 of a raw (unformatted, unswizzled) buffer on gfx9.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Delay-and-sum over K transmits t0 .. t0 + K - 1 of one pixel: for every
 // element, the K gathers of the two neighbouring complex samples are issued
-// together (branch-free: an index outside the record reads sample 0 of the
-// same channel with weight 0), then interpolated and summed, and the sum is
-// weighted by the element's apodisation.
+// together, then interpolated and summed, and the sum is weighted by the
+// element's apodisation.  Each gather is one 16-byte buffer load through a
+// resource spanning exactly the channel's S samples (its base is the same for
+// the whole wavefront, so the lane adds only a 32-bit offset).  A term whose
+// index is outside the record loads from offset 2^31, beyond the resource,
+// where the hardware returns zeros: it adds nothing, whatever its weights.
 template <int K>
 __device__ __forceinline__ void das_transmits(const DasParams &p, double x, double z, int t0, float &re, float &im) {
     SplitIdx tt[K];
@@ -118,11 +124,12 @@ __device__ __forceinline__ void das_transmits(const DasParams &p, double x, doub
             int i0;
             float fr;
             const bool in = das_term_index(rx, tt[k], p.S, i0, fr);
-            // channel base (the same for all lanes) + a 32-bit byte offset
-            const float2 *s = (const float2 *)((const char *)(ch + k * tstride) + (uint32_t)(in ? i0 : 0) * 8u);
-            v0[k] = s[0];
-            v1[k] = s[1];
-            wt[k] = in ? make_float2(1.0f - fr, fr) : make_float2(0.0f, 0.0f);
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float2 *>(ch + k * tstride), (short)0, p.S * 8, kRawBufferWord3);
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(in ? (uint32_t)i0 * 8u : 0x80000000u), 0, 0);
+            v0[k] = make_float2(__uint_as_float(q[0]), __uint_as_float(q[1]));
+            v1[k] = make_float2(__uint_as_float(q[2]), __uint_as_float(q[3]));
+            wt[k] = make_float2(1.0f - fr, fr);
         }
         float er = 0.0f, ei = 0.0f;
 #pragma unroll
