@@ -1931,6 +1931,408 @@ int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, i
     return grad_impl(a, s, 1, 1, rays, n, g, attach_choice, J, grad_z, grad_alpha, grad_sph, grad_amp);
 }
 
+/* ----------------------------------------- element-edge terms of direct hits */
+/* A direct hit is recorded into the element whose face holds its landing
+ * point on the array's plane, so its contribution jumps where the landing
+ * point crosses an element edge, an end of the aperture or an elevation
+ * edge, and a geometry parameter theta that moves landing points moves these
+ * jumps: or_trace_grad's interior derivative leaves their terms out.  Here
+ * they are integrated exactly along one random number: the emission origin's
+ * lateral coordinate u0 on the element face (Eq. 4), the direction, the
+ * elevation coordinate and every choice held fixed.  For such a family of
+ * paths F(u0) = c(u0) h(u0) (c the recorded value, h the adjoint g(t) of
+ * the element holding the landing point x, 0 outside the aperture) and, by
+ * the Leibniz rule on [0, 1], d/dtheta of its integral is the interior term
+ * plus, at every u0* where x crosses an edge,
+ *     [F] dx_n/dtheta / |dx_n/du0|,
+ * [F] the jump of F across the edge in the direction of increasing x_n (x_n
+ * the landing coordinate normal to the edge).  The crossings are found by
+ * evaluating the family at n_scan + 1 evenly spaced u0 and halving every
+ * interval whose ends follow different sequences of primitives and choices
+ * (down to 1e-12), then by safeguarded Newton steps inside each interval
+ * that follows one sequence.  The derivatives at u0* come from dual numbers with u0 and every
+ * parameter as tangents.  Linear arrays, smooth boundaries, uniform
+ * emission; the reflect-or-transmit choice is attached, as the result
+ * estimates the derivative of the expected data. */
+typedef struct {
+    int inside;      /* the landing point lies on an element */
+    int64_t er;      /* that element */
+    dnum x[2];       /* landing point (x, y) on the array's plane */
+    dnum c, t;       /* weight x receive directivity (whether inside or not), arrival time */
+    uint64_t sig;    /* the sequence of primitives and choices */
+} ed_out;
+
+/* Replays the family's path at origin coordinate u0 (tangent 0: u0; the
+ * parameters' tangents come with G's Z and cen).  Returns 1 if it ends on
+ * the array's plane within the bounce, time and length limits. */
+static int ed_path(const gctx *G, int64_t tx, int64_t e, uint32_t ray, double u0, ed_out *out)
+{
+    const octx *C = G->C;
+    const or_acq *a = C->a;
+    const or_scene *sc = C->s;
+    uint32_t x[4];
+    draw(C, ray, e, tx, 0, 0, 0, x);
+    double hl[3];
+    or_hemisphere(unif(x[2]), unif(x[3]), hl);
+    dnum o[3], d[3];
+    o[0] = dn_c(C->xe[e] + (u0 - 0.5) * a->pitch);
+    o[0].t[0] = a->pitch;
+    o[1] = dn_c((unif(x[1]) - 0.5) * a->elevation);
+    o[2] = dn_c(0.0);
+    for (int i = 0; i < 3; ++i) d[i] = dn_c(hl[i]);
+    const double pdf = 1.0 / (2.0 * PI);
+    dnum w = dn_c(hl[2] / (C->n_per_tx * pdf)), t = dn_c(C->tau[tx * a->n_elements + e]), len = dn_c(0.0);
+    int64_t med = sc->top_medium, last = -1;
+    uint64_t sig = 1469598103934665603ull;
+    for (int64_t b = 0; b <= a->max_bounces; ++b) {
+        double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
+        hit h = closest(C, ov, dv, last);
+        dnum tseg = grad_distance(G, &h, o, d);
+        int clipped = 0;
+        if (len.v + tseg.v > a->max_path) {
+            tseg = dn_sub(dn_c(a->max_path), len);
+            clipped = 1;
+        }
+        w = dn_mul(w, dn_exp(dn_neg(dn_mul(G->ka[med], tseg))));
+        t = dn_add(t, dn_mulc(tseg, C->inv_c[med]));
+        len = dn_add(len, tseg);
+        for (int i = 0; i < 3; ++i) o[i] = dn_add(o[i], dn_mul(tseg, d[i]));
+        if (clipped || t.v >= C->t_max) return 0;
+        sig = (sig ^ (uint64_t)(8 * (h.id + 1) + h.face + 1)) * 1099511628211ull;
+        if (h.id == C->id_box) {
+            if (h.face != 2) return 0;
+            out->x[0] = o[0];
+            out->x[1] = o[1];
+            out->inside = fabs(o[0].v) <= C->half_ap && fabs(o[1].v) <= 0.5 * a->elevation;
+            int64_t er = (int64_t)floor((o[0].v + C->half_ap) / a->pitch);
+            out->er = er < 0 ? 0 : (er > a->n_elements - 1 ? a->n_elements - 1 : er);
+            dnum al = dn_acos(dn_neg(d[2]));
+            out->c = or_directivity(al.v, a->alpha_m, a->alpha_c) > 0.0
+                         ? dn_mul(w, dn_directivity(al, a->alpha_m, a->alpha_c)) : dn_c(0.0);
+            out->t = t;
+            out->sig = sig;
+            return 1;
+        }
+        if (b == a->max_bounces) return 0;
+        dnum ng[3];
+        int64_t mf, mb;
+        if (h.id < C->id_sph0) {
+            double n[3];
+            tri_normal(sc->tri + 9 * h.id, n);
+            for (int i = 0; i < 3; ++i) ng[i] = dn_c(n[i]);
+            mf = sc->tri_mat[2 * h.id];
+            mb = sc->tri_mat[2 * h.id + 1];
+        } else if (h.id < C->id_pln0) {
+            int64_t j = h.id - C->id_sph0;
+            for (int i = 0; i < 3; ++i) ng[i] = dn_divc(dn_sub(o[i], G->cen[3 * j + i]), sc->sph[4 * j + 3]);
+            mf = sc->sph_mat[2 * j];
+            mb = sc->sph_mat[2 * j + 1];
+        } else {
+            const double *pl = sc->pln + 4 * (h.id - C->id_pln0);
+            for (int i = 0; i < 3; ++i) ng[i] = dn_c(pl[i]);
+            mf = sc->pln_mat[2 * (h.id - C->id_pln0)];
+            mb = sc->pln_mat[2 * (h.id - C->id_pln0) + 1];
+        }
+        int64_t before, after;
+        if (dn_dot(d, ng).v < 0.0) {
+            before = mf;
+            after = mb;
+        } else {
+            before = mb;
+            after = mf;
+            for (int i = 0; i < 3; ++i) ng[i] = dn_neg(ng[i]);
+        }
+        dnum z1 = G->Z[before], z2 = G->Z[after];
+        draw(C, ray, e, tx, b, 1, 0, x);
+        double y = unif(x[0]);
+        dnum cos_r = dn_neg(dn_dot(d, ng));
+        dnum eta = dn_div(z1, z2);
+        dnum rad = dn_sub(dn_c(1.0), dn_mul(dn_mul(eta, eta), dn_sub(dn_c(1.0), dn_mul(cos_r, cos_r))));
+        dnum R = dn_c(1.0), cos_t = dn_c(0.0);
+        if (rad.v >= 0.0) {
+            cos_t = dn_sqrt(rad);
+            dnum den = dn_add(dn_mul(z1, cos_r), dn_mul(z2, cos_t));
+            if (den.v != 0.0) {
+                dnum Ar = dn_div(dn_sub(dn_mul(z1, cos_r), dn_mul(z2, cos_t)), den);
+                R = dn_mul(Ar, Ar);
+            }
+        }
+        dnum nd[3];
+        int refl = y < R.v;
+        if (refl) {
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(d[i], dn_mul(dn_mulc(cos_r, 2.0), ng[i]));
+            if (G->attach) w = dn_mul(w, dn_divc(R, R.v));
+            med = before;
+        } else {
+            dnum f = dn_sub(dn_mul(eta, cos_r), cos_t);
+            for (int i = 0; i < 3; ++i) nd[i] = dn_add(dn_mul(eta, d[i]), dn_mul(f, ng[i]));
+            dnum Tr = dn_sub(dn_c(1.0), R);
+            if (G->attach) w = dn_mul(w, dn_divc(Tr, Tr.v));
+            med = after;
+        }
+        dnum l = dn_sqrt(dn_dot(nd, nd));
+        for (int i = 0; i < 3; ++i) d[i] = dn_div(nd[i], l);
+        sig = (sig ^ (uint64_t)(2 + refl)) * 1099511628211ull;
+        last = (h.id < C->id_sph0 || h.id >= C->id_pln0) ? h.id : -1;
+    }
+    return 0;
+}
+
+/* The adjoint g of element er at time t (as grad_record); 0 outside the
+ * recorded window. */
+static double ed_adj(const octx *C, const double *g, int64_t tx, int64_t er, double t)
+{
+    const or_acq *a = C->a;
+    if (!(t < C->t_max) || t < 0.0) return 0.0;
+    const double *ch = g + (tx * a->n_elements + er) * a->n_samples;
+    double x = t * a->f_s;
+    if (a->binning == 0) {
+        int64_t n = (int64_t)floor(x);
+        return (n >= 0 && n < a->n_samples) ? ch[n] : 0.0;
+    }
+    double tau = x - 0.5, f0 = floor(tau), f = tau - f0;
+    int64_t n0 = (int64_t)f0;
+    double g0 = (n0 >= 0 && n0 < a->n_samples) ? ch[n0] : 0.0;
+    double g1 = (n0 + 1 >= 0 && n0 + 1 < a->n_samples) ? ch[n0 + 1] : 0.0;
+    return (1.0 - f) * g0 + f * g1;
+}
+
+/* The u0 in (ua, ub) where landing coordinate k crosses X, by Newton steps
+ * kept inside the bracket (bisection when a step leaves it), on paths with
+ * the sequence sig.  Returns 1 with the path there, 0 if the sequence
+ * changes on the way. */
+static int ed_root(const gctx *G, int64_t tx, int64_t e, uint32_t ray, double ua, double ub, double fa, int k,
+                   double X, uint64_t sig, ed_out *out)
+{
+    double u = 0.5 * (ua + ub);
+    for (int it = 0; it < 100; ++it) {
+        if (!ed_path(G, tx, e, ray, u, out) || out->sig != sig) return 0;
+        double f = out->x[k].v - X, df = out->x[k].t[0];
+        if (f == 0.0 || ub - ua < 1e-15) return 1;
+        if ((f < 0.0) == (fa < 0.0)) {
+            ua = u;
+            fa = f;
+        } else {
+            ub = u;
+        }
+        double un = df != 0.0 ? u - f / df : 0.5 * (ua + ub);
+        if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);
+        if (un == u) return 1;
+        u = un;
+    }
+    return 1;
+}
+
+/* The edge crossings of the family on [ua, ub] (landings A at ua and B at
+ * ub, if any), added to acc: an interval whose ends follow different
+ * sequences is halved until each part follows one (parts narrower than
+ * 1e-12 are dropped). */
+static void ed_interval(const gctx *G, const double *g, int64_t tx, int64_t e, uint32_t ray, double ua, int ha,
+                        const ed_out *A, double ub, int hb, const ed_out *B, int depth, double *acc, int np)
+{
+    const octx *C = G->C;
+    const or_acq *a = C->a;
+    if (!ha && !hb) return;
+    if (!ha || !hb || A->sig != B->sig) {
+        if (depth >= 48 || ub - ua < 1e-12) return;
+        const double um = 0.5 * (ua + ub);
+        ed_out M;
+        const int hm = ed_path(G, tx, e, ray, um, &M);
+        ed_interval(G, g, tx, e, ray, ua, ha, A, um, hm, &M, depth + 1, acc, np);
+        ed_interval(G, g, tx, e, ray, um, hm, &M, ub, hb, B, depth + 1, acc, np);
+        return;
+    }
+    ed_out at;
+    const double half_el = 0.5 * a->elevation;
+    /* element edges and aperture ends crossed in x */
+    const double xa = A->x[0].v, xb = B->x[0].v;
+    const double lo = xa < xb ? xa : xb, hi = xa < xb ? xb : xa;
+    for (int64_t k = 0; k <= a->n_elements; ++k) {
+        const double X = -C->half_ap + (double)k * a->pitch;
+        if (!(X > lo && X < hi)) continue;
+        if (!ed_root(G, tx, e, ray, ua, ub, xa - X, 0, X, A->sig, &at)) continue;
+        if (!(fabs(at.x[1].v) <= half_el)) continue;
+        const double hr = k < a->n_elements ? ed_adj(C, g, tx, k, at.t.v) : 0.0;
+        const double hl = k > 0 ? ed_adj(C, g, tx, k - 1, at.t.v) : 0.0;
+        const double jump = at.c.v * (hr - hl), du = fabs(at.x[0].t[0]);
+        if (!(du > 0.0)) continue;
+        for (int p = 0; p < np; ++p) acc[p] += jump * at.x[0].t[1 + p] / du;
+    }
+    /* elevation edges crossed in y: inside below the edge in |y|, so F
+     * jumps by -F_in across +Y and by +F_in across -Y */
+    const double ya = A->x[1].v, yb = B->x[1].v;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const double Y = sgn * half_el;
+        if (!((ya - Y) * (yb - Y) < 0.0)) continue;
+        if (!ed_root(G, tx, e, ray, ua, ub, ya - Y, 1, Y, A->sig, &at)) continue;
+        if (!(fabs(at.x[0].v) <= C->half_ap)) continue;
+        const double fin = at.c.v * ed_adj(C, g, tx, at.er, at.t.v);
+        const double jump = sgn > 0 ? -fin : fin, du = fabs(at.x[1].t[0]);
+        if (!(du > 0.0)) continue;
+        for (int p = 0; p < np; ++p) acc[p] += jump * at.x[1].t[1 + p] / du;
+    }
+}
+
+/* Parameters of the edge replays: impedances (tangents 1 ..), then sphere
+ * centres; tangent 0 is the origin coordinate u0. */
+static int ed_setup(const or_acq *a, const or_scene *s, int attach, octx *C, gctx *G)
+{
+    if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
+        a->rays_per_element < 0 || a->max_bounces < 0 || a->cdf != NULL || a->scheme == 1)
+        return -1;
+    if (a->radius != 0.0) return -2;
+    if (1 + s->n_mat + 3 * s->n_sph > GRAD_MAX) return -1;
+    if (s->rough)
+        for (int64_t m = 0; m < s->n_mat; ++m)
+            if (s->rough[m] > 0.0) return -3;
+    int rc = ctx_init(C, a, s);
+    if (rc) {
+        ctx_free(C);
+        return rc;
+    }
+    g_nt = (int)(1 + s->n_mat + 3 * s->n_sph);
+    G->C = C;
+    G->g = NULL;
+    G->attach = attach;
+    G->n_mat = (int)s->n_mat;
+    G->Z = (dnum *)malloc(sizeof(dnum) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    G->ka = (dnum *)malloc(sizeof(dnum) * (size_t)(s->n_mat > 0 ? s->n_mat : 1));
+    G->cen = (dnum *)malloc(sizeof(dnum) * (size_t)(3 * s->n_sph + 1));
+    for (int64_t m = 0; m < s->n_mat; ++m) {
+        G->Z[m] = dn_c(s->mat[3 * m]);
+        G->Z[m].t[1 + m] = 1.0;
+        G->ka[m] = dn_c(C->ka[m]);
+    }
+    for (int64_t j = 0; j < 3 * s->n_sph; ++j) {
+        G->cen[j] = dn_c(s->sph[4 * (j / 3) + j % 3]);
+        G->cen[j].t[1 + s->n_mat + j] = 1.0;
+    }
+    return 0;
+}
+
+static void ed_free(octx *C, gctx *G)
+{
+    free(G->Z);
+    free(G->ka);
+    free(G->cen);
+    ctx_free(C);
+}
+
+/* The edge term of one family, added to acc [np]. */
+static void ed_family(const gctx *G, const double *g, int64_t tx, int64_t e, uint32_t ray, int n_scan, double *acc,
+                      int np)
+{
+    ed_out prev, cur;
+    int have_prev = ed_path(G, tx, e, ray, 0.0, &prev);
+    for (int j = 1; j <= n_scan; ++j) {
+        const double ua = (double)(j - 1) / n_scan, ub = (double)j / n_scan;
+        int have = ed_path(G, tx, e, ray, ub, &cur);
+        ed_interval(G, g, tx, e, ray, ua, have_prev, &prev, ub, have, &cur, 0, acc, np);
+        prev = cur;
+        have_prev = have;
+    }
+}
+
+int or_trace_grad_edges(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const double *g,
+                        int n_scan, double *corr_z, double *corr_sph)
+{
+    if (ray_stride <= 0 || !g || n_scan < 1) return -1;
+    octx C;
+    gctx G;
+    int rc = ed_setup(a, s, 1, &C, &G);
+    if (rc) return rc;
+    G.g = g;
+    const int np = (int)(s->n_mat + 3 * s->n_sph);
+    int nt = n_threads;
+#ifdef _OPENMP
+    if (nt <= 0) nt = omp_get_max_threads();
+#else
+    nt = 1;
+#endif
+    if (nt < 1) nt = 1;
+    double *acc = (double *)calloc((size_t)nt * (size_t)(np > 0 ? np : 1), sizeof(double));
+    int64_t per_el = (a->rays_per_element + ray_stride - 1) / ray_stride;
+    int64_t n_work = a->n_tx * a->n_elements * per_el;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+#endif
+    for (int64_t i = 0; i < n_work; ++i) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int64_t rr = (i % per_el) * ray_stride;
+        int64_t e = (i / per_el) % a->n_elements;
+        int64_t tx = i / (per_el * a->n_elements);
+        ed_family(&G, g, tx, e, (uint32_t)rr, n_scan, acc + (size_t)tid * np, np);
+    }
+    for (int p = 0; p < np; ++p) {
+        double v = 0.0;
+        for (int i = 0; i < nt; ++i) v += acc[(size_t)i * np + p];
+        if (p < s->n_mat) {
+            if (corr_z) corr_z[p] = v;
+        } else if (corr_sph) {
+            corr_sph[p - s->n_mat] = v;
+        }
+    }
+    free(acc);
+    ed_free(&C, &G);
+    return 0;
+}
+
+/* One family (transmit tx, element e, ray) at the n origin coordinates u0:
+ * F = c g(t) (0 if the landing is off the elements or the path does not
+ * land), its interior derivative along every parameter dF [n][np]
+ * (g(t) dc + c g'(t) dt), the landing point X [n][2] (NaN if none) and the
+ * sequence sig [n] (0 if none); and the family's edge term B [np] from an
+ * n_scan scan.  attach 0 freezes the reflect-or-transmit choice. */
+int or_edge_family(const or_acq *a, const or_scene *s, const double *g, int64_t tx, int64_t e, int64_t ray, int attach,
+                   int64_t n, const double *u0, double *F, double *dF, double *X, uint64_t *sig, int n_scan, double *B)
+{
+    if (!g || n < 0 || (n > 0 && (!u0 || !F || !dF || !X || !sig)) || n_scan < 1 || !B || tx < 0 || tx >= a->n_tx ||
+        e < 0 || e >= a->n_elements || ray < 0 || ray >= a->rays_per_element)
+        return -1;
+    octx C;
+    gctx G;
+    int rc = ed_setup(a, s, attach, &C, &G);
+    if (rc) return rc;
+    G.g = g;
+    const int np = (int)(s->n_mat + 3 * s->n_sph);
+    for (int64_t i = 0; i < n; ++i) {
+        ed_out o;
+        F[i] = 0.0;
+        for (int p = 0; p < np; ++p) dF[i * np + p] = 0.0;
+        X[2 * i] = X[2 * i + 1] = NAN;
+        sig[i] = 0;
+        if (!ed_path(&G, tx, e, (uint32_t)ray, u0[i], &o)) continue;
+        X[2 * i] = o.x[0].v;
+        X[2 * i + 1] = o.x[1].v;
+        sig[i] = o.sig;
+        if (!o.inside || !(o.t.v < C.t_max) || o.t.v < 0.0) continue;
+        const double *ch = g + (tx * a->n_elements + o.er) * a->n_samples;
+        double gv, gs;
+        double x = o.t.v * a->f_s;
+        if (a->binning == 0) {
+            int64_t k = (int64_t)floor(x);
+            gv = (k >= 0 && k < a->n_samples) ? ch[k] : 0.0;
+            gs = 0.0;
+        } else {
+            double tau = x - 0.5, f0 = floor(tau), f = tau - f0;
+            int64_t k = (int64_t)f0;
+            double g0 = (k >= 0 && k < a->n_samples) ? ch[k] : 0.0;
+            double g1 = (k + 1 >= 0 && k + 1 < a->n_samples) ? ch[k + 1] : 0.0;
+            gv = (1.0 - f) * g0 + f * g1;
+            gs = (g1 - g0) * a->f_s;
+        }
+        F[i] = o.c.v * gv;
+        for (int p = 0; p < np; ++p) dF[i * np + p] = o.c.t[1 + p] * gv + o.c.v * gs * o.t.t[1 + p];
+    }
+    for (int p = 0; p < np; ++p) B[p] = 0.0;
+    ed_family(&G, g, tx, e, (uint32_t)ray, n_scan, B, np);
+    ed_free(&C, &G);
+    return 0;
+}
+
 /* ---------------------------------------------------------------- pulse Eq. 14 */
 /* Analytic pulse h[m] = g(m/fs) (sin(2 pi fc m/fs) - i cos(2 pi fc m/fs)),
  * whose real part is Eq. 14 with the Gaussian written exp(-t^2/(2 sigma^2));

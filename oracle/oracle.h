@@ -101,6 +101,24 @@ int or_trace_grad(const or_acq *a, const or_scene *s, int n_threads, int64_t ray
 int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, int64_t n, const double *g,
                        int attach_choice, double *J, double *grad_z, double *grad_alpha, double *grad_sph,
                        double *grad_amp);
+/* Element-edge terms of the direct hits that or_trace_grad's interior
+ * derivative leaves out (element edges, aperture ends, elevation edges),
+ * integrated exactly along the emission origin's lateral coordinate: for
+ * every path family of or_trace_subset's paths, the crossings of the landing
+ * point over n_scan + 1 evenly spaced origins (choice attached).  corr_z
+ * [n_mat], corr_sph [n_sph][3] (each nullable).  Linear arrays and uniform
+ * emission only (-2 for a convex array); -3 for rough boundaries, -1 for
+ * bad arguments. */
+int or_trace_grad_edges(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const double *g,
+                        int n_scan, double *corr_z, double *corr_sph);
+/* One path family of or_trace_grad_edges (transmit tx, element e, ray):
+ * at the n origin coordinates u0, F = c g(t) (0 off the elements or without
+ * a landing), its interior derivative dF [n][n_mat + 3 n_sph], the landing
+ * point X [n][2] (NaN if none) and the sequence of primitives and choices
+ * sig [n] (0 if none); B [n_mat + 3 n_sph] the family's edge term from an
+ * n_scan scan.  attach 0 freezes the reflect-or-transmit choice. */
+int or_edge_family(const or_acq *a, const or_scene *s, const double *g, int64_t tx, int64_t e, int64_t ray, int attach,
+                   int64_t n, const double *u0, double *F, double *dF, double *X, uint64_t *sig, int n_scan, double *B);
 int or_pulse_taps(const or_acq *a, double *taps, int64_t cap);   /* returns K, taps [2K+1][2] */
 int or_pulse(const or_acq *a, int64_t n_channels, const double *ch_raw, double *ch_rf);
 /* Plane waves synthesised from synthetic-aperture data ch_sa [E][E][S]:

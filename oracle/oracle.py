@@ -103,6 +103,11 @@ def lib():
                      P(C.c_double)]
         L.or_trace_grad.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64] + grad_args
         L.or_trace_rays_grad.argtypes = [P(Acq), P(SceneS), P(Ray), C.c_int64] + grad_args
+        L.or_trace_grad_edges.argtypes = [P(Acq), P(SceneS), C.c_int, C.c_int64, P(C.c_double), C.c_int,
+                                          P(C.c_double), P(C.c_double)]
+        L.or_edge_family.argtypes = [P(Acq), P(SceneS), P(C.c_double), C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                     C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double),
+                                     P(C.c_uint64), C.c_int, P(C.c_double)]
         L.or_pulse_taps.argtypes = [P(Acq), P(C.c_double), C.c_int64]
         L.or_pulse.argtypes = [P(Acq), C.c_int64, P(C.c_double), P(C.c_double)]
         L.or_das.argtypes = [P(Acq), C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -299,6 +304,49 @@ def trace_grad(workload, g, attach_choice=False, ray_stride=1, n_threads=0, seed
     if rc != 0:
         raise RuntimeError(f"or_trace_grad failed ({rc})")
     return dict(J=J.value, z=gz, alpha=ga, sph=gs, amp=gk[:nk])
+
+
+def trace_grad_edges(workload, g, ray_stride=1, n_scan=16, n_threads=0, seed=None):
+    """Element-edge terms of the direct hits (element edges, aperture ends,
+    elevation edges) that trace_grad's interior derivative leaves out,
+    integrated exactly along the emission origin's lateral coordinate (choice
+    attached): dict(z [n_mat], sph [n_sph][3]).  trace_grad(...,
+    attach_choice=True) plus these estimates the derivative of the expected
+    data where direct hits carry the only discontinuities."""
+    keep = _Keep()
+    acq, sc = workload.acq, workload.scene
+    a = make_acq(acq, workload.seed if seed is None else seed, keep)
+    s = make_scene(sc, keep)
+    gg = keep.f64(np.ascontiguousarray(g, np.float64).reshape(acq.n_tx, acq.n_elements, acq.n_samples))
+    nm, ns = len(sc.materials), len(sc.sph)
+    cz, cs = np.zeros(nm), np.zeros((max(ns, 1), 3))
+    rc = lib().or_trace_grad_edges(C.byref(a), C.byref(s), int(n_threads), int(ray_stride), _dp(gg), int(n_scan),
+                                   _dp(cz), _dp(cs))
+    if rc != 0:
+        raise RuntimeError(f"or_trace_grad_edges failed ({rc})")
+    return dict(z=cz, sph=cs[:ns])
+
+
+def edge_family(workload, g, tx, e, ray, u0, attach=False, n_scan=16, seed=None):
+    """One path family of trace_grad_edges at the origin coordinates u0:
+    dict(F [n], dF [n][n_mat + 3 n_sph], X [n][2], sig [n], B [n_mat + 3 n_sph])
+    (see or_edge_family)."""
+    keep = _Keep()
+    acq, sc = workload.acq, workload.scene
+    a = make_acq(acq, workload.seed if seed is None else seed, keep)
+    s = make_scene(sc, keep)
+    gg = keep.f64(np.ascontiguousarray(g, np.float64).reshape(acq.n_tx, acq.n_elements, acq.n_samples))
+    np_ = len(sc.materials) + 3 * len(sc.sph)
+    uu = np.ascontiguousarray(u0, np.float64)
+    n = len(uu)
+    F, dF, X = np.zeros(n), np.zeros((n, np_)), np.zeros((n, 2))
+    sig, B = np.zeros(n, np.uint64), np.zeros(max(np_, 1))
+    rc = lib().or_edge_family(C.byref(a), C.byref(s), _dp(gg), int(tx), int(e), int(ray), int(bool(attach)), n,
+                              _dp(uu), _dp(F), _dp(dF), _dp(X), sig.ctypes.data_as(C.POINTER(C.c_uint64)),
+                              int(n_scan), _dp(B))
+    if rc != 0:
+        raise RuntimeError(f"or_edge_family failed ({rc})")
+    return dict(F=F, dF=dF, X=X, sig=sig, B=B[:np_])
 
 
 def pulse_taps(acq):
