@@ -498,6 +498,31 @@ typedef struct ur_grad_desc {
 UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                                   const float *g_raw_dev, const ur_grad_desc *grads, void *stream);
 
+/* Visibility-boundary terms of the direct hits (the paper's differentiable
+ * framework, Sec. 1 and Sec. 5), which ur_trace_adjoint's interior
+ * derivative leaves out: a direct hit is binned into the element whose face
+ * holds its landing point (Sec. 2.3), so its contribution jumps where that
+ * point crosses an element edge, an end of the aperture or an elevation
+ * edge, and impedances and sphere centres move the crossings.  The jumps are
+ * integrated exactly along the emission origin's lateral coordinate u0 on
+ * the element face (Eq. 4) of every path family of the same (seed,
+ * ray_stride, ray_offset) paths: n_scan + 1 evenly spaced origins per family,
+ * intervals whose ends follow different sequences of primitives and choices
+ * halved, every crossing located by Newton steps and weighted by the Leibniz
+ * rule, [F] dx/dtheta / |dx/du0|.  Accumulates (each output cleared first)
+ * corr_z_dev (double [n_mat]) and corr_sph_dev (double [n_sph][3]), each
+ * nullable; adding them to ur_trace_adjoint's Z and sph_center with the
+ * choice attached (frozen_choice = 0) estimates the derivative of the
+ * expected data when the direct hits carry the only discontinuities.
+ * g_raw_dev as for ur_trace_adjoint.  Linear arrays, plane-wave transmits,
+ * uniform emission, smooth boundaries (else UR_ERR_UNSUPPORTED).  Each
+ * parameter costs n_scan + 1 replays per family plus about 48 for every
+ * change of sequence along the origin, so meshes (a new triangle at every
+ * facet edge) make it far dearer than analytic scenes.  Async on `stream`. */
+UR_API ur_status ur_trace_grad_edges(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
+                                     const float *g_raw_dev, int32_t n_scan, double *corr_z_dev, double *corr_sph_dev,
+                                     void *stream);
+
 /* Philox4x32-10 evaluated on the device for n counters (host arrays
  * ctr [n][4], out [n][4]) under key (key0, key1); for checking that the
  * device stream equals the published generator.  Synchronous. */

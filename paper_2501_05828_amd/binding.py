@@ -129,6 +129,8 @@ SIGNATURES = [
     ("ur_beamform_adjoint", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
     ("ur_trace_adjoint", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, P(GradDesc), C.c_void_p]),
+    ("ur_trace_grad_edges", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
 ]
 
 _lib = None
@@ -319,6 +321,13 @@ class Context:
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
         self.check(rc, "ur_trace_adjoint")
+
+    def ur_trace_grad_edges(self, seed, g_raw, Z=None, sph_center=None, n_scan=16, ray_stride=1, ray_offset=0,
+                            stream=None):
+        rc = self.lib.ur_trace_grad_edges(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
+                                          int(ray_offset), _ptr(g_raw), int(n_scan), _ptr(Z), _ptr(sph_center),
+                                          _stream_ptr(stream))
+        self.check(rc, "ur_trace_grad_edges")
 
     def ur_scan_convert(self, sector, img, cart, out, fill=0.0, stream=None):
         gs, gc = _grid_desc(sector, UR_APOD_NONE, 90.0), _grid_desc(cart, UR_APOD_NONE, 90.0)

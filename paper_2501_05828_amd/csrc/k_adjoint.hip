@@ -827,3 +827,317 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangen
     }
     return hipSuccess;
 }
+
+// ---------------------------------------------------- direct-hit edge terms
+// A direct hit is binned into the element whose face holds its landing
+// point, so its contribution jumps where the landing point crosses an
+// element edge, an end of the aperture or an elevation edge; a geometry
+// parameter moves those crossings.  The term is integrated exactly along the
+// emission origin's lateral coordinate u0 (Eq. 4) of every path family, the
+// direction, elevation coordinate and choices held fixed: by the Leibniz rule
+// each crossing at u0* adds [F] dx_n/dtheta / |dx_n/du0|, F = c g(t) and [F]
+// its jump across the edge in the direction of increasing x_n.  The family is
+// evaluated at n_scan + 1 evenly spaced u0; an interval whose ends follow
+// different sequences of primitives and choices is halved (down to 1e-12 or
+// 48 levels), and inside an interval that follows one sequence every edge
+// between its landings is located by safeguarded Newton steps.  Linear
+// arrays, smooth boundaries, uniform emission, choice attached.  Dual
+// numbers carry two tangents: u0 and the parameter direction of the launch.
+namespace {
+using E2 = Rep<2>;
+using D2 = DK<2>;
+static_assert(kAdjTan >= 2, "the edge pass carries two directions: u0 and one parameter");
+
+struct EdgeHit {
+    bool inside;             // the landing point lies on an element
+    int er;                  // that element
+    D2 x[2];                 // landing point (x, y)
+    D2 c, t;                 // weight x receive directivity, arrival time
+    unsigned long long sig;  // the sequence of primitives and choices
+};
+
+// The family's path at origin coordinate u0; true if it ends on the array's
+// plane within the bounce, time and length limits.
+__device__ bool edge_path(const AdjParams &A, int tx, int e, uint32_t ray, double u0, LdsStack stk, EdgeHit &out) {
+    const TraceParams &P = A.P;
+    uint32_t x[4];
+    draw(P, ray, e, tx, 0, 0, 0, x);
+    double dv0[3];
+    hemisphere(u01(x[2]), u01(x[3]), dv0);
+    D2 o[3] = {E2::dd(P.xe[e] + (u0 - 0.5) * P.pitch), E2::dd((u01(x[1]) - 0.5) * P.elev), E2::dd(0.0)};
+    o[0].t[0] = P.pitch;
+    D2 d[3] = {E2::dd(dv0[0]), E2::dd(dv0[1]), E2::dd(dv0[2])};
+    D2 w = E2::dd(dv0[2] / (P.n_per_tx * (1.0 / (2.0 * M_PI)))), t = E2::dd(P.tau[(int64_t)tx * P.E + e]);
+    D2 len = E2::dd(0.0);
+    int med = P.top_medium;
+    int64_t last = -1;
+    unsigned long long sig = 1469598103934665603ull;
+    for (int b = 0; b <= P.B; ++b) {
+        const double ov[3] = {o[0].v, o[1].v, o[2].v}, dv[3] = {d[0].v, d[1].v, d[2].v};
+        Counters cnt;
+        const Hit h = closest_hit<false>(P, ov, dv, last, stk, cnt);
+        const int64_t hid = h.id;
+        const int hloc = h.local, face = h.face;
+        D2 th, sc[3];
+        double srad = 0.0;
+        if (hid == P.id_box) {
+            const int ax = face % 3;
+            th = (E2::dd(P.box[face]) - o[ax]) / d[ax];
+        } else if (hid < P.id_sph0) {
+            const double *tr = P.tri + 9 * (int64_t)hloc, *v0 = tr, *e1 = tr + 3, *e2 = tr + 6;
+            const D2 tq[3] = {o[0] - E2::dd(v0[0]), o[1] - E2::dd(v0[1]), o[2] - E2::dd(v0[2])};
+            const D2 pv[3] = {d[1] * E2::dd(e2[2]) - d[2] * E2::dd(e2[1]), d[2] * E2::dd(e2[0]) - d[0] * E2::dd(e2[2]),
+                              d[0] * E2::dd(e2[1]) - d[1] * E2::dd(e2[0])};
+            const D2 qq[3] = {tq[1] * E2::dd(e1[2]) - tq[2] * E2::dd(e1[1]),
+                              tq[2] * E2::dd(e1[0]) - tq[0] * E2::dd(e1[2]),
+                              tq[0] * E2::dd(e1[1]) - tq[1] * E2::dd(e1[0])};
+            th = ddot(qq, e2) / ddot(pv, e1);
+        } else if (hid < P.id_pln0) {
+            E2::sph_center(A, hloc, sc, &srad);
+            const D2 oc[3] = {o[0] - sc[0], o[1] - sc[1], o[2] - sc[2]};
+            const D2 bb = ddot(oc, d), cc = ddot(oc, oc) - E2::dd(srad * srad);
+            const D2 sq = dsqrt(bb * bb - cc);
+            const D2 r0 = -bb - sq;
+            th = r0.v > kEpsT ? r0 : -bb + sq;
+        } else {
+            const double *pl = P.pln + 4 * hloc;
+            th = (E2::dd(pl[3]) - ddot(o, pl)) / ddot(d, pl);
+        }
+        th.v = h.t;
+        D2 tseg = th;
+        bool clipped = false;
+        if (len.v + tseg.v > P.max_path) {
+            tseg = E2::dd(P.max_path) - len;
+            clipped = true;
+        }
+        const Material M = P.mat[med];
+        w = w * dexp(-(M.ka * tseg));
+        t = t + M.inv_c * tseg;
+        len = len + tseg;
+        for (int i = 0; i < 3; ++i) o[i] = o[i] + tseg * d[i];
+        if (clipped || t.v >= P.t_max) return false;
+        sig = (sig ^ (unsigned long long)(8 * (hid + 1) + face + 1)) * 1099511628211ull;
+        if (hid == P.id_box) {
+            if (face != 2) return false;
+            out.x[0] = o[0];
+            out.x[1] = o[1];
+            out.inside = fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev;
+            int er = (int)floor((o[0].v + P.half_ap) / P.pitch);
+            out.er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+            const D2 al = dacos(-d[2]);
+            out.c = al.v <= P.alpha_c
+                        ? w * (al.v <= P.alpha_m ? E2::dd(1.0) : (E2::dd(P.alpha_c) - al) / E2::dd(P.alpha_c - P.alpha_m))
+                        : E2::dd(0.0);
+            out.t = t;
+            out.sig = sig;
+            return true;
+        }
+        if (b == P.B) return false;
+        D2 ng[3];
+        int mf, mb;
+        if (hid < P.id_sph0) {
+            double nv[3];
+            tri_normal(P, hloc, nv);
+            for (int i = 0; i < 3; ++i) ng[i] = E2::dd(nv[i]);
+            mf = P.tri_mat[2 * hloc];
+            mb = P.tri_mat[2 * hloc + 1];
+        } else if (hid < P.id_pln0) {
+            for (int i = 0; i < 3; ++i) ng[i] = (o[i] - sc[i]) / E2::dd(srad);
+            mf = P.sph_mat[2 * hloc];
+            mb = P.sph_mat[2 * hloc + 1];
+        } else {
+            const double *pl = P.pln + 4 * hloc;
+            for (int i = 0; i < 3; ++i) ng[i] = E2::dd(pl[i]);
+            mf = P.pln_mat[2 * hloc];
+            mb = P.pln_mat[2 * hloc + 1];
+        }
+        int before, after;
+        if (ddot(d, ng).v < 0.0) {
+            before = mf;
+            after = mb;
+        } else {
+            before = mb;
+            after = mf;
+            for (int i = 0; i < 3; ++i) ng[i] = -ng[i];
+        }
+        const D2 z1 = E2::mat_Z(A, before), z2 = E2::mat_Z(A, after);
+        draw(P, ray, e, tx, b, 1, 0, x);
+        const double y = u01(x[0]);
+        const D2 cos_r = -ddot(d, ng);
+        const D2 eta = z1 / z2;
+        const D2 rad = E2::dd(1.0) - eta * eta * (E2::dd(1.0) - cos_r * cos_r);
+        D2 R = E2::dd(1.0), cos_t = E2::dd(0.0);
+        if (rad.v >= 0.0) {
+            cos_t = dsqrt(rad);
+            const D2 den = z1 * cos_r + z2 * cos_t;
+            if (den.v != 0.0) {
+                const D2 Ar = (z1 * cos_r - z2 * cos_t) / den;
+                R = Ar * Ar;
+            }
+        }
+        D2 nd[3];
+        const bool refl = y < R.v;
+        if (refl) {
+            for (int i = 0; i < 3; ++i) nd[i] = d[i] + E2::dd(2.0) * cos_r * ng[i];
+            w = w * (R / E2::dd(R.v));
+            med = before;
+        } else {
+            const D2 f = eta * cos_r - cos_t;
+            for (int i = 0; i < 3; ++i) nd[i] = eta * d[i] + f * ng[i];
+            const D2 Tr = E2::dd(1.0) - R;
+            w = w * (Tr / E2::dd(Tr.v));
+            med = after;
+        }
+        const D2 l = dsqrt(ddot(nd, nd));
+        for (int i = 0; i < 3; ++i) d[i] = nd[i] / l;
+        sig = (sig ^ (unsigned long long)(2 + (refl ? 1 : 0))) * 1099511628211ull;
+        last = hid < P.id_sph0 ? hloc : (hid >= P.id_pln0 ? hid : -1);
+    }
+    return false;
+}
+
+// One end of a scanned interval.
+struct EdgeEnd {
+    double u, x, y;
+    unsigned long long sig;
+    bool have;
+};
+
+__device__ __forceinline__ EdgeEnd edge_end(const AdjParams &A, int tx, int e, uint32_t ray, double u, LdsStack stk) {
+    EdgeHit h;
+    EdgeEnd r;
+    r.u = u;
+    r.have = edge_path(A, tx, e, ray, u, stk, h);
+    r.x = r.have ? h.x[0].v : 0.0;
+    r.y = r.have ? h.x[1].v : 0.0;
+    r.sig = r.have ? h.sig : 0ull;
+    return r;
+}
+
+// The u0 in (ua, ub) where landing coordinate k crosses X (Newton steps kept
+// inside the bracket, bisection when a step leaves it), on paths with the
+// sequence sig; false if the sequence changes on the way.
+__device__ bool edge_root(const AdjParams &A, int tx, int e, uint32_t ray, double ua, double ub, double fa, int k,
+                          double X, unsigned long long sig, LdsStack stk, EdgeHit &out) {
+    double u = 0.5 * (ua + ub);
+    for (int it = 0; it < 100; ++it) {
+        if (!edge_path(A, tx, e, ray, u, stk, out) || out.sig != sig) return false;
+        const double f = out.x[k].v - X, df = out.x[k].t[0];
+        if (f == 0.0 || ub - ua < 1e-15) return true;
+        if ((f < 0.0) == (fa < 0.0)) {
+            ua = u;
+            fa = f;
+        } else {
+            ub = u;
+        }
+        double un = df != 0.0 ? u - f / df : 0.5 * (ua + ub);
+        if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);
+        if (un == u) return true;
+        u = un;
+    }
+    return true;
+}
+
+// The edge crossings of one interval that follows one sequence (ends a, b).
+__device__ double edge_crossings(const AdjParams &A, int tx, int e, uint32_t ray, const EdgeEnd &a, const EdgeEnd &b,
+                                 LdsStack stk) {
+    const TraceParams &P = A.P;
+    const double half_el = 0.5 * P.elev;
+    double sum = 0.0;
+    EdgeHit at;
+    double gv, gs;
+    const double lo = fmin(a.x, b.x), hi = fmax(a.x, b.x);
+    // element edges and aperture ends (the edge k lies between elements k-1 and k)
+    const int k0 = (int)ceil((lo + P.half_ap) / P.pitch) - 1, k1 = (int)floor((hi + P.half_ap) / P.pitch) + 1;
+    for (int k = k0 < 0 ? 0 : k0; k <= (k1 > P.E ? P.E : k1); ++k) {
+        const double X = -P.half_ap + (double)k * P.pitch;
+        if (!(X > lo && X < hi)) continue;
+        if (!edge_root(A, tx, e, ray, a.u, b.u, a.x - X, 0, X, a.sig, stk, at)) continue;
+        if (!(fabs(at.x[1].v) <= half_el)) continue;
+        const double hr = k < P.E && adj_at(A, tx, k, at.t.v, gv, gs) ? gv : 0.0;
+        const double hl = k > 0 && adj_at(A, tx, k - 1, at.t.v, gv, gs) ? gv : 0.0;
+        const double du = fabs(at.x[0].t[0]);
+        if (!(du > 0.0)) continue;
+        sum += at.c.v * (hr - hl) * at.x[0].t[1] / du;
+    }
+    // elevation edges: inside below the edge in |y|
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const double Y = sgn * half_el;
+        if (!((a.y - Y) * (b.y - Y) < 0.0)) continue;
+        if (!edge_root(A, tx, e, ray, a.u, b.u, a.y - Y, 1, Y, a.sig, stk, at)) continue;
+        if (!(fabs(at.x[0].v) <= P.half_ap)) continue;
+        const double fin = adj_at(A, tx, at.er, at.t.v, gv, gs) ? at.c.v * gv : 0.0;
+        const double du = fabs(at.x[1].t[0]);
+        if (!(du > 0.0)) continue;
+        sum += (sgn > 0 ? -fin : fin) * at.x[1].t[1] / du;
+    }
+    return sum;
+}
+
+// The family's edge term: the scan, the halving of intervals whose ends
+// follow different sequences (a depth-first stack of intervals, the lower
+// half first), and the crossings of the rest.
+constexpr int kEdgeDepth = 48;
+__device__ double edge_family(const AdjParams &A, int tx, int e, uint32_t ray, int n_scan, LdsStack stk) {
+    struct Item {
+        EdgeEnd a, b;
+        int depth;
+    };
+    Item st[kEdgeDepth + 2];
+    double sum = 0.0;
+    EdgeEnd prev = edge_end(A, tx, e, ray, 0.0, stk);
+    for (int j = 1; j <= n_scan; ++j) {
+        const EdgeEnd cur = edge_end(A, tx, e, ray, (double)j / n_scan, stk);
+        int sp = 0;
+        st[sp++] = Item{prev, cur, 0};
+        while (sp > 0) {
+            const Item it = st[--sp];
+            if (!it.a.have && !it.b.have) continue;
+            if (!it.a.have || !it.b.have || it.a.sig != it.b.sig) {
+                if (it.depth >= kEdgeDepth || it.b.u - it.a.u < 1e-12) continue;
+                const EdgeEnd m = edge_end(A, tx, e, ray, 0.5 * (it.a.u + it.b.u), stk);
+                st[sp++] = Item{m, it.b, it.depth + 1};   // (at most one entry per level stays pending)
+                st[sp++] = Item{it.a, m, it.depth + 1};
+                continue;
+            }
+            sum += edge_crossings(A, tx, e, ray, it.a, it.b, stk);
+        }
+        prev = cur;
+    }
+    return sum;
+}
+
+__global__ __launch_bounds__(256) void k_edges(AdjParams A, int n_scan, double *out) {
+    __shared__ int2 s_stack[kStack * 256];
+    const LdsStack stk{s_stack + threadIdx.x, 256};
+    const TraceParams &P = A.P;
+    const int64_t i = A.rec.begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < A.rec.end) {
+        const int64_t q = i / P.per_el;
+        const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
+        v = edge_family(A, (int)(q / P.E), (int)(q % P.E), ray, n_scan, stk);
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(out, v);
+}
+}  // namespace
+
+hipError_t ur_launch_edges(const ur::TraceParams &p, const AdjTangent &dir, const float *g, int n_scan, hipStream_t s) {
+    if (n_scan < 1 || !dir.out) return hipErrorInvalidValue;
+    if (p.n_work <= 0) return hipSuccess;
+    AdjParams A;
+    A.P = p;
+    A.n_tan = 2;
+    A.tan[0] = AdjTangent{3, 0, 0, nullptr};   // tangent 0: the origin coordinate (seeded in edge_path)
+    A.tan[1] = dir;
+    A.g = g;
+    A.grad_amp = nullptr;
+    A.grad_alpha = nullptr;
+    A.value_out = nullptr;
+    A.kappa = 0.0;
+    A.attach_choice = 1;
+    A.rec = AdjRecord{0, 0, p.n_work, nullptr, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(k_edges, dim3((unsigned)((p.n_work + 255) / 256)), dim3(256), 0, s, A, n_scan, dir.out);
+    return hipGetLastError();
+}

@@ -1254,6 +1254,44 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
     });
 }
 
+UR_API ur_status ur_trace_grad_edges(ur_context *c, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
+                                     const float *g_raw_dev, int32_t n_scan, double *corr_z_dev, double *corr_sph_dev,
+                                     void *stream) {
+    return guarded(c, [&]() -> ur_status {
+        if (!c->has_setup) return c->fail(UR_ERR_CALL_ORDER, "call ur_scene_upload and ur_transmit_setup first");
+        if (!g_raw_dev || (!corr_z_dev && !corr_sph_dev))
+            return c->fail(UR_ERR_INVALID_ARG, "g_raw_dev and at least one output are required");
+        if (n_scan < 1) return c->fail(UR_ERR_INVALID_ARG, "n_scan must be >= 1");
+        if (ray_stride < 1 || ray_offset < 0 || ray_offset >= ray_stride)
+            return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
+        TraceParams P;
+        fill_params(c, P, seed);
+        if (P.convex || P.sa || P.proposal || P.any_rough)
+            return c->fail(UR_ERR_UNSUPPORTED, "the edge terms need a linear array, plane-wave transmits, uniform "
+                                               "emission and smooth boundaries");
+        const int n_mat = (int)(c->mat.size() / 3);
+        const int64_t nel = c->acq.rays_per_element;
+        P.stride = ray_stride;
+        P.offset = ray_offset;
+        P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
+        P.n_work = (int64_t)P.T * P.E * P.per_el;
+        hipStream_t s = (hipStream_t)stream;
+        if (corr_z_dev) {
+            HIP_TRY(c, ur_launch_zero_f64(corr_z_dev, n_mat, s));
+            for (int m = 0; m < n_mat; ++m)
+                HIP_TRY(c, ur_launch_edges(P, AdjTangent{1, m, 0, corr_z_dev + m}, g_raw_dev, n_scan, s));
+        }
+        if (corr_sph_dev) {
+            HIP_TRY(c, ur_launch_zero_f64(corr_sph_dev, 3 * (int)c->n_sph, s));
+            for (int j = 0; j < (int)c->n_sph; ++j)
+                for (int k = 0; k < 3; ++k)
+                    HIP_TRY(c, ur_launch_edges(P, AdjTangent{2, j, k, corr_sph_dev + 3 * j + k}, g_raw_dev, n_scan,
+                                               s));
+        }
+        return UR_OK;
+    });
+}
+
 // ------------------------------------------------------------ proposal network
 namespace {
 constexpr int kIn = 34, kHid = 64, kOut = 1024, kParams = 77120;
