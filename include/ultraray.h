@@ -515,10 +515,11 @@ UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_st
  * choice attached (frozen_choice = 0) estimates the derivative of the
  * expected data when the direct hits carry the only discontinuities.
  * g_raw_dev as for ur_trace_adjoint.  Linear arrays, plane-wave transmits,
- * uniform emission, smooth boundaries (else UR_ERR_UNSUPPORTED).  Each
- * parameter costs n_scan + 1 replays per family plus about 48 for every
- * change of sequence along the origin, so meshes (a new triangle at every
- * facet edge) make it far dearer than analytic scenes.  Async on `stream`. */
+ * uniform emission, smooth boundaries, at most 32 impedances and sphere
+ * coordinates (else UR_ERR_UNSUPPORTED).  A family costs n_scan + 1
+ * replays, about 48 more for every change of sequence along the origin
+ * (meshes: a new triangle at every facet edge) and a few per crossing and
+ * parameter.  Async on `stream`. */
 UR_API ur_status ur_trace_grad_edges(ur_context *ctx, uint64_t seed, int64_t ray_stride, int64_t ray_offset,
                                      const float *g_raw_dev, int32_t n_scan, double *corr_z_dev, double *corr_sph_dev,
                                      void *stream);

@@ -842,7 +842,9 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangen
 // 48 levels), and inside an interval that follows one sequence every edge
 // between its landings is located by safeguarded Newton steps.  Linear
 // arrays, smooth boundaries, uniform emission, choice attached.  Dual
-// numbers carry two tangents: u0 and the parameter direction of the launch.
+// numbers carry two tangents: u0 and one parameter direction; the scan and
+// the crossings are found once per family, and each crossing is replayed
+// once per parameter for its derivative.
 namespace {
 using E2 = Rep<2>;
 using D2 = DK<2>;
@@ -856,9 +858,11 @@ struct EdgeHit {
     unsigned long long sig;  // the sequence of primitives and choices
 };
 
-// The family's path at origin coordinate u0; true if it ends on the array's
+// The family's path at origin coordinate u0 (tangent 0: u0; tangent 1: the
+// parameter direction dir, kind 0 for none); true if it ends on the array's
 // plane within the bounce, time and length limits.
-__device__ bool edge_path(const AdjParams &A, int tx, int e, uint32_t ray, double u0, LdsStack stk, EdgeHit &out) {
+__device__ bool edge_path(const AdjParams &A, const AdjTangent &dir, int tx, int e, uint32_t ray, double u0,
+                          LdsStack stk, EdgeHit &out) {
     const TraceParams &P = A.P;
     uint32_t x[4];
     draw(P, ray, e, tx, 0, 0, 0, x);
@@ -893,7 +897,12 @@ __device__ bool edge_path(const AdjParams &A, int tx, int e, uint32_t ray, doubl
                               tq[0] * E2::dd(e1[1]) - tq[1] * E2::dd(e1[0])};
             th = ddot(qq, e2) / ddot(pv, e1);
         } else if (hid < P.id_pln0) {
-            E2::sph_center(A, hloc, sc, &srad);
+            const double *sp = P.sph + 4 * hloc;
+            for (int i = 0; i < 3; ++i) {
+                sc[i] = E2::dd(sp[i]);
+                sc[i].t[1] = (dir.kind == 2 && dir.index == hloc && dir.coord == i) ? 1.0 : 0.0;
+            }
+            srad = sp[3];
             const D2 oc[3] = {o[0] - sc[0], o[1] - sc[1], o[2] - sc[2]};
             const D2 bb = ddot(oc, d), cc = ddot(oc, oc) - E2::dd(srad * srad);
             const D2 sq = dsqrt(bb * bb - cc);
@@ -960,7 +969,9 @@ __device__ bool edge_path(const AdjParams &A, int tx, int e, uint32_t ray, doubl
             after = mf;
             for (int i = 0; i < 3; ++i) ng[i] = -ng[i];
         }
-        const D2 z1 = E2::mat_Z(A, before), z2 = E2::mat_Z(A, after);
+        D2 z1 = E2::dd(P.mat[before].Z), z2 = E2::dd(P.mat[after].Z);
+        z1.t[1] = (dir.kind == 1 && dir.index == before) ? 1.0 : 0.0;
+        z2.t[1] = (dir.kind == 1 && dir.index == after) ? 1.0 : 0.0;
         draw(P, ray, e, tx, b, 1, 0, x);
         const double y = u01(x[0]);
         const D2 cos_r = -ddot(d, ng);
@@ -1003,11 +1014,13 @@ struct EdgeEnd {
     bool have;
 };
 
+constexpr AdjTangent kNoDirection{0, 0, 0, nullptr};
+
 __device__ __forceinline__ EdgeEnd edge_end(const AdjParams &A, int tx, int e, uint32_t ray, double u, LdsStack stk) {
     EdgeHit h;
     EdgeEnd r;
     r.u = u;
-    r.have = edge_path(A, tx, e, ray, u, stk, h);
+    r.have = edge_path(A, kNoDirection, tx, e, ray, u, stk, h);
     r.x = r.have ? h.x[0].v : 0.0;
     r.y = r.have ? h.x[1].v : 0.0;
     r.sig = r.have ? h.sig : 0ull;
@@ -1018,10 +1031,12 @@ __device__ __forceinline__ EdgeEnd edge_end(const AdjParams &A, int tx, int e, u
 // inside the bracket, bisection when a step leaves it), on paths with the
 // sequence sig; false if the sequence changes on the way.
 __device__ bool edge_root(const AdjParams &A, int tx, int e, uint32_t ray, double ua, double ub, double fa, int k,
-                          double X, unsigned long long sig, LdsStack stk, EdgeHit &out) {
+                          double X, unsigned long long sig, LdsStack stk, double &root) {
     double u = 0.5 * (ua + ub);
+    EdgeHit out;
     for (int it = 0; it < 100; ++it) {
-        if (!edge_path(A, tx, e, ray, u, stk, out) || out.sig != sig) return false;
+        root = u;
+        if (!edge_path(A, kNoDirection, tx, e, ray, u, stk, out) || out.sig != sig) return false;
         const double f = out.x[k].v - X, df = out.x[k].t[0];
         if (f == 0.0 || ub - ua < 1e-15) return true;
         if ((f < 0.0) == (fa < 0.0)) {
@@ -1038,53 +1053,74 @@ __device__ bool edge_root(const AdjParams &A, int tx, int e, uint32_t ray, doubl
     return true;
 }
 
+// Parameter p of the edge pass: impedances first, then sphere coordinates.
+__device__ __forceinline__ AdjTangent edge_direction(const TraceParams &P, int p) {
+    return p < P.n_mat ? AdjTangent{1, p, 0, nullptr} : AdjTangent{2, (p - P.n_mat) / 3, (p - P.n_mat) % 3, nullptr};
+}
+
+// Adds the jump term of a crossing of landing coordinate k at u0 = root, with
+// jump(hit) the jump of F there, for every parameter to acc.
+template <class J>
+__device__ void edge_terms(const AdjParams &A, int tx, int e, uint32_t ray, double root, int k, LdsStack stk,
+                           J jump, double *acc) {
+    const TraceParams &P = A.P;
+    const int np = P.n_mat + 3 * P.n_sph;
+    for (int p = 0; p < np; ++p) {
+        EdgeHit at;
+        if (!edge_path(A, edge_direction(P, p), tx, e, ray, root, stk, at)) return;
+        const double du = fabs(at.x[k].t[0]);
+        if (!(du > 0.0)) return;
+        const double jf = jump(at);
+        if (jf == 0.0) return;
+        acc[p] += jf * at.x[k].t[1] / du;
+    }
+}
+
 // The edge crossings of one interval that follows one sequence (ends a, b).
-__device__ double edge_crossings(const AdjParams &A, int tx, int e, uint32_t ray, const EdgeEnd &a, const EdgeEnd &b,
-                                 LdsStack stk) {
+__device__ void edge_crossings(const AdjParams &A, int tx, int e, uint32_t ray, const EdgeEnd &a, const EdgeEnd &b,
+                               LdsStack stk, double *acc) {
     const TraceParams &P = A.P;
     const double half_el = 0.5 * P.elev;
-    double sum = 0.0;
-    EdgeHit at;
-    double gv, gs;
+    double root;
     const double lo = fmin(a.x, b.x), hi = fmax(a.x, b.x);
     // element edges and aperture ends (the edge k lies between elements k-1 and k)
     const int k0 = (int)ceil((lo + P.half_ap) / P.pitch) - 1, k1 = (int)floor((hi + P.half_ap) / P.pitch) + 1;
     for (int k = k0 < 0 ? 0 : k0; k <= (k1 > P.E ? P.E : k1); ++k) {
         const double X = -P.half_ap + (double)k * P.pitch;
         if (!(X > lo && X < hi)) continue;
-        if (!edge_root(A, tx, e, ray, a.u, b.u, a.x - X, 0, X, a.sig, stk, at)) continue;
-        if (!(fabs(at.x[1].v) <= half_el)) continue;
-        const double hr = k < P.E && adj_at(A, tx, k, at.t.v, gv, gs) ? gv : 0.0;
-        const double hl = k > 0 && adj_at(A, tx, k - 1, at.t.v, gv, gs) ? gv : 0.0;
-        const double du = fabs(at.x[0].t[0]);
-        if (!(du > 0.0)) continue;
-        sum += at.c.v * (hr - hl) * at.x[0].t[1] / du;
+        if (!edge_root(A, tx, e, ray, a.u, b.u, a.x - X, 0, X, a.sig, stk, root)) continue;
+        edge_terms(A, tx, e, ray, root, 0, stk, [&](const EdgeHit &at) {
+            if (!(fabs(at.x[1].v) <= half_el)) return 0.0;
+            double gv, gs;
+            const double hr = k < P.E && adj_at(A, tx, k, at.t.v, gv, gs) ? gv : 0.0;
+            const double hl = k > 0 && adj_at(A, tx, k - 1, at.t.v, gv, gs) ? gv : 0.0;
+            return at.c.v * (hr - hl);
+        }, acc);
     }
     // elevation edges: inside below the edge in |y|
     for (int sgn = -1; sgn <= 1; sgn += 2) {
         const double Y = sgn * half_el;
         if (!((a.y - Y) * (b.y - Y) < 0.0)) continue;
-        if (!edge_root(A, tx, e, ray, a.u, b.u, a.y - Y, 1, Y, a.sig, stk, at)) continue;
-        if (!(fabs(at.x[0].v) <= P.half_ap)) continue;
-        const double fin = adj_at(A, tx, at.er, at.t.v, gv, gs) ? at.c.v * gv : 0.0;
-        const double du = fabs(at.x[1].t[0]);
-        if (!(du > 0.0)) continue;
-        sum += (sgn > 0 ? -fin : fin) * at.x[1].t[1] / du;
+        if (!edge_root(A, tx, e, ray, a.u, b.u, a.y - Y, 1, Y, a.sig, stk, root)) continue;
+        edge_terms(A, tx, e, ray, root, 1, stk, [&](const EdgeHit &at) {
+            if (!(fabs(at.x[0].v) <= P.half_ap)) return 0.0;
+            double gv, gs;
+            const double fin = adj_at(A, tx, at.er, at.t.v, gv, gs) ? at.c.v * gv : 0.0;
+            return sgn > 0 ? -fin : fin;
+        }, acc);
     }
-    return sum;
 }
 
 // The family's edge term: the scan, the halving of intervals whose ends
 // follow different sequences (a depth-first stack of intervals, the lower
 // half first), and the crossings of the rest.
 constexpr int kEdgeDepth = 48;
-__device__ double edge_family(const AdjParams &A, int tx, int e, uint32_t ray, int n_scan, LdsStack stk) {
+__device__ void edge_family(const AdjParams &A, int tx, int e, uint32_t ray, int n_scan, LdsStack stk, double *acc) {
     struct Item {
         EdgeEnd a, b;
         int depth;
     };
     Item st[kEdgeDepth + 2];
-    double sum = 0.0;
     EdgeEnd prev = edge_end(A, tx, e, ray, 0.0, stk);
     for (int j = 1; j <= n_scan; ++j) {
         const EdgeEnd cur = edge_end(A, tx, e, ray, (double)j / n_scan, stk);
@@ -1100,37 +1136,43 @@ __device__ double edge_family(const AdjParams &A, int tx, int e, uint32_t ray, i
                 st[sp++] = Item{it.a, m, it.depth + 1};
                 continue;
             }
-            sum += edge_crossings(A, tx, e, ray, it.a, it.b, stk);
+            edge_crossings(A, tx, e, ray, it.a, it.b, stk, acc);
         }
         prev = cur;
     }
-    return sum;
 }
 
-__global__ __launch_bounds__(256) void k_edges(AdjParams A, int n_scan, double *out) {
+constexpr int kEdgeMaxParams = 32;
+__global__ __launch_bounds__(256) void k_edges(AdjParams A, int n_scan, double *out_z, double *out_sph) {
     __shared__ int2 s_stack[kStack * 256];
     const LdsStack stk{s_stack + threadIdx.x, 256};
     const TraceParams &P = A.P;
+    const int np = P.n_mat + 3 * P.n_sph;
+    double acc[kEdgeMaxParams];
+    for (int p = 0; p < kEdgeMaxParams; ++p) acc[p] = 0.0;
     const int64_t i = A.rec.begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
     if (i < A.rec.end) {
         const int64_t q = i / P.per_el;
         const uint32_t ray = (uint32_t)((i - q * P.per_el) * P.stride + P.offset);
-        v = edge_family(A, (int)(q / P.E), (int)(q % P.E), ray, n_scan, stk);
+        edge_family(A, (int)(q / P.E), (int)(q % P.E), ray, n_scan, stk, acc);
     }
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(out, v);
+    for (int p = 0; p < np; ++p) {
+        double v = acc[p];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        double *o = p < P.n_mat ? out_z + p : (out_sph ? out_sph + (p - P.n_mat) : nullptr);
+        if (p < P.n_mat && !out_z) o = nullptr;
+        if ((threadIdx.x & 63) == 0 && v != 0.0 && o) atomicAdd(o, v);
+    }
 }
 }  // namespace
 
-hipError_t ur_launch_edges(const ur::TraceParams &p, const AdjTangent &dir, const float *g, int n_scan, hipStream_t s) {
-    if (n_scan < 1 || !dir.out) return hipErrorInvalidValue;
+hipError_t ur_launch_edges(const ur::TraceParams &p, double *out_z, double *out_sph, const float *g, int n_scan,
+                           hipStream_t s) {
+    if (n_scan < 1 || (!out_z && !out_sph) || p.n_mat + 3 * p.n_sph > kEdgeMaxParams) return hipErrorInvalidValue;
     if (p.n_work <= 0) return hipSuccess;
     AdjParams A;
     A.P = p;
-    A.n_tan = 2;
-    A.tan[0] = AdjTangent{3, 0, 0, nullptr};   // tangent 0: the origin coordinate (seeded in edge_path)
-    A.tan[1] = dir;
+    A.n_tan = 0;
     A.g = g;
     A.grad_amp = nullptr;
     A.grad_alpha = nullptr;
@@ -1138,6 +1180,6 @@ hipError_t ur_launch_edges(const ur::TraceParams &p, const AdjTangent &dir, cons
     A.kappa = 0.0;
     A.attach_choice = 1;
     A.rec = AdjRecord{0, 0, p.n_work, nullptr, nullptr, nullptr, nullptr};
-    hipLaunchKernelGGL(k_edges, dim3((unsigned)((p.n_work + 255) / 256)), dim3(256), 0, s, A, n_scan, dir.out);
+    hipLaunchKernelGGL(k_edges, dim3((unsigned)((p.n_work + 255) / 256)), dim3(256), 0, s, A, n_scan, out_z, out_sph);
     return hipGetLastError();
 }

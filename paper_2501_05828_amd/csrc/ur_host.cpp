@@ -1276,18 +1276,11 @@ UR_API ur_status ur_trace_grad_edges(ur_context *c, uint64_t seed, int64_t ray_s
         P.per_el = nel > ray_offset ? (nel - ray_offset + ray_stride - 1) / ray_stride : 0;
         P.n_work = (int64_t)P.T * P.E * P.per_el;
         hipStream_t s = (hipStream_t)stream;
-        if (corr_z_dev) {
-            HIP_TRY(c, ur_launch_zero_f64(corr_z_dev, n_mat, s));
-            for (int m = 0; m < n_mat; ++m)
-                HIP_TRY(c, ur_launch_edges(P, AdjTangent{1, m, 0, corr_z_dev + m}, g_raw_dev, n_scan, s));
-        }
-        if (corr_sph_dev) {
-            HIP_TRY(c, ur_launch_zero_f64(corr_sph_dev, 3 * (int)c->n_sph, s));
-            for (int j = 0; j < (int)c->n_sph; ++j)
-                for (int k = 0; k < 3; ++k)
-                    HIP_TRY(c, ur_launch_edges(P, AdjTangent{2, j, k, corr_sph_dev + 3 * j + k}, g_raw_dev, n_scan,
-                                               s));
-        }
+        if (n_mat + 3 * (int)c->n_sph > 32)
+            return c->fail(UR_ERR_UNSUPPORTED, "the edge terms support at most 32 impedances and sphere coordinates");
+        if (corr_z_dev) HIP_TRY(c, ur_launch_zero_f64(corr_z_dev, n_mat, s));
+        if (corr_sph_dev) HIP_TRY(c, ur_launch_zero_f64(corr_sph_dev, 3 * (int)c->n_sph, s));
+        HIP_TRY(c, ur_launch_edges(P, corr_z_dev, corr_sph_dev, g_raw_dev, n_scan, s));
         return UR_OK;
     });
 }

@@ -243,9 +243,10 @@ struct AdjTangent {
 hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangent *tans, const float *g,
                             float *grad_amp, double *grad_alpha, double *value_out, double kappa, int attach_choice,
                             const AdjRecord &rec, hipStream_t s);
-// The direct-hit edge term along one parameter direction (dir.kind 1 or 2),
-// added to dir.out, over the work items of p (n_scan + 1 origins per family).
-hipError_t ur_launch_edges(const ur::TraceParams &p, const AdjTangent &dir, const float *g, int n_scan,
+// The direct-hit edge terms of every impedance (added to out_z [n_mat]) and
+// sphere coordinate (out_sph [n_sph][3]), each nullable, over the work items
+// of p (n_scan + 1 origins per family; at most 32 parameters).
+hipError_t ur_launch_edges(const ur::TraceParams &p, double *out_z, double *out_sph, const float *g, int n_scan,
                            hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);
