@@ -61,3 +61,50 @@ def test_edge_terms_refuse_convex_arrays(torch_gpu):
     Z = torch.empty(len(w.scene.materials), dtype=torch.float64, device="cuda")
     with pytest.raises(URError):
         s.ctx.ur_trace_grad_edges(w.seed, torch.from_numpy(g).cuda(), Z=Z)
+
+
+def test_autograd_adds_edge_terms(torch_gpu):
+    """simulate_envelope(..., edge_terms=True): the impedance and
+    sphere-centre gradients gain exactly ur_trace_grad_edges of the channel
+    adjoint that the backward pass forms (envelope, delay-and-sum and pulse
+    adjoints of the loss gradient)."""
+    from paper_2501_05828_amd import binding
+    from paper_2501_05828_amd.adjoint import simulate_envelope
+    from paper_2501_05828_amd.sim import Simulator
+    torch = torch_gpu
+    w, _ = _case()
+    s = Simulator(w)
+    sc = w.scene
+
+    def grads(edge_terms):
+        Z = torch.tensor(sc.materials[:, 0], requires_grad=True)
+        cen = torch.tensor(sc.sph[:, :3], requires_grad=True)
+        amp = torch.tensor(sc.scat[:, 3] if len(sc.scat) else np.zeros(0))
+        alpha = torch.tensor(sc.materials[:, 1])
+        env = simulate_envelope(s, amp, alpha, Z, cen, edge_terms=edge_terms)
+        loss = 0.5 * (env.double() ** 2).sum()
+        loss.backward()
+        return Z.grad.clone(), cen.grad.clone(), env.detach()
+
+    z0, c0, env = grads(False)
+    z1, c1, _ = grads(True)
+    # the channel adjoint of the same loss, formed as the backward pass forms it
+    s.trace(w.seed)
+    s.beamform(bmode=False)
+    g_rf, g_raw = torch.empty_like(s.ch_rf), torch.empty_like(s.ch_raw)
+    apod = binding.UR_APOD_HANN if w.apod == "hann" else binding.UR_APOD_NONE
+    s.ctx.ur_beamform_adjoint(w.grid, g_rf, iq=s.iq.clone(), g_env=env.float().contiguous(), apod=apod)
+    s.ctx.ur_pulse_adjoint(g_rf, g_raw)
+    ez = torch.empty(len(sc.materials), dtype=torch.float64, device="cuda")
+    es = torch.empty((len(sc.sph), 3), dtype=torch.float64, device="cuda")
+    s.ctx.ur_trace_grad_edges(w.seed, g_raw, Z=ez, sph_center=es)
+    dz, dc = (z1 - z0).numpy(), (c1 - c0).numpy()
+    print(f"[edges-gpu] autograd: Z {dz} vs {ez.cpu().numpy()}, centre {dc.ravel()} vs {es.cpu().numpy().ravel()}",
+          flush=True)
+    # the delay-and-sum adjoint scatters with FP32 atomics, so the channel
+    # adjoint of two backward passes differs in its last bits (about 1e-6 of
+    # the terms here)
+    ezn, esn = ez.cpu().numpy(), es.cpu().numpy()
+    assert np.abs(esn).max() > 0.0
+    assert np.allclose(dz, ezn, rtol=1e-4, atol=1e-5 * np.abs(ezn).max())
+    assert np.allclose(dc, esn, rtol=1e-4, atol=1e-5 * np.abs(esn).max())
