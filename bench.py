@@ -441,6 +441,80 @@ def rough_nee_experiment(args):
                       "curves": curves}))
 
 
+def edges_experiment(args):
+    """The direct-hit edge terms (ur_trace_grad_edges) against common-random-
+    number differences of the expected data.  The small scene with its
+    sphere under the aperture (12 mm deep, radius 3 mm), no scatterers,
+    linear binning, receive angles 10 / 45 degrees, args.edge_rays rays per
+    element; the channel adjoint g is one smooth random time profile (white
+    noise filtered by a Gaussian of 40 samples) with one sign per half of the
+    aperture, so it jumps at the centre edge.  For every key (Philox seed):
+    J(x_c +- h) of the sphere centre's x from the replay's FP64 functional,
+    the interior adjoint (choice attached) and the edge terms.  Prints one
+    JSON line with the means and standard errors over the keys."""
+    import dataclasses
+    import math
+
+    import numpy as np
+    import torch
+    from scipy.ndimage import gaussian_filter1d
+
+    from paper_2501_05828_amd import scenes
+    from paper_2501_05828_amd.sim import Simulator
+
+    w = scenes.tiny(rays_per_element=args.edge_rays)
+    acq = dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45), binning=scenes.LINEAR,
+                              angles=np.deg2rad([0.0]))
+    sph = np.array([[1.0e-3, 0.5e-3, 12.0e-3, 3.0e-3]])
+    sc = dataclasses.replace(w.scene, sph=sph, sph_mat=np.array([[0, 2]], np.int32), scat=np.zeros((0, 4)))
+    w = dataclasses.replace(w, acq=acq, scene=sc)
+    A = w.acq
+    rng = np.random.default_rng(5)
+    prof = np.abs(gaussian_filter1d(rng.normal(size=A.n_samples), 40.0) * 10)
+    sign = np.where(np.arange(A.n_elements) < A.n_elements // 2, 1.0, -1.0)
+    g = torch.from_numpy((prof[None, None, :] * sign[None, :, None]).astype(np.float32)).cuda()
+    sim = Simulator(w)
+    ctx = sim.ctx
+    hs = (1e-4, 1e-5, 2e-6)
+    v = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cen = torch.empty((1, 3), dtype=torch.float64, device="cuda")
+
+    def J(seed, dx):
+        s2 = sph.copy()
+        s2[0, 0] += dx
+        ctx.ur_scene_update(sph=s2)
+        ctx.ur_trace_adjoint(seed, g, value=v)
+        return float(v.item())
+
+    fd = {h: [] for h in hs}
+    interior, edges = [], []
+    t0 = time.perf_counter()
+    for key in range(args.edge_keys):
+        seed = w.seed + 1000 * key
+        for h in hs:
+            fd[h].append((J(seed, h) - J(seed, -h)) / (2 * h))
+        ctx.ur_scene_update(sph=sph)
+        ctx.ur_trace_adjoint(seed, g, sph_center=cen, frozen_choice=False)
+        interior.append(float(cen[0, 0].item()))
+        ctx.ur_trace_grad_edges(seed, g, sph_center=cen)
+        edges.append(float(cen[0, 0].item()))
+        if (key + 1) % 500 == 0:
+            print(f"[edges] {key + 1} keys, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+
+    def stat(x):
+        x = np.asarray(x)
+        return {"mean": float(x.mean()), "se": float(x.std(ddof=1) / math.sqrt(len(x)))}
+
+    it, ed = np.asarray(interior), np.asarray(edges)
+    out = {"experiment": "edge_terms", "workload": "small scene, sphere under the aperture, no scatterers, "
+           f"{A.n_elements} elements x {A.rays_per_element} rays, adjoint with one sign per half aperture",
+           "keys": args.edge_keys, "parameter": "sphere centre x",
+           "differences": {f"h={h:g} m": stat(fd[h]) for h in hs},
+           "interior": stat(it), "edge_terms": stat(ed), "interior_plus_edges": stat(it + ed),
+           "seconds": time.perf_counter() - t0}
+    print(json.dumps(out))
+
+
 def binning_experiment(args):
     """Records per frame and trace time of the bone frame under four receive
     configurations: the uniform and the cone-restricted element choice at the
@@ -502,7 +576,7 @@ def main():
     ap.add_argument("--workload", default="bone", choices=["bone", "batched", "tiny", "convex", "bone_rough", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=150000)
-    ap.add_argument("--experiment", choices=["learned", "rough-nee", "binning"], default=None,
+    ap.add_argument("--experiment", choices=["learned", "rough-nee", "binning", "edges"], default=None,
                     help="learned: channel MSE vs GPU time, learned vs uniform emission; rough-nee: with vs "
                          "without transducer sampling at the rough bone; binning: records per frame and trace time "
                          "under four receive configurations")
@@ -523,6 +597,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the batched-workload trace and DAS measurement")
     ap.add_argument("--c3-only", action="store_true", help="run only the batched-workload trace and DAS measurement")
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint measurement on the large scene")
+    ap.add_argument("--edge-keys", type=int, default=4000, help="keys of --experiment edges")
+    ap.add_argument("--edge-rays", type=int, default=2048, help="rays per element of --experiment edges")
     ap.add_argument("--backward-only", action="store_true", help="run only the adjoint measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
@@ -547,6 +623,9 @@ def main():
         return
     if args.experiment == "binning":
         binning_experiment(args)
+        return
+    if args.experiment == "edges":
+        edges_experiment(args)
         return
     if args.backward_only:
         print(json.dumps(backward_measure()))
