@@ -1950,17 +1950,41 @@ int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, i
  * evaluating the family at n_scan + 1 evenly spaced u0 and halving every
  * interval whose ends follow different sequences of primitives and choices
  * (down to 1e-12), then by safeguarded Newton steps inside each interval
- * that follows one sequence.  The derivatives at u0* come from dual numbers with u0 and every
- * parameter as tangents.  Linear arrays, smooth boundaries, uniform
- * emission; the reflect-or-transmit choice is attached, as the result
- * estimates the derivative of the expected data. */
+ * that follows one sequence.  The derivatives at u0* come from dual
+ * numbers with u0 and every parameter as tangents.  On a convex array the
+ * origin moves along the element's arc and the direction turns with it, the
+ * landing coordinate across the elements is the arc angle, and each element
+ * receives against its own normal, so F jumps in c as well as in g.  Smooth
+ * boundaries, uniform emission; the reflect-or-transmit choice is attached,
+ * as the result estimates the derivative of the expected data. */
 typedef struct {
     int inside;      /* the landing point lies on an element */
     int64_t er;      /* that element */
-    dnum x[2];       /* landing point (x, y) on the array's plane */
-    dnum c, t;       /* weight x receive directivity (whether inside or not), arrival time */
+    dnum x[2];       /* landing coordinates: across the elements (x, or the arc angle of a convex array), y */
+    dnum c, t;       /* weight x receive directivity of element er (whether inside or not), arrival time */
+    double w, d[3];  /* the weight and the arrival direction (values) */
     uint64_t sig;    /* the sequence of primitives and choices */
 } ed_out;
+
+/* Weight x receive directivity (Eq. 13) of a landing with weight w and
+ * direction d into element er, against that element's normal. */
+static double ed_c(const octx *C, const ed_out *o, int64_t er)
+{
+    const or_acq *a = C->a;
+    double ca = a->radius > 0.0 ? -(o->d[0] * C->sne[er] + o->d[2] * C->cne[er]) : -o->d[2];
+    double al = acos(ca > 1.0 ? 1.0 : (ca < -1.0 ? -1.0 : ca));
+    return o->w * or_directivity(al, a->alpha_m, a->alpha_c);
+}
+
+/* sin and cos of a dual */
+static void dn_sincos(dnum a, dnum *sn, dnum *cs)
+{
+    double s = sin(a.v), c = cos(a.v);
+    *sn = dn_mulc(a, c);
+    sn->v = s;
+    *cs = dn_mulc(a, -s);
+    cs->v = c;
+}
 
 /* Replays the family's path at origin coordinate u0 (tangent 0: u0; the
  * parameters' tangents come with G's Z and cen).  Returns 1 if it ends on
@@ -1975,11 +1999,25 @@ static int ed_path(const gctx *G, int64_t tx, int64_t e, uint32_t ray, double u0
     double hl[3];
     or_hemisphere(unif(x[2]), unif(x[3]), hl);
     dnum o[3], d[3];
-    o[0] = dn_c(C->xe[e] + (u0 - 0.5) * a->pitch);
-    o[0].t[0] = a->pitch;
     o[1] = dn_c((unif(x[1]) - 0.5) * a->elevation);
-    o[2] = dn_c(0.0);
-    for (int i = 0; i < 3; ++i) d[i] = dn_c(hl[i]);
+    if (a->radius > 0.0) {
+        /* on the element's arc; the direction turns with the local normal */
+        dnum ph = dn_c(((double)e - 0.5 * (double)(a->n_elements - 1) + (u0 - 0.5)) * C->dphi);
+        ph.t[0] = C->dphi;
+        dnum sp, cp, sh, chh;
+        dn_sincos(ph, &sp, &cp);
+        dn_sincos(dn_mulc(ph, 0.5), &sh, &chh);
+        o[0] = dn_mulc(sp, a->radius);
+        o[2] = dn_mul(dn_mulc(sh, -2.0 * a->radius), sh);
+        d[0] = dn_add(dn_mulc(cp, hl[0]), dn_mulc(sp, hl[2]));
+        d[1] = dn_c(hl[1]);
+        d[2] = dn_sub(dn_mulc(cp, hl[2]), dn_mulc(sp, hl[0]));
+    } else {
+        o[0] = dn_c(C->xe[e] + (u0 - 0.5) * a->pitch);
+        o[0].t[0] = a->pitch;
+        o[2] = dn_c(0.0);
+        for (int i = 0; i < 3; ++i) d[i] = dn_c(hl[i]);
+    }
     const double pdf = 1.0 / (2.0 * PI);
     dnum w = dn_c(hl[2] / (C->n_per_tx * pdf)), t = dn_c(C->tau[tx * a->n_elements + e]), len = dn_c(0.0);
     int64_t med = sc->top_medium, last = -1;
@@ -2000,13 +2038,33 @@ static int ed_path(const gctx *G, int64_t tx, int64_t e, uint32_t ray, double u0
         if (clipped || t.v >= C->t_max) return 0;
         sig = (sig ^ (uint64_t)(8 * (h.id + 1) + h.face + 1)) * 1099511628211ull;
         if (h.id == C->id_box) {
-            if (h.face != 2) return 0;
-            out->x[0] = o[0];
+            int64_t er;
+            dnum ca;
+            if (a->radius > 0.0) {
+                /* the arc angle atan2(x, z + R) of the landing point */
+                if (h.face != 6) return 0;
+                dnum zc = dn_add(o[2], dn_c(a->radius));
+                double r2 = o[0].v * o[0].v + zc.v * zc.v;
+                dnum ph = dn_c(atan2(o[0].v, zc.v));
+                for (int i = 0; i < g_nt; ++i) ph.t[i] = (zc.v * o[0].t[i] - o[0].v * zc.t[i]) / r2;
+                out->x[0] = ph;
+                out->inside = fabs(ph.v) <= C->half_arc && fabs(o[1].v) <= 0.5 * a->elevation;
+                er = (int64_t)floor(ph.v / C->dphi + 0.5 * (double)a->n_elements);
+                er = er < 0 ? 0 : (er > a->n_elements - 1 ? a->n_elements - 1 : er);
+                ca = dn_neg(dn_add(dn_mulc(d[0], C->sne[er]), dn_mulc(d[2], C->cne[er])));
+            } else {
+                if (h.face != 2) return 0;
+                out->x[0] = o[0];
+                out->inside = fabs(o[0].v) <= C->half_ap && fabs(o[1].v) <= 0.5 * a->elevation;
+                er = (int64_t)floor((o[0].v + C->half_ap) / a->pitch);
+                er = er < 0 ? 0 : (er > a->n_elements - 1 ? a->n_elements - 1 : er);
+                ca = dn_neg(d[2]);
+            }
             out->x[1] = o[1];
-            out->inside = fabs(o[0].v) <= C->half_ap && fabs(o[1].v) <= 0.5 * a->elevation;
-            int64_t er = (int64_t)floor((o[0].v + C->half_ap) / a->pitch);
-            out->er = er < 0 ? 0 : (er > a->n_elements - 1 ? a->n_elements - 1 : er);
-            dnum al = dn_acos(dn_neg(d[2]));
+            out->er = er;
+            out->w = w.v;
+            for (int i = 0; i < 3; ++i) out->d[i] = d[i].v;
+            dnum al = dn_acos(ca);
             out->c = or_directivity(al.v, a->alpha_m, a->alpha_c) > 0.0
                          ? dn_mul(w, dn_directivity(al, a->alpha_m, a->alpha_c)) : dn_c(0.0);
             out->t = t;
@@ -2144,17 +2202,20 @@ static void ed_interval(const gctx *G, const double *g, int64_t tx, int64_t e, u
     }
     ed_out at;
     const double half_el = 0.5 * a->elevation;
-    /* element edges and aperture ends crossed in x */
+    /* element edges and aperture ends crossed (in x, or in the arc angle of
+     * a convex array, whose elements each have their own normal) */
+    const int convex = a->radius > 0.0;
     const double xa = A->x[0].v, xb = B->x[0].v;
     const double lo = xa < xb ? xa : xb, hi = xa < xb ? xb : xa;
     for (int64_t k = 0; k <= a->n_elements; ++k) {
-        const double X = -C->half_ap + (double)k * a->pitch;
+        const double X = convex ? ((double)k - 0.5 * (double)a->n_elements) * C->dphi
+                                : -C->half_ap + (double)k * a->pitch;
         if (!(X > lo && X < hi)) continue;
         if (!ed_root(G, tx, e, ray, ua, ub, xa - X, 0, X, A->sig, &at)) continue;
         if (!(fabs(at.x[1].v) <= half_el)) continue;
-        const double hr = k < a->n_elements ? ed_adj(C, g, tx, k, at.t.v) : 0.0;
-        const double hl = k > 0 ? ed_adj(C, g, tx, k - 1, at.t.v) : 0.0;
-        const double jump = at.c.v * (hr - hl), du = fabs(at.x[0].t[0]);
+        const double fr = k < a->n_elements ? ed_c(C, &at, k) * ed_adj(C, g, tx, k, at.t.v) : 0.0;
+        const double fl = k > 0 ? ed_c(C, &at, k - 1) * ed_adj(C, g, tx, k - 1, at.t.v) : 0.0;
+        const double jump = fr - fl, du = fabs(at.x[0].t[0]);
         if (!(du > 0.0)) continue;
         for (int p = 0; p < np; ++p) acc[p] += jump * at.x[0].t[1 + p] / du;
     }
@@ -2165,7 +2226,7 @@ static void ed_interval(const gctx *G, const double *g, int64_t tx, int64_t e, u
         const double Y = sgn * half_el;
         if (!((ya - Y) * (yb - Y) < 0.0)) continue;
         if (!ed_root(G, tx, e, ray, ua, ub, ya - Y, 1, Y, A->sig, &at)) continue;
-        if (!(fabs(at.x[0].v) <= C->half_ap)) continue;
+        if (!(fabs(at.x[0].v) <= (convex ? C->half_arc : C->half_ap))) continue;
         const double fin = at.c.v * ed_adj(C, g, tx, at.er, at.t.v);
         const double jump = sgn > 0 ? -fin : fin, du = fabs(at.x[1].t[0]);
         if (!(du > 0.0)) continue;
@@ -2180,7 +2241,6 @@ static int ed_setup(const or_acq *a, const or_scene *s, int attach, octx *C, gct
     if (a->n_elements <= 0 || a->n_elements > 65535 || a->n_tx <= 0 || a->n_tx > 65535 || a->n_samples <= 0 ||
         a->rays_per_element < 0 || a->max_bounces < 0 || a->cdf != NULL || a->scheme == 1)
         return -1;
-    if (a->radius != 0.0) return -2;
     if (1 + s->n_mat + 3 * s->n_sph > GRAD_MAX) return -1;
     if (s->rough)
         for (int64_t m = 0; m < s->n_mat; ++m)

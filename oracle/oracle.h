@@ -106,8 +106,8 @@ int or_trace_rays_grad(const or_acq *a, const or_scene *s, const or_ray *rays, i
  * integrated exactly along the emission origin's lateral coordinate: for
  * every path family of or_trace_subset's paths, the crossings of the landing
  * point over n_scan + 1 evenly spaced origins (choice attached).  corr_z
- * [n_mat], corr_sph [n_sph][3] (each nullable).  Linear arrays and uniform
- * emission only (-2 for a convex array); -3 for rough boundaries, -1 for
+ * [n_mat], corr_sph [n_sph][3] (each nullable).  Linear and convex arrays,
+ * plane-wave transmits, uniform emission; -3 for rough boundaries, -1 for
  * bad arguments. */
 int or_trace_grad_edges(const or_acq *a, const or_scene *s, int n_threads, int64_t ray_stride, const double *g,
                         int n_scan, double *corr_z, double *corr_sph);
