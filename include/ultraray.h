@@ -514,9 +514,11 @@ UR_API ur_status ur_trace_adjoint(ur_context *ctx, uint64_t seed, int64_t ray_st
  * nullable; adding them to ur_trace_adjoint's Z and sph_center with the
  * choice attached (frozen_choice = 0) estimates the derivative of the
  * expected data when the direct hits carry the only discontinuities.
- * g_raw_dev as for ur_trace_adjoint.  Linear arrays, plane-wave transmits,
- * uniform emission, smooth boundaries, at most 32 impedances and sphere
- * coordinates (else UR_ERR_UNSUPPORTED).  A family costs n_scan + 1
+ * g_raw_dev as for ur_trace_adjoint.  Linear and convex arrays (on a convex
+ * one the origin moves along the element's arc, the landing coordinate is
+ * the arc angle and every element receives against its own normal);
+ * plane-wave transmits, uniform emission, smooth boundaries, at most 32
+ * impedances and sphere coordinates (else UR_ERR_UNSUPPORTED).  A family costs n_scan + 1
  * replays, about 48 more for every change of sequence along the origin
  * (meshes: a new triangle at every facet edge) and a few per crossing and
  * parameter.  Async on `stream`. */

@@ -840,8 +840,11 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangen
 // evaluated at n_scan + 1 evenly spaced u0; an interval whose ends follow
 // different sequences of primitives and choices is halved (down to 1e-12 or
 // 48 levels), and inside an interval that follows one sequence every edge
-// between its landings is located by safeguarded Newton steps.  Linear
-// arrays, smooth boundaries, uniform emission, choice attached.  Dual
+// between its landings is located by safeguarded Newton steps.  On a
+// convex array the origin moves along the element's arc and the direction
+// turns with it, the landing coordinate across the elements is the arc
+// angle, and each element receives against its own normal.  Plane-wave
+// transmits, smooth boundaries, uniform emission, choice attached.  Dual
 // numbers carry two tangents: u0 and one parameter direction; the scan and
 // the crossings are found once per family, and each crossing is replayed
 // once per parameter for its derivative.
@@ -853,10 +856,26 @@ static_assert(kAdjTan >= 2, "the edge pass carries two directions: u0 and one pa
 struct EdgeHit {
     bool inside;             // the landing point lies on an element
     int er;                  // that element
-    D2 x[2];                 // landing point (x, y)
-    D2 c, t;                 // weight x receive directivity, arrival time
+    D2 x[2];                 // landing coordinates: across the elements (x, or the arc angle), y
+    D2 c, t;                 // weight x receive directivity of element er, arrival time
+    double w, d[3];          // the weight and the arrival direction (values)
     unsigned long long sig;  // the sequence of primitives and choices
 };
+
+// Weight x receive directivity (Eq. 13) of the landing h into element er,
+// against that element's normal.
+__device__ __forceinline__ double edge_c(const TraceParams &P, const EdgeHit &h, int er) {
+    double ca;
+    if (P.convex) {
+        const double4 g = P.elem[er];
+        ca = -(h.d[0] * g.z + h.d[2] * g.w);
+    } else {
+        ca = -h.d[2];
+    }
+    const double al = acos(fmin(1.0, fmax(-1.0, ca)));
+    if (!(al <= P.alpha_c)) return 0.0;
+    return h.w * (al <= P.alpha_m ? 1.0 : (P.alpha_c - al) / (P.alpha_c - P.alpha_m));
+}
 
 // The family's path at origin coordinate u0 (tangent 0: u0; tangent 1: the
 // parameter direction dir, kind 0 for none); true if it ends on the array's
@@ -868,9 +887,29 @@ __device__ bool edge_path(const AdjParams &A, const AdjTangent &dir, int tx, int
     draw(P, ray, e, tx, 0, 0, 0, x);
     double dv0[3];
     hemisphere(u01(x[2]), u01(x[3]), dv0);
-    D2 o[3] = {E2::dd(P.xe[e] + (u0 - 0.5) * P.pitch), E2::dd((u01(x[1]) - 0.5) * P.elev), E2::dd(0.0)};
-    o[0].t[0] = P.pitch;
-    D2 d[3] = {E2::dd(dv0[0]), E2::dd(dv0[1]), E2::dd(dv0[2])};
+    D2 o[3], d[3];
+    o[1] = E2::dd((u01(x[1]) - 0.5) * P.elev);
+    if (P.convex) {
+        // on the element's arc; the direction turns with the local normal
+        const double ph = ((double)e - 0.5 * (double)(P.E - 1) + (u0 - 0.5)) * P.dphi;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        const double h = sin(0.5 * ph);
+        o[0] = E2::dd(P.radius * sp);
+        o[0].t[0] = P.radius * cp * P.dphi;
+        o[2] = E2::dd(-2.0 * P.radius * h * h);
+        o[2].t[0] = -2.0 * P.radius * h * cos(0.5 * ph) * P.dphi;
+        d[0] = E2::dd(dv0[0] * cp + dv0[2] * sp);
+        d[0].t[0] = (-dv0[0] * sp + dv0[2] * cp) * P.dphi;
+        d[1] = E2::dd(dv0[1]);
+        d[2] = E2::dd(dv0[2] * cp - dv0[0] * sp);
+        d[2].t[0] = (-dv0[2] * sp - dv0[0] * cp) * P.dphi;
+    } else {
+        o[0] = E2::dd(P.xe[e] + (u0 - 0.5) * P.pitch);
+        o[0].t[0] = P.pitch;
+        o[2] = E2::dd(0.0);
+        for (int i = 0; i < 3; ++i) d[i] = E2::dd(dv0[i]);
+    }
     D2 w = E2::dd(dv0[2] / (P.n_per_tx * (1.0 / (2.0 * M_PI)))), t = E2::dd(P.tau[(int64_t)tx * P.E + e]);
     D2 len = E2::dd(0.0);
     int med = P.top_medium;
@@ -884,7 +923,12 @@ __device__ bool edge_path(const AdjParams &A, const AdjTangent &dir, int tx, int
         const int hloc = h.local, face = h.face;
         D2 th, sc[3];
         double srad = 0.0;
-        if (hid == P.id_box) {
+        if (hid == P.id_box && face == 6) {
+            const D2 R = E2::dd(P.radius);
+            const D2 aa = d[0] * d[0] + d[2] * d[2], bq = o[0] * d[0] + (o[2] + R) * d[2];
+            const D2 cq = o[0] * o[0] + o[2] * (o[2] + E2::dd(2.0) * R);
+            th = cq / (-bq + dsqrt(bq * bq - aa * cq));
+        } else if (hid == P.id_box) {
             const int ax = face % 3;
             th = (E2::dd(P.box[face]) - o[ax]) / d[ax];
         } else if (hid < P.id_sph0) {
@@ -927,13 +971,34 @@ __device__ bool edge_path(const AdjParams &A, const AdjTangent &dir, int tx, int
         if (clipped || t.v >= P.t_max) return false;
         sig = (sig ^ (unsigned long long)(8 * (hid + 1) + face + 1)) * 1099511628211ull;
         if (hid == P.id_box) {
-            if (face != 2) return false;
-            out.x[0] = o[0];
+            int er;
+            D2 ca;
+            if (P.convex) {
+                // the arc angle atan2(x, z + R) of the landing point
+                if (face != 6) return false;
+                const D2 zc = o[2] + E2::dd(P.radius);
+                const double r2 = o[0].v * o[0].v + zc.v * zc.v;
+                D2 ph = E2::dd(atan2(o[0].v, zc.v));
+                for (int k = 0; k < 2; ++k) ph.t[k] = (zc.v * o[0].t[k] - o[0].v * zc.t[k]) / r2;
+                out.x[0] = ph;
+                out.inside = fabs(ph.v) <= P.half_arc && fabs(o[1].v) <= 0.5 * P.elev;
+                er = (int)floor(ph.v / P.dphi + 0.5 * (double)P.E);
+                er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+                const double4 g = P.elem[er];
+                ca = -(d[0] * E2::dd(g.z) + d[2] * E2::dd(g.w));
+            } else {
+                if (face != 2) return false;
+                out.x[0] = o[0];
+                out.inside = fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev;
+                er = (int)floor((o[0].v + P.half_ap) / P.pitch);
+                er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
+                ca = -d[2];
+            }
             out.x[1] = o[1];
-            out.inside = fabs(o[0].v) <= P.half_ap && fabs(o[1].v) <= 0.5 * P.elev;
-            int er = (int)floor((o[0].v + P.half_ap) / P.pitch);
-            out.er = er < 0 ? 0 : (er > P.E - 1 ? P.E - 1 : er);
-            const D2 al = dacos(-d[2]);
+            out.er = er;
+            out.w = w.v;
+            for (int i = 0; i < 3; ++i) out.d[i] = d[i].v;
+            const D2 al = dacos(ca);
             out.c = al.v <= P.alpha_c
                         ? w * (al.v <= P.alpha_m ? E2::dd(1.0) : (E2::dd(P.alpha_c) - al) / E2::dd(P.alpha_c - P.alpha_m))
                         : E2::dd(0.0);
@@ -1083,18 +1148,20 @@ __device__ void edge_crossings(const AdjParams &A, int tx, int e, uint32_t ray, 
     const double half_el = 0.5 * P.elev;
     double root;
     const double lo = fmin(a.x, b.x), hi = fmax(a.x, b.x);
-    // element edges and aperture ends (the edge k lies between elements k-1 and k)
-    const int k0 = (int)ceil((lo + P.half_ap) / P.pitch) - 1, k1 = (int)floor((hi + P.half_ap) / P.pitch) + 1;
+    // element edges and aperture ends (the edge k lies between elements k-1
+    // and k), in x or in the arc angle
+    const double x0 = P.convex ? -0.5 * (double)P.E * P.dphi : -P.half_ap, step = P.convex ? P.dphi : P.pitch;
+    const int k0 = (int)ceil((lo - x0) / step) - 1, k1 = (int)floor((hi - x0) / step) + 1;
     for (int k = k0 < 0 ? 0 : k0; k <= (k1 > P.E ? P.E : k1); ++k) {
-        const double X = -P.half_ap + (double)k * P.pitch;
+        const double X = P.convex ? ((double)k - 0.5 * (double)P.E) * P.dphi : -P.half_ap + (double)k * P.pitch;
         if (!(X > lo && X < hi)) continue;
         if (!edge_root(A, tx, e, ray, a.u, b.u, a.x - X, 0, X, a.sig, stk, root)) continue;
         edge_terms(A, tx, e, ray, root, 0, stk, [&](const EdgeHit &at) {
             if (!(fabs(at.x[1].v) <= half_el)) return 0.0;
             double gv, gs;
-            const double hr = k < P.E && adj_at(A, tx, k, at.t.v, gv, gs) ? gv : 0.0;
-            const double hl = k > 0 && adj_at(A, tx, k - 1, at.t.v, gv, gs) ? gv : 0.0;
-            return at.c.v * (hr - hl);
+            const double fr = k < P.E && adj_at(A, tx, k, at.t.v, gv, gs) ? edge_c(P, at, k) * gv : 0.0;
+            const double fl = k > 0 && adj_at(A, tx, k - 1, at.t.v, gv, gs) ? edge_c(P, at, k - 1) * gv : 0.0;
+            return fr - fl;
         }, acc);
     }
     // elevation edges: inside below the edge in |y|
@@ -1103,7 +1170,7 @@ __device__ void edge_crossings(const AdjParams &A, int tx, int e, uint32_t ray, 
         if (!((a.y - Y) * (b.y - Y) < 0.0)) continue;
         if (!edge_root(A, tx, e, ray, a.u, b.u, a.y - Y, 1, Y, a.sig, stk, root)) continue;
         edge_terms(A, tx, e, ray, root, 1, stk, [&](const EdgeHit &at) {
-            if (!(fabs(at.x[0].v) <= P.half_ap)) return 0.0;
+            if (!(fabs(at.x[0].v) <= (P.convex ? P.half_arc : P.half_ap))) return 0.0;
             double gv, gs;
             const double fin = adj_at(A, tx, at.er, at.t.v, gv, gs) ? at.c.v * gv : 0.0;
             return sgn > 0 ? -fin : fin;

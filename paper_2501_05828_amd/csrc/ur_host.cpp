@@ -1266,9 +1266,9 @@ UR_API ur_status ur_trace_grad_edges(ur_context *c, uint64_t seed, int64_t ray_s
             return c->fail(UR_ERR_INVALID_ARG, "need ray_stride >= 1 and 0 <= ray_offset < ray_stride");
         TraceParams P;
         fill_params(c, P, seed);
-        if (P.convex || P.sa || P.proposal || P.any_rough)
-            return c->fail(UR_ERR_UNSUPPORTED, "the edge terms need a linear array, plane-wave transmits, uniform "
-                                               "emission and smooth boundaries");
+        if (P.sa || P.proposal || P.any_rough)
+            return c->fail(UR_ERR_UNSUPPORTED, "the edge terms need plane-wave transmits, uniform emission and "
+                                               "smooth boundaries");
         const int n_mat = (int)(c->mat.size() / 3);
         const int64_t nel = c->acq.rays_per_element;
         P.stride = ray_stride;

@@ -31,10 +31,15 @@ def _case():
     return w, T._adjoint(w.acq, 5).astype(np.float32)
 
 
-def test_edge_terms_match_oracle(oracle, torch_gpu):
+@pytest.mark.parametrize("convex", [False, True])
+def test_edge_terms_match_oracle(oracle, torch_gpu, convex):
+    """Linear array, and a convex one of 20 mm radius (origin on the arc,
+    arc-angle landing coordinate, per-element receive normals)."""
     from paper_2501_05828_amd.sim import Simulator
     torch = torch_gpu
     w, g = _case()
+    if convex:
+        w = scenes.convex_probe(w, 20e-3)
     nm, ns = len(w.scene.materials), len(w.scene.sph)
     ref = oracle.trace_grad_edges(w, g.astype(np.float64), n_scan=16)
     s = Simulator(w)
@@ -45,18 +50,21 @@ def test_edge_terms_match_oracle(oracle, torch_gpu):
     for key in ("z", "sph"):
         a, b = got[key].ravel(), ref[key].ravel()
         scale = np.abs(b).max()
-        print(f"[edges-gpu] {key}: oracle {b} gpu {a} max err {np.abs(a - b).max():.3e}", flush=True)
+        print(f"[edges-gpu] convex={convex} {key}: oracle {b} gpu {a} max err {np.abs(a - b).max():.3e}", flush=True)
         assert scale > 0.0
         assert np.array_equal(a[b == 0.0], b[b == 0.0])
         assert np.abs(a - b).max() <= 1e-6 * scale
 
 
-def test_edge_terms_refuse_convex_arrays(torch_gpu):
+def test_edge_terms_refuse_rough_boundaries(torch_gpu):
     from paper_2501_05828_amd.binding import URError
     from paper_2501_05828_amd.sim import Simulator
     torch = torch_gpu
     w, g = _case()
-    w = scenes.convex_probe(w, 20e-3)
+    rough = np.zeros(len(w.scene.materials))
+    rough[2] = 0.3
+    w = dataclasses.replace(w, scene=dataclasses.replace(w.scene, rough=rough),
+                            acq=dataclasses.replace(w.acq, rough_direct_only=1))
     s = Simulator(w)
     Z = torch.empty(len(w.scene.materials), dtype=torch.float64, device="cuda")
     with pytest.raises(URError):
