@@ -446,7 +446,8 @@ def edges_experiment(args):
     number differences of the expected data.  The small scene with its
     sphere under the aperture (12 mm deep, radius 3 mm), no scatterers,
     linear binning, receive angles 10 / 45 degrees, args.edge_rays rays per
-    element; the channel adjoint g is one smooth random time profile (white
+    element, a linear array or (args.edge_convex) a convex one of 20 mm
+    radius; the channel adjoint g is one smooth random time profile (white
     noise filtered by a Gaussian of 40 samples) with one sign per half of the
     aperture, so it jumps at the centre edge.  For every key (Philox seed):
     J(x_c +- h) of the sphere centre's x from the replay's FP64 functional,
@@ -468,6 +469,8 @@ def edges_experiment(args):
     sph = np.array([[1.0e-3, 0.5e-3, 12.0e-3, 3.0e-3]])
     sc = dataclasses.replace(w.scene, sph=sph, sph_mat=np.array([[0, 2]], np.int32), scat=np.zeros((0, 4)))
     w = dataclasses.replace(w, acq=acq, scene=sc)
+    if args.edge_convex:
+        w = scenes.convex_probe(w, 20e-3)
     A = w.acq
     rng = np.random.default_rng(5)
     prof = np.abs(gaussian_filter1d(rng.normal(size=A.n_samples), 40.0) * 10)
@@ -506,8 +509,9 @@ def edges_experiment(args):
         return {"mean": float(x.mean()), "se": float(x.std(ddof=1) / math.sqrt(len(x)))}
 
     it, ed = np.asarray(interior), np.asarray(edges)
+    array = "convex array of 20 mm radius" if args.edge_convex else "linear array"
     out = {"experiment": "edge_terms", "workload": "small scene, sphere under the aperture, no scatterers, "
-           f"{A.n_elements} elements x {A.rays_per_element} rays, adjoint with one sign per half aperture",
+           f"{array}, {A.n_elements} elements x {A.rays_per_element} rays, adjoint with one sign per half aperture",
            "keys": args.edge_keys, "parameter": "sphere centre x",
            "differences": {f"h={h:g} m": stat(fd[h]) for h in hs},
            "interior": stat(it), "edge_terms": stat(ed), "interior_plus_edges": stat(it + ed),
@@ -599,6 +603,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint measurement on the large scene")
     ap.add_argument("--edge-keys", type=int, default=4000, help="keys of --experiment edges")
     ap.add_argument("--edge-rays", type=int, default=2048, help="rays per element of --experiment edges")
+    ap.add_argument("--edge-convex", action="store_true", help="--experiment edges through a 20 mm convex array")
     ap.add_argument("--backward-only", action="store_true", help="run only the adjoint measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
