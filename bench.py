@@ -447,7 +447,8 @@ def edges_experiment(args):
     sphere under the aperture (12 mm deep, radius 3 mm), no scatterers,
     linear binning, receive angles 10 / 45 degrees, args.edge_rays rays per
     element, a linear array or (args.edge_convex) a convex one of 20 mm
-    radius; the channel adjoint g is one smooth random time profile (white
+    radius, without scatterers or (args.edge_scatterers) with the scene's
+    2000; the channel adjoint g is one smooth random time profile (white
     noise filtered by a Gaussian of 40 samples) with one sign per half of the
     aperture, so it jumps at the centre edge.  For every key (Philox seed):
     J(x_c +- h) of the sphere centre's x from the replay's FP64 functional,
@@ -467,7 +468,8 @@ def edges_experiment(args):
     acq = dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45), binning=scenes.LINEAR,
                               angles=np.deg2rad([0.0]))
     sph = np.array([[1.0e-3, 0.5e-3, 12.0e-3, 3.0e-3]])
-    sc = dataclasses.replace(w.scene, sph=sph, sph_mat=np.array([[0, 2]], np.int32), scat=np.zeros((0, 4)))
+    scat = w.scene.scat if args.edge_scatterers else np.zeros((0, 4))
+    sc = dataclasses.replace(w.scene, sph=sph, sph_mat=np.array([[0, 2]], np.int32), scat=scat)
     w = dataclasses.replace(w, acq=acq, scene=sc)
     if args.edge_convex:
         w = scenes.convex_probe(w, 20e-3)
@@ -510,7 +512,8 @@ def edges_experiment(args):
 
     it, ed = np.asarray(interior), np.asarray(edges)
     array = "convex array of 20 mm radius" if args.edge_convex else "linear array"
-    out = {"experiment": "edge_terms", "workload": "small scene, sphere under the aperture, no scatterers, "
+    scat_note = f"{len(w.scene.scat)} scatterers" if args.edge_scatterers else "no scatterers"
+    out = {"experiment": "edge_terms", "workload": f"small scene, sphere under the aperture, {scat_note}, "
            f"{array}, {A.n_elements} elements x {A.rays_per_element} rays, adjoint with one sign per half aperture",
            "keys": args.edge_keys, "parameter": "sphere centre x",
            "differences": {f"h={h:g} m": stat(fd[h]) for h in hs},
@@ -604,6 +607,8 @@ def main():
     ap.add_argument("--edge-keys", type=int, default=4000, help="keys of --experiment edges")
     ap.add_argument("--edge-rays", type=int, default=2048, help="rays per element of --experiment edges")
     ap.add_argument("--edge-convex", action="store_true", help="--experiment edges through a 20 mm convex array")
+    ap.add_argument("--edge-scatterers", action="store_true",
+                    help="--experiment edges with the small scene's 2000 scatterers (their capture terms are not built)")
     ap.add_argument("--backward-only", action="store_true", help="run only the adjoint measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for PMC byte-counter calibration)")
