@@ -450,7 +450,8 @@ def edges_experiment(args):
     radius, without scatterers or (args.edge_scatterers) with the scene's
     2000; the channel adjoint g is one smooth random time profile (white
     noise filtered by a Gaussian of 40 samples) with one sign per half of the
-    aperture, so it jumps at the centre edge.  For every key (Philox seed):
+    aperture, so it jumps at the centre edge, or (args.edge_adjoint random)
+    such noise drawn for every element.  For every key (Philox seed):
     J(x_c +- h) of the sphere centre's x from the replay's FP64 functional,
     the interior adjoint (choice attached) and the edge terms.  Prints one
     JSON line with the means and standard errors over the keys."""
@@ -475,9 +476,13 @@ def edges_experiment(args):
         w = scenes.convex_probe(w, 20e-3)
     A = w.acq
     rng = np.random.default_rng(5)
-    prof = np.abs(gaussian_filter1d(rng.normal(size=A.n_samples), 40.0) * 10)
-    sign = np.where(np.arange(A.n_elements) < A.n_elements // 2, 1.0, -1.0)
-    g = torch.from_numpy((prof[None, None, :] * sign[None, :, None]).astype(np.float32)).cuda()
+    if args.edge_adjoint == "step":
+        prof = np.abs(gaussian_filter1d(rng.normal(size=A.n_samples), 40.0) * 10)
+        sign = np.where(np.arange(A.n_elements) < A.n_elements // 2, 1.0, -1.0)
+        gn = prof[None, None, :] * sign[None, :, None]
+    else:
+        gn = gaussian_filter1d(rng.normal(size=(A.n_tx, A.n_elements, A.n_samples)), 40.0, axis=2) * 10
+    g = torch.from_numpy(gn.astype(np.float32)).cuda()
     sim = Simulator(w)
     ctx = sim.ctx
     hs = (1e-4, 1e-5, 2e-6)
@@ -514,7 +519,8 @@ def edges_experiment(args):
     array = "convex array of 20 mm radius" if args.edge_convex else "linear array"
     scat_note = f"{len(w.scene.scat)} scatterers" if args.edge_scatterers else "no scatterers"
     out = {"experiment": "edge_terms", "workload": f"small scene, sphere under the aperture, {scat_note}, "
-           f"{array}, {A.n_elements} elements x {A.rays_per_element} rays, adjoint with one sign per half aperture",
+           f"{array}, {A.n_elements} elements x {A.rays_per_element} rays, adjoint "
+           + ("with one sign per half aperture" if args.edge_adjoint == "step" else "random per element"),
            "keys": args.edge_keys, "parameter": "sphere centre x",
            "differences": {f"h={h:g} m": stat(fd[h]) for h in hs},
            "interior": stat(it), "edge_terms": stat(ed), "interior_plus_edges": stat(it + ed),
@@ -607,6 +613,8 @@ def main():
     ap.add_argument("--edge-keys", type=int, default=4000, help="keys of --experiment edges")
     ap.add_argument("--edge-rays", type=int, default=2048, help="rays per element of --experiment edges")
     ap.add_argument("--edge-convex", action="store_true", help="--experiment edges through a 20 mm convex array")
+    ap.add_argument("--edge-adjoint", choices=["step", "random"], default="step",
+                    help="--experiment edges: one time profile signed per half aperture, or smooth random per element")
     ap.add_argument("--edge-scatterers", action="store_true",
                     help="--experiment edges with the small scene's 2000 scatterers (their capture terms are not built)")
     ap.add_argument("--backward-only", action="store_true", help="run only the adjoint measurement")
