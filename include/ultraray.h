@@ -255,6 +255,18 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
  * Defaults: 2^30 rays, 2^25 candidates (80 bytes each). */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
+/* Binning mode of later ur_trace calls (Sec. 2.3, each echo binned by its
+ * arrival time into the channel data).  deterministic = 0 (default): every
+ * record is added with device-wide float atomics, so the low bits of the
+ * channel data depend on the order of arrival.  deterministic = 1: records
+ * are staged (up to `capacity`, 24 bytes each, library-owned device memory)
+ * and binned after the trace with exact 64-bit integer arithmetic at one
+ * scale per call (below 1e-13 of the largest record for 1e5 records), so
+ * the channel data are the same bits on every call with the same inputs.
+ * A trace that offers more than `capacity` records returns
+ * UR_ERR_CAPACITY.  ur_trace_rays always uses atomics. */
+UR_API ur_status ur_set_binning(ur_context *ctx, int32_t deterministic, int64_t capacity);
+
 /* Steered plane waves synthesised from synthetic-aperture channel data
  * (any acquisition scheme from one set of traces, Sec. 1; delays of
  * Sec. 2.3 / Fig. 3):

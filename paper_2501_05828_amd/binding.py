@@ -129,6 +129,7 @@ SIGNATURES = [
     ("ur_beamform_adjoint", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
     ("ur_trace_adjoint", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, P(GradDesc), C.c_void_p]),
+    ("ur_set_binning", C.c_int, [_CTX, C.c_int32, C.c_int64]),
     ("ur_trace_grad_edges", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
 ]
@@ -321,6 +322,9 @@ class Context:
         rc = self.lib.ur_trace_adjoint(self.h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(ray_stride),
                                        int(ray_offset), _ptr(g_raw), C.byref(d), _stream_ptr(stream))
         self.check(rc, "ur_trace_adjoint")
+
+    def ur_set_binning(self, deterministic, capacity=1 << 24):
+        self.check(self.lib.ur_set_binning(self.h, 1 if deterministic else 0, int(capacity)), "ur_set_binning")
 
     def ur_trace_grad_edges(self, seed, g_raw, Z=None, sph_center=None, n_scan=16, ray_stride=1, ray_offset=0,
                             stream=None):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libultraray.so")
-SOURCES = ["ur_host.cpp", "bvh.cpp", "scatter_grid.cpp", "k_trace.hip", "k_trace_rays.hip", "k_signal.hip", "k_mlp.hip",
+SOURCES = ["ur_host.cpp", "bvh.cpp", "scatter_grid.cpp", "k_trace.hip", "k_trace_rays.hip", "k_bin.hip", "k_signal.hip", "k_mlp.hip",
            "k_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

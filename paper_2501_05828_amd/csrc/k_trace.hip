@@ -63,7 +63,8 @@ __device__ __forceinline__ void log_event(const EventLog &L, int kind, int tx, i
     }
 }
 
-// Bins one arriving contribution into ch_raw with device-scope float atomics.
+// Bins one arriving contribution into ch_raw with device-scope float atomics
+// (or, in the deterministic mode, stages it for k_bin.hip).
 template <bool COUNT, bool LOG>
 __device__ __forceinline__ void record(const TraceParams &P, const EventLog &L, Counters &cnt, int kind, int tx,
                                        int e, int seg, int64_t id, double t, double v, const double *p, int e_emit,
@@ -83,6 +84,12 @@ __device__ __forceinline__ void record(const TraceParams &P, const EventLog &L, 
     if constexpr (COUNT) {
         const double fr = x - floor(x);
         if (fr < 1e-5 || fr > 1.0 - 1e-5) ++cnt.v[C_EDGE];
+    }
+    if (P.det) {
+        // deterministic binning: staged, binned after the trace in a fixed order
+        const unsigned long long slot = atomicAdd(P.det_count, 1ull);
+        if ((int64_t)slot < P.det_cap) P.det[slot] = DetRecord{x, v, (int64_t)tx * P.E + e};
+        return;
     }
     float *ch = P.ch_raw + ((int64_t)tx * P.E + e) * P.S;
     if (P.binning == UR_BIN_NEAREST) {

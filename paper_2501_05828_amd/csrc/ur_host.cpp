@@ -84,6 +84,9 @@ struct ur_context {
     DevBuf d_giq;                          // adjoint of IQ inside ur_beamform_adjoint
     DevBuf d_adj_seg, d_adj_cap, d_adj_ncap;   // decisions of the adjoint's value pass over a range of paths
     DevBuf d_adj_next;                     // work counter of the adjoint's persistent replay
+    DevBuf d_det, d_det_ctr, d_det_bins;   // deterministic binning: staged records, counters, integer bins
+    bool det_mode = false;                 // bin by staged records instead of float atomics
+    int64_t det_cap = 0;
     DevBuf d_elem, d_ze;                   // convex arrays: element centre / normal table, centre depths
     DevBuf d_theta, d_m, d_v, d_grad, d_rff, d_X, d_H1, d_H2, d_H3, d_Z, d_dZ, d_dH3, d_dH2, d_dH1, d_angles, d_scal;
     // contribution recording
@@ -372,7 +375,7 @@ UR_API void ur_context_destroy(ur_context *c) {
                       &c->d_rays, &c->d_events, &c->d_evcount, &c->d_ctr, &c->d_nee, &c->d_counters, &c->d_theta,
                       &c->d_m, &c->d_v, &c->d_grad, &c->d_rff, &c->d_X, &c->d_H1, &c->d_H2, &c->d_H3, &c->d_Z,
                       &c->d_dZ, &c->d_dH3, &c->d_dH2, &c->d_dH1, &c->d_angles, &c->d_scal, &c->d_segq, &c->d_segc,
-                      &c->d_giq, &c->d_elem, &c->d_ze, &c->d_adj_seg, &c->d_adj_cap, &c->d_adj_ncap, &c->d_adj_next})
+                      &c->d_giq, &c->d_elem, &c->d_ze, &c->d_adj_seg, &c->d_adj_cap, &c->d_adj_ncap, &c->d_adj_next, &c->d_det, &c->d_det_ctr, &c->d_det_bins})
         b->release();
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -795,6 +798,17 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         c->trace_timed = false;
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr + 6, 1);
         P.seg_lost = ctr + 6;
+        if (c->det_mode) {
+            if ((st = alloc(c, c->d_det, (size_t)c->det_cap * sizeof(DetRecord)))) return st;
+            if ((st = alloc(c, c->d_det_ctr, 2 * sizeof(unsigned long long)))) return st;
+            if ((st = alloc(c, c->d_det_bins, (size_t)n_ch * sizeof(long long)))) return st;
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)c->d_det_ctr.p, 2);
+            HIP_TRY(c, zero_f32((float *)c->d_det_bins.p, 2 * n_ch, s));   // int64 zeros are float zeros twice
+            HIP_TRY(c, hipGetLastError());
+            P.det = (DetRecord *)c->d_det.p;
+            P.det_count = (unsigned long long *)c->d_det_ctr.p;
+            P.det_cap = c->det_cap;
+        }
         HIP_TRY(c, hipEventRecord(c->ev[0], s));
         // Work is launched in ranges: extend (closest hits, shading, segment
         // queue), scatter (captures into the transducer-sampling queue), cast
@@ -823,19 +837,27 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             P2.stats = st2;
             HIP_TRY(c, ur_launch_trace(P2, stats != nullptr, kInlineNeeOnly, s));
         }
+        if (c->det_mode)
+            HIP_TRY(c, ur_launch_det_bin(P.det, P.det_cap, P.det_count, (long long *)c->d_det_bins.p, ch_raw_dev,
+                                         (int64_t)P.T * P.E, P.S, P.binning, s));
         HIP_TRY(c, hipEventRecord(c->ev[1], s));
         c->trace_timed = c->n_tev > 0;
         if (ch_rf_dev) HIP_TRY(c, ur_launch_pulse(ch_raw_dev, (float2 *)ch_rf_dev, (const float2 *)c->d_taps.p, c->K,
                                                   (int64_t)P.T * P.E, P.S, s));
-        // every call checks the segment queue's lost count (one 8-byte read)
-        unsigned long long lost = 0;
+        // every call checks the segment queue's lost count (one 8-byte read),
+        // and in the deterministic mode the staged records offered
+        unsigned long long lost = 0, offered = 0;
         HIP_TRY(c, hipMemcpyAsync(&lost, ctr + 6, sizeof(lost), hipMemcpyDeviceToHost, s));
+        if (c->det_mode) HIP_TRY(c, hipMemcpyAsync(&offered, P.det_count, sizeof(offered), hipMemcpyDeviceToHost, s));
         if (stats) {
             unsigned long long h[kNumStats], h2[kNumStats];
             HIP_TRY(c, hipMemcpyAsync(h, st1, sizeof(h), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipMemcpyAsync(h2, st2, sizeof(h2), hipMemcpyDeviceToHost, s));
             HIP_TRY(c, hipStreamSynchronize(s));
             if (lost) return c->fail(UR_ERR_CAPACITY, "segment queue overflow (%llu segments lost)", lost);
+            if ((int64_t)offered > c->det_cap && c->det_mode)
+                return c->fail(UR_ERR_CAPACITY, "deterministic binning: %llu records for a capacity of %lld", offered,
+                               (long long)c->det_cap);
             // the overflow re-trace contributes only its transducer-sampling work
             uint64_t *dst = &stats->rays;
             for (int k = 0; k < kNumStats; ++k) dst[k] = h[k];
@@ -852,7 +874,20 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         } else {
             HIP_TRY(c, hipStreamSynchronize(s));
             if (lost) return c->fail(UR_ERR_CAPACITY, "segment queue overflow (%llu segments lost)", lost);
+            if ((int64_t)offered > c->det_cap && c->det_mode)
+                return c->fail(UR_ERR_CAPACITY, "deterministic binning: %llu records for a capacity of %lld", offered,
+                               (long long)c->det_cap);
         }
+        return UR_OK;
+    });
+}
+
+UR_API ur_status ur_set_binning(ur_context *c, int32_t deterministic, int64_t capacity) {
+    return guarded(c, [&]() -> ur_status {
+        if (deterministic != 0 && deterministic != 1) return c->fail(UR_ERR_INVALID_ARG, "deterministic must be 0 or 1");
+        if (deterministic && capacity < 1) return c->fail(UR_ERR_INVALID_ARG, "need a capacity >= 1");
+        c->det_mode = deterministic == 1;
+        c->det_cap = deterministic ? capacity : 0;
         return UR_OK;
     });
 }

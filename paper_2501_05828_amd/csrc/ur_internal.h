@@ -143,6 +143,17 @@ struct TraceParams {
     RecordEntry *rec;                 // contribution records, or null
     unsigned long long *rec_count;    // records offered (may exceed capacity)
     int64_t rec_cap;
+    // deterministic binning: records staged here instead of float atomics
+    struct DetRecord *det = nullptr;
+    unsigned long long *det_count = nullptr;   // records offered (may exceed det_cap)
+    int64_t det_cap = 0;
+};
+
+// One record staged for deterministic binning: its fractional sample
+// position x = t fs, its value and its channel tx * E + e.
+struct DetRecord {
+    double x, v;
+    int64_t ch;
 };
 
 // Explicit-ray logging (test path).
@@ -248,5 +259,11 @@ hipError_t ur_launch_replay(const ur::TraceParams &p, int n_tan, const AdjTangen
 // of p (n_scan + 1 origins per family; at most 32 parameters).
 hipError_t ur_launch_edges(const ur::TraceParams &p, double *out_z, double *out_sph, const float *g, int n_scan,
                            hipStream_t s);
+// Deterministic binning of the staged records into ch_raw [n_ch][S] (every
+// sample written): ctr[0] the records offered, ctr[1] scratch for their
+// largest |value| (cleared by the caller), bins [n_ch][S] int64 scratch
+// (cleared by the caller).
+hipError_t ur_launch_det_bin(const ur::DetRecord *rec, int64_t cap, unsigned long long *ctr, long long *bins,
+                             float *ch_raw, int64_t n_ch, int S, int binning, hipStream_t s);
 hipError_t ur_launch_philox(const uint32_t *ctr, uint32_t *out, int64_t n, uint32_t k0, uint32_t k1,
                             hipStream_t s);
