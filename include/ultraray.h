@@ -243,17 +243,28 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
 
 /* Work-size limits of later ur_trace calls.  A trace is cut into equal
- * launch ranges of at most min(rays_per_launch, 2^25) rays; with scatterers
- * present a range is also cut so that its segment queue (below) stays within
- * 1/8 of the device memory (but not below 2^16 rays).  Each range queues its
- * primary-ray segments for the scatterer walk in library-owned device memory
- * of 96 bytes x (rays x (max_bounces + 1) + 256 x resident wavefronts), and
- * up to nee_queue_capacity transducer-sampling candidates (80 bytes each,
- * library-owned) before their secondary rays are cast.  If a range produces
- * more candidates than fit, that range is traced again with the secondary
- * rays cast inline, so results never depend on these limits.
- * Defaults: 2^30 rays, 2^25 candidates (80 bytes each). */
+ * launch ranges of at most min(rays_per_launch, 2^27) rays.  With scatterers
+ * present, each launch queues its primary-ray segments for the scatterer walk
+ * in library-owned device memory (96 bytes a segment, plus a chunk of 256 per
+ * resident wavefront).  If the worst case of a range (max_bounces + 1
+ * segments a ray) fits the segment budget (ur_set_segment_queue), the queue
+ * holds that worst case; otherwise it holds the budget, and the launch admits
+ * rays only while the worst case of the rays it has not finished still fits:
+ * it ends early and the next launch goes on from there.  Up to
+ * nee_queue_capacity transducer-sampling candidates (80 bytes each,
+ * library-owned) are queued per launch before their secondary rays are cast;
+ * a launch that produces more is traced again with the secondary rays cast
+ * inline.  Results never depend on these limits.
+ * Defaults: 2^30 rays; candidates: until this call sets it, the larger of
+ * 2^25 and the rays of one range. */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
+
+/* Segment budget of later ur_trace calls: the segment queue holds at most
+ * `segments` segments (96 bytes each) beyond its per-wavefront chunks; 0
+ * (default) allows 1/8 of the device memory.  A budget below 1024 x
+ * (max_bounces + 1) segments makes launches as short as the worst case needs
+ * (but not below 2^16 rays).  segments < 0: UR_ERR_INVALID_ARG. */
+UR_API ur_status ur_set_segment_queue(ur_context *ctx, int64_t segments);
 
 /* Binning mode of later ur_trace calls (Sec. 2.3, each echo binned by its
  * arrival time into the channel data).  deterministic = 0 (default): every

@@ -102,6 +102,7 @@ SIGNATURES = [
     ("ur_trace", C.c_int, [_CTX, C.c_uint64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, P(TraceStats),
                            C.c_void_p]),
     ("ur_set_limits", C.c_int, [_CTX, C.c_int64, C.c_int64]),
+    ("ur_set_segment_queue", C.c_int, [_CTX, C.c_int64]),
     ("ur_pulse", C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ur_beamform_static", C.c_int, [_CTX, P(GridDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -264,6 +265,9 @@ class Context:
 
     def ur_set_limits(self, rays_per_launch, nee_queue_capacity):
         self.check(self.lib.ur_set_limits(self.h, int(rays_per_launch), int(nee_queue_capacity)), "ur_set_limits")
+
+    def ur_set_segment_queue(self, segments):
+        self.check(self.lib.ur_set_segment_queue(self.h, int(segments)), "ur_set_segment_queue")
 
     def ur_pulse(self, ch_raw, ch_rf, stream=None):
         self.check(self.lib.ur_pulse(self.h, _ptr(ch_raw), _ptr(ch_rf), _stream_ptr(stream)), "ur_pulse")

@@ -105,7 +105,7 @@ __device__ __forceinline__ void record(const TraceParams &P, const EventLog &L, 
     }
 }
 
-constexpr int kChunk = 1024;   // work items a wave takes from the range at a time (largest chunk)
+constexpr int kChunk = kRayChunk;   // work items a wave takes from the range at a time (largest chunk)
 
 // Guided self-scheduling: a wavefront takes about 1/8 of its share of the
 // work still left (seen at its last grab), between 64 and kChunk items, so
@@ -914,6 +914,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
     pd.mask = 0u;
     float tmf = 0.0f;
     int cur = 0, sp = 0, visits = 0;
+    int npush = 0, ret = 0;   // segments this lane's ray may have queued; budget to hand back
     bool active = false, trav = false, overflow = false, exhausted = false, near_grid = false;
     unsigned long long cbeg = 0, cend = 0;
     auto start_segment = [&]() {
@@ -938,8 +939,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
             if (need && (__popcll(need) >= kBatchExtend || busy == 0ull)) {
                 if (cbeg >= cend) {
                     const unsigned long long want = guided_chunk(n_range > cend ? n_range - cend : 0ull);
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(P.work_next, want);
+                    bool admit = true;
+                    if (P.seg_commit) {
+                        // admission: the worst case of the new chunk, less what
+                        // the rays finished since the last take did not queue
+                        int back = ret;
+                        for (int off = 32; off > 0; off >>= 1) back += __shfl_xor(back, off, 64);
+                        ret = 0;
+                        int ok = 0;
+                        if (lane == 0) {
+                            const unsigned long long add = want * (unsigned long long)(P.B + 1);
+                            const unsigned long long delta = add - (unsigned long long)(long long)back;
+                            const unsigned long long old = atomicAdd(P.seg_commit, delta);
+                            ok = old + delta <= P.seg_limit;
+                            if (!ok) atomicAdd(P.seg_commit, 0ull - add);
+                        }
+                        admit = __shfl(ok, 0) != 0;
+                    }
+                    unsigned long long base = n_range;
+                    if (admit && lane == 0) base = atomicAdd(P.work_next, want);
                     const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
                     base = ((unsigned long long)hi << 32) | lo;
                     if (base >= n_range) {
@@ -968,6 +986,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
                         R.seg = 0;
                         active = true;
                         visits = 0;
+                        npush = 0;
                         CNT(C_RAYS);
                         start_segment();
                     }
@@ -1003,7 +1022,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
         if (active && !trav && pd.mask == 0u) {
             if (overflow) walk_threaded<COUNT>(P, R.o, R.d, R.last, cr, tmf, h, cnt);
             resolve_hit(P, h);
+            npush += near_grid;   // after_hit queues the segment only if it meets the grid
             active = after_hit<COUNT, false, kDeferNee, true, ROUGH, CONVEX>(P, L, cnt, R, h, chunk, near_grid);
+            if (!active) ret += P.B + 1 - npush;
             if (active) {
                 start_segment();
             } else if (P.cost && R.cell >= 0) {

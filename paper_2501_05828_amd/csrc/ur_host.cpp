@@ -98,6 +98,8 @@ struct ur_context {
     std::vector<hipEvent_t> tev;           // [4 * launches]: before extend, after extend, after scatter, after sampling
     int n_tev = 0;
     int64_t nee_cap = int64_t(1) << 25;      // 80 B each: 2.7 GB (the cone choice casts nearly every capture)
+    bool nee_auto = true;                    // capacity not set by the caller: at least one per ray of a range
+    int64_t seg_budget = 0;                  // segments the segment queue may hold (0: 1/8 of device memory)
     const float *pdf = nullptr, *cdf = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool trace_timed = false, das_timed = false;
@@ -748,11 +750,8 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         P.ch_raw = ch_raw_dev;
         const int64_t n_ch = (int64_t)P.T * P.E * P.S;
         ur_status st;
-        if ((st = alloc(c, c->d_nee, (size_t)c->nee_cap * sizeof(NeeEntry)))) return st;
         HIP_TRY(c, zero_f32(ch_raw_dev, n_ch, s));
         unsigned long long *ctr = (unsigned long long *)c->d_counters.p;
-        P.nee = (NeeEntry *)c->d_nee.p;
-        P.nee_cap = c->nee_cap;
         P.nee_count = ctr + 2;
         P.rec = c->rec;
         P.rec_count = c->rec_count;
@@ -764,36 +763,61 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, st2, kNumStats);
             HIP_TRY(c, hipGetLastError());
         }
-        // launch ranges: the segment queue between the extend and scatter
-        // kernels holds the worst case of one range (every ray using all
-        // B + 1 segments) plus one partly used chunk per wavefront.  Ranges
-        // are as long as possible (fewer kernel tails) while the queue stays
-        // within 1/8 of the device memory.
+        // Launch ranges: fewer, longer ranges have fewer kernel tails (each
+        // range boundary costs about 1.3 ms on the bone frame).  The segment
+        // queue between the extend and scatter kernels stays within 1/8 of the
+        // device memory.  If that holds the worst case of a range (every ray
+        // queueing all B + 1 segments, plus one partly used chunk per
+        // wavefront), every launch takes its whole range; otherwise the queue
+        // takes the whole 1/8 and the extend kernel admits rays only while the
+        // worst case of the rays not yet finished still fits, so a launch ends
+        // where the queue would fill and the next one starts there.
         int64_t range = std::max<int64_t>(1, std::min<int64_t>(c->rays_per_launch, kSplitRays));
-        if (P.n_scat > 0) {
-            size_t free_b = 0, total_b = 0;
-            HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
-            const int64_t fit = (int64_t)(total_b / 8 / ((sizeof(SegHot) + sizeof(SegCold)) * (size_t)(P.B + 1)));
-            range = std::min(range, std::max<int64_t>(int64_t(1) << 16, fit));
-        }
+        bool admit = false;
         if (P.n_scat > 0) {
             const int64_t waves = ur_extend_max_waves();
             if (waves < 0) return c->fail(UR_ERR_HIP, "occupancy query failed");
-            const int64_t cap = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1)) * (int64_t)(P.B + 1) +
-                                waves * kSegChunk;
+            const int64_t slack = waves * kSegChunk;
+            int64_t budget = c->seg_budget;
+            if (budget == 0) {
+                size_t free_b = 0, total_b = 0;
+                HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
+                budget = (int64_t)(total_b / 8 / (sizeof(SegHot) + sizeof(SegCold))) - slack;
+            }
+            const int64_t n_first = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1));
+            int64_t cap = n_first * (int64_t)(P.B + 1) + slack;
+            if (cap > budget + slack) {
+                // admission needs room for the first chunk of rays at least
+                if (budget >= (int64_t)kRayChunk * (P.B + 1)) {
+                    admit = true;
+                    cap = budget + slack;
+                } else {
+                    const int64_t fit = budget / (int64_t)(P.B + 1);
+                    range = std::min(range, std::max<int64_t>(int64_t(1) << 16, fit));
+                    cap = std::min<int64_t>(range, std::max<int64_t>(P.n_work, 1)) * (int64_t)(P.B + 1) + slack;
+                }
+            }
             if ((st = alloc(c, c->d_segq, (size_t)cap * sizeof(SegHot)))) return st;
             if ((st = alloc(c, c->d_segc, (size_t)cap * sizeof(SegCold)))) return st;
             P.segq = (SegHot *)c->d_segq.p;
             P.segc = (SegCold *)c->d_segc.p;
             P.seg_cap = cap;
+            if (admit) {
+                P.seg_commit = ctr + 7;
+                P.seg_limit = (unsigned long long)(cap - slack);
+            }
         }
-        const int64_t launches = (P.n_work + range - 1) / range;
-        if (launches > 1) range = (P.n_work + launches - 1) / launches;   // equal ranges
-        while ((int64_t)c->tev.size() < 4 * launches) {
-            hipEvent_t e;
-            HIP_TRY(c, hipEventCreate(&e));
-            c->tev.push_back(e);
+        {
+            const int64_t launches = (P.n_work + range - 1) / range;
+            if (launches > 1) range = (P.n_work + launches - 1) / launches;   // equal ranges
         }
+        // the transducer-sampling queue: a range that overflows it is traced
+        // again, so by default it holds at least one candidate per ray
+        const int64_t nee_cap = c->nee_auto ? std::max<int64_t>(c->nee_cap, std::min<int64_t>(range, P.n_work))
+                                            : c->nee_cap;
+        if ((st = alloc(c, c->d_nee, (size_t)nee_cap * sizeof(NeeEntry)))) return st;
+        P.nee = (NeeEntry *)c->d_nee.p;
+        P.nee_cap = nee_cap;
         c->n_tev = 0;
         c->trace_timed = false;
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr + 6, 1);
@@ -814,10 +838,16 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         // queue), scatter (captures into the transducer-sampling queue), cast
         // the sampling queue, then (only if that queue overflowed) re-trace
         // the range casting the sampling rays inline without direct hits.
-        for (int64_t begin = 0; begin < P.n_work; begin += range) {
+        for (int64_t begin = 0; begin < P.n_work;) {
             P.work_begin = begin;
             P.work_end = std::min(P.n_work, begin + range);
+            while ((int64_t)c->tev.size() < 4 * (c->n_tev + 1)) {
+                hipEvent_t e;
+                HIP_TRY(c, hipEventCreate(&e));
+                c->tev.push_back(e);
+            }
             hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 6);
+            if (admit) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr + 7, 1);
             HIP_TRY(c, hipGetLastError());
             P.work_next = ctr;
             P.seg_count = ctr + 3;
@@ -827,6 +857,17 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             HIP_TRY(c, hipEventRecord(ev[0], s));
             HIP_TRY(c, ur_launch_extend(P, stats != nullptr, s));
             HIP_TRY(c, hipEventRecord(ev[1], s));
+            if (admit) {
+                // the rays this launch took: [0, work_next) of the range, all
+                // of them traced (a wavefront takes a chunk only once admitted)
+                unsigned long long next = 0;
+                HIP_TRY(c, hipMemcpyAsync(&next, ctr, sizeof(next), hipMemcpyDeviceToHost, s));
+                HIP_TRY(c, hipStreamSynchronize(s));
+                const int64_t taken = std::min<int64_t>((int64_t)next, P.work_end - P.work_begin);
+                if (taken <= 0) return c->fail(UR_ERR_CAPACITY, "segment queue admits no rays");
+                P.work_end = P.work_begin + taken;
+            }
+            begin = P.work_end;
             if (P.n_scat > 0) HIP_TRY(c, ur_launch_scatter(P, stats != nullptr, s));
             HIP_TRY(c, hipEventRecord(ev[2], s));
             HIP_TRY(c, ur_launch_nee(P, stats != nullptr, s));
@@ -892,12 +933,23 @@ UR_API ur_status ur_set_binning(ur_context *c, int32_t deterministic, int64_t ca
     });
 }
 
+UR_API ur_status ur_set_segment_queue(ur_context *c, int64_t segments) {
+    return guarded(c, [&]() -> ur_status {
+        if (segments < 0) return c->fail(UR_ERR_INVALID_ARG, "need segments >= 0");
+        c->seg_budget = segments;
+        c->d_segq.release();
+        c->d_segc.release();
+        return UR_OK;
+    });
+}
+
 UR_API ur_status ur_set_limits(ur_context *c, int64_t rays_per_launch, int64_t nee_queue_capacity) {
     return guarded(c, [&]() -> ur_status {
         if (rays_per_launch < 1 || nee_queue_capacity < 1 || nee_queue_capacity > (int64_t(1) << 31))
             return c->fail(UR_ERR_INVALID_ARG, "need rays_per_launch >= 1 and 1 <= nee_queue_capacity <= 2^31");
         c->rays_per_launch = rays_per_launch;
         c->nee_cap = nee_queue_capacity;
+        c->nee_auto = false;
         c->d_nee.release();
         return UR_OK;
     });

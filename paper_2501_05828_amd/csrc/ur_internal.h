@@ -18,7 +18,8 @@ constexpr int kCells = 1024;          // 32 x 32 emission-direction cells
 constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
 constexpr int kNumStats = 27;
 constexpr int kSegChunk = 256;   // segment-queue slots a wavefront reserves at a time
-constexpr int64_t kSplitRays = int64_t(1) << 25;   // most rays per launch range
+constexpr int kRayChunk = 1024;  // most work items a wavefront takes from a range at a time
+constexpr int64_t kSplitRays = int64_t(1) << 27;   // most rays per launch range
 
 // Per-material constants, FP64: impedance, amplitude attenuation [Np/m] at
 // the centre frequency, slowness [s/m].
@@ -137,6 +138,13 @@ struct TraceParams {
     unsigned long long *seg_next;     // scatter-kernel work counter
     unsigned long long *seg_lost;     // segments that found no slot (must stay 0)
     int64_t seg_cap;
+    // Admission to the segment queue when it cannot hold the worst case of a
+    // whole range: a wavefront takes a chunk of c rays only by adding c (B + 1)
+    // to seg_commit without passing seg_limit, and hands back (B + 1) less the
+    // segments each finished ray queued at its next take; a launch then ends
+    // when no more rays are admitted (null: every ray of the range is taken).
+    unsigned long long *seg_commit = nullptr;
+    unsigned long long seg_limit = 0;
     NeeEntry *nee;                    // transducer-sampling queue
     unsigned long long *nee_count;    // entries written (may exceed capacity)
     int64_t nee_cap;

@@ -338,6 +338,32 @@ def test_ragged_launch_ranges(torch_gpu, oracle):
     assert s.ctx.ur_last_trace_kernels_ms()[3] == 11
 
 
+def test_segment_queue_admission(torch_gpu, oracle):
+    """A segment budget of 40,000 segments for 65,536 rays that queue about
+    two segments each: every launch admits rays only while the worst case of
+    its unfinished rays fits and ends where the queue would fill, so the trace
+    takes several launches; no segment is lost, the stats are exact and the
+    channel data equal the oracle's."""
+    w = scenes.tiny(rays_per_element=1024)
+    s = _sim(w)
+    s.ctx.ur_set_segment_queue(40_000)
+    try:
+        st = s.trace(stats=True, pulse=False)
+        launches = s.ctx.ur_last_trace_kernels_ms()[3]
+        g = s.ch_raw.cpu().numpy()
+    finally:
+        s.ctx.ur_set_segment_queue(0)
+    ref, ost = oracle.trace(w)
+    print(f"[admission] {launches} launches for {ost['rays']} rays, {st['segments']} segments", flush=True)
+    assert ost["rays"] == 65536
+    assert launches >= 2
+    assert_stats(st, ost)
+    assert rel_l2(g, ref) <= TOL_CH
+    from paper_2501_05828_amd import binding
+    with pytest.raises(binding.URError, match="INVALID_ARG"):
+        s.ctx.ur_set_segment_queue(-1)
+
+
 def test_context_destroy_returns_device_memory(torch_gpu):
     """Contexts that traced (segment queue, secondary-ray queue, grid) give
     all their device memory back when destroyed."""
