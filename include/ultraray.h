@@ -484,7 +484,7 @@ UR_API ur_status ur_beamform_adjoint(ur_context *ctx, const ur_grid_desc *grid, 
  * expectation over the choice); 1: the choice counts as fixed, giving the
  * derivative of the fixed-seed estimator between decision changes.
  * record_paths: with Z or sph_center requested, the paths go in ranges of
- * this many (0: as many as fit in 512 MiB of records); the value pass over
+ * this many (0: as many as fit in 1/32 of the device memory); the value pass over
  * a range keeps each segment's closest primitive (16 bytes a segment) and up
  * to 8 contributing captures a path (8 bytes each), which the tangent passes
  * over the range replay.  The context keeps these buffers (grown, never

@@ -37,8 +37,10 @@ struct DevBuf {
 // gives every device that loads the library its own copy, held until the
 // process ends.  Host code never uses the symbol itself as an address: it
 // takes each device's address once (static_scratch) and passes that.
-// Bound on the adjoint's record buffers (paths of one range times their decisions).
-constexpr size_t kAdjRecBytes = size_t(512) << 20;
+// Share of the device memory the adjoint's record buffers may take (paths of
+// one range times their decisions): longer ranges have fewer kernel tails (on
+// the large scene 128 ranges of 512 MiB took 4.88 s, 8 ranges 4.29 s).
+constexpr size_t kAdjRecShare = 32;
 
 constexpr int64_t kStaticHeader = 64;                  // floats (256 bytes)
 constexpr int64_t kStaticPixels = int64_t(1) << 22;    // 2048 x 2048 pixels, 16 MiB
@@ -1309,7 +1311,9 @@ UR_API ur_status ur_trace_adjoint(ur_context *c, uint64_t seed, int64_t ray_stri
         ur_status st;
         const bool use_rec = n_tan > 0 && P.E <= 65535 && P.B < 65535;
         const size_t per_ray = (size_t)(P.B + 1) * sizeof(AdjSeg) + kAdjCapRec * sizeof(AdjCap) + 1;
-        const int64_t fit = std::max<int64_t>(1, (int64_t)(kAdjRecBytes / per_ray));
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
+        const int64_t fit = std::max<int64_t>(1, (int64_t)(total_b / kAdjRecShare / per_ray));
         const int64_t range = !use_rec ? std::max<int64_t>(1, P.n_work)
                                        : std::max<int64_t>(1, std::min(P.n_work, grads->record_paths > 0
                                                                                       ? grads->record_paths
