@@ -10,8 +10,8 @@ GPU before timing starts; each step draws a fresh Philox key.
 Prints one JSON line.  The roofline entry is for the extend kernel (the
 dominant kernel of the trace): algorithmic FLOPs (per-unit costs below x
 unit counts from an instrumented pass over the same workload) divided by its
-duration, both per frame; a frame launches the kernel once per launch range
-of equal size, so this equals FLOPs per launch over the average launch
+duration, both per frame; a frame launches the kernel once per launch, so
+this equals the average FLOPs per launch over the average launch
 duration.  Durations come from HIP events that the library records on the
 stream it launches on.  The scatter kernel is reported beside it.  The CPU
 baseline is the FP64 oracle timed on a bounded, evenly strided sample of the
@@ -226,8 +226,8 @@ def backward_measure(ray_stride=1):
 
 def load_traffic(workload):
     """HBM bytes per launch of the extend kernel (the frame's total over its
-    equal launch ranges, divided by their number) from the committed
-    rocprofv3 PMC summary, or None."""
+    launches, divided by their number) from the committed rocprofv3 PMC
+    summary, or None."""
     d = load_pmc(workload)
     if d is None:
         return None
@@ -698,7 +698,7 @@ def main():
           f"scatter {1e3 * t_sca:.1f}), DAS {1e3 * t_das:.3f} ms", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (extend): FLOPs of one frame over its
-    # launch time summed over the frame's launch ranges
+    # launch time summed over the frame's launches
     achieved = (xf32 + xf64) / t_ext
     peak = (xf32 + xf64) / (xf32 / PEAK_FP32 + xf64 / PEAK_FP64)
     traffic = load_traffic(w.name)

@@ -335,17 +335,17 @@ UR_API ur_status ur_beamform_static(ur_context *ctx, const ur_grid_desc *grid, c
 
 /* Device time in milliseconds, between HIP events recorded on the call's
  * stream immediately around each kernel launch: the trace kernels of the
- * last ur_trace call (extend + scatter, summed over launch ranges; secondary
+ * last ur_trace call (extend + scatter, summed over launches; secondary
  * rays and pulse shaping excluded) and the delay-and-sum kernel of the last
  * ur_beamform call; -1 where no such call was made.  Waits for those
  * events. */
 UR_API ur_status ur_last_kernel_ms(ur_context *ctx, double *trace_ms, double *das_ms);
 
 /* The trace kernels of the last ur_trace call separately (milliseconds,
- * summed over launch ranges): extend (emission, closest hits, interface
+ * summed over launches): extend (emission, closest hits, interface
  * events, direct hits), scatter (scatterer captures) and sampling (secondary
  * rays of the captures); -1 if no call was made.  launches receives the
- * number of launch ranges (each kernel ran once per range).  Any pointer may
+ * number of launches (each kernel ran once per launch).  Any pointer may
  * be NULL. */
 UR_API ur_status ur_last_trace_kernels_ms(ur_context *ctx, double *extend_ms, double *scatter_ms, double *sampling_ms,
                                           int64_t *launches);
