@@ -81,7 +81,7 @@ DAS_FLOP_PER_PX_ELEM = 9
 DAS_FLOP_PER_PX_TX = 4
 DAS_FLOP_PER_PX = 4
 
-TRACE_SOURCES = ["k_trace.hip", "k_bin.hip", "closest_hit.h", "trace_device.h", "scatter_grid.h", "bvh_layout.h", "philox.h", "ur_internal.h"]
+TRACE_SOURCES = ["k_trace.hip", "k_bin.hip", "closest_hit.h", "trace_device.h", "scatter_grid.h", "scatter_grid.cpp", "bvh_layout.h", "philox.h", "ur_internal.h"]
 DAS_SOURCES = ["k_signal.hip", "ur_internal.h"]
 
 

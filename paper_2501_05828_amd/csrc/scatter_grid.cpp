@@ -41,9 +41,36 @@ ScatterGrid build_scatter_grid(const double *box, const double *scat, long n_sca
         vol *= ext[k];
     }
     const double rho = g.kept > 0 ? (double)g.kept / vol : 1.0 / vol;
-    double h = std::cbrt(UR_GRID_ITEMS_PER_CELL / rho);
-    h = std::max(h, 4.0 * r_s);
-    h = std::max(h, std::cbrt(vol / (double)(1 << 24)) * 1.0001);
+    const double h_min = std::max(4.0 * r_s, std::cbrt(vol / (double)(1 << 24)) * 1.0001);
+    double h = std::max(std::cbrt(UR_GRID_ITEMS_PER_CELL / rho), h_min);
+    // The kept scatterers may fill only part of their bounding box (a convex
+    // array hears a thin curved slab): then the cells they occupy hold many
+    // more than the mean.  Cells shrink until the occupied ones hold about
+    // UR_GRID_ITEMS_PER_CELL registrations on average.
+    for (int pass = 0; pass < 4 && g.kept > 0 && h > h_min; ++pass) {
+        int n[3];
+        for (int k = 0; k < 3; ++k) n[k] = std::max(1, (int)std::ceil(ext[k] / h));
+        std::vector<int> count((size_t)n[0] * n[1] * n[2], 0);
+        long regs = 0, occupied = 0;
+        for (long i = 0; i < n_scat; ++i) {
+            if (!keep[(size_t)i]) continue;
+            const double *p = scat + 4 * i;
+            int a[3], b[3];
+            for (int k = 0; k < 3; ++k) {
+                a[k] = std::max(0, (int)std::floor((p[k] - r - lo[k]) / h));
+                b[k] = std::min(n[k] - 1, (int)std::floor((p[k] + r - lo[k]) / h));
+            }
+            for (int z = a[2]; z <= b[2]; ++z)
+                for (int y = a[1]; y <= b[1]; ++y)
+                    for (int x = a[0]; x <= b[0]; ++x) {
+                        occupied += count[((size_t)z * n[1] + y) * n[0] + x]++ == 0;
+                        ++regs;
+                    }
+        }
+        const double mean = occupied > 0 ? (double)regs / (double)occupied : 0.0;
+        if (!(mean > 1.5 * UR_GRID_ITEMS_PER_CELL)) break;
+        h = std::max(h_min, h * std::cbrt(UR_GRID_ITEMS_PER_CELL / mean));
+    }
     for (int k = 0; k < 3; ++k) {
         g.info.lo[k] = lo[k];
         g.info.n[k] = std::max(1, (int)std::ceil(ext[k] / h));
