@@ -168,13 +168,23 @@ __global__ void k_colsum(const float *X, int R, int N, float *out) {
     out[j] = s;
 }
 
-__global__ void k_sum(const float *x, int64_t n, float *out) {
-    __shared__ float red[256];
+// Sum of n floats by one block in a fixed order (each thread a fixed stride,
+// then a fixed tree), so the total is the same bits on every call: it
+// normalises every gradient of the training step, and a float atomic across
+// blocks would round in arrival order.
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void k_sum(const float *x, int64_t n, float *out) {
+    __shared__ float red[kSumThreads];
     float s = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        s += x[i];
-    s = block_reduce(s, red, false);
-    if (threadIdx.x == 0) atomicAdd(out, s);
+#pragma unroll 8
+    for (int64_t i = threadIdx.x; i < n; i += kSumThreads) s += x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kSumThreads / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 __global__ void k_fill(float *p, int64_t n, float v) {
@@ -277,8 +287,7 @@ hipError_t ur_mlp_colsum(const float *X, int R, int N, float *out, hipStream_t s
 }
 
 hipError_t ur_mlp_sum(const float *x, int64_t n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, out, (int64_t)1, 0.f);
-    hipLaunchKernelGGL(k_sum, blocks_for(n), dim3(256), 0, s, x, n, out);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kSumThreads), 0, s, x, n, out);
     return hipGetLastError();
 }
 
