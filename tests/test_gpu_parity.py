@@ -339,14 +339,16 @@ def test_ragged_launch_ranges(torch_gpu, oracle):
 
 
 def test_segment_queue_admission(torch_gpu, oracle):
-    """A segment budget of 40,000 segments for 65,536 rays that queue about
-    two segments each: every launch admits rays only while the worst case of
-    its unfinished rays fits and ends where the queue would fill, so the trace
-    takes several launches; no segment is lost, the stats are exact and the
-    channel data equal the oracle's."""
+    """A segment budget of 20,000 segments for 65,536 rays.  With wide
+    receive cones nearly every scatterer is audible and nearly every segment
+    meets the grid and is queued (about 1.3 a ray).  A launch admits rays only
+    while the worst case of its unfinished rays fits, so it never queues more
+    than the budget and the trace takes several launches; no segment is lost,
+    the stats are exact and the channel data equal the oracle's."""
     w = scenes.tiny(rays_per_element=1024)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45)))
     s = _sim(w)
-    s.ctx.ur_set_segment_queue(40_000)
+    s.ctx.ur_set_segment_queue(20_000)
     try:
         st = s.trace(stats=True, pulse=False)
         launches = s.ctx.ur_last_trace_kernels_ms()[3]
