@@ -767,13 +767,14 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
         }
         // Launch ranges: fewer, longer ranges have fewer kernel tails (each
         // range boundary costs about 1.3 ms on the bone frame).  The segment
-        // queue between the extend and scatter kernels stays within 1/8 of the
-        // device memory.  If that holds the worst case of a range (every ray
-        // queueing all B + 1 segments, plus one partly used chunk per
-        // wavefront), every launch takes its whole range; otherwise the queue
-        // takes the whole 1/8 and the extend kernel admits rays only while the
-        // worst case of the rays not yet finished still fits, so a launch ends
-        // where the queue would fill and the next one starts there.
+        // queue between the extend and scatter kernels stays within its
+        // budget (1/8 of the device memory unless ur_set_segment_queue set
+        // one).  If that holds the worst case of a range (every ray queueing
+        // all B + 1 segments, plus one partly used chunk per wavefront), every
+        // launch takes its whole range; otherwise the queue takes the whole
+        // budget and the extend kernel admits rays only while the worst case
+        // of the rays not yet finished still fits, so a launch ends where the
+        // queue would fill and the next one starts there.
         int64_t range = std::max<int64_t>(1, std::min<int64_t>(c->rays_per_launch, kSplitRays));
         bool admit = false;
         if (P.n_scat > 0) {
