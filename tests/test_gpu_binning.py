@@ -58,7 +58,10 @@ def test_deterministic_binning_capacity(torch_gpu):
     from paper_2501_05828_amd.sim import Simulator
     s = Simulator(scenes.tiny(rays_per_element=1024))
     s.ctx.ur_set_binning(True, 10)
-    with pytest.raises(URError):
+    with pytest.raises(URError, match="CAPACITY"):
         s.trace(pulse=False)
     s.ctx.ur_set_binning(False)
     s.trace(pulse=False)
+    assert s.ctx.lib.ur_set_binning(s.ctx.h, 2, 10) == -1   # UR_ERR_INVALID_ARG: mode not 0 or 1
+    with pytest.raises(URError, match="INVALID_ARG"):
+        s.ctx.ur_set_binning(True, 0)
