@@ -92,3 +92,31 @@ def test_deterministic_binning_with_sampling_overflow(oracle, torch_gpu):
     print(f"[binning] overflow re-trace, deterministic vs oracle {rel:.2e}", flush=True)
     assert torch_gpu.equal(d1, d2)
     assert rel <= 1e-4
+
+
+def test_deterministic_binning_across_admitted_launches(oracle, torch_gpu):
+    """A segment budget that splits the trace into several launches: the
+    records of every launch are staged and binned once after the last."""
+    import dataclasses
+    import math
+    from paper_2501_05828_amd.sim import Simulator
+    w = scenes.tiny(rays_per_element=1024)
+    w = dataclasses.replace(w, acq=dataclasses.replace(w.acq, alpha_m=math.radians(10), alpha_c=math.radians(45)))
+    s = Simulator(w)
+    s.ctx.ur_set_binning(True, 1 << 20)
+    try:
+        s.trace(pulse=False)
+        one = s.ch_raw.clone()
+        s.ctx.ur_set_segment_queue(20_000)
+        s.trace(pulse=False)
+        launches = s.ctx.ur_last_trace_kernels_ms()[3]
+        split = s.ch_raw.clone()
+    finally:
+        s.ctx.ur_set_binning(False)
+        s.ctx.ur_set_segment_queue(0)
+    ref, _ = oracle.trace(w)
+    rel = np.linalg.norm(split.cpu().double().numpy() - ref) / np.linalg.norm(ref)
+    print(f"[binning] {launches} launches, deterministic vs oracle {rel:.2e}", flush=True)
+    assert launches >= 2
+    assert torch_gpu.equal(one, split)
+    assert rel <= 1e-4
