@@ -243,7 +243,7 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
                           float *ch_raw_dev, float *ch_rf_dev, ur_trace_stats *stats, void *stream);
 
 /* Work-size limits of later ur_trace calls.  A trace is cut into equal
- * launch ranges of at most min(rays_per_launch, 2^27) rays.  With scatterers
+ * launch ranges of at most min(rays_per_launch, 2^29) rays.  With scatterers
  * present, each launch queues its primary-ray segments for the scatterer walk
  * in library-owned device memory (96 bytes a segment, plus a chunk of 256 per
  * resident wavefront).  If the worst case of a range (max_bounces + 1
@@ -255,8 +255,8 @@ UR_API ur_status ur_trace(ur_context *ctx, uint64_t seed, int64_t ray_stride, in
  * library-owned) are queued per launch before their secondary rays are cast;
  * a launch that produces more is traced again with the secondary rays cast
  * inline.  Results never depend on these limits.
- * Defaults: 2^30 rays; candidates: until this call sets it, the larger of
- * 2^25 and the rays of one range. */
+ * Defaults: 2^30 rays; candidates: until this call sets it, the rays of one
+ * range, but at least 2^25 and at most 2^27. */
 UR_API ur_status ur_set_limits(ur_context *ctx, int64_t rays_per_launch, int64_t nee_queue_capacity);
 
 /* Segment budget of later ur_trace calls: the segment queue holds at most

@@ -952,7 +952,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ROUGH ? UR_
                             const unsigned long long delta = add - (unsigned long long)(long long)back;
                             const unsigned long long old = atomicAdd(P.seg_commit, delta);
                             ok = old + delta <= P.seg_limit;
-                            if (!ok) atomicAdd(P.seg_commit, 0ull - add);
+                            // the first refusal closes the launch to every
+                            // wavefront (the counter stays beyond any limit),
+                            // so it drains at once as at the end of its range
+                            if (!ok) atomicMax(P.seg_commit, ~0ull >> 2);
                         }
                         admit = __shfl(ok, 0) != 0;
                     }

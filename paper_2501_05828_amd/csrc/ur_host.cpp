@@ -815,9 +815,11 @@ UR_API ur_status ur_trace(ur_context *c, uint64_t seed, int64_t ray_stride, int6
             if (launches > 1) range = (P.n_work + launches - 1) / launches;   // equal ranges
         }
         // the transducer-sampling queue: a range that overflows it is traced
-        // again, so by default it holds at least one candidate per ray
-        const int64_t nee_cap = c->nee_auto ? std::max<int64_t>(c->nee_cap, std::min<int64_t>(range, P.n_work))
-                                            : c->nee_cap;
+        // again, so by default it holds one candidate per ray of a range, at
+        // least 2^25 and at most 2^27 (10.7 GB)
+        const int64_t nee_cap =
+            c->nee_auto ? std::max<int64_t>(c->nee_cap, std::min<int64_t>({range, P.n_work, int64_t(1) << 27}))
+                        : c->nee_cap;
         if ((st = alloc(c, c->d_nee, (size_t)nee_cap * sizeof(NeeEntry)))) return st;
         P.nee = (NeeEntry *)c->d_nee.p;
         P.nee_cap = nee_cap;

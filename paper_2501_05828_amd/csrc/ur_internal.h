@@ -19,7 +19,7 @@ constexpr double kEpsT = 1e-9;        // self-intersection guard along a ray [m]
 constexpr int kNumStats = 27;
 constexpr int kSegChunk = 256;   // segment-queue slots a wavefront reserves at a time
 constexpr int kRayChunk = 1024;  // most work items a wavefront takes from a range at a time
-constexpr int64_t kSplitRays = int64_t(1) << 27;   // most rays per launch range
+constexpr int64_t kSplitRays = int64_t(1) << 29;   // most rays per launch range
 
 // Per-material constants, FP64: impedance, amplitude attenuation [Np/m] at
 // the centre frequency, slowness [s/m].
@@ -141,8 +141,9 @@ struct TraceParams {
     // Admission to the segment queue when it cannot hold the worst case of a
     // whole range: a wavefront takes a chunk of c rays only by adding c (B + 1)
     // to seg_commit without passing seg_limit, and hands back (B + 1) less the
-    // segments each finished ray queued at its next take; a launch then ends
-    // when no more rays are admitted (null: every ray of the range is taken).
+    // segments each finished ray queued at its next take; the first refusal
+    // closes the launch, which then ends when its rays finish (null: every
+    // ray of the range is taken).
     unsigned long long *seg_commit = nullptr;
     unsigned long long seg_limit = 0;
     NeeEntry *nee;                    // transducer-sampling queue
