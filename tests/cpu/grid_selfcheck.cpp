@@ -139,9 +139,11 @@ int main(int argc, char **argv) {
         else if (!cull && got != want) ++bad;
         events += (long)want.size();
     }
-    std::printf("grid %dx%dx%d h=%.3g kept=%ld items=%zu segments=%ld events=%ld culled_events=%ld heard=%ld "
-                "cells/seg=%.1f tests/seg=%.1f bad=%ld heard_culled=%ld\n",
-                g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, n_kept, g.items.size(), nseg, events, culled_events,
-                heard, (double)cells / nseg, (double)tests / nseg, bad, heard_culled);
+    long occupied = 0;
+    for (size_t c = 0; c + 1 < g.cell_start.size(); ++c) occupied += g.cell_start[c + 1] > g.cell_start[c];
+    std::printf("grid %dx%dx%d h=%.3g kept=%ld items=%zu occupied=%ld segments=%ld events=%ld culled_events=%ld "
+                "heard=%ld cells/seg=%.1f tests/seg=%.1f bad=%ld heard_culled=%ld\n",
+                g.info.n[0], g.info.n[1], g.info.n[2], g.info.h, n_kept, g.items.size(), occupied, nseg, events,
+                culled_events, heard, (double)cells / nseg, (double)tests / nseg, bad, heard_culled);
     return bad || heard_culled ? 1 : 0;
 }

@@ -147,3 +147,21 @@ def test_scatter_grid_audibility_cull_convex(grid_checker, alpha_c_deg, r_s):
         assert kept == 20000
     if alpha_c_deg == 2.0:
         assert kept < 0.25 * 20000 and _field(out, "culled_events") > 0, out
+
+
+def test_scatter_grid_cells_sized_by_occupied_cells(grid_checker):
+    """The convex workload's 200,000 scatterers at alpha_c = 2 degrees: the
+    audible ones fill a thin curved slab, a small part of their bounding box,
+    so cells sized by the mean density over the box hold about 12.7
+    registrations where occupied.  The builder shrinks the cells until the
+    occupied ones hold about two (at most 1.5 times that), and the walk still
+    finds every heard capture exactly once."""
+    w = scenes.convex(rays_per_element=1)
+    R, E = w.acq.radius, w.acq.n_elements
+    half = 0.5 * (E - 1) * w.acq.pitch / R
+    rx = (0.0, 0.0, w.acq.alpha_c, R, -half, half)
+    out = _run_grid(grid_checker, w.scene.scat, w.scene.box, w.acq.r_s, 200, seed=6, rx=rx)
+    assert "bad=0" in out and "heard_culled=0" in out, out
+    per_cell = _field(out, "items") / _field(out, "occupied")
+    print(f"[grid] convex workload: {per_cell:.2f} registrations per occupied cell")
+    assert per_cell <= 3.0, out
