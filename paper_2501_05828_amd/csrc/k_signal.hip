@@ -147,7 +147,7 @@ __device__ __forceinline__ void das_transmits(const DasParams &p, double x, doub
 // 256 lanes covers a 16 x 16 tile of the image and each wavefront an 8 x 8
 // sub-tile (8 consecutive depths per lateral position), so the samples that
 // one gather of a wavefront touches lie within a few cache lines.  The
-// transmits are taken in register batches of 8 and one batch of the rest;
+// transmits are taken in register batches of 11 and one batch of the rest;
 // the receive delay (one FP64 square root per pixel and element) is formed
 // once per batch.  The interpolation and accumulation are FP32.
 constexpr int kDasTile = 16;
@@ -160,9 +160,12 @@ __global__ __launch_bounds__(256) void k_das(DasParams p) {
     das_pixel(p, ix, iz, x, z);
     float re = 0.0f, im = 0.0f;
     int t0 = 0;
-    for (; t0 + 8 <= p.T; t0 += 8) das_transmits<8>(p, x, z, t0, re, im);
+    for (; t0 + 11 <= p.T; t0 += 11) das_transmits<11>(p, x, z, t0, re, im);
     // the remaining transmits in one batch (one receive delay per element)
     switch (p.T - t0) {
+    case 10: das_transmits<10>(p, x, z, t0, re, im); break;
+    case 9: das_transmits<9>(p, x, z, t0, re, im); break;
+    case 8: das_transmits<8>(p, x, z, t0, re, im); break;
     case 7: das_transmits<7>(p, x, z, t0, re, im); break;
     case 6: das_transmits<6>(p, x, z, t0, re, im); break;
     case 5: das_transmits<5>(p, x, z, t0, re, im); break;
